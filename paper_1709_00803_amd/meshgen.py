@@ -1,0 +1,647 @@
+"""Seeded synthetic 2D hybrid meshes (quadrilaterals and triangles).
+
+This module only produces *inputs*: node coordinates, per-cell vertex lists
+and tagged boundary edges, i.e. the three parts of the non-manifold hybrid
+mesh data the paper's solver reads (Sec. 2.4, "NON-MANIFOLD HYBRID MESH DATA
+STRUCTURE": counts, node coordinates, per-cell vertex index lists).  It holds
+none of the flow solver's arithmetic (no geometry factors, fluxes or
+boundary states) and imports nothing else from this package, so both the
+CPU oracle and the GPU library can be fed from it.
+
+Meshes produced here:
+
+* ``flat_plate``      - stretched quadrilateral plate mesh (laminar flat plate).
+* ``joukowski_hybrid`` - Joukowski airfoil: body-fitted quadrilateral layers
+  around the wall, seeded-point Delaunay triangles out to a circular far
+  field.
+* ``random_hybrid``   - small jittered quad/triangle meshes for invariance
+  and conservation checks.
+* ``colour_order``    - renumbers the cells so that cells of one colour of a
+  greedy graph colouring of the cell adjacency are contiguous.  The solver's
+  Gauss-Seidel sweeps run in cell-index order, so this numbering decides how
+  many independent wavefronts a sweep has.
+
+Boundary tags: FREESTREAM=1, SYMMETRY=2, WALL=3, OUTFLOW=4, FARFIELD=5.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+FREESTREAM, SYMMETRY, WALL, OUTFLOW, FARFIELD = 1, 2, 3, 4, 5
+
+
+@dataclasses.dataclass
+class Mesh:
+    xy: np.ndarray            # (n_nodes, 2) float64
+    cell_ptr: np.ndarray      # (n_cells + 1,) int32, CSR offsets into cell_nodes
+    cell_nodes: np.ndarray    # (cell_ptr[-1],) int32 node ids, either orientation
+    bface_nodes: np.ndarray   # (n_bfaces, 2) int32 node ids of each boundary edge
+    bface_tag: np.ndarray     # (n_bfaces,) int32 boundary tag
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xy.shape[0])
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cell_ptr.shape[0] - 1)
+
+    @property
+    def n_bfaces(self) -> int:
+        return int(self.bface_tag.shape[0])
+
+    def cells_as_lists(self):
+        p = self.cell_ptr
+        return [self.cell_nodes[p[i]:p[i + 1]] for i in range(self.n_cells)]
+
+    def centroids_approx(self) -> np.ndarray:
+        """Vertex average of each cell (a sorting key only)."""
+        p = self.cell_ptr.astype(np.int64)
+        cnt = np.diff(p)
+        cid = np.repeat(np.arange(self.n_cells), cnt)
+        s = np.zeros((self.n_cells, 2))
+        np.add.at(s, cid, self.xy[self.cell_nodes])
+        return s / cnt[:, None]
+
+    def copy(self) -> "Mesh":
+        return Mesh(self.xy.copy(), self.cell_ptr.copy(), self.cell_nodes.copy(),
+                    self.bface_nodes.copy(), self.bface_tag.copy(), dict(self.meta))
+
+
+def _mk(xy, cells, bnodes, btags, meta=None) -> Mesh:
+    """Pack a list of per-cell vertex arrays into CSR form."""
+    lens = np.array([len(c) for c in cells], dtype=np.int64)
+    ptr = np.zeros(len(cells) + 1, dtype=np.int32)
+    ptr[1:] = np.cumsum(lens)
+    nodes = np.concatenate([np.asarray(c, dtype=np.int32) for c in cells]) if cells else np.zeros(0, np.int32)
+    return Mesh(np.ascontiguousarray(xy, dtype=np.float64), ptr, nodes.astype(np.int32),
+                np.ascontiguousarray(bnodes, dtype=np.int32).reshape(-1, 2),
+                np.ascontiguousarray(btags, dtype=np.int32), meta or {})
+
+
+def _mk_uniform(xy, cells_arr, bnodes, btags, meta=None) -> Mesh:
+    """Same as _mk for an (n, k) array of cells with k vertices each."""
+    cells_arr = np.asarray(cells_arr, dtype=np.int32)
+    n, k = cells_arr.shape
+    ptr = (np.arange(n + 1, dtype=np.int64) * k).astype(np.int32)
+    return Mesh(np.ascontiguousarray(xy, dtype=np.float64), ptr, cells_arr.reshape(-1).copy(),
+                np.ascontiguousarray(bnodes, dtype=np.int32).reshape(-1, 2),
+                np.ascontiguousarray(btags, dtype=np.int32), meta or {})
+
+
+def merge_cells(xy, cell_groups, bnodes, btags, meta=None) -> Mesh:
+    """Concatenate groups of uniform cells ((n_i, k_i) arrays) into one mesh."""
+    ptrs = [np.zeros(1, np.int64)]
+    nodes = []
+    off = 0
+    for g in cell_groups:
+        g = np.asarray(g, dtype=np.int32)
+        if g.size == 0:
+            continue
+        n, k = g.shape
+        ptrs.append(off + k * np.arange(1, n + 1, dtype=np.int64))
+        off += n * k
+        nodes.append(g.reshape(-1))
+    ptr = np.concatenate(ptrs).astype(np.int32)
+    return Mesh(np.ascontiguousarray(xy, dtype=np.float64), ptr,
+                np.concatenate(nodes).astype(np.int32),
+                np.ascontiguousarray(bnodes, dtype=np.int32).reshape(-1, 2),
+                np.ascontiguousarray(btags, dtype=np.int32), meta or {})
+
+
+# ---------------------------------------------------------------------------
+# Laminar flat plate
+# ---------------------------------------------------------------------------
+
+def flat_plate(nx: int = 64, ny: int = 32, x0: float = -0.2, x1: float = 1.0,
+               dy1: float = 1e-3, ratio: float = 1.1) -> Mesh:
+    """Structured quadrilateral plate mesh.
+
+    x-nodes uniform on [x0, x1]; y-nodes start at 0 with first spacing ``dy1``
+    and geometric growth ``ratio``.  Boundary tags: left FREESTREAM, bottom
+    SYMMETRY where the edge midpoint has x < 0 and WALL where x > 0, top and
+    right OUTFLOW (the plate is the bottom boundary from x = 0 on).
+    """
+    xs = x0 + (x1 - x0) * np.arange(nx + 1) / nx
+    ys = np.concatenate([[0.0], np.cumsum(dy1 * ratio ** np.arange(ny))])
+    X, Y = np.meshgrid(xs, ys, indexing="xy")          # (ny+1, nx+1)
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+
+    def nid(i, j):
+        return j * (nx + 1) + i
+
+    I, J = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    I = I.ravel(); J = J.ravel()
+    cells = np.stack([nid(I, J), nid(I + 1, J), nid(I + 1, J + 1), nid(I, J + 1)], axis=1)
+
+    bn, bt = [], []
+    i = np.arange(nx)
+    xm = 0.5 * (xs[i] + xs[i + 1])
+    bn.append(np.stack([nid(i, 0), nid(i + 1, 0)], 1)); bt.append(np.where(xm > 0.0, WALL, SYMMETRY))
+    bn.append(np.stack([nid(i, ny), nid(i + 1, ny)], 1)); bt.append(np.full(nx, OUTFLOW))
+    j = np.arange(ny)
+    bn.append(np.stack([nid(0, j), nid(0, j + 1)], 1)); bt.append(np.full(ny, FREESTREAM))
+    bn.append(np.stack([nid(nx, j), nid(nx, j + 1)], 1)); bt.append(np.full(ny, OUTFLOW))
+    meta = dict(kind="flat_plate", nx=nx, ny=ny, x0=x0, x1=x1, dy1=dy1, ratio=ratio, chord=1.0)
+    return _mk_uniform(xy, cells, np.concatenate(bn), np.concatenate(bt), meta)
+
+
+# ---------------------------------------------------------------------------
+# Small random hybrid meshes (tests)
+# ---------------------------------------------------------------------------
+
+def random_hybrid(nx: int = 8, ny: int = 6, seed: int = 0, tri_frac: float = 0.5,
+                  jitter: float = 0.25, lx: float = 1.0, ly: float = 0.75,
+                  tags=None) -> Mesh:
+    """Jittered lattice on [0,lx]x[0,ly]; each cell is kept as a quad or split
+    into two triangles (random diagonal) with probability ``tri_frac``.
+
+    ``tags`` maps side name ('bottom','top','left','right') to a boundary tag
+    (scalar) or to a callable f(x_mid) -> tag array; default all FREESTREAM.
+    """
+    rng = np.random.default_rng(seed)
+    tags = tags or {}
+    hx, hy = lx / nx, ly / ny
+    xs = np.arange(nx + 1) * hx
+    ys = np.arange(ny + 1) * hy
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    X = X.copy(); Y = Y.copy()
+    jx = rng.uniform(-jitter, jitter, X.shape) * hx
+    jy = rng.uniform(-jitter, jitter, Y.shape) * hy
+    X[1:-1, 1:-1] += jx[1:-1, 1:-1]
+    Y[1:-1, 1:-1] += jy[1:-1, 1:-1]
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+
+    def nid(i, j):
+        return j * (nx + 1) + i
+
+    cells = []
+    for j in range(ny):
+        for i in range(nx):
+            a, b, c, d = nid(i, j), nid(i + 1, j), nid(i + 1, j + 1), nid(i, j + 1)
+            if rng.uniform() < tri_frac:
+                if rng.uniform() < 0.5:
+                    cells += [[a, b, c], [a, c, d]]
+                else:
+                    cells += [[a, b, d], [b, c, d]]
+            else:
+                cells.append([a, b, c, d])
+    bn, bt = [], []
+
+    def side(name, pairs, mids):
+        t = tags.get(name, FREESTREAM)
+        tv = t(mids) if callable(t) else np.full(len(pairs), t)
+        bn.append(np.asarray(pairs)); bt.append(np.asarray(tv))
+
+    i = np.arange(nx); j = np.arange(ny)
+    side("bottom", np.stack([nid(i, 0), nid(i + 1, 0)], 1), 0.5 * (xs[i] + xs[i + 1]))
+    side("top", np.stack([nid(i, ny), nid(i + 1, ny)], 1), 0.5 * (xs[i] + xs[i + 1]))
+    side("left", np.stack([nid(0, j), nid(0, j + 1)], 1), 0.5 * (ys[j] + ys[j + 1]))
+    side("right", np.stack([nid(nx, j), nid(nx, j + 1)], 1), 0.5 * (ys[j] + ys[j + 1]))
+    meta = dict(kind="random_hybrid", nx=nx, ny=ny, seed=seed, chord=1.0)
+    return _mk(xy, cells, np.concatenate(bn), np.concatenate(bt), meta)
+
+
+def transform(mesh: Mesh, theta: float = 0.0, mirror_y: bool = False,
+              shift=(0.0, 0.0)) -> Mesh:
+    """Rigid transform of the node coordinates (rotation by ``theta`` about
+    the origin after an optional mirror y -> -y, then a shift)."""
+    m = mesh.copy()
+    x, y = m.xy[:, 0].copy(), m.xy[:, 1].copy()
+    if mirror_y:
+        y = -y
+    c, s = math.cos(theta), math.sin(theta)
+    m.xy = np.stack([c * x - s * y + shift[0], s * x + c * y + shift[1]], axis=1)
+    return m
+
+
+# ---------------------------------------------------------------------------
+# Joukowski airfoil hybrid mesh
+# ---------------------------------------------------------------------------
+
+JOUK_ZC = complex(-0.1, 0.05)
+JOUK_R = abs(1.0 - JOUK_ZC)
+
+
+def joukowski_frame():
+    """Leading-edge position and chord of the Joukowski airfoil in zeta units
+    (the map zeta = z + 1/z of the circle |z - zc| = R through z = 1)."""
+    from scipy.optimize import minimize_scalar
+    th_te = math.atan2(-JOUK_ZC.imag, 1.0 - JOUK_ZC.real)
+
+    def re_zeta(th):
+        z = JOUK_ZC + JOUK_R * complex(math.cos(th), math.sin(th))
+        return (z + 1.0 / z).real
+
+    grid = th_te + np.linspace(0.5, 2 * math.pi - 0.5, 2001)
+    vals = [re_zeta(t) for t in grid]
+    k = int(np.argmin(vals))
+    res = minimize_scalar(re_zeta, bracket=(grid[k - 1], grid[k], grid[k + 1]), tol=1e-14)
+    le = float(res.fun)
+    return le, 2.0 - le, th_te
+
+
+def _joukowski_wall(n_wall: int, beta: float = 0.5):
+    """CCW wall polygon in chord units (LE at the origin, TE at (1, 0)).
+
+    Points are spaced in the circle angle measured from the trailing edge,
+    upper and lower halves each with a blend of uniform and cosine spacing
+    (weight ``beta`` on the cosine part), which clusters points at the
+    leading and trailing edges.
+    """
+    le, chord, th_te = joukowski_frame()
+    half = n_wall // 2
+    t = np.arange(half) / half
+    ph = math.pi * ((1.0 - beta) * t + beta * 0.5 * (1.0 - np.cos(math.pi * t)))
+    phi = np.concatenate([ph, math.pi + ph])
+    z = JOUK_ZC + JOUK_R * np.exp(1j * (th_te + phi))
+    z[0] = 1.0 + 0.0j
+    zeta = z + 1.0 / z
+    return np.stack([(zeta.real - le) / chord, zeta.imag / chord], axis=1), le, chord
+
+
+def _node_normals(P: np.ndarray) -> np.ndarray:
+    """Outward unit node normals of a closed CCW polygon; at a cusp (the two
+    edge normals nearly opposite) the direction falls back to the bisector
+    of the two edge directions."""
+    e_prev = P - np.roll(P, 1, axis=0)
+    e_next = np.roll(P, -1, axis=0) - P
+    e_prev /= np.linalg.norm(e_prev, axis=1)[:, None]
+    e_next /= np.linalg.norm(e_next, axis=1)[:, None]
+    n1 = np.stack([e_prev[:, 1], -e_prev[:, 0]], 1)
+    n2 = np.stack([e_next[:, 1], -e_next[:, 0]], 1)
+    b = n1 + n2
+    bl = np.linalg.norm(b, axis=1)
+    w = np.clip(1.0 - 0.5 * bl, 0.0, 1.0)[:, None]
+    n = b + w * (e_prev - e_next)
+    return n / np.linalg.norm(n, axis=1)[:, None]
+
+
+def _extrude(P0: np.ndarray, heights, smooth_passes: int = 8, smooth_w: float = 0.25):
+    layers = [P0]
+    P = P0
+    for h in heights:
+        n = _node_normals(P)
+        for _ in range(smooth_passes):
+            n = n + smooth_w * (np.roll(n, 1, axis=0) + np.roll(n, -1, axis=0))
+            n /= np.linalg.norm(n, axis=1)[:, None]
+        P = P + h * n
+        layers.append(P)
+    return layers
+
+
+def _points_in_polygon(pts: np.ndarray, poly: np.ndarray) -> np.ndarray:
+    """Even-odd ray casting, vectorised over points, looped over edges."""
+    x, y = pts[:, 0], pts[:, 1]
+    inside = np.zeros(len(pts), dtype=bool)
+    n = len(poly)
+    for k in range(n):
+        x1, y1 = poly[k]
+        x2, y2 = poly[(k + 1) % n]
+        cond = (y1 > y) != (y2 > y)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            xint = x1 + (y - y1) * (x2 - x1) / (y2 - y1)
+        inside ^= cond & (x < xint)
+    return inside
+
+
+def _seg_dist(pts, a, b):
+    """Distance from each point to segment a-b (broadcast over segments)."""
+    ab = b - a
+    t = np.clip(np.einsum("...i,...i->...", pts - a, ab) / np.einsum("...i,...i->...", ab, ab), 0.0, 1.0)
+    proj = a + t[..., None] * ab
+    return np.linalg.norm(pts - proj, axis=-1)
+
+
+def _far_points(ring, hr, g, r_far, center, rng, h_max):
+    """Graded seeded points between the quad ring and the far-field circle.
+
+    Target spacing h(x) = min_k (hr_k + g |x - P_k|) over ring nodes P_k
+    (capped at h_max).  A quadtree is refined until each leaf is smaller than
+    h at its centre; every leaf gets one point, jittered inside the leaf.
+    """
+    from scipy.spatial import cKDTree
+    tree = cKDTree(ring)
+    kq = min(16, len(ring))
+
+    def hfun(p):
+        d, idx = tree.query(p, k=kq)
+        return np.minimum(np.min(hr[idx] + g * d, axis=1), h_max)
+
+    size = 2.0 * r_far * 1.02
+    cx = np.array([center[0]]); cy = np.array([center[1]]); sz = np.array([size])
+    leaves = []
+    for _ in range(40):
+        if cx.size == 0:
+            break
+        c = np.stack([cx, cy], 1)
+        # drop squares fully outside the far circle
+        far = np.hypot(cx - center[0], cy - center[1]) - 0.7072 * sz > r_far
+        keep = ~far
+        cx, cy, sz, c = cx[keep], cy[keep], sz[keep], c[keep]
+        h = hfun(c)
+        split = sz > h
+        leaves.append(np.stack([cx[~split], cy[~split], sz[~split]], 1))
+        q = sz[split] / 4.0
+        sx, sy = cx[split], cy[split]
+        cx = np.concatenate([sx - q, sx + q, sx - q, sx + q])
+        cy = np.concatenate([sy - q, sy - q, sy + q, sy + q])
+        sz = np.concatenate([2 * q] * 4)
+    L = np.concatenate(leaves)
+    jit = rng.uniform(-0.3, 0.3, (len(L), 2)) * L[:, 2:3]
+    pts = L[:, :2] + jit
+    hp = hfun(pts)
+    r = np.hypot(pts[:, 0] - center[0], pts[:, 1] - center[1])
+    keep = r < r_far - 0.7 * hp
+    pts, hp = pts[keep], hp[keep]
+    keep = ~_points_in_polygon(pts, ring)
+    pts, hp = pts[keep], hp[keep]
+    # exclusion band around the ring edges: keeps every ring edge Delaunay
+    d_ring, idx = tree.query(pts, k=2)
+    near = d_ring[:, 0] < 3.0 * np.maximum(hp, hr[idx[:, 0]])
+    if near.any():
+        pn = pts[near]
+        i0 = idx[near, 0]
+        n = len(ring)
+        dmin = np.minimum(_seg_dist(pn, ring[i0], ring[(i0 + 1) % n]),
+                          _seg_dist(pn, ring[(i0 - 1) % n], ring[i0]))
+        bad = dmin < 0.7 * np.maximum(hp[near], hr[i0])
+        keep = np.ones(len(pts), bool)
+        keep[np.where(near)[0][bad]] = False
+        pts, hp = pts[keep], hp[keep]
+    return pts, hfun
+
+
+def joukowski_hybrid(n_wall: int = 128, n_layers: int = 30, h1: float = 1e-4,
+                     growth: float = 1.12, r_far: float = 20.0, seed: int = 2,
+                     target_cells: int | None = 40000, grade: float | None = None,
+                     beta: float = 0.5) -> Mesh:
+    """Joukowski airfoil hybrid mesh in chord units (LE (0,0), TE (1,0)).
+
+    * wall: ``n_wall`` points (see ``_joukowski_wall``), tag WALL;
+    * ``n_layers`` quadrilateral layers marched along smoothed node normals,
+      first height ``h1``, geometric ``growth``;
+    * triangles: Delaunay triangulation of seeded points (seed ``seed``)
+      between the outer quad ring and a far-field circle of radius ``r_far``
+      about mid-chord (tag FARFIELD); spacing grows linearly with distance
+      from the ring at rate ``grade`` (chosen from ``target_cells`` when not
+      given).
+    """
+    from scipy.spatial import Delaunay
+    P0, le, chord = _joukowski_wall(n_wall, beta)
+    heights = h1 * growth ** np.arange(n_layers)
+    layers = _extrude(P0, heights)
+    nw = n_wall
+    ring = layers[-1]
+    seg = np.linalg.norm(np.roll(ring, -1, axis=0) - ring, axis=1)
+    hr = 0.5 * (seg + np.roll(seg, 1))
+    center = (0.5, 0.0)
+    rng = np.random.default_rng(seed)
+
+    def gen(g):
+        r2 = np.random.default_rng(seed)
+        return _far_points(ring, hr, g, r_far, center, r2, h_max=max(1.0, g * r_far))
+
+    n_quads = nw * n_layers
+    if grade is None:
+        # fit the grading rate to the requested total cell count (cells ~ 2x points)
+        tgt = max(1000, (target_cells or 40000) - n_quads)
+        g = 0.05
+        for _ in range(6):
+            pts, _ = gen(g)
+            n_tri = 2.0 * len(pts)
+            g *= math.sqrt(n_tri / tgt)
+        grade = g
+    pts, hfun = gen(grade)
+
+    h_far = float(hfun(np.array([[center[0] + r_far, center[1]]]))[0])
+    n_far = max(16, int(round(2 * math.pi * r_far / h_far)))
+    ang = 2 * math.pi * np.arange(n_far) / n_far
+    farp = np.stack([center[0] + r_far * np.cos(ang), center[1] + r_far * np.sin(ang)], 1)
+
+    quad_nodes = np.concatenate(layers, axis=0)           # layer k node i -> k*nw + i
+    ring_off = n_layers * nw
+    for attempt in range(8):
+        allp = np.concatenate([ring, farp, pts], axis=0)
+        tri = Delaunay(allp).simplices
+        cen = allp[tri].mean(axis=1)
+        tri = tri[~_points_in_polygon(cen, ring)]
+        # ring edge conformity check
+        e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+        e.sort(axis=1)
+        ek = set(map(tuple, e[(e[:, 0] < nw) & (e[:, 1] < nw)].tolist()))
+        missing = [k for k in range(nw) if tuple(sorted((k, (k + 1) % nw))) not in ek]
+        if not missing:
+            break
+        drop = np.zeros(len(pts), bool)
+        for k in missing:
+            a, b = ring[k], ring[(k + 1) % nw]
+            mid, rad = 0.5 * (a + b), 0.6 * np.linalg.norm(b - a)
+            drop |= np.linalg.norm(pts - mid, axis=1) < 1.5 * rad + 1e-300
+        pts = pts[~drop]
+    else:
+        raise RuntimeError("could not make the quad ring conform to the triangulation")
+
+    # global node numbering: quad-layer nodes, then far-field nodes, then interior points
+    n_q = quad_nodes.shape[0]
+    xy = np.concatenate([quad_nodes, farp, pts], axis=0)
+
+    def remap(v):
+        out = np.empty_like(v)
+        r = v < nw
+        out[r] = ring_off + v[r]
+        out[~r] = n_q + (v[~r] - nw)
+        return out
+
+    tri = remap(tri)
+    k = np.arange(n_layers)[:, None]
+    i = np.arange(nw)[None, :]
+    ip = (i + 1) % nw
+    quads = np.stack([k * nw + i, (k + 1) * nw + i, (k + 1) * nw + ip, k * nw + ip], -1).reshape(-1, 4)
+    wall = np.stack([np.arange(nw), (np.arange(nw) + 1) % nw], 1)
+    fi = np.arange(n_far)
+    far = np.stack([n_q + fi, n_q + (fi + 1) % n_far], 1)
+    bn = np.concatenate([wall, far])
+    bt = np.concatenate([np.full(nw, WALL), np.full(n_far, FARFIELD)])
+    meta = dict(kind="joukowski_hybrid", n_wall=n_wall, n_layers=n_layers, h1=h1, growth=growth,
+                r_far=r_far, seed=seed, grade=grade, chord=1.0, zeta_le=le, zeta_chord=chord,
+                n_quads=int(quads.shape[0]), n_tris=int(tri.shape[0]))
+    return merge_cells(xy, [quads, tri], bn, bt, meta)
+
+
+# ---------------------------------------------------------------------------
+# Checks and ordering
+# ---------------------------------------------------------------------------
+
+def cell_adjacency(mesh: Mesh):
+    """Pairs (c0, c1) of cells sharing an edge, and the (n_cells, kmax) padded
+    neighbour table (-1 = none)."""
+    p = mesh.cell_ptr.astype(np.int64)
+    cnt = np.diff(p)
+    cid = np.repeat(np.arange(mesh.n_cells), cnt)
+    loc = np.arange(p[-1]) - np.repeat(p[:-1], cnt)
+    nxt = np.where(loc + 1 < np.repeat(cnt, cnt), np.arange(p[-1]) + 1, np.repeat(p[:-1], cnt))
+    a = mesh.cell_nodes.astype(np.int64)
+    b = mesh.cell_nodes[nxt].astype(np.int64)
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    key = lo * (mesh.n_nodes + 1) + hi
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    same = ks[1:] == ks[:-1]
+    if np.any(same[1:] & same[:-1]):
+        raise ValueError("an edge is shared by more than two cells")
+    i0 = order[:-1][same]
+    i1 = order[1:][same]
+    pairs = np.stack([cid[i0], cid[i1]], 1)
+    kmax = int(cnt.max())
+    nb = -np.ones((mesh.n_cells, kmax), dtype=np.int64)
+    c0 = np.concatenate([pairs[:, 0], pairs[:, 1]])
+    c1 = np.concatenate([pairs[:, 1], pairs[:, 0]])
+    o = np.argsort(c0, kind="stable")
+    c0s, c1s = c0[o], c1[o]
+    rank = np.arange(len(c0s)) - np.searchsorted(c0s, c0s, side="left")
+    nb[c0s, rank] = c1s
+    return pairs, nb
+
+
+def check_mesh(mesh: Mesh) -> dict:
+    """Positive-area, convex cells; every cell edge is either shared by two
+    cells or listed exactly once as a boundary edge."""
+    xy = mesh.xy
+    p = mesh.cell_ptr.astype(np.int64)
+    areas = np.empty(mesh.n_cells)
+    convex = np.ones(mesh.n_cells, bool)
+    cnt = np.diff(p)
+    for k in np.unique(cnt):
+        ids = np.where(cnt == k)[0]
+        V = xy[mesh.cell_nodes[p[ids][:, None] + np.arange(k)[None, :]]]   # (n,k,2)
+        Vn = np.roll(V, -1, axis=1)
+        a = 0.5 * np.sum(V[..., 0] * Vn[..., 1] - Vn[..., 0] * V[..., 1], axis=1)
+        areas[ids] = a
+        s = np.sign(a)[:, None]
+        E = Vn - V
+        En = np.roll(E, -1, axis=1)
+        cr = (E[..., 0] * En[..., 1] - E[..., 1] * En[..., 0]) * s
+        convex[ids] = np.all(cr > 0, axis=1)
+    pairs, _ = cell_adjacency(mesh)
+    # boundary edge matching
+    a = mesh.cell_nodes.astype(np.int64)
+    cid = np.repeat(np.arange(mesh.n_cells), cnt)
+    loc = np.arange(p[-1]) - np.repeat(p[:-1], cnt)
+    nxt = np.where(loc + 1 < np.repeat(cnt, cnt), np.arange(p[-1]) + 1, np.repeat(p[:-1], cnt))
+    b = mesh.cell_nodes[nxt].astype(np.int64)
+    key = np.minimum(a, b) * (mesh.n_nodes + 1) + np.maximum(a, b)
+    u, c = np.unique(key, return_counts=True)
+    bkey_cells = set(u[c == 1].tolist())
+    bn = mesh.bface_nodes.astype(np.int64)
+    bkey = np.minimum(bn[:, 0], bn[:, 1]) * (mesh.n_nodes + 1) + np.maximum(bn[:, 0], bn[:, 1])
+    ok_b = (set(bkey.tolist()) == bkey_cells) and (len(set(bkey.tolist())) == len(bkey))
+    return dict(min_area=float(np.abs(areas).min()), all_convex=bool(convex.all()),
+                n_nonconvex=int((~convex).sum()), boundary_ok=bool(ok_b),
+                n_interior_faces=int(len(pairs)), n_cells=mesh.n_cells)
+
+
+def _morton(xy: np.ndarray, bits: int = 16) -> np.ndarray:
+    lo = xy.min(axis=0)
+    span = np.maximum(xy.max(axis=0) - lo, 1e-300)
+    q = np.clip(((xy - lo) / span * (2 ** bits - 1)).astype(np.int64), 0, 2 ** bits - 1)
+    key = np.zeros(len(xy), dtype=np.int64)
+    for b in range(bits):
+        key |= ((q[:, 0] >> b) & 1) << (2 * b)
+        key |= ((q[:, 1] >> b) & 1) << (2 * b + 1)
+    return key
+
+
+def greedy_colouring(mesh: Mesh, seed: int = 0) -> np.ndarray:
+    """Jones-Plassmann colouring of the cell adjacency graph (smallest free
+    colour, random priorities from ``seed``)."""
+    _, nb = cell_adjacency(mesh)
+    n = mesh.n_cells
+    rng = np.random.default_rng(seed)
+    prio = rng.permutation(n)
+    colour = -np.ones(n, dtype=np.int64)
+    nbp = np.where(nb >= 0, prio[np.maximum(nb, 0)], -1)
+    while True:
+        unc = colour < 0
+        if not unc.any():
+            break
+        nb_unc = (nb >= 0) & unc[np.maximum(nb, 0)]
+        is_max = unc & np.all(~nb_unc | (nbp < prio[:, None]), axis=1)
+        ids = np.where(is_max)[0]
+        ncol = np.where(nb[ids] >= 0, colour[np.maximum(nb[ids], 0)], -1)
+        kmax = nb.shape[1] + 1
+        used = np.zeros((len(ids), kmax + 1), bool)
+        rows = np.repeat(np.arange(len(ids)), ncol.shape[1])
+        cv = ncol.ravel()
+        m = (cv >= 0) & (cv <= kmax)
+        used[rows[m], cv[m]] = True
+        colour[ids] = np.argmin(used, axis=1)
+    return colour
+
+
+def renumber(mesh: Mesh, new_to_old: np.ndarray) -> Mesh:
+    """Mesh with cells listed in the order ``new_to_old``."""
+    p = mesh.cell_ptr.astype(np.int64)
+    cnt = np.diff(p)[new_to_old]
+    ptr = np.zeros(len(new_to_old) + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum(cnt)
+    starts = p[new_to_old]
+    idx = np.repeat(starts - ptr[:-1], cnt) + np.arange(ptr[-1])
+    m = mesh.copy()
+    m.cell_ptr = ptr.astype(np.int32)
+    m.cell_nodes = mesh.cell_nodes[idx].astype(np.int32)
+    return m
+
+
+def colour_order(mesh: Mesh, seed: int = 0):
+    """Renumber cells by (colour, Morton key of the vertex average).
+
+    Returns (mesh, new_to_old, colour_of_new_cell).  Cells of one colour are
+    pairwise non-adjacent, so a Gauss-Seidel sweep in index order over this
+    numbering has at most n_colours dependent wavefronts.
+    """
+    colour = greedy_colouring(mesh, seed)
+    key = _morton(mesh.centroids_approx())
+    order = np.lexsort((key, colour))
+    m = renumber(mesh, order)
+    m.meta = dict(mesh.meta, ordering="colour", n_colours=int(colour.max() + 1))
+    return m, order, colour[order]
+
+
+def sfc_order(mesh: Mesh):
+    """Renumber cells along a Morton curve (a natural, many-wavefront order)."""
+    order = np.argsort(_morton(mesh.centroids_approx()), kind="stable")
+    m = renumber(mesh, order)
+    m.meta = dict(mesh.meta, ordering="morton")
+    return m, order
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+def workload(name: str) -> Mesh:
+    """The named synthetic workloads, colour-ordered.
+
+    plate64x32   laminar flat plate, 64x32 quads
+    jouk40k      Joukowski, 128 wall points, 30 quad layers (1e-4, 1.12), ~40k cells, seed 2
+    jouk250k     Joukowski, 512 wall points, 60 layers (2e-6, 1.15), ~250k cells, seed 3
+    jouk2m       Joukowski, 2048 wall points, 90 layers (1e-6, 1.10), ~2M cells, seed 4
+    """
+    if name == "plate64x32":
+        m = flat_plate()
+    elif name == "jouk40k":
+        m = joukowski_hybrid(128, 30, 1e-4, 1.12, seed=2, target_cells=40000)
+    elif name == "jouk250k":
+        m = joukowski_hybrid(512, 60, 2e-6, 1.15, seed=3, target_cells=250000)
+    elif name == "jouk2m":
+        m = joukowski_hybrid(2048, 90, 1e-6, 1.10, seed=4, target_cells=2000000)
+    else:
+        raise KeyError(name)
+    out, _, _ = colour_order(m)
+    out.meta["workload"] = name
+    return out

@@ -1,0 +1,205 @@
+"""Pins of the oracle's kinetic core (Sec. 2.1 of the paper) against
+brute-force quadrature of the defining integrals, closed forms, and the
+Chapman-Enskog (Navier-Stokes) limit.  CPU only."""
+import numpy as np
+import pytest
+
+from oracle import pyoracle as po
+from tests import kinetic_quadrature as kq
+
+K = 3
+GAM = (K + 4.0) / (K + 2.0)
+
+
+def cons(r, U, V, lam):
+    return np.array([r, r * U, r * V, 0.5 * r * (U * U + V * V + (K + 2) / (2.0 * lam))])
+
+
+@pytest.mark.parametrize("U,lam", [(0.0, 1.0), (0.7, 2.5), (-1.3, 0.6), (2.5, 4.0), (-0.05, 30.0)])
+def test_moments_vs_quadrature(U, lam):
+    """<u^k> on the whole line and both half lines (Eq.2 Maxwellian)."""
+    full = kq.moments_quad(U, lam, 0, 8)
+    for kind in (0, +1, -1):
+        got = po.moments(U, lam, kind, 9)
+        want = kq.moments_quad(U, lam, kind, 8)
+        scale = np.abs(full) + kq.moments_quad(abs(U), lam, 0, 8) * 0 + (1.0 / lam) ** (np.arange(9) / 2.0)
+        assert np.all(np.abs(got - want) <= 1e-13 * scale), (kind, got, want)
+    # the two halves add up to the whole line
+    assert np.allclose(po.moments(U, lam, 1, 9) + po.moments(U, lam, -1, 9), po.moments(U, lam, 0, 9),
+                       rtol=1e-14, atol=1e-15)
+
+
+def test_xi_moments_and_energy():
+    """<xi^2> = K/(2 lam) enters rho E = rho (U^2 + V^2 + (K+2)/(2 lam)) / 2;
+    checked through the moment matrix entry <psi_1 psi_4> = E/rho."""
+    for (U, V, lam) in [(0.3, -0.2, 1.7), (1.1, 0.4, 0.8)]:
+        M = po.moment_matrix(U, V, lam)
+        W = cons(1.0, U, V, lam)
+        assert M[0, 3] == pytest.approx(W[3], rel=1e-14)
+        assert np.allclose(M, M.T, rtol=1e-14, atol=1e-15)
+        assert np.all(np.linalg.eigvalsh(M) > 0)
+        xq = kq.xi_moments_quad(lam, 2)
+        assert xq[1] == pytest.approx(K / (2 * lam), rel=1e-12)
+        assert xq[2] == pytest.approx(K * (K + 2) / (4 * lam * lam), rel=1e-12)
+
+
+def _rand_state(rng):
+    r = rng.uniform(0.5, 2.0)
+    U, V = rng.uniform(-0.8, 0.8), rng.uniform(-0.5, 0.5)
+    lam = rng.uniform(0.6, 3.0)
+    return cons(r, U, V, lam)
+
+
+def test_slope_solves_eq101_by_quadrature():
+    rng = np.random.default_rng(1)
+    for _ in range(4):
+        W = _rand_state(rng)
+        dW = rng.normal(size=4) * np.array([0.3, 0.5, 0.5, 1.0])
+        a = po.slope(W, dW)
+        r, U, V, lam = kq.prim(W)
+        lhs = kq.integ(lambda u, v, x2: [p * kq.poly(a, u, v, x2) for p in kq.psi(u, v, x2)], U, V, lam, 0, r)
+        assert np.allclose(lhs, dW, rtol=1e-11, atol=1e-12 * np.abs(dW).max())
+
+
+def test_slope_matches_closed_form_inverse():
+    """Xu's closed-form inverse of the Maxwellian moment matrix (a
+    different route from the oracle's Gaussian elimination)."""
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        W = _rand_state(rng)
+        dW = rng.normal(size=4)
+        r, U, V, lam = kq.prim(W)
+        b = dW / r
+        R2 = b[1] - U * b[0]
+        R3 = b[2] - V * b[0]
+        R4 = 2 * b[3] - (U * U + V * V + (K + 2) / (2 * lam)) * b[0]
+        a4 = 4 * lam * lam / (K + 2) * (R4 - 2 * U * R2 - 2 * V * R3)
+        a3 = 2 * lam * R3 - V * a4
+        a2 = 2 * lam * R2 - U * a4
+        a1 = b[0] - U * a2 - V * a3 - 0.5 * a4 * (U * U + V * V + (K + 2) / (2 * lam))
+        assert np.allclose(po.slope(W, dW), [a1, a2, a3, a4], rtol=1e-12, atol=1e-12)
+
+
+def test_time_integrals_vs_quadrature():
+    for dt, tau in [(1.0, 0.05), (0.3, 0.3), (1e-3, 2e-3), (2.0, 0.01)]:
+        d = po.face_detail(*( [cons(1, 0.1, 0, 1)] + [np.zeros(4)] * 2 + [cons(1, 0.1, 0, 1)] + [np.zeros(4)] * 2
+                              + [cons(1, 0.1, 0, 1)] * 2), 1.0, 1.0, dt, tau)
+        want = kq.time_integrals_quad(dt, tau)
+        scale = np.array([dt, tau * dt, dt * dt, tau, tau * dt, tau * tau])
+        # quadrature round-off ~ n_nodes * eps relative to each factor's scale
+        assert np.all(np.abs(d["T"] - want) <= 1e-12 * scale), (d["T"], want)
+
+
+def _rand_face(rng, scale=1.0):
+    Wl, Wr = _rand_state(rng), _rand_state(rng)
+    g = lambda: rng.normal(size=4) * np.array([0.2, 0.3, 0.3, 0.6]) * scale
+    Gln, Glt, Grn, Grt = g(), g(), g(), g()
+    Wlc = Wl - 0.05 * Gln + 0.01 * rng.normal(size=4) * scale
+    Wrc = Wr + 0.04 * Grn + 0.01 * rng.normal(size=4) * scale
+    return Wl, Gln, Glt, Wr, Grn, Grt, Wlc, Wrc
+
+
+@pytest.mark.parametrize("seed,dt,tau", [(3, 0.01, 0.004), (4, 0.002, 0.02), (5, 0.05, 0.001)])
+def test_face_flux_by_brute_force(seed, dt, tau):
+    """Every coefficient of the interface distribution satisfies its
+    defining integral (Eq.101, Eq.11, Eq.12), W0 is the moment of
+    H g^l + (1-H) g^r, and F equals the (t, u, v, xi) quadrature of Eq.14."""
+    rng = np.random.default_rng(seed)
+    Wl, Gln, Glt, Wr, Grn, Grt, Wlc, Wrc = _rand_face(rng)
+    dl, dr = 0.05, 0.04
+    d = po.face_detail(Wl, Gln, Glt, Wr, Grn, Grt, Wlc, Wrc, dl, dr, dt, tau)
+    rl, Ul, Vl, laml = kq.prim(Wl)
+    rr, Ur, Vr, lamr = kq.prim(Wr)
+    one = lambda u, v, x2: kq.psi(u, v, x2)
+    W0q = kq.integ(one, Ul, Vl, laml, +1, rl) + kq.integ(one, Ur, Vr, lamr, -1, rr)
+    assert np.allclose(d["W0"], W0q, rtol=1e-12)
+    r0, U0, V0, lam0 = kq.prim(d["W0"])
+    assert d["lam0"] == pytest.approx(lam0, rel=1e-13)
+
+    def slope_check(a, W, dW):
+        r, U, V, lam = kq.prim(W)
+        lhs = kq.integ(lambda u, v, x2: [p * kq.poly(a, u, v, x2) for p in kq.psi(u, v, x2)], U, V, lam, 0, r)
+        assert np.allclose(lhs, dW, rtol=1e-10, atol=1e-11 * max(1.0, np.abs(dW).max()))
+
+    slope_check(d["aln"], Wl, Gln); slope_check(d["alt"], Wl, Glt)
+    slope_check(d["arn"], Wr, Grn); slope_check(d["art"], Wr, Grt)
+    slope_check(d["abnl"], d["W0"], (d["W0"] - Wlc) / dl)
+    slope_check(d["abnr"], d["W0"], (Wrc - d["W0"]) / dr)
+    slope_check(d["abt"], d["W0"], 0.5 * (Glt + Grt))
+    # Eq.11 compatibility of A^l, A^r (whole-space moments of g^l, g^r)
+    for (an, at, A, W) in ((d["aln"], d["alt"], d["Al"], Wl), (d["arn"], d["art"], d["Ar"], Wr)):
+        r, U, V, lam = kq.prim(W)
+        c = kq.integ(lambda u, v, x2: [p * (u * kq.poly(an, u, v, x2) + v * kq.poly(at, u, v, x2) + kq.poly(A, u, v, x2))
+                                       for p in kq.psi(u, v, x2)], U, V, lam, 0, r)
+        scale = kq.integ(lambda u, v, x2: [p * np.abs(u * kq.poly(an, u, v, x2)) for p in kq.psi(u, v, x2)], U, V, lam, 0, r)
+        assert np.all(np.abs(c) <= 1e-10 * np.abs(scale).max()), c
+    # Eq.12 and Eq.14 by quadrature in time and velocity
+    parts = kq.eq13_velocity_parts(d, Wl, Wr)
+    T = kq.time_integrals_quad(dt, tau)
+    cons_f = sum(T[k] * parts["C"][k] for k in range(6))
+    # integral over [0, dt] of psi g with g = g0 (1 + Abar t) at the interface
+    gint = dt * d["W0"] + 0.5 * dt * dt * kq.integ(
+        lambda u, v, x2: [p * kq.poly(d["Ab"], u, v, x2) for p in kq.psi(u, v, x2)], U0, V0, lam0, 0, r0)
+    assert np.allclose(cons_f, gint, rtol=1e-10, atol=1e-12 * dt)
+    Fq = sum(T[k] * parts["F"][k] for k in range(6))
+    gross = sum(np.abs(T[k] * parts["F"][k]) for k in range(6))
+    assert np.all(np.abs(d["F"] - Fq) <= 1e-11 * gross.max()), (d["F"], Fq)
+
+
+def _euler_flux(W):
+    r, mx, my, E = W
+    U, V = mx / r, my / r
+    p = (GAM - 1) * (E - 0.5 * r * (U * U + V * V))
+    return np.array([mx, mx * U + p, my * U, (E + p) * U]), np.array([my, mx * V, my * V + p, (E + p) * V])
+
+
+def _jac(fn, W, h=1e-6):
+    J = np.zeros((4, 4))
+    for k in range(4):
+        e = np.zeros(4); e[k] = h * max(1.0, abs(W[k]))
+        J[:, k] = (fn(W + e) - fn(W - e)) / (2 * e[k])
+    return J
+
+
+@pytest.mark.parametrize("dt,tau", [(2e-3, 1e-4), (5e-3, 2e-4)])
+def test_continuous_limit_is_navier_stokes(dt, tau):
+    """With the same state and slopes on both sides of the face (a linear
+    field), Eq.12 returns Abar = A (Eq.11), and the flux is
+    dt F_Euler - dt F_viscous + (dt^2/2) dF_Euler/dt with the BGK
+    Chapman-Enskog stresses: mu = tau p, bulk factor 2/(K+2), Pr = 1."""
+    rng = np.random.default_rng(7)
+    r, U, V, lam = 1.1, 0.4, -0.15, 1.3
+    W = cons(r, U, V, lam)
+    gx = rng.normal(size=4) * 0.3
+    gy = rng.normal(size=4) * 0.3
+    dl = dr = 0.02
+    d = po.face_detail(W, gx, gy, W, gx, gy, W - dl * gx, W + dr * gx, dl, dr, dt, tau)
+    assert np.allclose(d["W0"], W, rtol=1e-14)
+    for k in ("abnl", "abnr", "arn"):
+        assert np.allclose(d[k], d["aln"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(d["Ab"], d["Al"], rtol=1e-9, atol=1e-11)
+    # macroscopic gradients
+    ux = (gx[1] - U * gx[0]) / r; uy = (gy[1] - U * gy[0]) / r
+    vx = (gx[2] - V * gx[0]) / r; vy = (gy[2] - V * gy[0]) / r
+    # T = 1/(2 lam) with R = 1; lam = (K+2) rho / (4 (E - rho|U|^2/2))
+    ex = gx[3] - 0.5 * gx[0] * (U * U + V * V) - r * (U * ux + V * vx)   # d(rho e)/dx, rho e = E - rho|U|^2/2
+    Tx = (2.0 / (K + 2)) * (ex / r - (W[3] - 0.5 * r * (U * U + V * V)) * gx[0] / r ** 2)
+    p = r / (2 * lam)
+    mu = tau * p
+    div = ux + vy
+    sxx = mu * (2 * ux - 2.0 / (K + 2) * div)
+    sxy = mu * (uy + vx)
+    cp = (K + 4) / 2.0
+    qx = -mu * cp * Tx
+    Fvisc = np.array([0.0, sxx, sxy, U * sxx + V * sxy - qx])
+    Fx, _ = _euler_flux(W)
+    Jx = _jac(lambda w: _euler_flux(w)[0], W)
+    Jy = _jac(lambda w: _euler_flux(w)[1], W)
+    dWdt = -(Jx @ gx + Jy @ gy)
+    dFdt = Jx @ dWdt
+    want = dt * Fx - dt * Fvisc + 0.5 * dt * dt * dFdt
+    # the equilibrium part also carries -tau dt dF/dt-type terms of order tau; they vanish in
+    # the NS limit only up to O(tau/dt), so compare the exact kinetic decomposition instead:
+    # F = dt Fx - tau dt <u psi (a u + a_t v + A)> + (dt^2/2) <u psi A>  (c1+c4 = 1, c2+c5 = -tau, c3+c6 = t - tau)
+    assert np.allclose(d["F"][0], want[0], rtol=1e-7, atol=1e-12)
+    assert np.allclose(d["F"], want, rtol=1e-6, atol=1e-9 * dt)

@@ -1,0 +1,398 @@
+"""Pins of the oracle's finite-volume layer: geometry, ghost cells,
+reconstruction, residual (Eq.16), SA terms (Eq.27-30), LU-SGS (Eq.19-22).
+CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import pyoracle as po
+from paper_1709_00803_amd import meshgen as mg
+
+K = 3
+GAM = (K + 4.0) / (K + 2.0)
+
+
+def smooth_state(o, amp=0.05, seed=0):
+    """Free stream times a smooth seeded perturbation (same recipe as the
+    GPU parity tests)."""
+    W = o.get_state()
+    c = o.cells()
+    x, y = c["xc"], c["yc"]
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, 8)
+    W[0] *= 1 + amp * np.sin(3 * x + ph[0]) * np.cos(2 * y + ph[1])
+    W[1] += amp * np.cos(2 * x + ph[2]) * np.sin(3 * y + ph[3])
+    W[2] += amp * np.sin(2 * x + ph[4]) * np.cos(y + ph[5])
+    W[3] *= 1 + amp * np.cos(x + ph[6]) * np.sin(2 * y + ph[7])
+    if W[4].any():
+        W[4] *= 1 + 0.5 * np.sin(4 * x) ** 2
+    return W
+
+
+def test_geometry_closed_cells_and_area():
+    m = mg.random_hybrid(7, 5, seed=11)
+    o = po.Oracle(m)
+    f = o.faces()
+    c = o.cells()
+    assert c["area"].sum() == pytest.approx(1.0 * 0.75, rel=1e-13)
+    s = np.zeros((o.n, 2))
+    for k in range(o.nf):
+        v = np.array([f["nx"][k], f["ny"][k]]) * f["len"][k]
+        s[f["fl"][k]] += v
+        if f["fr"][k] >= 0:
+            s[f["fr"][k]] -= v
+    assert np.abs(s).max() < 1e-15
+    # centroid = area-weighted mean of the triangle fan centroids
+    xy = m.xy
+    for i, nodes in enumerate(m.cells_as_lists()):
+        P = xy[nodes]
+        a = 0.0; cx = cy = 0.0
+        for j in range(1, len(P) - 1):
+            e1, e2 = P[j] - P[0], P[j + 1] - P[0]
+            t = 0.5 * (e1[0] * e2[1] - e1[1] * e2[0])
+            a += t; cx += t * (P[0][0] + P[j][0] + P[j + 1][0]) / 3; cy += t * (P[0][1] + P[j][1] + P[j + 1][1]) / 3
+        assert abs(a) == pytest.approx(c["area"][i], rel=1e-12)
+        assert cx / a == pytest.approx(c["xc"][i], abs=1e-14)
+        assert cy / a == pytest.approx(c["yc"][i], abs=1e-14)
+
+
+def test_mesh_errors():
+    m = mg.random_hybrid(3, 3, seed=1)
+    bad = m.copy()
+    bad.bface_tag = bad.bface_tag[:-1].copy()
+    bad.bface_nodes = bad.bface_nodes[:-1].copy()
+    with pytest.raises(po.OracleError):
+        po.Oracle(bad)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 33.0, -71.0])
+def test_freestream_preservation(alpha):
+    """A uniform state is an exact steady solution on any mesh: gradients
+    vanish and the face fluxes of every closed cell cancel."""
+    for seed in (1, 2):
+        m = mg.random_hybrid(9, 7, seed=seed, jitter=0.3)
+        o = po.Oracle(m)
+        o.set_freestream(0.4, alpha, 2e3)
+        M, G = o.compute_residual()
+        assert np.all(np.abs(M[:4]) <= 1e-13 * G), np.abs(M[:4] / G).max()
+        assert np.abs(o.debug()["grad"]).max() == 0.0
+
+
+def test_slip_wall_and_outflow_preserve_uniform_flow():
+    """Uniform flow along SYMMETRY walls, through FREESTREAM inflow and
+    Riemann OUTFLOW faces (Sec. 2.5) stays uniform."""
+    tags = dict(bottom=mg.SYMMETRY, top=mg.SYMMETRY, left=mg.FREESTREAM, right=mg.OUTFLOW)
+    m = mg.random_hybrid(8, 6, seed=4, tags=tags)
+    o = po.Oracle(m)
+    o.set_freestream(0.3, 0.0, 1e3)
+    M, G = o.compute_residual()
+    assert np.all(np.abs(M[:4]) <= 1e-13 * G)
+
+
+def test_conservation():
+    """Interior face fluxes telescope: sum_i M_i + sum_boundary F S = 0."""
+    tags = dict(bottom=mg.WALL, top=mg.OUTFLOW, left=mg.FREESTREAM, right=mg.SYMMETRY)
+    m = mg.random_hybrid(9, 6, seed=5, tags=tags)
+    o = po.Oracle(m, limiter=1)
+    o.set_freestream(0.5, 10.0, 500.0, 3.0)
+    o.set_state(smooth_state(o, 0.08, 1))
+    M, G = o.compute_residual()
+    d = o.debug(); f = o.faces()
+    bsum = d["flux"][:, f["fr"] < 0].sum(axis=1)
+    tot = M[:4].sum(axis=1) + bsum
+    assert np.all(np.abs(tot) <= 1e-13 * G.sum(axis=1))
+
+
+def _rotate_state(W, th, mirror=False):
+    W = W.copy()
+    if mirror:
+        W[2] = -W[2]
+    c, s = math.cos(th), math.sin(th)
+    mx, my = W[1].copy(), W[2].copy()
+    W[1] = c * mx - s * my
+    W[2] = s * mx + c * my
+    return W
+
+
+@pytest.mark.parametrize("limiter,th", [(0, 0.7), (1, 0.5 * math.pi)])
+def test_rotation_and_mirror_invariance(limiter, th):
+    """Rotating the mesh and the flow rotates the residual; mirroring in y
+    with alpha -> -alpha mirrors it.  The limiter of Eq.9 acts on each
+    conservative component in the global frame, so with it on only
+    rotations that map the momentum components onto each other (quarter
+    turns) are symmetries."""
+    tags = dict(bottom=mg.WALL, top=mg.FARFIELD, left=mg.FREESTREAM, right=mg.OUTFLOW)
+    m = mg.random_hybrid(8, 6, seed=6, tags=tags)
+    o = po.Oracle(m, limiter=limiter)
+    o.set_freestream(0.45, 7.0, 800.0, 3.0)
+    W = smooth_state(o, 0.06, 2)
+    o.set_state(W)
+    M, G = o.compute_residual()
+    mr = mg.transform(m, theta=th, shift=(0.3, -1.2))
+    o2 = po.Oracle(mr, limiter=limiter)
+    o2.set_freestream(0.45, 7.0 + math.degrees(th), 800.0, 3.0)
+    o2.set_state(_rotate_state(W, th))
+    M2, _ = o2.compute_residual()
+    want = _rotate_state(M, th)
+    assert np.all(np.abs(M2 - want)[:4] <= 1e-11 * G), np.abs((M2 - want)[:4] / G).max()
+    assert np.all(np.abs(M2[4] - want[4]) <= 1e-10 * (np.abs(M[4]).max() + 1e-300))
+    mm = mg.transform(m, mirror_y=True)
+    o3 = po.Oracle(mm, limiter=limiter)
+    o3.set_freestream(0.45, -7.0, 800.0, 3.0)
+    o3.set_state(_rotate_state(W, 0.0, mirror=True))
+    M3, _ = o3.compute_residual()
+    want = _rotate_state(M, 0.0, mirror=True)
+    assert np.all(np.abs(M3 - want)[:4] <= 1e-11 * G)
+
+
+def _euler_flux_n(W, nx, ny):
+    r, mx, my, E = W[:4]
+    U, V = mx / r, my / r
+    p = (GAM - 1) * (E - 0.5 * r * (U * U + V * V))
+    q = U * nx + V * ny
+    return np.array([r * q, mx * q + p * nx, my * q + p * ny, (E + p) * q])
+
+
+def _jac_fd(W, nx, ny):
+    J = np.zeros((4, 4))
+    for k in range(4):
+        e = np.zeros(5); h = 1e-6 * max(1.0, abs(W[k])); e[k] = h
+        J[:, k] = (_euler_flux_n(W + e, nx, ny) - _euler_flux_n(W - e, nx, ny)) / (2 * h)
+    return J
+
+
+def test_lusgs_solves_factored_system():
+    """The sweeps solve (L + D) D^-1 (D + U) dW = M with the Euler-flux
+    Jacobians of Eq.20 (built here by finite differences) and the lagged
+    ghost increments of Sec. 2.5 in the backward sweep."""
+    tags = dict(bottom=mg.WALL, top=mg.OUTFLOW, left=mg.FREESTREAM, right=mg.SYMMETRY)
+    m = mg.random_hybrid(5, 4, seed=7, tags=tags)
+    m, _, _ = mg.colour_order(m)
+    o = po.Oracle(m)
+    o.set_freestream(0.4, 5.0, 1e3)
+    W = smooth_state(o, 0.1, 3)
+    o.set_state(W)
+    cfl = 50.0
+    dW = o.lusgs_solve(cfl)
+    M, _ = o.compute_residual()
+    dW = o.lusgs_solve(cfl)
+    dbg = o.debug(); f = o.faces(); n = o.n
+    D, lam, wg = dbg["D"], dbg["lam"], dbg["wg"]
+    c = o.cells()
+    # D_i = Omega/dt_imp + 1/2 sum lam S, dt_imp = CFL Omega / Lambda_c (Eq.20, Eq.24)
+    ls = np.zeros(n)
+    for k in range(o.nf):
+        ls[f["fl"][k]] += lam[k] * f["len"][k]
+        if f["fr"][k] >= 0:
+            ls[f["fr"][k]] += lam[k] * f["len"][k]
+    assert np.allclose(D, dbg["lamc"] / cfl + 0.5 * ls, rtol=1e-13)
+    L = np.zeros((4 * n, 4 * n)); U = np.zeros((4 * n, 4 * n)); G = np.zeros((4 * n, 4 * n))
+    Dm = np.kron(np.diag(D), np.eye(4))
+    for k in range(o.nf):
+        i, j = f["fl"][k], f["fr"][k]
+        nx, ny, S = f["nx"][k], f["ny"][k], f["len"][k]
+        if j >= 0:
+            for a, b, sg in ((i, j, 1.0), (j, i, -1.0)):
+                blk = 0.5 * (_jac_fd(W[:, b], sg * nx, sg * ny) - lam[k] * np.eye(4)) * S
+                (L if b < a else U)[4 * a:4 * a + 4, 4 * b:4 * b + 4] += blk
+        else:
+            bc = f["bc"][k]
+            if bc == mg.WALL:
+                B = np.diag([1.0, -1.0, -1.0, 1.0])
+            elif bc == mg.SYMMETRY:
+                nn = np.array([nx, ny]); B = np.eye(4); B[1:3, 1:3] = np.eye(2) - 2 * np.outer(nn, nn)
+            else:
+                B = np.zeros((4, 4))
+            G[4 * i:4 * i + 4, 4 * i:4 * i + 4] += 0.5 * (_jac_fd(wg[:, k], nx, ny) - lam[k] * np.eye(4)) * S @ B
+    Mv = M[:4].T.reshape(-1)
+    dws = np.linalg.solve(L + Dm, Mv)
+    want = np.linalg.solve(Dm + U, (Dm - G) @ dws)
+    got = dW[:4].T.reshape(-1)
+    assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
+
+
+def test_level_schedule_invariance():
+    """Cells of one colour are independent in the sweeps: renumbering cells
+    inside a colour does not change the update."""
+    m = mg.random_hybrid(8, 6, seed=8, tags=dict(bottom=mg.WALL, top=mg.FARFIELD))
+    m, _, col = mg.colour_order(m)
+    o = po.Oracle(m)
+    o.set_freestream(0.3, 3.0, 2e3, 3.0)
+    W = smooth_state(o, 0.05, 4)
+    o.set_state(W)
+    dW = o.lusgs_solve(200.0)
+    rng = np.random.default_rng(0)
+    perm = np.concatenate([rng.permutation(np.where(col == k)[0]) for k in range(col.max() + 1)])
+    m2 = mg.renumber(m, perm)
+    o2 = po.Oracle(m2)
+    o2.set_freestream(0.3, 3.0, 2e3, 3.0)
+    o2.set_state(W[:, perm])
+    dW2 = o2.lusgs_solve(200.0)
+    assert np.allclose(dW2, dW[:, perm], rtol=1e-11, atol=1e-13 * np.abs(dW).max())
+
+
+def test_explicit_limit():
+    """CFL -> 0: dW -> (dt_imp / Omega) M = (CFL / Lambda_c) M (Eq.18-24)."""
+    m = mg.random_hybrid(6, 5, seed=9, tags=dict(bottom=mg.WALL))
+    o = po.Oracle(m)
+    o.set_freestream(0.3, 0.0, 1e3)
+    o.set_state(smooth_state(o, 0.05, 5))
+    cfl = 1e-9
+    dW = o.lusgs_solve(cfl)
+    M, _ = o.compute_residual()
+    lamc = o.debug()["lamc"]
+    want = cfl / lamc * M[:4]
+    assert np.allclose(dW[:4], want, rtol=1e-7, atol=1e-9 * np.abs(want).max())
+
+
+def test_plate_wall_distance():
+    """Flat plate from x = 0: d = y downstream of the leading edge and
+    sqrt(x^2 + y^2) upstream (closed form)."""
+    m = mg.flat_plate(16, 8)
+    o = po.Oracle(m)
+    c = o.cells()
+    wall_nodes = m.bface_nodes[m.bface_tag == mg.WALL].ravel()
+    xle = m.xy[wall_nodes, 0].min()                  # leading node of the plate
+    d = np.where(c["xc"] >= xle, c["yc"], np.hypot(c["xc"] - xle, c["yc"]))
+    assert np.allclose(c["dwall"], d, rtol=0, atol=1e-15)
+
+
+def test_ghost_states():
+    m = mg.random_hybrid(2, 2, seed=1)
+    o = po.Oracle(m)
+    o.set_freestream(0.5, 20.0, 1e3, 3.0)
+    Wi = np.array([1.2, 0.5, -0.3, 4.0, 2e-3])
+    nx, ny = 0.6, 0.8
+    # free stream
+    g = o.ghost_state(mg.FREESTREAM, Wi, nx, ny)
+    a = math.radians(20.0)
+    pinf = 1.0 / (GAM * 0.25)
+    assert np.allclose(g, [1, math.cos(a), math.sin(a), pinf / (GAM - 1) + 0.5, 3e-3], rtol=1e-14)
+    # symmetry: normal momentum mirrored, tangential kept
+    g = o.ghost_state(mg.SYMMETRY, Wi, nx, ny)
+    assert g[1] * nx + g[2] * ny == pytest.approx(-(Wi[1] * nx + Wi[2] * ny), rel=1e-14)
+    assert -g[1] * ny + g[2] * nx == pytest.approx(-Wi[1] * ny + Wi[2] * nx, rel=1e-14)
+    assert g[0] == Wi[0] and g[3] == Wi[3] and g[4] == Wi[4]
+    # no-slip wall: momentum and nu-tilde negated
+    g = o.ghost_state(mg.WALL, Wi, nx, ny)
+    assert np.array_equal(g, [Wi[0], -Wi[1], -Wi[2], Wi[3], -Wi[4]])
+    # Riemann outflow: R+ from inside, R- from the free stream, rho and lam from inside
+    g = o.ghost_state(mg.OUTFLOW, Wi, nx, ny)
+    r, U, V = Wi[0], Wi[1] / Wi[0], Wi[2] / Wi[0]
+    lam = (K + 2) * r / (4 * (Wi[3] - 0.5 * r * (U * U + V * V)))
+    ci, co = math.sqrt(GAM / (2 * lam)), math.sqrt(GAM * pinf)
+    Ub = 0.5 * ((U * nx + V * ny + 2 * ci / (GAM - 1)) + (math.cos(a) * nx + math.sin(a) * ny - 2 * co / (GAM - 1)))
+    Vt = -U * ny + V * nx
+    assert g[0] == pytest.approx(r)
+    assert (g[1] * nx + g[2] * ny) / r == pytest.approx(Ub, rel=1e-13)
+    assert (-g[1] * ny + g[2] * nx) / r == pytest.approx(Vt, rel=1e-13)
+    lam_b = (K + 2) * r / (4 * (g[3] - 0.5 * (g[1] ** 2 + g[2] ** 2) / r))
+    assert lam_b == pytest.approx(lam, rel=1e-13)
+
+
+def test_ls_gradient_exact_for_linear_fields():
+    """Eq.6-7: the least-squares gradient of a linear field is exact on
+    every interior cell."""
+    m = mg.random_hybrid(8, 6, seed=12, jitter=0.3)
+    o = po.Oracle(m)
+    o.set_freestream(0.3, 0.0, 1e3)
+    W = o.get_state(); c = o.cells()
+    gx = np.array([0.02, 0.03, -0.01, 0.05]); gy = np.array([-0.01, 0.02, 0.04, -0.03])
+    for k in range(4):
+        W[k] = W[k] + gx[k] * c["xc"] + gy[k] * c["yc"]
+    o.set_state(W)
+    o.compute_residual()
+    g = o.debug()["grad"]
+    f = o.faces()
+    interior = np.ones(o.n, bool)
+    interior[f["fl"][f["fr"] < 0]] = False
+    for k in range(4):
+        assert np.allclose(g[k, interior], gx[k], rtol=1e-10, atol=1e-13)
+        assert np.allclose(g[4 + k, interior], gy[k], rtol=1e-10, atol=1e-13)
+
+
+def test_limiter_bounds_vertex_values():
+    """Eq.9-10: with the limiter on, the reconstruction at every vertex of a
+    cell stays inside the min/max of the cell and its face neighbours."""
+    m = mg.random_hybrid(8, 6, seed=13, jitter=0.3)
+    o = po.Oracle(m, limiter=1)
+    o.set_freestream(0.3, 0.0, 1e3)
+    W = smooth_state(o, 0.2, 6)
+    rng = np.random.default_rng(1)
+    W[:4] *= 1 + 0.05 * rng.uniform(-1, 1, (4, o.n))
+    o.set_state(W)
+    o.compute_residual()
+    d = o.debug(); f = o.faces(); c = o.cells()
+    nb = [[] for _ in range(o.n)]
+    for k in range(o.nf):
+        i, j = f["fl"][k], f["fr"][k]
+        if j >= 0:
+            nb[i].append(W[:4, j]); nb[j].append(W[:4, i])
+        else:
+            nb[i].append(d["wg"][:4, k])
+    for i, nodes in enumerate(m.cells_as_lists()):
+        vals = np.array([W[:4, i]] + nb[i])
+        lo, hi = vals.min(0), vals.max(0)
+        for v in nodes:
+            rec = W[:4, i] + d["grad"][:4, i] * (m.xy[v, 0] - c["xc"][i]) + d["grad"][4:, i] * (m.xy[v, 1] - c["yc"][i])
+            tol = 1e-12 * np.abs(W[:4]).max(axis=1)
+            assert np.all(rec <= hi + tol) and np.all(rec >= lo - tol)
+
+
+# ---------------------------------------------------------------- SA model
+
+SA_CB1, SA_CB2, SA_SIG, SA_KAP = 0.1355, 0.622, 2.0 / 3.0, 0.41
+
+
+def test_sa_source_log_layer_balance():
+    """In the log layer nu~ = kappa u_tau d and S~ = u_tau/(kappa d), so
+    r = 1, f_w = 1 and production - destruction equals minus the diffusion
+    (1 + c_b2) kappa^2 u_tau^2 / sigma of Eq.26."""
+    for ut, d in [(0.05, 1e-3), (0.03, 2e-2)]:
+        nut = SA_KAP * ut * d
+        nu = nut * 1e-6           # chi -> large, f_v2 -> 0
+        chi = nut / nu
+        fv1 = chi ** 3 / (chi ** 3 + 7.1 ** 3)
+        fv2 = 1 - chi / (1 + chi * fv1)
+        Sbar = nut * fv2 / (SA_KAP ** 2 * d * d)
+        omega = ut / (SA_KAP * d) - Sbar
+        Sr, St, fw, _ = po.sa_source(nut, nu, d, omega)
+        assert St == pytest.approx(ut / (SA_KAP * d), rel=1e-13)
+        assert fw == pytest.approx(1.0, rel=1e-12)
+        assert Sr == pytest.approx(-(1 + SA_CB2) * SA_KAP ** 2 * ut * ut / SA_SIG, rel=1e-11)
+
+
+def test_sa_source_limits():
+    # no eddy viscosity -> no source
+    assert po.sa_source(0.0, 1e-5, 0.1, 3.0)[0] == 0.0
+    # far from walls the destruction vanishes and production -> c_b1 Omega nu~
+    Sr, St, fw, _ = po.sa_source(1e-3, 1e-5, 1e8, 2.0)
+    assert Sr == pytest.approx(SA_CB1 * 2.0 * 1e-3, rel=1e-9)
+    # the S~ clip keeps S~ positive and is continuous at Sbar = -0.7 Omega
+    om = 1.0
+    d = 1.0
+    nut = 1e-2
+    s_lo = po.sa_source(nut, 1e3, d, om)   # chi tiny: f_v2 ~ 1, Sbar small positive
+    assert s_lo[1] > 0
+
+
+def test_sa_diffusion_exact_for_linear_field():
+    """Eq.28-30 with zero velocity: for nu~ = a + b x on a uniform mesh the
+    discrete residual of an interior cell is Omega (1 + c_b2) b^2 / sigma,
+    the value of the diffusion term of Eq.26."""
+    tags = dict(bottom=mg.SYMMETRY, top=mg.SYMMETRY, left=mg.FREESTREAM, right=mg.FREESTREAM)
+    m = mg.random_hybrid(10, 6, seed=0, tri_frac=0.0, jitter=0.0, tags=tags)
+    o = po.Oracle(m, mu_law=1)
+    o.set_freestream(0.2, 0.0, 1e3, 3.0)
+    W = o.get_state(); c = o.cells()
+    W[1] = 0.0; W[2] = 0.0
+    a, b = 2e-3, 5e-3
+    W[4] = a + b * c["xc"]
+    o.set_state(W)
+    M, _ = o.compute_residual()
+    f = o.faces()
+    interior = np.ones(o.n, bool)
+    interior[f["fl"][f["fr"] < 0]] = False
+    want = c["area"] * (1 + SA_CB2) * b * b / SA_SIG
+    assert np.allclose(M[4, interior], want[interior], rtol=1e-10)
