@@ -1,0 +1,195 @@
+/*
+ * igks.h - C ABI of the MI355X (gfx950) implicit gas-kinetic scheme
+ * library, libigks.so.
+ *
+ * What it computes (Pan, Zhong & Zhuo, "An Implicit Gas-Kinetic Scheme for
+ * Turbulent Flow on Unstructured Hybrid Mesh"):
+ *   - per face, the BGK gas-kinetic flux of Sec. 2.1 (least-squares
+ *     reconstruction Eq.6-7 with the Eq.9-10 limiter, Maxwellian moments,
+ *     the interface distribution Eq.13 and its flux Eq.14), with the
+ *     Spalart-Allmaras working variable carried alongside (Sec. 2.3,
+ *     Eq.26-34);
+ *   - per iteration, the residual of Eq.16, the implicit CFL law Eq.24-25
+ *     and the matrix-free LU-SGS forward/backward sweeps of Eq.18-22 and
+ *     Eq.31-32, with the ghost-cell boundary conditions of Sec. 2.5;
+ *   on a 2D hybrid (triangle + quadrilateral) mesh given in the node /
+ *   per-cell vertex list form of Sec. 2.4, on one GPU.
+ *
+ * Conventions
+ *   - Every call returns an int status: IGKS_OK (0) or a negative error
+ *     code; igks_last_error() gives a message.  A context is used by one
+ *     host thread at a time; there is no global state.
+ *   - Host pointers are read or written during the call only (copied); the
+ *     caller keeps ownership.  Device memory comes from the caller: the
+ *     library asks for a workspace size and works inside that one buffer,
+ *     and never allocates or frees device memory itself.
+ *   - All work is queued on the HIP stream given at creation (or, for a
+ *     NULL stream, on a stream the library creates at default priority).
+ *     Calls that return host data synchronise that stream.
+ *   - Cells are numbered as uploaded.  The Gauss-Seidel sweeps visit them
+ *     in increasing (forward) and decreasing (backward) index: the
+ *     "j < i" and "j > i" of Eq.20.  The library runs each sweep as
+ *     wavefronts of mutually independent cells, which gives the same result
+ *     as the sequential sweep; fewer wavefronts = more parallel work per
+ *     launch, so callers that want speed number cells by a colouring.
+ *   - Non-dimensionalisation: rho_inf = 1, |V_inf| = 1, reference length 1,
+ *     p_inf = 1/(gamma Ma^2), mu_inf = 1/Re; gamma = 1.4 (K = 3, Sec. 2.1).
+ */
+#ifndef IGKS_H
+#define IGKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define IGKS_OK 0
+#define IGKS_EINVAL (-1)   /* bad argument or call order */
+#define IGKS_EMESH (-2)    /* invalid mesh (see igks_mesh_upload) */
+#define IGKS_ENOMEM (-3)   /* workspace too small */
+#define IGKS_ENONPHYS (-4) /* an update produced rho <= 0, p <= 0 or a non-finite value */
+#define IGKS_EHIP (-5)     /* a HIP runtime call failed */
+
+/* boundary tags of boundary edges (Sec. 2.5) */
+#define IGKS_BC_FREESTREAM 1 /* ghost = free stream, ghost increment 0 */
+#define IGKS_BC_SYMMETRY 2   /* normal momentum mirrored */
+#define IGKS_BC_WALL 3       /* no-slip: momentum and nu-tilde negated */
+#define IGKS_BC_OUTFLOW 4    /* Riemann-invariant outflow, ghost increment 0 */
+#define IGKS_BC_FARFIELD 5   /* FREESTREAM where V_inf . n < 0, else OUTFLOW */
+
+/* precision of the implicit sweeps */
+#define IGKS_FP64 0  /* everything in FP64 */
+#define IGKS_MIXED 1 /* LU-SGS sweeps and Jacobian products in FP32; residual, update, SA source FP64 */
+
+typedef struct igks_options {
+    int precision;      /* IGKS_FP64 or IGKS_MIXED */
+    int limiter;        /* 0: off, 1: the limiter of Eq.9-10 */
+    double cfl_init;    /* implicit CFL of the first iteration (Eq.25 start) */
+    double cfl_min;     /* clamp of the Eq.25 CFL */
+    double cfl_max;
+    int cfl_mode;       /* 0: Eq.25 (residual-ratio law), 1: fixed cfl_init */
+    double cfl_flux;    /* delta_CFL0 of Eq.23 (time step inside the flux) */
+    int visc_sr;        /* 1: add 2 nu_eff / |r.n| to the LU-SGS spectral radius */
+    int mu_law;         /* 0: Sutherland, 1: constant viscosity */
+    int chunk;          /* iterations per captured HIP graph launch; 0 = no graph */
+    int block;          /* threads per block of the cell/face kernels; 0 = 256 */
+} igks_options;
+
+typedef struct igks_residual {
+    int32_t iteration;  /* iterations committed so far */
+    double res_l2;      /* ||M_rho||_2 of the last residual evaluation (Eq.16) */
+    double res_drop;    /* res_l2 / res_l2 of the first iteration */
+    double res_inf;     /* max over cells and the 4 flow components of |M| */
+    double eq40;        /* max_i ||W_i^{n+1} - W_i^n||_2 / ||W_i^n||_2 (Eq.40) */
+    double cfl;         /* implicit CFL used by the last update (Eq.25) */
+    double dt_flux;     /* Eq.23 time step used inside the flux */
+    double sa_l2;       /* ||R_SA||_2 (Eq.27 right-hand side) */
+} igks_residual;
+
+/* iteration scalars for checkpoint / resume */
+typedef struct igks_scalars {
+    int32_t iteration;
+    double cfl;          /* CFL of the last committed iteration */
+    double res_inf_prev; /* ||M||_inf of the last committed iteration */
+    double res0;         /* ||M_rho||_2 of the first iteration */
+} igks_scalars;
+
+typedef struct igks_ctx igks_ctx;
+
+/* Fill *opt with the defaults: FP64, limiter off, cfl_init 1000 (Sec. 3.1),
+ * cfl_min 1, cfl_max 1e6, Eq.25 law, cfl_flux 1, visc_sr on, Sutherland,
+ * chunk 20, block 256. */
+void igks_default_options(igks_options *opt);
+
+/* Create a context.  opt may be NULL (defaults).  hip_stream is a
+ * hipStream_t (NULL: the library creates its own).  *out owns the
+ * context until igks_destroy. */
+int igks_create(igks_ctx **out, const igks_options *opt, void *hip_stream);
+void igks_destroy(igks_ctx *ctx);
+const char *igks_last_error(const igks_ctx *ctx);
+
+/* Mesh in the form of Sec. 2.4: n_nodes coordinates xy[2*n_nodes]
+ * (x0,y0,x1,y1,...); cells as CSR: vertices of cell i are
+ * cell_nodes[cell_ptr[i] .. cell_ptr[i+1]-1], 3 or 4 of them, either
+ * orientation; n_bfaces boundary edges bface_nodes[2*b], [2*b+1] with tags
+ * bface_tag[b] (IGKS_BC_*).  All host memory, copied.
+ * IGKS_EMESH: a cell with fewer than 3 or more than 4 nodes, a degenerate
+ * (zero-area) cell, an edge shared by more than two cells, a cell edge on
+ * the boundary without a tag, a tagged edge that is not on the boundary, a
+ * bad tag, or a node index out of range.  Replaces any previous mesh and
+ * unbinds the workspace. */
+int igks_mesh_upload(igks_ctx *ctx, int32_t n_nodes, const double *xy, int32_t n_cells,
+                     const int32_t *cell_ptr, const int32_t *cell_nodes, int32_t n_bfaces,
+                     const int32_t *bface_nodes, const int32_t *bface_tag);
+
+/* Sizes of the uploaded mesh: cells, faces, wall faces, sweep wavefronts. */
+int igks_mesh_info(const igks_ctx *ctx, int32_t *n_cells, int32_t *n_faces, int32_t *n_wall_faces,
+                   int32_t *n_levels);
+
+/* Device bytes the library needs for the uploaded mesh and options. */
+int igks_workspace_size(const igks_ctx *ctx, size_t *bytes);
+
+/* Bind caller-owned device memory (at least igks_workspace_size bytes,
+ * 256-byte aligned), upload the mesh data into it and compute the wall
+ * distance on the GPU.  The caller keeps the buffer alive until the
+ * context is destroyed or rebound.  IGKS_ENOMEM if too small. */
+int igks_bind_workspace(igks_ctx *ctx, void *dptr, size_t bytes);
+
+/* Free stream (Mach, angle of attack in degrees, Reynolds number per unit
+ * reference length, nu-tilde_inf / nu_inf).  nut_ratio < 0 runs laminar
+ * (no SA equation).  Sets every cell to the free stream (impulsive start),
+ * the iteration counter to 0 and the CFL to cfl_init.  IGKS_EINVAL if
+ * Ma <= 0 or Re <= 0 or no workspace is bound. */
+int igks_set_freestream(igks_ctx *ctx, double mach, double alpha_deg, double reynolds, double nut_ratio);
+
+/* Run n nonlinear iterations (residual, CFL law, LU-SGS sweeps, update).
+ * Work is queued in chunks of opt.chunk iterations (one HIP graph launch
+ * each) and the stream is synchronised at each chunk end.  *n_done (may be
+ * NULL) = iterations committed.  IGKS_ENONPHYS: an update was rejected;
+ * the state is the last committed iterate. */
+int igks_iterate(igks_ctx *ctx, int32_t n, int32_t *n_done);
+
+/* Scalars of the last iteration. */
+int igks_get_residual(igks_ctx *ctx, igks_residual *out);
+
+/* Per-iteration history of the last igks_iterate call: up to max entries
+ * of 6 doubles each (res_l2, res_inf, cfl, dt_flux, eq40, sa_l2), oldest
+ * first.  *n_out = entries written. */
+int igks_get_history(igks_ctx *ctx, double *out, int32_t max, int32_t *n_out);
+
+/* State, SoA host array W[k * n_cells + i], k = rho, rho U, rho V, rho E,
+ * nu-tilde, in upload cell order. */
+int igks_get_state(igks_ctx *ctx, double *W);
+/* Set the state (same layout).  sc may be NULL (iteration 0, CFL =
+ * cfl_init) or the scalars of a checkpoint.  IGKS_ENONPHYS (state left
+ * unchanged) if a cell has rho <= 0, p <= 0 or a non-finite value. */
+int igks_set_state(igks_ctx *ctx, const double *W, const igks_scalars *sc);
+int igks_get_scalars(igks_ctx *ctx, igks_scalars *out);
+
+/* Residual of the current state, SoA host array M[k * n_cells + i]:
+ * k = 0..3 the flow residual M of Eq.16 (minus the sum of the outgoing
+ * face fluxes times face length), k = 4 the SA right-hand side
+ * Omega Sr + R of Eq.27.  Does not advance the iteration. */
+int igks_compute_residual(igks_ctx *ctx, double *M);
+
+/* Wall loads of the current state from the face fluxes through WALL
+ * faces: lift and drag coefficients per unit span (reference
+ * 0.5 rho_inf |V_inf|^2 times length 1) and, per wall face in the order the
+ * WALL edges appear in the uploaded boundary list, Cp, Cf and the x of the
+ * face midpoint.  Every pointer may be NULL; arrays hold n_wall_faces. */
+int igks_get_wall_loads(igks_ctx *ctx, double *cl, double *cd, double *cf, double *cp, double *xw);
+
+/* Average duration (ms) of each kernel class over the last igks_iterate
+ * call, measured with HIP events when opt.chunk == 0 and profiling was
+ * enabled by igks_set_profiling(ctx, 1); 0 otherwise.  Order: prep, flux,
+ * gather, reduce, sweep_fwd (all levels), sweep_bwd (all levels), update. */
+int igks_set_profiling(igks_ctx *ctx, int on);
+int igks_get_kernel_times(igks_ctx *ctx, double *ms7);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IGKS_H */

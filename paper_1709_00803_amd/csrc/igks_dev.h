@@ -1,0 +1,93 @@
+// igks_dev.h - data shared by the host driver and the HIP kernels of
+// libigks (gfx950).  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace igks {
+
+// Sec. 2.1 after Eq.2: K = 3 internal degrees of freedom; gamma = (K+4)/(K+2).
+constexpr int KDOF = 3;
+constexpr double GAMMA = (KDOF + 4.0) / (KDOF + 2.0);
+
+enum { BC_FREESTREAM = 1, BC_SYMMETRY = 2, BC_WALL = 3, BC_OUTFLOW = 4, BC_FARFIELD = 5 };
+
+// cell -> face entry flags
+constexpr int CF_OWNER = 1;   // the cell is the face's owner (normal points outward)
+constexpr int CF_LOWER = 2;   // interior neighbour with a smaller upload index
+
+constexpr int MAXV = 4;       // vertices per cell (triangles padded by repeating a vertex)
+constexpr int HIST_W = 6;     // doubles per history entry
+constexpr int RED_THREADS = 256;
+
+// Per-context scalars living in device memory.  Integer atomics only:
+// non-negative doubles compare like their bit patterns, so min/max of
+// them is exact and order independent.
+struct DevScalars {
+    unsigned long long dtmin_bits;   // Eq.23 minimum over cells
+    unsigned long long resinf_bits;  // max |M|
+    unsigned long long e40_bits;     // Eq.40 maximum
+    int bad;                         // an update produced a non-physical state
+    int halt;                        // stop the rest of the queued work
+    int ncommit;                     // committed iterations; its parity picks the state buffer
+    int hist_n;                      // history entries of the current chunk
+    double cfl;                      // implicit CFL of the current iteration
+    double res_inf_prev;             // ||M||_inf of the previous iteration
+    double res0;                     // ||M_rho||_2 of iteration 0
+    double res_l2, sa_l2, res_inf, dt_flux, e40;
+};
+
+template <typename T>
+struct Params {
+    int nc, nf;
+    int sa, limiter, visc_sr, mu_law, cfl_mode;
+    double cfl_init, cfl_min, cfl_max, cfl_flux;
+    double Winf[5];
+    double lam_inf, mu_inf, p_inf;
+    // cell arrays (SoA, internal order)
+    double *Wa, *Wb;           // state ping-pong, 5 x nc
+    double *grad;              // limited gradients: d/dx of rho, rhoU, rhoV, rhoE, then d/dy
+    double *lamc;              // Eq.21 spectral radius sum
+    double *vort;              // |dV/dx - dU/dy| (unlimited gradients)
+    double *nu;                // laminar kinematic viscosity
+    double *M;                 // residual: 4 flow components + SA right-hand side
+    double *lsum;              // 1/2 sum lambda S (Eq.20 diagonal)
+    double *sadiag;            // SA diagonal without Omega/dt
+    T *dW;                     // LU-SGS increment, 5 x nc
+    const double *xc, *yc, *area, *lsinv, *dwall, *vtx;
+    const int *cf_ptr, *cf_face, *cf_nbr, *cf_flag;
+    const double *cf_dx, *cf_dy;
+    // face arrays (internal face order)
+    const int *fl, *fr, *fbc;
+    const double *fnx, *fny, *flen, *frl, *frr, *fdl, *fdr, *frn;
+    double *flux;              // 4 x nf: time-averaged flux times length, global frame
+    double *lam;               // spectral radius per face
+    double *saf;               // SA: (-F_inv + F_vis) S
+    double *sag;               // SA: (nu~_r - nu~_l)/|r.n| S
+    double *part;              // 2 x max_blocks reduction partials
+    int max_blocks;
+    double *hist;              // HIST_W x hist_cap
+    int hist_cap;
+    DevScalars *sc;
+};
+
+// launchers (igks_kernels.hip)
+struct Launch {
+    hipStream_t s;
+    int block;
+};
+template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int mode);
+template <typename T> void launch_prep(const Launch &L, const Params<T> &P);
+template <typename T> void launch_flux(const Launch &L, const Params<T> &P);
+template <typename T> void launch_gather(const Launch &L, const Params<T> &P);
+template <typename T> void launch_reduce(const Launch &L, const Params<T> &P);
+template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd);
+template <typename T> void launch_update(const Launch &L, const Params<T> &P);
+template <typename T> void launch_commit(const Launch &L, const Params<T> &P);
+void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, int nw,
+                          const double *wseg, double *dwall);
+void launch_gather_faces(const Launch &L, int n, const int *faces, const double *flux, int nf, double *out);
+void launch_set_state(const Launch &L, int nc, const double *Winf, double *W);
+
+}  // namespace igks

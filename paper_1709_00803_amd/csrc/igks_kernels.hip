@@ -1,0 +1,911 @@
+// igks_kernels.hip - HIP kernels of the implicit gas-kinetic scheme for
+// gfx950 (MI355X).
+//
+// One iteration = prep (per cell) -> flux (per face) -> gather (per cell)
+// -> reduce (one block) -> forward sweep (one launch per wavefront) ->
+// backward sweep -> update (per cell) -> commit (one thread).
+//
+// Data are structure-of-arrays in the library's internal cell order
+// (wavefront, then upload index) and face order (owner cell).  Face results
+// go to per-face arrays and every cell sums its faces in a fixed order, so
+// results are deterministic without floating-point atomics; the only
+// atomics are integer min/max on the bit patterns of non-negative doubles.
+#include "igks_dev.h"
+
+#include <math.h>
+
+namespace igks {
+
+// ---------------------------------------------------------------- helpers
+
+// Sutherland's law relative to the 288.15 K free stream, T/T_inf = lam_inf/lam.
+template <typename T>
+__device__ __forceinline__ double mu_lam(const Params<T> &P, double lam)
+{
+    if (P.mu_law) return P.mu_inf;
+    const double S = 110.4 / 288.15;
+    double th = P.lam_inf / lam;
+    return P.mu_inf * th * sqrt(th) * (1.0 + S) / (th + S);
+}
+
+__device__ __forceinline__ double lam_of(const double *w)
+{
+    double r = w[0], U = w[1] / r, V = w[2] / r;
+    return (KDOF + 2.0) * r / (4.0 * (w[3] - 0.5 * r * (U * U + V * V)));
+}
+
+__device__ __forceinline__ double sa_fv1(double chi)
+{
+    double c3 = chi * chi * chi;
+    return c3 / (c3 + 7.1 * 7.1 * 7.1);
+}
+
+// SA constants (standard model without the f_t2 term)
+#define SA_CB1 0.1355
+#define SA_CB2 0.622
+#define SA_SIGMA (2.0 / 3.0)
+#define SA_KAPPA 0.41
+#define SA_CW2 0.3
+#define SA_CW3 2.0
+
+// Eq.28a source and the non-negative part of -dSr/dnu~ (implicit diagonal).
+__device__ __forceinline__ void sa_source(double nut, double nu, double d, double om, double &Sr, double &jd)
+{
+    const double cw1 = SA_CB1 / (SA_KAPPA * SA_KAPPA) + (1.0 + SA_CB2) / SA_SIGMA;
+    double k2d2 = SA_KAPPA * SA_KAPPA * d * d;
+    double chi = nut / nu;
+    double fv2 = 1.0 - chi / (1.0 + chi * sa_fv1(chi));
+    double Sb = nut * fv2 / k2d2;
+    double St = (Sb >= -0.7 * om) ? om + Sb : om + om * (0.49 * om + 0.9 * Sb) / ((0.9 - 1.4) * om - Sb);
+    double r = (St > 0.0) ? nut / (St * k2d2) : 10.0;
+    r = fmin(r, 10.0);
+    double r2 = r * r, r6 = r2 * r2 * r2;
+    double g = r + SA_CW2 * (r6 - r);
+    double g2 = g * g, g6 = g2 * g2 * g2;
+    const double c6 = 64.0;   // c_w3^6
+    double fw = g * pow((1.0 + c6) / (g6 + c6), 1.0 / 6.0);
+    Sr = SA_CB1 * St * nut - cw1 * fw * (nut / d) * (nut / d);
+    jd = fmax(2.0 * cw1 * fw * nut / (d * d) - SA_CB1 * St, 0.0);
+}
+
+// Ghost cell-centre state across a boundary face with outward unit normal n
+// (Sec. 2.5).
+template <typename T>
+__device__ __forceinline__ void ghost(const Params<T> &P, int bc, const double *w, double nx, double ny, double *g)
+{
+    if (bc == BC_FREESTREAM) {
+#pragma unroll
+        for (int k = 0; k < 5; k++) g[k] = P.Winf[k];
+        return;
+    }
+    double r = w[0], mx = w[1], my = w[2];
+    if (bc == BC_SYMMETRY) {
+        double mn = mx * nx + my * ny;
+        g[0] = r; g[1] = mx - 2.0 * mn * nx; g[2] = my - 2.0 * mn * ny; g[3] = w[3]; g[4] = w[4];
+        return;
+    }
+    if (bc == BC_WALL) {
+        g[0] = r; g[1] = -mx; g[2] = -my; g[3] = w[3]; g[4] = -w[4];
+        return;
+    }
+    // Riemann-invariant outflow: U_b from R+ (inside) and R- (free stream),
+    // rho and lam from inside, tangential velocity from inside.
+    double U = mx / r, V = my / r, lam = lam_of(w);
+    double ci = sqrt(GAMMA / (2.0 * lam));
+    double co = sqrt(GAMMA / (2.0 * P.lam_inf));
+    double Ui = U * nx + V * ny;
+    double Uo = P.Winf[1] * nx + P.Winf[2] * ny;
+    double Ub = 0.5 * ((Ui + 2.0 * ci / (GAMMA - 1.0)) + (Uo - 2.0 * co / (GAMMA - 1.0)));
+    double Vt = -U * ny + V * nx;
+    g[0] = r;
+    g[1] = r * (Ub * nx - Vt * ny);
+    g[2] = r * (Ub * ny + Vt * nx);
+    g[3] = 0.5 * r * (Ub * Ub + Vt * Vt + (KDOF + 2.0) / (2.0 * lam));
+    g[4] = w[4];
+}
+
+// ghost increments (Sec. 2.5)
+template <typename V>
+__device__ __forceinline__ void ghost_incr(int bc, const V *d, V nx, V ny, V *g)
+{
+    if (bc == BC_SYMMETRY) {
+        V mn = d[1] * nx + d[2] * ny;
+        g[0] = d[0]; g[1] = d[1] - V(2) * mn * nx; g[2] = d[2] - V(2) * mn * ny; g[3] = d[3]; g[4] = d[4];
+    } else if (bc == BC_WALL) {
+        g[0] = d[0]; g[1] = -d[1]; g[2] = -d[2]; g[3] = d[3]; g[4] = -d[4];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; k++) g[k] = V(0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ const double *cur_state(const Params<T> &P)
+{
+    return (P.sc->ncommit & 1) ? P.Wb : P.Wa;
+}
+
+// ------------------------------------------------------- kinetic building blocks
+
+// <u^k>, k = 0..7, of the normalised Maxwellian exp(-lam (u-U)^2) on the
+// whole line (S = 0), on u > 0 (S = +1) or on u < 0 (S = -1).
+template <int S>
+__device__ __forceinline__ void mom_u(double U, double lam, double *m)
+{
+    if (S == 0) {
+        m[0] = 1.0; m[1] = U;
+    } else {
+        double x = sqrt(lam) * U;
+        double e = exp(-x * x) * (0.5 / sqrt(M_PI * lam));
+        if (S > 0) { m[0] = 0.5 * erfc(-x); m[1] = U * m[0] + e; }
+        else { m[0] = 0.5 * erfc(x); m[1] = U * m[0] - e; }
+    }
+    double h = 0.5 / lam;
+#pragma unroll
+    for (int k = 0; k < 6; k++) m[k + 2] = U * m[k + 1] + (k + 1) * h * m[k];
+}
+// <xi^0>, <xi^2>, <xi^4> over K internal dimensions
+__device__ __forceinline__ void mom_xi(double lam, double *x)
+{
+    x[0] = 1.0;
+    x[1] = KDOF / (2.0 * lam);
+    x[2] = x[1] * (KDOF + 2.0) / (2.0 * lam);
+}
+
+// out = < u^A v^B (c0 + c1 u + c2 v + c3 (u^2+v^2+xi^2)/2) psi > with
+// psi = (1, u, v, (u^2+v^2+xi^2)/2); the exponents are compile-time so the
+// moment arrays stay in registers.
+template <int A, int B>
+__device__ __forceinline__ void pmom(const double *mu, const double *mv, const double *mx, const double *c,
+                                     double *out)
+{
+    auto h = [&](int a, int b, int x) { return mu[a] * mv[b] * mx[x]; };
+    auto t = [&](int a, int b, int x) {
+        return c[0] * h(a, b, x) + c[1] * h(a + 1, b, x) + c[2] * h(a, b + 1, x) +
+               0.5 * c[3] * (h(a + 2, b, x) + h(a, b + 2, x) + h(a, b, x + 1));
+    };
+    out[0] = t(A, B, 0);
+    out[1] = t(A + 1, B, 0);
+    out[2] = t(A, B + 1, 0);
+    out[3] = 0.5 * (t(A + 2, B, 0) + t(A, B + 2, 0) + t(A, B, 1));
+}
+// <u^A psi>
+template <int A>
+__device__ __forceinline__ void pmom1(const double *mu, const double *mv, const double *mx, double *out)
+{
+    out[0] = mu[A];
+    out[1] = mu[A + 1];
+    out[2] = mu[A] * mv[1];
+    out[3] = 0.5 * (mu[A + 2] + mu[A] * mv[2] + mu[A] * mx[1]);
+}
+
+// Closed-form solution of M(g) a = b for the Maxwellian moment matrix
+// M_ij = <psi_i psi_j> (Eq.101 divided by rho).
+__device__ __forceinline__ void msolve(double U, double V, double lam, const double *b, double *a)
+{
+    double B = U * U + V * V + (KDOF + 2.0) / (2.0 * lam);
+    double R2 = b[1] - U * b[0], R3 = b[2] - V * b[0], R4 = 2.0 * b[3] - B * b[0];
+    a[3] = 4.0 * lam * lam / (KDOF + 2.0) * (R4 - 2.0 * U * R2 - 2.0 * V * R3);
+    a[2] = 2.0 * lam * R3 - V * a[3];
+    a[1] = 2.0 * lam * R2 - U * a[3];
+    a[0] = b[0] - U * a[1] - V * a[2] - 0.5 * a[3] * B;
+}
+
+// Per-side part of the interface distribution that does not depend on the
+// equilibrium state: slopes a_n, a_t (Eq.4, Eq.101), A (Eq.11) and the
+// half-space moments that multiply them.  S = +1: left state on u > 0;
+// S = -1: right state on u < 0.  Accumulates (rho-weighted):
+//   w0 += <psi>, q5 += <(u a_n + v a_t) psi>, q6 += <A psi>,
+//   f4 += <u psi>, f5 += <u (u a_n + v a_t) psi>, f6 += <u A psi>.
+template <int S>
+__device__ __forceinline__ void side_terms(const double *w, const double *gn, const double *gt, double *w0,
+                                           double *q5, double *q6, double *f4, double *f5, double *f6)
+{
+    double r = w[0], U = w[1] / r, V = w[2] / r, lam = lam_of(w);
+    double an[4], at[4], A[4], b[4];
+    double ir = 1.0 / r;
+#pragma unroll
+    for (int k = 0; k < 4; k++) b[k] = gn[k] * ir;
+    msolve(U, V, lam, b, an);
+#pragma unroll
+    for (int k = 0; k < 4; k++) b[k] = gt[k] * ir;
+    msolve(U, V, lam, b, at);
+    double mv[8], mx[3], mu[8];
+    mom_u<0>(V, lam, mv);
+    mom_xi(lam, mx);
+    {
+        double mf[8], t1[4], t2[4];
+        mom_u<0>(U, lam, mf);
+        pmom<1, 0>(mf, mv, mx, an, t1);
+        pmom<0, 1>(mf, mv, mx, at, t2);
+#pragma unroll
+        for (int k = 0; k < 4; k++) b[k] = -(t1[k] + t2[k]);
+        msolve(U, V, lam, b, A);
+    }
+    mom_u<S>(U, lam, mu);
+    double t[4], s[4];
+    pmom1<0>(mu, mv, mx, t);
+#pragma unroll
+    for (int k = 0; k < 4; k++) w0[k] += r * t[k];
+    pmom1<1>(mu, mv, mx, t);
+#pragma unroll
+    for (int k = 0; k < 4; k++) f4[k] += r * t[k];
+    pmom<1, 0>(mu, mv, mx, an, t);
+    pmom<0, 1>(mu, mv, mx, at, s);
+#pragma unroll
+    for (int k = 0; k < 4; k++) q5[k] += r * (t[k] + s[k]);
+    pmom<2, 0>(mu, mv, mx, an, t);
+    pmom<1, 1>(mu, mv, mx, at, s);
+#pragma unroll
+    for (int k = 0; k < 4; k++) f5[k] += r * (t[k] + s[k]);
+    pmom<0, 0>(mu, mv, mx, A, t);
+#pragma unroll
+    for (int k = 0; k < 4; k++) q6[k] += r * t[k];
+    pmom<1, 0>(mu, mv, mx, A, t);
+#pragma unroll
+    for (int k = 0; k < 4; k++) f6[k] += r * t[k];
+}
+
+// GKS interface flux (Eq.4-5, Eq.11-14) in the face frame; returns the
+// flux integrated over [0, dt].
+template <typename T>
+__device__ __forceinline__ void gks_flux(const Params<T> &P, const double *wl, const double *gln, const double *glt,
+                                         const double *wr, const double *grn, const double *grt, const double *wlc,
+                                         const double *wrc, double dl, double dr, double dt, double nut_f,
+                                         double *F)
+{
+    double w0[4] = {0, 0, 0, 0}, q5[4] = {0, 0, 0, 0}, q6[4] = {0, 0, 0, 0};
+    double f4[4] = {0, 0, 0, 0}, f5[4] = {0, 0, 0, 0}, f6[4] = {0, 0, 0, 0};
+    side_terms<+1>(wl, gln, glt, w0, q5, q6, f4, f5, f6);
+    side_terms<-1>(wr, grn, grt, w0, q5, q6, f4, f5, f6);
+
+    // interface equilibrium g0 (moments of H g^l + (1-H) g^r)
+    double r0 = w0[0], U0 = w0[1] / r0, V0 = w0[2] / r0, lam0 = lam_of(w0);
+    double mf[8], mp[8], mm[8], mv[8], mx[3];
+    mom_u<0>(U0, lam0, mf);
+    mom_u<+1>(U0, lam0, mp);
+    mom_u<-1>(U0, lam0, mm);
+    mom_u<0>(V0, lam0, mv);
+    mom_xi(lam0, mx);
+    double abl[4], abr[4], abt[4], b[4];
+    double ir0 = 1.0 / r0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) b[k] = (w0[k] - wlc[k]) / dl * ir0;
+    msolve(U0, V0, lam0, b, abl);
+#pragma unroll
+    for (int k = 0; k < 4; k++) b[k] = (wrc[k] - w0[k]) / dr * ir0;
+    msolve(U0, V0, lam0, b, abr);
+#pragma unroll
+    for (int k = 0; k < 4; k++) b[k] = 0.5 * (glt[k] + grt[k]) * ir0;
+    msolve(U0, V0, lam0, b, abt);
+
+    // Eq.34 collision time at the interface
+    double mul = mu_lam(P, lam0), mut = 0.0;
+    if (P.sa && nut_f > 0.0) mut = r0 * nut_f * sa_fv1(nut_f * r0 / mul);
+    double tau = (mul + mut) * 2.0 * lam0 / r0;
+
+    // time integrals of the six Eq.13 factors over [0, dt]
+    double eta = exp(-dt / tau), ome = -expm1(-dt / tau);
+    double T1 = dt - tau * ome;
+    double T2 = -tau * dt * (1.0 + eta) + 2.0 * tau * tau * ome;
+    double T3 = 0.5 * dt * dt - tau * dt + tau * tau * ome;
+    double T4 = tau * ome;
+    double T5 = tau * dt * eta - 2.0 * tau * tau * ome;
+    double T6 = -tau * tau * ome;
+
+    // Eq.12 -> Abar
+    double q2[4], t[4], s[4], Ab[4];
+    pmom<1, 0>(mp, mv, mx, abl, t);
+    pmom<1, 0>(mm, mv, mx, abr, s);
+    pmom<0, 1>(mf, mv, mx, abt, q2);
+#pragma unroll
+    for (int k = 0; k < 4; k++) q2[k] = r0 * (q2[k] + t[k] + s[k]);
+    double den = r0 * (0.5 * dt * dt - T3);
+#pragma unroll
+    for (int k = 0; k < 4; k++) b[k] = (T2 * q2[k] + T5 * q5[k] + T6 * q6[k]) / den;
+    msolve(U0, V0, lam0, b, Ab);
+
+    // Eq.14
+    double e1[4], e2[4], e3[4];
+    pmom1<1>(mf, mv, mx, e1);
+    pmom<2, 0>(mp, mv, mx, abl, t);
+    pmom<2, 0>(mm, mv, mx, abr, s);
+    pmom<1, 1>(mf, mv, mx, abt, e2);
+    pmom<1, 0>(mf, mv, mx, Ab, e3);
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+        F[k] = T1 * r0 * e1[k] + T2 * r0 * (t[k] + s[k] + e2[k]) + T3 * r0 * e3[k] + T4 * f4[k] + T5 * f5[k] +
+               T6 * f6[k];
+}
+
+// Euler flux Jacobian-vector product J(W, n) d (the linearised flux of the
+// implicit operator, Eq.18-20).
+template <typename V>
+__device__ __forceinline__ void jac_vec(const V *W, V nx, V ny, const V *d, V *out)
+{
+    V r = W[0], U = W[1] / r, Vv = W[2] / r, E = W[3];
+    V ke = V(0.5) * (U * U + Vv * Vv);
+    V p = V(GAMMA - 1.0) * (E - r * ke);
+    V q = U * nx + Vv * ny;
+    V dmn = d[1] * nx + d[2] * ny;
+    V dq = (dmn - q * d[0]) / r;
+    V dp = V(GAMMA - 1.0) * (d[3] - (U * d[1] + Vv * d[2]) + ke * d[0]);
+    out[0] = dmn;
+    out[1] = d[1] * q + W[1] * dq + dp * nx;
+    out[2] = d[2] * q + W[2] * dq + dp * ny;
+    out[3] = (d[3] + dp) * q + (E + p) * dq;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// mode bit 1: per-iteration atomics; 2: halt/bad flags; 4: chunk history
+template <typename T>
+__global__ void k_reset(Params<T> P, int mode)
+{
+    DevScalars *sc = P.sc;
+    if (mode & 1) {
+        sc->dtmin_bits = 0x7ff0000000000000ull;   // +inf
+        sc->resinf_bits = 0ull;
+        sc->e40_bits = 0ull;
+    }
+    if (mode & 2) { sc->bad = 0; sc->halt = 0; }
+    if (mode & 4) sc->hist_n = 0;
+}
+
+// Per cell: Eq.21 spectral radius and the Eq.23 minimum, least-squares
+// gradients (Eq.6-7, ghost cells included), the Eq.9-10 limiter,
+// vorticity and the laminar viscosity.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prep(Params<T> P)
+{
+    if (P.sc->halt) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.nc) return;
+    const int N = P.nc;
+    const double *W = cur_state(P);
+    double w[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
+    double r = w[0], U = w[1] / r, V = w[2] / r;
+    double lam = lam_of(w);
+    double cs = sqrt(GAMMA / (2.0 * lam));
+    P.nu[c] = mu_lam(P, lam) / r;
+    double lc = 0.0, b1[4] = {0, 0, 0, 0}, b2[4] = {0, 0, 0, 0}, wmax[4], wmin[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) wmax[k] = wmin[k] = w[k];
+    int e0 = P.cf_ptr[c], e1 = P.cf_ptr[c + 1];
+    for (int e = e0; e < e1; e++) {
+        int f = P.cf_face[e];
+        double nx = P.fnx[f], ny = P.fny[f], S = P.flen[f];
+        lc += (fabs(U * nx + V * ny) + cs) * S;
+        int j = P.cf_nbr[e];
+        double wj[5];
+        if (j >= 0) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) wj[k] = W[k * N + j];
+        } else {
+            ghost(P, P.fbc[f], w, nx, ny, wj);
+        }
+        double dx = P.cf_dx[e], dy = P.cf_dy[e];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            double d = wj[k] - w[k];
+            b1[k] += dx * d;
+            b2[k] += dy * d;
+            wmax[k] = fmax(wmax[k], wj[k]);
+            wmin[k] = fmin(wmin[k], wj[k]);
+        }
+    }
+    P.lamc[c] = lc;
+    double dt = P.cfl_flux * P.area[c] / lc;
+    atomicMin(&P.sc->dtmin_bits, (unsigned long long)__double_as_longlong(dt));
+    double L11 = P.lsinv[c], L12 = P.lsinv[N + c], L22 = P.lsinv[2 * N + c];
+    double gx[4], gy[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        gx[k] = L11 * b1[k] + L12 * b2[k];
+        gy[k] = L12 * b1[k] + L22 * b2[k];
+    }
+    double dUdy = (gy[1] - U * gy[0]) / r;
+    double dVdx = (gx[2] - V * gx[0]) / r;
+    P.vort[c] = fabs(dVdx - dUdy);
+    if (P.limiter) {
+        double vx[MAXV], vy[MAXV];
+#pragma unroll
+        for (int v = 0; v < MAXV; v++) { vx[v] = P.vtx[(2 * v) * N + c]; vy[v] = P.vtx[(2 * v + 1) * N + c]; }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            double nmax = -INFINITY, nmin = INFINITY;
+#pragma unroll
+            for (int v = 0; v < MAXV; v++) {
+                double wv = w[k] + gx[k] * vx[v] + gy[k] * vy[v];
+                nmax = fmax(nmax, wv);
+                nmin = fmin(nmin, wv);
+            }
+            double phi = 1.0;
+            if (nmax > w[k]) phi = fmin(phi, (wmax[k] - w[k]) / (nmax - w[k]));
+            if (nmin < w[k]) phi = fmin(phi, (wmin[k] - w[k]) / (nmin - w[k]));
+            gx[k] *= phi;
+            gy[k] *= phi;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        P.grad[k * N + c] = gx[k];
+        P.grad[(4 + k) * N + c] = gy[k];
+    }
+}
+
+__device__ __forceinline__ bool physical(const double *w)
+{
+    return w[0] > 0.0 && (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]) > 0.0;
+}
+
+// Per face: reconstruction (Eq.10), ghost side, the GKS flux, the LU-SGS
+// spectral radius and the SA face terms (Eq.28-30).
+template <typename T>
+__global__ __launch_bounds__(256) void k_flux(Params<T> P)
+{
+    if (P.sc->halt) return;
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= P.nf) return;
+    const int N = P.nc, F = P.nf;
+    const double *W = cur_state(P);
+    int l = P.fl[f], rr = P.fr[f];
+    double nx = P.fnx[f], ny = P.fny[f], S = P.flen[f];
+    double tx = -ny, ty = nx;
+    double wl[5], WL[4], glx[4], gly[4];
+#pragma unroll
+    for (int k = 0; k < 5; k++) wl[k] = W[k * N + l];
+    double rlx = P.frl[2 * f], rly = P.frl[2 * f + 1];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        glx[k] = P.grad[k * N + l];
+        gly[k] = P.grad[(4 + k) * N + l];
+        WL[k] = wl[k] + glx[k] * rlx + gly[k] * rly;
+    }
+    if (!physical(WL)) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) { WL[k] = wl[k]; glx[k] = gly[k] = 0.0; }
+    }
+    double WR[4], grx[4], gry[4], wrc[5], dr, rn;
+    double dl = P.fdl[f];
+    if (rr >= 0) {
+        double rrx = P.frr[2 * f], rry = P.frr[2 * f + 1];
+#pragma unroll
+        for (int k = 0; k < 5; k++) wrc[k] = W[k * N + rr];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            grx[k] = P.grad[k * N + rr];
+            gry[k] = P.grad[(4 + k) * N + rr];
+            WR[k] = wrc[k] + grx[k] * rrx + gry[k] * rry;
+        }
+        if (!physical(WR)) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) { WR[k] = wrc[k]; grx[k] = gry[k] = 0.0; }
+        }
+        dr = P.fdr[f];
+        rn = P.frn[f];
+    } else {
+        // ghost side: boundary map of the reconstructed interior face state,
+        // zero slopes; cell-centre ghost value from the interior cell centre
+        int bc = P.fbc[f];
+        double tmp[5] = {WL[0], WL[1], WL[2], WL[3], wl[4]}, out[5];
+        ghost(P, bc, tmp, nx, ny, out);
+#pragma unroll
+        for (int k = 0; k < 4; k++) { WR[k] = out[k]; grx[k] = gry[k] = 0.0; }
+        ghost(P, bc, wl, nx, ny, wrc);
+        dr = dl;
+        rn = P.frn[f];
+    }
+    // face frame
+    double fwl[4], fwr[4], fwlc[4], fwrc[4], gln[4], glt[4], grn[4], grt[4];
+    auto rot = [&](const double *src, double *dst) {
+        dst[0] = src[0];
+        dst[1] = src[1] * nx + src[2] * ny;
+        dst[2] = src[1] * tx + src[2] * ty;
+        dst[3] = src[3];
+    };
+    rot(WL, fwl); rot(WR, fwr); rot(wl, fwlc); rot(wrc, fwrc);
+    {
+        double tn[4], tt[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) { tn[k] = glx[k] * nx + gly[k] * ny; tt[k] = glx[k] * tx + gly[k] * ty; }
+        rot(tn, gln); rot(tt, glt);
+#pragma unroll
+        for (int k = 0; k < 4; k++) { tn[k] = grx[k] * nx + gry[k] * ny; tt[k] = grx[k] * tx + gry[k] * ty; }
+        rot(tn, grn); rot(tt, grt);
+    }
+    double dt = __longlong_as_double((long long)P.sc->dtmin_bits);
+    double nutf = fmax(0.5 * (wl[4] + wrc[4]), 0.0);
+    double Fr[4];
+    gks_flux(P, fwl, gln, glt, fwr, grn, grt, fwlc, fwrc, dl, dr, dt, nutf, Fr);
+    double idt = 1.0 / dt;
+    double Fn = Fr[1] * idt, Ft = Fr[2] * idt;
+    P.flux[f] = Fr[0] * idt * S;
+    P.flux[F + f] = (Fn * nx + Ft * tx) * S;
+    P.flux[2 * F + f] = (Fn * ny + Ft * ty) * S;
+    P.flux[3 * F + f] = Fr[3] * idt * S;
+
+    // spectral radius of the face for the implicit operator
+    double qi = (wl[1] * nx + wl[2] * ny) / wl[0], qj = (wrc[1] * nx + wrc[2] * ny) / wrc[0];
+    double li = fabs(qi) + sqrt(GAMMA / (2.0 * lam_of(wl)));
+    double lj = fabs(qj) + sqrt(GAMMA / (2.0 * lam_of(wrc)));
+    double lamf = fmax(li, lj);
+    double mi = mu_lam(P, lam_of(wl)), mj = mu_lam(P, lam_of(wrc));
+    if (P.visc_sr) {
+        double ei = mi, ej = mj;
+        if (P.sa) {
+            if (wl[4] > 0) ei += wl[0] * wl[4] * sa_fv1(wl[4] * wl[0] / mi);
+            if (wrc[4] > 0) ej += wrc[0] * wrc[4] * sa_fv1(wrc[4] * wrc[0] / mj);
+        }
+        lamf += (ei / wl[0] + ej / wrc[0]) / rn;
+    }
+    P.lam[f] = lamf;
+    if (P.sa) {
+        double nui = mi / wl[0], nuj = mj / wrc[0];
+        double ti = wl[4], tj = wrc[4];
+        double g = (tj - ti) / rn;
+        double Finv = 0.5 * (qi + fabs(qi)) * ti + 0.5 * (qj - fabs(qj)) * tj;
+        double Fvis = (0.5 / SA_SIGMA) * ((nui + nuj) + (1.0 + SA_CB2) * (ti + tj)) * g;
+        P.saf[f] = (Fvis - Finv) * S;
+        P.sag[f] = g * S;
+    }
+}
+
+// Per cell: residual M (Eq.16) as the signed sum of its face fluxes, the
+// LU-SGS diagonal pieces, the SA residual and diagonal (Eq.27-32), and the
+// norms (max exact via integer atomics, L2 as block partial sums).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(Params<T> P)
+{
+    __shared__ double red0[256], red1[256];
+    if (P.sc->halt) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = P.nc, F = P.nf;
+    double s0 = 0.0, s1 = 0.0;
+    if (c < N) {
+        const double *W = cur_state(P);
+        double m[4] = {0, 0, 0, 0}, ls = 0.0, saR = 0.0, sagS = 0.0, sad = 0.0;
+        double w[5];
+#pragma unroll
+        for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
+        double nuc = P.nu[c];
+        int e0 = P.cf_ptr[c], e1 = P.cf_ptr[c + 1];
+        for (int e = e0; e < e1; e++) {
+            int f = P.cf_face[e];
+            double sg = (P.cf_flag[e] & CF_OWNER) ? 1.0 : -1.0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) m[k] -= sg * P.flux[k * F + f];
+            double S = P.flen[f];
+            ls += P.lam[f] * S;
+            if (P.sa) {
+                saR += sg * P.saf[f];
+                sagS += sg * P.sag[f];
+                double nx = sg * P.fnx[f], ny = sg * P.fny[f];
+                int j = P.cf_nbr[e];
+                double nuj, tj;
+                if (j >= 0) {
+                    nuj = P.nu[j];
+                    tj = W[4 * N + j];
+                } else {
+                    double g[5];
+                    ghost(P, P.fbc[f], w, nx, ny, g);
+                    nuj = mu_lam(P, lam_of(g)) / g[0];
+                    tj = g[4];
+                }
+                double qc = (w[1] * nx + w[2] * ny) / w[0];
+                double kf = (1.0 / SA_SIGMA) * (0.5 * (nuc + nuj) + (1.0 + SA_CB2) * 0.5 * (w[4] + tj));
+                sad += 0.5 * (qc + fabs(qc)) * S + kf * S / P.frn[f];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) P.M[k * N + c] = m[k];
+        P.lsum[c] = 0.5 * ls;
+        double rinf = fmax(fmax(fabs(m[0]), fabs(m[1])), fmax(fabs(m[2]), fabs(m[3])));
+        atomicMax(&P.sc->resinf_bits, (unsigned long long)__double_as_longlong(rinf));
+        s0 = m[0] * m[0];
+        if (P.sa) {
+            double Sr, jd;
+            sa_source(w[4], nuc, P.dwall[c], P.vort[c], Sr, jd);
+            double a = P.area[c];
+            double rsa = saR - (SA_CB2 / SA_SIGMA) * w[4] * sagS + a * Sr;
+            P.M[4 * N + c] = rsa;
+            P.sadiag[c] = sad + a * jd;
+            s1 = rsa * rsa;
+        } else {
+            P.M[4 * N + c] = 0.0;
+        }
+    }
+    red0[threadIdx.x] = s0;
+    red1[threadIdx.x] = s1;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            red0[threadIdx.x] += red0[threadIdx.x + h];
+            red1[threadIdx.x] += red1[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        P.part[blockIdx.x] = red0[0];
+        P.part[P.max_blocks + blockIdx.x] = red1[0];
+    }
+}
+
+// One block: fixed-order sum of the partials, the Eq.25 CFL law, history.
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void k_reduce(Params<T> P, int nblocks)
+{
+    __shared__ double a[RED_THREADS], b[RED_THREADS];
+    DevScalars *sc = P.sc;
+    if (sc->halt) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += RED_THREADS) {
+        s0 += P.part[i];
+        s1 += P.part[P.max_blocks + i];
+    }
+    a[threadIdx.x] = s0;
+    b[threadIdx.x] = s1;
+    __syncthreads();
+    for (int h = RED_THREADS / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) { a[threadIdx.x] += a[threadIdx.x + h]; b[threadIdx.x] += b[threadIdx.x + h]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double l2 = sqrt(a[0]), sal2 = sqrt(b[0]);
+        double rinf = __longlong_as_double((long long)sc->resinf_bits);
+        if (sc->ncommit == 0) {
+            sc->res0 = l2;
+            sc->cfl = P.cfl_init;
+        } else if (P.cfl_mode == 0) {
+            double cf = sc->cfl * sc->res_inf_prev / rinf;
+            if (!(cf >= P.cfl_min)) cf = P.cfl_min;
+            if (cf > P.cfl_max) cf = P.cfl_max;
+            sc->cfl = cf;
+        }
+        sc->res_inf_prev = rinf;
+        sc->res_l2 = l2;
+        sc->sa_l2 = sal2;
+        sc->res_inf = rinf;
+        sc->dt_flux = __longlong_as_double((long long)sc->dtmin_bits);
+        sc->resinf_bits = 0ull;
+        int h = sc->hist_n;
+        if (h < P.hist_cap) {
+            double *e = P.hist + HIST_W * h;
+            e[0] = l2; e[1] = rinf; e[2] = sc->cfl; e[3] = sc->dt_flux; e[4] = 0.0; e[5] = sal2;
+        }
+    }
+}
+
+// One wavefront of the forward (FWD) or backward LU-SGS sweep (Eq.22): the
+// cells [c0, c1) are mutually independent.  Forward:
+//   dW*_i = D^-1 [M_i - sum_{j<i} (J(W_j, n_ij) dW*_j - lam_ij dW*_j) S_ij / 2];
+// backward, in place:
+//   dW_i = dW*_i - D^-1 sum_{j>i} (J(W_j, n_ij) dW_j - lam_ij dW_j) S_ij / 2,
+// boundary ghosts counted as upper neighbours with the ghost increments of
+// Sec. 2.5 taken from dW*_i.  The SA equation (Eq.31-32) is swept alongside.
+template <typename T, bool FWD>
+__global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
+{
+    if (P.sc->halt) return;
+    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= c1) return;
+    const int N = P.nc;
+    const double *W = cur_state(P);
+    const T cfl = T(P.sc->cfl);
+    double w[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
+    T acc[5], dws[5];
+    if (FWD) {
+#pragma unroll
+        for (int k = 0; k < 5; k++) { acc[k] = T(P.M[k * N + c]); dws[k] = T(0); }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; k++) { acc[k] = T(0); dws[k] = P.dW[k * N + c]; }
+    }
+    double nuc = P.nu[c];
+    int e0 = P.cf_ptr[c], e1 = P.cf_ptr[c + 1];
+    for (int e = e0; e < e1; e++) {
+        int j = P.cf_nbr[e];
+        int fl = P.cf_flag[e];
+        if (FWD) {
+            if (j < 0 || !(fl & CF_LOWER)) continue;
+        } else {
+            if (j >= 0 && (fl & CF_LOWER)) continue;
+        }
+        int f = P.cf_face[e];
+        double sg = (fl & CF_OWNER) ? 1.0 : -1.0;
+        double nx = sg * P.fnx[f], ny = sg * P.fny[f];
+        T S = T(P.flen[f]), lam = T(P.lam[f]);
+        double wj[5];
+        T dj[5];
+        if (j >= 0) {
+#pragma unroll
+            for (int k = 0; k < 5; k++) { wj[k] = W[k * N + j]; dj[k] = P.dW[k * N + j]; }
+        } else {
+            ghost(P, P.fbc[f], w, nx, ny, wj);
+            ghost_incr<T>(P.fbc[f], dws, T(nx), T(ny), dj);
+        }
+        T wjt[4] = {T(wj[0]), T(wj[1]), T(wj[2]), T(wj[3])};
+        T jv[4];
+        jac_vec<T>(wjt, T(nx), T(ny), dj, jv);
+        T h = T(0.5) * S;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (FWD) acc[k] -= h * (jv[k] - lam * dj[k]);
+            else acc[k] += h * (jv[k] - lam * dj[k]);
+        }
+        if (P.sa) {
+            double nuj = (j >= 0) ? P.nu[j] : mu_lam(P, lam_of(wj)) / wj[0];
+            double qj = (wj[1] * nx + wj[2] * ny) / wj[0];
+            double kf = (1.0 / SA_SIGMA) * (0.5 * (nuc + nuj) + (1.0 + SA_CB2) * 0.5 * (w[4] + wj[4]));
+            double off = (-0.5 * (qj - fabs(qj)) + kf / P.frn[f]) * P.flen[f];
+            acc[4] += T(off) * dj[4];
+        }
+    }
+    T odt = T(P.lamc[c]) / cfl;   // Omega / dt_imp with dt_imp = CFL Omega / Lambda_c (Eq.24)
+    T D = odt + T(P.lsum[c]);
+    if (FWD) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) P.dW[k * N + c] = acc[k] / D;
+        P.dW[4 * N + c] = P.sa ? acc[4] / (odt + T(P.sadiag[c])) : T(0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) P.dW[k * N + c] = dws[k] - acc[k] / D;
+        P.dW[4 * N + c] = P.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
+    }
+}
+
+// Per cell: W^{n+1} = W^n + dW into the other state buffer (Eq.17),
+// nu~ clipped at 0, positivity check, Eq.40.
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(Params<T> P)
+{
+    if (P.sc->halt) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.nc) return;
+    const int N = P.nc;
+    const double *W = cur_state(P);
+    double *Wn = (P.sc->ncommit & 1) ? P.Wa : P.Wb;
+    double w[5], num = 0.0, den = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        double o = W[k * N + c], d = double(P.dW[k * N + c]);
+        num += d * d;
+        den += o * o;
+        w[k] = o + d;
+        Wn[k * N + c] = w[k];
+    }
+    double t = W[4 * N + c];
+    if (P.sa) t = fmax(t + double(P.dW[4 * N + c]), 0.0);
+    Wn[4 * N + c] = t;
+    double p = w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0];
+    if (!(w[0] > 0.0) || !(p > 0.0) || !isfinite(t) || !isfinite(p)) atomicOr(&P.sc->bad, 1);
+    double e = sqrt(num / den);
+    if (isfinite(e)) atomicMax(&P.sc->e40_bits, (unsigned long long)__double_as_longlong(e));
+}
+
+template <typename T>
+__global__ void k_commit(Params<T> P)
+{
+    DevScalars *sc = P.sc;
+    if (sc->halt) return;
+    double e40 = __longlong_as_double((long long)sc->e40_bits);
+    sc->e40 = e40;
+    int h = sc->hist_n;
+    if (h < P.hist_cap) P.hist[HIST_W * h + 4] = e40;
+    sc->hist_n = h + 1;
+    if (sc->bad) {
+        sc->halt = 1;
+    } else {
+        sc->ncommit += 1;
+    }
+    sc->dtmin_bits = 0x7ff0000000000000ull;
+    sc->e40_bits = 0ull;
+}
+
+// exact distance from each centroid to the nearest wall segment
+__global__ __launch_bounds__(256) void k_wall_distance(int nc, const double *xc, const double *yc, int nw,
+                                                       const double *seg, double *d)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double px = xc[c], py = yc[c], best = 1e300;
+    for (int s = 0; s < nw; s++) {
+        double ax = seg[4 * s], ay = seg[4 * s + 1], bx = seg[4 * s + 2], by = seg[4 * s + 3];
+        double ex = bx - ax, ey = by - ay;
+        double t = ((px - ax) * ex + (py - ay) * ey) / (ex * ex + ey * ey);
+        t = fmin(fmax(t, 0.0), 1.0);
+        double dx = px - ax - t * ex, dy = py - ay - t * ey;
+        best = fmin(best, sqrt(dx * dx + dy * dy));
+    }
+    d[c] = best;
+}
+
+__global__ void k_gather_faces(int n, const int *faces, const double *flux, int nf, double *out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int f = faces[i];
+#pragma unroll
+    for (int k = 0; k < 4; k++) out[4 * i + k] = flux[k * nf + f];
+}
+
+__global__ void k_set_state(int nc, double w0, double w1, double w2, double w3, double w4, double *W)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    W[c] = w0; W[nc + c] = w1; W[2 * nc + c] = w2; W[3 * nc + c] = w3; W[4 * nc + c] = w4;
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline int nblk(int n, int b) { return (n + b - 1) / b; }
+
+template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int mode)
+{
+    hipLaunchKernelGGL(k_reset<T>, dim3(1), dim3(1), 0, L.s, P, mode);
+}
+template <typename T> void launch_prep(const Launch &L, const Params<T> &P)
+{
+    hipLaunchKernelGGL(k_prep<T>, dim3(nblk(P.nc, L.block)), dim3(L.block), 0, L.s, P);
+}
+template <typename T> void launch_flux(const Launch &L, const Params<T> &P)
+{
+    hipLaunchKernelGGL(k_flux<T>, dim3(nblk(P.nf, L.block)), dim3(L.block), 0, L.s, P);
+}
+template <typename T> void launch_gather(const Launch &L, const Params<T> &P)
+{
+    // the shared reduction assumes 256 threads
+    hipLaunchKernelGGL(k_gather<T>, dim3(nblk(P.nc, 256)), dim3(256), 0, L.s, P);
+}
+template <typename T> void launch_reduce(const Launch &L, const Params<T> &P)
+{
+    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(RED_THREADS), 0, L.s, P, nblk(P.nc, 256));
+}
+template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd)
+{
+    if (c1 <= c0) return;
+    dim3 g(nblk(c1 - c0, L.block)), b(L.block);
+    if (fwd) hipLaunchKernelGGL((k_sweep<T, true>), g, b, 0, L.s, P, c0, c1);
+    else hipLaunchKernelGGL((k_sweep<T, false>), g, b, 0, L.s, P, c0, c1);
+}
+template <typename T> void launch_update(const Launch &L, const Params<T> &P)
+{
+    hipLaunchKernelGGL(k_update<T>, dim3(nblk(P.nc, L.block)), dim3(L.block), 0, L.s, P);
+}
+template <typename T> void launch_commit(const Launch &L, const Params<T> &P)
+{
+    hipLaunchKernelGGL(k_commit<T>, dim3(1), dim3(1), 0, L.s, P);
+}
+void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, int nw, const double *wseg,
+                          double *dwall)
+{
+    hipLaunchKernelGGL(k_wall_distance, dim3(nblk(nc, 256)), dim3(256), 0, L.s, nc, xc, yc, nw, wseg, dwall);
+}
+void launch_gather_faces(const Launch &L, int n, const int *faces, const double *flux, int nf, double *out)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_faces, dim3(nblk(n, 256)), dim3(256), 0, L.s, n, faces, flux, nf, out);
+}
+void launch_set_state(const Launch &L, int nc, const double *Winf, double *W)
+{
+    hipLaunchKernelGGL(k_set_state, dim3(nblk(nc, 256)), dim3(256), 0, L.s, nc, Winf[0], Winf[1], Winf[2], Winf[3],
+                       Winf[4], W);
+}
+
+#define INST(T)                                                                               \
+    template void launch_reset<T>(const Launch &, const Params<T> &, int);                    \
+    template void launch_prep<T>(const Launch &, const Params<T> &);                          \
+    template void launch_flux<T>(const Launch &, const Params<T> &);                          \
+    template void launch_gather<T>(const Launch &, const Params<T> &);                        \
+    template void launch_reduce<T>(const Launch &, const Params<T> &);                        \
+    template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, bool);         \
+    template void launch_update<T>(const Launch &, const Params<T> &);                        \
+    template void launch_commit<T>(const Launch &, const Params<T> &);
+INST(double)
+INST(float)
+
+}  // namespace igks

@@ -1,0 +1,208 @@
+"""Python binding of libigks.so (include/igks.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library.  PyTorch provides the
+device workspace (a uint8 tensor) and the stream.  If the library is not
+built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libigks.so")
+
+IGKS_OK, IGKS_EINVAL, IGKS_EMESH, IGKS_ENOMEM, IGKS_ENONPHYS, IGKS_EHIP = 0, -1, -2, -3, -4, -5
+IGKS_FP64, IGKS_MIXED = 0, 1
+HIST_W = 6
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1709_00803_amd.build "
+                      "(or __graft_entry__.build())")
+_lib = C.CDLL(LIB_PATH)
+
+
+class igks_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("limiter", C.c_int), ("cfl_init", C.c_double),
+                ("cfl_min", C.c_double), ("cfl_max", C.c_double), ("cfl_mode", C.c_int),
+                ("cfl_flux", C.c_double), ("visc_sr", C.c_int), ("mu_law", C.c_int),
+                ("chunk", C.c_int), ("block", C.c_int)]
+
+
+class igks_residual(C.Structure):
+    _fields_ = [("iteration", C.c_int32), ("res_l2", C.c_double), ("res_drop", C.c_double),
+                ("res_inf", C.c_double), ("eq40", C.c_double), ("cfl", C.c_double),
+                ("dt_flux", C.c_double), ("sa_l2", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class igks_scalars(C.Structure):
+    _fields_ = [("iteration", C.c_int32), ("cfl", C.c_double), ("res_inf_prev", C.c_double),
+                ("res0", C.c_double)]
+
+
+_P = C.c_void_p
+_DP = C.POINTER(C.c_double)
+_IP = C.POINTER(C.c_int32)
+_SIGS = {
+    "igks_default_options": (None, [C.POINTER(igks_options)]),
+    "igks_create": (C.c_int, [C.POINTER(_P), C.POINTER(igks_options), _P]),
+    "igks_destroy": (None, [_P]),
+    "igks_last_error": (C.c_char_p, [_P]),
+    "igks_mesh_upload": (C.c_int, [_P, C.c_int32, _DP, C.c_int32, _IP, _IP, C.c_int32, _IP, _IP]),
+    "igks_mesh_info": (C.c_int, [_P, _IP, _IP, _IP, _IP]),
+    "igks_workspace_size": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "igks_bind_workspace": (C.c_int, [_P, _P, C.c_size_t]),
+    "igks_set_freestream": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "igks_iterate": (C.c_int, [_P, C.c_int32, _IP]),
+    "igks_get_residual": (C.c_int, [_P, C.POINTER(igks_residual)]),
+    "igks_get_history": (C.c_int, [_P, _DP, C.c_int32, _IP]),
+    "igks_get_state": (C.c_int, [_P, _DP]),
+    "igks_set_state": (C.c_int, [_P, _DP, C.POINTER(igks_scalars)]),
+    "igks_get_scalars": (C.c_int, [_P, C.POINTER(igks_scalars)]),
+    "igks_compute_residual": (C.c_int, [_P, _DP]),
+    "igks_get_wall_loads": (C.c_int, [_P, _DP, _DP, _DP, _DP, _DP]),
+    "igks_set_profiling": (C.c_int, [_P, C.c_int]),
+    "igks_get_kernel_times": (C.c_int, [_P, _DP]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+EXPORTED = tuple(_SIGS)
+
+
+class IgksError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"igks error {code}: {msg}")
+        self.code = code
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_DP)
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_IP)
+
+
+def default_options(**kw) -> igks_options:
+    o = igks_options()
+    igks_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Solver:
+    """One mesh + flow condition on one GPU.
+
+    ``mesh`` needs xy, cell_ptr, cell_nodes, bface_nodes, bface_tag (see
+    meshgen.Mesh).  ``stream``: a torch.cuda.Stream (default: a new one).
+    """
+
+    def __init__(self, mesh, options: igks_options | None = None, stream=None, device="cuda", **kw):
+        import torch
+        self.torch = torch
+        self.opt = options or default_options(**kw)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self.ctx = _P()
+        self._chk(igks_create(C.byref(self.ctx), C.byref(self.opt), _P(self.stream.cuda_stream)))
+        xy, pxy = _d(mesh.xy.reshape(-1))
+        cp, pcp = _i(mesh.cell_ptr)
+        cn, pcn = _i(mesh.cell_nodes)
+        bn, pbn = _i(mesh.bface_nodes.reshape(-1))
+        bt, pbt = _i(mesh.bface_tag)
+        self._chk(igks_mesh_upload(self.ctx, mesh.n_nodes, pxy, mesh.n_cells, pcp, pcn, mesh.n_bfaces, pbn, pbt))
+        nc, nf, nw, nl = (C.c_int32() for _ in range(4))
+        self._chk(igks_mesh_info(self.ctx, C.byref(nc), C.byref(nf), C.byref(nw), C.byref(nl)))
+        self.n, self.nf, self.nwall, self.nlev = nc.value, nf.value, nw.value, nl.value
+        sz = C.c_size_t()
+        self._chk(igks_workspace_size(self.ctx, C.byref(sz)))
+        self.ws_bytes = sz.value
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._chk(igks_bind_workspace(self.ctx, _P(aligned), self.ws_bytes))
+
+    def _chk(self, rc):
+        if rc != IGKS_OK:
+            msg = igks_last_error(self.ctx).decode() if self.ctx else ""
+            raise IgksError(rc, msg)
+        return rc
+
+    def close(self):
+        if self.ctx:
+            igks_destroy(self.ctx)
+            self.ctx = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_freestream(self, mach, alpha_deg, reynolds, nut_ratio=-1.0):
+        self._chk(igks_set_freestream(self.ctx, mach, alpha_deg, reynolds, nut_ratio))
+
+    def iterate(self, n):
+        done = C.c_int32(0)
+        rc = igks_iterate(self.ctx, n, C.byref(done))
+        self._chk(rc)
+        return done.value
+
+    def residual(self) -> dict:
+        r = igks_residual()
+        self._chk(igks_get_residual(self.ctx, C.byref(r)))
+        return r.as_dict()
+
+    def history(self, max_entries=1 << 20):
+        out = np.zeros((max_entries, HIST_W))
+        n = C.c_int32()
+        self._chk(igks_get_history(self.ctx, out.ctypes.data_as(_DP), max_entries, C.byref(n)))
+        return out[:n.value]
+
+    def get_state(self):
+        W = np.zeros((5, self.n))
+        self._chk(igks_get_state(self.ctx, W.ctypes.data_as(_DP)))
+        return W
+
+    def set_state(self, W, scalars: igks_scalars | None = None):
+        W, p = _d(np.asarray(W).reshape(5, self.n))
+        self._chk(igks_set_state(self.ctx, p, C.byref(scalars) if scalars is not None else None))
+
+    def scalars(self) -> igks_scalars:
+        s = igks_scalars()
+        self._chk(igks_get_scalars(self.ctx, C.byref(s)))
+        return s
+
+    def compute_residual(self):
+        M = np.zeros((5, self.n))
+        self._chk(igks_compute_residual(self.ctx, M.ctypes.data_as(_DP)))
+        return M
+
+    def wall_loads(self):
+        cl, cd = C.c_double(), C.c_double()
+        cf, cp, xw = (np.zeros(max(self.nwall, 1)) for _ in range(3))
+        P = lambda a: a.ctypes.data_as(_DP)
+        self._chk(igks_get_wall_loads(self.ctx, C.byref(cl), C.byref(cd), P(cf), P(cp), P(xw)))
+        n = self.nwall
+        return dict(cl=cl.value, cd=cd.value, cf=cf[:n], cp=cp[:n], xw=xw[:n])
+
+    def set_profiling(self, on=True):
+        self._chk(igks_set_profiling(self.ctx, 1 if on else 0))
+
+    def kernel_times(self):
+        t = np.zeros(7)
+        self._chk(igks_get_kernel_times(self.ctx, t.ctypes.data_as(_DP)))
+        return dict(zip(("prep", "flux", "gather", "reduce", "sweep_fwd", "sweep_bwd", "update"), t))

@@ -1,0 +1,185 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle
+on the same seeded inputs.
+
+Tolerances (floating point): the residual M of Eq.16 is a sum of face
+fluxes that nearly cancel, so it is compared per cell and component
+against 1e-12 times that cell's gross flux sum_faces |F S| (the
+arithmetic error of both sides is a few ulp of the gross flux); the SA
+right-hand side against 1e-10 of its largest magnitude (source and
+diffusion terms cancel in it as well); states after a few iterations
+against 1e-9 relative; converged lift/drag against 1e-9 relative.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pyoracle as po
+from paper_1709_00803_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def igks():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1709_00803_amd import igks as m
+    return m
+
+
+def smooth_state(W, xc, yc, amp, seed):
+    W = W.copy()
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, 8)
+    W[0] *= 1 + amp * np.sin(3 * xc + ph[0]) * np.cos(2 * yc + ph[1])
+    W[1] += amp * np.cos(2 * xc + ph[2]) * np.sin(3 * yc + ph[3])
+    W[2] += amp * np.sin(2 * xc + ph[4]) * np.cos(yc + ph[5])
+    W[3] *= 1 + amp * np.cos(xc + ph[6]) * np.sin(2 * yc + ph[7])
+    if W[4].any():
+        W[4] *= 1 + 0.5 * np.sin(4 * xc) ** 2
+    return W
+
+
+def pair(igks, mesh, flow, **opt):
+    o = po.Oracle(mesh, **{k: v for k, v in opt.items() if k in ("limiter", "cfl_init", "cfl_mode", "cfl_flux",
+                                                                   "visc_sr", "mu_law", "cfl_min", "cfl_max")})
+    o.set_freestream(*flow)
+    g = igks.Solver(mesh, **opt)
+    g.set_freestream(*flow)
+    return o, g
+
+
+def check_residual(o, g, W, tag):
+    o.set_state(W)
+    g.set_state(W)
+    Mo, G = o.compute_residual()
+    Mg = g.compute_residual()
+    err = np.abs(Mg[:4] - Mo[:4]) / G
+    say(f"[{tag}] flow residual max |dM|/gross = {err.max():.3e}")
+    assert err.max() <= 1e-12, tag
+    sa_scale = np.abs(Mo[4]).max()
+    if sa_scale > 0:
+        e4 = np.abs(Mg[4] - Mo[4]).max() / sa_scale
+        say(f"[{tag}] SA residual max |dR|/max|R| = {e4:.3e}")
+        assert e4 <= 1e-10, tag
+    else:
+        assert np.abs(Mg[4]).max() == 0.0
+
+
+TAGS_ALL = dict(bottom=mg.WALL, top=mg.FARFIELD, left=mg.FREESTREAM, right=mg.OUTFLOW)
+TAGS_SYM = dict(bottom=lambda x: np.where(x < 0.3, mg.SYMMETRY, mg.WALL), top=mg.OUTFLOW,
+                left=mg.FREESTREAM, right=mg.OUTFLOW)
+
+
+@pytest.mark.parametrize("case", [
+    dict(nx=9, ny=7, seed=1, tags=TAGS_ALL, flow=(0.4, 5.0, 800.0, -1.0), limiter=0, order="colour"),
+    dict(nx=9, ny=7, seed=2, tags=TAGS_SYM, flow=(0.3, 0.0, 2000.0, -1.0), limiter=1, order="colour"),
+    dict(nx=12, ny=9, seed=3, tags=TAGS_ALL, flow=(0.5, 3.0, 5e4, 3.0), limiter=0, order="natural"),
+    dict(nx=12, ny=9, seed=4, tags=TAGS_SYM, flow=(0.2, -4.0, 1e6, 3.0), limiter=1, order="colour"),
+])
+def test_residual_parity_small(igks, case):
+    m = mg.random_hybrid(case["nx"], case["ny"], seed=case["seed"], tags=case["tags"], jitter=0.3)
+    if case["order"] == "colour":
+        m, _, _ = mg.colour_order(m)
+    tag = f"small seed={case['seed']} lim={case['limiter']} sa={case['flow'][3] >= 0}"
+    say("case", tag, m.n_cells, "cells")
+    o, g = pair(igks, m, case["flow"], limiter=case["limiter"])
+    c = o.cells()
+    W0 = o.get_state()
+    check_residual(o, g, W0, tag + " freestream")
+    check_residual(o, g, smooth_state(W0, c["xc"], c["yc"], 0.08, case["seed"]), tag + " perturbed")
+
+
+@pytest.mark.parametrize("sa,limiter", [(False, 0), (True, 1)])
+def test_trajectory_parity(igks, sa, limiter):
+    """Same start, same ordering: the iterates of the GPU and the oracle stay
+    together (Eq.19-25 path, including the CFL law)."""
+    m = mg.random_hybrid(14, 10, seed=5, tags=TAGS_SYM, jitter=0.25)
+    m, _, _ = mg.colour_order(m)
+    flow = (0.3, 2.0, 3e4 if sa else 3e3, 3.0 if sa else -1.0)
+    tag = f"trajectory sa={sa} lim={limiter}"
+    say("case", tag)
+    o, g = pair(igks, m, flow, limiter=limiter, cfl_init=5.0, chunk=5)
+    for step in range(4):
+        o.iterate(5)
+        g.iterate(5)
+        Wo, Wg = o.get_state(), g.get_state()
+        scale = np.abs(Wo).max(axis=1, keepdims=True)
+        err = (np.abs(Wg - Wo) / np.maximum(scale, 1e-300)).max()
+        ro, rg = o.residual(), g.residual()
+        say(f"[{tag}] it={5 * (step + 1)} state err={err:.3e} cfl o={ro['cfl']:.6e} g={rg['cfl']:.6e}")
+        assert err <= 1e-9
+        assert rg["iteration"] == ro["iteration"]
+        assert abs(rg["cfl"] - ro["cfl"]) <= 1e-8 * ro["cfl"]
+        assert abs(rg["res_l2"] - ro["res_l2"]) <= 1e-8 * ro["res_l2"]
+        assert abs(rg["dt_flux"] - ro["dt_flux"]) <= 1e-12 * ro["dt_flux"]
+
+
+def test_plate_residual_and_wall_loads(igks):
+    m = mg.flat_plate()
+    flow = (0.3, 0.0, 1e4, -1.0)
+    say("case plate64x32")
+    o, g = pair(igks, m, flow, cfl_init=10.0)
+    c = o.cells()
+    W = smooth_state(o.get_state(), c["xc"], c["yc"], 0.05, 11)
+    check_residual(o, g, W, "plate perturbed")
+    lo, lg = o.wall_loads(), g.wall_loads()
+    assert np.allclose(lg["xw"], lo["xw"], rtol=0, atol=1e-15)
+    assert abs(lg["cd"] - lo["cd"]) <= 1e-11 * abs(lo["cd"])
+    assert np.allclose(lg["cf"], lo["cf"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(lg["cp"], lo["cp"], rtol=1e-10, atol=1e-12)
+
+
+def test_joukowski_full_size_residual(igks):
+    """The 40k-cell Joukowski hybrid mesh at its full size, in the launch
+    configuration the benchmark times: every cell compared."""
+    m = mg.workload("jouk40k")
+    say("case jouk40k", m.n_cells, "cells")
+    o, g = pair(igks, m, (0.5, 2.0, 5000.0, -1.0))
+    c = o.cells()
+    check_residual(o, g, o.get_state(), "jouk40k freestream")
+    check_residual(o, g, smooth_state(o.get_state(), c["xc"], c["yc"], 0.03, 7), "jouk40k perturbed")
+
+
+def test_set_state_rejects_nonphysical(igks):
+    m = mg.random_hybrid(4, 3, seed=1)
+    g = igks.Solver(m)
+    g.set_freestream(0.3, 0.0, 1e3)
+    W = g.get_state()
+    bad = W.copy()
+    bad[0, 3] = -1.0
+    with pytest.raises(igks.IgksError) as e:
+        g.set_state(bad)
+    assert e.value.code == igks.IGKS_ENONPHYS
+    assert np.array_equal(g.get_state(), W)
+
+
+def test_deterministic_runs(igks):
+    m = mg.random_hybrid(10, 8, seed=9, tags=TAGS_SYM)
+    m, _, _ = mg.colour_order(m)
+    runs = []
+    for _ in range(2):
+        g = igks.Solver(m, cfl_init=5.0, chunk=4)
+        g.set_freestream(0.3, 1.0, 1e4, 3.0)
+        g.iterate(12)
+        runs.append(g.get_state())
+    assert np.array_equal(runs[0], runs[1])
+
+
+def test_graph_chunks_match_direct_launches(igks):
+    m = mg.random_hybrid(10, 8, seed=10, tags=TAGS_ALL)
+    m, _, _ = mg.colour_order(m)
+    out = []
+    for chunk in (0, 3):
+        g = igks.Solver(m, cfl_init=5.0, chunk=chunk)
+        g.set_freestream(0.4, 2.0, 1e4)
+        g.iterate(9)
+        out.append(g.get_state())
+    assert np.array_equal(out[0], out[1])
