@@ -76,6 +76,8 @@ typedef struct igks_options {
     int mu_law;         /* 0: Sutherland, 1: constant viscosity */
     int chunk;          /* iterations per captured HIP graph launch; 0 = no graph */
     int block;          /* threads per block of the cell/face kernels; 0 = 256 */
+    int sweep;          /* LU-SGS sweep schedule: 0 auto, 1 one launch per wavefront,
+                           2 all wavefronts in one workgroup (barrier between wavefronts) */
 } igks_options;
 
 typedef struct igks_residual {
@@ -101,7 +103,8 @@ typedef struct igks_ctx igks_ctx;
 
 /* Fill *opt with the defaults: FP64, limiter off, cfl_init 1000 (Sec. 3.1),
  * cfl_min 1, cfl_max 1e6, Eq.25 law, cfl_flux 1, visc_sr on, Sutherland,
- * chunk 20, block 256. */
+ * chunk 20, block 256, sweep auto (one workgroup when the wavefronts are many and
+ * narrow: more than 16 of them averaging under 4096 cells). */
 void igks_default_options(igks_options *opt);
 
 /* Create a context.  opt may be NULL (defaults).  hip_stream is a

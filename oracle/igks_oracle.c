@@ -514,18 +514,23 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
     for (int i = 0; i < n_cells; i++) {
         int p0 = c->cptr[i], k = c->cptr[i + 1] - p0;
         if (k < 3) { seterr(c, "cell with fewer than 3 nodes"); return -2; }
+        /* shoelace area and area centroid, with coordinates taken relative
+         * to the cell's first vertex (the same formula; it keeps small cells
+         * far from the origin free of cancellation) */
         double a = 0, sx = 0, sy = 0;
+        double ox = c->x[c->cnod[p0]], oy = c->y[c->cnod[p0]];
         for (int j = 0; j < k; j++) {
             int n1 = c->cnod[p0 + j], n2 = c->cnod[p0 + (j + 1) % k];
-            double cr = c->x[n1] * c->y[n2] - c->x[n2] * c->y[n1];
-            a += cr; sx += (c->x[n1] + c->x[n2]) * cr; sy += (c->y[n1] + c->y[n2]) * cr;
+            double x1 = c->x[n1] - ox, y1 = c->y[n1] - oy, x2 = c->x[n2] - ox, y2 = c->y[n2] - oy;
+            double cr = x1 * y2 - x2 * y1;
+            a += cr; sx += (x1 + x2) * cr; sy += (y1 + y2) * cr;
         }
         if (a < 0) {   /* reverse */
             for (int j = 0; j < k / 2; j++) { int t = c->cnod[p0 + j]; c->cnod[p0 + j] = c->cnod[p0 + k - 1 - j]; c->cnod[p0 + k - 1 - j] = t; }
             a = -a; sx = -sx; sy = -sy;
         }
         if (!(a > 0)) { seterr(c, "degenerate cell"); return -2; }
-        c->area[i] = 0.5 * a; c->xc[i] = sx / (3.0 * a); c->yc[i] = sy / (3.0 * a);
+        c->area[i] = 0.5 * a; c->xc[i] = ox + sx / (3.0 * a); c->yc[i] = oy + sy / (3.0 * a);
     }
     /* edges: sort (min node, max node) keys and pair them */
     edge_rec *E = malloc(sizeof(edge_rec) * nv);

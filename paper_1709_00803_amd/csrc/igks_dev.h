@@ -83,6 +83,7 @@ template <typename T> void launch_flux(const Launch &L, const Params<T> &P);
 template <typename T> void launch_gather(const Launch &L, const Params<T> &P);
 template <typename T> void launch_reduce(const Launch &L, const Params<T> &P);
 template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd);
+template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd);
 template <typename T> void launch_update(const Launch &L, const Params<T> &P);
 template <typename T> void launch_commit(const Launch &L, const Params<T> &P);
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, int nw,

@@ -54,6 +54,8 @@ struct igks_ctx {
     Params<double> P64{};
     Params<float> P32{};
     int *d_wall_faces = nullptr;
+    int *d_lev_off = nullptr;
+    bool sweep_wg = false;
     double *d_wall_out = nullptr;
     double *d_wseg = nullptr;
     int max_blocks = 0;
@@ -348,7 +350,7 @@ struct WsMap {
     Buf sc, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, dW, xc, yc, area, lsinv, dwall, vtx;
     Buf cf_ptr, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
     Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, part, hist;
-    Buf wall_faces, wall_out, wseg;
+    Buf wall_faces, wall_out, wseg, lev_off;
     size_t total;
 };
 
@@ -376,6 +378,7 @@ WsMap layout(const HostMesh &m, const igks_options &o, int max_blocks, int hist_
     w.wall_faces = L.add((size_t)std::max(1, m.nwall) * I);
     w.wall_out = L.add((size_t)4 * std::max(1, m.nwall) * D);
     w.wseg = L.add((size_t)4 * std::max(1, m.nwall) * D);
+    w.lev_off = L.add((size_t)(m.nlev + 1) * I);
     w.total = L.total;
     return w;
 }
@@ -438,9 +441,13 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev)
     mark(3);
     launch_reduce(L, P);
     mark(4);
-    for (int l = 0; l < c->m.nlev; l++) launch_sweep(L, P, c->m.lev_off[l], c->m.lev_off[l + 1], true);
+    if (c->sweep_wg) launch_sweep_wg(L, P, c->d_lev_off, c->m.nlev, true);
+    else
+        for (int l = 0; l < c->m.nlev; l++) launch_sweep(L, P, c->m.lev_off[l], c->m.lev_off[l + 1], true);
     mark(5);
-    for (int l = c->m.nlev - 1; l >= 0; l--) launch_sweep(L, P, c->m.lev_off[l], c->m.lev_off[l + 1], false);
+    if (c->sweep_wg) launch_sweep_wg(L, P, c->d_lev_off, c->m.nlev, false);
+    else
+        for (int l = c->m.nlev - 1; l >= 0; l--) launch_sweep(L, P, c->m.lev_off[l], c->m.lev_off[l + 1], false);
     mark(6);
     launch_update(L, P);
     mark(7);
@@ -539,6 +546,7 @@ void igks_default_options(igks_options *o)
     o->mu_law = 0;
     o->chunk = 20;
     o->block = 256;
+    o->sweep = 0;
 }
 
 int igks_create(igks_ctx **out, const igks_options *opt, void *hip_stream)
@@ -551,6 +559,7 @@ int igks_create(igks_ctx **out, const igks_options *opt, void *hip_stream)
     if (c->opt.precision != IGKS_FP64 && c->opt.precision != IGKS_MIXED) { delete c; return IGKS_EINVAL; }
     if (c->opt.block <= 0) c->opt.block = 256;
     if (c->opt.block % 64 != 0 || c->opt.block > 1024) { delete c; return IGKS_EINVAL; }
+    if (c->opt.sweep < 0 || c->opt.sweep > 2) { delete c; return IGKS_EINVAL; }
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {
@@ -637,7 +646,13 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     rc |= up(w.fdl, m.fdl.data(), F * D); rc |= up(w.fdr, m.fdr.data(), F * D); rc |= up(w.frn, m.frn.data(), F * D);
     rc |= up(w.wall_faces, m.wall_faces.data(), m.wall_faces.size() * I);
     rc |= up(w.wseg, m.wseg.data(), m.wseg.size() * D);
+    rc |= up(w.lev_off, m.lev_off.data(), m.lev_off.size() * I);
     if (rc) return rc;
+    c->d_lev_off = (int *)(b + w.lev_off.off);
+    {
+        double width = (double)m.nc / std::max(1, m.nlev);
+        c->sweep_wg = c->opt.sweep == 2 || (c->opt.sweep == 0 && m.nlev > 16 && width < 4096.0);
+    }
     c->d_wall_faces = (int *)(b + w.wall_faces.off);
     c->d_wall_out = (double *)(b + w.wall_out.off);
     c->d_wseg = (double *)(b + w.wseg.off);

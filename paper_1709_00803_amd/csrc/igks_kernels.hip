@@ -686,14 +686,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(Params<T> P, int nblocks
 // boundary ghosts counted as upper neighbours with the ghost increments of
 // Sec. 2.5 taken from dW*_i.  The SA equation (Eq.31-32) is swept alongside.
 template <typename T, bool FWD>
-__global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
+__device__ __forceinline__ void sweep_cell(const Params<T> &P, const double *W, T cfl, int c)
 {
-    if (P.sc->halt) return;
-    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= c1) return;
     const int N = P.nc;
-    const double *W = cur_state(P);
-    const T cfl = T(P.sc->cfl);
     double w[5];
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
@@ -755,6 +750,33 @@ __global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
 #pragma unroll
         for (int k = 0; k < 4; k++) P.dW[k * N + c] = dws[k] - acc[k] / D;
         P.dW[4 * N + c] = P.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
+    }
+}
+
+template <typename T, bool FWD>
+__global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
+{
+    if (P.sc->halt) return;
+    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= c1) return;
+    sweep_cell<T, FWD>(P, cur_state(P), T(P.sc->cfl), c);
+}
+
+// The whole sweep in one workgroup: wavefront after wavefront, separated by
+// workgroup barriers (all waves of a workgroup share one CU and its L1, so
+// the barrier orders the dW writes of one wavefront before the reads of the
+// next).  Used when wavefronts are many and narrow.
+template <typename T, bool FWD>
+__global__ __launch_bounds__(1024) void k_sweep_wg(Params<T> P, const int *lev_off, int nlev)
+{
+    if (P.sc->halt) return;
+    const double *W = cur_state(P);
+    const T cfl = T(P.sc->cfl);
+    for (int i = 0; i < nlev; i++) {
+        int l = FWD ? i : nlev - 1 - i;
+        int c0 = lev_off[l], c1 = lev_off[l + 1];
+        for (int c = c0 + (int)threadIdx.x; c < c1; c += (int)blockDim.x) sweep_cell<T, FWD>(P, W, cfl, c);
+        __syncthreads();
     }
 }
 
@@ -872,6 +894,11 @@ template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int
     if (fwd) hipLaunchKernelGGL((k_sweep<T, true>), g, b, 0, L.s, P, c0, c1);
     else hipLaunchKernelGGL((k_sweep<T, false>), g, b, 0, L.s, P, c0, c1);
 }
+template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd)
+{
+    if (fwd) hipLaunchKernelGGL((k_sweep_wg<T, true>), dim3(1), dim3(1024), 0, L.s, P, lev_off, nlev);
+    else hipLaunchKernelGGL((k_sweep_wg<T, false>), dim3(1), dim3(1024), 0, L.s, P, lev_off, nlev);
+}
 template <typename T> void launch_update(const Launch &L, const Params<T> &P)
 {
     hipLaunchKernelGGL(k_update<T>, dim3(nblk(P.nc, L.block)), dim3(L.block), 0, L.s, P);
@@ -903,6 +930,7 @@ void launch_set_state(const Launch &L, int nc, const double *Winf, double *W)
     template void launch_gather<T>(const Launch &, const Params<T> &);                        \
     template void launch_reduce<T>(const Launch &, const Params<T> &);                        \
     template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, bool);         \
+    template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool); \
     template void launch_update<T>(const Launch &, const Params<T> &);                        \
     template void launch_commit<T>(const Launch &, const Params<T> &);
 INST(double)

@@ -183,3 +183,18 @@ def test_graph_chunks_match_direct_launches(igks):
         g.iterate(9)
         out.append(g.get_state())
     assert np.array_equal(out[0], out[1])
+
+
+def test_sweep_schedules_match(igks):
+    """One launch per wavefront and all wavefronts in one workgroup give
+    bitwise the same iterates (same per-cell arithmetic, same order)."""
+    m = mg.random_hybrid(12, 9, seed=12, tags=TAGS_SYM)      # natural order: many wavefronts
+    out = []
+    for sweep in (1, 2):
+        g = igks.Solver(m, cfl_init=20.0, chunk=4, sweep=sweep)
+        g.set_freestream(0.3, 1.0, 3e4, 3.0)
+        g.iterate(8)
+        out.append(g.get_state())
+    say("wavefronts", g.nlev)
+    assert g.nlev > 16
+    assert np.array_equal(out[0], out[1])
