@@ -295,17 +295,14 @@ def _extrude(P0: np.ndarray, heights, smooth_passes: int = 8, smooth_w: float = 
 
 
 def _points_in_polygon(pts: np.ndarray, poly: np.ndarray) -> np.ndarray:
-    """Even-odd ray casting, vectorised over points, looped over edges."""
-    x, y = pts[:, 0], pts[:, 1]
+    """Points strictly inside a simple polygon (matplotlib's even-odd test),
+    restricted to the polygon's bounding box first."""
+    from matplotlib.path import Path
+    lo, hi = poly.min(axis=0), poly.max(axis=0)
+    box = np.all((pts >= lo) & (pts <= hi), axis=1)
     inside = np.zeros(len(pts), dtype=bool)
-    n = len(poly)
-    for k in range(n):
-        x1, y1 = poly[k]
-        x2, y2 = poly[(k + 1) % n]
-        cond = (y1 > y) != (y2 > y)
-        with np.errstate(divide="ignore", invalid="ignore"):
-            xint = x1 + (y - y1) * (x2 - x1) / (y2 - y1)
-        inside ^= cond & (x < xint)
+    if box.any():
+        inside[box] = Path(poly).contains_points(pts[box])
     return inside
 
 
@@ -326,7 +323,7 @@ def _far_points(ring, hr, g, r_far, center, rng, h_max):
     """
     from scipy.spatial import cKDTree
     tree = cKDTree(ring)
-    kq = min(16, len(ring))
+    kq = min(8, len(ring))
 
     def hfun(p):
         d, idx = tree.query(p, k=kq)
@@ -413,8 +410,10 @@ def joukowski_hybrid(n_wall: int = 128, n_layers: int = 30, h1: float = 1e-4,
         g = 0.05
         for _ in range(6):
             pts, _ = gen(g)
-            n_tri = 2.0 * len(pts)
-            g *= math.sqrt(n_tri / tgt)
+            ratio = 2.0 * len(pts) / tgt
+            if abs(ratio - 1.0) < 0.03:
+                break
+            g *= math.sqrt(ratio)
         grade = g
     pts, hfun = gen(grade)
 
