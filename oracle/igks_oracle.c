@@ -839,8 +839,10 @@ static int residual(oigks_ctx *c)
         } else {
             /* reading (ghost-cell method): the ghost side of a boundary face
              * carries the boundary map of the reconstructed interior face
-             * state, with zero slopes; its cell-centre value is the map of
-             * the interior cell-centre value at the reflected centroid. */
+             * state (slopes: zero on free-stream and outflow faces, reflected
+             * on symmetry and wall faces, below); its cell-centre value is the
+             * map of the interior cell-centre value at the reflected
+             * centroid. */
             double tmp[5], out[5];
             for (int k = 0; k < 4; k++) tmp[k] = WL[k];
             tmp[4] = Wi[4];
@@ -862,6 +864,20 @@ static int residual(oigks_ctx *c)
         for (int k = 0; k < 4; k++) { tn[k] = GRx[k] * nx + GRy[k] * ny; tt[k] = GRx[k] * tx + GRy[k] * ty; }
         ROT(grn, tn); ROT(grt, tt);
 #undef ROT
+        if (j < 0 && (c->fbc[f] == BC_SYMMETRY || c->fbc[f] == BC_WALL)) {
+            /* reading (ghost-cell method): the ghost cell of a symmetry face
+             * is the mirror image of the interior cell and that of a no-slip
+             * wall its point reflection through the face (momentum reversed,
+             * bounce-back), slopes included.  In the face frame the normal
+             * derivative flips sign and the boundary map acts on the momentum
+             * components: symmetry (rho, -m_n, m_t, E), wall (rho, -m_n, -m_t,
+             * E); the wall also flips the tangential derivative.  This keeps
+             * the mass and energy fluxes through such faces zero. */
+            double sn = -1.0, st = (c->fbc[f] == BC_WALL) ? -1.0 : 1.0;
+            double bm_t = (c->fbc[f] == BC_WALL) ? -1.0 : 1.0;
+            double Bk[4] = {1.0, -1.0, bm_t, 1.0};
+            for (int k = 0; k < 4; k++) { grn[k] = sn * Bk[k] * gln[k]; grt[k] = st * Bk[k] * glt[k]; }
+        }
         /* tau from the interface equilibrium (Eq.34); the core needs W0
          * first, which it computes the same way */
         double sl[4], sr[4];

@@ -119,6 +119,22 @@ __device__ __forceinline__ void ghost_incr(int bc, const V *d, V nx, V ny, V *g)
     }
 }
 
+__device__ __forceinline__ double wave_min(double v)
+{
+    for (int o = warpSize / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = warpSize / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_or(int v)
+{
+    for (int o = warpSize / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ const double *cur_state(const Params<T> &P)
 {
@@ -356,11 +372,8 @@ __global__ void k_reset(Params<T> P, int mode)
 // gradients (Eq.6-7, ghost cells included), the Eq.9-10 limiter,
 // vorticity and the laminar viscosity.
 template <typename T>
-__global__ __launch_bounds__(256) void k_prep(Params<T> P)
+__device__ __forceinline__ void prep_cell(const Params<T> &P, int c, double &dtc)
 {
-    if (P.sc->halt) return;
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= P.nc) return;
     const int N = P.nc;
     const double *W = cur_state(P);
     double w[5];
@@ -397,8 +410,7 @@ __global__ __launch_bounds__(256) void k_prep(Params<T> P)
         }
     }
     P.lamc[c] = lc;
-    double dt = P.cfl_flux * P.area[c] / lc;
-    atomicMin(&P.sc->dtmin_bits, (unsigned long long)__double_as_longlong(dt));
+    dtc = P.cfl_flux * P.area[c] / lc;
     double L11 = P.lsinv[c], L12 = P.lsinv[N + c], L22 = P.lsinv[2 * N + c];
     double gx[4], gy[4];
 #pragma unroll
@@ -434,6 +446,20 @@ __global__ __launch_bounds__(256) void k_prep(Params<T> P)
         P.grad[k * N + c] = gx[k];
         P.grad[(4 + k) * N + c] = gy[k];
     }
+}
+
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prep(Params<T> P)
+{
+    if (P.sc->halt) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double dtc = INFINITY;
+    if (c < P.nc) prep_cell(P, c, dtc);
+    // one atomic per wave: the Eq.23 minimum over cells
+    dtc = wave_min(dtc);
+    if ((threadIdx.x & (warpSize - 1)) == 0 && dtc < INFINITY)
+        atomicMin(&P.sc->dtmin_bits, (unsigned long long)__double_as_longlong(dtc));
 }
 
 __device__ __forceinline__ bool physical(const double *w)
@@ -516,6 +542,19 @@ __global__ __launch_bounds__(256) void k_flux(Params<T> P)
         for (int k = 0; k < 4; k++) { tn[k] = grx[k] * nx + gry[k] * ny; tt[k] = grx[k] * tx + gry[k] * ty; }
         rot(tn, grn); rot(tt, grt);
     }
+    if (rr < 0) {
+        // ghost cell of a symmetry face = mirror image of the interior cell,
+        // of a no-slip wall = its point reflection through the face
+        // (bounce-back), slopes included: the normal derivative flips, the
+        // boundary map acts on the face-frame momentum, and the wall also
+        // flips the tangential derivative.
+        int bc = P.fbc[f];
+        if (bc == BC_SYMMETRY || bc == BC_WALL) {
+            double bt = (bc == BC_WALL) ? -1.0 : 1.0;
+            grn[0] = -gln[0]; grn[1] = gln[1]; grn[2] = -bt * gln[2]; grn[3] = -gln[3];
+            grt[0] = bt * glt[0]; grt[1] = -bt * glt[1]; grt[2] = glt[2]; grt[3] = bt * glt[3];
+        }
+    }
     double dt = __longlong_as_double((long long)P.sc->dtmin_bits);
     double nutf = fmax(0.5 * (wl[4] + wrc[4]), 0.0);
     double Fr[4];
@@ -559,11 +598,11 @@ __global__ __launch_bounds__(256) void k_flux(Params<T> P)
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather(Params<T> P)
 {
-    __shared__ double red0[256], red1[256];
+    __shared__ double red0[256], red1[256], red2[256];
     if (P.sc->halt) return;
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = P.nc, F = P.nf;
-    double s0 = 0.0, s1 = 0.0;
+    double s0 = 0.0, s1 = 0.0, rinf = 0.0;
     if (c < N) {
         const double *W = cur_state(P);
         double m[4] = {0, 0, 0, 0}, ls = 0.0, saR = 0.0, sagS = 0.0, sad = 0.0;
@@ -602,8 +641,7 @@ __global__ __launch_bounds__(256) void k_gather(Params<T> P)
 #pragma unroll
         for (int k = 0; k < 4; k++) P.M[k * N + c] = m[k];
         P.lsum[c] = 0.5 * ls;
-        double rinf = fmax(fmax(fabs(m[0]), fabs(m[1])), fmax(fabs(m[2]), fabs(m[3])));
-        atomicMax(&P.sc->resinf_bits, (unsigned long long)__double_as_longlong(rinf));
+        rinf = fmax(fmax(fabs(m[0]), fabs(m[1])), fmax(fabs(m[2]), fabs(m[3])));
         s0 = m[0] * m[0];
         if (P.sa) {
             double Sr, jd;
@@ -619,17 +657,20 @@ __global__ __launch_bounds__(256) void k_gather(Params<T> P)
     }
     red0[threadIdx.x] = s0;
     red1[threadIdx.x] = s1;
+    red2[threadIdx.x] = rinf;
     __syncthreads();
     for (int h = blockDim.x / 2; h > 0; h >>= 1) {
         if (threadIdx.x < h) {
             red0[threadIdx.x] += red0[threadIdx.x + h];
             red1[threadIdx.x] += red1[threadIdx.x + h];
+            red2[threadIdx.x] = fmax(red2[threadIdx.x], red2[threadIdx.x + h]);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         P.part[blockIdx.x] = red0[0];
         P.part[P.max_blocks + blockIdx.x] = red1[0];
+        atomicMax(&P.sc->resinf_bits, (unsigned long long)__double_as_longlong(red2[0]));
     }
 }
 
@@ -783,11 +824,8 @@ __global__ __launch_bounds__(1024) void k_sweep_wg(Params<T> P, const int *lev_o
 // Per cell: W^{n+1} = W^n + dW into the other state buffer (Eq.17),
 // nu~ clipped at 0, positivity check, Eq.40.
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(Params<T> P)
+__device__ __forceinline__ void update_cell(const Params<T> &P, int c, double &e40, int &bad)
 {
-    if (P.sc->halt) return;
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= P.nc) return;
     const int N = P.nc;
     const double *W = cur_state(P);
     double *Wn = (P.sc->ncommit & 1) ? P.Wa : P.Wb;
@@ -804,10 +842,27 @@ __global__ __launch_bounds__(256) void k_update(Params<T> P)
     if (P.sa) t = fmax(t + double(P.dW[4 * N + c]), 0.0);
     Wn[4 * N + c] = t;
     double p = w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0];
-    if (!(w[0] > 0.0) || !(p > 0.0) || !isfinite(t) || !isfinite(p)) atomicOr(&P.sc->bad, 1);
+    if (!(w[0] > 0.0) || !(p > 0.0) || !isfinite(t) || !isfinite(p)) bad = 1;
     double e = sqrt(num / den);
-    if (isfinite(e)) atomicMax(&P.sc->e40_bits, (unsigned long long)__double_as_longlong(e));
+    e40 = isfinite(e) ? e : 0.0;
 }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(Params<T> P)
+{
+    if (P.sc->halt) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    int bad = 0;
+    if (c < P.nc) update_cell(P, c, e, bad);
+    e = wave_max(e);
+    bad = wave_or(bad);
+    if ((threadIdx.x & (warpSize - 1)) == 0) {
+        if (e > 0.0) atomicMax(&P.sc->e40_bits, (unsigned long long)__double_as_longlong(e));
+        if (bad) atomicOr(&P.sc->bad, 1);
+    }
+}
+
 
 template <typename T>
 __global__ void k_commit(Params<T> P)

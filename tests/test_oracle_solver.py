@@ -104,6 +104,22 @@ def test_conservation():
     assert np.all(np.abs(tot) <= 1e-13 * G.sum(axis=1))
 
 
+@pytest.mark.parametrize("bc", [mg.SYMMETRY, mg.WALL])
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_closed_box_conserves_mass_and_energy(bc, limiter):
+    """Sec. 2.5 ghost cells: a symmetry face (mirror image) and a no-slip
+    wall (point reflection, bounce-back) let no mass and no energy through,
+    so in a box closed by them sum_i M_rho,i = sum_i M_E,i = 0 for any state."""
+    tags = dict(bottom=bc, top=bc, left=bc, right=bc)
+    m = mg.random_hybrid(9, 7, seed=14, tags=tags, jitter=0.3)
+    o = po.Oracle(m, limiter=limiter)
+    o.set_freestream(0.4, 20.0, 300.0, 3.0)
+    o.set_state(smooth_state(o, 0.1, 9))
+    M, G = o.compute_residual()
+    for k in (0, 3):
+        assert abs(M[k].sum()) <= 1e-13 * G[k].sum(), (k, M[k].sum(), G[k].sum())
+
+
 def _rotate_state(W, th, mirror=False):
     W = W.copy()
     if mirror:
