@@ -24,10 +24,12 @@ constexpr int RED_THREADS = 256;
 // Per-context scalars living in device memory.  Integer atomics only:
 // non-negative doubles compare like their bit patterns, so min/max of
 // them is exact and order independent.
+constexpr int NSLOT = 64;     // atomic min/max targets are spread over this many slots
+
 struct DevScalars {
-    unsigned long long dtmin_bits;   // Eq.23 minimum over cells
-    unsigned long long resinf_bits;  // max |M|
-    unsigned long long e40_bits;     // Eq.40 maximum
+    unsigned long long dtmin_bits[NSLOT];   // Eq.23 minimum over cells (min over slots)
+    unsigned long long resinf_bits[NSLOT];  // max |M| (max over slots)
+    unsigned long long e40_bits[NSLOT];     // Eq.40 maximum (max over slots)
     int bad;                         // an update produced a non-physical state
     int halt;                        // stop the rest of the queued work
     int ncommit;                     // committed iterations; its parity picks the state buffer

@@ -782,7 +782,7 @@ int igks_set_state(igks_ctx *c, const double *W, const igks_scalars *sc)
         s.res_inf_prev = sc->res_inf_prev;
         s.res0 = sc->res0;
     }
-    s.dtmin_bits = 0x7ff0000000000000ull;
+    for (int i = 0; i < NSLOT; i++) s.dtmin_bits[i] = 0x7ff0000000000000ull;
     double *dst = (s.ncommit & 1) ? c->P64.Wb : c->P64.Wa;
     HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), sizeof(double) * 5 * N, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P64.sc, &s, sizeof(DevScalars), hipMemcpyHostToDevice, c->stream));

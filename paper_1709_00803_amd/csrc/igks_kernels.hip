@@ -263,7 +263,8 @@ __device__ __forceinline__ void side_terms(const double *w, const double *gn, co
 }
 
 // GKS interface flux (Eq.4-5, Eq.11-14) in the face frame; returns the
-// flux integrated over [0, dt].
+// flux integrated over [0, dt].  The equilibrium part is evaluated one
+// half space at a time so that only one set of moments is live at once.
 template <typename T>
 __device__ __forceinline__ void gks_flux(const Params<T> &P, const double *wl, const double *gln, const double *glt,
                                          const double *wr, const double *grn, const double *grt, const double *wlc,
@@ -277,30 +278,13 @@ __device__ __forceinline__ void gks_flux(const Params<T> &P, const double *wl, c
 
     // interface equilibrium g0 (moments of H g^l + (1-H) g^r)
     double r0 = w0[0], U0 = w0[1] / r0, V0 = w0[2] / r0, lam0 = lam_of(w0);
-    double mf[8], mp[8], mm[8], mv[8], mx[3];
-    mom_u<0>(U0, lam0, mf);
-    mom_u<+1>(U0, lam0, mp);
-    mom_u<-1>(U0, lam0, mm);
-    mom_u<0>(V0, lam0, mv);
-    mom_xi(lam0, mx);
-    double abl[4], abr[4], abt[4], b[4];
     double ir0 = 1.0 / r0;
-#pragma unroll
-    for (int k = 0; k < 4; k++) b[k] = (w0[k] - wlc[k]) / dl * ir0;
-    msolve(U0, V0, lam0, b, abl);
-#pragma unroll
-    for (int k = 0; k < 4; k++) b[k] = (wrc[k] - w0[k]) / dr * ir0;
-    msolve(U0, V0, lam0, b, abr);
-#pragma unroll
-    for (int k = 0; k < 4; k++) b[k] = 0.5 * (glt[k] + grt[k]) * ir0;
-    msolve(U0, V0, lam0, b, abt);
 
-    // Eq.34 collision time at the interface
+    // Eq.34 collision time at the interface and the time integrals of the
+    // six Eq.13 factors over [0, dt]
     double mul = mu_lam(P, lam0), mut = 0.0;
     if (P.sa && nut_f > 0.0) mut = r0 * nut_f * sa_fv1(nut_f * r0 / mul);
     double tau = (mul + mut) * 2.0 * lam0 / r0;
-
-    // time integrals of the six Eq.13 factors over [0, dt]
     double eta = exp(-dt / tau), ome = -expm1(-dt / tau);
     double T1 = dt - tau * ome;
     double T2 = -tau * dt * (1.0 + eta) + 2.0 * tau * tau * ome;
@@ -309,29 +293,59 @@ __device__ __forceinline__ void gks_flux(const Params<T> &P, const double *wl, c
     double T5 = tau * dt * eta - 2.0 * tau * tau * ome;
     double T6 = -tau * tau * ome;
 
-    // Eq.12 -> Abar
-    double q2[4], t[4], s[4], Ab[4];
-    pmom<1, 0>(mp, mv, mx, abl, t);
-    pmom<1, 0>(mm, mv, mx, abr, s);
-    pmom<0, 1>(mf, mv, mx, abt, q2);
+    double mv[8], mx[3];
+    mom_u<0>(V0, lam0, mv);
+    mom_xi(lam0, mx);
+    // q2 = <psi (abar_n H u + abar_n' (1-H) u + abar_t v)> and its flux
+    // moment f2 = <u psi (...)>, half space by half space
+    double q2[4], f2[4], a[4], b[4], t[4];
+    {
 #pragma unroll
-    for (int k = 0; k < 4; k++) q2[k] = r0 * (q2[k] + t[k] + s[k]);
+        for (int k = 0; k < 4; k++) b[k] = (w0[k] - wlc[k]) / dl * ir0;
+        msolve(U0, V0, lam0, b, a);
+        double mp[8];
+        mom_u<+1>(U0, lam0, mp);
+        pmom<1, 0>(mp, mv, mx, a, q2);
+        pmom<2, 0>(mp, mv, mx, a, f2);
+    }
+    {
+#pragma unroll
+        for (int k = 0; k < 4; k++) b[k] = (wrc[k] - w0[k]) / dr * ir0;
+        msolve(U0, V0, lam0, b, a);
+        double mm[8];
+        mom_u<-1>(U0, lam0, mm);
+        pmom<1, 0>(mm, mv, mx, a, t);
+#pragma unroll
+        for (int k = 0; k < 4; k++) q2[k] += t[k];
+        pmom<2, 0>(mm, mv, mx, a, t);
+#pragma unroll
+        for (int k = 0; k < 4; k++) f2[k] += t[k];
+    }
+    double mf[8];
+    mom_u<0>(U0, lam0, mf);
+#pragma unroll
+    for (int k = 0; k < 4; k++) b[k] = 0.5 * (glt[k] + grt[k]) * ir0;
+    msolve(U0, V0, lam0, b, a);
+    pmom<0, 1>(mf, mv, mx, a, t);
+#pragma unroll
+    for (int k = 0; k < 4; k++) q2[k] = r0 * (q2[k] + t[k]);
+    pmom<1, 1>(mf, mv, mx, a, t);
+#pragma unroll
+    for (int k = 0; k < 4; k++) f2[k] += t[k];
+
+    // Eq.12 -> Abar
     double den = r0 * (0.5 * dt * dt - T3);
 #pragma unroll
     for (int k = 0; k < 4; k++) b[k] = (T2 * q2[k] + T5 * q5[k] + T6 * q6[k]) / den;
-    msolve(U0, V0, lam0, b, Ab);
+    msolve(U0, V0, lam0, b, a);
 
     // Eq.14
-    double e1[4], e2[4], e3[4];
+    double e1[4];
     pmom1<1>(mf, mv, mx, e1);
-    pmom<2, 0>(mp, mv, mx, abl, t);
-    pmom<2, 0>(mm, mv, mx, abr, s);
-    pmom<1, 1>(mf, mv, mx, abt, e2);
-    pmom<1, 0>(mf, mv, mx, Ab, e3);
+    pmom<1, 0>(mf, mv, mx, a, t);
 #pragma unroll
     for (int k = 0; k < 4; k++)
-        F[k] = T1 * r0 * e1[k] + T2 * r0 * (t[k] + s[k] + e2[k]) + T3 * r0 * e3[k] + T4 * f4[k] + T5 * f5[k] +
-               T6 * f6[k];
+        F[k] = T1 * r0 * e1[k] + T2 * r0 * f2[k] + T3 * r0 * t[k] + T4 * f4[k] + T5 * f5[k] + T6 * f6[k];
 }
 
 // Euler flux Jacobian-vector product J(W, n) d (the linearised flux of the
@@ -354,16 +368,36 @@ __device__ __forceinline__ void jac_vec(const V *W, V nx, V ny, const V *d, V *o
 
 // ------------------------------------------------------------------ kernels
 
+__device__ __forceinline__ void reset_slots(DevScalars *sc)
+{
+    for (int i = 0; i < NSLOT; i++) {
+        sc->dtmin_bits[i] = 0x7ff0000000000000ull;   // +inf
+        sc->resinf_bits[i] = 0ull;
+        sc->e40_bits[i] = 0ull;
+    }
+}
+// min / max over the slots, read by one full wave (lane i reads slot i)
+__device__ __forceinline__ double slots_min(const unsigned long long *b)
+{
+    double v = __longlong_as_double((long long)b[threadIdx.x & (NSLOT - 1)]);
+    return wave_min(v);
+}
+__device__ __forceinline__ double slots_max(const unsigned long long *b)
+{
+    double v = __longlong_as_double((long long)b[threadIdx.x & (NSLOT - 1)]);
+    return wave_max(v);
+}
+__device__ __forceinline__ unsigned slot_of(int wave)
+{
+    return (unsigned)wave & (NSLOT - 1);
+}
+
 // mode bit 1: per-iteration atomics; 2: halt/bad flags; 4: chunk history
 template <typename T>
 __global__ void k_reset(Params<T> P, int mode)
 {
     DevScalars *sc = P.sc;
-    if (mode & 1) {
-        sc->dtmin_bits = 0x7ff0000000000000ull;   // +inf
-        sc->resinf_bits = 0ull;
-        sc->e40_bits = 0ull;
-    }
+    if (mode & 1) reset_slots(sc);
     if (mode & 2) { sc->bad = 0; sc->halt = 0; }
     if (mode & 4) sc->hist_n = 0;
 }
@@ -458,8 +492,10 @@ __global__ __launch_bounds__(256) void k_prep(Params<T> P)
     if (c < P.nc) prep_cell(P, c, dtc);
     // one atomic per wave: the Eq.23 minimum over cells
     dtc = wave_min(dtc);
-    if ((threadIdx.x & (warpSize - 1)) == 0 && dtc < INFINITY)
-        atomicMin(&P.sc->dtmin_bits, (unsigned long long)__double_as_longlong(dtc));
+    if ((threadIdx.x & (warpSize - 1)) == 0 && dtc < INFINITY) {
+        int wv = (blockIdx.x * blockDim.x + threadIdx.x) / warpSize;
+        atomicMin(&P.sc->dtmin_bits[slot_of(wv)], (unsigned long long)__double_as_longlong(dtc));
+    }
 }
 
 __device__ __forceinline__ bool physical(const double *w)
@@ -470,11 +506,8 @@ __device__ __forceinline__ bool physical(const double *w)
 // Per face: reconstruction (Eq.10), ghost side, the GKS flux, the LU-SGS
 // spectral radius and the SA face terms (Eq.28-30).
 template <typename T>
-__global__ __launch_bounds__(256) void k_flux(Params<T> P)
+__device__ __forceinline__ void flux_face(const Params<T> &P, int f, double dt)
 {
-    if (P.sc->halt) return;
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= P.nf) return;
     const int N = P.nc, F = P.nf;
     const double *W = cur_state(P);
     int l = P.fl[f], rr = P.fr[f];
@@ -524,6 +557,30 @@ __global__ __launch_bounds__(256) void k_flux(Params<T> P)
         dr = dl;
         rn = P.frn[f];
     }
+    // spectral radius of the face for the implicit operator
+    double qi = (wl[1] * nx + wl[2] * ny) / wl[0], qj = (wrc[1] * nx + wrc[2] * ny) / wrc[0];
+    double li = fabs(qi) + sqrt(GAMMA / (2.0 * lam_of(wl)));
+    double lj = fabs(qj) + sqrt(GAMMA / (2.0 * lam_of(wrc)));
+    double lamf = fmax(li, lj);
+    double mi = mu_lam(P, lam_of(wl)), mj = mu_lam(P, lam_of(wrc));
+    if (P.visc_sr) {
+        double ei = mi, ej = mj;
+        if (P.sa) {
+            if (wl[4] > 0) ei += wl[0] * wl[4] * sa_fv1(wl[4] * wl[0] / mi);
+            if (wrc[4] > 0) ej += wrc[0] * wrc[4] * sa_fv1(wrc[4] * wrc[0] / mj);
+        }
+        lamf += (ei / wl[0] + ej / wrc[0]) / rn;
+    }
+    P.lam[f] = lamf;
+    if (P.sa) {
+        double nui = mi / wl[0], nuj = mj / wrc[0];
+        double ti = wl[4], tj = wrc[4];
+        double g = (tj - ti) / rn;
+        double Finv = 0.5 * (qi + fabs(qi)) * ti + 0.5 * (qj - fabs(qj)) * tj;
+        double Fvis = (0.5 / SA_SIGMA) * ((nui + nuj) + (1.0 + SA_CB2) * (ti + tj)) * g;
+        P.saf[f] = (Fvis - Finv) * S;
+        P.sag[f] = g * S;
+    }
     // face frame
     double fwl[4], fwr[4], fwlc[4], fwrc[4], gln[4], glt[4], grn[4], grt[4];
     auto rot = [&](const double *src, double *dst) {
@@ -555,7 +612,6 @@ __global__ __launch_bounds__(256) void k_flux(Params<T> P)
             grt[0] = bt * glt[0]; grt[1] = -bt * glt[1]; grt[2] = glt[2]; grt[3] = bt * glt[3];
         }
     }
-    double dt = __longlong_as_double((long long)P.sc->dtmin_bits);
     double nutf = fmax(0.5 * (wl[4] + wrc[4]), 0.0);
     double Fr[4];
     gks_flux(P, fwl, gln, glt, fwr, grn, grt, fwlc, fwrc, dl, dr, dt, nutf, Fr);
@@ -566,30 +622,20 @@ __global__ __launch_bounds__(256) void k_flux(Params<T> P)
     P.flux[2 * F + f] = (Fn * ny + Ft * ty) * S;
     P.flux[3 * F + f] = Fr[3] * idt * S;
 
-    // spectral radius of the face for the implicit operator
-    double qi = (wl[1] * nx + wl[2] * ny) / wl[0], qj = (wrc[1] * nx + wrc[2] * ny) / wrc[0];
-    double li = fabs(qi) + sqrt(GAMMA / (2.0 * lam_of(wl)));
-    double lj = fabs(qj) + sqrt(GAMMA / (2.0 * lam_of(wrc)));
-    double lamf = fmax(li, lj);
-    double mi = mu_lam(P, lam_of(wl)), mj = mu_lam(P, lam_of(wrc));
-    if (P.visc_sr) {
-        double ei = mi, ej = mj;
-        if (P.sa) {
-            if (wl[4] > 0) ei += wl[0] * wl[4] * sa_fv1(wl[4] * wl[0] / mi);
-            if (wrc[4] > 0) ej += wrc[0] * wrc[4] * sa_fv1(wrc[4] * wrc[0] / mj);
-        }
-        lamf += (ei / wl[0] + ej / wrc[0]) / rn;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_flux(Params<T> P)
+{
+    __shared__ double sdt;
+    if (P.sc->halt) return;
+    if (threadIdx.x < warpSize) {
+        double v = slots_min(P.sc->dtmin_bits);   // Eq.23 time step
+        if (threadIdx.x == 0) sdt = v;
     }
-    P.lam[f] = lamf;
-    if (P.sa) {
-        double nui = mi / wl[0], nuj = mj / wrc[0];
-        double ti = wl[4], tj = wrc[4];
-        double g = (tj - ti) / rn;
-        double Finv = 0.5 * (qi + fabs(qi)) * ti + 0.5 * (qj - fabs(qj)) * tj;
-        double Fvis = (0.5 / SA_SIGMA) * ((nui + nuj) + (1.0 + SA_CB2) * (ti + tj)) * g;
-        P.saf[f] = (Fvis - Finv) * S;
-        P.sag[f] = g * S;
-    }
+    __syncthreads();
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < P.nf) flux_face(P, f, sdt);
 }
 
 // Per cell: residual M (Eq.16) as the signed sum of its face fluxes, the
@@ -670,7 +716,7 @@ __global__ __launch_bounds__(256) void k_gather(Params<T> P)
     if (threadIdx.x == 0) {
         P.part[blockIdx.x] = red0[0];
         P.part[P.max_blocks + blockIdx.x] = red1[0];
-        atomicMax(&P.sc->resinf_bits, (unsigned long long)__double_as_longlong(red2[0]));
+        atomicMax(&P.sc->resinf_bits[slot_of(blockIdx.x)], (unsigned long long)__double_as_longlong(red2[0]));
     }
 }
 
@@ -693,9 +739,13 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(Params<T> P, int nblocks
         if (threadIdx.x < h) { a[threadIdx.x] += a[threadIdx.x + h]; b[threadIdx.x] += b[threadIdx.x + h]; }
         __syncthreads();
     }
+    double rinf = 0.0, dtf = 0.0;
+    if (threadIdx.x < warpSize) {
+        rinf = slots_max(sc->resinf_bits);
+        dtf = slots_min(sc->dtmin_bits);
+    }
     if (threadIdx.x == 0) {
         double l2 = sqrt(a[0]), sal2 = sqrt(b[0]);
-        double rinf = __longlong_as_double((long long)sc->resinf_bits);
         if (sc->ncommit == 0) {
             sc->res0 = l2;
             sc->cfl = P.cfl_init;
@@ -709,8 +759,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(Params<T> P, int nblocks
         sc->res_l2 = l2;
         sc->sa_l2 = sal2;
         sc->res_inf = rinf;
-        sc->dt_flux = __longlong_as_double((long long)sc->dtmin_bits);
-        sc->resinf_bits = 0ull;
+        sc->dt_flux = dtf;
         int h = sc->hist_n;
         if (h < P.hist_cap) {
             double *e = P.hist + HIST_W * h;
@@ -858,7 +907,8 @@ __global__ __launch_bounds__(256) void k_update(Params<T> P)
     e = wave_max(e);
     bad = wave_or(bad);
     if ((threadIdx.x & (warpSize - 1)) == 0) {
-        if (e > 0.0) atomicMax(&P.sc->e40_bits, (unsigned long long)__double_as_longlong(e));
+        int wv = (blockIdx.x * blockDim.x + threadIdx.x) / warpSize;
+        if (e > 0.0) atomicMax(&P.sc->e40_bits[slot_of(wv)], (unsigned long long)__double_as_longlong(e));
         if (bad) atomicOr(&P.sc->bad, 1);
     }
 }
@@ -869,7 +919,8 @@ __global__ void k_commit(Params<T> P)
 {
     DevScalars *sc = P.sc;
     if (sc->halt) return;
-    double e40 = __longlong_as_double((long long)sc->e40_bits);
+    double e40 = slots_max(sc->e40_bits);
+    if (threadIdx.x != 0) return;
     sc->e40 = e40;
     int h = sc->hist_n;
     if (h < P.hist_cap) P.hist[HIST_W * h + 4] = e40;
@@ -879,8 +930,7 @@ __global__ void k_commit(Params<T> P)
     } else {
         sc->ncommit += 1;
     }
-    sc->dtmin_bits = 0x7ff0000000000000ull;
-    sc->e40_bits = 0ull;
+    reset_slots(sc);
 }
 
 // exact distance from each centroid to the nearest wall segment
@@ -960,7 +1010,7 @@ template <typename T> void launch_update(const Launch &L, const Params<T> &P)
 }
 template <typename T> void launch_commit(const Launch &L, const Params<T> &P)
 {
-    hipLaunchKernelGGL(k_commit<T>, dim3(1), dim3(1), 0, L.s, P);
+    hipLaunchKernelGGL(k_commit<T>, dim3(1), dim3(64), 0, L.s, P);
 }
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, int nw, const double *wseg,
                           double *dwall)
