@@ -35,6 +35,10 @@ WORKLOADS = {
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 FP64_VALU_PEAK_TFS = 78.6   # MI355X FP64 vector
+# FP64 operations per face of k_flux, counted with rocprofv3
+# (SQ_INSTS_VALU_FMA_F64 x 2 + MUL + ADD + TRANS, per wave / faces per wave)
+FLUX_FLOP_PER_FACE = 3918.0
+KSRC = os.path.join(ROOT, "paper_1709_00803_amd", "csrc", "igks_kernels.hip")
 
 
 def kernel_bytes(n, f, e, sa, mixed):
@@ -54,6 +58,46 @@ def kernel_bytes(n, f, e, sa, mixed):
     b["update"] = 5 * d * n + 5 * dw * n + 5 * d * n
     b["reduce"] = 2 * d * ((n + 255) // 256)
     return b
+
+
+def kernel_source_hash():
+    import hashlib
+    return hashlib.sha256(open(KSRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary (profiles/traffic_<workload>.json), or None when the kernels
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch", {}).get(kernel)
+
+
+def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000):
+    """Iterations and seconds from the impulsive start to a density-residual
+    drop of `target` on the laminar flat plate (64x32, natural order)."""
+    import torch
+    m = mg.flat_plate()
+    s = igks.Solver(m, precision=precision, cfl_init=10.0, chunk=100)
+    s.set_freestream(*WORKLOADS["plate64x32"]["flow"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = 0
+    while it < max_it:
+        s.iterate(100)
+        it += 100
+        if s.residual()["res_drop"] <= target:
+            break
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    wl = s.wall_loads()
+    return dict(iterations=it, seconds=round(dt, 4), drop=s.residual()["res_drop"], cd=wl["cd"],
+                cell_updates_per_s=m.n_cells * it / dt)
 
 
 def run_cpu_baseline(mesh, flow, budget_s=12.0, max_it=60):
@@ -84,6 +128,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=20)
     ap.add_argument("--profile-iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -129,10 +174,21 @@ def main():
     dom = max(kt, key=lambda k: kt[k])
     launches = {"sweep_fwd": solver.nlev, "sweep_bwd": solver.nlev}.get(dom, 1)
     t_ms = kt[dom]
-    achieved = kb[dom] / (t_ms * 1e-3) / 1e9 if t_ms > 0 else 0.0
-    roofline = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None, launches_per_step=launches,
-                    ms_per_step=t_ms, kernel_ms_per_step={k: round(v, 5) for k, v in kt.items()})
+    if dom == "flux":
+        achieved = FLUX_FLOP_PER_FACE * solver.nf / (t_ms * 1e-3) / 1e12 if t_ms > 0 else 0.0
+        roofline = dict(kernel=dom, bound="alu", achieved=achieved, peak=FP64_VALU_PEAK_TFS, unit="TFLOP/s",
+                        frac=achieved / FP64_VALU_PEAK_TFS)
+    else:
+        achieved = kb[dom] / launches / (t_ms / launches * 1e-3) / 1e9 if t_ms > 0 else 0.0
+        roofline = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=achieved / HBM_PEAK_GBS)
+    tr = measured_traffic(args.workload, dom) if not mixed else None
+    roofline.update(traffic=tr, launches_per_step=launches, ms_per_step=t_ms,
+                    algorithmic_bytes_per_step=kb[dom],
+                    kernel_ms_per_step={k: round(v, 5) for k, v in kt.items()})
+    # the face-flux kernel against the FP64 vector peak, whatever dominates
+    tf = kt.get("flux", 0.0)
+    roofline["flux_fp64_tflops"] = FLUX_FLOP_PER_FACE * solver.nf / (tf * 1e-3) / 1e12 if tf > 0 else 0.0
 
     out = {
         "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
@@ -144,6 +200,10 @@ def main():
                    "chunk": args.chunk, "res_drop_after": res["res_drop"]},
         "roofline": roofline,
     }
+    if not args.no_drop:
+        out["time_to_1e-10"] = {"workload": "plate64x32 (natural order), Ma 0.3 Re_L 1e4, CFL 10 -> Eq.25",
+                                "fp64": time_to_drop(igks, mg, igks.IGKS_FP64),
+                                "mixed": time_to_drop(igks, mg, igks.IGKS_MIXED)}
     if not args.no_cpu:
         out["cpu_baseline"] = run_cpu_baseline(mesh, wl["flow"])
     print(json.dumps(out), flush=True)

@@ -198,3 +198,54 @@ def test_sweep_schedules_match(igks):
     say("wavefronts", g.nlev)
     assert g.nlev > 16
     assert np.array_equal(out[0], out[1])
+
+
+def test_mixed_precision_tracks_fp64(igks):
+    """FP32 sweeps with the FP64 residual and update: the iterates stay
+    within FP32 rounding of the FP64 path, and the residual evaluation
+    itself is unchanged (it is FP64 in both modes)."""
+    m = mg.random_hybrid(14, 10, seed=5, tags=TAGS_SYM, jitter=0.25)
+    m, _, _ = mg.colour_order(m)
+    flow = (0.3, 2.0, 3e4, 3.0)
+    out = {}
+    for prec in (igks.IGKS_FP64, igks.IGKS_MIXED):
+        g = igks.Solver(m, precision=prec, cfl_init=5.0, chunk=5)
+        g.set_freestream(*flow)
+        g.iterate(10)
+        out[prec] = (g.get_state(), g.compute_residual())
+    W64, M64 = out[igks.IGKS_FP64]
+    W32, M32 = out[igks.IGKS_MIXED]
+    scale = np.abs(W64).max(axis=1, keepdims=True)
+    err = (np.abs(W32 - W64) / scale).max()
+    say(f"[mixed] state err after 10 iterations {err:.3e}")
+    assert err < 1e-5
+    assert err > 0.0
+
+
+def test_converged_plate_drag_matches_oracle(igks):
+    """Converged lift/drag parity (1e-9): the GPU runs the laminar plate from
+    the impulsive start to a 1e-10 drop; the oracle's converged state is the
+    stored fixture written by tests/golden/make_plate_state.py."""
+    import os
+    fx = np.load(os.path.join(os.path.dirname(__file__), "golden", "plate64x32_converged.npz"))
+    m = mg.flat_plate()
+    o = po.Oracle(m, cfl_init=10.0)
+    o.set_freestream(0.3, 0.0, 1e4)
+    o.set_state(fx["W"])
+    lo = o.wall_loads()
+    for prec in (igks.IGKS_FP64, igks.IGKS_MIXED):
+        g = igks.Solver(m, precision=prec, cfl_init=10.0, chunk=100)
+        g.set_freestream(0.3, 0.0, 1e4)
+        it = 0
+        while it < 20000:
+            g.iterate(500)
+            it += 500
+            if g.residual()["res_drop"] < 1e-10:
+                break
+        lg = g.wall_loads()
+        rel = abs(lg["cd"] - lo["cd"]) / abs(lo["cd"])
+        dW = (np.abs(g.get_state() - fx["W"]) / np.abs(fx["W"]).max(axis=1, keepdims=True)).max()
+        say(f"[converged plate prec={prec}] {it} its drop={g.residual()['res_drop']:.2e} "
+            f"cd gpu={lg['cd']:.15e} oracle={lo['cd']:.15e} rel={rel:.2e} state={dW:.2e}")
+        assert g.residual()["res_drop"] < 1e-10
+        assert rel <= 1e-9
