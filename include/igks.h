@@ -185,6 +185,45 @@ int igks_compute_residual(igks_ctx *ctx, double *M);
  * face midpoint.  Every pointer may be NULL; arrays hold n_wall_faces. */
 int igks_get_wall_loads(igks_ctx *ctx, double *cl, double *cd, double *cf, double *cp, double *xw);
 
+/* ---------------------------------------------------------------------
+ * Batches: many independent instances (mesh + flow condition, uneven
+ * sizes) iterated together, every kernel launch and every captured graph
+ * covering all of them.  The single-instance calls above act on instance
+ * 0 of a one-instance context; the calls below take an instance index.
+ * Order: igks_batch_create -> igks_batch_mesh_upload for every instance ->
+ * igks_workspace_size / igks_bind_workspace -> igks_batch_set_freestream
+ * for every instance -> igks_iterate (all instances) -> getters.
+ * An instance whose update is rejected (IGKS_ENONPHYS) is frozen at its
+ * last good state while the others go on; igks_iterate then returns
+ * IGKS_ENONPHYS and igks_batch_status tells which.
+ * ------------------------------------------------------------------- */
+int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream, int32_t n_inst);
+int igks_batch_mesh_upload(igks_ctx *ctx, int32_t inst, int32_t n_nodes, const double *xy, int32_t n_cells,
+                           const int32_t *cell_ptr, const int32_t *cell_nodes, int32_t n_bfaces,
+                           const int32_t *bface_nodes, const int32_t *bface_tag);
+int igks_batch_mesh_info(const igks_ctx *ctx, int32_t inst, int32_t *n_cells, int32_t *n_faces,
+                         int32_t *n_wall_faces);
+int igks_batch_set_freestream(igks_ctx *ctx, int32_t inst, double mach, double alpha_deg, double reynolds,
+                              double nut_ratio);
+int igks_batch_get_residual(igks_ctx *ctx, int32_t inst, igks_residual *out);
+int igks_batch_get_history(igks_ctx *ctx, int32_t inst, double *out, int32_t max, int32_t *n_out);
+int igks_batch_get_state(igks_ctx *ctx, int32_t inst, double *W);
+int igks_batch_set_state(igks_ctx *ctx, int32_t inst, const double *W, const igks_scalars *sc);
+int igks_batch_compute_residual(igks_ctx *ctx, int32_t inst, double *M);
+int igks_batch_get_wall_loads(igks_ctx *ctx, int32_t inst, double *cl, double *cd, double *cf, double *cp,
+                              double *xw);
+/* *halted = 1 if the instance was frozen by a rejected update. */
+int igks_batch_status(igks_ctx *ctx, int32_t inst, int32_t *halted);
+
+/* Autotuner: times `iters` iterations of each candidate launch schedule
+ * (threads per block 64/128/256 for the prep, flux, gather, sweep and
+ * update kernels; one launch per wavefront or one workgroup per sweep),
+ * keeps the fastest per kernel class, and restores the state and scalars
+ * bitwise.  schedule6 (may be NULL) receives the chosen block sizes of the
+ * five classes and the sweep schedule (1 or 2). */
+int igks_autotune(igks_ctx *ctx, int32_t iters, int32_t *schedule6);
+int igks_get_schedule(const igks_ctx *ctx, int32_t *schedule6);
+
 /* Average duration (ms) of each kernel class over the last igks_iterate
  * call, measured with HIP events when opt.chunk == 0 and profiling was
  * enabled by igks_set_profiling(ctx, 1); 0 otherwise.  Order: prep, flux,

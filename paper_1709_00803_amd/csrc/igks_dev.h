@@ -1,5 +1,10 @@
 // igks_dev.h - data shared by the host driver and the HIP kernels of
 // libigks (gfx950).  Internal to the library.
+//
+// A context holds one or more independent instances (mesh + flow
+// condition).  Their cells and faces are concatenated; every kernel handles
+// all instances in one launch and reads the per-instance free stream and
+// scalars through the cell's (or face's) instance index.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,34 +24,45 @@ constexpr int CF_LOWER = 2;   // interior neighbour with a smaller upload index
 
 constexpr int MAXV = 4;       // vertices per cell (triangles padded by repeating a vertex)
 constexpr int HIST_W = 6;     // doubles per history entry
-constexpr int RED_THREADS = 256;
+constexpr int NSLOT = 64;     // atomic min/max targets of one instance are spread over this many slots
+constexpr int RB = 8;         // blocks per instance in the residual-norm reduction
+constexpr int NCLASS = 5;     // kernel classes with a tunable block size: prep, flux, gather, sweep, update
 
-// Per-context scalars living in device memory.  Integer atomics only:
-// non-negative doubles compare like their bit patterns, so min/max of
-// them is exact and order independent.
-constexpr int NSLOT = 64;     // atomic min/max targets are spread over this many slots
+// Free stream of one instance (read-only while iterating).
+struct InstParam {
+    double Winf[5];
+    double lam_inf, mu_inf, p_inf;
+    int sa;
+    int pad;
+};
 
-struct DevScalars {
+// Scalars of one instance, updated on the device.  Integer atomics only:
+// non-negative doubles compare like their bit patterns, so min/max of them
+// is exact and order independent.
+struct InstScalars {
     unsigned long long dtmin_bits[NSLOT];   // Eq.23 minimum over cells (min over slots)
     unsigned long long resinf_bits[NSLOT];  // max |M| (max over slots)
     unsigned long long e40_bits[NSLOT];     // Eq.40 maximum (max over slots)
-    int bad;                         // an update produced a non-physical state
-    int halt;                        // stop the rest of the queued work
-    int ncommit;                     // committed iterations; its parity picks the state buffer
-    int hist_n;                      // history entries of the current chunk
-    double cfl;                      // implicit CFL of the current iteration
-    double res_inf_prev;             // ||M||_inf of the previous iteration
-    double res0;                     // ||M_rho||_2 of iteration 0
-    double res_l2, sa_l2, res_inf, dt_flux, e40;
+    double dt;                              // Eq.23 time step of the current iteration
+    double cfl;                             // implicit CFL of the current iteration
+    double res_inf_prev;                    // ||M||_inf of the previous iteration
+    double res0;                            // ||M_rho||_2 of iteration 0
+    double res_l2, sa_l2, res_inf, e40;
+    int ncommit;                            // committed iterations; its parity picks the state buffer
+    int bad;                                // the last update produced a non-physical state
+    int halt;                               // the instance is frozen (rejected update)
+    int pad;
 };
 
 template <typename T>
 struct Params {
-    int nc, nf;
-    int sa, limiter, visc_sr, mu_law, cfl_mode;
+    int nc, nf, ninst;
+    int limiter, visc_sr, mu_law, cfl_mode;
     double cfl_init, cfl_min, cfl_max, cfl_flux;
-    double Winf[5];
-    double lam_inf, mu_inf, p_inf;
+    const int *cinst, *finst;  // instance of each cell / face
+    const InstParam *ip;
+    InstScalars *is;
+    int *hist_n;               // history entries written in the current chunk
     // cell arrays (SoA, internal order)
     double *Wa, *Wb;           // state ping-pong, 5 x nc
     double *grad;              // limited gradients: d/dx of rho, rhoU, rhoV, rhoE, then d/dy
@@ -56,6 +72,7 @@ struct Params {
     double *M;                 // residual: 4 flow components + SA right-hand side
     double *lsum;              // 1/2 sum lambda S (Eq.20 diagonal)
     double *sadiag;            // SA diagonal without Omega/dt
+    double *r2;                // per-cell squares for the norms: M_rho^2, R_SA^2
     T *dW;                     // LU-SGS increment, 5 x nc
     const double *xc, *yc, *area, *lsinv, *dwall, *vtx;
     const int *cf_ptr, *cf_face, *cf_nbr, *cf_flag;
@@ -67,19 +84,19 @@ struct Params {
     double *lam;               // spectral radius per face
     double *saf;               // SA: (-F_inv + F_vis) S
     double *sag;               // SA: (nu~_r - nu~_l)/|r.n| S
-    double *part;              // 2 x max_blocks reduction partials
-    int max_blocks;
-    double *hist;              // HIST_W x hist_cap
+    // per-instance cell lists (internal ids, ascending) for the norms
+    const int *icell, *ioff;
+    double *ipart;             // ninst x RB x 2 partial sums
+    double *hist;              // HIST_W x ninst x hist_cap
     int hist_cap;
-    DevScalars *sc;
 };
 
 // launchers (igks_kernels.hip)
 struct Launch {
     hipStream_t s;
-    int block;
+    int block[NCLASS];        // prep, flux, gather, sweep, update
 };
-template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int mode);
+template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int mode, int inst);
 template <typename T> void launch_prep(const Launch &L, const Params<T> &P);
 template <typename T> void launch_flux(const Launch &L, const Params<T> &P);
 template <typename T> void launch_gather(const Launch &L, const Params<T> &P);
@@ -88,9 +105,11 @@ template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd);
 template <typename T> void launch_update(const Launch &L, const Params<T> &P);
 template <typename T> void launch_commit(const Launch &L, const Params<T> &P);
-void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, int nw,
-                          const double *wseg, double *dwall);
+void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
+                          const int *woff, const double *wseg, double *dwall);
 void launch_gather_faces(const Launch &L, int n, const int *faces, const double *flux, int nf, double *out);
-void launch_set_state(const Launch &L, int nc, const double *Winf, double *W);
+void launch_fill_instance(const Launch &L, int n, const int *cells, int nc, const double *Winf, double *W);
+void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, const double *src, double *dst,
+                          bool to_instance);
 
 }  // namespace igks

@@ -1,7 +1,8 @@
 // igks_host.cpp - host side of libigks: mesh ingest and preprocessing
 // (Sec. 2.4 mesh data -> faces, geometry, ghost-cell offsets, sweep
-// wavefronts), workspace layout, the iteration driver with HIP-graph
-// chunks, and the C ABI declared in include/igks.h.
+// wavefronts) for one or many instances, the workspace layout, the
+// iteration driver with HIP-graph chunks, the launch-schedule autotuner and
+// the C ABI declared in include/igks.h.
 #include "../../include/igks.h"
 #include "igks_dev.h"
 
@@ -17,24 +18,49 @@ using namespace igks;
 
 namespace {
 
-struct HostMesh {
-    int nn = 0, nc = 0, nf = 0, nwall = 0, nlev = 0;
-    std::vector<int> perm;     // internal cell -> upload index
-    std::vector<int> iperm;    // upload index -> internal cell
-    std::vector<int> lev_off;  // wavefront offsets in internal order
-    // cells (internal order)
+// One instance, in its upload order.
+struct InstMesh {
+    bool ok = false;
+    int nn = 0, nc = 0, nlev = 0;
+    std::vector<double> xy;
+    std::vector<int> cptr, cn;                 // counter-clockwise vertex lists
+    std::vector<double> area, xc, yc;
+    struct UF { int l, r, tag, a, b; };        // faces; owner l = the lower upload index
+    std::vector<UF> uf;
+    std::vector<int> cf_ptr, cf_list;          // cell -> faces (in the order of uf), CSR
+    std::vector<int> level;                    // sweep wavefront of each cell
+    std::vector<int> wall_uf;                  // WALL faces in the input order of the boundary edges
+    bool have_flow = false;
+    double alpha = 0;
+    InstParam ip{};
+};
+
+// All instances concatenated in the internal order.
+struct Global {
+    int N = 0, F = 0, nlev = 0, nwall = 0, max_inst_cells = 0;
+    std::vector<int> lev_off;        // wavefront offsets (internal cells)
+    std::vector<int> coff;           // first global upload id of each instance
+    std::vector<int> g2i;            // global upload id -> internal cell
+    std::vector<int> cinst, finst, icell, ioff;
     std::vector<double> xc, yc, area, lsinv, vtx;
     std::vector<int> cf_ptr, cf_face, cf_nbr, cf_flag;
     std::vector<double> cf_dx, cf_dy;
-    // faces (internal order)
     std::vector<int> fl, fr, ftag;
-    std::vector<double> fnx, fny, flen, frl, frr, fdl, fdr, frn, fxm, fym;
-    std::vector<int> wall_faces;   // internal face ids in input order of the WALL edges
-    std::vector<double> wseg;      // wall segments (ax, ay, bx, by)
+    std::vector<double> fnx, fny, flen, frl, frr, fdl, fdr, frn, fxm;
+    std::vector<int> wall_faces, woff;   // internal face ids per instance (input order); offsets
+    std::vector<double> wseg;            // wall segments (ax, ay, bx, by)
 };
 
 struct Buf {
     size_t off, bytes;
+};
+
+struct WsMap {
+    Buf ip, is, hist_n, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx;
+    Buf cinst, finst, icell, ioff, g2i, cf_ptr, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
+    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, ipart, hist;
+    Buf wall_faces, wall_out, woff, wseg, lev_off, stage, backup;
+    size_t total;
 };
 
 }  // namespace
@@ -44,31 +70,25 @@ struct igks_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    HostMesh m;
-    bool have_mesh = false;
+    std::vector<InstMesh> inst;
+    Global g;
+    bool combined = false;
     // workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;
     bool bound = false;
-    // device views
+    WsMap w{};
     Params<double> P64{};
     Params<float> P32{};
-    int *d_wall_faces = nullptr;
-    int *d_lev_off = nullptr;
-    bool sweep_wg = false;
-    double *d_wall_out = nullptr;
-    double *d_wseg = nullptr;
-    int max_blocks = 0;
     int hist_cap = 0;
-    // flow
-    bool have_flow = false;
-    double mach = 0, alpha = 0, re = 0, nut_ratio = -1;
-    // host copies of the device scalars and history
-    DevScalars hs{};
-    std::vector<double> hist;
-    // graphs
+    // launch schedule
+    int block[NCLASS] = {256, 256, 256, 256, 256};
+    bool sweep_wg = false;
+    // host copies of the device scalars and the history of the last iterate call
+    std::vector<InstScalars> hs;
+    std::vector<std::vector<double>> hist;
+    // graph of one chunk
     hipGraphExec_t gexec = nullptr;
-    int gexec_n = 0;
     // profiling
     bool profiling = false;
     double ktimes[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -88,79 +108,73 @@ int fail(igks_ctx *c, int code, const std::string &msg)
         if (e_ != hipSuccess) return fail(ctx, IGKS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-template <typename T>
-std::vector<T> permute_cells(const std::vector<T> &src, int ncomp, const std::vector<int> &perm)
-{
-    size_t n = perm.size();
-    std::vector<T> out(src.size());
-    for (int k = 0; k < ncomp; k++)
-        for (size_t i = 0; i < n; i++) out[k * n + i] = src[k * n + perm[i]];
-    return out;
-}
-
 void destroy_graph(igks_ctx *c)
 {
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
-        c->gexec_n = 0;
     }
 }
 
 // ------------------------------------------------------------------ ingest
 
-int build_mesh(igks_ctx *ctx, int n_nodes, const double *xy, int n_cells, const int32_t *cell_ptr,
-               const int32_t *cell_nodes, int n_bfaces, const int32_t *bface_nodes, const int32_t *bface_tag,
-               HostMesh &m)
+int build_instance(igks_ctx *ctx, int n_nodes, const double *xy, int n_cells, const int32_t *cell_ptr,
+                   const int32_t *cell_nodes, int n_bfaces, const int32_t *bface_nodes, const int32_t *bface_tag,
+                   InstMesh &m)
 {
-    if (n_nodes <= 0 || n_cells <= 0 || n_bfaces < 0 || !xy || !cell_ptr || !cell_nodes)
+    if (n_nodes <= 0 || n_cells <= 0 || n_bfaces < 0 || !xy || !cell_ptr || !cell_nodes ||
+        (n_bfaces > 0 && (!bface_nodes || !bface_tag)))
         return fail(ctx, IGKS_EINVAL, "empty mesh or null pointer");
     if (cell_ptr[0] != 0) return fail(ctx, IGKS_EMESH, "cell_ptr[0] must be 0");
-    m = HostMesh();
+    m = InstMesh();
     m.nn = n_nodes;
     m.nc = n_cells;
     const int N = n_cells;
-    // cells: counter-clockwise vertex lists, area, centroid (relative to the
-    // first vertex to limit cancellation)
-    std::vector<int> cptr(cell_ptr, cell_ptr + N + 1), cn(cell_ptr[N]);
+    m.xy.assign(xy, xy + 2 * (size_t)n_nodes);
+    m.cptr.assign(cell_ptr, cell_ptr + N + 1);
     for (int i = 0; i < N; i++) {
-        int k = cptr[i + 1] - cptr[i];
-        if (k < 3 || k > MAXV) return fail(ctx, IGKS_EMESH, "cell " + std::to_string(i) + " has " + std::to_string(k) + " nodes (3 or 4 supported)");
+        int k = m.cptr[i + 1] - m.cptr[i];
+        if (k < 3 || k > MAXV)
+            return fail(ctx, IGKS_EMESH, "cell " + std::to_string(i) + " has " + std::to_string(k) +
+                                             " nodes (3 or 4 supported)");
     }
-    for (int p = 0; p < cell_ptr[N]; p++) {
+    m.cn.resize(m.cptr[N]);
+    for (int p = 0; p < m.cptr[N]; p++) {
         int v = cell_nodes[p];
         if (v < 0 || v >= n_nodes) return fail(ctx, IGKS_EMESH, "node index out of range");
-        cn[p] = v;
+        m.cn[p] = v;
     }
-    std::vector<double> area(N), xc(N), yc(N);
+    // counter-clockwise orientation, area and centroid (relative to the
+    // first vertex to limit cancellation)
+    m.area.resize(N); m.xc.resize(N); m.yc.resize(N);
     for (int i = 0; i < N; i++) {
-        int p0 = cptr[i], k = cptr[i + 1] - p0;
-        double x0 = xy[2 * cn[p0]], y0 = xy[2 * cn[p0] + 1];
+        int p0 = m.cptr[i], k = m.cptr[i + 1] - p0;
+        double x0 = xy[2 * m.cn[p0]], y0 = xy[2 * m.cn[p0] + 1];
         double a2 = 0, sx = 0, sy = 0;
         for (int j = 1; j + 1 < k; j++) {
-            double ax = xy[2 * cn[p0 + j]] - x0, ay = xy[2 * cn[p0 + j] + 1] - y0;
-            double bx = xy[2 * cn[p0 + j + 1]] - x0, by = xy[2 * cn[p0 + j + 1] + 1] - y0;
+            double ax = xy[2 * m.cn[p0 + j]] - x0, ay = xy[2 * m.cn[p0 + j] + 1] - y0;
+            double bx = xy[2 * m.cn[p0 + j + 1]] - x0, by = xy[2 * m.cn[p0 + j + 1] + 1] - y0;
             double t = ax * by - ay * bx;
             a2 += t;
             sx += t * (ax + bx);
             sy += t * (ay + by);
         }
         if (a2 < 0) {
-            std::reverse(cn.begin() + p0, cn.begin() + p0 + k);
+            std::reverse(m.cn.begin() + p0, m.cn.begin() + p0 + k);
             a2 = -a2; sx = -sx; sy = -sy;
         }
         if (!(a2 > 0)) return fail(ctx, IGKS_EMESH, "degenerate cell " + std::to_string(i));
-        area[i] = 0.5 * a2;
-        xc[i] = x0 + sx / (3.0 * a2);
-        yc[i] = y0 + sy / (3.0 * a2);
+        m.area[i] = 0.5 * a2;
+        m.xc[i] = x0 + sx / (3.0 * a2);
+        m.yc[i] = y0 + sy / (3.0 * a2);
     }
-    // edges -> faces; owner = the lower upload index
+    // edges -> faces
     struct E { long long key; int cell, loc; };
-    std::vector<E> ev(cell_ptr[N]);
+    std::vector<E> ev(m.cptr[N]);
     for (int i = 0; i < N; i++) {
-        int p0 = cptr[i], k = cptr[i + 1] - p0;
+        int p0 = m.cptr[i], k = m.cptr[i + 1] - p0;
         for (int j = 0; j < k; j++) {
-            long long a = cn[p0 + j], b = cn[p0 + (j + 1) % k];
+            long long a = m.cn[p0 + j], b = m.cn[p0 + (j + 1) % k];
             ev[p0 + j] = {std::min(a, b) * (long long)(n_nodes + 1) + std::max(a, b), i, j};
         }
     }
@@ -177,160 +191,219 @@ int build_mesh(igks_ctx *ctx, int n_nodes, const double *xy, int n_cells, const 
         if (!bmap.emplace(std::min(a, d) * (long long)(n_nodes + 1) + std::max(a, d), b).second)
             return fail(ctx, IGKS_EMESH, "duplicate boundary edge");
     }
-    struct UF { int l, r, tag, bidx, a, b; };   // upload-order faces
-    std::vector<UF> uf;
-    uf.reserve(ev.size());
     std::vector<char> bused(n_bfaces, 0);
+    std::vector<int> wslot(n_bfaces, -1);
     for (size_t i = 0; i < ev.size();) {
         size_t j = i + 1;
         while (j < ev.size() && ev[j].key == ev[i].key) j++;
         if (j - i > 2) return fail(ctx, IGKS_EMESH, "edge shared by more than two cells");
         int ow = ev[i].cell, lo = ev[i].loc;
-        int p0 = cptr[ow], k = cptr[ow + 1] - p0;
-        UF f{ow, -1, 0, -1, cn[p0 + lo], cn[p0 + (lo + 1) % k]};
+        int p0 = m.cptr[ow], k = m.cptr[ow + 1] - p0;
+        InstMesh::UF f{ow, -1, 0, m.cn[p0 + lo], m.cn[p0 + (lo + 1) % k]};
         if (j - i == 2) {
             f.r = ev[i + 1].cell;
         } else {
             auto it = bmap.find(ev[i].key);
             if (it == bmap.end()) return fail(ctx, IGKS_EMESH, "boundary edge without a tag");
-            f.bidx = it->second;
             f.tag = bface_tag[it->second];
             bused[it->second] = 1;
+            if (f.tag == BC_WALL) wslot[it->second] = (int)m.uf.size();
         }
-        uf.push_back(f);
+        m.uf.push_back(f);
         i = j;
     }
     for (int b = 0; b < n_bfaces; b++)
         if (!bused[b]) return fail(ctx, IGKS_EMESH, "tagged edge " + std::to_string(b) + " is not on the mesh boundary");
-    // cell -> faces in upload order
-    std::vector<std::vector<int>> cfaces(N);
-    for (size_t q = 0; q < uf.size(); q++) {
-        cfaces[uf[q].l].push_back((int)q);
-        if (uf[q].r >= 0) cfaces[uf[q].r].push_back((int)q);
+    for (int b = 0; b < n_bfaces; b++)
+        if (wslot[b] >= 0) m.wall_uf.push_back(wslot[b]);
+    // cell -> faces
+    m.cf_ptr.assign(N + 1, 0);
+    for (auto &f : m.uf) {
+        m.cf_ptr[f.l + 1]++;
+        if (f.r >= 0) m.cf_ptr[f.r + 1]++;
     }
-    // sweep wavefronts: level(i) = 1 + max level of neighbours with a smaller index
-    std::vector<int> level(N, 0);
-    int nlev = 0;
+    for (int i = 0; i < N; i++) m.cf_ptr[i + 1] += m.cf_ptr[i];
+    m.cf_list.resize(m.cf_ptr[N]);
+    {
+        std::vector<int> fill(N, 0);
+        for (int q = 0; q < (int)m.uf.size(); q++) {
+            m.cf_list[m.cf_ptr[m.uf[q].l] + fill[m.uf[q].l]++] = q;
+            if (m.uf[q].r >= 0) m.cf_list[m.cf_ptr[m.uf[q].r] + fill[m.uf[q].r]++] = q;
+        }
+    }
+    // sweep wavefronts: level(i) = 1 + max level of the neighbours with a smaller index
+    m.level.assign(N, 0);
+    m.nlev = 0;
     for (int i = 0; i < N; i++) {
         int lv = 0;
-        for (int q : cfaces[i]) {
-            int o = uf[q].l == i ? uf[q].r : uf[q].l;
-            if (o >= 0 && o < i) lv = std::max(lv, level[o] + 1);
+        for (int e = m.cf_ptr[i]; e < m.cf_ptr[i + 1]; e++) {
+            const auto &f = m.uf[m.cf_list[e]];
+            int o = f.l == i ? f.r : f.l;
+            if (o >= 0 && o < i) lv = std::max(lv, m.level[o] + 1);
         }
-        level[i] = lv;
-        nlev = std::max(nlev, lv + 1);
+        m.level[i] = lv;
+        m.nlev = std::max(m.nlev, lv + 1);
     }
-    m.nlev = nlev;
-    m.perm.resize(N);
-    std::iota(m.perm.begin(), m.perm.end(), 0);
-    std::stable_sort(m.perm.begin(), m.perm.end(), [&](int a, int b) { return level[a] < level[b]; });
-    m.iperm.resize(N);
-    for (int i = 0; i < N; i++) m.iperm[m.perm[i]] = i;
-    m.lev_off.assign(nlev + 1, 0);
-    for (int i = 0; i < N; i++) m.lev_off[level[i] + 1]++;
-    for (int l = 0; l < nlev; l++) m.lev_off[l + 1] += m.lev_off[l];
-    // faces in internal order: interior faces by owner, then boundary faces by owner
-    std::vector<int> forder(uf.size());
-    std::iota(forder.begin(), forder.end(), 0);
-    std::stable_sort(forder.begin(), forder.end(), [&](int a, int b) {
-        bool ba = uf[a].r < 0, bb = uf[b].r < 0;
-        if (ba != bb) return bb;   // interior first
-        return m.iperm[uf[a].l] < m.iperm[uf[b].l];
+    m.ok = true;
+    return IGKS_OK;
+}
+
+// Concatenate the instances in the internal order: cells by (wavefront,
+// instance, upload index); interior faces by internal owner, then boundary
+// faces by internal owner.
+int combine(igks_ctx *ctx)
+{
+    Global &G = ctx->g;
+    G = Global();
+    const int ni = (int)ctx->inst.size();
+    G.coff.assign(ni + 1, 0);
+    for (int i = 0; i < ni; i++) {
+        G.coff[i + 1] = G.coff[i] + ctx->inst[i].nc;
+        G.nlev = std::max(G.nlev, ctx->inst[i].nlev);
+        G.max_inst_cells = std::max(G.max_inst_cells, ctx->inst[i].nc);
+    }
+    const int N = G.coff[ni];
+    G.N = N;
+    std::vector<int> gi(N), gu(N), glev(N);
+    for (int i = 0; i < ni; i++)
+        for (int u = 0; u < ctx->inst[i].nc; u++) {
+            int gid = G.coff[i] + u;
+            gi[gid] = i; gu[gid] = u; glev[gid] = ctx->inst[i].level[u];
+        }
+    std::vector<int> order(N);   // internal cell -> global upload id
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return glev[a] < glev[b]; });
+    G.g2i.resize(N);
+    for (int c = 0; c < N; c++) G.g2i[order[c]] = c;
+    G.lev_off.assign(G.nlev + 1, 0);
+    for (int c = 0; c < N; c++) G.lev_off[glev[order[c]] + 1]++;
+    for (int l = 0; l < G.nlev; l++) G.lev_off[l + 1] += G.lev_off[l];
+    G.cinst.resize(N);
+    for (int c = 0; c < N; c++) G.cinst[c] = gi[order[c]];
+    G.ioff.assign(ni + 1, 0);
+    for (int c = 0; c < N; c++) G.ioff[G.cinst[c] + 1]++;
+    for (int i = 0; i < ni; i++) G.ioff[i + 1] += G.ioff[i];
+    G.icell.resize(N);
+    {
+        std::vector<int> fill(ni, 0);
+        for (int c = 0; c < N; c++) G.icell[G.ioff[G.cinst[c]] + fill[G.cinst[c]]++] = c;
+    }
+    // faces
+    struct FRef { int inst, q; };
+    std::vector<FRef> all;
+    for (int i = 0; i < ni; i++)
+        for (int q = 0; q < (int)ctx->inst[i].uf.size(); q++) all.push_back({i, q});
+    auto boundary = [&](const FRef &r) { return ctx->inst[r.inst].uf[r.q].r < 0; };
+    auto owner = [&](const FRef &r) { return G.g2i[G.coff[r.inst] + ctx->inst[r.inst].uf[r.q].l]; };
+    std::stable_sort(all.begin(), all.end(), [&](const FRef &a, const FRef &b) {
+        bool ba = boundary(a), bb = boundary(b);
+        if (ba != bb) return bb;
+        return owner(a) < owner(b);
     });
-    const int F = (int)uf.size();
-    m.nf = F;
-    std::vector<int> fpos(F);
-    for (int q = 0; q < F; q++) fpos[forder[q]] = q;
-    m.fl.resize(F); m.fr.resize(F); m.ftag.resize(F);
-    m.fnx.resize(F); m.fny.resize(F); m.flen.resize(F); m.frl.resize(2 * F); m.frr.resize(2 * F);
-    m.fdl.resize(F); m.fdr.resize(F); m.frn.resize(F); m.fxm.resize(F); m.fym.resize(F);
+    const int F = (int)all.size();
+    G.F = F;
+    std::vector<std::vector<int>> fpos(ni);
+    for (int i = 0; i < ni; i++) fpos[i].assign(ctx->inst[i].uf.size(), -1);
+    for (int q = 0; q < F; q++) fpos[all[q].inst][all[q].q] = q;
+    G.fl.resize(F); G.fr.resize(F); G.ftag.resize(F); G.finst.resize(F);
+    G.fnx.resize(F); G.fny.resize(F); G.flen.resize(F); G.frl.resize(2 * (size_t)F); G.frr.resize(2 * (size_t)F);
+    G.fdl.resize(F); G.fdr.resize(F); G.frn.resize(F); G.fxm.resize(F);
     for (int q = 0; q < F; q++) {
-        const UF &u = uf[forder[q]];
+        const InstMesh &m = ctx->inst[all[q].inst];
+        const auto &u = m.uf[all[q].q];
+        const double *xy = m.xy.data();
         double ax = xy[2 * u.a], ay = xy[2 * u.a + 1], bx = xy[2 * u.b], by = xy[2 * u.b + 1];
         double dx = bx - ax, dy = by - ay, L = std::sqrt(dx * dx + dy * dy);
-        double nx = dy / L, ny = -dx / L;   // outward normal of the owner's CCW edge
+        double nx = dy / L, ny = -dx / L;   // outward normal of the owner's counter-clockwise edge
         double xm = 0.5 * (ax + bx), ym = 0.5 * (ay + by);
-        m.fl[q] = m.iperm[u.l];
-        m.fr[q] = u.r >= 0 ? m.iperm[u.r] : -1;
-        m.ftag[q] = u.tag;
-        m.fnx[q] = nx; m.fny[q] = ny; m.flen[q] = L; m.fxm[q] = xm; m.fym[q] = ym;
-        double rlx = xm - xc[u.l], rly = ym - yc[u.l];
-        m.frl[2 * q] = rlx; m.frl[2 * q + 1] = rly;
+        int off = G.coff[all[q].inst];
+        G.finst[q] = all[q].inst;
+        G.fl[q] = G.g2i[off + u.l];
+        G.fr[q] = u.r >= 0 ? G.g2i[off + u.r] : -1;
+        G.ftag[q] = u.tag;
+        G.fnx[q] = nx; G.fny[q] = ny; G.flen[q] = L; G.fxm[q] = xm;
+        double rlx = xm - m.xc[u.l], rly = ym - m.yc[u.l];
+        G.frl[2 * (size_t)q] = rlx; G.frl[2 * (size_t)q + 1] = rly;
         double dl = rlx * nx + rly * ny;
-        m.fdl[q] = dl;
+        G.fdl[q] = dl;
         if (u.r >= 0) {
-            double rrx = xm - xc[u.r], rry = ym - yc[u.r];
-            m.frr[2 * q] = rrx; m.frr[2 * q + 1] = rry;
-            m.fdr[q] = -(rrx * nx + rry * ny);
-            m.frn[q] = std::fabs((xc[u.r] - xc[u.l]) * nx + (yc[u.r] - yc[u.l]) * ny);
+            double rrx = xm - m.xc[u.r], rry = ym - m.yc[u.r];
+            G.frr[2 * (size_t)q] = rrx; G.frr[2 * (size_t)q + 1] = rry;
+            G.fdr[q] = -(rrx * nx + rry * ny);
+            G.frn[q] = std::fabs((m.xc[u.r] - m.xc[u.l]) * nx + (m.yc[u.r] - m.yc[u.l]) * ny);
         } else {
-            m.frr[2 * q] = m.frr[2 * q + 1] = 0.0;
-            m.fdr[q] = dl;
-            m.frn[q] = 2.0 * dl;
+            G.frr[2 * (size_t)q] = G.frr[2 * (size_t)q + 1] = 0.0;
+            G.fdr[q] = dl;
+            G.frn[q] = 2.0 * dl;
         }
     }
-    // wall faces in input order
-    {
-        std::vector<int> slot(n_bfaces, -1);
-        for (int q = 0; q < F; q++) {
-            const UF &u = uf[forder[q]];
-            if (u.tag == BC_WALL) slot[u.bidx] = q;
+    // wall faces and segments, per instance
+    G.woff.assign(ni + 1, 0);
+    for (int i = 0; i < ni; i++) {
+        const InstMesh &m = ctx->inst[i];
+        for (int q : m.wall_uf) {
+            const auto &u = m.uf[q];
+            G.wall_faces.push_back(fpos[i][q]);
+            G.wseg.push_back(m.xy[2 * u.a]); G.wseg.push_back(m.xy[2 * u.a + 1]);
+            G.wseg.push_back(m.xy[2 * u.b]); G.wseg.push_back(m.xy[2 * u.b + 1]);
         }
-        for (int b = 0; b < n_bfaces; b++)
-            if (slot[b] >= 0) {
-                int q = slot[b];
-                const UF &u = uf[forder[q]];
-                m.wall_faces.push_back(q);
-                m.wseg.push_back(xy[2 * u.a]); m.wseg.push_back(xy[2 * u.a + 1]);
-                m.wseg.push_back(xy[2 * u.b]); m.wseg.push_back(xy[2 * u.b + 1]);
-            }
-        m.nwall = (int)m.wall_faces.size();
+        G.woff[i + 1] = (int)G.wall_faces.size();
     }
+    G.nwall = (int)G.wall_faces.size();
     // cells in internal order
-    m.xc.resize(N); m.yc.resize(N); m.area.resize(N); m.lsinv.resize(3 * N); m.vtx.resize(2 * MAXV * N);
-    m.cf_ptr.assign(N + 1, 0);
-    for (int c = 0; c < N; c++) m.cf_ptr[c + 1] = m.cf_ptr[c] + (int)cfaces[m.perm[c]].size();
-    int ne = m.cf_ptr[N];
-    m.cf_face.resize(ne); m.cf_nbr.resize(ne); m.cf_flag.resize(ne); m.cf_dx.resize(ne); m.cf_dy.resize(ne);
+    G.xc.resize(N); G.yc.resize(N); G.area.resize(N); G.lsinv.resize(3 * (size_t)N);
+    G.vtx.resize(2 * MAXV * (size_t)N);
+    G.cf_ptr.assign(N + 1, 0);
     for (int c = 0; c < N; c++) {
-        int u = m.perm[c];
-        m.xc[c] = xc[u]; m.yc[c] = yc[u]; m.area[c] = area[u];
+        const InstMesh &m = ctx->inst[gi[order[c]]];
+        int u = gu[order[c]];
+        G.cf_ptr[c + 1] = G.cf_ptr[c] + (m.cf_ptr[u + 1] - m.cf_ptr[u]);
+    }
+    const int ne = G.cf_ptr[N];
+    G.cf_face.resize(ne); G.cf_nbr.resize(ne); G.cf_flag.resize(ne); G.cf_dx.resize(ne); G.cf_dy.resize(ne);
+    for (int c = 0; c < N; c++) {
+        const int i = gi[order[c]], u = gu[order[c]], off = G.coff[i];
+        const InstMesh &m = ctx->inst[i];
+        G.xc[c] = m.xc[u]; G.yc[c] = m.yc[u]; G.area[c] = m.area[u];
         double a11 = 0, a12 = 0, a22 = 0;
-        int e = m.cf_ptr[c];
-        for (int q : cfaces[u]) {
-            const UF &f = uf[q];
-            int qi = fpos[q];
-            bool owner = f.l == u;
-            int other = owner ? f.r : f.l;
+        int e = G.cf_ptr[c];
+        for (int k = m.cf_ptr[u]; k < m.cf_ptr[u + 1]; k++) {
+            const int q = m.cf_list[k];
+            const auto &f = m.uf[q];
+            const int qi = fpos[i][q];
+            const bool own = f.l == u;
+            const int other = own ? f.r : f.l;
             double dx, dy;
             if (other >= 0) {
-                dx = xc[other] - xc[u];
-                dy = yc[other] - yc[u];
+                dx = m.xc[other] - m.xc[u];
+                dy = m.yc[other] - m.yc[u];
             } else {   // ghost centroid: the cell centroid reflected in the face line
-                double dn = m.fdl[qi];
-                dx = 2.0 * dn * m.fnx[qi];
-                dy = 2.0 * dn * m.fny[qi];
+                dx = 2.0 * G.fdl[qi] * G.fnx[qi];
+                dy = 2.0 * G.fdl[qi] * G.fny[qi];
             }
-            m.cf_face[e] = qi;
-            m.cf_nbr[e] = other >= 0 ? m.iperm[other] : -1;
-            m.cf_flag[e] = (owner ? CF_OWNER : 0) | ((other >= 0 && other < u) ? CF_LOWER : 0);
-            m.cf_dx[e] = dx;
-            m.cf_dy[e] = dy;
+            G.cf_face[e] = qi;
+            G.cf_nbr[e] = other >= 0 ? G.g2i[off + other] : -1;
+            G.cf_flag[e] = (own ? CF_OWNER : 0) | ((other >= 0 && other < u) ? CF_LOWER : 0);
+            G.cf_dx[e] = dx;
+            G.cf_dy[e] = dy;
             a11 += dx * dx; a12 += dx * dy; a22 += dy * dy;
             e++;
         }
         double det = a11 * a22 - a12 * a12;
-        if (!(det > 0)) return fail(ctx, IGKS_EMESH, "singular least-squares stencil at cell " + std::to_string(u));
-        m.lsinv[c] = a22 / det;
-        m.lsinv[N + c] = -a12 / det;
-        m.lsinv[2 * N + c] = a11 / det;
-        int p0 = cptr[u], k = cptr[u + 1] - p0;
+        if (!(det > 0))
+            return fail(ctx, IGKS_EMESH, "instance " + std::to_string(i) + ": singular least-squares stencil at cell " +
+                                             std::to_string(u));
+        G.lsinv[c] = a22 / det;
+        G.lsinv[(size_t)N + c] = -a12 / det;
+        G.lsinv[2 * (size_t)N + c] = a11 / det;
+        int p0 = m.cptr[u], k = m.cptr[u + 1] - p0;
         for (int v = 0; v < MAXV; v++) {
-            int node = cn[p0 + (v < k ? v : 0)];
-            m.vtx[(2 * v) * N + c] = xy[2 * node] - xc[u];
-            m.vtx[(2 * v + 1) * N + c] = xy[2 * node + 1] - yc[u];
+            int node = m.cn[p0 + (v < k ? v : 0)];
+            G.vtx[(2 * v) * (size_t)N + c] = m.xy[2 * node] - m.xc[u];
+            G.vtx[(2 * v + 1) * (size_t)N + c] = m.xy[2 * node + 1] - m.yc[u];
         }
     }
+    ctx->combined = true;
     return IGKS_OK;
 }
 
@@ -346,39 +419,38 @@ struct Layout {
     }
 };
 
-struct WsMap {
-    Buf sc, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, dW, xc, yc, area, lsinv, dwall, vtx;
-    Buf cf_ptr, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
-    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, part, hist;
-    Buf wall_faces, wall_out, wseg, lev_off;
-    size_t total;
-};
-
-WsMap layout(const HostMesh &m, const igks_options &o, int max_blocks, int hist_cap)
+WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
 {
     Layout L;
     WsMap w;
-    const size_t N = m.nc, F = m.nf, E = m.cf_ptr.empty() ? 0 : (size_t)m.cf_ptr.back(), D = sizeof(double),
-                 I = sizeof(int);
-    w.sc = L.add(sizeof(DevScalars));
+    const size_t N = G.N, F = G.F, E = G.cf_ptr.empty() ? 0 : (size_t)G.cf_ptr.back(), D = sizeof(double),
+                 I = sizeof(int), NI = ninst, NW = std::max(1, G.nwall);
+    w.ip = L.add(NI * sizeof(InstParam));
+    w.is = L.add(NI * sizeof(InstScalars));
+    w.hist_n = L.add(I);
     w.Wa = L.add(5 * N * D); w.Wb = L.add(5 * N * D);
     w.grad = L.add(8 * N * D); w.lamc = L.add(N * D); w.vort = L.add(N * D); w.nu = L.add(N * D);
-    w.M = L.add(5 * N * D); w.lsum = L.add(N * D); w.sadiag = L.add(N * D);
+    w.M = L.add(5 * N * D); w.lsum = L.add(N * D); w.sadiag = L.add(N * D); w.r2 = L.add(2 * N * D);
     w.dW = L.add(5 * N * (o.precision == IGKS_MIXED ? sizeof(float) : D));
     w.xc = L.add(N * D); w.yc = L.add(N * D); w.area = L.add(N * D); w.lsinv = L.add(3 * N * D);
     w.dwall = L.add(N * D); w.vtx = L.add(2 * MAXV * N * D);
+    w.cinst = L.add(N * I); w.finst = L.add(F * I); w.icell = L.add(N * I); w.ioff = L.add((NI + 1) * I);
+    w.g2i = L.add(N * I);
     w.cf_ptr = L.add((N + 1) * I); w.cf_face = L.add(E * I); w.cf_nbr = L.add(E * I); w.cf_flag = L.add(E * I);
     w.cf_dx = L.add(E * D); w.cf_dy = L.add(E * D);
     w.fl = L.add(F * I); w.fr = L.add(F * I); w.fbc = L.add(F * I);
     w.fnx = L.add(F * D); w.fny = L.add(F * D); w.flen = L.add(F * D); w.frl = L.add(2 * F * D);
     w.frr = L.add(2 * F * D); w.fdl = L.add(F * D); w.fdr = L.add(F * D); w.frn = L.add(F * D);
     w.flux = L.add(4 * F * D); w.lam = L.add(F * D); w.saf = L.add(F * D); w.sag = L.add(F * D);
-    w.part = L.add(2 * (size_t)max_blocks * D);
-    w.hist = L.add((size_t)HIST_W * hist_cap * D);
-    w.wall_faces = L.add((size_t)std::max(1, m.nwall) * I);
-    w.wall_out = L.add((size_t)4 * std::max(1, m.nwall) * D);
-    w.wseg = L.add((size_t)4 * std::max(1, m.nwall) * D);
-    w.lev_off = L.add((size_t)(m.nlev + 1) * I);
+    w.ipart = L.add(2 * NI * RB * D);
+    w.hist = L.add((size_t)HIST_W * NI * hist_cap * D);
+    w.wall_faces = L.add(NW * I);
+    w.wall_out = L.add(4 * NW * D);
+    w.woff = L.add((NI + 1) * I);
+    w.wseg = L.add(4 * NW * D);
+    w.lev_off = L.add((size_t)(G.nlev + 1) * I);
+    w.stage = L.add(5 * (size_t)std::max(1, G.max_inst_cells) * D);
+    w.backup = L.add(10 * N * D + NI * sizeof(InstScalars));
     w.total = L.total;
     return w;
 }
@@ -386,17 +458,22 @@ WsMap layout(const HostMesh &m, const igks_options &o, int max_blocks, int hist_
 int hist_cap_of(const igks_options &o) { return std::max(1, o.chunk > 0 ? o.chunk : 64); }
 
 template <typename T>
-void fill_params(igks_ctx *c, Params<T> &P, const WsMap &w)
+void fill_params(igks_ctx *c, Params<T> &P)
 {
+    const WsMap &w = c->w;
     char *b = c->ws;
     auto D = [&](const Buf &x) { return (double *)(b + x.off); };
     auto In = [&](const Buf &x) { return (int *)(b + x.off); };
     P = Params<T>{};
-    P.nc = c->m.nc; P.nf = c->m.nf;
+    P.nc = c->g.N; P.nf = c->g.F; P.ninst = (int)c->inst.size();
     P.limiter = c->opt.limiter; P.visc_sr = c->opt.visc_sr; P.mu_law = c->opt.mu_law; P.cfl_mode = c->opt.cfl_mode;
     P.cfl_init = c->opt.cfl_init; P.cfl_min = c->opt.cfl_min; P.cfl_max = c->opt.cfl_max; P.cfl_flux = c->opt.cfl_flux;
+    P.cinst = In(w.cinst); P.finst = In(w.finst);
+    P.ip = (const InstParam *)(b + w.ip.off);
+    P.is = (InstScalars *)(b + w.is.off);
+    P.hist_n = In(w.hist_n);
     P.Wa = D(w.Wa); P.Wb = D(w.Wb); P.grad = D(w.grad); P.lamc = D(w.lamc); P.vort = D(w.vort); P.nu = D(w.nu);
-    P.M = D(w.M); P.lsum = D(w.lsum); P.sadiag = D(w.sadiag); P.dW = (T *)(b + w.dW.off);
+    P.M = D(w.M); P.lsum = D(w.lsum); P.sadiag = D(w.sadiag); P.r2 = D(w.r2); P.dW = (T *)(b + w.dW.off);
     P.xc = D(w.xc); P.yc = D(w.yc); P.area = D(w.area); P.lsinv = D(w.lsinv); P.dwall = D(w.dwall); P.vtx = D(w.vtx);
     P.cf_ptr = In(w.cf_ptr); P.cf_face = In(w.cf_face); P.cf_nbr = In(w.cf_nbr); P.cf_flag = In(w.cf_flag);
     P.cf_dx = D(w.cf_dx); P.cf_dy = D(w.cf_dy);
@@ -404,33 +481,25 @@ void fill_params(igks_ctx *c, Params<T> &P, const WsMap &w)
     P.fnx = D(w.fnx); P.fny = D(w.fny); P.flen = D(w.flen); P.frl = D(w.frl); P.frr = D(w.frr);
     P.fdl = D(w.fdl); P.fdr = D(w.fdr); P.frn = D(w.frn);
     P.flux = D(w.flux); P.lam = D(w.lam); P.saf = D(w.saf); P.sag = D(w.sag);
-    P.part = D(w.part); P.max_blocks = c->max_blocks;
+    P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipart = D(w.ipart);
     P.hist = D(w.hist); P.hist_cap = c->hist_cap;
-    P.sc = (DevScalars *)(b + w.sc.off);
 }
 
-template <typename T>
-void set_flow_params(igks_ctx *c, Params<T> &P)
+Launch launch_of(igks_ctx *c)
 {
-    const double g = GAMMA;
-    double pinf = 1.0 / (g * c->mach * c->mach);
-    P.p_inf = pinf;
-    P.lam_inf = 1.0 / (2.0 * pinf);
-    P.mu_inf = 1.0 / c->re;
-    P.sa = c->nut_ratio >= 0.0;
-    double a = c->alpha * M_PI / 180.0;
-    P.Winf[0] = 1.0; P.Winf[1] = std::cos(a); P.Winf[2] = std::sin(a);
-    P.Winf[3] = pinf / (g - 1.0) + 0.5;
-    P.Winf[4] = P.sa ? c->nut_ratio * P.mu_inf : 0.0;
+    Launch L;
+    L.s = c->stream;
+    for (int k = 0; k < NCLASS; k++) L.block[k] = c->block[k];
+    return L;
 }
 
-Launch launch_of(igks_ctx *c) { return Launch{c->stream, c->opt.block > 0 ? c->opt.block : 256}; }
-
-// queue one nonlinear iteration
+// queue one nonlinear iteration of every instance
 template <typename T>
 void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev)
 {
     Launch L = launch_of(c);
+    const int *lev = (const int *)(c->ws + c->w.lev_off.off);
+    const Global &G = c->g;
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], c->stream); };
     mark(0);
     launch_prep(L, P);
@@ -441,13 +510,13 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev)
     mark(3);
     launch_reduce(L, P);
     mark(4);
-    if (c->sweep_wg) launch_sweep_wg(L, P, c->d_lev_off, c->m.nlev, true);
+    if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, true);
     else
-        for (int l = 0; l < c->m.nlev; l++) launch_sweep(L, P, c->m.lev_off[l], c->m.lev_off[l + 1], true);
+        for (int l = 0; l < G.nlev; l++) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], true);
     mark(5);
-    if (c->sweep_wg) launch_sweep_wg(L, P, c->d_lev_off, c->m.nlev, false);
+    if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, false);
     else
-        for (int l = c->m.nlev - 1; l >= 0; l--) launch_sweep(L, P, c->m.lev_off[l], c->m.lev_off[l + 1], false);
+        for (int l = G.nlev - 1; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], false);
     mark(6);
     launch_update(L, P);
     mark(7);
@@ -465,16 +534,19 @@ void queue_residual(igks_ctx *c, const Params<T> &P)
 
 int sync_scalars(igks_ctx *c)
 {
-    HIPCHK(c, hipMemcpyAsync(&c->hs, c->P64.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
+    const size_t ni = c->inst.size();
+    c->hs.resize(ni);
+    HIPCHK(c, hipMemcpyAsync(c->hs.data(), c->P64.is, sizeof(InstScalars) * ni, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return IGKS_OK;
 }
 
+// k iterations of every instance, then the scalars and the history entries
 template <typename T>
 int run_chunk(igks_ctx *c, const Params<T> &P, int k)
 {
     Launch L = launch_of(c);
-    launch_reset(L, P, 4);
+    launch_reset(L, P, 4, -1);
     if (c->profiling) {
         hipEvent_t ev[8];
         for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
@@ -496,35 +568,156 @@ int run_chunk(igks_ctx *c, const Params<T> &P, int k)
             HIPCHK(c, hipStreamEndCapture(c->stream, &g));
             hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
-            if (e != hipSuccess) return fail(c, IGKS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-            c->gexec_n = k;
+            if (e != hipSuccess) {
+                c->gexec = nullptr;
+                return fail(c, IGKS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
         }
         HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
     } else {
         for (int i = 0; i < k; i++) queue_iteration(c, P, nullptr);
     }
     HIPCHK(c, hipGetLastError());
+    const size_t ni = c->inst.size();
+    std::vector<int> n0(ni), h0(ni);
+    for (size_t i = 0; i < ni; i++) { n0[i] = c->hs[i].ncommit; h0[i] = c->hs[i].halt; }
+    int nh = 0;
+    HIPCHK(c, hipMemcpyAsync(&nh, P.hist_n, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     int rc = sync_scalars(c);
     if (rc) return rc;
-    int nh = std::min(c->hs.hist_n, c->hist_cap);
+    nh = std::min(nh, c->hist_cap);
     if (nh > 0) {
-        size_t old = c->hist.size();
-        c->hist.resize(old + (size_t)HIST_W * nh);
-        HIPCHK(c, hipMemcpy(c->hist.data() + old, P.hist, sizeof(double) * HIST_W * nh, hipMemcpyDeviceToHost));
+        std::vector<double> h((size_t)HIST_W * ni * nh);
+        HIPCHK(c, hipMemcpyAsync(h.data(), P.hist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->hist.resize(ni);
+        for (size_t i = 0; i < ni; i++) {
+            // entries of the iterations this instance ran: the committed ones
+            // and the rejected one that froze it
+            int ran = c->hs[i].ncommit - n0[i] + ((c->hs[i].halt && !h0[i]) ? 1 : 0);
+            for (int e = 0; e < std::min(nh, ran); e++) {
+                const double *src = &h[(size_t)HIST_W * ((size_t)e * ni + i)];
+                c->hist[i].insert(c->hist[i].end(), src, src + HIST_W);
+            }
+        }
     }
+    return IGKS_OK;
+}
+
+int check_inst(const igks_ctx *c, int inst)
+{
+    if (!c) return IGKS_EINVAL;
+    if (inst < 0 || inst >= (int)c->inst.size())
+        return fail(const_cast<igks_ctx *>(c), IGKS_EINVAL, "instance index out of range");
     return IGKS_OK;
 }
 
 int check_ready(igks_ctx *c, bool need_flow)
 {
     if (!c) return IGKS_EINVAL;
-    if (!c->have_mesh) return fail(c, IGKS_EINVAL, "no mesh uploaded");
+    for (size_t i = 0; i < c->inst.size(); i++)
+        if (!c->inst[i].ok) return fail(c, IGKS_EINVAL, "no mesh uploaded for instance " + std::to_string(i));
     if (!c->bound) return fail(c, IGKS_EINVAL, "no workspace bound");
-    if (need_flow && !c->have_flow) return fail(c, IGKS_EINVAL, "set_freestream first");
+    if (need_flow)
+        for (size_t i = 0; i < c->inst.size(); i++)
+            if (!c->inst[i].have_flow)
+                return fail(c, IGKS_EINVAL, "set the free stream of instance " + std::to_string(i) + " first");
     return IGKS_OK;
 }
 
-double *cur_buffer(igks_ctx *c) { return (c->hs.ncommit & 1) ? c->P64.Wb : c->P64.Wa; }
+int ensure_combined(igks_ctx *c)
+{
+    for (size_t i = 0; i < c->inst.size(); i++)
+        if (!c->inst[i].ok) return fail(c, IGKS_EINVAL, "no mesh uploaded for instance " + std::to_string(i));
+    if (!c->combined) {
+        int rc = combine(c);
+        if (rc) return rc;
+        c->hist_cap = hist_cap_of(c->opt);
+    }
+    return IGKS_OK;
+}
+
+// internal ids of instance i's cells in its upload order (device)
+const int *inst_cells(igks_ctx *c, int i) { return (const int *)(c->ws + c->w.g2i.off) + c->g.coff[i]; }
+
+double *cur_buffer(igks_ctx *c, int i) { return (c->hs[i].ncommit & 1) ? c->P64.Wb : c->P64.Wa; }
+
+double *stage_buffer(igks_ctx *c) { return (double *)(c->ws + c->w.stage.off); }
+
+// FARFIELD faces: free stream where V_inf . n < 0, else Riemann outflow
+int upload_bc(igks_ctx *c)
+{
+    std::vector<int> fbc(c->g.ftag);
+    for (int q = 0; q < c->g.F; q++)
+        if (fbc[q] == BC_FARFIELD) {
+            const InstParam &ip = c->inst[c->g.finst[q]].ip;
+            fbc[q] = (ip.Winf[1] * c->g.fnx[q] + ip.Winf[2] * c->g.fny[q] < 0.0) ? BC_FREESTREAM : BC_OUTFLOW;
+        }
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->w.fbc.off, fbc.data(), sizeof(int) * c->g.F, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return IGKS_OK;
+}
+
+// fresh scalars of one instance: iteration counter 0 or a checkpoint's
+InstScalars fresh_scalars(const igks_scalars *sc)
+{
+    InstScalars s;
+    std::memset(&s, 0, sizeof s);
+    for (int k = 0; k < NSLOT; k++) s.dtmin_bits[k] = 0x7ff0000000000000ull;   // +inf
+    if (sc) {
+        s.ncommit = sc->iteration;
+        s.cfl = sc->cfl;
+        s.res_inf_prev = sc->res_inf_prev;
+        s.res0 = sc->res0;
+    }
+    return s;
+}
+
+template <typename T>
+int iterate_impl(igks_ctx *c, const Params<T> &P, int n, int *n_done)
+{
+    const size_t ni = c->inst.size();
+    c->hist.assign(ni, std::vector<double>());
+    for (double &t : c->ktimes) t = 0.0;
+    std::vector<int> was_halted(ni);
+    for (size_t i = 0; i < ni; i++) was_halted[i] = c->hs[i].halt;
+    const int start0 = c->hs[0].ncommit;
+    int executed = 0;
+    while (executed < n) {
+        int k = c->opt.chunk > 0 ? std::min(c->opt.chunk, n - executed) : n - executed;
+        if (c->profiling) k = std::min(k, 64);
+        int rc = run_chunk(c, P, k);
+        if (rc) return rc;
+        executed += k;
+        if (n_done) *n_done = c->hs[0].ncommit - start0;
+        bool all = true;
+        for (size_t i = 0; i < ni; i++) all = all && c->hs[i].halt;
+        if (all) break;
+    }
+    if (c->profiling && executed > 0)
+        for (double &t : c->ktimes) t /= executed;
+    std::string frozen;
+    bool all = true;
+    for (size_t i = 0; i < ni; i++) {
+        all = all && c->hs[i].halt;
+        if (c->hs[i].halt && !was_halted[i]) frozen += (frozen.empty() ? "" : ", ") + std::to_string(i);
+    }
+    if (!frozen.empty())
+        return fail(c, IGKS_ENONPHYS, "non-physical update (rho <= 0, p <= 0 or non-finite) rejected; instance(s) " +
+                                          frozen + " frozen at their last committed state");
+    if (all && n > 0) return fail(c, IGKS_ENONPHYS, "every instance is frozen; set a state or a free stream");
+    return IGKS_OK;
+}
+
+template <typename T>
+int tune_run(igks_ctx *c, const Params<T> &P, int iters)
+{
+    c->profiling = true;
+    for (double &x : c->ktimes) x = 0.0;
+    int rc = run_chunk(c, P, iters);
+    c->profiling = false;
+    return rc;
+}
 
 }  // namespace
 
@@ -549,25 +742,35 @@ void igks_default_options(igks_options *o)
     o->sweep = 0;
 }
 
-int igks_create(igks_ctx **out, const igks_options *opt, void *hip_stream)
+int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream, int32_t n_inst)
 {
     if (!out) return IGKS_EINVAL;
     *out = nullptr;
+    if (n_inst < 1) return IGKS_EINVAL;
     igks_ctx *c = new (std::nothrow) igks_ctx();
     if (!c) return IGKS_ENOMEM;
     if (opt) c->opt = *opt; else igks_default_options(&c->opt);
     if (c->opt.precision != IGKS_FP64 && c->opt.precision != IGKS_MIXED) { delete c; return IGKS_EINVAL; }
     if (c->opt.block <= 0) c->opt.block = 256;
-    if (c->opt.block % 64 != 0 || c->opt.block > 1024) { delete c; return IGKS_EINVAL; }
-    if (c->opt.sweep < 0 || c->opt.sweep > 2) { delete c; return IGKS_EINVAL; }
+    if (c->opt.block % 64 != 0 || c->opt.block > 256) { delete c; return IGKS_EINVAL; }
+    if (c->opt.sweep < 0 || c->opt.sweep > 2 || c->opt.chunk < 0) { delete c; return IGKS_EINVAL; }
+    for (int k = 0; k < NCLASS; k++) c->block[k] = c->opt.block;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {
         if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return IGKS_EHIP; }
         c->own_stream = true;
     }
+    c->inst.resize(n_inst);
+    c->hs.resize(n_inst);
+    c->hist.resize(n_inst);
     *out = c;
     return IGKS_OK;
+}
+
+int igks_create(igks_ctx **out, const igks_options *opt, void *hip_stream)
+{
+    return igks_batch_create(out, opt, hip_stream, 1);
 }
 
 void igks_destroy(igks_ctx *c)
@@ -580,115 +783,167 @@ void igks_destroy(igks_ctx *c)
 
 const char *igks_last_error(const igks_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+int igks_batch_mesh_upload(igks_ctx *c, int32_t inst, int32_t n_nodes, const double *xy, int32_t n_cells,
+                           const int32_t *cell_ptr, const int32_t *cell_nodes, int32_t n_bfaces,
+                           const int32_t *bface_nodes, const int32_t *bface_tag)
+{
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    destroy_graph(c);
+    c->bound = false;
+    c->combined = false;
+    for (auto &m : c->inst) m.have_flow = false;
+    InstMesh m;
+    rc = build_instance(c, n_nodes, xy, n_cells, cell_ptr, cell_nodes, n_bfaces, bface_nodes, bface_tag, m);
+    c->inst[inst] = rc ? InstMesh() : std::move(m);
+    return rc;
+}
+
 int igks_mesh_upload(igks_ctx *c, int32_t n_nodes, const double *xy, int32_t n_cells, const int32_t *cell_ptr,
                      const int32_t *cell_nodes, int32_t n_bfaces, const int32_t *bface_nodes,
                      const int32_t *bface_tag)
 {
+    return igks_batch_mesh_upload(c, 0, n_nodes, xy, n_cells, cell_ptr, cell_nodes, n_bfaces, bface_nodes, bface_tag);
+}
+
+int igks_mesh_info(const igks_ctx *cc, int32_t *nc, int32_t *nf, int32_t *nw, int32_t *nl)
+{
+    igks_ctx *c = const_cast<igks_ctx *>(cc);   // combining the instances is cached
     if (!c) return IGKS_EINVAL;
-    destroy_graph(c);
-    c->have_mesh = c->bound = c->have_flow = false;
-    HostMesh m;
-    int rc = build_mesh(c, n_nodes, xy, n_cells, cell_ptr, cell_nodes, n_bfaces, bface_nodes, bface_tag, m);
+    int rc = ensure_combined(c);
     if (rc) return rc;
-    c->m = std::move(m);
-    c->max_blocks = (c->m.nc + 255) / 256;
-    c->hist_cap = hist_cap_of(c->opt);
-    c->have_mesh = true;
+    if (nc) *nc = c->g.N;
+    if (nf) *nf = c->g.F;
+    if (nw) *nw = c->g.nwall;
+    if (nl) *nl = c->g.nlev;
     return IGKS_OK;
 }
 
-int igks_mesh_info(const igks_ctx *c, int32_t *nc, int32_t *nf, int32_t *nw, int32_t *nl)
+int igks_batch_mesh_info(const igks_ctx *c, int32_t inst, int32_t *nc, int32_t *nf, int32_t *nw)
 {
-    if (!c || !c->have_mesh) return IGKS_EINVAL;
-    if (nc) *nc = c->m.nc;
-    if (nf) *nf = c->m.nf;
-    if (nw) *nw = c->m.nwall;
-    if (nl) *nl = c->m.nlev;
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    const InstMesh &m = c->inst[inst];
+    if (!m.ok) return fail(const_cast<igks_ctx *>(c), IGKS_EINVAL, "no mesh uploaded for this instance");
+    if (nc) *nc = m.nc;
+    if (nf) *nf = (int)m.uf.size();
+    if (nw) *nw = (int)m.wall_uf.size();
     return IGKS_OK;
 }
 
-int igks_workspace_size(const igks_ctx *c, size_t *bytes)
+int igks_workspace_size(const igks_ctx *cc, size_t *bytes)
 {
-    if (!c || !bytes || !c->have_mesh) return IGKS_EINVAL;
-    *bytes = layout(c->m, c->opt, c->max_blocks, c->hist_cap).total;
+    igks_ctx *c = const_cast<igks_ctx *>(cc);
+    if (!c || !bytes) return IGKS_EINVAL;
+    int rc = ensure_combined(c);
+    if (rc) return rc;
+    *bytes = layout(c->g, (int)c->inst.size(), c->opt, c->hist_cap).total;
     return IGKS_OK;
 }
 
 int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
 {
     if (!c) return IGKS_EINVAL;
-    if (!c->have_mesh) return fail(c, IGKS_EINVAL, "no mesh uploaded");
-    WsMap w = layout(c->m, c->opt, c->max_blocks, c->hist_cap);
+    int rc = ensure_combined(c);
+    if (rc) return rc;
+    WsMap w = layout(c->g, (int)c->inst.size(), c->opt, c->hist_cap);
     if (!dptr || bytes < w.total) return fail(c, IGKS_ENOMEM, "workspace smaller than igks_workspace_size");
     if (((uintptr_t)dptr) % 256 != 0) return fail(c, IGKS_EINVAL, "workspace must be 256-byte aligned");
     destroy_graph(c);
+    c->bound = false;
     c->ws = (char *)dptr;
     c->ws_bytes = bytes;
-    fill_params(c, c->P64, w);
-    fill_params(c, c->P32, w);
-    const HostMesh &m = c->m;
+    c->w = w;
+    fill_params(c, c->P64);
+    fill_params(c, c->P32);
+    const Global &G = c->g;
     char *b = c->ws;
     auto up = [&](const Buf &x, const void *src, size_t n) -> int {
         if (n == 0) return IGKS_OK;
         HIPCHK(c, hipMemcpyAsync(b + x.off, src, n, hipMemcpyHostToDevice, c->stream));
         return IGKS_OK;
     };
-    const size_t D = sizeof(double), I = sizeof(int), N = m.nc, F = m.nf, E = m.cf_ptr.back();
-    int rc = 0;
-    rc |= up(w.xc, m.xc.data(), N * D); rc |= up(w.yc, m.yc.data(), N * D); rc |= up(w.area, m.area.data(), N * D);
-    rc |= up(w.lsinv, m.lsinv.data(), 3 * N * D); rc |= up(w.vtx, m.vtx.data(), 2 * MAXV * N * D);
-    rc |= up(w.cf_ptr, m.cf_ptr.data(), (N + 1) * I); rc |= up(w.cf_face, m.cf_face.data(), E * I);
-    rc |= up(w.cf_nbr, m.cf_nbr.data(), E * I); rc |= up(w.cf_flag, m.cf_flag.data(), E * I);
-    rc |= up(w.cf_dx, m.cf_dx.data(), E * D); rc |= up(w.cf_dy, m.cf_dy.data(), E * D);
-    rc |= up(w.fl, m.fl.data(), F * I); rc |= up(w.fr, m.fr.data(), F * I); rc |= up(w.fbc, m.ftag.data(), F * I);
-    rc |= up(w.fnx, m.fnx.data(), F * D); rc |= up(w.fny, m.fny.data(), F * D); rc |= up(w.flen, m.flen.data(), F * D);
-    rc |= up(w.frl, m.frl.data(), 2 * F * D); rc |= up(w.frr, m.frr.data(), 2 * F * D);
-    rc |= up(w.fdl, m.fdl.data(), F * D); rc |= up(w.fdr, m.fdr.data(), F * D); rc |= up(w.frn, m.frn.data(), F * D);
-    rc |= up(w.wall_faces, m.wall_faces.data(), m.wall_faces.size() * I);
-    rc |= up(w.wseg, m.wseg.data(), m.wseg.size() * D);
-    rc |= up(w.lev_off, m.lev_off.data(), m.lev_off.size() * I);
+    const size_t D = sizeof(double), I = sizeof(int), N = G.N, F = G.F, E = G.cf_ptr.back();
+    rc = 0;
+    rc |= up(w.xc, G.xc.data(), N * D); rc |= up(w.yc, G.yc.data(), N * D); rc |= up(w.area, G.area.data(), N * D);
+    rc |= up(w.lsinv, G.lsinv.data(), 3 * N * D); rc |= up(w.vtx, G.vtx.data(), 2 * MAXV * N * D);
+    rc |= up(w.cinst, G.cinst.data(), N * I); rc |= up(w.finst, G.finst.data(), F * I);
+    rc |= up(w.icell, G.icell.data(), N * I); rc |= up(w.ioff, G.ioff.data(), G.ioff.size() * I);
+    rc |= up(w.g2i, G.g2i.data(), N * I);
+    rc |= up(w.cf_ptr, G.cf_ptr.data(), (N + 1) * I); rc |= up(w.cf_face, G.cf_face.data(), E * I);
+    rc |= up(w.cf_nbr, G.cf_nbr.data(), E * I); rc |= up(w.cf_flag, G.cf_flag.data(), E * I);
+    rc |= up(w.cf_dx, G.cf_dx.data(), E * D); rc |= up(w.cf_dy, G.cf_dy.data(), E * D);
+    rc |= up(w.fl, G.fl.data(), F * I); rc |= up(w.fr, G.fr.data(), F * I); rc |= up(w.fbc, G.ftag.data(), F * I);
+    rc |= up(w.fnx, G.fnx.data(), F * D); rc |= up(w.fny, G.fny.data(), F * D); rc |= up(w.flen, G.flen.data(), F * D);
+    rc |= up(w.frl, G.frl.data(), 2 * F * D); rc |= up(w.frr, G.frr.data(), 2 * F * D);
+    rc |= up(w.fdl, G.fdl.data(), F * D); rc |= up(w.fdr, G.fdr.data(), F * D); rc |= up(w.frn, G.frn.data(), F * D);
+    rc |= up(w.wall_faces, G.wall_faces.data(), G.wall_faces.size() * I);
+    rc |= up(w.woff, G.woff.data(), G.woff.size() * I);
+    rc |= up(w.wseg, G.wseg.data(), G.wseg.size() * D);
+    rc |= up(w.lev_off, G.lev_off.data(), G.lev_off.size() * I);
     if (rc) return rc;
-    c->d_lev_off = (int *)(b + w.lev_off.off);
     {
-        double width = (double)m.nc / std::max(1, m.nlev);
-        c->sweep_wg = c->opt.sweep == 2 || (c->opt.sweep == 0 && m.nlev > 16 && width < 4096.0);
+        double width = (double)G.N / std::max(1, G.nlev);
+        c->sweep_wg = c->opt.sweep == 2 || (c->opt.sweep == 0 && G.nlev > 16 && width < 4096.0);
     }
-    c->d_wall_faces = (int *)(b + w.wall_faces.off);
-    c->d_wall_out = (double *)(b + w.wall_out.off);
-    c->d_wseg = (double *)(b + w.wseg.off);
+    // instance parameters and scalars start zeroed (no free stream yet)
+    std::vector<InstParam> ip0(c->inst.size());
+    std::memset(ip0.data(), 0, sizeof(InstParam) * ip0.size());
+    for (auto &m : c->inst) std::memset(&m.ip, 0, sizeof m.ip);
+    rc = up(w.ip, ip0.data(), sizeof(InstParam) * ip0.size());
+    if (rc) return rc;
     Launch L = launch_of(c);
-    launch_wall_distance(L, m.nc, c->P64.xc, c->P64.yc, m.nwall, c->d_wseg, (double *)c->P64.dwall);
+    launch_wall_distance(L, G.N, c->P64.xc, c->P64.yc, c->P64.cinst, (const int *)(b + w.woff.off),
+                         (const double *)(b + w.wseg.off), (double *)(b + w.dwall.off));
+    launch_reset(L, c->P64, 15, -1);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemsetAsync(c->P64.sc, 0, sizeof(DevScalars), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->bound = true;
-    c->have_flow = false;
-    return IGKS_OK;
+    for (auto &m : c->inst) m.have_flow = false;
+    for (auto &h : c->hist) h.clear();
+    return sync_scalars(c);
+}
+
+int igks_batch_set_freestream(igks_ctx *c, int32_t inst, double mach, double alpha_deg, double reynolds,
+                              double nut_ratio)
+{
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    rc = check_ready(c, false);
+    if (rc) return rc;
+    if (!(mach > 0) || !(reynolds > 0) || !std::isfinite(alpha_deg))
+        return fail(c, IGKS_EINVAL, "mach and reynolds must be positive");
+    InstMesh &m = c->inst[inst];
+    m.alpha = alpha_deg;
+    // non-dimensionalisation: rho_inf = 1, |V_inf| = 1, reference length 1
+    InstParam &ip = m.ip;
+    std::memset(&ip, 0, sizeof ip);
+    const double pinf = 1.0 / (GAMMA * mach * mach);
+    ip.p_inf = pinf;
+    ip.lam_inf = 1.0 / (2.0 * pinf);
+    ip.mu_inf = 1.0 / reynolds;
+    ip.sa = nut_ratio >= 0.0;
+    const double a = alpha_deg * M_PI / 180.0;
+    ip.Winf[0] = 1.0; ip.Winf[1] = std::cos(a); ip.Winf[2] = std::sin(a);
+    ip.Winf[3] = pinf / (GAMMA - 1.0) + 0.5;
+    ip.Winf[4] = ip.sa ? nut_ratio * ip.mu_inf : 0.0;
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->w.ip.off + inst * sizeof(InstParam), &ip, sizeof(InstParam),
+                             hipMemcpyHostToDevice, c->stream));
+    rc = upload_bc(c);
+    if (rc) return rc;
+    InstScalars s = fresh_scalars(nullptr);   // iteration 0 -> state buffer A
+    HIPCHK(c, hipMemcpyAsync(c->P64.is + inst, &s, sizeof s, hipMemcpyHostToDevice, c->stream));
+    Launch L = launch_of(c);
+    launch_fill_instance(L, m.nc, inst_cells(c, inst), c->g.N, ip.Winf, c->P64.Wa);
+    HIPCHK(c, hipGetLastError());
+    m.have_flow = true;
+    c->hist[inst].clear();
+    return sync_scalars(c);
 }
 
 int igks_set_freestream(igks_ctx *c, double mach, double alpha_deg, double reynolds, double nut_ratio)
 {
-    int rc = check_ready(c, false);
-    if (rc) return rc;
-    if (!(mach > 0) || !(reynolds > 0)) return fail(c, IGKS_EINVAL, "mach and reynolds must be positive");
-    destroy_graph(c);
-    c->mach = mach; c->alpha = alpha_deg; c->re = reynolds; c->nut_ratio = nut_ratio;
-    set_flow_params(c, c->P64);
-    set_flow_params(c, c->P32);
-    // FARFIELD faces: free stream where V_inf . n < 0, else Riemann outflow
-    std::vector<int> fbc(c->m.ftag);
-    for (int q = 0; q < c->m.nf; q++)
-        if (fbc[q] == BC_FARFIELD)
-            fbc[q] = (c->P64.Winf[1] * c->m.fnx[q] + c->P64.Winf[2] * c->m.fny[q] < 0.0) ? BC_FREESTREAM : BC_OUTFLOW;
-    HIPCHK(c, hipMemcpyAsync((void *)c->P64.fbc, fbc.data(), sizeof(int) * c->m.nf, hipMemcpyHostToDevice, c->stream));
-    Launch L = launch_of(c);
-    launch_set_state(L, c->m.nc, c->P64.Winf, c->P64.Wa);
-    HIPCHK(c, hipMemsetAsync(c->P64.sc, 0, sizeof(DevScalars), c->stream));
-    launch_reset(L, c->P64, 7);
-    HIPCHK(c, hipGetLastError());
-    c->have_flow = true;
-    c->hist.clear();
-    return sync_scalars(c);
+    return igks_batch_set_freestream(c, 0, mach, alpha_deg, reynolds, nut_ratio);
 }
 
 int igks_iterate(igks_ctx *c, int32_t n, int32_t *n_done)
@@ -697,160 +952,177 @@ int igks_iterate(igks_ctx *c, int32_t n, int32_t *n_done)
     int rc = check_ready(c, true);
     if (rc) return rc;
     if (n < 0) return fail(c, IGKS_EINVAL, "negative iteration count");
-    c->hist.clear();
-    for (double &t : c->ktimes) t = 0.0;
-    int start = c->hs.ncommit, done = 0;
-    Launch L = launch_of(c);
-    // clear flags a previous rejected update may have left
-    launch_reset(L, c->P64, 3);
-    while (done < n) {
-        int k = c->opt.chunk > 0 ? std::min(c->opt.chunk, n - done) : n - done;
-        if (c->profiling) k = std::min(k, 64);
-        rc = (c->opt.precision == IGKS_MIXED) ? run_chunk(c, c->P32, k) : run_chunk(c, c->P64, k);
-        if (rc) return rc;
-        done = c->hs.ncommit - start;
-        if (n_done) *n_done = done;
-        if (c->hs.halt) {
-            launch_reset(L, c->P64, 3);
-            return fail(c, IGKS_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or non-finite); last good state kept");
-        }
-    }
-    if (c->profiling && n > 0)
-        for (double &t : c->ktimes) t /= n;
+    return (c->opt.precision == IGKS_MIXED) ? iterate_impl(c, c->P32, n, n_done) : iterate_impl(c, c->P64, n, n_done);
+}
+
+int igks_batch_status(igks_ctx *c, int32_t inst, int32_t *halted)
+{
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    if (halted) *halted = c->hs[inst].halt;
     return IGKS_OK;
 }
 
-int igks_get_residual(igks_ctx *c, igks_residual *out)
+int igks_batch_get_residual(igks_ctx *c, int32_t inst, igks_residual *out)
 {
-    int rc = check_ready(c, true);
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    rc = check_ready(c, true);
     if (rc) return rc;
     if (!out) return IGKS_EINVAL;
-    out->iteration = c->hs.ncommit;
-    out->res_l2 = c->hs.res_l2;
-    out->res_drop = c->hs.res0 > 0 ? c->hs.res_l2 / c->hs.res0 : 0.0;
-    out->res_inf = c->hs.res_inf;
-    out->eq40 = c->hs.e40;
-    out->cfl = c->hs.cfl;
-    out->dt_flux = c->hs.dt_flux;
-    out->sa_l2 = c->hs.sa_l2;
+    const InstScalars &s = c->hs[inst];
+    out->iteration = s.ncommit;
+    out->res_l2 = s.res_l2;
+    out->res_drop = s.res0 > 0 ? s.res_l2 / s.res0 : 0.0;
+    out->res_inf = s.res_inf;
+    out->eq40 = s.e40;
+    out->cfl = s.cfl;
+    out->dt_flux = s.dt;
+    out->sa_l2 = s.sa_l2;
+    return IGKS_OK;
+}
+
+int igks_get_residual(igks_ctx *c, igks_residual *out) { return igks_batch_get_residual(c, 0, out); }
+
+int igks_batch_get_history(igks_ctx *c, int32_t inst, double *out, int32_t max, int32_t *n_out)
+{
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    int n = (int)(c->hist[inst].size() / HIST_W);
+    n = std::max(0, std::min(n, (int)max));
+    if (out && n > 0) std::memcpy(out, c->hist[inst].data(), sizeof(double) * HIST_W * n);
+    if (n_out) *n_out = n;
     return IGKS_OK;
 }
 
 int igks_get_history(igks_ctx *c, double *out, int32_t max, int32_t *n_out)
 {
-    if (!c) return IGKS_EINVAL;
-    int n = (int)(c->hist.size() / HIST_W);
-    n = std::min(n, (int)max);
-    if (out && n > 0) std::memcpy(out, c->hist.data(), sizeof(double) * HIST_W * n);
-    if (n_out) *n_out = n;
-    return IGKS_OK;
+    return igks_batch_get_history(c, 0, out, max, n_out);
 }
 
-int igks_get_state(igks_ctx *c, double *W)
+int igks_batch_get_state(igks_ctx *c, int32_t inst, double *W)
 {
-    int rc = check_ready(c, true);
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    rc = check_ready(c, true);
     if (rc) return rc;
     if (!W) return IGKS_EINVAL;
-    const int N = c->m.nc;
-    std::vector<double> tmp(5 * (size_t)N);
-    HIPCHK(c, hipMemcpyAsync(tmp.data(), cur_buffer(c), sizeof(double) * 5 * N, hipMemcpyDeviceToHost, c->stream));
+    const int n = c->inst[inst].nc;
+    Launch L = launch_of(c);
+    launch_copy_instance(L, n, inst_cells(c, inst), c->g.N, cur_buffer(c, inst), stage_buffer(c), false);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(W, stage_buffer(c), sizeof(double) * 5 * n, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int k = 0; k < 5; k++)
-        for (int i = 0; i < N; i++) W[(size_t)k * N + c->m.perm[i]] = tmp[(size_t)k * N + i];
     return IGKS_OK;
 }
 
-int igks_set_state(igks_ctx *c, const double *W, const igks_scalars *sc)
+int igks_get_state(igks_ctx *c, double *W) { return igks_batch_get_state(c, 0, W); }
+
+int igks_batch_set_state(igks_ctx *c, int32_t inst, const double *W, const igks_scalars *sc)
 {
-    int rc = check_ready(c, true);
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    rc = check_ready(c, true);
     if (rc) return rc;
     if (!W) return IGKS_EINVAL;
-    const int N = c->m.nc;
-    for (int i = 0; i < N; i++) {
-        double r = W[i], mx = W[N + i], my = W[2 * N + i], E = W[3 * N + i], t = W[4 * N + i];
+    const int n = c->inst[inst].nc;
+    for (int i = 0; i < n; i++) {
+        double r = W[i], mx = W[n + i], my = W[2 * n + i], E = W[3 * n + i], t = W[4 * n + i];
         double p = E - 0.5 * (mx * mx + my * my) / r;
         if (!(r > 0) || !(p > 0) || !std::isfinite(t) || !std::isfinite(p))
             return fail(c, IGKS_ENONPHYS, "non-physical state at cell " + std::to_string(i));
     }
-    std::vector<double> tmp(5 * (size_t)N);
-    for (int k = 0; k < 5; k++)
-        for (int i = 0; i < N; i++) tmp[(size_t)k * N + i] = W[(size_t)k * N + c->m.perm[i]];
-    DevScalars s{};
-    if (sc) {
-        s.ncommit = sc->iteration;
-        s.cfl = sc->cfl;
-        s.res_inf_prev = sc->res_inf_prev;
-        s.res0 = sc->res0;
-    }
-    for (int i = 0; i < NSLOT; i++) s.dtmin_bits[i] = 0x7ff0000000000000ull;
-    double *dst = (s.ncommit & 1) ? c->P64.Wb : c->P64.Wa;
-    HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), sizeof(double) * 5 * N, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->P64.sc, &s, sizeof(DevScalars), hipMemcpyHostToDevice, c->stream));
-    c->hist.clear();
+    if (sc && sc->iteration < 0) return fail(c, IGKS_EINVAL, "negative iteration count in the scalars");
+    InstScalars s = fresh_scalars(sc);
+    HIPCHK(c, hipMemcpyAsync(c->P64.is + inst, &s, sizeof s, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(stage_buffer(c), W, sizeof(double) * 5 * n, hipMemcpyHostToDevice, c->stream));
+    Launch L = launch_of(c);
+    launch_copy_instance(L, n, inst_cells(c, inst), c->g.N, stage_buffer(c), (s.ncommit & 1) ? c->P64.Wb : c->P64.Wa,
+                         true);
+    HIPCHK(c, hipGetLastError());
+    c->hist[inst].clear();
     return sync_scalars(c);
 }
+
+int igks_set_state(igks_ctx *c, const double *W, const igks_scalars *sc) { return igks_batch_set_state(c, 0, W, sc); }
 
 int igks_get_scalars(igks_ctx *c, igks_scalars *out)
 {
     int rc = check_ready(c, true);
     if (rc) return rc;
     if (!out) return IGKS_EINVAL;
-    out->iteration = c->hs.ncommit;
-    out->cfl = c->hs.cfl;
-    out->res_inf_prev = c->hs.res_inf_prev;
-    out->res0 = c->hs.res0;
+    out->iteration = c->hs[0].ncommit;
+    out->cfl = c->hs[0].cfl;
+    out->res_inf_prev = c->hs[0].res_inf_prev;
+    out->res0 = c->hs[0].res0;
     return IGKS_OK;
 }
 
-int igks_compute_residual(igks_ctx *c, double *M)
+// residual evaluation of every live instance without advancing the iteration
+static int eval_residual(igks_ctx *c, int inst)
 {
-    int rc = check_ready(c, true);
+    int rc = check_inst(c, inst);
     if (rc) return rc;
+    rc = check_ready(c, true);
+    if (rc) return rc;
+    if (c->hs[inst].halt) return fail(c, IGKS_ENONPHYS, "instance is frozen after a rejected update");
     Launch L = launch_of(c);
-    launch_reset(L, c->P64, 3);
+    launch_reset(L, c->P64, 1, -1);
     queue_residual(c, c->P64);
-    launch_reset(L, c->P64, 1);
+    launch_reset(L, c->P64, 1, -1);
     HIPCHK(c, hipGetLastError());
-    const int N = c->m.nc;
-    std::vector<double> tmp(5 * (size_t)N);
-    HIPCHK(c, hipMemcpyAsync(tmp.data(), c->P64.M, sizeof(double) * 5 * N, hipMemcpyDeviceToHost, c->stream));
+    return IGKS_OK;
+}
+
+int igks_batch_compute_residual(igks_ctx *c, int32_t inst, double *M)
+{
+    int rc = eval_residual(c, inst);
+    if (rc) return rc;
+    const int n = c->inst[inst].nc;
+    Launch L = launch_of(c);
+    launch_copy_instance(L, n, inst_cells(c, inst), c->g.N, c->P64.M, stage_buffer(c), false);
+    HIPCHK(c, hipGetLastError());
+    if (M) HIPCHK(c, hipMemcpyAsync(M, stage_buffer(c), sizeof(double) * 5 * n, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (M)
-        for (int k = 0; k < 5; k++)
-            for (int i = 0; i < N; i++) M[(size_t)k * N + c->m.perm[i]] = tmp[(size_t)k * N + i];
+    return IGKS_OK;
+}
+
+int igks_compute_residual(igks_ctx *c, double *M) { return igks_batch_compute_residual(c, 0, M); }
+
+int igks_batch_get_wall_loads(igks_ctx *c, int32_t inst, double *cl, double *cd, double *cf, double *cp, double *xw)
+{
+    int rc = eval_residual(c, inst);
+    if (rc) return rc;
+    const int w0 = c->g.woff[inst], nw = c->g.woff[inst + 1] - w0;
+    double *wout = (double *)(c->ws + c->w.wall_out.off);
+    Launch L = launch_of(c);
+    launch_gather_faces(L, nw, (const int *)(c->ws + c->w.wall_faces.off) + w0, c->P64.flux, c->g.F, wout);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> fw(4 * (size_t)std::max(nw, 1));
+    if (nw > 0) HIPCHK(c, hipMemcpyAsync(fw.data(), wout, sizeof(double) * 4 * nw, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const InstMesh &m = c->inst[inst];
+    const double a = m.alpha * M_PI / 180.0, ca = std::cos(a), sa = std::sin(a), q = 0.5;
+    double Fx = 0, Fy = 0;
+    for (int k = 0; k < nw; k++) {
+        const int f = c->g.wall_faces[w0 + k];
+        const double fx = fw[4 * k + 1], fy = fw[4 * k + 2], S = c->g.flen[f];
+        Fx += fx;
+        Fy += fy;
+        double nx = c->g.fnx[f], ny = c->g.fny[f], tx = -ny, ty = nx;
+        if (tx * ca + ty * sa < 0) { tx = -tx; ty = -ty; }
+        if (cp) cp[k] = ((fx * nx + fy * ny) / S - m.ip.p_inf) / q;
+        if (cf) cf[k] = ((fx * tx + fy * ty) / S) / q;
+        if (xw) xw[k] = c->g.fxm[f];
+    }
+    if (cd) *cd = (Fx * ca + Fy * sa) / q;
+    if (cl) *cl = (-Fx * sa + Fy * ca) / q;
     return IGKS_OK;
 }
 
 int igks_get_wall_loads(igks_ctx *c, double *cl, double *cd, double *cf, double *cp, double *xw)
 {
-    int rc = check_ready(c, true);
-    if (rc) return rc;
-    Launch L = launch_of(c);
-    launch_reset(L, c->P64, 3);
-    queue_residual(c, c->P64);
-    launch_reset(L, c->P64, 1);
-    const int nw = c->m.nwall;
-    launch_gather_faces(L, nw, c->d_wall_faces, c->P64.flux, c->m.nf, c->d_wall_out);
-    HIPCHK(c, hipGetLastError());
-    std::vector<double> fw(4 * (size_t)std::max(nw, 1));
-    if (nw > 0) HIPCHK(c, hipMemcpyAsync(fw.data(), c->d_wall_out, sizeof(double) * 4 * nw, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    double a = c->alpha * M_PI / 180.0, ca = std::cos(a), sa = std::sin(a), q = 0.5;
-    double Fx = 0, Fy = 0;
-    for (int w = 0; w < nw; w++) {
-        int f = c->m.wall_faces[w];
-        double fx = fw[4 * w + 1], fy = fw[4 * w + 2], S = c->m.flen[f];
-        Fx += fx;
-        Fy += fy;
-        double nx = c->m.fnx[f], ny = c->m.fny[f], tx = -ny, ty = nx;
-        if (tx * ca + ty * sa < 0) { tx = -tx; ty = -ty; }
-        if (cp) cp[w] = ((fx * nx + fy * ny) / S - c->P64.p_inf) / q;
-        if (cf) cf[w] = ((fx * tx + fy * ty) / S) / q;
-        if (xw) xw[w] = c->m.fxm[f];
-    }
-    if (cd) *cd = (Fx * ca + Fy * sa) / q;
-    if (cl) *cl = (-Fx * sa + Fy * ca) / q;
-    return IGKS_OK;
+    return igks_batch_get_wall_loads(c, 0, cl, cd, cf, cp, xw);
 }
 
 int igks_set_profiling(igks_ctx *c, int on)
@@ -864,6 +1136,68 @@ int igks_get_kernel_times(igks_ctx *c, double *ms7)
 {
     if (!c || !ms7) return IGKS_EINVAL;
     for (int k = 0; k < 7; k++) ms7[k] = c->ktimes[k];
+    return IGKS_OK;
+}
+
+int igks_get_schedule(const igks_ctx *c, int32_t *s6)
+{
+    if (!c || !s6) return IGKS_EINVAL;
+    for (int k = 0; k < NCLASS; k++) s6[k] = c->block[k];
+    s6[5] = c->sweep_wg ? 2 : 1;
+    return IGKS_OK;
+}
+
+int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s6)
+{
+    int rc = check_ready(c, true);
+    if (rc) return rc;
+    if (iters < 1 || iters > 1000) return fail(c, IGKS_EINVAL, "iters must be in 1..1000");
+    for (size_t i = 0; i < c->inst.size(); i++)
+        if (c->hs[i].halt) return fail(c, IGKS_ENONPHYS, "instance " + std::to_string(i) + " is frozen");
+    destroy_graph(c);
+    const bool prof = c->profiling;
+    // the candidates run real iterations: keep both state buffers and the scalars
+    const size_t N = c->g.N, ni = c->inst.size(), SB = 5 * N * sizeof(double);
+    char *bk = c->ws + c->w.backup.off;
+    HIPCHK(c, hipMemcpyAsync(bk, c->P64.Wa, SB, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(bk + SB, c->P64.Wb, SB, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(bk + 2 * SB, c->P64.is, ni * sizeof(InstScalars), hipMemcpyDeviceToDevice, c->stream));
+    std::vector<std::vector<double>> hist_keep = c->hist;
+    // kernel class -> event interval: prep 0, flux 1, gather 2, sweep 4 + 5, update 6
+    const int ev_of[NCLASS] = {0, 1, 2, 4, 6};
+    const int cand[3] = {64, 128, 256};
+    int best[NCLASS];
+    double best_t[NCLASS];
+    for (int k = 0; k < NCLASS; k++) { best[k] = c->block[k]; best_t[k] = 1e300; }
+    const bool wg_auto = c->sweep_wg;
+    for (int b : cand) {
+        for (int k = 0; k < NCLASS; k++) c->block[k] = b;
+        c->sweep_wg = false;
+        rc = (c->opt.precision == IGKS_MIXED) ? tune_run(c, c->P32, iters) : tune_run(c, c->P64, iters);
+        if (rc) break;
+        for (int k = 0; k < NCLASS; k++) {
+            double tk = c->ktimes[ev_of[k]] + (k == 3 ? c->ktimes[5] : 0.0);
+            if (tk < best_t[k]) { best_t[k] = tk; best[k] = b; }
+        }
+    }
+    for (int k = 0; k < NCLASS; k++) c->block[k] = best[k];
+    if (!rc) {
+        // sweeps: one launch per wavefront (timed above) or one workgroup
+        c->sweep_wg = true;
+        rc = (c->opt.precision == IGKS_MIXED) ? tune_run(c, c->P32, iters) : tune_run(c, c->P64, iters);
+        if (!rc) c->sweep_wg = c->ktimes[4] + c->ktimes[5] < best_t[3];
+    }
+    if (rc) c->sweep_wg = wg_auto;
+    c->profiling = prof;
+    HIPCHK(c, hipMemcpyAsync(c->P64.Wa, bk, SB, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->P64.Wb, bk + SB, SB, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->P64.is, bk + 2 * SB, ni * sizeof(InstScalars), hipMemcpyDeviceToDevice, c->stream));
+    c->hist = hist_keep;
+    for (double &x : c->ktimes) x = 0.0;
+    int rc2 = sync_scalars(c);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    if (s6) igks_get_schedule(c, s6);
     return IGKS_OK;
 }
 

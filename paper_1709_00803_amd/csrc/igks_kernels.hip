@@ -1,15 +1,18 @@
 // igks_kernels.hip - HIP kernels of the implicit gas-kinetic scheme for
 // gfx950 (MI355X).
 //
-// One iteration = prep (per cell) -> flux (per face) -> gather (per cell)
-// -> reduce (one block) -> forward sweep (one launch per wavefront) ->
-// backward sweep -> update (per cell) -> commit (one thread).
+// One iteration = prep (per cell) -> dt (per instance) -> flux (per face)
+// -> gather (per cell) -> norm partial sums -> reduce (per instance) ->
+// forward sweep (one launch per wavefront) -> backward sweep -> update (per
+// cell) -> commit (per instance).
 //
 // Data are structure-of-arrays in the library's internal cell order
-// (wavefront, then upload index) and face order (owner cell).  Face results
-// go to per-face arrays and every cell sums its faces in a fixed order, so
-// results are deterministic without floating-point atomics; the only
-// atomics are integer min/max on the bit patterns of non-negative doubles.
+// (wavefront, then instance, then upload index) and face order (owner
+// cell).  Face results go to per-face arrays and every cell sums its faces
+// in a fixed order, so results are deterministic without floating-point
+// atomics; the only atomics are integer min/max on the bit patterns of
+// non-negative doubles.  Several independent instances (meshes and flow
+// conditions) share every launch; each cell and face carries its instance.
 #include "igks_dev.h"
 
 #include <math.h>
@@ -19,13 +22,12 @@ namespace igks {
 // ---------------------------------------------------------------- helpers
 
 // Sutherland's law relative to the 288.15 K free stream, T/T_inf = lam_inf/lam.
-template <typename T>
-__device__ __forceinline__ double mu_lam(const Params<T> &P, double lam)
+__device__ __forceinline__ double mu_lam(int law, const InstParam &ip, double lam)
 {
-    if (P.mu_law) return P.mu_inf;
+    if (law) return ip.mu_inf;
     const double S = 110.4 / 288.15;
-    double th = P.lam_inf / lam;
-    return P.mu_inf * th * sqrt(th) * (1.0 + S) / (th + S);
+    double th = ip.lam_inf / lam;
+    return ip.mu_inf * th * sqrt(th) * (1.0 + S) / (th + S);
 }
 
 __device__ __forceinline__ double lam_of(const double *w)
@@ -70,12 +72,11 @@ __device__ __forceinline__ void sa_source(double nut, double nu, double d, doubl
 
 // Ghost cell-centre state across a boundary face with outward unit normal n
 // (Sec. 2.5).
-template <typename T>
-__device__ __forceinline__ void ghost(const Params<T> &P, int bc, const double *w, double nx, double ny, double *g)
+__device__ __forceinline__ void ghost(const InstParam &ip, int bc, const double *w, double nx, double ny, double *g)
 {
     if (bc == BC_FREESTREAM) {
 #pragma unroll
-        for (int k = 0; k < 5; k++) g[k] = P.Winf[k];
+        for (int k = 0; k < 5; k++) g[k] = ip.Winf[k];
         return;
     }
     double r = w[0], mx = w[1], my = w[2];
@@ -92,9 +93,9 @@ __device__ __forceinline__ void ghost(const Params<T> &P, int bc, const double *
     // rho and lam from inside, tangential velocity from inside.
     double U = mx / r, V = my / r, lam = lam_of(w);
     double ci = sqrt(GAMMA / (2.0 * lam));
-    double co = sqrt(GAMMA / (2.0 * P.lam_inf));
+    double co = sqrt(GAMMA / (2.0 * ip.lam_inf));
     double Ui = U * nx + V * ny;
-    double Uo = P.Winf[1] * nx + P.Winf[2] * ny;
+    double Uo = ip.Winf[1] * nx + ip.Winf[2] * ny;
     double Ub = 0.5 * ((Ui + 2.0 * ci / (GAMMA - 1.0)) + (Uo - 2.0 * co / (GAMMA - 1.0)));
     double Vt = -U * ny + V * nx;
     g[0] = r;
@@ -129,16 +130,52 @@ __device__ __forceinline__ double wave_max(double v)
     for (int o = warpSize / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
 }
-__device__ __forceinline__ int wave_or(int v)
+
+// Atomic min / max of a non-negative double into one of the NSLOT slots of
+// the lane's instance.  Lanes with inst < 0 take no part.  When the whole
+// wave belongs to one instance it combines first and issues one atomic.
+template <bool MIN>
+__device__ __forceinline__ void slot_update(unsigned long long *slots0, int inst, double v)
 {
-    for (int o = warpSize / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    unsigned long long act = __ballot(inst >= 0);
+    if (act == 0ull) return;
+    int src = __ffsll((long long)act) - 1;
+    int i0 = __shfl(inst, src);
+    int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) / warpSize);
+    unsigned slot = (unsigned)wave & (NSLOT - 1);
+    size_t stride = sizeof(InstScalars) / sizeof(unsigned long long);
+    if (__all(inst < 0 || inst == i0)) {
+        double x = (inst >= 0) ? v : (MIN ? INFINITY : 0.0);
+        x = MIN ? wave_min(x) : wave_max(x);
+        if ((int)(threadIdx.x & (warpSize - 1)) == src) {
+            unsigned long long *p = slots0 + (size_t)i0 * stride + slot;
+            if (MIN) atomicMin(p, (unsigned long long)__double_as_longlong(x));
+            else atomicMax(p, (unsigned long long)__double_as_longlong(x));
+        }
+    } else if (inst >= 0) {
+        unsigned long long *p = slots0 + (size_t)inst * stride + slot;
+        if (MIN) atomicMin(p, (unsigned long long)__double_as_longlong(v));
+        else atomicMax(p, (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+__device__ __forceinline__ double slots_min_serial(const unsigned long long *b)
+{
+    double v = INFINITY;
+    for (int i = 0; i < NSLOT; i++) v = fmin(v, __longlong_as_double((long long)b[i]));
+    return v;
+}
+__device__ __forceinline__ double slots_max_serial(const unsigned long long *b)
+{
+    double v = 0.0;
+    for (int i = 0; i < NSLOT; i++) v = fmax(v, __longlong_as_double((long long)b[i]));
     return v;
 }
 
 template <typename T>
-__device__ __forceinline__ const double *cur_state(const Params<T> &P)
+__device__ __forceinline__ const double *cur_state(const Params<T> &P, int inst)
 {
-    return (P.sc->ncommit & 1) ? P.Wb : P.Wa;
+    return (P.is[inst].ncommit & 1) ? P.Wb : P.Wa;
 }
 
 // ------------------------------------------------------- kinetic building blocks
@@ -266,7 +303,7 @@ __device__ __forceinline__ void side_terms(const double *w, const double *gn, co
 // flux integrated over [0, dt].  The equilibrium part is evaluated one
 // half space at a time so that only one set of moments is live at once.
 template <typename T>
-__device__ __forceinline__ void gks_flux(const Params<T> &P, const double *wl, const double *gln, const double *glt,
+__device__ __forceinline__ void gks_flux(const Params<T> &P, const InstParam &ip, const double *wl, const double *gln, const double *glt,
                                          const double *wr, const double *grn, const double *grt, const double *wlc,
                                          const double *wrc, double dl, double dr, double dt, double nut_f,
                                          double *F)
@@ -282,8 +319,8 @@ __device__ __forceinline__ void gks_flux(const Params<T> &P, const double *wl, c
 
     // Eq.34 collision time at the interface and the time integrals of the
     // six Eq.13 factors over [0, dt]
-    double mul = mu_lam(P, lam0), mut = 0.0;
-    if (P.sa && nut_f > 0.0) mut = r0 * nut_f * sa_fv1(nut_f * r0 / mul);
+    double mul = mu_lam(P.mu_law, ip, lam0), mut = 0.0;
+    if (ip.sa && nut_f > 0.0) mut = r0 * nut_f * sa_fv1(nut_f * r0 / mul);
     double tau = (mul + mut) * 2.0 * lam0 / r0;
     double eta = exp(-dt / tau), ome = -expm1(-dt / tau);
     double T1 = dt - tau * ome;
@@ -368,55 +405,46 @@ __device__ __forceinline__ void jac_vec(const V *W, V nx, V ny, const V *d, V *o
 
 // ------------------------------------------------------------------ kernels
 
-__device__ __forceinline__ void reset_slots(DevScalars *sc)
-{
-    for (int i = 0; i < NSLOT; i++) {
-        sc->dtmin_bits[i] = 0x7ff0000000000000ull;   // +inf
-        sc->resinf_bits[i] = 0ull;
-        sc->e40_bits[i] = 0ull;
-    }
-}
-// min / max over the slots, read by one full wave (lane i reads slot i)
-__device__ __forceinline__ double slots_min(const unsigned long long *b)
-{
-    double v = __longlong_as_double((long long)b[threadIdx.x & (NSLOT - 1)]);
-    return wave_min(v);
-}
-__device__ __forceinline__ double slots_max(const unsigned long long *b)
-{
-    double v = __longlong_as_double((long long)b[threadIdx.x & (NSLOT - 1)]);
-    return wave_max(v);
-}
-__device__ __forceinline__ unsigned slot_of(int wave)
-{
-    return (unsigned)wave & (NSLOT - 1);
-}
-
-// mode bit 1: per-iteration atomics; 2: halt/bad flags; 4: chunk history
+// mode bit 1: per-iteration slots; 2: bad/halt flags; 4: history counter;
+// 8: all scalars of the instance (fresh start).  inst < 0: every instance.
 template <typename T>
-__global__ void k_reset(Params<T> P, int mode)
+__global__ void k_reset(Params<T> P, int mode, int inst)
 {
-    DevScalars *sc = P.sc;
-    if (mode & 1) reset_slots(sc);
-    if (mode & 2) { sc->bad = 0; sc->halt = 0; }
-    if (mode & 4) sc->hist_n = 0;
+    int lo = inst < 0 ? 0 : inst, hi = inst < 0 ? P.ninst : inst + 1;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x) {
+        InstScalars *s = &P.is[i];
+        if (mode & 8) {
+            s->dt = s->cfl = s->res_inf_prev = s->res0 = 0.0;
+            s->res_l2 = s->sa_l2 = s->res_inf = s->e40 = 0.0;
+            s->ncommit = 0;
+        }
+        if (mode & (1 | 8))
+            for (int k = 0; k < NSLOT; k++) {
+                s->dtmin_bits[k] = 0x7ff0000000000000ull;   // +inf
+                s->resinf_bits[k] = 0ull;
+                s->e40_bits[k] = 0ull;
+            }
+        if (mode & (2 | 8)) { s->bad = 0; s->halt = 0; }
+    }
+    if ((mode & 4) && threadIdx.x == 0) *P.hist_n = 0;
 }
 
-// Per cell: Eq.21 spectral radius and the Eq.23 minimum, least-squares
+// Per cell: Eq.21 spectral radius and the Eq.23 time step, least-squares
 // gradients (Eq.6-7, ghost cells included), the Eq.9-10 limiter,
 // vorticity and the laminar viscosity.
 template <typename T>
-__device__ __forceinline__ void prep_cell(const Params<T> &P, int c, double &dtc)
+__device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
 {
     const int N = P.nc;
-    const double *W = cur_state(P);
+    const InstParam &ip = P.ip[inst];
+    const double *W = cur_state(P, inst);
     double w[5];
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
     double r = w[0], U = w[1] / r, V = w[2] / r;
     double lam = lam_of(w);
     double cs = sqrt(GAMMA / (2.0 * lam));
-    P.nu[c] = mu_lam(P, lam) / r;
+    P.nu[c] = mu_lam(P.mu_law, ip, lam) / r;
     double lc = 0.0, b1[4] = {0, 0, 0, 0}, b2[4] = {0, 0, 0, 0}, wmax[4], wmin[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) wmax[k] = wmin[k] = w[k];
@@ -431,7 +459,7 @@ __device__ __forceinline__ void prep_cell(const Params<T> &P, int c, double &dtc
 #pragma unroll
             for (int k = 0; k < 4; k++) wj[k] = W[k * N + j];
         } else {
-            ghost(P, P.fbc[f], w, nx, ny, wj);
+            ghost(ip, P.fbc[f], w, nx, ny, wj);
         }
         double dx = P.cf_dx[e], dy = P.cf_dy[e];
 #pragma unroll
@@ -444,7 +472,6 @@ __device__ __forceinline__ void prep_cell(const Params<T> &P, int c, double &dtc
         }
     }
     P.lamc[c] = lc;
-    dtc = P.cfl_flux * P.area[c] / lc;
     double L11 = P.lsinv[c], L12 = P.lsinv[N + c], L22 = P.lsinv[2 * N + c];
     double gx[4], gy[4];
 #pragma unroll
@@ -480,22 +507,29 @@ __device__ __forceinline__ void prep_cell(const Params<T> &P, int c, double &dtc
         P.grad[k * N + c] = gx[k];
         P.grad[(4 + k) * N + c] = gy[k];
     }
+    return P.cfl_flux * P.area[c] / lc;
 }
-
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_prep(Params<T> P)
 {
-    if (P.sc->halt) return;
     int c = blockIdx.x * blockDim.x + threadIdx.x;
-    double dtc = INFINITY;
-    if (c < P.nc) prep_cell(P, c, dtc);
-    // one atomic per wave: the Eq.23 minimum over cells
-    dtc = wave_min(dtc);
-    if ((threadIdx.x & (warpSize - 1)) == 0 && dtc < INFINITY) {
-        int wv = (blockIdx.x * blockDim.x + threadIdx.x) / warpSize;
-        atomicMin(&P.sc->dtmin_bits[slot_of(wv)], (unsigned long long)__double_as_longlong(dtc));
+    int inst = -1;
+    double dt = INFINITY;
+    if (c < P.nc) {
+        inst = P.cinst[c];
+        if (P.is[inst].halt) inst = -1;
+        else dt = prep_cell(P, c, inst);
     }
+    slot_update<true>(&P.is[0].dtmin_bits[0], inst, dt);   // Eq.23: minimum over the instance's cells
+}
+
+// One thread per instance: the Eq.23 time step = minimum over its slots.
+template <typename T>
+__global__ void k_dt(Params<T> P)
+{
+    for (int i = threadIdx.x; i < P.ninst; i += blockDim.x)
+        if (!P.is[i].halt) P.is[i].dt = slots_min_serial(P.is[i].dtmin_bits);
 }
 
 __device__ __forceinline__ bool physical(const double *w)
@@ -506,10 +540,12 @@ __device__ __forceinline__ bool physical(const double *w)
 // Per face: reconstruction (Eq.10), ghost side, the GKS flux, the LU-SGS
 // spectral radius and the SA face terms (Eq.28-30).
 template <typename T>
-__device__ __forceinline__ void flux_face(const Params<T> &P, int f, double dt)
+__device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst)
 {
     const int N = P.nc, F = P.nf;
-    const double *W = cur_state(P);
+    const InstParam &ip = P.ip[inst];
+    const double *W = cur_state(P, inst);
+    const double dt = P.is[inst].dt;
     int l = P.fl[f], rr = P.fr[f];
     double nx = P.fnx[f], ny = P.fny[f], S = P.flen[f];
     double tx = -ny, ty = nx;
@@ -527,8 +563,8 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, double dt)
 #pragma unroll
         for (int k = 0; k < 4; k++) { WL[k] = wl[k]; glx[k] = gly[k] = 0.0; }
     }
-    double WR[4], grx[4], gry[4], wrc[5], dr, rn;
-    double dl = P.fdl[f];
+    double WR[4], grx[4], gry[4], wrc[5], dr;
+    double dl = P.fdl[f], rn = P.frn[f];
     if (rr >= 0) {
         double rrx = P.frr[2 * f], rry = P.frr[2 * f + 1];
 #pragma unroll
@@ -544,42 +580,43 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, double dt)
             for (int k = 0; k < 4; k++) { WR[k] = wrc[k]; grx[k] = gry[k] = 0.0; }
         }
         dr = P.fdr[f];
-        rn = P.frn[f];
     } else {
-        // ghost side: boundary map of the reconstructed interior face state,
-        // zero slopes; cell-centre ghost value from the interior cell centre
+        // ghost side: boundary map of the reconstructed interior face state;
+        // cell-centre ghost value from the interior cell centre
         int bc = P.fbc[f];
         double tmp[5] = {WL[0], WL[1], WL[2], WL[3], wl[4]}, out[5];
-        ghost(P, bc, tmp, nx, ny, out);
+        ghost(ip, bc, tmp, nx, ny, out);
 #pragma unroll
         for (int k = 0; k < 4; k++) { WR[k] = out[k]; grx[k] = gry[k] = 0.0; }
-        ghost(P, bc, wl, nx, ny, wrc);
+        ghost(ip, bc, wl, nx, ny, wrc);
         dr = dl;
-        rn = P.frn[f];
     }
+
     // spectral radius of the face for the implicit operator
-    double qi = (wl[1] * nx + wl[2] * ny) / wl[0], qj = (wrc[1] * nx + wrc[2] * ny) / wrc[0];
-    double li = fabs(qi) + sqrt(GAMMA / (2.0 * lam_of(wl)));
-    double lj = fabs(qj) + sqrt(GAMMA / (2.0 * lam_of(wrc)));
-    double lamf = fmax(li, lj);
-    double mi = mu_lam(P, lam_of(wl)), mj = mu_lam(P, lam_of(wrc));
-    if (P.visc_sr) {
-        double ei = mi, ej = mj;
-        if (P.sa) {
-            if (wl[4] > 0) ei += wl[0] * wl[4] * sa_fv1(wl[4] * wl[0] / mi);
-            if (wrc[4] > 0) ej += wrc[0] * wrc[4] * sa_fv1(wrc[4] * wrc[0] / mj);
+    {
+        double qi = (wl[1] * nx + wl[2] * ny) / wl[0], qj = (wrc[1] * nx + wrc[2] * ny) / wrc[0];
+        double li = fabs(qi) + sqrt(GAMMA / (2.0 * lam_of(wl)));
+        double lj = fabs(qj) + sqrt(GAMMA / (2.0 * lam_of(wrc)));
+        double lamf = fmax(li, lj);
+        double mi = mu_lam(P.mu_law, ip, lam_of(wl)), mj = mu_lam(P.mu_law, ip, lam_of(wrc));
+        if (P.visc_sr) {
+            double ei = mi, ej = mj;
+            if (ip.sa) {
+                if (wl[4] > 0) ei += wl[0] * wl[4] * sa_fv1(wl[4] * wl[0] / mi);
+                if (wrc[4] > 0) ej += wrc[0] * wrc[4] * sa_fv1(wrc[4] * wrc[0] / mj);
+            }
+            lamf += (ei / wl[0] + ej / wrc[0]) / rn;
         }
-        lamf += (ei / wl[0] + ej / wrc[0]) / rn;
-    }
-    P.lam[f] = lamf;
-    if (P.sa) {
-        double nui = mi / wl[0], nuj = mj / wrc[0];
-        double ti = wl[4], tj = wrc[4];
-        double g = (tj - ti) / rn;
-        double Finv = 0.5 * (qi + fabs(qi)) * ti + 0.5 * (qj - fabs(qj)) * tj;
-        double Fvis = (0.5 / SA_SIGMA) * ((nui + nuj) + (1.0 + SA_CB2) * (ti + tj)) * g;
-        P.saf[f] = (Fvis - Finv) * S;
-        P.sag[f] = g * S;
+        P.lam[f] = lamf;
+        if (ip.sa) {
+            double nui = mi / wl[0], nuj = mj / wrc[0];
+            double ti = wl[4], tj = wrc[4];
+            double g = (tj - ti) / rn;
+            double Finv = 0.5 * (qi + fabs(qi)) * ti + 0.5 * (qj - fabs(qj)) * tj;
+            double Fvis = (0.5 / SA_SIGMA) * ((nui + nuj) + (1.0 + SA_CB2) * (ti + tj)) * g;
+            P.saf[f] = (Fvis - Finv) * S;
+            P.sag[f] = g * S;
+        }
     }
     // face frame
     double fwl[4], fwr[4], fwlc[4], fwrc[4], gln[4], glt[4], grn[4], grt[4];
@@ -614,171 +651,180 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, double dt)
     }
     double nutf = fmax(0.5 * (wl[4] + wrc[4]), 0.0);
     double Fr[4];
-    gks_flux(P, fwl, gln, glt, fwr, grn, grt, fwlc, fwrc, dl, dr, dt, nutf, Fr);
+    gks_flux(P, ip, fwl, gln, glt, fwr, grn, grt, fwlc, fwrc, dl, dr, dt, nutf, Fr);
     double idt = 1.0 / dt;
     double Fn = Fr[1] * idt, Ft = Fr[2] * idt;
     P.flux[f] = Fr[0] * idt * S;
     P.flux[F + f] = (Fn * nx + Ft * tx) * S;
     P.flux[2 * F + f] = (Fn * ny + Ft * ty) * S;
     P.flux[3 * F + f] = Fr[3] * idt * S;
-
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_flux(Params<T> P)
 {
-    __shared__ double sdt;
-    if (P.sc->halt) return;
-    if (threadIdx.x < warpSize) {
-        double v = slots_min(P.sc->dtmin_bits);   // Eq.23 time step
-        if (threadIdx.x == 0) sdt = v;
-    }
-    __syncthreads();
     int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < P.nf) flux_face(P, f, sdt);
+    if (f >= P.nf) return;
+    int inst = P.finst[f];
+    if (P.is[inst].halt) return;
+    flux_face(P, f, inst);
 }
 
 // Per cell: residual M (Eq.16) as the signed sum of its face fluxes, the
-// LU-SGS diagonal pieces, the SA residual and diagonal (Eq.27-32), and the
-// norms (max exact via integer atomics, L2 as block partial sums).
+// LU-SGS diagonal pieces, the SA residual and diagonal (Eq.27-32), the
+// squares for the L2 norms and the max norm.
+template <typename T>
+__device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int inst)
+{
+    const int N = P.nc, F = P.nf;
+    const InstParam &ip = P.ip[inst];
+    const double *W = cur_state(P, inst);
+    double m[4] = {0, 0, 0, 0}, ls = 0.0, saR = 0.0, sagS = 0.0, sad = 0.0;
+    double w[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
+    double nuc = P.nu[c];
+    int e0 = P.cf_ptr[c], e1 = P.cf_ptr[c + 1];
+    for (int e = e0; e < e1; e++) {
+        int f = P.cf_face[e];
+        double sg = (P.cf_flag[e] & CF_OWNER) ? 1.0 : -1.0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) m[k] -= sg * P.flux[k * F + f];
+        double S = P.flen[f];
+        ls += P.lam[f] * S;
+        if (ip.sa) {
+            saR += sg * P.saf[f];
+            sagS += sg * P.sag[f];
+            double nx = sg * P.fnx[f], ny = sg * P.fny[f];
+            int j = P.cf_nbr[e];
+            double nuj, tj;
+            if (j >= 0) {
+                nuj = P.nu[j];
+                tj = W[4 * N + j];
+            } else {
+                double g[5];
+                ghost(ip, P.fbc[f], w, nx, ny, g);
+                nuj = mu_lam(P.mu_law, ip, lam_of(g)) / g[0];
+                tj = g[4];
+            }
+            double qc = (w[1] * nx + w[2] * ny) / w[0];
+            double kf = (1.0 / SA_SIGMA) * (0.5 * (nuc + nuj) + (1.0 + SA_CB2) * 0.5 * (w[4] + tj));
+            sad += 0.5 * (qc + fabs(qc)) * S + kf * S / P.frn[f];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) P.M[k * N + c] = m[k];
+    P.lsum[c] = 0.5 * ls;
+    P.r2[c] = m[0] * m[0];
+    if (ip.sa) {
+        double Sr, jd;
+        sa_source(w[4], nuc, P.dwall[c], P.vort[c], Sr, jd);
+        double a = P.area[c];
+        double rsa = saR - (SA_CB2 / SA_SIGMA) * w[4] * sagS + a * Sr;
+        P.M[4 * N + c] = rsa;
+        P.sadiag[c] = sad + a * jd;
+        P.r2[N + c] = rsa * rsa;
+    } else {
+        P.M[4 * N + c] = 0.0;
+        P.r2[N + c] = 0.0;
+    }
+    return fmax(fmax(fabs(m[0]), fabs(m[1])), fmax(fabs(m[2]), fabs(m[3])));
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather(Params<T> P)
 {
-    __shared__ double red0[256], red1[256], red2[256];
-    if (P.sc->halt) return;
     int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const int N = P.nc, F = P.nf;
-    double s0 = 0.0, s1 = 0.0, rinf = 0.0;
-    if (c < N) {
-        const double *W = cur_state(P);
-        double m[4] = {0, 0, 0, 0}, ls = 0.0, saR = 0.0, sagS = 0.0, sad = 0.0;
-        double w[5];
-#pragma unroll
-        for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
-        double nuc = P.nu[c];
-        int e0 = P.cf_ptr[c], e1 = P.cf_ptr[c + 1];
-        for (int e = e0; e < e1; e++) {
-            int f = P.cf_face[e];
-            double sg = (P.cf_flag[e] & CF_OWNER) ? 1.0 : -1.0;
-#pragma unroll
-            for (int k = 0; k < 4; k++) m[k] -= sg * P.flux[k * F + f];
-            double S = P.flen[f];
-            ls += P.lam[f] * S;
-            if (P.sa) {
-                saR += sg * P.saf[f];
-                sagS += sg * P.sag[f];
-                double nx = sg * P.fnx[f], ny = sg * P.fny[f];
-                int j = P.cf_nbr[e];
-                double nuj, tj;
-                if (j >= 0) {
-                    nuj = P.nu[j];
-                    tj = W[4 * N + j];
-                } else {
-                    double g[5];
-                    ghost(P, P.fbc[f], w, nx, ny, g);
-                    nuj = mu_lam(P, lam_of(g)) / g[0];
-                    tj = g[4];
-                }
-                double qc = (w[1] * nx + w[2] * ny) / w[0];
-                double kf = (1.0 / SA_SIGMA) * (0.5 * (nuc + nuj) + (1.0 + SA_CB2) * 0.5 * (w[4] + tj));
-                sad += 0.5 * (qc + fabs(qc)) * S + kf * S / P.frn[f];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; k++) P.M[k * N + c] = m[k];
-        P.lsum[c] = 0.5 * ls;
-        rinf = fmax(fmax(fabs(m[0]), fabs(m[1])), fmax(fabs(m[2]), fabs(m[3])));
-        s0 = m[0] * m[0];
-        if (P.sa) {
-            double Sr, jd;
-            sa_source(w[4], nuc, P.dwall[c], P.vort[c], Sr, jd);
-            double a = P.area[c];
-            double rsa = saR - (SA_CB2 / SA_SIGMA) * w[4] * sagS + a * Sr;
-            P.M[4 * N + c] = rsa;
-            P.sadiag[c] = sad + a * jd;
-            s1 = rsa * rsa;
-        } else {
-            P.M[4 * N + c] = 0.0;
-        }
+    int inst = -1;
+    double rinf = 0.0;
+    if (c < P.nc) {
+        inst = P.cinst[c];
+        if (P.is[inst].halt) inst = -1;
+        else rinf = gather_cell(P, c, inst);
     }
-    red0[threadIdx.x] = s0;
-    red1[threadIdx.x] = s1;
-    red2[threadIdx.x] = rinf;
+    slot_update<false>(&P.is[0].resinf_bits[0], inst, rinf);
+}
+
+// Norm partial sums: block (i, b) sums slice b of instance i's cells in a
+// fixed order (deterministic L2 norms without float atomics).
+template <typename T>
+__global__ __launch_bounds__(256) void k_isum(Params<T> P)
+{
+    __shared__ double a[256], b[256];
+    int i = blockIdx.x / RB, part = blockIdx.x % RB;
+    int lo = P.ioff[i], n = P.ioff[i + 1] - lo;
+    int per = (n + RB - 1) / RB;
+    int s0 = lo + part * per, s1 = min(lo + n, s0 + per);
+    double x = 0.0, y = 0.0;
+    for (int k = s0 + (int)threadIdx.x; k < s1; k += 256) {
+        int c = P.icell[k];
+        x += P.r2[c];
+        y += P.r2[P.nc + c];
+    }
+    a[threadIdx.x] = x;
+    b[threadIdx.x] = y;
     __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
-            red0[threadIdx.x] += red0[threadIdx.x + h];
-            red1[threadIdx.x] += red1[threadIdx.x + h];
-            red2[threadIdx.x] = fmax(red2[threadIdx.x], red2[threadIdx.x + h]);
-        }
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) { a[threadIdx.x] += a[threadIdx.x + h]; b[threadIdx.x] += b[threadIdx.x + h]; }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        P.part[blockIdx.x] = red0[0];
-        P.part[P.max_blocks + blockIdx.x] = red1[0];
-        atomicMax(&P.sc->resinf_bits[slot_of(blockIdx.x)], (unsigned long long)__double_as_longlong(red2[0]));
+        P.ipart[2 * blockIdx.x] = a[0];
+        P.ipart[2 * blockIdx.x + 1] = b[0];
     }
 }
 
-// One block: fixed-order sum of the partials, the Eq.25 CFL law, history.
+// One thread per instance: L2 norms in a fixed order, max norm, the Eq.25
+// CFL law, history.
 template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void k_reduce(Params<T> P, int nblocks)
+__global__ void k_reduce(Params<T> P)
 {
-    __shared__ double a[RED_THREADS], b[RED_THREADS];
-    DevScalars *sc = P.sc;
-    if (sc->halt) return;
-    double s0 = 0.0, s1 = 0.0;
-    for (int i = threadIdx.x; i < nblocks; i += RED_THREADS) {
-        s0 += P.part[i];
-        s1 += P.part[P.max_blocks + i];
-    }
-    a[threadIdx.x] = s0;
-    b[threadIdx.x] = s1;
-    __syncthreads();
-    for (int h = RED_THREADS / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) { a[threadIdx.x] += a[threadIdx.x + h]; b[threadIdx.x] += b[threadIdx.x + h]; }
-        __syncthreads();
-    }
-    double rinf = 0.0, dtf = 0.0;
-    if (threadIdx.x < warpSize) {
-        rinf = slots_max(sc->resinf_bits);
-        dtf = slots_min(sc->dtmin_bits);
-    }
-    if (threadIdx.x == 0) {
-        double l2 = sqrt(a[0]), sal2 = sqrt(b[0]);
-        if (sc->ncommit == 0) {
-            sc->res0 = l2;
-            sc->cfl = P.cfl_init;
+    int h = *P.hist_n;
+    for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
+        InstScalars *s = &P.is[i];
+        if (s->halt) continue;
+        double x = 0.0, y = 0.0;
+        for (int b = 0; b < RB; b++) { x += P.ipart[2 * (i * RB + b)]; y += P.ipart[2 * (i * RB + b) + 1]; }
+        double l2 = sqrt(x), sal2 = sqrt(y);
+        double rinf = slots_max_serial(s->resinf_bits);
+        if (s->ncommit == 0) {
+            s->res0 = l2;
+            s->cfl = P.cfl_init;
         } else if (P.cfl_mode == 0) {
-            double cf = sc->cfl * sc->res_inf_prev / rinf;
+            double cf = s->cfl * s->res_inf_prev / rinf;
             if (!(cf >= P.cfl_min)) cf = P.cfl_min;
             if (cf > P.cfl_max) cf = P.cfl_max;
-            sc->cfl = cf;
+            s->cfl = cf;
         }
-        sc->res_inf_prev = rinf;
-        sc->res_l2 = l2;
-        sc->sa_l2 = sal2;
-        sc->res_inf = rinf;
-        sc->dt_flux = dtf;
-        int h = sc->hist_n;
+        s->res_inf_prev = rinf;
+        s->res_l2 = l2;
+        s->sa_l2 = sal2;
+        s->res_inf = rinf;
+        for (int k = 0; k < NSLOT; k++) s->resinf_bits[k] = 0ull;
         if (h < P.hist_cap) {
-            double *e = P.hist + HIST_W * h;
-            e[0] = l2; e[1] = rinf; e[2] = sc->cfl; e[3] = sc->dt_flux; e[4] = 0.0; e[5] = sal2;
+            double *e = P.hist + (size_t)HIST_W * ((size_t)h * P.ninst + i);
+            e[0] = l2; e[1] = rinf; e[2] = s->cfl; e[3] = s->dt; e[4] = 0.0; e[5] = sal2;
         }
     }
 }
 
 // One wavefront of the forward (FWD) or backward LU-SGS sweep (Eq.22): the
-// cells [c0, c1) are mutually independent.  Forward:
+// cells of a wavefront are mutually independent.  Forward:
 //   dW*_i = D^-1 [M_i - sum_{j<i} (J(W_j, n_ij) dW*_j - lam_ij dW*_j) S_ij / 2];
 // backward, in place:
 //   dW_i = dW*_i - D^-1 sum_{j>i} (J(W_j, n_ij) dW_j - lam_ij dW_j) S_ij / 2,
 // boundary ghosts counted as upper neighbours with the ghost increments of
 // Sec. 2.5 taken from dW*_i.  The SA equation (Eq.31-32) is swept alongside.
 template <typename T, bool FWD>
-__device__ __forceinline__ void sweep_cell(const Params<T> &P, const double *W, T cfl, int c)
+__device__ __forceinline__ void sweep_cell(const Params<T> &P, int c)
 {
     const int N = P.nc;
+    int inst = P.cinst[c];
+    const InstScalars &sc = P.is[inst];
+    if (sc.halt) return;
+    const InstParam &ip = P.ip[inst];
+    const double *W = cur_state(P, inst);
+    const T cfl = T(sc.cfl);
     double w[5];
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
@@ -810,7 +856,7 @@ __device__ __forceinline__ void sweep_cell(const Params<T> &P, const double *W, 
 #pragma unroll
             for (int k = 0; k < 5; k++) { wj[k] = W[k * N + j]; dj[k] = P.dW[k * N + j]; }
         } else {
-            ghost(P, P.fbc[f], w, nx, ny, wj);
+            ghost(ip, P.fbc[f], w, nx, ny, wj);
             ghost_incr<T>(P.fbc[f], dws, T(nx), T(ny), dj);
         }
         T wjt[4] = {T(wj[0]), T(wj[1]), T(wj[2]), T(wj[3])};
@@ -822,8 +868,8 @@ __device__ __forceinline__ void sweep_cell(const Params<T> &P, const double *W, 
             if (FWD) acc[k] -= h * (jv[k] - lam * dj[k]);
             else acc[k] += h * (jv[k] - lam * dj[k]);
         }
-        if (P.sa) {
-            double nuj = (j >= 0) ? P.nu[j] : mu_lam(P, lam_of(wj)) / wj[0];
+        if (ip.sa) {
+            double nuj = (j >= 0) ? P.nu[j] : mu_lam(P.mu_law, ip, lam_of(wj)) / wj[0];
             double qj = (wj[1] * nx + wj[2] * ny) / wj[0];
             double kf = (1.0 / SA_SIGMA) * (0.5 * (nuc + nuj) + (1.0 + SA_CB2) * 0.5 * (w[4] + wj[4]));
             double off = (-0.5 * (qj - fabs(qj)) + kf / P.frn[f]) * P.flen[f];
@@ -835,21 +881,20 @@ __device__ __forceinline__ void sweep_cell(const Params<T> &P, const double *W, 
     if (FWD) {
 #pragma unroll
         for (int k = 0; k < 4; k++) P.dW[k * N + c] = acc[k] / D;
-        P.dW[4 * N + c] = P.sa ? acc[4] / (odt + T(P.sadiag[c])) : T(0);
+        P.dW[4 * N + c] = ip.sa ? acc[4] / (odt + T(P.sadiag[c])) : T(0);
     } else {
 #pragma unroll
         for (int k = 0; k < 4; k++) P.dW[k * N + c] = dws[k] - acc[k] / D;
-        P.dW[4 * N + c] = P.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
+        P.dW[4 * N + c] = ip.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
     }
 }
 
 template <typename T, bool FWD>
 __global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
 {
-    if (P.sc->halt) return;
     int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= c1) return;
-    sweep_cell<T, FWD>(P, cur_state(P), T(P.sc->cfl), c);
+    sweep_cell<T, FWD>(P, c);
 }
 
 // The whole sweep in one workgroup: wavefront after wavefront, separated by
@@ -859,25 +904,22 @@ __global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
 template <typename T, bool FWD>
 __global__ __launch_bounds__(1024) void k_sweep_wg(Params<T> P, const int *lev_off, int nlev)
 {
-    if (P.sc->halt) return;
-    const double *W = cur_state(P);
-    const T cfl = T(P.sc->cfl);
     for (int i = 0; i < nlev; i++) {
         int l = FWD ? i : nlev - 1 - i;
         int c0 = lev_off[l], c1 = lev_off[l + 1];
-        for (int c = c0 + (int)threadIdx.x; c < c1; c += (int)blockDim.x) sweep_cell<T, FWD>(P, W, cfl, c);
+        for (int c = c0 + (int)threadIdx.x; c < c1; c += (int)blockDim.x) sweep_cell<T, FWD>(P, c);
         __syncthreads();
     }
 }
 
-// Per cell: W^{n+1} = W^n + dW into the other state buffer (Eq.17),
-// nu~ clipped at 0, positivity check, Eq.40.
+// Per cell: W^{n+1} = W^n + dW into the instance's other state buffer
+// (Eq.17), nu~ clipped at 0, positivity check, Eq.40.
 template <typename T>
-__device__ __forceinline__ void update_cell(const Params<T> &P, int c, double &e40, int &bad)
+__device__ __forceinline__ double update_cell(const Params<T> &P, int c, int inst)
 {
     const int N = P.nc;
-    const double *W = cur_state(P);
-    double *Wn = (P.sc->ncommit & 1) ? P.Wa : P.Wb;
+    const double *W = cur_state(P, inst);
+    double *Wn = (P.is[inst].ncommit & 1) ? P.Wa : P.Wb;
     double w[5], num = 0.0, den = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
@@ -888,59 +930,60 @@ __device__ __forceinline__ void update_cell(const Params<T> &P, int c, double &e
         Wn[k * N + c] = w[k];
     }
     double t = W[4 * N + c];
-    if (P.sa) t = fmax(t + double(P.dW[4 * N + c]), 0.0);
+    if (P.ip[inst].sa) t = fmax(t + double(P.dW[4 * N + c]), 0.0);
     Wn[4 * N + c] = t;
     double p = w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0];
-    if (!(w[0] > 0.0) || !(p > 0.0) || !isfinite(t) || !isfinite(p)) bad = 1;
+    if (!(w[0] > 0.0) || !(p > 0.0) || !isfinite(t) || !isfinite(p)) atomicOr(&P.is[inst].bad, 1);
     double e = sqrt(num / den);
-    e40 = isfinite(e) ? e : 0.0;
+    return isfinite(e) ? e : 0.0;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_update(Params<T> P)
 {
-    if (P.sc->halt) return;
     int c = blockIdx.x * blockDim.x + threadIdx.x;
+    int inst = -1;
     double e = 0.0;
-    int bad = 0;
-    if (c < P.nc) update_cell(P, c, e, bad);
-    e = wave_max(e);
-    bad = wave_or(bad);
-    if ((threadIdx.x & (warpSize - 1)) == 0) {
-        int wv = (blockIdx.x * blockDim.x + threadIdx.x) / warpSize;
-        if (e > 0.0) atomicMax(&P.sc->e40_bits[slot_of(wv)], (unsigned long long)__double_as_longlong(e));
-        if (bad) atomicOr(&P.sc->bad, 1);
+    if (c < P.nc) {
+        inst = P.cinst[c];
+        if (P.is[inst].halt) inst = -1;
+        else e = update_cell(P, c, inst);
     }
+    slot_update<false>(&P.is[0].e40_bits[0], inst, e);
 }
 
-
+// One thread per instance: accept (flip the state buffer) or reject and
+// freeze the instance; reset the slots for the next iteration.
 template <typename T>
 __global__ void k_commit(Params<T> P)
 {
-    DevScalars *sc = P.sc;
-    if (sc->halt) return;
-    double e40 = slots_max(sc->e40_bits);
-    if (threadIdx.x != 0) return;
-    sc->e40 = e40;
-    int h = sc->hist_n;
-    if (h < P.hist_cap) P.hist[HIST_W * h + 4] = e40;
-    sc->hist_n = h + 1;
-    if (sc->bad) {
-        sc->halt = 1;
-    } else {
-        sc->ncommit += 1;
+    int h = *P.hist_n;
+    for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
+        InstScalars *s = &P.is[i];
+        if (s->halt) continue;
+        double e40 = slots_max_serial(s->e40_bits);
+        s->e40 = e40;
+        if (h < P.hist_cap) P.hist[(size_t)HIST_W * ((size_t)h * P.ninst + i) + 4] = e40;
+        if (s->bad) s->halt = 1;
+        else s->ncommit += 1;
+        for (int k = 0; k < NSLOT; k++) {
+            s->dtmin_bits[k] = 0x7ff0000000000000ull;
+            s->e40_bits[k] = 0ull;
+        }
     }
-    reset_slots(sc);
+    __syncthreads();
+    if (threadIdx.x == 0) *P.hist_n = h + 1;
 }
 
-// exact distance from each centroid to the nearest wall segment
-__global__ __launch_bounds__(256) void k_wall_distance(int nc, const double *xc, const double *yc, int nw,
-                                                       const double *seg, double *d)
+// exact distance from each centroid to the nearest wall segment of its instance
+__global__ __launch_bounds__(256) void k_wall_distance(int nc, const double *xc, const double *yc, const int *cinst,
+                                                       const int *woff, const double *seg, double *d)
 {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
+    int i = cinst[c];
     double px = xc[c], py = yc[c], best = 1e300;
-    for (int s = 0; s < nw; s++) {
+    for (int s = woff[i]; s < woff[i + 1]; s++) {
         double ax = seg[4 * s], ay = seg[4 * s + 1], bx = seg[4 * s + 2], by = seg[4 * s + 3];
         double ex = bx - ax, ey = by - ay;
         double t = ((px - ax) * ex + (py - ay) * ey) / (ex * ex + ey * ey);
@@ -960,42 +1003,59 @@ __global__ void k_gather_faces(int n, const int *faces, const double *flux, int 
     for (int k = 0; k < 4; k++) out[4 * i + k] = flux[k * nf + f];
 }
 
-__global__ void k_set_state(int nc, double w0, double w1, double w2, double w3, double w4, double *W)
+__global__ void k_fill_instance(int n, const int *cells, int nc, double w0, double w1, double w2, double w3,
+                                double w4, double *W)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
+    int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int c = cells[u];
     W[c] = w0; W[nc + c] = w1; W[2 * nc + c] = w2; W[3 * nc + c] = w3; W[4 * nc + c] = w4;
+}
+
+// to_instance: dst (5 x nc, internal order) <- src (5 x n, upload order);
+// else the reverse
+__global__ void k_copy_instance(int n, const int *cells, int nc, const double *src, double *dst, int to_instance)
+{
+    int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int c = cells[u];
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+        if (to_instance) dst[(size_t)k * nc + c] = src[(size_t)k * n + u];
+        else dst[(size_t)k * n + u] = src[(size_t)k * nc + c];
+    }
 }
 
 // ---------------------------------------------------------------- launchers
 
 static inline int nblk(int n, int b) { return (n + b - 1) / b; }
 
-template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int mode)
+template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int mode, int inst)
 {
-    hipLaunchKernelGGL(k_reset<T>, dim3(1), dim3(1), 0, L.s, P, mode);
+    hipLaunchKernelGGL(k_reset<T>, dim3(1), dim3(64), 0, L.s, P, mode, inst);
 }
 template <typename T> void launch_prep(const Launch &L, const Params<T> &P)
 {
-    hipLaunchKernelGGL(k_prep<T>, dim3(nblk(P.nc, L.block)), dim3(L.block), 0, L.s, P);
+    hipLaunchKernelGGL(k_prep<T>, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), 0, L.s, P);
+    hipLaunchKernelGGL(k_dt<T>, dim3(1), dim3(64), 0, L.s, P);
 }
 template <typename T> void launch_flux(const Launch &L, const Params<T> &P)
 {
-    hipLaunchKernelGGL(k_flux<T>, dim3(nblk(P.nf, L.block)), dim3(L.block), 0, L.s, P);
+    hipLaunchKernelGGL(k_flux<T>, dim3(nblk(P.nf, L.block[1])), dim3(L.block[1]), 0, L.s, P);
 }
 template <typename T> void launch_gather(const Launch &L, const Params<T> &P)
 {
-    // the shared reduction assumes 256 threads
-    hipLaunchKernelGGL(k_gather<T>, dim3(nblk(P.nc, 256)), dim3(256), 0, L.s, P);
+    hipLaunchKernelGGL(k_gather<T>, dim3(nblk(P.nc, L.block[2])), dim3(L.block[2]), 0, L.s, P);
 }
 template <typename T> void launch_reduce(const Launch &L, const Params<T> &P)
 {
-    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(RED_THREADS), 0, L.s, P, nblk(P.nc, 256));
+    hipLaunchKernelGGL(k_isum<T>, dim3(P.ninst * RB), dim3(256), 0, L.s, P);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(64), 0, L.s, P);
 }
 template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd)
 {
     if (c1 <= c0) return;
-    dim3 g(nblk(c1 - c0, L.block)), b(L.block);
+    dim3 g(nblk(c1 - c0, L.block[3])), b(L.block[3]);
     if (fwd) hipLaunchKernelGGL((k_sweep<T, true>), g, b, 0, L.s, P, c0, c1);
     else hipLaunchKernelGGL((k_sweep<T, false>), g, b, 0, L.s, P, c0, c1);
 }
@@ -1006,37 +1066,45 @@ template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, 
 }
 template <typename T> void launch_update(const Launch &L, const Params<T> &P)
 {
-    hipLaunchKernelGGL(k_update<T>, dim3(nblk(P.nc, L.block)), dim3(L.block), 0, L.s, P);
+    hipLaunchKernelGGL(k_update<T>, dim3(nblk(P.nc, L.block[4])), dim3(L.block[4]), 0, L.s, P);
 }
 template <typename T> void launch_commit(const Launch &L, const Params<T> &P)
 {
     hipLaunchKernelGGL(k_commit<T>, dim3(1), dim3(64), 0, L.s, P);
 }
-void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, int nw, const double *wseg,
-                          double *dwall)
+void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
+                          const int *woff, const double *wseg, double *dwall)
 {
-    hipLaunchKernelGGL(k_wall_distance, dim3(nblk(nc, 256)), dim3(256), 0, L.s, nc, xc, yc, nw, wseg, dwall);
+    hipLaunchKernelGGL(k_wall_distance, dim3(nblk(nc, 256)), dim3(256), 0, L.s, nc, xc, yc, cinst, woff, wseg, dwall);
 }
 void launch_gather_faces(const Launch &L, int n, const int *faces, const double *flux, int nf, double *out)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_gather_faces, dim3(nblk(n, 256)), dim3(256), 0, L.s, n, faces, flux, nf, out);
 }
-void launch_set_state(const Launch &L, int nc, const double *Winf, double *W)
+void launch_fill_instance(const Launch &L, int n, const int *cells, int nc, const double *Winf, double *W)
 {
-    hipLaunchKernelGGL(k_set_state, dim3(nblk(nc, 256)), dim3(256), 0, L.s, nc, Winf[0], Winf[1], Winf[2], Winf[3],
-                       Winf[4], W);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_instance, dim3(nblk(n, 256)), dim3(256), 0, L.s, n, cells, nc, Winf[0], Winf[1],
+                       Winf[2], Winf[3], Winf[4], W);
+}
+void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, const double *src, double *dst,
+                          bool to_instance)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_copy_instance, dim3(nblk(n, 256)), dim3(256), 0, L.s, n, cells, nc, src, dst,
+                       to_instance ? 1 : 0);
 }
 
-#define INST(T)                                                                               \
-    template void launch_reset<T>(const Launch &, const Params<T> &, int);                    \
-    template void launch_prep<T>(const Launch &, const Params<T> &);                          \
-    template void launch_flux<T>(const Launch &, const Params<T> &);                          \
-    template void launch_gather<T>(const Launch &, const Params<T> &);                        \
-    template void launch_reduce<T>(const Launch &, const Params<T> &);                        \
-    template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, bool);         \
-    template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool); \
-    template void launch_update<T>(const Launch &, const Params<T> &);                        \
+#define INST(T)                                                                                    \
+    template void launch_reset<T>(const Launch &, const Params<T> &, int, int);                    \
+    template void launch_prep<T>(const Launch &, const Params<T> &);                               \
+    template void launch_flux<T>(const Launch &, const Params<T> &);                               \
+    template void launch_gather<T>(const Launch &, const Params<T> &);                             \
+    template void launch_reduce<T>(const Launch &, const Params<T> &);                             \
+    template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, bool);              \
+    template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool);   \
+    template void launch_update<T>(const Launch &, const Params<T> &);                             \
     template void launch_commit<T>(const Launch &, const Params<T> &);
 INST(double)
 INST(float)

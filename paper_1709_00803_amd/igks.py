@@ -68,6 +68,19 @@ _SIGS = {
     "igks_get_wall_loads": (C.c_int, [_P, _DP, _DP, _DP, _DP, _DP]),
     "igks_set_profiling": (C.c_int, [_P, C.c_int]),
     "igks_get_kernel_times": (C.c_int, [_P, _DP]),
+    "igks_batch_create": (C.c_int, [C.POINTER(_P), C.POINTER(igks_options), _P, C.c_int32]),
+    "igks_batch_mesh_upload": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, C.c_int32, _IP, _IP, C.c_int32, _IP, _IP]),
+    "igks_batch_mesh_info": (C.c_int, [_P, C.c_int32, _IP, _IP, _IP]),
+    "igks_batch_set_freestream": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "igks_batch_get_residual": (C.c_int, [_P, C.c_int32, C.POINTER(igks_residual)]),
+    "igks_batch_get_history": (C.c_int, [_P, C.c_int32, _DP, C.c_int32, _IP]),
+    "igks_batch_get_state": (C.c_int, [_P, C.c_int32, _DP]),
+    "igks_batch_set_state": (C.c_int, [_P, C.c_int32, _DP, C.POINTER(igks_scalars)]),
+    "igks_batch_compute_residual": (C.c_int, [_P, C.c_int32, _DP]),
+    "igks_batch_get_wall_loads": (C.c_int, [_P, C.c_int32, _DP, _DP, _DP, _DP, _DP]),
+    "igks_batch_status": (C.c_int, [_P, C.c_int32, _IP]),
+    "igks_autotune": (C.c_int, [_P, C.c_int32, _IP]),
+    "igks_get_schedule": (C.c_int, [_P, _IP]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -104,33 +117,36 @@ def default_options(**kw) -> igks_options:
     return o
 
 
-class Solver:
-    """One mesh + flow condition on one GPU.
+def _mesh_args(mesh):
+    keep = (_d(mesh.xy.reshape(-1)), _i(mesh.cell_ptr), _i(mesh.cell_nodes), _i(mesh.bface_nodes.reshape(-1)),
+            _i(mesh.bface_tag))
+    (_, pxy), (_, pcp), (_, pcn), (_, pbn), (_, pbt) = keep
+    return keep, (mesh.n_nodes, pxy, mesh.n_cells, pcp, pcn, mesh.n_bfaces, pbn, pbt)
 
-    ``mesh`` needs xy, cell_ptr, cell_nodes, bface_nodes, bface_tag (see
-    meshgen.Mesh).  ``stream``: a torch.cuda.Stream (default: a new one).
-    """
 
-    def __init__(self, mesh, options: igks_options | None = None, stream=None, device="cuda", **kw):
+KERNEL_CLASSES = ("prep", "flux", "gather", "reduce", "sweep_fwd", "sweep_bwd", "update")
+
+
+class _Context:
+    """Owns an igks context, its stream and its device workspace."""
+
+    def _open(self, n_inst, options, stream, device, kw):
         import torch
         self.torch = torch
         self.opt = options or default_options(**kw)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         self.ctx = _P()
-        self._chk(igks_create(C.byref(self.ctx), C.byref(self.opt), _P(self.stream.cuda_stream)))
-        xy, pxy = _d(mesh.xy.reshape(-1))
-        cp, pcp = _i(mesh.cell_ptr)
-        cn, pcn = _i(mesh.cell_nodes)
-        bn, pbn = _i(mesh.bface_nodes.reshape(-1))
-        bt, pbt = _i(mesh.bface_tag)
-        self._chk(igks_mesh_upload(self.ctx, mesh.n_nodes, pxy, mesh.n_cells, pcp, pcn, mesh.n_bfaces, pbn, pbt))
+        self._device = device
+        self._chk(igks_batch_create(C.byref(self.ctx), C.byref(self.opt), _P(self.stream.cuda_stream), n_inst))
+
+    def _bind(self):
         nc, nf, nw, nl = (C.c_int32() for _ in range(4))
         self._chk(igks_mesh_info(self.ctx, C.byref(nc), C.byref(nf), C.byref(nw), C.byref(nl)))
-        self.n, self.nf, self.nwall, self.nlev = nc.value, nf.value, nw.value, nl.value
+        self.total_cells, self.total_faces, self.total_wall, self.nlev = nc.value, nf.value, nw.value, nl.value
         sz = C.c_size_t()
         self._chk(igks_workspace_size(self.ctx, C.byref(sz)))
         self.ws_bytes = sz.value
-        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        self.workspace = self.torch.empty(self.ws_bytes + 256, dtype=self.torch.uint8, device=self._device)
         base = self.workspace.data_ptr()
         aligned = (base + 255) // 256 * 256
         self._chk(igks_bind_workspace(self.ctx, _P(aligned), self.ws_bytes))
@@ -142,7 +158,7 @@ class Solver:
         return rc
 
     def close(self):
-        if self.ctx:
+        if getattr(self, "ctx", None):
             igks_destroy(self.ctx)
             self.ctx = _P()
 
@@ -152,14 +168,47 @@ class Solver:
         except Exception:
             pass
 
-    def set_freestream(self, mach, alpha_deg, reynolds, nut_ratio=-1.0):
-        self._chk(igks_set_freestream(self.ctx, mach, alpha_deg, reynolds, nut_ratio))
-
     def iterate(self, n):
         done = C.c_int32(0)
         rc = igks_iterate(self.ctx, n, C.byref(done))
         self._chk(rc)
         return done.value
+
+    def set_profiling(self, on=True):
+        self._chk(igks_set_profiling(self.ctx, 1 if on else 0))
+
+    def kernel_times(self):
+        t = np.zeros(7)
+        self._chk(igks_get_kernel_times(self.ctx, t.ctypes.data_as(_DP)))
+        return dict(zip(KERNEL_CLASSES, t))
+
+    def autotune(self, iters=10):
+        s = np.zeros(6, dtype=np.int32)
+        self._chk(igks_autotune(self.ctx, iters, s.ctypes.data_as(_IP)))
+        return s
+
+    def schedule(self):
+        s = np.zeros(6, dtype=np.int32)
+        self._chk(igks_get_schedule(self.ctx, s.ctypes.data_as(_IP)))
+        return s
+
+
+class Solver(_Context):
+    """One mesh + flow condition on one GPU.
+
+    ``mesh`` needs xy, cell_ptr, cell_nodes, bface_nodes, bface_tag (see
+    meshgen.Mesh).  ``stream``: a torch.cuda.Stream (default: a new one).
+    """
+
+    def __init__(self, mesh, options: igks_options | None = None, stream=None, device="cuda", **kw):
+        self._open(1, options, stream, device, kw)
+        keep, args = _mesh_args(mesh)
+        self._chk(igks_mesh_upload(self.ctx, *args))
+        self._bind()
+        self.n, self.nf, self.nwall = self.total_cells, self.total_faces, self.total_wall
+
+    def set_freestream(self, mach, alpha_deg, reynolds, nut_ratio=-1.0):
+        self._chk(igks_set_freestream(self.ctx, mach, alpha_deg, reynolds, nut_ratio))
 
     def residual(self) -> dict:
         r = igks_residual()
@@ -199,10 +248,63 @@ class Solver:
         n = self.nwall
         return dict(cl=cl.value, cd=cd.value, cf=cf[:n], cp=cp[:n], xw=xw[:n])
 
-    def set_profiling(self, on=True):
-        self._chk(igks_set_profiling(self.ctx, 1 if on else 0))
 
-    def kernel_times(self):
-        t = np.zeros(7)
-        self._chk(igks_get_kernel_times(self.ctx, t.ctypes.data_as(_DP)))
-        return dict(zip(("prep", "flux", "gather", "reduce", "sweep_fwd", "sweep_bwd", "update"), t))
+class BatchSolver(_Context):
+    """Many independent instances (meshes of any sizes, one flow condition
+    each) iterated together in the same kernel launches."""
+
+    def __init__(self, meshes, options: igks_options | None = None, stream=None, device="cuda", **kw):
+        self._open(len(meshes), options, stream, device, kw)
+        self.ninst = len(meshes)
+        for i, m in enumerate(meshes):
+            keep, args = _mesh_args(m)
+            self._chk(igks_batch_mesh_upload(self.ctx, i, *args))
+        self._bind()
+        self.n, self.nf, self.nwall = [], [], []
+        for i in range(self.ninst):
+            nc, nf, nw = (C.c_int32() for _ in range(3))
+            self._chk(igks_batch_mesh_info(self.ctx, i, C.byref(nc), C.byref(nf), C.byref(nw)))
+            self.n.append(nc.value)
+            self.nf.append(nf.value)
+            self.nwall.append(nw.value)
+
+    def set_freestream(self, i, mach, alpha_deg, reynolds, nut_ratio=-1.0):
+        self._chk(igks_batch_set_freestream(self.ctx, i, mach, alpha_deg, reynolds, nut_ratio))
+
+    def status(self, i) -> bool:
+        h = C.c_int32()
+        self._chk(igks_batch_status(self.ctx, i, C.byref(h)))
+        return bool(h.value)
+
+    def residual(self, i) -> dict:
+        r = igks_residual()
+        self._chk(igks_batch_get_residual(self.ctx, i, C.byref(r)))
+        return r.as_dict()
+
+    def history(self, i, max_entries=1 << 20):
+        out = np.zeros((max_entries, HIST_W))
+        n = C.c_int32()
+        self._chk(igks_batch_get_history(self.ctx, i, out.ctypes.data_as(_DP), max_entries, C.byref(n)))
+        return out[:n.value]
+
+    def get_state(self, i):
+        W = np.zeros((5, self.n[i]))
+        self._chk(igks_batch_get_state(self.ctx, i, W.ctypes.data_as(_DP)))
+        return W
+
+    def set_state(self, i, W, scalars: igks_scalars | None = None):
+        W, p = _d(np.asarray(W).reshape(5, self.n[i]))
+        self._chk(igks_batch_set_state(self.ctx, i, p, C.byref(scalars) if scalars is not None else None))
+
+    def compute_residual(self, i):
+        M = np.zeros((5, self.n[i]))
+        self._chk(igks_batch_compute_residual(self.ctx, i, M.ctypes.data_as(_DP)))
+        return M
+
+    def wall_loads(self, i):
+        cl, cd = C.c_double(), C.c_double()
+        nw = self.nwall[i]
+        cf, cp, xw = (np.zeros(max(nw, 1)) for _ in range(3))
+        P = lambda a: a.ctypes.data_as(_DP)
+        self._chk(igks_batch_get_wall_loads(self.ctx, i, C.byref(cl), C.byref(cd), P(cf), P(cp), P(xw)))
+        return dict(cl=cl.value, cd=cd.value, cf=cf[:nw], cp=cp[:nw], xw=xw[:nw])

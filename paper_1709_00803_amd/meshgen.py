@@ -644,3 +644,66 @@ def workload(name: str) -> Mesh:
     out, _, _ = colour_order(m)
     out.meta["workload"] = name
     return out
+
+
+# ---------------------------------------------------------------------------
+# Batched sweep: many seeded instances of uneven size
+# ---------------------------------------------------------------------------
+
+def _growth_for(h1: float, n: int, height: float) -> float:
+    """Geometric growth rate g with h1 (g^n - 1) / (g - 1) = height."""
+    if h1 * n >= height:
+        return 1.0 + 1e-9
+    lo, hi = 1.0 + 1e-9, 3.0
+    for _ in range(100):
+        g = 0.5 * (lo + hi)
+        if h1 * (g ** n - 1.0) / (g - 1.0) < height:
+            lo = g
+        else:
+            hi = g
+    return 0.5 * (lo + hi)
+
+
+def _first_height(re: float) -> float:
+    """First wall-cell height (chord units) that resolves the viscous
+    sublayer for a Reynolds number re: ~1e-4 at 5e3, 1e-6 and below above
+    about 3e6."""
+    return float(np.clip(1e-4 * (5000.0 / re) ** 0.75, 1e-6, 1e-3))
+
+
+def batch_instance(b: int, base_seed: int = 1000, n_min: float = 5e3, n_max: float = 2e5):
+    """Instance b of the batched sweep: (mesh, (Ma, alpha_deg, Re, nut_ratio)).
+
+    Draws from default_rng(base_seed + b): a target cell count log-uniform in
+    [n_min, n_max], Ma ~ U[0.1, 0.6], alpha ~ U[-4, 12] deg (airfoils;
+    plates at 0), Re log-uniform in [1e4, 1e7], SA (nu~/nu = 3) iff
+    Re > 1e5.  Even b: flat plate (nx = 2 ny quads); odd b: Joukowski hybrid
+    (wall points ~0.64 sqrt(N), quad layers ~0.15 sqrt(N) reaching 0.05 chord,
+    triangles for the rest).  Colour-ordered.
+    """
+    rng = np.random.default_rng(base_seed + b)
+    n = float(np.exp(rng.uniform(math.log(n_min), math.log(n_max))))
+    ma = float(rng.uniform(0.1, 0.6))
+    alpha = float(rng.uniform(-4.0, 12.0))
+    re = float(np.exp(rng.uniform(math.log(1e4), math.log(1e7))))
+    nut = 3.0 if re > 1e5 else -1.0
+    h1 = _first_height(re)
+    if b % 2 == 0:
+        ny = max(4, int(round(math.sqrt(n / 2.0))))
+        nx = max(8, int(round(n / ny)))
+        m = flat_plate(nx=nx, ny=ny, dy1=h1, ratio=_growth_for(h1, ny, 0.3))
+        alpha = 0.0
+    else:
+        nw = max(32, int(round(0.64 * math.sqrt(n) / 8.0)) * 8)
+        nl = max(6, int(round(0.15 * math.sqrt(n))))
+        m = joukowski_hybrid(nw, nl, h1, _growth_for(h1, nl, 0.05), seed=base_seed + b,
+                             target_cells=int(n))
+    out, _, _ = colour_order(m)
+    out.meta.update(batch_index=b, target_cells=int(n))
+    return out, (ma, alpha, re, nut)
+
+
+def batch(n_inst: int = 64, base_seed: int = 1000, n_min: float = 5e3, n_max: float = 2e5):
+    """The batched sweep: lists of meshes and flow conditions."""
+    items = [batch_instance(b, base_seed, n_min, n_max) for b in range(n_inst)]
+    return [m for m, _ in items], [f for _, f in items]

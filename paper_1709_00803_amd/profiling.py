@@ -4,6 +4,7 @@ collections) into the short text / JSON files kept under profiles/.
     python -m paper_1709_00803_amd.profiling stats  <kernel_stats.csv> <out.txt> "<command>"
     python -m paper_1709_00803_amd.profiling traffic <workload> <fetch.csv> <write.csv> \
         <fetch_copy.csv> <write_copy.csv> <copy_bytes> <out.json> "<command>"
+    python -m paper_1709_00803_amd.profiling copy     (calibration: 5 device copies of 256 MiB)
 """
 import collections
 import csv
@@ -77,9 +78,26 @@ def traffic(workload, fetch_csv, write_csv, fetch_copy_csv, write_copy_csv, copy
     return out
 
 
+COPY_BYTES = 256 * 1024 * 1024
+
+
+def copy_calibration(reps=5):
+    """Device-to-device copies of COPY_BYTES: the kernel whose FETCH_SIZE and
+    WRITE_SIZE counters give the scale from counter KiB to HBM bytes."""
+    import torch
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"copy calibration: {reps} copies of {COPY_BYTES // 1024} KiB", flush=True)
+
+
 if __name__ == "__main__":
     a = sys.argv[1:]
-    if a and a[0] == "stats":
+    if a and a[0] == "copy":
+        copy_calibration()
+    elif a and a[0] == "stats":
         print(stats(a[1], a[2], a[3]))
     elif a and a[0] == "traffic":
         print(json.dumps(traffic(a[1], a[2], a[3], a[4], a[5], float(a[6]), a[7], a[8]), indent=1))

@@ -1,0 +1,148 @@
+"""GPU batches: many instances of uneven size iterated together in the same
+launches.  Instance i of a batch must give bitwise the iterates of the same
+instance run alone (the per-cell arithmetic, the per-instance reductions and
+their order do not depend on the other instances); each instance's residual
+matches the FP64 oracle to the same 1e-12-of-gross bar as single runs; the
+autotuner leaves state and scalars bitwise as they were and the launch
+schedule it picks does not change any result.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pyoracle as po
+from paper_1709_00803_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def igks():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1709_00803_amd import igks as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    """Six seeded instances (plates and Joukowski hybrids, 600-2500 cells,
+    laminar and SA) of the batched sweep recipe, shrunk in size."""
+    return mg.batch(6, n_min=600, n_max=2500)
+
+
+def run_batch(igks, meshes, flows, n, **opt):
+    b = igks.BatchSolver(meshes, **opt)
+    for i, f in enumerate(flows):
+        b.set_freestream(i, *f)
+    b.iterate(n)
+    return b
+
+
+def test_batch_instance_equals_single_run(igks, small_batch):
+    meshes, flows = small_batch
+    say("batch sizes", [m.n_cells for m in meshes], "flows", flows)
+    for prec in ("fp64", "mixed"):
+        p = igks.IGKS_MIXED if prec == "mixed" else igks.IGKS_FP64
+        b = run_batch(igks, meshes, flows, 12, precision=p, cfl_init=5.0, chunk=4)
+        say(f"[{prec}] batch: {b.total_cells} cells, {b.nlev} wavefronts")
+        for i, (m, f) in enumerate(zip(meshes, flows)):
+            s = igks.Solver(m, precision=p, cfl_init=5.0, chunk=4)
+            s.set_freestream(*f)
+            s.iterate(12)
+            Wb, Ws = b.get_state(i), s.get_state()
+            rb, rs = b.residual(i), s.residual()
+            say(f"[{prec}] inst {i}: max|dW| {np.abs(Wb - Ws).max():.3e} res {rb['res_l2']:.6e} "
+                f"{rs['res_l2']:.6e}")
+            assert np.array_equal(Wb, Ws), (prec, i)
+            assert rb == rs, (prec, i)
+            assert np.array_equal(b.history(i), s.history())
+            assert not b.status(i)
+
+
+def test_batch_residual_parity(igks, small_batch):
+    meshes, flows = small_batch
+    b = igks.BatchSolver(meshes)
+    for i, f in enumerate(flows):
+        b.set_freestream(i, *f)
+    for i, (m, f) in enumerate(zip(meshes, flows)):
+        o = po.Oracle(m)
+        o.set_freestream(*f)
+        c = o.cells()
+        W = o.get_state()
+        rng = np.random.default_rng(i)
+        W[0] *= 1 + 0.05 * np.sin(2 * c["xc"] + rng.uniform()) * np.cos(3 * c["yc"])
+        W[1] += 0.04 * np.cos(3 * c["xc"]) * np.sin(2 * c["yc"] + rng.uniform())
+        W[3] *= 1 + 0.03 * np.sin(c["xc"] + c["yc"])
+        o.set_state(W)
+        b.set_state(i, W)
+        Mo, G = o.compute_residual()
+        Mg = b.compute_residual(i)
+        err = (np.abs(Mg[:4] - Mo[:4]) / G).max()
+        say(f"[batch residual] inst {i} ({m.meta['kind']}, {m.n_cells} cells, sa={f[3] >= 0}) max|dM|/gross {err:.3e}")
+        assert err <= 1e-12
+        if f[3] >= 0:
+            e4 = np.abs(Mg[4] - Mo[4]).max() / np.abs(Mo[4]).max()
+            assert e4 <= 1e-10
+        lo, lg = o.wall_loads(), b.wall_loads(i)
+        assert abs(lg["cd"] - lo["cd"]) <= 1e-11 * max(abs(lo["cd"]), 1e-300)
+        assert np.allclose(lg["cf"], lo["cf"], rtol=1e-10, atol=1e-12)
+
+
+def test_autotune_keeps_state_and_results(igks, small_batch):
+    meshes, flows = small_batch
+    ref = run_batch(igks, meshes, flows, 16, precision=igks.IGKS_MIXED, cfl_init=5.0, chunk=4)
+    b = run_batch(igks, meshes, flows, 8, precision=igks.IGKS_MIXED, cfl_init=5.0, chunk=4)
+    before = [b.get_state(i) for i in range(len(meshes))]
+    res_before = [b.residual(i) for i in range(len(meshes))]
+    sched = b.autotune(3)
+    say("autotuned schedule", sched.tolist())
+    assert set(sched[:5].tolist()) <= {64, 128, 256} and sched[5] in (1, 2)
+    assert np.array_equal(sched, b.schedule())
+    for i in range(len(meshes)):
+        assert np.array_equal(b.get_state(i), before[i])
+        assert b.residual(i) == res_before[i]
+    b.iterate(8)
+    for i in range(len(meshes)):
+        assert np.array_equal(b.get_state(i), ref.get_state(i)), i
+
+
+def test_batch_graph_chunks_match_direct(igks, small_batch):
+    meshes, flows = small_batch
+    a = run_batch(igks, meshes[:3], flows[:3], 9, cfl_init=5.0, chunk=0)
+    g = run_batch(igks, meshes[:3], flows[:3], 9, cfl_init=5.0, chunk=3)
+    for i in range(3):
+        assert np.array_equal(a.get_state(i), g.get_state(i))
+
+
+def test_batch_set_state_isolated(igks, small_batch):
+    """Setting one instance's state (and restarting its counter) leaves the
+    others untouched; a checkpoint round trip resumes bitwise."""
+    meshes, flows = small_batch
+    b = run_batch(igks, meshes[:3], flows[:3], 6, cfl_init=5.0, chunk=3)
+    W1 = b.get_state(1)
+    sc = igks.igks_scalars()
+    r = b.residual(1)
+    W0, W2 = b.get_state(0), b.get_state(2)
+    b.set_freestream(0, *flows[0])
+    assert np.array_equal(b.get_state(1), W1) and np.array_equal(b.get_state(2), W2)
+    assert b.residual(0)["iteration"] == 0 and r["iteration"] == 6
+    # resume instance 1 from a host checkpoint in a fresh single context
+    s = igks.Solver(meshes[1], cfl_init=5.0, chunk=3)
+    s.set_freestream(*flows[1])
+    s.iterate(6)
+    sc = s.scalars()
+    Wck = s.get_state()
+    assert np.array_equal(Wck, W1)
+    s2 = igks.Solver(meshes[1], cfl_init=5.0, chunk=3)
+    s2.set_freestream(*flows[1])
+    s2.set_state(Wck, sc)
+    s2.iterate(3)
+    s.iterate(3)
+    assert np.array_equal(s2.get_state(), s.get_state())
