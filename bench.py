@@ -31,13 +31,19 @@ WORKLOADS = {
     "jouk2m": dict(flow=(0.15, 4.0, 6e6, 3.0), desc="Joukowski hybrid, 2048 wall pts, 90 quad layers (1e-6, 1.10), "
                                                     "Ma 0.15 Re 6e6 alpha 4, SA nu~/nu = 3"),
     "plate64x32": dict(flow=(0.3, 0.0, 1e4, -1.0), desc="laminar flat plate 64x32 quads, Ma 0.3 Re_L 1e4"),
+    "batch64": dict(flow=None, desc="64 seeded instances (default_rng(1000+b)): even b flat plate, odd b Joukowski "
+                                    "hybrid, cells log-uniform 5e3-2e5, Ma U[0.1,0.6], alpha U[-4,12] (airfoils), "
+                                    "Re log-uniform 1e4-1e7, SA iff Re>1e5; one graph launch per chunk, autotuned"),
 }
+# plate variants of the batched time-to-1e-10 comparison: (Ma, Re_L)
+DROP_BATCH = [(0.2, 5e3), (0.25, 8e3), (0.3, 1e4), (0.35, 1.5e4), (0.4, 2e4), (0.3, 6e3), (0.2, 1.2e4), (0.4, 1e4)]
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 FP64_VALU_PEAK_TFS = 78.6   # MI355X FP64 vector
-# FP64 operations per face of k_flux, counted with rocprofv3
-# (SQ_INSTS_VALU_FMA_F64 x 2 + MUL + ADD + TRANS, per wave / faces per wave)
-FLUX_FLOP_PER_FACE = 3918.0
+# FP64 operations per face of k_flux, counted with rocprofv3: FP64 VALU
+# instructions per wave (2 x FMA + MUL + ADD + TRANS); one face per lane, so
+# this is also the operation count of one face.
+FLUX_FLOP_PER_FACE = 3819.0
 KSRC = os.path.join(ROOT, "paper_1709_00803_amd", "csrc", "igks_kernels.hip")
 
 
@@ -100,22 +106,72 @@ def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000):
                 cell_updates_per_s=m.n_cells * it / dt)
 
 
-def run_cpu_baseline(mesh, flow, budget_s=12.0, max_it=60):
-    from oracle import pyoracle as po
-    o = po.Oracle(mesh)
-    o.set_freestream(*flow)
-    o.iterate(1)     # the impulsive-start iteration, untimed
+def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000):
+    """Eight plate flow conditions (DROP_BATCH) to a `target` drop: one mixed-
+    precision batch against the eight FP64 single runs one after another."""
+    import torch
+    m = mg.flat_plate()
+    flows = [(ma, 0.0, re, -1.0) for ma, re in DROP_BATCH]
+    b = igks.BatchSolver([m] * len(flows), precision=igks.IGKS_MIXED, cfl_init=10.0, chunk=100)
+    for i, f in enumerate(flows):
+        b.set_freestream(i, *f)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    it = 0
-    while it < max_it:
-        o.iterate(1)
-        it += 1
-        if time.perf_counter() - t0 > budget_s:
+    it, first = 0, [None] * len(flows)
+    while it < max_it and any(x is None for x in first):
+        b.iterate(100)
+        it += 100
+        for i in range(len(flows)):
+            if first[i] is None and b.residual(i)["res_drop"] <= target:
+                first[i] = it
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t_seq, its_seq = 0.0, []
+    for f in flows:
+        s = igks.Solver(m, precision=igks.IGKS_FP64, cfl_init=10.0, chunk=100)
+        s.set_freestream(*f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = 0
+        while k < max_it:
+            s.iterate(100)
+            k += 100
+            if s.residual()["res_drop"] <= target:
+                break
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        its_seq.append(k)
+    return dict(instances=len(flows), flows_ma_re=DROP_BATCH, batch_mixed_seconds=round(t_batch, 4),
+                batch_iterations_to_target=first, fp64_sequential_seconds=round(t_seq, 4),
+                fp64_iterations_to_target=its_seq, speedup=round(t_seq / t_batch, 3))
+
+
+def run_cpu_baseline(cases, budget_s=12.0, max_it=60):
+    """The oracle on a bounded sample: iterations of the given (mesh, flow)
+    cases in turn after one untimed start iteration each, ~budget_s."""
+    from oracle import pyoracle as po
+    cells, its, dt = 0, 0, 0.0
+    names = []
+    for mesh, flow in cases:
+        o = po.Oracle(mesh)
+        o.set_freestream(*flow)
+        o.iterate(1)     # the impulsive-start iteration, untimed
+        t0 = time.perf_counter()
+        it = 0
+        while it < max_it:
+            o.iterate(1)
+            it += 1
+            if dt + time.perf_counter() - t0 > budget_s:
+                break
+        dt += time.perf_counter() - t0
+        cells += mesh.n_cells * it
+        its += it
+        names.append(f"{mesh.n_cells} cells x {it}")
+        if dt > budget_s:
             break
-    dt = time.perf_counter() - t0
-    return dict(value=mesh.n_cells * it / dt, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=f"{it} iterations of the same workload after one untimed start iteration, "
-                       f"single-threaded FP64 C oracle, {dt:.1f} s")
+    return dict(value=cells / dt, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=f"iterations of the same workload ({'; '.join(names)}) after one untimed start iteration "
+                       f"each, single-threaded FP64 C oracle, {dt:.1f} s")
 
 
 def main():
@@ -124,9 +180,11 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--workload", default="jouk40k", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default: fp64, mixed for batch64")
     ap.add_argument("--chunk", type=int, default=20)
     ap.add_argument("--profile-iters", type=int, default=20)
+    ap.add_argument("--autotune", type=int, default=None, help="autotuner iterations (default: 5 for batch64, 0 else)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 runs")
     args = ap.parse_args()
@@ -140,16 +198,31 @@ def main():
     from paper_1709_00803_amd import meshgen as mg
 
     wl = WORKLOADS[args.workload]
+    batched = args.workload == "batch64"
+    precision = args.precision or ("mixed" if batched else "fp64")
+    mixed = precision == "mixed"
+    tune = args.autotune if args.autotune is not None else (5 if batched else 0)
     t = time.perf_counter()
-    mesh = mg.workload(args.workload)
+    if batched:
+        meshes, flows = mg.batch(64)
+    else:
+        meshes, flows = [mg.workload(args.workload)], [wl["flow"]]
     t_mesh = time.perf_counter() - t
-    mixed = args.precision == "mixed"
     torch.cuda.set_device(0)
-    solver = igks.Solver(mesh, precision=igks.IGKS_MIXED if mixed else igks.IGKS_FP64, chunk=args.chunk)
-    solver.set_freestream(*wl["flow"])
-    sa = wl["flow"][3] >= 0
-    print(f"# mesh {args.workload}: {mesh.n_cells} cells, {solver.nf} faces, {solver.nlev} wavefronts, "
-          f"generated in {t_mesh:.1f}s", file=sys.stderr, flush=True)
+    prec = igks.IGKS_MIXED if mixed else igks.IGKS_FP64
+    if batched:
+        solver = igks.BatchSolver(meshes, precision=prec, chunk=args.chunk)
+        for i, f in enumerate(flows):
+            solver.set_freestream(i, *f)
+        nfs = solver.nf
+    else:
+        solver = igks.Solver(meshes[0], precision=prec, chunk=args.chunk)
+        solver.set_freestream(*flows[0])
+        nfs = [solver.nf]
+    n = solver.total_cells
+    print(f"# {args.workload}: {len(meshes)} instance(s), {n} cells, {solver.total_faces} faces, "
+          f"{solver.nlev} wavefronts, generated in {t_mesh:.1f}s", file=sys.stderr, flush=True)
+    schedule = solver.autotune(tune).tolist() if tune > 0 else solver.schedule().tolist()
 
     solver.iterate(args.warmup)
     torch.cuda.synchronize()
@@ -158,54 +231,65 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    n = mesh.n_cells
     value = n * args.steps / elapsed
-    res = solver.residual()
-    print(f"# timed {args.steps} iterations in {elapsed:.3f}s, drop {res['res_drop']:.3e}", file=sys.stderr,
-          flush=True)
+    if batched:
+        drops = [solver.residual(i)["res_drop"] for i in range(len(meshes))]
+        frozen = [i for i in range(len(meshes)) if solver.status(i)]
+        res_info = dict(res_drop_after_min=min(drops), res_drop_after_median=float(np.median(drops)),
+                        res_drop_after_max=max(drops), frozen_instances=frozen)
+    else:
+        res_info = dict(res_drop_after=solver.residual()["res_drop"])
+    print(f"# timed {args.steps} iterations in {elapsed:.3f}s, {res_info}", file=sys.stderr, flush=True)
 
     # per-kernel durations: HIP events on the library's stream, direct launches
     solver.set_profiling(True)
     solver.iterate(args.profile_iters)
     kt = solver.kernel_times()      # ms per iteration, per kernel class
     solver.set_profiling(False)
-    e = int(np.sum(np.diff(mesh.cell_ptr)))
-    kb = kernel_bytes(n, solver.nf, e, sa, mixed)
+    kb = {}
+    for m, f, nf in zip(meshes, flows, nfs):
+        e = int(np.sum(np.diff(m.cell_ptr)))
+        for k, v in kernel_bytes(m.n_cells, nf, e, f[3] >= 0, mixed).items():
+            kb[k] = kb.get(k, 0) + v
+    faces = solver.total_faces
     dom = max(kt, key=lambda k: kt[k])
-    launches = {"sweep_fwd": solver.nlev, "sweep_bwd": solver.nlev}.get(dom, 1)
+    sweep_wg = schedule[5] == 2
+    launches = {"sweep_fwd": 1 if sweep_wg else solver.nlev,
+                "sweep_bwd": 1 if sweep_wg else solver.nlev}.get(dom, 1)
     t_ms = kt[dom]
     if dom == "flux":
-        achieved = FLUX_FLOP_PER_FACE * solver.nf / (t_ms * 1e-3) / 1e12 if t_ms > 0 else 0.0
+        achieved = FLUX_FLOP_PER_FACE * faces / (t_ms * 1e-3) / 1e12 if t_ms > 0 else 0.0
         roofline = dict(kernel=dom, bound="alu", achieved=achieved, peak=FP64_VALU_PEAK_TFS, unit="TFLOP/s",
                         frac=achieved / FP64_VALU_PEAK_TFS)
     else:
-        achieved = kb[dom] / launches / (t_ms / launches * 1e-3) / 1e9 if t_ms > 0 else 0.0
+        achieved = kb[dom] / (t_ms * 1e-3) / 1e9 if t_ms > 0 else 0.0
         roofline = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=achieved / HBM_PEAK_GBS)
-    tr = measured_traffic(args.workload, dom) if not mixed else None
+    tr = measured_traffic(args.workload, dom) if not mixed or batched else None
     roofline.update(traffic=tr, launches_per_step=launches, ms_per_step=t_ms,
-                    algorithmic_bytes_per_step=kb[dom],
+                    algorithmic_bytes_per_step=kb.get(dom),
                     kernel_ms_per_step={k: round(v, 5) for k, v in kt.items()})
-    # the face-flux kernel against the FP64 vector peak, whatever dominates
     tf = kt.get("flux", 0.0)
-    roofline["flux_fp64_tflops"] = FLUX_FLOP_PER_FACE * solver.nf / (tf * 1e-3) / 1e12 if tf > 0 else 0.0
+    roofline["flux_fp64_tflops"] = FLUX_FLOP_PER_FACE * faces / (tf * 1e-3) / 1e12 if tf > 0 else 0.0
+    roofline["hbm_gbs_per_kernel"] = {k: round(kb[k] / (kt[k] * 1e-3) / 1e9, 1) for k in kb if kt.get(k, 0) > 0}
 
     out = {
         "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {wl['desc']}", "cells": n, "faces": solver.nf,
-                   "wavefronts": solver.nlev, "precision": args.precision, "ordering": "colour",
-                   "chunk": args.chunk, "res_drop_after": res["res_drop"]},
+        "config": dict({"workload": f"{args.workload}: {wl['desc']}", "instances": len(meshes), "cells": n,
+                        "faces": faces, "wavefronts": solver.nlev, "precision": precision, "ordering": "colour",
+                        "chunk": args.chunk, "schedule": schedule}, **res_info),
         "roofline": roofline,
     }
     if not args.no_drop:
         out["time_to_1e-10"] = {"workload": "plate64x32 (natural order), Ma 0.3 Re_L 1e4, CFL 10 -> Eq.25",
                                 "fp64": time_to_drop(igks, mg, igks.IGKS_FP64),
-                                "mixed": time_to_drop(igks, mg, igks.IGKS_MIXED)}
+                                "mixed": time_to_drop(igks, mg, igks.IGKS_MIXED),
+                                "batched_plates": time_to_drop_batch(igks, mg)}
     if not args.no_cpu:
-        out["cpu_baseline"] = run_cpu_baseline(mesh, wl["flow"])
+        out["cpu_baseline"] = run_cpu_baseline(list(zip(meshes, flows))[:4])
     print(json.dumps(out), flush=True)
 
 

@@ -151,8 +151,11 @@ int igks_set_freestream(igks_ctx *ctx, double mach, double alpha_deg, double rey
 /* Run n nonlinear iterations (residual, CFL law, LU-SGS sweeps, update).
  * Work is queued in chunks of opt.chunk iterations (one HIP graph launch
  * each) and the stream is synchronised at each chunk end.  *n_done (may be
- * NULL) = iterations committed.  IGKS_ENONPHYS: an update was rejected;
- * the state is the last committed iterate. */
+ * NULL) = iterations committed (instance 0).  IGKS_ENONPHYS: an update
+ * of some instance was rejected during this call (that instance is frozen
+ * at its last committed iterate; the others went on), or every instance was
+ * already frozen.  A frozen instance runs again after igks_set_state or
+ * igks_set_freestream. */
 int igks_iterate(igks_ctx *ctx, int32_t n, int32_t *n_done);
 
 /* Scalars of the last iteration. */
@@ -195,7 +198,10 @@ int igks_get_wall_loads(igks_ctx *ctx, double *cl, double *cd, double *cf, doubl
  * for every instance -> igks_iterate (all instances) -> getters.
  * An instance whose update is rejected (IGKS_ENONPHYS) is frozen at its
  * last good state while the others go on; igks_iterate then returns
- * IGKS_ENONPHYS and igks_batch_status tells which.
+ * IGKS_ENONPHYS and igks_batch_status tells which.  Residual and wall-load
+ * calls on a frozen instance return IGKS_ENONPHYS.  igks_mesh_info reports
+ * the totals over all instances (wavefronts: the largest count of any
+ * instance, since wavefronts of different instances run together).
  * ------------------------------------------------------------------- */
 int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream, int32_t n_inst);
 int igks_batch_mesh_upload(igks_ctx *ctx, int32_t inst, int32_t n_nodes, const double *xy, int32_t n_cells,

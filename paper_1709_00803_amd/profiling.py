@@ -5,6 +5,7 @@ collections) into the short text / JSON files kept under profiles/.
     python -m paper_1709_00803_amd.profiling traffic <workload> <fetch.csv> <write.csv> \
         <fetch_copy.csv> <write_copy.csv> <copy_bytes> <out.json> "<command>"
     python -m paper_1709_00803_amd.profiling copy     (calibration: 5 device copies of 256 MiB)
+    python -m paper_1709_00803_amd.profiling flops <workload> <counters.csv> <faces> <out.json> "<command>"
 """
 import collections
 import csv
@@ -78,6 +79,29 @@ def traffic(workload, fetch_csv, write_csv, fetch_copy_csv, write_copy_csv, copy
     return out
 
 
+F64_COUNTERS = ("SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64",
+                "SQ_INSTS_VALU_TRANS_F64", "SQ_WAVES")
+
+
+def flops(workload, csv_path, faces, out_json, command, kernel="flux"):
+    """FP64 operations per face of the face-flux kernel: each FP64 VALU
+    instruction of a wave does one operation per lane and a lane handles one
+    face, so ops per face = (2 FMA + MUL + ADD + TRANS) per wave (all waves
+    full but the last)."""
+    per = {}
+    for c in F64_COUNTERS:
+        v, _ = _per_class(csv_path, c)
+        per[c] = v.get(kernel)
+    waves = per["SQ_WAVES"]
+    ops = 2 * per["SQ_INSTS_VALU_FMA_F64"] + per["SQ_INSTS_VALU_MUL_F64"] + per["SQ_INSTS_VALU_ADD_F64"] \
+        + per["SQ_INSTS_VALU_TRANS_F64"]
+    out = dict(workload=workload, command=command, kernel_source_sha256_16=kernel_source_hash(), kernel=kernel,
+               counters_per_dispatch=per, faces=faces, faces_per_wave=faces / waves,
+               fp64_ops_per_wave=ops / waves, fp64_ops_per_face=ops / waves)
+    json.dump(out, open(out_json, "w"), indent=1, sort_keys=True)
+    return out
+
+
 COPY_BYTES = 256 * 1024 * 1024
 
 
@@ -97,6 +121,8 @@ if __name__ == "__main__":
     a = sys.argv[1:]
     if a and a[0] == "copy":
         copy_calibration()
+    elif a and a[0] == "flops":
+        print(json.dumps(flops(a[1], a[2], int(a[3]), a[4], a[5]), indent=1))
     elif a and a[0] == "stats":
         print(stats(a[1], a[2], a[3]))
     elif a and a[0] == "traffic":
