@@ -48,21 +48,31 @@ KSRC = os.path.join(ROOT, "paper_1709_00803_amd", "csrc", "igks_kernels.hip")
 
 
 def kernel_bytes(n, f, e, sa, mixed):
-    """Compulsory HBM bytes per launch of each kernel class: every array
-    element the kernel needs is counted once (neighbour re-reads assumed
-    cached).  n cells, f faces, e cell-face entries."""
-    d = 8
+    """Compulsory HBM bytes per iteration of each kernel class: every array
+    element a kernel needs is counted once (re-reads of neighbour data are
+    assumed to hit in cache); limiter off.  n cells, f faces, e cell-face
+    entries; sa: the SA equation is on."""
+    d, i4 = 8, 4
     dw = 4 if mixed else 8
+    s = 1 if sa else 0
     b = {}
-    b["prep"] = 5 * d * n + 4 * n + (4 + 4 + 8 + 8) * e + 3 * d * f + (3 + 1) * d * n + (3 + 8) * d * n
-    b["flux"] = (8 + 3 * d + 4 * d + 3 * d) * f + (5 + 8) * d * n + (4 + 1 + (2 if sa else 0)) * d * f
-    b["gather"] = 4 * n + 8 * e + (4 + 2) * d * f + (5 + 1) * d * n + (5 + 1 + (1 if sa else 0)) * d * n \
-        + ((2 + 3) * d * f + 4 * e if sa else 0)
-    sweep = (5 + 1 + 1 + 1 + (1 if sa else 0)) * d * n + 4 * n + 12 * e + 4 * d * f + 5 * dw * n
+    # W, cinst, cf_ptr; cf_face/cf_nbr/cf_dx/cf_dy; face normal and length;
+    # lsinv, area; writes nu, lamc, vort, gradients
+    b["prep"] = 5 * d * n + 2 * i4 * n + (2 * i4 + 2 * d) * e + 3 * d * f + 4 * d * n + (3 + 8) * d * n
+    # fl, fr, finst; normal, length, face-centre offsets, distances; W and
+    # gradients of both sides; writes flux, lam (+ SA saf, sag, sak)
+    b["flux"] = (3 * i4 + 10 * d) * f + (5 + 8) * d * n + (4 + 1 + 3 * s) * d * f
+    # cinst, cf_ptr, ipos; cf_face/cf_flag; flux, lam, length (+ SA: saf, sag,
+    # sak, normal); W (+ SA: nu, wall distance, vorticity, area); writes M,
+    # lsum, r2 (+ SA diagonal)
+    b["gather"] = 3 * i4 * n + 2 * i4 * e + 6 * d * f + 5 * d * n + (5 + 1 + 2) * d * n \
+        + s * (5 * d * f + 4 * d * n + d * n)
+    b["reduce"] = 2 * d * n
+    # cinst, cf_ptr; cf_nbr/cf_flag/cf_face; normal, length, lam (+ sak) of
+    # the faces swept; W, lamc, lsum (+ SA diagonal); writes dW
+    sweep = 2 * i4 * n + 3 * i4 * e + (4 + s) * d * f + (5 + 2 + s) * d * n + 5 * dw * n
     b["sweep_fwd"] = sweep + 5 * d * n                      # + M
-    b["sweep_bwd"] = sweep + 5 * dw * n                     # + own dW*
-    b["update"] = 5 * d * n + 5 * dw * n + 5 * d * n
-    b["reduce"] = 2 * d * ((n + 255) // 256)
+    b["sweep_bwd"] = sweep + 5 * dw * n + 5 * d * n         # + own dW*, writes W^{n+1}
     return b
 
 
@@ -253,7 +263,7 @@ def main():
             kb[k] = kb.get(k, 0) + v
     faces = solver.total_faces
     dom = max(kt, key=lambda k: kt[k])
-    sweep_wg = schedule[5] == 2
+    sweep_wg = schedule[4] == 2
     launches = {"sweep_fwd": 1 if sweep_wg else solver.nlev,
                 "sweep_bwd": 1 if sweep_wg else solver.nlev}.get(dom, 1)
     t_ms = kt[dom]

@@ -221,21 +221,27 @@ int igks_batch_get_wall_loads(igks_ctx *ctx, int32_t inst, double *cl, double *c
 /* *halted = 1 if the instance was frozen by a rejected update. */
 int igks_batch_status(igks_ctx *ctx, int32_t inst, int32_t *halted);
 
-/* Autotuner: times `iters` iterations of each candidate launch schedule
- * (threads per block 64/128/256 for the prep, flux, gather, sweep and
- * update kernels; one launch per wavefront or one workgroup per sweep),
- * keeps the fastest per kernel class, and restores the state and scalars
- * bitwise.  schedule6 (may be NULL) receives the chosen block sizes of the
- * five classes and the sweep schedule (1 or 2). */
-int igks_autotune(igks_ctx *ctx, int32_t iters, int32_t *schedule6);
-int igks_get_schedule(const igks_ctx *ctx, int32_t *schedule6);
+/* Autotuner: runs `iters` iterations under each candidate launch schedule
+ * (threads per block 64/128/256 for the prep, flux, gather and sweep
+ * kernels; for the sweeps also one workgroup for all wavefronts, tried
+ * while wavefronts average under 16384 cells), keeps the fastest per kernel
+ * class, and then restores both state buffers, the scalars and the history
+ * bitwise.  The schedule changes launch shapes only, never results.
+ * schedule5 (may be NULL) receives the block sizes of the four classes and
+ * the sweep schedule (1: one launch per wavefront, 2: one workgroup).
+ * IGKS_EINVAL unless 1 <= iters <= 1000; IGKS_ENONPHYS if an instance is
+ * frozen. */
+int igks_autotune(igks_ctx *ctx, int32_t iters, int32_t *schedule5);
+int igks_get_schedule(const igks_ctx *ctx, int32_t *schedule5);
 
-/* Average duration (ms) of each kernel class over the last igks_iterate
- * call, measured with HIP events when opt.chunk == 0 and profiling was
- * enabled by igks_set_profiling(ctx, 1); 0 otherwise.  Order: prep, flux,
- * gather, reduce, sweep_fwd (all levels), sweep_bwd (all levels), update. */
+/* With profiling on (igks_set_profiling(ctx, 1)) igks_iterate launches
+ * directly, not through graphs, and times each kernel class with HIP events
+ * on the context's stream; igks_get_kernel_times then gives the average ms
+ * per iteration of: prep (with the Eq.23 time step), flux, gather, norms
+ * (with the Eq.25 CFL), sweep_fwd (all wavefronts), sweep_bwd (all
+ * wavefronts, with the update and commit).  0 when profiling was off. */
 int igks_set_profiling(igks_ctx *ctx, int on);
-int igks_get_kernel_times(igks_ctx *ctx, double *ms7);
+int igks_get_kernel_times(igks_ctx *ctx, double *ms6);
 
 #ifdef __cplusplus
 }

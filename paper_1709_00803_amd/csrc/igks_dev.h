@@ -25,8 +25,9 @@ constexpr int CF_LOWER = 2;   // interior neighbour with a smaller upload index
 constexpr int MAXV = 4;       // vertices per cell (triangles padded by repeating a vertex)
 constexpr int HIST_W = 6;     // doubles per history entry
 constexpr int NSLOT = 64;     // atomic min/max targets of one instance are spread over this many slots
-constexpr int RB = 8;         // blocks per instance in the residual-norm reduction
-constexpr int NCLASS = 5;     // kernel classes with a tunable block size: prep, flux, gather, sweep, update
+constexpr int RB = 32;        // blocks per instance in the residual-norm reduction
+constexpr int NTICKET = 4;    // last-block tickets: prep, norms, backward sweep
+constexpr int NCLASS = 4;     // kernel classes with a tunable block size: prep, flux, gather, sweep
 
 // Free stream of one instance (read-only while iterating).
 struct InstParam {
@@ -72,7 +73,7 @@ struct Params {
     double *M;                 // residual: 4 flow components + SA right-hand side
     double *lsum;              // 1/2 sum lambda S (Eq.20 diagonal)
     double *sadiag;            // SA diagonal without Omega/dt
-    double *r2;                // per-cell squares for the norms: M_rho^2, R_SA^2
+    double *r2;                // squares for the norms, M_rho^2 then R_SA^2, at the cell's ipos
     T *dW;                     // LU-SGS increment, 5 x nc
     const double *xc, *yc, *area, *lsinv, *dwall, *vtx;
     const int *cf_ptr, *cf_face, *cf_nbr, *cf_flag;
@@ -84,9 +85,12 @@ struct Params {
     double *lam;               // spectral radius per face
     double *saf;               // SA: (-F_inv + F_vis) S
     double *sag;               // SA: (nu~_r - nu~_l)/|r.n| S
+    double *sak;               // SA: diffusion coefficient of the face times S/|r.n|
     // per-instance cell lists (internal ids, ascending) for the norms
     const int *icell, *ioff;
+    const int *ipos;           // position of each cell in icell
     double *ipart;             // ninst x RB x 2 partial sums
+    unsigned *ticket;          // NTICKET counters, zero between launches
     double *hist;              // HIST_W x ninst x hist_cap
     int hist_cap;
 };
@@ -94,17 +98,17 @@ struct Params {
 // launchers (igks_kernels.hip)
 struct Launch {
     hipStream_t s;
-    int block[NCLASS];        // prep, flux, gather, sweep, update
+    int block[NCLASS];        // prep, flux, gather, sweep
 };
 template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int mode, int inst);
 template <typename T> void launch_prep(const Launch &L, const Params<T> &P);
 template <typename T> void launch_flux(const Launch &L, const Params<T> &P);
 template <typename T> void launch_gather(const Launch &L, const Params<T> &P);
 template <typename T> void launch_reduce(const Launch &L, const Params<T> &P);
-template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd);
+// backward sweeps also update the state (Eq.17) and, in their last launch
+// (commit = true), accept or reject the iteration of every instance
+template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd, bool commit);
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd);
-template <typename T> void launch_update(const Launch &L, const Params<T> &P);
-template <typename T> void launch_commit(const Launch &L, const Params<T> &P);
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
                           const int *woff, const double *wseg, double *dwall);
 void launch_gather_faces(const Launch &L, int n, const int *faces, const double *flux, int nf, double *out);

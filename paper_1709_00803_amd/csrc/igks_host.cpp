@@ -41,7 +41,7 @@ struct Global {
     std::vector<int> lev_off;        // wavefront offsets (internal cells)
     std::vector<int> coff;           // first global upload id of each instance
     std::vector<int> g2i;            // global upload id -> internal cell
-    std::vector<int> cinst, finst, icell, ioff;
+    std::vector<int> cinst, finst, icell, ioff, ipos;
     std::vector<double> xc, yc, area, lsinv, vtx;
     std::vector<int> cf_ptr, cf_face, cf_nbr, cf_flag;
     std::vector<double> cf_dx, cf_dy;
@@ -55,10 +55,13 @@ struct Buf {
     size_t off, bytes;
 };
 
+// timed kernel classes: prep, flux, gather, norms, forward sweep, backward sweep with update
+constexpr int NKT = 6;
+
 struct WsMap {
     Buf ip, is, hist_n, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx;
     Buf cinst, finst, icell, ioff, g2i, cf_ptr, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
-    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, ipart, hist;
+    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, sak, ipart, hist, ipos, ticket;
     Buf wall_faces, wall_out, woff, wseg, lev_off, stage, backup;
     size_t total;
 };
@@ -82,7 +85,7 @@ struct igks_ctx {
     Params<float> P32{};
     int hist_cap = 0;
     // launch schedule
-    int block[NCLASS] = {256, 256, 256, 256, 256};
+    int block[NCLASS] = {256, 256, 256, 256};
     bool sweep_wg = false;
     // host copies of the device scalars and the history of the last iterate call
     std::vector<InstScalars> hs;
@@ -91,7 +94,7 @@ struct igks_ctx {
     hipGraphExec_t gexec = nullptr;
     // profiling
     bool profiling = false;
-    double ktimes[7] = {0, 0, 0, 0, 0, 0, 0};
+    double ktimes[NKT] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -284,9 +287,14 @@ int combine(igks_ctx *ctx)
     for (int c = 0; c < N; c++) G.ioff[G.cinst[c] + 1]++;
     for (int i = 0; i < ni; i++) G.ioff[i + 1] += G.ioff[i];
     G.icell.resize(N);
+    G.ipos.resize(N);
     {
         std::vector<int> fill(ni, 0);
-        for (int c = 0; c < N; c++) G.icell[G.ioff[G.cinst[c]] + fill[G.cinst[c]]++] = c;
+        for (int c = 0; c < N; c++) {
+            int k = G.ioff[G.cinst[c]] + fill[G.cinst[c]]++;
+            G.icell[k] = c;
+            G.ipos[c] = k;
+        }
     }
     // faces
     struct FRef { int inst, q; };
@@ -442,7 +450,10 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.fnx = L.add(F * D); w.fny = L.add(F * D); w.flen = L.add(F * D); w.frl = L.add(2 * F * D);
     w.frr = L.add(2 * F * D); w.fdl = L.add(F * D); w.fdr = L.add(F * D); w.frn = L.add(F * D);
     w.flux = L.add(4 * F * D); w.lam = L.add(F * D); w.saf = L.add(F * D); w.sag = L.add(F * D);
+    w.sak = L.add(F * D);
     w.ipart = L.add(2 * NI * RB * D);
+    w.ipos = L.add(N * I);
+    w.ticket = L.add(NTICKET * sizeof(unsigned));
     w.hist = L.add((size_t)HIST_W * NI * hist_cap * D);
     w.wall_faces = L.add(NW * I);
     w.wall_out = L.add(4 * NW * D);
@@ -480,8 +491,9 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.fl = In(w.fl); P.fr = In(w.fr); P.fbc = In(w.fbc);
     P.fnx = D(w.fnx); P.fny = D(w.fny); P.flen = D(w.flen); P.frl = D(w.frl); P.frr = D(w.frr);
     P.fdl = D(w.fdl); P.fdr = D(w.fdr); P.frn = D(w.frn);
-    P.flux = D(w.flux); P.lam = D(w.lam); P.saf = D(w.saf); P.sag = D(w.sag);
-    P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipart = D(w.ipart);
+    P.flux = D(w.flux); P.lam = D(w.lam); P.saf = D(w.saf); P.sag = D(w.sag); P.sak = D(w.sak);
+    P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipos = In(w.ipos); P.ipart = D(w.ipart);
+    P.ticket = (unsigned *)(b + w.ticket.off);
     P.hist = D(w.hist); P.hist_cap = c->hist_cap;
 }
 
@@ -512,15 +524,13 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev)
     mark(4);
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, true);
     else
-        for (int l = 0; l < G.nlev; l++) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], true);
+        for (int l = 0; l < G.nlev; l++) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], true, false);
     mark(5);
+    // backward sweep with the update; its last launch commits
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, false);
     else
-        for (int l = G.nlev - 1; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], false);
+        for (int l = G.nlev - 1; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], false, l == 0);
     mark(6);
-    launch_update(L, P);
-    mark(7);
-    launch_commit(L, P);
 }
 
 template <typename T>
@@ -548,12 +558,12 @@ int run_chunk(igks_ctx *c, const Params<T> &P, int k)
     Launch L = launch_of(c);
     launch_reset(L, P, 4, -1);
     if (c->profiling) {
-        hipEvent_t ev[8];
+        hipEvent_t ev[NKT + 1];
         for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
         for (int i = 0; i < k; i++) {
             queue_iteration(c, P, ev);
-            HIPCHK(c, hipEventSynchronize(ev[7]));
-            for (int j = 0; j < 7; j++) {
+            HIPCHK(c, hipEventSynchronize(ev[NKT]));
+            for (int j = 0; j < NKT; j++) {
                 float ms = 0;
                 (void)hipEventElapsedTime(&ms, ev[j], ev[j + 1]);
                 c->ktimes[j] += ms;
@@ -869,6 +879,7 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     rc |= up(w.lsinv, G.lsinv.data(), 3 * N * D); rc |= up(w.vtx, G.vtx.data(), 2 * MAXV * N * D);
     rc |= up(w.cinst, G.cinst.data(), N * I); rc |= up(w.finst, G.finst.data(), F * I);
     rc |= up(w.icell, G.icell.data(), N * I); rc |= up(w.ioff, G.ioff.data(), G.ioff.size() * I);
+    rc |= up(w.ipos, G.ipos.data(), N * I);
     rc |= up(w.g2i, G.g2i.data(), N * I);
     rc |= up(w.cf_ptr, G.cf_ptr.data(), (N + 1) * I); rc |= up(w.cf_face, G.cf_face.data(), E * I);
     rc |= up(w.cf_nbr, G.cf_nbr.data(), E * I); rc |= up(w.cf_flag, G.cf_flag.data(), E * I);
@@ -892,6 +903,7 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     for (auto &m : c->inst) std::memset(&m.ip, 0, sizeof m.ip);
     rc = up(w.ip, ip0.data(), sizeof(InstParam) * ip0.size());
     if (rc) return rc;
+    HIPCHK(c, hipMemsetAsync(b + w.ticket.off, 0, w.ticket.bytes, c->stream));
     Launch L = launch_of(c);
     launch_wall_distance(L, G.N, c->P64.xc, c->P64.yc, c->P64.cinst, (const int *)(b + w.woff.off),
                          (const double *)(b + w.wseg.off), (double *)(b + w.dwall.off));
@@ -1132,22 +1144,22 @@ int igks_set_profiling(igks_ctx *c, int on)
     return IGKS_OK;
 }
 
-int igks_get_kernel_times(igks_ctx *c, double *ms7)
+int igks_get_kernel_times(igks_ctx *c, double *ms6)
 {
-    if (!c || !ms7) return IGKS_EINVAL;
-    for (int k = 0; k < 7; k++) ms7[k] = c->ktimes[k];
+    if (!c || !ms6) return IGKS_EINVAL;
+    for (int k = 0; k < NKT; k++) ms6[k] = c->ktimes[k];
     return IGKS_OK;
 }
 
-int igks_get_schedule(const igks_ctx *c, int32_t *s6)
+int igks_get_schedule(const igks_ctx *c, int32_t *s5)
 {
-    if (!c || !s6) return IGKS_EINVAL;
-    for (int k = 0; k < NCLASS; k++) s6[k] = c->block[k];
-    s6[5] = c->sweep_wg ? 2 : 1;
+    if (!c || !s5) return IGKS_EINVAL;
+    for (int k = 0; k < NCLASS; k++) s5[k] = c->block[k];
+    s5[NCLASS] = c->sweep_wg ? 2 : 1;
     return IGKS_OK;
 }
 
-int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s6)
+int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s5)
 {
     int rc = check_ready(c, true);
     if (rc) return rc;
@@ -1163,8 +1175,8 @@ int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s6)
     HIPCHK(c, hipMemcpyAsync(bk + SB, c->P64.Wb, SB, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(bk + 2 * SB, c->P64.is, ni * sizeof(InstScalars), hipMemcpyDeviceToDevice, c->stream));
     std::vector<std::vector<double>> hist_keep = c->hist;
-    // kernel class -> event interval: prep 0, flux 1, gather 2, sweep 4 + 5, update 6
-    const int ev_of[NCLASS] = {0, 1, 2, 4, 6};
+    // kernel class -> event interval: prep 0, flux 1, gather 2, sweep 4 + 5
+    const int ev_of[NCLASS] = {0, 1, 2, 4};
     const int cand[3] = {64, 128, 256};
     int best[NCLASS];
     double best_t[NCLASS];
@@ -1181,11 +1193,14 @@ int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s6)
         }
     }
     for (int k = 0; k < NCLASS; k++) c->block[k] = best[k];
-    if (!rc) {
+    if (!rc && (double)c->g.N / std::max(1, c->g.nlev) < 16384.0) {
         // sweeps: one launch per wavefront (timed above) or one workgroup
+        // (a candidate only while wavefronts are narrow)
         c->sweep_wg = true;
         rc = (c->opt.precision == IGKS_MIXED) ? tune_run(c, c->P32, iters) : tune_run(c, c->P64, iters);
         if (!rc) c->sweep_wg = c->ktimes[4] + c->ktimes[5] < best_t[3];
+    } else if (!rc) {
+        c->sweep_wg = false;
     }
     if (rc) c->sweep_wg = wg_auto;
     c->profiling = prof;
@@ -1197,7 +1212,7 @@ int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s6)
     int rc2 = sync_scalars(c);
     if (rc) return rc;
     if (rc2) return rc2;
-    if (s6) igks_get_schedule(c, s6);
+    if (s5) igks_get_schedule(c, s5);
     return IGKS_OK;
 }
 

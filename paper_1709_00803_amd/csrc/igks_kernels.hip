@@ -1,10 +1,11 @@
 // igks_kernels.hip - HIP kernels of the implicit gas-kinetic scheme for
 // gfx950 (MI355X).
 //
-// One iteration = prep (per cell) -> dt (per instance) -> flux (per face)
-// -> gather (per cell) -> norm partial sums -> reduce (per instance) ->
-// forward sweep (one launch per wavefront) -> backward sweep -> update (per
-// cell) -> commit (per instance).
+// One iteration = prep (per cell; its last block takes the per-instance
+// Eq.23 time step) -> flux (per face) -> gather (per cell) -> norm partial
+// sums (their last block: per-instance norms and the Eq.25 CFL) -> forward
+// sweep (one launch per wavefront) -> backward sweep with the state update
+// (the last block of its last launch commits or rejects every instance).
 //
 // Data are structure-of-arrays in the library's internal cell order
 // (wavefront, then instance, then upload index) and face order (owner
@@ -118,6 +119,34 @@ __device__ __forceinline__ void ghost_incr(int bc, const V *d, V nx, V ny, V *g)
 #pragma unroll
         for (int k = 0; k < 5; k++) g[k] = V(0);
     }
+}
+
+// Block index remapped so that each XCD works on one contiguous range of
+// cells or faces (workgroups are dealt to the 8 XCDs in turn, and each XCD
+// has its own L2): neighbour data of a range then stay in one L2.  A
+// bijection of [0, gridDim.x) whatever the dealing order.
+__device__ __forceinline__ int xcd_block()
+{
+    const int nxcd = 8;
+    int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    int q = nb / nxcd, r = nb % nxcd, x = b % nxcd;
+    return x * q + min(x, r) + b / nxcd;
+}
+
+// Every block publishes its writes and takes a ticket; true in the block
+// that takes the last one, which then sees the writes of all the others.
+// That block puts the counter back to zero for the next launch.
+__device__ __forceinline__ bool last_block(unsigned *ticket)
+{
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = atomicAdd(ticket, 1u) == gridDim.x - 1u;
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    if (threadIdx.x == 0) atomicExch(ticket, 0u);
+    return true;
 }
 
 __device__ __forceinline__ double wave_min(double v)
@@ -513,7 +542,7 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
 template <typename T>
 __global__ __launch_bounds__(256) void k_prep(Params<T> P)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    int c = xcd_block() * blockDim.x + threadIdx.x;
     int inst = -1;
     double dt = INFINITY;
     if (c < P.nc) {
@@ -522,14 +551,9 @@ __global__ __launch_bounds__(256) void k_prep(Params<T> P)
         else dt = prep_cell(P, c, inst);
     }
     slot_update<true>(&P.is[0].dtmin_bits[0], inst, dt);   // Eq.23: minimum over the instance's cells
-}
-
-// One thread per instance: the Eq.23 time step = minimum over its slots.
-template <typename T>
-__global__ void k_dt(Params<T> P)
-{
-    for (int i = threadIdx.x; i < P.ninst; i += blockDim.x)
-        if (!P.is[i].halt) P.is[i].dt = slots_min_serial(P.is[i].dtmin_bits);
+    if (last_block(P.ticket + 0))
+        for (int i = threadIdx.x; i < P.ninst; i += blockDim.x)
+            if (!P.is[i].halt) P.is[i].dt = slots_min_serial(P.is[i].dtmin_bits);
 }
 
 __device__ __forceinline__ bool physical(const double *w)
@@ -616,6 +640,7 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst)
             double Fvis = (0.5 / SA_SIGMA) * ((nui + nuj) + (1.0 + SA_CB2) * (ti + tj)) * g;
             P.saf[f] = (Fvis - Finv) * S;
             P.sag[f] = g * S;
+            P.sak[f] = (0.5 / SA_SIGMA) * ((nui + nuj) + (1.0 + SA_CB2) * (ti + tj)) * S / rn;
         }
     }
     // face frame
@@ -663,7 +688,7 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst)
 template <typename T>
 __global__ __launch_bounds__(256) void k_flux(Params<T> P)
 {
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    int f = xcd_block() * blockDim.x + threadIdx.x;
     if (f >= P.nf) return;
     int inst = P.finst[f];
     if (P.is[inst].halt) return;
@@ -695,27 +720,15 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
         if (ip.sa) {
             saR += sg * P.saf[f];
             sagS += sg * P.sag[f];
-            double nx = sg * P.fnx[f], ny = sg * P.fny[f];
-            int j = P.cf_nbr[e];
-            double nuj, tj;
-            if (j >= 0) {
-                nuj = P.nu[j];
-                tj = W[4 * N + j];
-            } else {
-                double g[5];
-                ghost(ip, P.fbc[f], w, nx, ny, g);
-                nuj = mu_lam(P.mu_law, ip, lam_of(g)) / g[0];
-                tj = g[4];
-            }
-            double qc = (w[1] * nx + w[2] * ny) / w[0];
-            double kf = (1.0 / SA_SIGMA) * (0.5 * (nuc + nuj) + (1.0 + SA_CB2) * 0.5 * (w[4] + tj));
-            sad += 0.5 * (qc + fabs(qc)) * S + kf * S / P.frn[f];
+            double qc = sg * (w[1] * P.fnx[f] + w[2] * P.fny[f]) / w[0];
+            sad += 0.5 * (qc + fabs(qc)) * S + P.sak[f];
         }
     }
 #pragma unroll
     for (int k = 0; k < 4; k++) P.M[k * N + c] = m[k];
     P.lsum[c] = 0.5 * ls;
-    P.r2[c] = m[0] * m[0];
+    const int pos = P.ipos[c];
+    P.r2[pos] = m[0] * m[0];
     if (ip.sa) {
         double Sr, jd;
         sa_source(w[4], nuc, P.dwall[c], P.vort[c], Sr, jd);
@@ -723,10 +736,10 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
         double rsa = saR - (SA_CB2 / SA_SIGMA) * w[4] * sagS + a * Sr;
         P.M[4 * N + c] = rsa;
         P.sadiag[c] = sad + a * jd;
-        P.r2[N + c] = rsa * rsa;
+        P.r2[N + pos] = rsa * rsa;
     } else {
         P.M[4 * N + c] = 0.0;
-        P.r2[N + c] = 0.0;
+        P.r2[N + pos] = 0.0;
     }
     return fmax(fmax(fabs(m[0]), fabs(m[1])), fmax(fabs(m[2]), fabs(m[3])));
 }
@@ -734,7 +747,7 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather(Params<T> P)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    int c = xcd_block() * blockDim.x + threadIdx.x;
     int inst = -1;
     double rinf = 0.0;
     if (c < P.nc) {
@@ -745,39 +758,10 @@ __global__ __launch_bounds__(256) void k_gather(Params<T> P)
     slot_update<false>(&P.is[0].resinf_bits[0], inst, rinf);
 }
 
-// Norm partial sums: block (i, b) sums slice b of instance i's cells in a
-// fixed order (deterministic L2 norms without float atomics).
+// Per instance: L2 norms in a fixed order, max norm, the Eq.25 CFL law,
+// history (one thread per instance).
 template <typename T>
-__global__ __launch_bounds__(256) void k_isum(Params<T> P)
-{
-    __shared__ double a[256], b[256];
-    int i = blockIdx.x / RB, part = blockIdx.x % RB;
-    int lo = P.ioff[i], n = P.ioff[i + 1] - lo;
-    int per = (n + RB - 1) / RB;
-    int s0 = lo + part * per, s1 = min(lo + n, s0 + per);
-    double x = 0.0, y = 0.0;
-    for (int k = s0 + (int)threadIdx.x; k < s1; k += 256) {
-        int c = P.icell[k];
-        x += P.r2[c];
-        y += P.r2[P.nc + c];
-    }
-    a[threadIdx.x] = x;
-    b[threadIdx.x] = y;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) { a[threadIdx.x] += a[threadIdx.x + h]; b[threadIdx.x] += b[threadIdx.x + h]; }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        P.ipart[2 * blockIdx.x] = a[0];
-        P.ipart[2 * blockIdx.x + 1] = b[0];
-    }
-}
-
-// One thread per instance: L2 norms in a fixed order, max norm, the Eq.25
-// CFL law, history.
-template <typename T>
-__global__ void k_reduce(Params<T> P)
+__device__ __forceinline__ void reduce_instances(const Params<T> &P)
 {
     int h = *P.hist_n;
     for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
@@ -808,6 +792,39 @@ __global__ void k_reduce(Params<T> P)
     }
 }
 
+// Norm partial sums: block (i, b) sums slice b of instance i's squares
+// (contiguous, instance-grouped) in a fixed order, so the L2 norms are
+// deterministic without float atomics; the last block finishes the
+// per-instance reduction.
+template <typename T>
+__global__ __launch_bounds__(256) void k_isum(Params<T> P)
+{
+    __shared__ double a[256], b[256];
+    int i = blockIdx.x / RB, part = blockIdx.x % RB;
+    int lo = P.ioff[i], n = P.ioff[i + 1] - lo;
+    int per = (n + RB - 1) / RB;
+    int s0 = lo + part * per, s1 = min(lo + n, s0 + per);
+    double x = 0.0, y = 0.0;
+    const double *r2a = P.r2, *r2b = P.r2 + P.nc;
+#pragma unroll 4
+    for (int k = s0 + (int)threadIdx.x; k < s1; k += 256) {
+        x += r2a[k];
+        y += r2b[k];
+    }
+    a[threadIdx.x] = x;
+    b[threadIdx.x] = y;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) { a[threadIdx.x] += a[threadIdx.x + h]; b[threadIdx.x] += b[threadIdx.x + h]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        P.ipart[2 * blockIdx.x] = a[0];
+        P.ipart[2 * blockIdx.x + 1] = b[0];
+    }
+    if (last_block(P.ticket + 1)) reduce_instances(P);
+}
+
 // One wavefront of the forward (FWD) or backward LU-SGS sweep (Eq.22): the
 // cells of a wavefront are mutually independent.  Forward:
 //   dW*_i = D^-1 [M_i - sum_{j<i} (J(W_j, n_ij) dW*_j - lam_ij dW*_j) S_ij / 2];
@@ -815,13 +832,19 @@ __global__ void k_reduce(Params<T> P)
 //   dW_i = dW*_i - D^-1 sum_{j>i} (J(W_j, n_ij) dW_j - lam_ij dW_j) S_ij / 2,
 // boundary ghosts counted as upper neighbours with the ghost increments of
 // Sec. 2.5 taken from dW*_i.  The SA equation (Eq.31-32) is swept alongside.
+// The backward sweep also applies W^{n+1} = W^n + dW (Eq.17) into the
+// instance's other state buffer (nu~ clipped at 0), flags a non-physical
+// result and returns the Eq.40 ratio.  inst = -1 for a frozen instance.
 template <typename T, bool FWD>
-__device__ __forceinline__ void sweep_cell(const Params<T> &P, int c)
+__device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &inst)
 {
     const int N = P.nc;
-    int inst = P.cinst[c];
+    inst = P.cinst[c];
     const InstScalars &sc = P.is[inst];
-    if (sc.halt) return;
+    if (sc.halt) {
+        inst = -1;
+        return 0.0;
+    }
     const InstParam &ip = P.ip[inst];
     const double *W = cur_state(P, inst);
     const T cfl = T(sc.cfl);
@@ -836,7 +859,6 @@ __device__ __forceinline__ void sweep_cell(const Params<T> &P, int c)
 #pragma unroll
         for (int k = 0; k < 5; k++) { acc[k] = T(0); dws[k] = P.dW[k * N + c]; }
     }
-    double nuc = P.nu[c];
     int e0 = P.cf_ptr[c], e1 = P.cf_ptr[c + 1];
     for (int e = e0; e < e1; e++) {
         int j = P.cf_nbr[e];
@@ -869,10 +891,8 @@ __device__ __forceinline__ void sweep_cell(const Params<T> &P, int c)
             else acc[k] += h * (jv[k] - lam * dj[k]);
         }
         if (ip.sa) {
-            double nuj = (j >= 0) ? P.nu[j] : mu_lam(P.mu_law, ip, lam_of(wj)) / wj[0];
             double qj = (wj[1] * nx + wj[2] * ny) / wj[0];
-            double kf = (1.0 / SA_SIGMA) * (0.5 * (nuc + nuj) + (1.0 + SA_CB2) * 0.5 * (w[4] + wj[4]));
-            double off = (-0.5 * (qj - fabs(qj)) + kf / P.frn[f]) * P.flen[f];
+            double off = -0.5 * (qj - fabs(qj)) * P.flen[f] + P.sak[f];
             acc[4] += T(off) * dj[4];
         }
     }
@@ -882,80 +902,39 @@ __device__ __forceinline__ void sweep_cell(const Params<T> &P, int c)
 #pragma unroll
         for (int k = 0; k < 4; k++) P.dW[k * N + c] = acc[k] / D;
         P.dW[4 * N + c] = ip.sa ? acc[4] / (odt + T(P.sadiag[c])) : T(0);
-    } else {
+        return 0.0;
+    }
+    T d[5];
 #pragma unroll
-        for (int k = 0; k < 4; k++) P.dW[k * N + c] = dws[k] - acc[k] / D;
-        P.dW[4 * N + c] = ip.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
-    }
-}
-
-template <typename T, bool FWD>
-__global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
-{
-    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= c1) return;
-    sweep_cell<T, FWD>(P, c);
-}
-
-// The whole sweep in one workgroup: wavefront after wavefront, separated by
-// workgroup barriers (all waves of a workgroup share one CU and its L1, so
-// the barrier orders the dW writes of one wavefront before the reads of the
-// next).  Used when wavefronts are many and narrow.
-template <typename T, bool FWD>
-__global__ __launch_bounds__(1024) void k_sweep_wg(Params<T> P, const int *lev_off, int nlev)
-{
-    for (int i = 0; i < nlev; i++) {
-        int l = FWD ? i : nlev - 1 - i;
-        int c0 = lev_off[l], c1 = lev_off[l + 1];
-        for (int c = c0 + (int)threadIdx.x; c < c1; c += (int)blockDim.x) sweep_cell<T, FWD>(P, c);
-        __syncthreads();
-    }
-}
-
-// Per cell: W^{n+1} = W^n + dW into the instance's other state buffer
-// (Eq.17), nu~ clipped at 0, positivity check, Eq.40.
-template <typename T>
-__device__ __forceinline__ double update_cell(const Params<T> &P, int c, int inst)
-{
-    const int N = P.nc;
-    const double *W = cur_state(P, inst);
-    double *Wn = (P.is[inst].ncommit & 1) ? P.Wa : P.Wb;
-    double w[5], num = 0.0, den = 0.0;
+    for (int k = 0; k < 4; k++) d[k] = dws[k] - acc[k] / D;
+    d[4] = ip.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
+#pragma unroll
+    for (int k = 0; k < 5; k++) P.dW[k * N + c] = d[k];
+    // update (Eq.17) and the Eq.40 ratio
+    double *Wn = (sc.ncommit & 1) ? P.Wa : P.Wb;
+    double wn[4], num = 0.0, den = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        double o = W[k * N + c], d = double(P.dW[k * N + c]);
-        num += d * d;
-        den += o * o;
-        w[k] = o + d;
-        Wn[k * N + c] = w[k];
+        double dd = double(d[k]);
+        num += dd * dd;
+        den += w[k] * w[k];
+        wn[k] = w[k] + dd;
+        Wn[k * N + c] = wn[k];
     }
-    double t = W[4 * N + c];
-    if (P.ip[inst].sa) t = fmax(t + double(P.dW[4 * N + c]), 0.0);
+    double t = w[4];
+    if (ip.sa) t = fmax(t + double(d[4]), 0.0);
     Wn[4 * N + c] = t;
-    double p = w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0];
-    if (!(w[0] > 0.0) || !(p > 0.0) || !isfinite(t) || !isfinite(p)) atomicOr(&P.is[inst].bad, 1);
-    double e = sqrt(num / den);
-    return isfinite(e) ? e : 0.0;
+    double p = wn[3] - 0.5 * (wn[1] * wn[1] + wn[2] * wn[2]) / wn[0];
+    if (!(wn[0] > 0.0) || !(p > 0.0) || !isfinite(t) || !isfinite(p)) atomicOr(&P.is[inst].bad, 1);
+    double r = sqrt(num / den);
+    return isfinite(r) ? r : 0.0;
 }
 
+// Per instance: accept (flip the state buffer) or reject and freeze the
+// instance, take the Eq.40 maximum, reset the slots for the next iteration
+// (block-wide, one thread per instance).
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(Params<T> P)
-{
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    int inst = -1;
-    double e = 0.0;
-    if (c < P.nc) {
-        inst = P.cinst[c];
-        if (P.is[inst].halt) inst = -1;
-        else e = update_cell(P, c, inst);
-    }
-    slot_update<false>(&P.is[0].e40_bits[0], inst, e);
-}
-
-// One thread per instance: accept (flip the state buffer) or reject and
-// freeze the instance; reset the slots for the next iteration.
-template <typename T>
-__global__ void k_commit(Params<T> P)
+__device__ __forceinline__ void commit_instances(const Params<T> &P)
 {
     int h = *P.hist_n;
     for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
@@ -973,6 +952,45 @@ __global__ void k_commit(Params<T> P)
     }
     __syncthreads();
     if (threadIdx.x == 0) *P.hist_n = h + 1;
+}
+
+template <typename T, bool FWD>
+__global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1, int commit)
+{
+    int c = c0 + xcd_block() * blockDim.x + threadIdx.x;
+    int inst = -1;
+    double e = 0.0;
+    if (c < c1) e = sweep_cell<T, FWD>(P, c, inst);
+    if (!FWD) {
+        slot_update<false>(&P.is[0].e40_bits[0], inst, e);
+        if (commit && last_block(P.ticket + 2)) commit_instances(P);
+    }
+}
+
+// The whole sweep in one workgroup: wavefront after wavefront, separated by
+// workgroup barriers (all waves of a workgroup share one CU and its L1, so
+// the barrier orders the dW writes of one wavefront before the reads of the
+// next).  Used when wavefronts are many and narrow.  Every thread runs the
+// same number of rounds, so the wave-wide slot updates see full waves.
+template <typename T, bool FWD>
+__global__ __launch_bounds__(1024) void k_sweep_wg(Params<T> P, const int *lev_off, int nlev)
+{
+    for (int i = 0; i < nlev; i++) {
+        int l = FWD ? i : nlev - 1 - i;
+        int c0 = lev_off[l], c1 = lev_off[l + 1];
+        for (int base = c0; base < c1; base += (int)blockDim.x) {
+            int c = base + (int)threadIdx.x, inst = -1;
+            double e = 0.0;
+            if (c < c1) e = sweep_cell<T, FWD>(P, c, inst);
+            if (!FWD) slot_update<false>(&P.is[0].e40_bits[0], inst, e);
+        }
+        __syncthreads();
+    }
+    if (!FWD) {
+        __threadfence();
+        __syncthreads();
+        commit_instances(P);
+    }
 }
 
 // exact distance from each centroid to the nearest wall segment of its instance
@@ -1037,7 +1055,6 @@ template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int
 template <typename T> void launch_prep(const Launch &L, const Params<T> &P)
 {
     hipLaunchKernelGGL(k_prep<T>, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), 0, L.s, P);
-    hipLaunchKernelGGL(k_dt<T>, dim3(1), dim3(64), 0, L.s, P);
 }
 template <typename T> void launch_flux(const Launch &L, const Params<T> &P)
 {
@@ -1050,27 +1067,18 @@ template <typename T> void launch_gather(const Launch &L, const Params<T> &P)
 template <typename T> void launch_reduce(const Launch &L, const Params<T> &P)
 {
     hipLaunchKernelGGL(k_isum<T>, dim3(P.ninst * RB), dim3(256), 0, L.s, P);
-    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(64), 0, L.s, P);
 }
-template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd)
+template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd, bool commit)
 {
-    if (c1 <= c0) return;
-    dim3 g(nblk(c1 - c0, L.block[3])), b(L.block[3]);
-    if (fwd) hipLaunchKernelGGL((k_sweep<T, true>), g, b, 0, L.s, P, c0, c1);
-    else hipLaunchKernelGGL((k_sweep<T, false>), g, b, 0, L.s, P, c0, c1);
+    if (c1 <= c0 && !commit) return;
+    dim3 g(c1 > c0 ? nblk(c1 - c0, L.block[3]) : 1), b(L.block[3]);
+    if (fwd) hipLaunchKernelGGL((k_sweep<T, true>), g, b, 0, L.s, P, c0, c1, 0);
+    else hipLaunchKernelGGL((k_sweep<T, false>), g, b, 0, L.s, P, c0, c1, commit ? 1 : 0);
 }
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd)
 {
     if (fwd) hipLaunchKernelGGL((k_sweep_wg<T, true>), dim3(1), dim3(1024), 0, L.s, P, lev_off, nlev);
     else hipLaunchKernelGGL((k_sweep_wg<T, false>), dim3(1), dim3(1024), 0, L.s, P, lev_off, nlev);
-}
-template <typename T> void launch_update(const Launch &L, const Params<T> &P)
-{
-    hipLaunchKernelGGL(k_update<T>, dim3(nblk(P.nc, L.block[4])), dim3(L.block[4]), 0, L.s, P);
-}
-template <typename T> void launch_commit(const Launch &L, const Params<T> &P)
-{
-    hipLaunchKernelGGL(k_commit<T>, dim3(1), dim3(64), 0, L.s, P);
 }
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
                           const int *woff, const double *wseg, double *dwall)
@@ -1102,10 +1110,8 @@ void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, cons
     template void launch_flux<T>(const Launch &, const Params<T> &);                               \
     template void launch_gather<T>(const Launch &, const Params<T> &);                             \
     template void launch_reduce<T>(const Launch &, const Params<T> &);                             \
-    template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, bool);              \
-    template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool);   \
-    template void launch_update<T>(const Launch &, const Params<T> &);                             \
-    template void launch_commit<T>(const Launch &, const Params<T> &);
+    template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, bool, bool);        \
+    template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool);
 INST(double)
 INST(float)
 

@@ -124,7 +124,7 @@ def _mesh_args(mesh):
     return keep, (mesh.n_nodes, pxy, mesh.n_cells, pcp, pcn, mesh.n_bfaces, pbn, pbt)
 
 
-KERNEL_CLASSES = ("prep", "flux", "gather", "reduce", "sweep_fwd", "sweep_bwd", "update")
+KERNEL_CLASSES = ("prep", "flux", "gather", "reduce", "sweep_fwd", "sweep_bwd")
 
 
 class _Context:
@@ -178,17 +178,17 @@ class _Context:
         self._chk(igks_set_profiling(self.ctx, 1 if on else 0))
 
     def kernel_times(self):
-        t = np.zeros(7)
+        t = np.zeros(len(KERNEL_CLASSES))
         self._chk(igks_get_kernel_times(self.ctx, t.ctypes.data_as(_DP)))
         return dict(zip(KERNEL_CLASSES, t))
 
     def autotune(self, iters=10):
-        s = np.zeros(6, dtype=np.int32)
+        s = np.zeros(5, dtype=np.int32)
         self._chk(igks_autotune(self.ctx, iters, s.ctypes.data_as(_IP)))
         return s
 
     def schedule(self):
-        s = np.zeros(6, dtype=np.int32)
+        s = np.zeros(5, dtype=np.int32)
         self._chk(igks_get_schedule(self.ctx, s.ctypes.data_as(_IP)))
         return s
 

@@ -24,7 +24,7 @@ def kernel_class(name: str):
              ("k_sweep_wg<float, true>", "sweep_fwd"), ("k_sweep_wg<float, false>", "sweep_bwd"),
              ("k_sweep<double, true>", "sweep_fwd"), ("k_sweep<double, false>", "sweep_bwd"),
              ("k_sweep<float, true>", "sweep_fwd"), ("k_sweep<float, false>", "sweep_bwd"),
-             ("k_update", "update"), ("k_commit", "commit"), ("k_reset", "reset")]
+             ("k_isum", "reduce"), ("k_reset", "reset")]
     for key, cls in table:
         if key in name:
             return cls
