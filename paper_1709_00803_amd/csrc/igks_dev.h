@@ -26,7 +26,6 @@ constexpr int MAXV = 4;       // vertices per cell (triangles padded by repeatin
 constexpr int HIST_W = 6;     // doubles per history entry
 constexpr int NSLOT = 64;     // atomic min/max targets of one instance are spread over this many slots
 constexpr int RB = 32;        // blocks per instance in the residual-norm reduction
-constexpr int NTICKET = 4;    // last-block tickets: prep, norms, backward sweep
 constexpr int NCLASS = 4;     // kernel classes with a tunable block size: prep, flux, gather, sweep
 
 // Free stream of one instance (read-only while iterating).
@@ -90,7 +89,6 @@ struct Params {
     const int *icell, *ioff;
     const int *ipos;           // position of each cell in icell
     double *ipart;             // ninst x RB x 2 partial sums
-    unsigned *ticket;          // NTICKET counters, zero between launches
     double *hist;              // HIST_W x ninst x hist_cap
     int hist_cap;
 };
@@ -105,10 +103,11 @@ template <typename T> void launch_prep(const Launch &L, const Params<T> &P);
 template <typename T> void launch_flux(const Launch &L, const Params<T> &P);
 template <typename T> void launch_gather(const Launch &L, const Params<T> &P);
 template <typename T> void launch_reduce(const Launch &L, const Params<T> &P);
-// backward sweeps also update the state (Eq.17) and, in their last launch
-// (commit = true), accept or reject the iteration of every instance
-template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd, bool commit);
+// backward sweeps also update the state (Eq.17); launch_commit then accepts
+// or rejects the iteration of every instance
+template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd);
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd);
+template <typename T> void launch_commit(const Launch &L, const Params<T> &P);
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
                           const int *woff, const double *wseg, double *dwall);
 void launch_gather_faces(const Launch &L, int n, const int *faces, const double *flux, int nf, double *out);

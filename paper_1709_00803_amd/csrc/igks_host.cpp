@@ -61,7 +61,7 @@ constexpr int NKT = 6;
 struct WsMap {
     Buf ip, is, hist_n, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx;
     Buf cinst, finst, icell, ioff, g2i, cf_ptr, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
-    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, sak, ipart, hist, ipos, ticket;
+    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, sak, ipart, hist, ipos;
     Buf wall_faces, wall_out, woff, wseg, lev_off, stage, backup;
     size_t total;
 };
@@ -453,7 +453,6 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.sak = L.add(F * D);
     w.ipart = L.add(2 * NI * RB * D);
     w.ipos = L.add(N * I);
-    w.ticket = L.add(NTICKET * sizeof(unsigned));
     w.hist = L.add((size_t)HIST_W * NI * hist_cap * D);
     w.wall_faces = L.add(NW * I);
     w.wall_out = L.add(4 * NW * D);
@@ -493,7 +492,6 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.fdl = D(w.fdl); P.fdr = D(w.fdr); P.frn = D(w.frn);
     P.flux = D(w.flux); P.lam = D(w.lam); P.saf = D(w.saf); P.sag = D(w.sag); P.sak = D(w.sak);
     P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipos = In(w.ipos); P.ipart = D(w.ipart);
-    P.ticket = (unsigned *)(b + w.ticket.off);
     P.hist = D(w.hist); P.hist_cap = c->hist_cap;
 }
 
@@ -524,12 +522,13 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev)
     mark(4);
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, true);
     else
-        for (int l = 0; l < G.nlev; l++) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], true, false);
+        for (int l = 0; l < G.nlev; l++) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], true);
     mark(5);
-    // backward sweep with the update; its last launch commits
+    // backward sweep with the update
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, false);
     else
-        for (int l = G.nlev - 1; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], false, l == 0);
+        for (int l = G.nlev - 1; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], false);
+    launch_commit(L, P);
     mark(6);
 }
 
@@ -903,7 +902,6 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     for (auto &m : c->inst) std::memset(&m.ip, 0, sizeof m.ip);
     rc = up(w.ip, ip0.data(), sizeof(InstParam) * ip0.size());
     if (rc) return rc;
-    HIPCHK(c, hipMemsetAsync(b + w.ticket.off, 0, w.ticket.bytes, c->stream));
     Launch L = launch_of(c);
     launch_wall_distance(L, G.N, c->P64.xc, c->P64.yc, c->P64.cinst, (const int *)(b + w.woff.off),
                          (const double *)(b + w.wseg.off), (double *)(b + w.dwall.off));

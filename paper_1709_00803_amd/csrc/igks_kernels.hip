@@ -1,11 +1,13 @@
 // igks_kernels.hip - HIP kernels of the implicit gas-kinetic scheme for
 // gfx950 (MI355X).
 //
-// One iteration = prep (per cell; its last block takes the per-instance
-// Eq.23 time step) -> flux (per face) -> gather (per cell) -> norm partial
-// sums (their last block: per-instance norms and the Eq.25 CFL) -> forward
-// sweep (one launch per wavefront) -> backward sweep with the state update
-// (the last block of its last launch commits or rejects every instance).
+// One iteration = prep (per cell) -> flux (per face; each wave first takes
+// the Eq.23 time step of its instance from the prep minima) -> gather (per
+// cell) -> norm partial sums -> reduce (per instance: norms, Eq.25 CFL) ->
+// forward sweep (one launch per wavefront) -> backward sweep with the state
+// update -> commit (per instance).  No kernel waits on another inside a
+// launch: ordering comes from launch boundaries only (device-scope fences
+// inside a kernel would write back the XCD's whole L2).
 //
 // Data are structure-of-arrays in the library's internal cell order
 // (wavefront, then instance, then upload index) and face order (owner
@@ -131,22 +133,6 @@ __device__ __forceinline__ int xcd_block()
     int nb = (int)gridDim.x, b = (int)blockIdx.x;
     int q = nb / nxcd, r = nb % nxcd, x = b % nxcd;
     return x * q + min(x, r) + b / nxcd;
-}
-
-// Every block publishes its writes and takes a ticket; true in the block
-// that takes the last one, which then sees the writes of all the others.
-// That block puts the counter back to zero for the next launch.
-__device__ __forceinline__ bool last_block(unsigned *ticket)
-{
-    __shared__ int is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) is_last = atomicAdd(ticket, 1u) == gridDim.x - 1u;
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    if (threadIdx.x == 0) atomicExch(ticket, 0u);
-    return true;
 }
 
 __device__ __forceinline__ double wave_min(double v)
@@ -551,9 +537,21 @@ __global__ __launch_bounds__(256) void k_prep(Params<T> P)
         else dt = prep_cell(P, c, inst);
     }
     slot_update<true>(&P.is[0].dtmin_bits[0], inst, dt);   // Eq.23: minimum over the instance's cells
-    if (last_block(P.ticket + 0))
-        for (int i = threadIdx.x; i < P.ninst; i += blockDim.x)
-            if (!P.is[i].halt) P.is[i].dt = slots_min_serial(P.is[i].dtmin_bits);
+}
+
+// The Eq.23 time step of the lane's instance: the minimum over its slots.
+// A wave whose lanes share one instance reads the 64 slots one per lane.
+__device__ __forceinline__ double instance_dt(const InstScalars *is, int inst)
+{
+    int lane = (int)(threadIdx.x & (warpSize - 1));
+    unsigned long long act = __ballot(inst >= 0);
+    if (act == 0ull) return 0.0;
+    int i0 = __shfl(inst, __ffsll((long long)act) - 1);
+    if (__all(inst < 0 || inst == i0)) {
+        double v = __longlong_as_double((long long)is[i0].dtmin_bits[lane & (NSLOT - 1)]);
+        return wave_min(v);
+    }
+    return inst >= 0 ? slots_min_serial(is[inst].dtmin_bits) : 0.0;
 }
 
 __device__ __forceinline__ bool physical(const double *w)
@@ -564,12 +562,11 @@ __device__ __forceinline__ bool physical(const double *w)
 // Per face: reconstruction (Eq.10), ghost side, the GKS flux, the LU-SGS
 // spectral radius and the SA face terms (Eq.28-30).
 template <typename T>
-__device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst)
+__device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, double dt)
 {
     const int N = P.nc, F = P.nf;
     const InstParam &ip = P.ip[inst];
     const double *W = cur_state(P, inst);
-    const double dt = P.is[inst].dt;
     int l = P.fl[f], rr = P.fr[f];
     double nx = P.fnx[f], ny = P.fny[f], S = P.flen[f];
     double tx = -ny, ty = nx;
@@ -689,10 +686,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_flux(Params<T> P)
 {
     int f = xcd_block() * blockDim.x + threadIdx.x;
-    if (f >= P.nf) return;
-    int inst = P.finst[f];
-    if (P.is[inst].halt) return;
-    flux_face(P, f, inst);
+    int inst = -1;
+    if (f < P.nf) {
+        inst = P.finst[f];
+        if (P.is[inst].halt) inst = -1;
+    }
+    double dt = instance_dt(P.is, inst);
+    if (inst < 0) return;
+    flux_face(P, f, inst, dt);
 }
 
 // Per cell: residual M (Eq.16) as the signed sum of its face fluxes, the
@@ -758,15 +759,16 @@ __global__ __launch_bounds__(256) void k_gather(Params<T> P)
     slot_update<false>(&P.is[0].resinf_bits[0], inst, rinf);
 }
 
-// Per instance: L2 norms in a fixed order, max norm, the Eq.25 CFL law,
-// history (one thread per instance).
+// One thread per instance: L2 norms in a fixed order, max norm, the Eq.25
+// CFL law, history.
 template <typename T>
-__device__ __forceinline__ void reduce_instances(const Params<T> &P)
+__global__ void k_reduce(Params<T> P)
 {
     int h = *P.hist_n;
     for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
         InstScalars *s = &P.is[i];
         if (s->halt) continue;
+        s->dt = slots_min_serial(s->dtmin_bits);   // the time step the flux used
         double x = 0.0, y = 0.0;
         for (int b = 0; b < RB; b++) { x += P.ipart[2 * (i * RB + b)]; y += P.ipart[2 * (i * RB + b) + 1]; }
         double l2 = sqrt(x), sal2 = sqrt(y);
@@ -794,8 +796,7 @@ __device__ __forceinline__ void reduce_instances(const Params<T> &P)
 
 // Norm partial sums: block (i, b) sums slice b of instance i's squares
 // (contiguous, instance-grouped) in a fixed order, so the L2 norms are
-// deterministic without float atomics; the last block finishes the
-// per-instance reduction.
+// deterministic without float atomics.
 template <typename T>
 __global__ __launch_bounds__(256) void k_isum(Params<T> P)
 {
@@ -822,7 +823,6 @@ __global__ __launch_bounds__(256) void k_isum(Params<T> P)
         P.ipart[2 * blockIdx.x] = a[0];
         P.ipart[2 * blockIdx.x + 1] = b[0];
     }
-    if (last_block(P.ticket + 1)) reduce_instances(P);
 }
 
 // One wavefront of the forward (FWD) or backward LU-SGS sweep (Eq.22): the
@@ -930,11 +930,11 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     return isfinite(r) ? r : 0.0;
 }
 
-// Per instance: accept (flip the state buffer) or reject and freeze the
-// instance, take the Eq.40 maximum, reset the slots for the next iteration
-// (block-wide, one thread per instance).
+// One thread per instance: accept (flip the state buffer) or reject and
+// freeze the instance, take the Eq.40 maximum, reset the slots for the next
+// iteration.
 template <typename T>
-__device__ __forceinline__ void commit_instances(const Params<T> &P)
+__global__ void k_commit(Params<T> P)
 {
     int h = *P.hist_n;
     for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
@@ -955,16 +955,13 @@ __device__ __forceinline__ void commit_instances(const Params<T> &P)
 }
 
 template <typename T, bool FWD>
-__global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1, int commit)
+__global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
 {
     int c = c0 + xcd_block() * blockDim.x + threadIdx.x;
     int inst = -1;
     double e = 0.0;
     if (c < c1) e = sweep_cell<T, FWD>(P, c, inst);
-    if (!FWD) {
-        slot_update<false>(&P.is[0].e40_bits[0], inst, e);
-        if (commit && last_block(P.ticket + 2)) commit_instances(P);
-    }
+    if (!FWD) slot_update<false>(&P.is[0].e40_bits[0], inst, e);
 }
 
 // The whole sweep in one workgroup: wavefront after wavefront, separated by
@@ -985,11 +982,6 @@ __global__ __launch_bounds__(1024) void k_sweep_wg(Params<T> P, const int *lev_o
             if (!FWD) slot_update<false>(&P.is[0].e40_bits[0], inst, e);
         }
         __syncthreads();
-    }
-    if (!FWD) {
-        __threadfence();
-        __syncthreads();
-        commit_instances(P);
     }
 }
 
@@ -1056,6 +1048,10 @@ template <typename T> void launch_prep(const Launch &L, const Params<T> &P)
 {
     hipLaunchKernelGGL(k_prep<T>, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), 0, L.s, P);
 }
+template <typename T> void launch_commit(const Launch &L, const Params<T> &P)
+{
+    hipLaunchKernelGGL(k_commit<T>, dim3(1), dim3(64), 0, L.s, P);
+}
 template <typename T> void launch_flux(const Launch &L, const Params<T> &P)
 {
     hipLaunchKernelGGL(k_flux<T>, dim3(nblk(P.nf, L.block[1])), dim3(L.block[1]), 0, L.s, P);
@@ -1067,13 +1063,14 @@ template <typename T> void launch_gather(const Launch &L, const Params<T> &P)
 template <typename T> void launch_reduce(const Launch &L, const Params<T> &P)
 {
     hipLaunchKernelGGL(k_isum<T>, dim3(P.ninst * RB), dim3(256), 0, L.s, P);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(64), 0, L.s, P);
 }
-template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd, bool commit)
+template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd)
 {
-    if (c1 <= c0 && !commit) return;
-    dim3 g(c1 > c0 ? nblk(c1 - c0, L.block[3]) : 1), b(L.block[3]);
-    if (fwd) hipLaunchKernelGGL((k_sweep<T, true>), g, b, 0, L.s, P, c0, c1, 0);
-    else hipLaunchKernelGGL((k_sweep<T, false>), g, b, 0, L.s, P, c0, c1, commit ? 1 : 0);
+    if (c1 <= c0) return;
+    dim3 g(nblk(c1 - c0, L.block[3])), b(L.block[3]);
+    if (fwd) hipLaunchKernelGGL((k_sweep<T, true>), g, b, 0, L.s, P, c0, c1);
+    else hipLaunchKernelGGL((k_sweep<T, false>), g, b, 0, L.s, P, c0, c1);
 }
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd)
 {
@@ -1110,7 +1107,8 @@ void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, cons
     template void launch_flux<T>(const Launch &, const Params<T> &);                               \
     template void launch_gather<T>(const Launch &, const Params<T> &);                             \
     template void launch_reduce<T>(const Launch &, const Params<T> &);                             \
-    template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, bool, bool);        \
+    template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, bool);              \
+    template void launch_commit<T>(const Launch &, const Params<T> &);                             \
     template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool);
 INST(double)
 INST(float)
