@@ -21,6 +21,7 @@ enum { BC_FREESTREAM = 1, BC_SYMMETRY = 2, BC_WALL = 3, BC_OUTFLOW = 4, BC_FARFI
 // cell -> face entry flags
 constexpr int CF_OWNER = 1;   // the cell is the face's owner (normal points outward)
 constexpr int CF_LOWER = 2;   // interior neighbour with a smaller upload index
+constexpr int CF_VALID = 4;   // the entry exists (triangles leave their fourth entry empty)
 
 constexpr int MAXV = 4;       // vertices per cell (triangles padded by repeating a vertex)
 constexpr int HIST_W = 6;     // doubles per history entry
@@ -75,7 +76,9 @@ struct Params {
     double *r2;                // squares for the norms, M_rho^2 then R_SA^2, at the cell's ipos
     T *dW;                     // LU-SGS increment, 5 x nc
     const double *xc, *yc, *area, *lsinv, *dwall, *vtx;
-    const int *cf_ptr, *cf_face, *cf_nbr, *cf_flag;
+    // cell-face entries, MAXV per cell (entry MAXV c + k): face, neighbour
+    // (-1: ghost cell), flags, centroid offsets to the neighbour (or ghost)
+    const int *cf_face, *cf_nbr, *cf_flag;
     const double *cf_dx, *cf_dy;
     // face arrays (internal face order)
     const int *fl, *fr, *fbc;

@@ -43,7 +43,7 @@ struct Global {
     std::vector<int> g2i;            // global upload id -> internal cell
     std::vector<int> cinst, finst, icell, ioff, ipos;
     std::vector<double> xc, yc, area, lsinv, vtx;
-    std::vector<int> cf_ptr, cf_face, cf_nbr, cf_flag;
+    std::vector<int> cf_face, cf_nbr, cf_flag;   // MAXV entries per cell
     std::vector<double> cf_dx, cf_dy;
     std::vector<int> fl, fr, ftag;
     std::vector<double> fnx, fny, flen, frl, frr, fdl, fdr, frn, fxm;
@@ -60,7 +60,7 @@ constexpr int NKT = 6;
 
 struct WsMap {
     Buf ip, is, hist_n, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx;
-    Buf cinst, finst, icell, ioff, g2i, cf_ptr, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
+    Buf cinst, finst, icell, ioff, g2i, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
     Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, sak, ipart, hist, ipos;
     Buf wall_faces, wall_out, woff, wseg, lev_off, stage, backup;
     size_t total;
@@ -361,20 +361,17 @@ int combine(igks_ctx *ctx)
     // cells in internal order
     G.xc.resize(N); G.yc.resize(N); G.area.resize(N); G.lsinv.resize(3 * (size_t)N);
     G.vtx.resize(2 * MAXV * (size_t)N);
-    G.cf_ptr.assign(N + 1, 0);
-    for (int c = 0; c < N; c++) {
-        const InstMesh &m = ctx->inst[gi[order[c]]];
-        int u = gu[order[c]];
-        G.cf_ptr[c + 1] = G.cf_ptr[c] + (m.cf_ptr[u + 1] - m.cf_ptr[u]);
-    }
-    const int ne = G.cf_ptr[N];
-    G.cf_face.resize(ne); G.cf_nbr.resize(ne); G.cf_flag.resize(ne); G.cf_dx.resize(ne); G.cf_dy.resize(ne);
+    // entries: MAXV per cell, in the order of the cell's faces; unused
+    // entries point at the cell's first face with no flags
+    const size_t ne = (size_t)MAXV * N;
+    G.cf_face.assign(ne, 0); G.cf_nbr.assign(ne, -1); G.cf_flag.assign(ne, 0);
+    G.cf_dx.assign(ne, 0.0); G.cf_dy.assign(ne, 0.0);
     for (int c = 0; c < N; c++) {
         const int i = gi[order[c]], u = gu[order[c]], off = G.coff[i];
         const InstMesh &m = ctx->inst[i];
         G.xc[c] = m.xc[u]; G.yc[c] = m.yc[u]; G.area[c] = m.area[u];
         double a11 = 0, a12 = 0, a22 = 0;
-        int e = G.cf_ptr[c];
+        size_t e = (size_t)MAXV * c;
         for (int k = m.cf_ptr[u]; k < m.cf_ptr[u + 1]; k++) {
             const int q = m.cf_list[k];
             const auto &f = m.uf[q];
@@ -391,12 +388,13 @@ int combine(igks_ctx *ctx)
             }
             G.cf_face[e] = qi;
             G.cf_nbr[e] = other >= 0 ? G.g2i[off + other] : -1;
-            G.cf_flag[e] = (own ? CF_OWNER : 0) | ((other >= 0 && other < u) ? CF_LOWER : 0);
+            G.cf_flag[e] = CF_VALID | (own ? CF_OWNER : 0) | ((other >= 0 && other < u) ? CF_LOWER : 0);
             G.cf_dx[e] = dx;
             G.cf_dy[e] = dy;
             a11 += dx * dx; a12 += dx * dy; a22 += dy * dy;
             e++;
         }
+        for (size_t k = e; k < (size_t)MAXV * (c + 1); k++) G.cf_face[k] = G.cf_face[(size_t)MAXV * c];
         double det = a11 * a22 - a12 * a12;
         if (!(det > 0))
             return fail(ctx, IGKS_EMESH, "instance " + std::to_string(i) + ": singular least-squares stencil at cell " +
@@ -431,7 +429,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
 {
     Layout L;
     WsMap w;
-    const size_t N = G.N, F = G.F, E = G.cf_ptr.empty() ? 0 : (size_t)G.cf_ptr.back(), D = sizeof(double),
+    const size_t N = G.N, F = G.F, E = (size_t)MAXV * G.N, D = sizeof(double),
                  I = sizeof(int), NI = ninst, NW = std::max(1, G.nwall);
     w.ip = L.add(NI * sizeof(InstParam));
     w.is = L.add(NI * sizeof(InstScalars));
@@ -444,7 +442,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.dwall = L.add(N * D); w.vtx = L.add(2 * MAXV * N * D);
     w.cinst = L.add(N * I); w.finst = L.add(F * I); w.icell = L.add(N * I); w.ioff = L.add((NI + 1) * I);
     w.g2i = L.add(N * I);
-    w.cf_ptr = L.add((N + 1) * I); w.cf_face = L.add(E * I); w.cf_nbr = L.add(E * I); w.cf_flag = L.add(E * I);
+    w.cf_face = L.add(E * I); w.cf_nbr = L.add(E * I); w.cf_flag = L.add(E * I);
     w.cf_dx = L.add(E * D); w.cf_dy = L.add(E * D);
     w.fl = L.add(F * I); w.fr = L.add(F * I); w.fbc = L.add(F * I);
     w.fnx = L.add(F * D); w.fny = L.add(F * D); w.flen = L.add(F * D); w.frl = L.add(2 * F * D);
@@ -485,7 +483,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.Wa = D(w.Wa); P.Wb = D(w.Wb); P.grad = D(w.grad); P.lamc = D(w.lamc); P.vort = D(w.vort); P.nu = D(w.nu);
     P.M = D(w.M); P.lsum = D(w.lsum); P.sadiag = D(w.sadiag); P.r2 = D(w.r2); P.dW = (T *)(b + w.dW.off);
     P.xc = D(w.xc); P.yc = D(w.yc); P.area = D(w.area); P.lsinv = D(w.lsinv); P.dwall = D(w.dwall); P.vtx = D(w.vtx);
-    P.cf_ptr = In(w.cf_ptr); P.cf_face = In(w.cf_face); P.cf_nbr = In(w.cf_nbr); P.cf_flag = In(w.cf_flag);
+    P.cf_face = In(w.cf_face); P.cf_nbr = In(w.cf_nbr); P.cf_flag = In(w.cf_flag);
     P.cf_dx = D(w.cf_dx); P.cf_dy = D(w.cf_dy);
     P.fl = In(w.fl); P.fr = In(w.fr); P.fbc = In(w.fbc);
     P.fnx = D(w.fnx); P.fny = D(w.fny); P.flen = D(w.flen); P.frl = D(w.frl); P.frr = D(w.frr);
@@ -872,7 +870,7 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
         HIPCHK(c, hipMemcpyAsync(b + x.off, src, n, hipMemcpyHostToDevice, c->stream));
         return IGKS_OK;
     };
-    const size_t D = sizeof(double), I = sizeof(int), N = G.N, F = G.F, E = G.cf_ptr.back();
+    const size_t D = sizeof(double), I = sizeof(int), N = G.N, F = G.F, E = (size_t)MAXV * G.N;
     rc = 0;
     rc |= up(w.xc, G.xc.data(), N * D); rc |= up(w.yc, G.yc.data(), N * D); rc |= up(w.area, G.area.data(), N * D);
     rc |= up(w.lsinv, G.lsinv.data(), 3 * N * D); rc |= up(w.vtx, G.vtx.data(), 2 * MAXV * N * D);
@@ -880,7 +878,7 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     rc |= up(w.icell, G.icell.data(), N * I); rc |= up(w.ioff, G.ioff.data(), G.ioff.size() * I);
     rc |= up(w.ipos, G.ipos.data(), N * I);
     rc |= up(w.g2i, G.g2i.data(), N * I);
-    rc |= up(w.cf_ptr, G.cf_ptr.data(), (N + 1) * I); rc |= up(w.cf_face, G.cf_face.data(), E * I);
+    rc |= up(w.cf_face, G.cf_face.data(), E * I);
     rc |= up(w.cf_nbr, G.cf_nbr.data(), E * I); rc |= up(w.cf_flag, G.cf_flag.data(), E * I);
     rc |= up(w.cf_dx, G.cf_dx.data(), E * D); rc |= up(w.cf_dy, G.cf_dy.data(), E * D);
     rc |= up(w.fl, G.fl.data(), F * I); rc |= up(w.fr, G.fr.data(), F * I); rc |= up(w.fbc, G.ftag.data(), F * I);

@@ -187,6 +187,32 @@ __device__ __forceinline__ double slots_max_serial(const unsigned long long *b)
     return v;
 }
 
+// The (up to) four cell-face entries of cell c: face, neighbour (-1: ghost)
+// and flags, one 16-byte load each.
+struct Entries {
+    int face[MAXV], nbr[MAXV], flag[MAXV];
+};
+template <typename T>
+__device__ __forceinline__ Entries entries(const Params<T> &P, int c)
+{
+    const int4 f = reinterpret_cast<const int4 *>(P.cf_face)[c];
+    const int4 n = reinterpret_cast<const int4 *>(P.cf_nbr)[c];
+    const int4 g = reinterpret_cast<const int4 *>(P.cf_flag)[c];
+    return Entries{{f.x, f.y, f.z, f.w}, {n.x, n.y, n.z, n.w}, {g.x, g.y, g.z, g.w}};
+}
+
+// instance of a cell / face (a one-instance context needs no lookup)
+template <typename T>
+__device__ __forceinline__ int cell_inst(const Params<T> &P, int c)
+{
+    return P.ninst == 1 ? 0 : P.cinst[c];
+}
+template <typename T>
+__device__ __forceinline__ int face_inst(const Params<T> &P, int f)
+{
+    return P.ninst == 1 ? 0 : P.finst[f];
+}
+
 template <typename T>
 __device__ __forceinline__ const double *cur_state(const Params<T> &P, int inst)
 {
@@ -463,12 +489,13 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
     double lc = 0.0, b1[4] = {0, 0, 0, 0}, b2[4] = {0, 0, 0, 0}, wmax[4], wmin[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) wmax[k] = wmin[k] = w[k];
-    int e0 = P.cf_ptr[c], e1 = P.cf_ptr[c + 1];
-    for (int e = e0; e < e1; e++) {
-        int f = P.cf_face[e];
+    const Entries E = entries(P, c);
+#pragma unroll
+    for (int k = 0; k < MAXV; k++) {
+        if (!(E.flag[k] & CF_VALID)) continue;
+        const int e = MAXV * c + k, f = E.face[k], j = E.nbr[k];
         double nx = P.fnx[f], ny = P.fny[f], S = P.flen[f];
         lc += (fabs(U * nx + V * ny) + cs) * S;
-        int j = P.cf_nbr[e];
         double wj[5];
         if (j >= 0) {
 #pragma unroll
@@ -532,7 +559,7 @@ __global__ __launch_bounds__(256) void k_prep(Params<T> P)
     int inst = -1;
     double dt = INFINITY;
     if (c < P.nc) {
-        inst = P.cinst[c];
+        inst = cell_inst(P, c);
         if (P.is[inst].halt) inst = -1;
         else dt = prep_cell(P, c, inst);
     }
@@ -688,7 +715,7 @@ __global__ __launch_bounds__(256) void k_flux(Params<T> P)
     int f = xcd_block() * blockDim.x + threadIdx.x;
     int inst = -1;
     if (f < P.nf) {
-        inst = P.finst[f];
+        inst = face_inst(P, f);
         if (P.is[inst].halt) inst = -1;
     }
     double dt = instance_dt(P.is, inst);
@@ -710,10 +737,12 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
     double nuc = P.nu[c];
-    int e0 = P.cf_ptr[c], e1 = P.cf_ptr[c + 1];
-    for (int e = e0; e < e1; e++) {
-        int f = P.cf_face[e];
-        double sg = (P.cf_flag[e] & CF_OWNER) ? 1.0 : -1.0;
+    const Entries E = entries(P, c);
+#pragma unroll
+    for (int k = 0; k < MAXV; k++) {
+        if (!(E.flag[k] & CF_VALID)) continue;
+        const int f = E.face[k];
+        double sg = (E.flag[k] & CF_OWNER) ? 1.0 : -1.0;
 #pragma unroll
         for (int k = 0; k < 4; k++) m[k] -= sg * P.flux[k * F + f];
         double S = P.flen[f];
@@ -752,7 +781,7 @@ __global__ __launch_bounds__(256) void k_gather(Params<T> P)
     int inst = -1;
     double rinf = 0.0;
     if (c < P.nc) {
-        inst = P.cinst[c];
+        inst = cell_inst(P, c);
         if (P.is[inst].halt) inst = -1;
         else rinf = gather_cell(P, c, inst);
     }
@@ -839,7 +868,7 @@ template <typename T, bool FWD>
 __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &inst)
 {
     const int N = P.nc;
-    inst = P.cinst[c];
+    inst = cell_inst(P, c);
     const InstScalars &sc = P.is[inst];
     if (sc.halt) {
         inst = -1;
@@ -859,16 +888,17 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
 #pragma unroll
         for (int k = 0; k < 5; k++) { acc[k] = T(0); dws[k] = P.dW[k * N + c]; }
     }
-    int e0 = P.cf_ptr[c], e1 = P.cf_ptr[c + 1];
-    for (int e = e0; e < e1; e++) {
-        int j = P.cf_nbr[e];
-        int fl = P.cf_flag[e];
+    const Entries E = entries(P, c);
+#pragma unroll
+    for (int k = 0; k < MAXV; k++) {
+        const int j = E.nbr[k], fl = E.flag[k];
+        if (!(fl & CF_VALID)) continue;
         if (FWD) {
             if (j < 0 || !(fl & CF_LOWER)) continue;
         } else {
             if (j >= 0 && (fl & CF_LOWER)) continue;
         }
-        int f = P.cf_face[e];
+        const int f = E.face[k];
         double sg = (fl & CF_OWNER) ? 1.0 : -1.0;
         double nx = sg * P.fnx[f], ny = sg * P.fny[f];
         T S = T(P.flen[f]), lam = T(P.lam[f]);
