@@ -63,7 +63,6 @@ struct Params {
     const int *cinst, *finst;  // instance of each cell / face
     const InstParam *ip;
     InstScalars *is;
-    int *hist_n;               // history entries written in the current chunk
     // cell arrays (SoA, internal order)
     double *Wa, *Wb;           // state ping-pong, 5 x nc
     double *grad;              // limited gradients: d/dx of rho, rhoU, rhoV, rhoE, then d/dy
@@ -105,12 +104,13 @@ template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int
 template <typename T> void launch_prep(const Launch &L, const Params<T> &P);
 template <typename T> void launch_flux(const Launch &L, const Params<T> &P);
 template <typename T> void launch_gather(const Launch &L, const Params<T> &P);
-template <typename T> void launch_reduce(const Launch &L, const Params<T> &P);
+// it: the iteration's index in the current chunk (its history entry)
+template <typename T> void launch_reduce(const Launch &L, const Params<T> &P, int it);
 // backward sweeps also update the state (Eq.17); launch_commit then accepts
 // or rejects the iteration of every instance
 template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd);
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd);
-template <typename T> void launch_commit(const Launch &L, const Params<T> &P);
+template <typename T> void launch_commit(const Launch &L, const Params<T> &P, int it);
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
                           const int *woff, const double *wseg, double *dwall);
 void launch_gather_faces(const Launch &L, int n, const int *faces, const double *flux, int nf, double *out);

@@ -59,7 +59,7 @@ struct Buf {
 constexpr int NKT = 6;
 
 struct WsMap {
-    Buf ip, is, hist_n, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx;
+    Buf ip, is, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx;
     Buf cinst, finst, icell, ioff, g2i, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
     Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, sak, ipart, hist, ipos;
     Buf wall_faces, wall_out, woff, wseg, lev_off, stage, backup;
@@ -433,7 +433,6 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
                  I = sizeof(int), NI = ninst, NW = std::max(1, G.nwall);
     w.ip = L.add(NI * sizeof(InstParam));
     w.is = L.add(NI * sizeof(InstScalars));
-    w.hist_n = L.add(I);
     w.Wa = L.add(5 * N * D); w.Wb = L.add(5 * N * D);
     w.grad = L.add(8 * N * D); w.lamc = L.add(N * D); w.vort = L.add(N * D); w.nu = L.add(N * D);
     w.M = L.add(5 * N * D); w.lsum = L.add(N * D); w.sadiag = L.add(N * D); w.r2 = L.add(2 * N * D);
@@ -479,7 +478,6 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.cinst = In(w.cinst); P.finst = In(w.finst);
     P.ip = (const InstParam *)(b + w.ip.off);
     P.is = (InstScalars *)(b + w.is.off);
-    P.hist_n = In(w.hist_n);
     P.Wa = D(w.Wa); P.Wb = D(w.Wb); P.grad = D(w.grad); P.lamc = D(w.lamc); P.vort = D(w.vort); P.nu = D(w.nu);
     P.M = D(w.M); P.lsum = D(w.lsum); P.sadiag = D(w.sadiag); P.r2 = D(w.r2); P.dW = (T *)(b + w.dW.off);
     P.xc = D(w.xc); P.yc = D(w.yc); P.area = D(w.area); P.lsinv = D(w.lsinv); P.dwall = D(w.dwall); P.vtx = D(w.vtx);
@@ -503,7 +501,7 @@ Launch launch_of(igks_ctx *c)
 
 // queue one nonlinear iteration of every instance
 template <typename T>
-void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev)
+void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev, int it)
 {
     Launch L = launch_of(c);
     const int *lev = (const int *)(c->ws + c->w.lev_off.off);
@@ -516,7 +514,7 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev)
     mark(2);
     launch_gather(L, P);
     mark(3);
-    launch_reduce(L, P);
+    launch_reduce(L, P, it);
     mark(4);
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, true);
     else
@@ -526,7 +524,7 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev)
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, false);
     else
         for (int l = G.nlev - 1; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], false);
-    launch_commit(L, P);
+    launch_commit(L, P, it);
     mark(6);
 }
 
@@ -552,13 +550,11 @@ int sync_scalars(igks_ctx *c)
 template <typename T>
 int run_chunk(igks_ctx *c, const Params<T> &P, int k)
 {
-    Launch L = launch_of(c);
-    launch_reset(L, P, 4, -1);
     if (c->profiling) {
         hipEvent_t ev[NKT + 1];
         for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
         for (int i = 0; i < k; i++) {
-            queue_iteration(c, P, ev);
+            queue_iteration(c, P, ev, i);
             HIPCHK(c, hipEventSynchronize(ev[NKT]));
             for (int j = 0; j < NKT; j++) {
                 float ms = 0;
@@ -571,7 +567,7 @@ int run_chunk(igks_ctx *c, const Params<T> &P, int k)
         if (!c->gexec) {
             hipGraph_t g;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            for (int i = 0; i < k; i++) queue_iteration(c, P, nullptr);
+            for (int i = 0; i < k; i++) queue_iteration(c, P, nullptr, i);
             HIPCHK(c, hipStreamEndCapture(c->stream, &g));
             hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
@@ -582,17 +578,15 @@ int run_chunk(igks_ctx *c, const Params<T> &P, int k)
         }
         HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
     } else {
-        for (int i = 0; i < k; i++) queue_iteration(c, P, nullptr);
+        for (int i = 0; i < k; i++) queue_iteration(c, P, nullptr, i);
     }
     HIPCHK(c, hipGetLastError());
     const size_t ni = c->inst.size();
     std::vector<int> n0(ni), h0(ni);
     for (size_t i = 0; i < ni; i++) { n0[i] = c->hs[i].ncommit; h0[i] = c->hs[i].halt; }
-    int nh = 0;
-    HIPCHK(c, hipMemcpyAsync(&nh, P.hist_n, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     int rc = sync_scalars(c);
     if (rc) return rc;
-    nh = std::min(nh, c->hist_cap);
+    const int nh = std::min(k, c->hist_cap);
     if (nh > 0) {
         std::vector<double> h((size_t)HIST_W * ni * nh);
         HIPCHK(c, hipMemcpyAsync(h.data(), P.hist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));

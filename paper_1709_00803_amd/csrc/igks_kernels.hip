@@ -446,8 +446,8 @@ __device__ __forceinline__ void jac_vec(const V *W, V nx, V ny, const V *d, V *o
 
 // ------------------------------------------------------------------ kernels
 
-// mode bit 1: per-iteration slots; 2: bad/halt flags; 4: history counter;
-// 8: all scalars of the instance (fresh start).  inst < 0: every instance.
+// mode bit 1: per-iteration slots; 2: bad/halt flags; 8: all scalars of the
+// instance (fresh start).  inst < 0: every instance.
 template <typename T>
 __global__ void k_reset(Params<T> P, int mode, int inst)
 {
@@ -467,7 +467,6 @@ __global__ void k_reset(Params<T> P, int mode, int inst)
             }
         if (mode & (2 | 8)) { s->bad = 0; s->halt = 0; }
     }
-    if ((mode & 4) && threadIdx.x == 0) *P.hist_n = 0;
 }
 
 // Per cell: Eq.21 spectral radius and the Eq.23 time step, least-squares
@@ -788,38 +787,49 @@ __global__ __launch_bounds__(256) void k_gather(Params<T> P)
     slot_update<false>(&P.is[0].resinf_bits[0], inst, rinf);
 }
 
-// One thread per instance: L2 norms in a fixed order, max norm, the Eq.25
-// CFL law, history.
-template <typename T>
-__global__ void k_reduce(Params<T> P)
+// Sum over the wave by butterfly: every lane ends with the same value (each
+// step adds the same two numbers on both lanes), in a fixed order.
+__device__ __forceinline__ double wave_sum(double v)
 {
-    int h = *P.hist_n;
-    for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
-        InstScalars *s = &P.is[i];
-        if (s->halt) continue;
-        s->dt = slots_min_serial(s->dtmin_bits);   // the time step the flux used
-        double x = 0.0, y = 0.0;
-        for (int b = 0; b < RB; b++) { x += P.ipart[2 * (i * RB + b)]; y += P.ipart[2 * (i * RB + b) + 1]; }
-        double l2 = sqrt(x), sal2 = sqrt(y);
-        double rinf = slots_max_serial(s->resinf_bits);
-        if (s->ncommit == 0) {
-            s->res0 = l2;
-            s->cfl = P.cfl_init;
-        } else if (P.cfl_mode == 0) {
-            double cf = s->cfl * s->res_inf_prev / rinf;
-            if (!(cf >= P.cfl_min)) cf = P.cfl_min;
-            if (cf > P.cfl_max) cf = P.cfl_max;
-            s->cfl = cf;
-        }
-        s->res_inf_prev = rinf;
-        s->res_l2 = l2;
-        s->sa_l2 = sal2;
-        s->res_inf = rinf;
-        for (int k = 0; k < NSLOT; k++) s->resinf_bits[k] = 0ull;
-        if (h < P.hist_cap) {
-            double *e = P.hist + (size_t)HIST_W * ((size_t)h * P.ninst + i);
-            e[0] = l2; e[1] = rinf; e[2] = s->cfl; e[3] = s->dt; e[4] = 0.0; e[5] = sal2;
-        }
+    for (int o = 1; o < warpSize; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// One wave per instance (block i): the Eq.23 time step the flux used, L2
+// norms from the partial sums and the max norm, both in a fixed order, the
+// Eq.25 CFL law, history entry `it` of the chunk.
+template <typename T>
+__global__ __launch_bounds__(64) void k_reduce(Params<T> P, int it)
+{
+    const int i = blockIdx.x, lane = threadIdx.x;
+    InstScalars *s = &P.is[i];
+    if (s->halt) return;
+    double dt = wave_min(__longlong_as_double((long long)s->dtmin_bits[lane]));
+    double rinf = wave_max(__longlong_as_double((long long)s->resinf_bits[lane]));
+    double x = lane < RB ? P.ipart[2 * (i * RB + lane)] : 0.0;
+    double y = lane < RB ? P.ipart[2 * (i * RB + lane) + 1] : 0.0;
+    x = wave_sum(x);
+    y = wave_sum(y);
+    s->resinf_bits[lane] = 0ull;
+    if (lane != 0) return;
+    double l2 = sqrt(x), sal2 = sqrt(y);
+    s->dt = dt;
+    if (s->ncommit == 0) {
+        s->res0 = l2;
+        s->cfl = P.cfl_init;
+    } else if (P.cfl_mode == 0) {
+        double cf = s->cfl * s->res_inf_prev / rinf;
+        if (!(cf >= P.cfl_min)) cf = P.cfl_min;
+        if (cf > P.cfl_max) cf = P.cfl_max;
+        s->cfl = cf;
+    }
+    s->res_inf_prev = rinf;
+    s->res_l2 = l2;
+    s->sa_l2 = sal2;
+    s->res_inf = rinf;
+    if (it < P.hist_cap) {
+        double *e = P.hist + (size_t)HIST_W * ((size_t)it * P.ninst + i);
+        e[0] = l2; e[1] = rinf; e[2] = s->cfl; e[3] = dt; e[4] = 0.0; e[5] = sal2;
     }
 }
 
@@ -960,28 +970,24 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     return isfinite(r) ? r : 0.0;
 }
 
-// One thread per instance: accept (flip the state buffer) or reject and
-// freeze the instance, take the Eq.40 maximum, reset the slots for the next
+// One wave per instance (block i): accept (flip the state buffer) or reject
+// and freeze the instance, the Eq.40 maximum, slots reset for the next
 // iteration.
 template <typename T>
-__global__ void k_commit(Params<T> P)
+__global__ __launch_bounds__(64) void k_commit(Params<T> P, int it)
 {
-    int h = *P.hist_n;
-    for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
-        InstScalars *s = &P.is[i];
-        if (s->halt) continue;
-        double e40 = slots_max_serial(s->e40_bits);
-        s->e40 = e40;
-        if (h < P.hist_cap) P.hist[(size_t)HIST_W * ((size_t)h * P.ninst + i) + 4] = e40;
-        if (s->bad) s->halt = 1;
-        else s->ncommit += 1;
-        for (int k = 0; k < NSLOT; k++) {
-            s->dtmin_bits[k] = 0x7ff0000000000000ull;
-            s->e40_bits[k] = 0ull;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *P.hist_n = h + 1;
+    const int i = blockIdx.x, lane = threadIdx.x;
+    InstScalars *s = &P.is[i];
+    if (s->halt) return;
+    double e40 = wave_max(__longlong_as_double((long long)s->e40_bits[lane]));
+    int bad = s->bad;
+    s->dtmin_bits[lane] = 0x7ff0000000000000ull;
+    s->e40_bits[lane] = 0ull;
+    if (lane != 0) return;
+    s->e40 = e40;
+    if (it < P.hist_cap) P.hist[(size_t)HIST_W * ((size_t)it * P.ninst + i) + 4] = e40;
+    if (bad) s->halt = 1;
+    else s->ncommit += 1;
 }
 
 template <typename T, bool FWD>
@@ -1078,9 +1084,9 @@ template <typename T> void launch_prep(const Launch &L, const Params<T> &P)
 {
     hipLaunchKernelGGL(k_prep<T>, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), 0, L.s, P);
 }
-template <typename T> void launch_commit(const Launch &L, const Params<T> &P)
+template <typename T> void launch_commit(const Launch &L, const Params<T> &P, int it)
 {
-    hipLaunchKernelGGL(k_commit<T>, dim3(1), dim3(64), 0, L.s, P);
+    hipLaunchKernelGGL(k_commit<T>, dim3(P.ninst), dim3(64), 0, L.s, P, it);
 }
 template <typename T> void launch_flux(const Launch &L, const Params<T> &P)
 {
@@ -1090,10 +1096,10 @@ template <typename T> void launch_gather(const Launch &L, const Params<T> &P)
 {
     hipLaunchKernelGGL(k_gather<T>, dim3(nblk(P.nc, L.block[2])), dim3(L.block[2]), 0, L.s, P);
 }
-template <typename T> void launch_reduce(const Launch &L, const Params<T> &P)
+template <typename T> void launch_reduce(const Launch &L, const Params<T> &P, int it)
 {
     hipLaunchKernelGGL(k_isum<T>, dim3(P.ninst * RB), dim3(256), 0, L.s, P);
-    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(64), 0, L.s, P);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(P.ninst), dim3(64), 0, L.s, P, it);
 }
 template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd)
 {
@@ -1136,9 +1142,9 @@ void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, cons
     template void launch_prep<T>(const Launch &, const Params<T> &);                               \
     template void launch_flux<T>(const Launch &, const Params<T> &);                               \
     template void launch_gather<T>(const Launch &, const Params<T> &);                             \
-    template void launch_reduce<T>(const Launch &, const Params<T> &);                             \
+    template void launch_reduce<T>(const Launch &, const Params<T> &, int);                        \
     template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, bool);              \
-    template void launch_commit<T>(const Launch &, const Params<T> &);                             \
+    template void launch_commit<T>(const Launch &, const Params<T> &, int);                        \
     template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool);
 INST(double)
 INST(float)
