@@ -1,0 +1,204 @@
+"""Host logic of libigks on the CPU (no GPU calls): mesh validation, the
+face/wall/wavefront counts of the preprocessing, batch bookkeeping and
+call-order errors.  A context created with a caller stream never touches
+the GPU until a workspace is bound, so all of this runs here.
+
+The counts are checked against the oracle's own mesh preprocessing and
+against a wavefront count computed here from the cell adjacency.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle import pyoracle as po
+from paper_1709_00803_amd import meshgen as mg
+
+igks = pytest.importorskip("paper_1709_00803_amd.igks")
+
+FAKE_STREAM = C.c_void_p(0x1)   # stored, never used without a bound workspace
+
+
+def ctx_for(n_inst=1, **opt):
+    ctx = C.c_void_p()
+    o = igks.default_options(**opt)
+    rc = igks.igks_batch_create(C.byref(ctx), C.byref(o), FAKE_STREAM, n_inst)
+    return rc, ctx
+
+
+def upload(ctx, mesh, inst=None):
+    keep, args = igks._mesh_args(mesh)
+    if inst is None:
+        return igks.igks_mesh_upload(ctx, *args)
+    return igks.igks_batch_mesh_upload(ctx, inst, *args)
+
+
+def info(ctx):
+    v = [C.c_int32() for _ in range(4)]
+    rc = igks.igks_mesh_info(ctx, *(C.byref(x) for x in v))
+    return rc, [x.value for x in v]
+
+
+def levels_by_hand(mesh):
+    """Wavefront of each cell: 1 + the largest wavefront among its
+    neighbours of smaller index (0 without any)."""
+    _, nb = mg.cell_adjacency(mesh)
+    lev = np.zeros(mesh.n_cells, dtype=np.int64)
+    for i in range(mesh.n_cells):
+        lower = nb[i][(nb[i] >= 0) & (nb[i] < i)]
+        lev[i] = 1 + lev[lower].max() if len(lower) else 0
+    return int(lev.max()) + 1
+
+
+def broken_meshes():
+    m = mg.random_hybrid(4, 3, seed=3)
+    out = {}
+    b = m.copy(); b.bface_tag = b.bface_tag[:-1].copy(); b.bface_nodes = b.bface_nodes[:-1].copy()
+    out["untagged boundary edge"] = b
+    b = m.copy(); b.bface_tag = b.bface_tag.copy(); b.bface_tag[0] = 7
+    out["bad tag"] = b
+    b = m.copy(); b.bface_nodes = np.concatenate([b.bface_nodes, b.bface_nodes[:1]]); \
+        b.bface_tag = np.concatenate([b.bface_tag, b.bface_tag[:1]])
+    out["duplicate boundary edge"] = b
+    b = m.copy(); b.cell_nodes = b.cell_nodes.copy(); b.cell_nodes[0] = m.n_nodes + 5
+    out["node out of range"] = b
+    # an interior edge listed as boundary
+    pairs, _ = mg.cell_adjacency(m)
+    c0 = pairs[0, 0]
+    p0 = m.cell_ptr[c0]
+    nodes0 = set(m.cell_nodes[p0:m.cell_ptr[c0 + 1]].tolist())
+    c1 = pairs[0, 1]
+    nodes1 = set(m.cell_nodes[m.cell_ptr[c1]:m.cell_ptr[c1 + 1]].tolist())
+    shared = sorted(nodes0 & nodes1)
+    b = m.copy(); b.bface_nodes = np.concatenate([b.bface_nodes, [shared]]); \
+        b.bface_tag = np.concatenate([b.bface_tag, [mg.WALL]])
+    out["tagged interior edge"] = b
+    # a pentagon
+    xy = np.array([[0, 0], [1, 0], [1.3, 0.8], [0.5, 1.3], [-0.3, 0.8]], float)
+    out["five nodes"] = mg.Mesh(xy=xy, cell_ptr=np.array([0, 5], np.int32), cell_nodes=np.arange(5, dtype=np.int32),
+                                bface_nodes=np.array([[k, (k + 1) % 5] for k in range(5)], np.int32),
+                                bface_tag=np.full(5, mg.FREESTREAM, np.int32), meta={})
+    # a zero-area triangle
+    xy = np.array([[0, 0], [1, 0], [2, 0]], float)
+    out["degenerate"] = mg.Mesh(xy=xy, cell_ptr=np.array([0, 3], np.int32), cell_nodes=np.arange(3, dtype=np.int32),
+                                bface_nodes=np.array([[0, 1], [1, 2], [2, 0]], np.int32),
+                                bface_tag=np.full(3, mg.FREESTREAM, np.int32), meta={})
+    # three triangles on one edge
+    xy = np.array([[0, 0], [1, 0], [0.5, 1], [0.5, -1], [0.6, 0.5]], float)
+    cells = np.array([0, 1, 2, 0, 3, 1, 0, 1, 4], np.int32)
+    out["edge in three cells"] = mg.Mesh(xy=xy, cell_ptr=np.array([0, 3, 6, 9], np.int32), cell_nodes=cells,
+                                         bface_nodes=np.array([[1, 2], [2, 0], [0, 3], [3, 1], [1, 4], [4, 0]],
+                                                              np.int32),
+                                         bface_tag=np.full(6, mg.FREESTREAM, np.int32), meta={})
+    return out
+
+
+@pytest.mark.parametrize("name", sorted(broken_meshes()))
+def test_mesh_validation_matches_oracle(name):
+    mesh = broken_meshes()[name]
+    rc, ctx = ctx_for()
+    assert rc == igks.IGKS_OK
+    try:
+        rc = upload(ctx, mesh)
+        msg = igks.igks_last_error(ctx).decode()
+        assert rc == igks.IGKS_EMESH, (name, rc, msg)
+        assert msg
+        # after a rejected upload the context has no mesh
+        assert info(ctx)[0] == igks.IGKS_EINVAL
+    finally:
+        igks.igks_destroy(ctx)
+    if name != "five nodes":      # the oracle takes any polygon; the library is limited to Sec. 2.4's cells
+        with pytest.raises(po.OracleError):
+            po.Oracle(mesh)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: mg.random_hybrid(7, 5, seed=1, tags=dict(bottom=mg.WALL, top=mg.FARFIELD)),
+    lambda: mg.colour_order(mg.random_hybrid(9, 6, seed=2, tags=dict(bottom=mg.WALL)))[0],
+    lambda: mg.flat_plate(16, 8),
+    lambda: mg.colour_order(mg.flat_plate(12, 6))[0],
+])
+def test_counts_and_wavefronts(make):
+    mesh = make()
+    rc, ctx = ctx_for()
+    try:
+        assert upload(ctx, mesh) == igks.IGKS_OK
+        rc, (nc, nf, nw, nl) = info(ctx)
+        assert rc == igks.IGKS_OK
+        o = po.Oracle(mesh)
+        assert (nc, nf, nw) == (o.n, o.nf, o.nwall)
+        assert nl == levels_by_hand(mesh)
+        sz = C.c_size_t()
+        assert igks.igks_workspace_size(ctx, C.byref(sz)) == igks.IGKS_OK
+        assert sz.value >= (2 * 5 + 5) * 8 * nc      # two state buffers and the residual at least
+    finally:
+        igks.igks_destroy(ctx)
+
+
+def test_batch_bookkeeping():
+    meshes = [mg.random_hybrid(5, 4, seed=s, tags=dict(bottom=mg.WALL)) for s in (1, 2)] + [mg.flat_plate(10, 5)]
+    rc, ctx = ctx_for(len(meshes))
+    assert rc == igks.IGKS_OK
+    try:
+        assert upload(ctx, meshes[0], 0) == igks.IGKS_OK
+        sz = C.c_size_t()
+        # instances 1 and 2 have no mesh yet
+        assert igks.igks_workspace_size(ctx, C.byref(sz)) == igks.IGKS_EINVAL
+        for i in (1, 2):
+            assert upload(ctx, meshes[i], i) == igks.IGKS_OK
+        assert upload(ctx, meshes[0], 3) == igks.IGKS_EINVAL
+        assert upload(ctx, meshes[0], -1) == igks.IGKS_EINVAL
+        rc, (nc, nf, nw, nl) = info(ctx)
+        assert rc == igks.IGKS_OK
+        per = []
+        for i, m in enumerate(meshes):
+            v = [C.c_int32() for _ in range(3)]
+            assert igks.igks_batch_mesh_info(ctx, i, *(C.byref(x) for x in v)) == igks.IGKS_OK
+            o = po.Oracle(m)
+            assert [x.value for x in v] == [o.n, o.nf, o.nwall]
+            per.append((o.n, o.nf, o.nwall, levels_by_hand(m)))
+        assert nc == sum(p[0] for p in per) and nf == sum(p[1] for p in per) and nw == sum(p[2] for p in per)
+        assert nl == max(p[3] for p in per)      # wavefronts of different instances run together
+        assert igks.igks_workspace_size(ctx, C.byref(sz)) == igks.IGKS_OK
+        one = []
+        for m in meshes:
+            rc1, c1 = ctx_for()
+            upload(c1, m)
+            s1 = C.c_size_t()
+            igks.igks_workspace_size(c1, C.byref(s1))
+            one.append(s1.value)
+            igks.igks_destroy(c1)
+        assert sz.value < sum(one) + 64 * 1024
+    finally:
+        igks.igks_destroy(ctx)
+
+
+def test_call_order_and_option_errors():
+    for bad in (dict(block=96), dict(block=512), dict(sweep=3), dict(precision=5), dict(chunk=-1)):
+        rc, ctx = ctx_for(**bad)
+        assert rc == igks.IGKS_EINVAL, bad
+        assert not ctx.value
+    rc, ctx = ctx_for(n_inst=0)
+    assert rc == igks.IGKS_EINVAL
+    rc, ctx = ctx_for()
+    try:
+        done = C.c_int32(7)
+        assert igks.igks_iterate(ctx, 1, C.byref(done)) == igks.IGKS_EINVAL
+        assert done.value == 0
+        assert igks.igks_set_freestream(ctx, 0.3, 0.0, 1e4, -1.0) == igks.IGKS_EINVAL
+        assert upload(ctx, mg.random_hybrid(3, 3, seed=4)) == igks.IGKS_OK
+        # no workspace bound yet
+        assert igks.igks_set_freestream(ctx, 0.3, 0.0, 1e4, -1.0) == igks.IGKS_EINVAL
+        assert igks.igks_autotune(ctx, 3, None) == igks.IGKS_EINVAL
+        r = igks.igks_residual()
+        assert igks.igks_get_residual(ctx, C.byref(r)) == igks.IGKS_EINVAL
+        assert igks.igks_bind_workspace(ctx, C.c_void_p(0x100), 16) == igks.IGKS_ENOMEM
+        sz = C.c_size_t()
+        igks.igks_workspace_size(ctx, C.byref(sz))
+        assert igks.igks_bind_workspace(ctx, C.c_void_p(0x101), sz.value) == igks.IGKS_EINVAL   # misaligned
+        s5 = np.zeros(5, np.int32)
+        assert igks.igks_get_schedule(ctx, s5.ctypes.data_as(igks._IP)) == igks.IGKS_OK
+        assert s5.tolist() == [256, 256, 256, 256, 1]
+    finally:
+        igks.igks_destroy(ctx)
+    igks.igks_destroy(None)
