@@ -195,6 +195,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=20)
     ap.add_argument("--profile-iters", type=int, default=20)
     ap.add_argument("--autotune", type=int, default=None, help="autotuner iterations (default: 5 for batch64, 0 else)")
+    ap.add_argument("--cfl-init", type=float, default=None, help="initial implicit CFL (default: 1000, 10 for batch64)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 runs")
     args = ap.parse_args()
@@ -220,13 +221,14 @@ def main():
     t_mesh = time.perf_counter() - t
     torch.cuda.set_device(0)
     prec = igks.IGKS_MIXED if mixed else igks.IGKS_FP64
+    cfl0 = args.cfl_init if args.cfl_init is not None else (10.0 if batched else 1000.0)
     if batched:
-        solver = igks.BatchSolver(meshes, precision=prec, chunk=args.chunk)
+        solver = igks.BatchSolver(meshes, precision=prec, chunk=args.chunk, cfl_init=cfl0)
         for i, f in enumerate(flows):
             solver.set_freestream(i, *f)
         nfs = solver.nf
     else:
-        solver = igks.Solver(meshes[0], precision=prec, chunk=args.chunk)
+        solver = igks.Solver(meshes[0], precision=prec, chunk=args.chunk, cfl_init=cfl0)
         solver.set_freestream(*flows[0])
         nfs = [solver.nf]
     n = solver.total_cells
@@ -234,14 +236,32 @@ def main():
           f"{solver.nlev} wavefronts, generated in {t_mesh:.1f}s", file=sys.stderr, flush=True)
     schedule = solver.autotune(tune).tolist() if tune > 0 else solver.schedule().tolist()
 
-    solver.iterate(args.warmup)
+    def run(k):
+        """k iterations; a batch instance frozen by a rejected update is
+        reported, not fatal: the others go on."""
+        try:
+            solver.iterate(k)
+        except igks.IgksError as e:
+            if not batched or e.code != igks.IGKS_ENONPHYS:
+                raise
+            print(f"# {e}", file=sys.stderr, flush=True)
+
+    def committed():
+        if batched:
+            return [solver.residual(i)["iteration"] for i in range(len(meshes))]
+        return [solver.residual()["iteration"]]
+
+    run(args.warmup)
+    c0 = committed()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    solver.iterate(args.steps)
+    run(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    value = n * args.steps / elapsed
+    # cell updates actually committed (frozen instances do not count)
+    updates = sum(m.n_cells * (b - a) for m, a, b in zip(meshes, c0, committed()))
+    value = updates / elapsed
     if batched:
         drops = [solver.residual(i)["res_drop"] for i in range(len(meshes))]
         frozen = [i for i in range(len(meshes)) if solver.status(i)]
@@ -253,7 +273,7 @@ def main():
 
     # per-kernel durations: HIP events on the library's stream, direct launches
     solver.set_profiling(True)
-    solver.iterate(args.profile_iters)
+    run(args.profile_iters)
     kt = solver.kernel_times()      # ms per iteration, per kernel class
     solver.set_profiling(False)
     kb = {}
@@ -290,7 +310,8 @@ def main():
         "dtype": "f32+f64" if mixed else "f64", "data": "synthetic",
         "config": dict({"workload": f"{args.workload}: {wl['desc']}", "instances": len(meshes), "cells": n,
                         "faces": faces, "wavefronts": solver.nlev, "precision": precision, "ordering": "colour",
-                        "chunk": args.chunk, "schedule": schedule}, **res_info),
+                        "cfl_init": cfl0, "chunk": args.chunk, "schedule": schedule,
+                        "cell_updates_timed": updates}, **res_info),
         "roofline": roofline,
     }
     if not args.no_drop:

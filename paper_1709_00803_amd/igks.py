@@ -21,6 +21,12 @@ HIST_W = 6
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1709_00803_amd.build "
                       "(or __graft_entry__.build())")
+# PyTorch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+# Loading torch first makes libigks bind to that already-loaded runtime, so
+# the process holds a single HIP runtime; the other order loads two, and the
+# one initialised second finds no device.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 
