@@ -284,8 +284,10 @@ def main():
     faces = solver.total_faces
     dom = max(kt, key=lambda k: kt[k])
     sweep_wg = schedule[4] == 2
+    # per-wavefront launches; the last wavefront's backward step runs in the
+    # forward sweep's last launch
     launches = {"sweep_fwd": 1 if sweep_wg else solver.nlev,
-                "sweep_bwd": 1 if sweep_wg else solver.nlev}.get(dom, 1)
+                "sweep_bwd": 1 if sweep_wg else max(solver.nlev - 1, 1)}.get(dom, 1)
     t_ms = kt[dom]
     if dom == "flux":
         achieved = FLUX_FLOP_PER_FACE * faces / (t_ms * 1e-3) / 1e12 if t_ms > 0 else 0.0

@@ -106,9 +106,11 @@ template <typename T> void launch_flux(const Launch &L, const Params<T> &P);
 template <typename T> void launch_gather(const Launch &L, const Params<T> &P);
 // it: the iteration's index in the current chunk (its history entry)
 template <typename T> void launch_reduce(const Launch &L, const Params<T> &P, int it);
-// backward sweeps also update the state (Eq.17); launch_commit then accepts
-// or rejects the iteration of every instance
-template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd);
+// one wavefront of cells [c0, c1) of the sweeps; mode 0 forward, 1 backward,
+// 2 both (the last wavefront).  Backward steps also update the state
+// (Eq.17); launch_commit then accepts or rejects the iteration of every
+// instance
+template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, int mode);
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd);
 template <typename T> void launch_commit(const Launch &L, const Params<T> &P, int it);
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,

@@ -518,12 +518,15 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev, int it)
     mark(4);
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, true);
     else
-        for (int l = 0; l < G.nlev; l++) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], true);
+        // forward over all wavefronts; the last one also takes its backward
+        // step (only ghosts lie above it)
+        for (int l = 0; l < G.nlev; l++)
+            launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], l + 1 < G.nlev ? 0 : 2);
     mark(5);
     // backward sweep with the update
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, false);
     else
-        for (int l = G.nlev - 1; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], false);
+        for (int l = G.nlev - 2; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], 1);
     launch_commit(L, P, it);
     mark(6);
 }

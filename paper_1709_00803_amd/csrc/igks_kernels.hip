@@ -864,17 +864,58 @@ __global__ __launch_bounds__(256) void k_isum(Params<T> P)
     }
 }
 
-// One wavefront of the forward (FWD) or backward LU-SGS sweep (Eq.22): the
-// cells of a wavefront are mutually independent.  Forward:
+// Neighbour term of one cell-face entry in the LU-SGS sweeps (Eq.22 and
+// Eq.31-32): t[0..3] = (J(W_j, n) dW_j - lam dW_j) S / 2 with n pointing out
+// of the cell, t[4] = the SA off-diagonal coefficient times dnu~_j.  j < 0:
+// the ghost cell, whose increment follows from the cell's own dW* (Sec. 2.5).
+template <typename T>
+__device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &ip, const double *W,
+                                           const double *w, int f, int j, int fl, const T *dws, T *t)
+{
+    const int N = P.nc;
+    double sg = (fl & CF_OWNER) ? 1.0 : -1.0;
+    double nx = sg * P.fnx[f], ny = sg * P.fny[f];
+    T S = T(P.flen[f]), lam = T(P.lam[f]);
+    double wj[5];
+    T dj[5];
+    if (j >= 0) {
+#pragma unroll
+        for (int k = 0; k < 5; k++) { wj[k] = W[k * N + j]; dj[k] = P.dW[k * N + j]; }
+    } else {
+        ghost(ip, P.fbc[f], w, nx, ny, wj);
+        ghost_incr<T>(P.fbc[f], dws, T(nx), T(ny), dj);
+    }
+    T wjt[4] = {T(wj[0]), T(wj[1]), T(wj[2]), T(wj[3])};
+    T jv[4];
+    jac_vec<T>(wjt, T(nx), T(ny), dj, jv);
+    T h = T(0.5) * S;
+#pragma unroll
+    for (int k = 0; k < 4; k++) t[k] = h * (jv[k] - lam * dj[k]);
+    t[4] = T(0);
+    if (ip.sa) {
+        double qj = (wj[1] * nx + wj[2] * ny) / wj[0];
+        double off = -0.5 * (qj - fabs(qj)) * P.flen[f] + P.sak[f];
+        t[4] = T(off) * dj[4];
+    }
+}
+
+// sweep modes
+enum { SW_FWD = 0, SW_BWD = 1, SW_TOP = 2 };
+
+// One wavefront of the LU-SGS sweeps (Eq.22); the cells of a wavefront are
+// mutually independent.  Forward:
 //   dW*_i = D^-1 [M_i - sum_{j<i} (J(W_j, n_ij) dW*_j - lam_ij dW*_j) S_ij / 2];
 // backward, in place:
 //   dW_i = dW*_i - D^-1 sum_{j>i} (J(W_j, n_ij) dW_j - lam_ij dW_j) S_ij / 2,
 // boundary ghosts counted as upper neighbours with the ghost increments of
 // Sec. 2.5 taken from dW*_i.  The SA equation (Eq.31-32) is swept alongside.
-// The backward sweep also applies W^{n+1} = W^n + dW (Eq.17) into the
+// SW_TOP does both for the last wavefront: a neighbour j > i of a cell i
+// always lies in a later wavefront, so the cells of the last one have only
+// ghosts above them and their backward step needs nothing from other cells.
+// The backward step also applies W^{n+1} = W^n + dW (Eq.17) into the
 // instance's other state buffer (nu~ clipped at 0), flags a non-physical
 // result and returns the Eq.40 ratio.  inst = -1 for a frozen instance.
-template <typename T, bool FWD>
+template <typename T, int MODE>
 __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &inst)
 {
     const int N = P.nc;
@@ -890,59 +931,43 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     double w[5];
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
-    T acc[5], dws[5];
-    if (FWD) {
+    const Entries E = entries(P, c);
+    const T odt = T(P.lamc[c]) / cfl;   // Omega / dt_imp with dt_imp = CFL Omega / Lambda_c (Eq.24)
+    const T D = odt + T(P.lsum[c]);
+    T dws[5], acc[5], t[5];
+    if (MODE != SW_BWD) {
 #pragma unroll
-        for (int k = 0; k < 5; k++) { acc[k] = T(P.M[k * N + c]); dws[k] = T(0); }
+        for (int k = 0; k < 5; k++) acc[k] = T(P.M[k * N + c]);
+#pragma unroll
+        for (int k = 0; k < MAXV; k++) {
+            const int j = E.nbr[k], fl = E.flag[k];
+            if (!(fl & CF_VALID) || j < 0 || !(fl & CF_LOWER)) continue;
+            sweep_term(P, ip, W, w, E.face[k], j, fl, dws, t);
+#pragma unroll
+            for (int m = 0; m < 4; m++) acc[m] -= t[m];
+            acc[4] += t[4];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) dws[k] = acc[k] / D;
+        dws[4] = ip.sa ? acc[4] / (odt + T(P.sadiag[c])) : T(0);
+        if (MODE == SW_FWD) {
+#pragma unroll
+            for (int k = 0; k < 5; k++) P.dW[k * N + c] = dws[k];
+            return 0.0;
+        }
     } else {
 #pragma unroll
-        for (int k = 0; k < 5; k++) { acc[k] = T(0); dws[k] = P.dW[k * N + c]; }
+        for (int k = 0; k < 5; k++) dws[k] = P.dW[k * N + c];
     }
-    const Entries E = entries(P, c);
+#pragma unroll
+    for (int k = 0; k < 5; k++) acc[k] = T(0);
 #pragma unroll
     for (int k = 0; k < MAXV; k++) {
         const int j = E.nbr[k], fl = E.flag[k];
-        if (!(fl & CF_VALID)) continue;
-        if (FWD) {
-            if (j < 0 || !(fl & CF_LOWER)) continue;
-        } else {
-            if (j >= 0 && (fl & CF_LOWER)) continue;
-        }
-        const int f = E.face[k];
-        double sg = (fl & CF_OWNER) ? 1.0 : -1.0;
-        double nx = sg * P.fnx[f], ny = sg * P.fny[f];
-        T S = T(P.flen[f]), lam = T(P.lam[f]);
-        double wj[5];
-        T dj[5];
-        if (j >= 0) {
+        if (!(fl & CF_VALID) || (j >= 0 && (fl & CF_LOWER))) continue;
+        sweep_term(P, ip, W, w, E.face[k], j, fl, dws, t);
 #pragma unroll
-            for (int k = 0; k < 5; k++) { wj[k] = W[k * N + j]; dj[k] = P.dW[k * N + j]; }
-        } else {
-            ghost(ip, P.fbc[f], w, nx, ny, wj);
-            ghost_incr<T>(P.fbc[f], dws, T(nx), T(ny), dj);
-        }
-        T wjt[4] = {T(wj[0]), T(wj[1]), T(wj[2]), T(wj[3])};
-        T jv[4];
-        jac_vec<T>(wjt, T(nx), T(ny), dj, jv);
-        T h = T(0.5) * S;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            if (FWD) acc[k] -= h * (jv[k] - lam * dj[k]);
-            else acc[k] += h * (jv[k] - lam * dj[k]);
-        }
-        if (ip.sa) {
-            double qj = (wj[1] * nx + wj[2] * ny) / wj[0];
-            double off = -0.5 * (qj - fabs(qj)) * P.flen[f] + P.sak[f];
-            acc[4] += T(off) * dj[4];
-        }
-    }
-    T odt = T(P.lamc[c]) / cfl;   // Omega / dt_imp with dt_imp = CFL Omega / Lambda_c (Eq.24)
-    T D = odt + T(P.lsum[c]);
-    if (FWD) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) P.dW[k * N + c] = acc[k] / D;
-        P.dW[4 * N + c] = ip.sa ? acc[4] / (odt + T(P.sadiag[c])) : T(0);
-        return 0.0;
+        for (int m = 0; m < 5; m++) acc[m] += t[m];
     }
     T d[5];
 #pragma unroll
@@ -961,11 +986,11 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
         wn[k] = w[k] + dd;
         Wn[k * N + c] = wn[k];
     }
-    double t = w[4];
-    if (ip.sa) t = fmax(t + double(d[4]), 0.0);
-    Wn[4 * N + c] = t;
+    double tt = w[4];
+    if (ip.sa) tt = fmax(tt + double(d[4]), 0.0);
+    Wn[4 * N + c] = tt;
     double p = wn[3] - 0.5 * (wn[1] * wn[1] + wn[2] * wn[2]) / wn[0];
-    if (!(wn[0] > 0.0) || !(p > 0.0) || !isfinite(t) || !isfinite(p)) atomicOr(&P.is[inst].bad, 1);
+    if (!(wn[0] > 0.0) || !(p > 0.0) || !isfinite(tt) || !isfinite(p)) atomicOr(&P.is[inst].bad, 1);
     double r = sqrt(num / den);
     return isfinite(r) ? r : 0.0;
 }
@@ -990,14 +1015,14 @@ __global__ __launch_bounds__(64) void k_commit(Params<T> P, int it)
     else s->ncommit += 1;
 }
 
-template <typename T, bool FWD>
+template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
 {
     int c = c0 + xcd_block() * blockDim.x + threadIdx.x;
     int inst = -1;
     double e = 0.0;
-    if (c < c1) e = sweep_cell<T, FWD>(P, c, inst);
-    if (!FWD) slot_update<false>(&P.is[0].e40_bits[0], inst, e);
+    if (c < c1) e = sweep_cell<T, MODE>(P, c, inst);
+    if (MODE != SW_FWD) slot_update<false>(&P.is[0].e40_bits[0], inst, e);
 }
 
 // The whole sweep in one workgroup: wavefront after wavefront, separated by
@@ -1014,7 +1039,7 @@ __global__ __launch_bounds__(1024) void k_sweep_wg(Params<T> P, const int *lev_o
         for (int base = c0; base < c1; base += (int)blockDim.x) {
             int c = base + (int)threadIdx.x, inst = -1;
             double e = 0.0;
-            if (c < c1) e = sweep_cell<T, FWD>(P, c, inst);
+            if (c < c1) e = sweep_cell<T, FWD ? SW_FWD : SW_BWD>(P, c, inst);
             if (!FWD) slot_update<false>(&P.is[0].e40_bits[0], inst, e);
         }
         __syncthreads();
@@ -1101,12 +1126,13 @@ template <typename T> void launch_reduce(const Launch &L, const Params<T> &P, in
     hipLaunchKernelGGL(k_isum<T>, dim3(P.ninst * RB), dim3(256), 0, L.s, P);
     hipLaunchKernelGGL(k_reduce<T>, dim3(P.ninst), dim3(64), 0, L.s, P, it);
 }
-template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, bool fwd)
+template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, int mode)
 {
     if (c1 <= c0) return;
     dim3 g(nblk(c1 - c0, L.block[3])), b(L.block[3]);
-    if (fwd) hipLaunchKernelGGL((k_sweep<T, true>), g, b, 0, L.s, P, c0, c1);
-    else hipLaunchKernelGGL((k_sweep<T, false>), g, b, 0, L.s, P, c0, c1);
+    if (mode == SW_FWD) hipLaunchKernelGGL((k_sweep<T, SW_FWD>), g, b, 0, L.s, P, c0, c1);
+    else if (mode == SW_BWD) hipLaunchKernelGGL((k_sweep<T, SW_BWD>), g, b, 0, L.s, P, c0, c1);
+    else hipLaunchKernelGGL((k_sweep<T, SW_TOP>), g, b, 0, L.s, P, c0, c1);
 }
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd)
 {
@@ -1143,7 +1169,7 @@ void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, cons
     template void launch_flux<T>(const Launch &, const Params<T> &);                               \
     template void launch_gather<T>(const Launch &, const Params<T> &);                             \
     template void launch_reduce<T>(const Launch &, const Params<T> &, int);                        \
-    template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, bool);              \
+    template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, int);               \
     template void launch_commit<T>(const Launch &, const Params<T> &, int);                        \
     template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool);
 INST(double)
