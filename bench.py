@@ -194,7 +194,7 @@ def main():
                     help="default: fp64, mixed for batch64")
     ap.add_argument("--chunk", type=int, default=20)
     ap.add_argument("--profile-iters", type=int, default=20)
-    ap.add_argument("--autotune", type=int, default=None, help="autotuner iterations (default: 5 for batch64, 0 else)")
+    ap.add_argument("--autotune", type=int, default=None, help="autotuner iterations per candidate (default 5, 0: off)")
     ap.add_argument("--cfl-init", type=float, default=None, help="initial implicit CFL (default: 1000, 10 for batch64)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 runs")
@@ -212,7 +212,7 @@ def main():
     batched = args.workload == "batch64"
     precision = args.precision or ("mixed" if batched else "fp64")
     mixed = precision == "mixed"
-    tune = args.autotune if args.autotune is not None else (5 if batched else 0)
+    tune = args.autotune if args.autotune is not None else 5
     t = time.perf_counter()
     if batched:
         meshes, flows = mg.batch(64)

@@ -78,6 +78,8 @@ typedef struct igks_options {
     int block;          /* threads per block of the cell/face kernels; 0 = 256 */
     int sweep;          /* LU-SGS sweep schedule: 0 auto, 1 one launch per wavefront,
                            2 all wavefronts in one workgroup (barrier between wavefronts) */
+    int flux_lanes;     /* lanes per face of the flux kernel: 0 auto (2 from 131072 faces on),
+                           1 or 2; the two agree to rounding */
 } igks_options;
 
 typedef struct igks_residual {
@@ -104,7 +106,7 @@ typedef struct igks_ctx igks_ctx;
 /* Fill *opt with the defaults: FP64, limiter off, cfl_init 1000 (Sec. 3.1),
  * cfl_min 1, cfl_max 1e6, Eq.25 law, cfl_flux 1, visc_sr on, Sutherland,
  * chunk 20, block 256, sweep auto (one workgroup when the wavefronts are many and
- * narrow: more than 16 of them averaging under 4096 cells). */
+ * narrow: more than 16 of them averaging under 4096 cells), flux_lanes auto. */
 void igks_default_options(igks_options *opt);
 
 /* Create a context.  opt may be NULL (defaults).  hip_stream is a
@@ -215,6 +217,7 @@ int igks_batch_get_residual(igks_ctx *ctx, int32_t inst, igks_residual *out);
 int igks_batch_get_history(igks_ctx *ctx, int32_t inst, double *out, int32_t max, int32_t *n_out);
 int igks_batch_get_state(igks_ctx *ctx, int32_t inst, double *W);
 int igks_batch_set_state(igks_ctx *ctx, int32_t inst, const double *W, const igks_scalars *sc);
+int igks_batch_get_scalars(igks_ctx *ctx, int32_t inst, igks_scalars *out);
 int igks_batch_compute_residual(igks_ctx *ctx, int32_t inst, double *M);
 int igks_batch_get_wall_loads(igks_ctx *ctx, int32_t inst, double *cl, double *cd, double *cf, double *cp,
                               double *xw);
@@ -223,16 +226,19 @@ int igks_batch_status(igks_ctx *ctx, int32_t inst, int32_t *halted);
 
 /* Autotuner: runs `iters` iterations under each candidate launch schedule
  * (threads per block 64/128/256 for the prep, flux, gather and sweep
- * kernels; for the sweeps also one workgroup for all wavefronts, tried
- * while wavefronts average under 16384 cells), keeps the fastest per kernel
- * class, and then restores both state buffers, the scalars and the history
- * bitwise.  The schedule changes launch shapes only, never results.
- * schedule5 (may be NULL) receives the block sizes of the four classes and
- * the sweep schedule (1: one launch per wavefront, 2: one workgroup).
- * IGKS_EINVAL unless 1 <= iters <= 1000; IGKS_ENONPHYS if an instance is
- * frozen. */
-int igks_autotune(igks_ctx *ctx, int32_t iters, int32_t *schedule5);
-int igks_get_schedule(const igks_ctx *ctx, int32_t *schedule5);
+ * kernels, the face flux on one or two lanes per face; for the sweeps also
+ * one workgroup for all wavefronts, tried while wavefronts average under
+ * 16384 cells), keeps the fastest per kernel class, and then restores both
+ * state buffers, the scalars and the history bitwise.  Block sizes and the
+ * sweep schedule never change results; the one- and two-lane flux kernels
+ * agree to rounding (the compiler fuses a few multiply-adds differently).
+ * schedule6 (may be NULL) receives the
+ * block sizes of the four classes, the sweep schedule (1: one launch per
+ * wavefront, 2: one workgroup) and the lanes per face of the flux (1 or 2;
+ * before any tuning 2 from 131072 faces on).  IGKS_EINVAL unless
+ * 1 <= iters <= 1000; IGKS_ENONPHYS if an instance is frozen. */
+int igks_autotune(igks_ctx *ctx, int32_t iters, int32_t *schedule6);
+int igks_get_schedule(const igks_ctx *ctx, int32_t *schedule6);
 
 /* With profiling on (igks_set_profiling(ctx, 1)) igks_iterate launches
  * directly, not through graphs, and times each kernel class with HIP events

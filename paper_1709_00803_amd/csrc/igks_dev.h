@@ -99,6 +99,7 @@ struct Params {
 struct Launch {
     hipStream_t s;
     int block[NCLASS];        // prep, flux, gather, sweep
+    bool flux_pair;           // flux on two lanes per face (else one)
 };
 template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int mode, int inst);
 template <typename T> void launch_prep(const Launch &L, const Params<T> &P);

@@ -87,6 +87,7 @@ struct igks_ctx {
     // launch schedule
     int block[NCLASS] = {256, 256, 256, 256};
     bool sweep_wg = false;
+    bool flux_pair = false;   // face flux on two lanes per face
     // host copies of the device scalars and the history of the last iterate call
     std::vector<InstScalars> hs;
     std::vector<std::vector<double>> hist;
@@ -496,6 +497,7 @@ Launch launch_of(igks_ctx *c)
     Launch L;
     L.s = c->stream;
     for (int k = 0; k < NCLASS; k++) L.block[k] = c->block[k];
+    L.flux_pair = c->flux_pair;
     return L;
 }
 
@@ -629,6 +631,18 @@ int check_ready(igks_ctx *c, bool need_flow)
     return IGKS_OK;
 }
 
+// the context is bound and instance inst has its free stream
+int check_inst_ready(igks_ctx *c, int inst)
+{
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    rc = check_ready(c, false);
+    if (rc) return rc;
+    if (!c->inst[inst].have_flow)
+        return fail(c, IGKS_EINVAL, "set the free stream of instance " + std::to_string(inst) + " first");
+    return IGKS_OK;
+}
+
 int ensure_combined(igks_ctx *c)
 {
     for (size_t i = 0; i < c->inst.size(); i++)
@@ -744,6 +758,7 @@ void igks_default_options(igks_options *o)
     o->chunk = 20;
     o->block = 256;
     o->sweep = 0;
+    o->flux_lanes = 0;
 }
 
 int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream, int32_t n_inst)
@@ -758,6 +773,7 @@ int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream,
     if (c->opt.block <= 0) c->opt.block = 256;
     if (c->opt.block % 64 != 0 || c->opt.block > 256) { delete c; return IGKS_EINVAL; }
     if (c->opt.sweep < 0 || c->opt.sweep > 2 || c->opt.chunk < 0) { delete c; return IGKS_EINVAL; }
+    if (c->opt.flux_lanes < 0 || c->opt.flux_lanes > 2) { delete c; return IGKS_EINVAL; }
     for (int k = 0; k < NCLASS; k++) c->block[k] = c->opt.block;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
@@ -890,6 +906,9 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     {
         double width = (double)G.N / std::max(1, G.nlev);
         c->sweep_wg = c->opt.sweep == 2 || (c->opt.sweep == 0 && G.nlev > 16 && width < 4096.0);
+        // one lane per face leaves SIMDs idle on small meshes; two lanes pay
+        // off once a lane per face would already give two waves per SIMD
+        c->flux_pair = c->opt.flux_lanes == 2 || (c->opt.flux_lanes == 0 && G.F >= 131072);
     }
     // instance parameters and scalars start zeroed (no free stream yet)
     std::vector<InstParam> ip0(c->inst.size());
@@ -970,9 +989,7 @@ int igks_batch_status(igks_ctx *c, int32_t inst, int32_t *halted)
 
 int igks_batch_get_residual(igks_ctx *c, int32_t inst, igks_residual *out)
 {
-    int rc = check_inst(c, inst);
-    if (rc) return rc;
-    rc = check_ready(c, true);
+    int rc = check_inst_ready(c, inst);
     if (rc) return rc;
     if (!out) return IGKS_EINVAL;
     const InstScalars &s = c->hs[inst];
@@ -1007,9 +1024,7 @@ int igks_get_history(igks_ctx *c, double *out, int32_t max, int32_t *n_out)
 
 int igks_batch_get_state(igks_ctx *c, int32_t inst, double *W)
 {
-    int rc = check_inst(c, inst);
-    if (rc) return rc;
-    rc = check_ready(c, true);
+    int rc = check_inst_ready(c, inst);
     if (rc) return rc;
     if (!W) return IGKS_EINVAL;
     const int n = c->inst[inst].nc;
@@ -1025,9 +1040,7 @@ int igks_get_state(igks_ctx *c, double *W) { return igks_batch_get_state(c, 0, W
 
 int igks_batch_set_state(igks_ctx *c, int32_t inst, const double *W, const igks_scalars *sc)
 {
-    int rc = check_inst(c, inst);
-    if (rc) return rc;
-    rc = check_ready(c, true);
+    int rc = check_inst_ready(c, inst);
     if (rc) return rc;
     if (!W) return IGKS_EINVAL;
     const int n = c->inst[inst].nc;
@@ -1051,21 +1064,24 @@ int igks_batch_set_state(igks_ctx *c, int32_t inst, const double *W, const igks_
 
 int igks_set_state(igks_ctx *c, const double *W, const igks_scalars *sc) { return igks_batch_set_state(c, 0, W, sc); }
 
-int igks_get_scalars(igks_ctx *c, igks_scalars *out)
+int igks_batch_get_scalars(igks_ctx *c, int32_t inst, igks_scalars *out)
 {
-    int rc = check_ready(c, true);
+    int rc = check_inst_ready(c, inst);
     if (rc) return rc;
     if (!out) return IGKS_EINVAL;
-    out->iteration = c->hs[0].ncommit;
-    out->cfl = c->hs[0].cfl;
-    out->res_inf_prev = c->hs[0].res_inf_prev;
-    out->res0 = c->hs[0].res0;
+    out->iteration = c->hs[inst].ncommit;
+    out->cfl = c->hs[inst].cfl;
+    out->res_inf_prev = c->hs[inst].res_inf_prev;
+    out->res0 = c->hs[inst].res0;
     return IGKS_OK;
 }
+
+int igks_get_scalars(igks_ctx *c, igks_scalars *out) { return igks_batch_get_scalars(c, 0, out); }
 
 // residual evaluation of every live instance without advancing the iteration
 static int eval_residual(igks_ctx *c, int inst)
 {
+    // the kernels run over every instance, so every instance needs its flow
     int rc = check_inst(c, inst);
     if (rc) return rc;
     rc = check_ready(c, true);
@@ -1144,15 +1160,16 @@ int igks_get_kernel_times(igks_ctx *c, double *ms6)
     return IGKS_OK;
 }
 
-int igks_get_schedule(const igks_ctx *c, int32_t *s5)
+int igks_get_schedule(const igks_ctx *c, int32_t *s6)
 {
-    if (!c || !s5) return IGKS_EINVAL;
-    for (int k = 0; k < NCLASS; k++) s5[k] = c->block[k];
-    s5[NCLASS] = c->sweep_wg ? 2 : 1;
+    if (!c || !s6) return IGKS_EINVAL;
+    for (int k = 0; k < NCLASS; k++) s6[k] = c->block[k];
+    s6[NCLASS] = c->sweep_wg ? 2 : 1;
+    s6[NCLASS + 1] = c->flux_pair ? 2 : 1;
     return IGKS_OK;
 }
 
-int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s5)
+int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s6)
 {
     int rc = check_ready(c, true);
     if (rc) return rc;
@@ -1174,18 +1191,26 @@ int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s5)
     int best[NCLASS];
     double best_t[NCLASS];
     for (int k = 0; k < NCLASS; k++) { best[k] = c->block[k]; best_t[k] = 1e300; }
-    const bool wg_auto = c->sweep_wg;
-    for (int b : cand) {
-        for (int k = 0; k < NCLASS; k++) c->block[k] = b;
-        c->sweep_wg = false;
-        rc = (c->opt.precision == IGKS_MIXED) ? tune_run(c, c->P32, iters) : tune_run(c, c->P64, iters);
-        if (rc) break;
-        for (int k = 0; k < NCLASS; k++) {
-            double tk = c->ktimes[ev_of[k]] + (k == 3 ? c->ktimes[5] : 0.0);
-            if (tk < best_t[k]) { best_t[k] = tk; best[k] = b; }
+    bool best_pair = c->flux_pair;
+    const bool wg_auto = c->sweep_wg, pair_auto = c->flux_pair;
+    for (int pair = 0; pair < 2 && !rc; pair++)
+        for (int b : cand) {
+            for (int k = 0; k < NCLASS; k++) c->block[k] = b;
+            c->sweep_wg = false;
+            c->flux_pair = pair != 0;
+            rc = (c->opt.precision == IGKS_MIXED) ? tune_run(c, c->P32, iters) : tune_run(c, c->P64, iters);
+            if (rc) break;
+            for (int k = 0; k < NCLASS; k++) {
+                double tk = c->ktimes[ev_of[k]] + (k == 3 ? c->ktimes[5] : 0.0);
+                if (tk < best_t[k]) {
+                    best_t[k] = tk;
+                    best[k] = b;
+                    if (k == 1) best_pair = pair != 0;
+                }
+            }
         }
-    }
     for (int k = 0; k < NCLASS; k++) c->block[k] = best[k];
+    c->flux_pair = rc ? pair_auto : best_pair;
     if (!rc && (double)c->g.N / std::max(1, c->g.nlev) < 16384.0) {
         // sweeps: one launch per wavefront (timed above) or one workgroup
         // (a candidate only while wavefronts are narrow)
@@ -1205,7 +1230,7 @@ int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s5)
     int rc2 = sync_scalars(c);
     if (rc) return rc;
     if (rc2) return rc2;
-    if (s5) igks_get_schedule(c, s5);
+    if (s6) igks_get_schedule(c, s6);
     return IGKS_OK;
 }
 

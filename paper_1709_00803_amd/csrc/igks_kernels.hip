@@ -238,6 +238,21 @@ __device__ __forceinline__ void mom_u(double U, double lam, double *m)
 #pragma unroll
     for (int k = 0; k < 6; k++) m[k + 2] = U * m[k + 1] + (k + 1) * h * m[k];
 }
+// The same half-space moments with the half chosen at run time: sgn = +1
+// for u > 0, -1 for u < 0 (the two lanes of a face take opposite halves).
+__device__ __forceinline__ void mom_u_half(double U, double lam, double sgn, double *m)
+{
+    double x = sqrt(lam) * U;
+    double e = exp(-x * x) * (0.5 / sqrt(M_PI * lam));
+    // the sign is applied by selection, not by a product, so that m[1] is
+    // formed the same way whether sgn is known at compile time or not
+    double es = sgn > 0.0 ? e : -e, xs = sgn > 0.0 ? -x : x;
+    m[0] = 0.5 * erfc(xs);
+    m[1] = U * m[0] + es;
+    double h = 0.5 / lam;
+#pragma unroll
+    for (int k = 0; k < 6; k++) m[k + 2] = U * m[k + 1] + (k + 1) * h * m[k];
+}
 // <xi^0>, <xi^2>, <xi^4> over K internal dimensions
 __device__ __forceinline__ void mom_xi(double lam, double *x)
 {
@@ -285,15 +300,27 @@ __device__ __forceinline__ void msolve(double U, double V, double lam, const dou
     a[0] = b[0] - U * a[1] - V * a[2] - 0.5 * a[3] * B;
 }
 
-// Per-side part of the interface distribution that does not depend on the
+// Value of the partner lane of a face's lane pair.
+__device__ __forceinline__ double pair_other(double v) { return __shfl_xor(v, 1); }
+
+// a + b rounded once and never fused with the product that produced a or b:
+// the sum of a face's two sides is then the same number on either lane of a
+// pair and in the one-lane kernel (a fused multiply-add would round
+// differently depending on which side's product it absorbed).
+__device__ __forceinline__ double add_sides(double a, double b)
+{
+#pragma clang fp contract(off)
+    return a + b;
+}
+
+// One side's part of the interface distribution that does not depend on the
 // equilibrium state: slopes a_n, a_t (Eq.4, Eq.101), A (Eq.11) and the
-// half-space moments that multiply them.  S = +1: left state on u > 0;
-// S = -1: right state on u < 0.  Accumulates (rho-weighted):
-//   w0 += <psi>, q5 += <(u a_n + v a_t) psi>, q6 += <A psi>,
-//   f4 += <u psi>, f5 += <u (u a_n + v a_t) psi>, f6 += <u A psi>.
-template <int S>
-__device__ __forceinline__ void side_terms(const double *w, const double *gn, const double *gt, double *w0,
-                                           double *q5, double *q6, double *f4, double *f5, double *f6)
+// half-space moments that multiply them, for the left state on u > 0
+// (sgn = +1) or the right state on u < 0 (sgn = -1).  Writes (rho-weighted)
+//   acc[0..3] = <psi>, acc[4..7] = <(u a_n + v a_t) psi>, acc[8..11] = <A psi>,
+//   acc[12..15] = <u psi>, acc[16..19] = <u (u a_n + v a_t) psi>, acc[20..23] = <u A psi>.
+__device__ __forceinline__ void side_terms(double sgn, const double *w, const double *gn, const double *gt,
+                                           double *acc)
 {
     double r = w[0], U = w[1] / r, V = w[2] / r, lam = lam_of(w);
     double an[4], at[4], A[4], b[4];
@@ -316,114 +343,106 @@ __device__ __forceinline__ void side_terms(const double *w, const double *gn, co
         for (int k = 0; k < 4; k++) b[k] = -(t1[k] + t2[k]);
         msolve(U, V, lam, b, A);
     }
-    mom_u<S>(U, lam, mu);
+    mom_u_half(U, lam, sgn, mu);
     double t[4], s[4];
     pmom1<0>(mu, mv, mx, t);
 #pragma unroll
-    for (int k = 0; k < 4; k++) w0[k] += r * t[k];
+    for (int k = 0; k < 4; k++) acc[k] = r * t[k];
     pmom1<1>(mu, mv, mx, t);
 #pragma unroll
-    for (int k = 0; k < 4; k++) f4[k] += r * t[k];
+    for (int k = 0; k < 4; k++) acc[12 + k] = r * t[k];
     pmom<1, 0>(mu, mv, mx, an, t);
     pmom<0, 1>(mu, mv, mx, at, s);
 #pragma unroll
-    for (int k = 0; k < 4; k++) q5[k] += r * (t[k] + s[k]);
+    for (int k = 0; k < 4; k++) acc[4 + k] = r * (t[k] + s[k]);
     pmom<2, 0>(mu, mv, mx, an, t);
     pmom<1, 1>(mu, mv, mx, at, s);
 #pragma unroll
-    for (int k = 0; k < 4; k++) f5[k] += r * (t[k] + s[k]);
+    for (int k = 0; k < 4; k++) acc[16 + k] = r * (t[k] + s[k]);
     pmom<0, 0>(mu, mv, mx, A, t);
 #pragma unroll
-    for (int k = 0; k < 4; k++) q6[k] += r * t[k];
+    for (int k = 0; k < 4; k++) acc[8 + k] = r * t[k];
     pmom<1, 0>(mu, mv, mx, A, t);
 #pragma unroll
-    for (int k = 0; k < 4; k++) f6[k] += r * t[k];
+    for (int k = 0; k < 4; k++) acc[20 + k] = r * t[k];
 }
 
-// GKS interface flux (Eq.4-5, Eq.11-14) in the face frame; returns the
-// flux integrated over [0, dt].  The equilibrium part is evaluated one
-// half space at a time so that only one set of moments is live at once.
-template <typename T>
-__device__ __forceinline__ void gks_flux(const Params<T> &P, const InstParam &ip, const double *wl, const double *gln, const double *glt,
-                                         const double *wr, const double *grn, const double *grt, const double *wlc,
-                                         const double *wrc, double dl, double dr, double dt, double nut_f,
-                                         double *F)
-{
-    double w0[4] = {0, 0, 0, 0}, q5[4] = {0, 0, 0, 0}, q6[4] = {0, 0, 0, 0};
-    double f4[4] = {0, 0, 0, 0}, f5[4] = {0, 0, 0, 0}, f6[4] = {0, 0, 0, 0};
-    side_terms<+1>(wl, gln, glt, w0, q5, q6, f4, f5, f6);
-    side_terms<-1>(wr, grn, grt, w0, q5, q6, f4, f5, f6);
-
-    // interface equilibrium g0 (moments of H g^l + (1-H) g^r)
-    double r0 = w0[0], U0 = w0[1] / r0, V0 = w0[2] / r0, lam0 = lam_of(w0);
-    double ir0 = 1.0 / r0;
-
-    // Eq.34 collision time at the interface and the time integrals of the
-    // six Eq.13 factors over [0, dt]
-    double mul = mu_lam(P.mu_law, ip, lam0), mut = 0.0;
-    if (ip.sa && nut_f > 0.0) mut = r0 * nut_f * sa_fv1(nut_f * r0 / mul);
-    double tau = (mul + mut) * 2.0 * lam0 / r0;
-    double eta = exp(-dt / tau), ome = -expm1(-dt / tau);
-    double T1 = dt - tau * ome;
-    double T2 = -tau * dt * (1.0 + eta) + 2.0 * tau * tau * ome;
-    double T3 = 0.5 * dt * dt - tau * dt + tau * tau * ome;
-    double T4 = tau * ome;
-    double T5 = tau * dt * eta - 2.0 * tau * tau * ome;
-    double T6 = -tau * tau * ome;
-
+// Equilibrium part of the interface (Eq.4-5, Eq.11-14), split so that the
+// two half spaces can be evaluated on one lane or on the two lanes of a
+// face.  gks_eq: g0 from the summed side moments, the Eq.34 collision time
+// and the time integrals of the six Eq.13 factors over [0, dt].
+struct GksEq {
+    double r0, U0, V0, lam0, ir0;
+    double T1, T2, T3, T4, T5, T6;
     double mv[8], mx[3];
-    mom_u<0>(V0, lam0, mv);
-    mom_xi(lam0, mx);
-    // q2 = <psi (abar_n H u + abar_n' (1-H) u + abar_t v)> and its flux
-    // moment f2 = <u psi (...)>, half space by half space
-    double q2[4], f2[4], a[4], b[4], t[4];
-    {
+};
+template <typename T>
+__device__ __forceinline__ void gks_eq(const Params<T> &P, const InstParam &ip, const double *w0, double dt,
+                                       double nut_f, GksEq &q)
+{
+    q.r0 = w0[0]; q.U0 = w0[1] / q.r0; q.V0 = w0[2] / q.r0; q.lam0 = lam_of(w0);
+    q.ir0 = 1.0 / q.r0;
+    double mul = mu_lam(P.mu_law, ip, q.lam0), mut = 0.0;
+    if (ip.sa && nut_f > 0.0) mut = q.r0 * nut_f * sa_fv1(nut_f * q.r0 / mul);
+    double tau = (mul + mut) * 2.0 * q.lam0 / q.r0;
+    double eta = exp(-dt / tau), ome = -expm1(-dt / tau);
+    q.T1 = dt - tau * ome;
+    q.T2 = -tau * dt * (1.0 + eta) + 2.0 * tau * tau * ome;
+    q.T3 = 0.5 * dt * dt - tau * dt + tau * tau * ome;
+    q.T4 = tau * ome;
+    q.T5 = tau * dt * eta - 2.0 * tau * tau * ome;
+    q.T6 = -tau * tau * ome;
+    mom_u<0>(q.V0, q.lam0, q.mv);
+    mom_xi(q.lam0, q.mx);
+}
+// One half space of q2 = <psi (abar_n H u + abar_n' (1-H) u)> and of its flux
+// moment f2 = <u psi (...)>: left (sgn = +1) with the slope (W0 - W_l)/d_l
+// on u > 0, right (sgn = -1) with (W_r - W0)/d_r on u < 0.
+__device__ __forceinline__ void gks_half(const GksEq &q, double sgn, const double *w0, const double *wc, double d,
+                                         double *q2, double *f2)
+{
+    double b[4], a[4], mh[8];
 #pragma unroll
-        for (int k = 0; k < 4; k++) b[k] = (w0[k] - wlc[k]) / dl * ir0;
-        msolve(U0, V0, lam0, b, a);
-        double mp[8];
-        mom_u<+1>(U0, lam0, mp);
-        pmom<1, 0>(mp, mv, mx, a, q2);
-        pmom<2, 0>(mp, mv, mx, a, f2);
+    for (int k = 0; k < 4; k++) {
+        double dw = sgn > 0.0 ? w0[k] - wc[k] : wc[k] - w0[k];
+        b[k] = dw / d * q.ir0;
     }
-    {
+    msolve(q.U0, q.V0, q.lam0, b, a);
+    mom_u_half(q.U0, q.lam0, sgn, mh);
+    pmom<1, 0>(mh, q.mv, q.mx, a, q2);
+    pmom<2, 0>(mh, q.mv, q.mx, a, f2);
+}
+// The rest, from the summed side moments acc, the summed half-space q2 and
+// f2, and the sum of the two sides' tangential slopes: the abar_t term,
+// Abar from Eq.12 and the flux of Eq.14 integrated over [0, dt].
+__device__ __forceinline__ void gks_finish(const GksEq &q, const double *acc, double *q2, double *f2,
+                                           const double *gt_sum, double dt, double *F)
+{
+    const double *q5 = acc + 4, *q6 = acc + 8, *f4 = acc + 12, *f5 = acc + 16, *f6 = acc + 20;
+    double mf[8], a[4], b[4], t[4];
+    mom_u<0>(q.U0, q.lam0, mf);
 #pragma unroll
-        for (int k = 0; k < 4; k++) b[k] = (wrc[k] - w0[k]) / dr * ir0;
-        msolve(U0, V0, lam0, b, a);
-        double mm[8];
-        mom_u<-1>(U0, lam0, mm);
-        pmom<1, 0>(mm, mv, mx, a, t);
+    for (int k = 0; k < 4; k++) b[k] = 0.5 * gt_sum[k] * q.ir0;
+    msolve(q.U0, q.V0, q.lam0, b, a);
+    pmom<0, 1>(mf, q.mv, q.mx, a, t);
 #pragma unroll
-        for (int k = 0; k < 4; k++) q2[k] += t[k];
-        pmom<2, 0>(mm, mv, mx, a, t);
-#pragma unroll
-        for (int k = 0; k < 4; k++) f2[k] += t[k];
-    }
-    double mf[8];
-    mom_u<0>(U0, lam0, mf);
-#pragma unroll
-    for (int k = 0; k < 4; k++) b[k] = 0.5 * (glt[k] + grt[k]) * ir0;
-    msolve(U0, V0, lam0, b, a);
-    pmom<0, 1>(mf, mv, mx, a, t);
-#pragma unroll
-    for (int k = 0; k < 4; k++) q2[k] = r0 * (q2[k] + t[k]);
-    pmom<1, 1>(mf, mv, mx, a, t);
+    for (int k = 0; k < 4; k++) q2[k] = q.r0 * (q2[k] + t[k]);
+    pmom<1, 1>(mf, q.mv, q.mx, a, t);
 #pragma unroll
     for (int k = 0; k < 4; k++) f2[k] += t[k];
-
     // Eq.12 -> Abar
-    double den = r0 * (0.5 * dt * dt - T3);
+    double den = q.r0 * (0.5 * dt * dt - q.T3);
 #pragma unroll
-    for (int k = 0; k < 4; k++) b[k] = (T2 * q2[k] + T5 * q5[k] + T6 * q6[k]) / den;
-    msolve(U0, V0, lam0, b, a);
-
+    for (int k = 0; k < 4; k++) b[k] = (q.T2 * q2[k] + q.T5 * q5[k] + q.T6 * q6[k]) / den;
+    msolve(q.U0, q.V0, q.lam0, b, a);
     // Eq.14
     double e1[4];
-    pmom1<1>(mf, mv, mx, e1);
-    pmom<1, 0>(mf, mv, mx, a, t);
+    pmom1<1>(mf, q.mv, q.mx, e1);
+    pmom<1, 0>(mf, q.mv, q.mx, a, t);
 #pragma unroll
     for (int k = 0; k < 4; k++)
-        F[k] = T1 * r0 * e1[k] + T2 * r0 * f2[k] + T3 * r0 * t[k] + T4 * f4[k] + T5 * f5[k] + T6 * f6[k];
+        F[k] = q.T1 * q.r0 * e1[k] + q.T2 * q.r0 * f2[k] + q.T3 * q.r0 * t[k] + q.T4 * f4[k] + q.T5 * f5[k] +
+               q.T6 * f6[k];
 }
 
 // Euler flux Jacobian-vector product J(W, n) d (the linearised flux of the
@@ -585,133 +604,218 @@ __device__ __forceinline__ bool physical(const double *w)
     return w[0] > 0.0 && (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]) > 0.0;
 }
 
-// Per face: reconstruction (Eq.10), ghost side, the GKS flux, the LU-SGS
-// spectral radius and the SA face terms (Eq.28-30).
+// One side of a face (side 0: the owner cell; side 1: the neighbour, or on
+// a boundary face the ghost cell): reconstructed face state (Eq.10, the
+// cell value where the reconstruction is not physical), slopes and
+// cell-centre state rotated into the face frame (normal n out of the owner,
+// tangent t = (-n_y, n_x)), the distance to the face and the side's
+// spectral-radius and SA quantities.
+struct FaceSide {
+    double fw[4], gn[4], gt[4], fwc[4];
+    double nut;               // nu~ of the cell-centre state
+    double d;                 // centroid-face distance (d_l or d_r)
+    double ls, evr, nu, q;    // |V.n| + c, (mu + mu_t)/rho, nu, V.n
+};
 template <typename T>
-__device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, double dt)
+__device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &ip, const double *W, int f, int side,
+                                          FaceSide &o)
 {
-    const int N = P.nc, F = P.nf;
-    const InstParam &ip = P.ip[inst];
-    const double *W = cur_state(P, inst);
-    int l = P.fl[f], rr = P.fr[f];
-    double nx = P.fnx[f], ny = P.fny[f], S = P.flen[f];
-    double tx = -ny, ty = nx;
-    double wl[5], WL[4], glx[4], gly[4];
+    const int N = P.nc;
+    const int l = P.fl[f], rr = P.fr[f];
+    const bool bnd = rr < 0;
+    const double nx = P.fnx[f], ny = P.fny[f], tx = -ny, ty = nx;
+    // a ghost side starts from the owner's reconstruction
+    const bool own = side == 0 || bnd;
+    const int cm = own ? l : rr;
+    const double *rv = own ? P.frl : P.frr;
+    const double rx = rv[2 * f], ry = rv[2 * f + 1];
+    double wm[5], WM[4], gx[4], gy[4];
 #pragma unroll
-    for (int k = 0; k < 5; k++) wl[k] = W[k * N + l];
-    double rlx = P.frl[2 * f], rly = P.frl[2 * f + 1];
+    for (int k = 0; k < 5; k++) wm[k] = W[k * N + cm];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        glx[k] = P.grad[k * N + l];
-        gly[k] = P.grad[(4 + k) * N + l];
-        WL[k] = wl[k] + glx[k] * rlx + gly[k] * rly;
+        gx[k] = P.grad[k * N + cm];
+        gy[k] = P.grad[(4 + k) * N + cm];
+        WM[k] = wm[k] + gx[k] * rx + gy[k] * ry;
     }
-    if (!physical(WL)) {
+    if (!physical(WM)) {
 #pragma unroll
-        for (int k = 0; k < 4; k++) { WL[k] = wl[k]; glx[k] = gly[k] = 0.0; }
+        for (int k = 0; k < 4; k++) { WM[k] = wm[k]; gx[k] = gy[k] = 0.0; }
     }
-    double WR[4], grx[4], gry[4], wrc[5], dr;
-    double dl = P.fdl[f], rn = P.frn[f];
-    if (rr >= 0) {
-        double rrx = P.frr[2 * f], rry = P.frr[2 * f + 1];
-#pragma unroll
-        for (int k = 0; k < 5; k++) wrc[k] = W[k * N + rr];
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            grx[k] = P.grad[k * N + rr];
-            gry[k] = P.grad[(4 + k) * N + rr];
-            WR[k] = wrc[k] + grx[k] * rrx + gry[k] * rry;
-        }
-        if (!physical(WR)) {
-#pragma unroll
-            for (int k = 0; k < 4; k++) { WR[k] = wrc[k]; grx[k] = gry[k] = 0.0; }
-        }
-        dr = P.fdr[f];
-    } else {
-        // ghost side: boundary map of the reconstructed interior face state;
+    o.d = side ? P.fdr[f] : P.fdl[f];   // fdr = fdl on a boundary face
+    const bool ghost_side = bnd && side == 1;
+    const int bc = ghost_side ? P.fbc[f] : 0;
+    if (ghost_side) {
+        // boundary map of the reconstructed interior face state; the
         // cell-centre ghost value from the interior cell centre
-        int bc = P.fbc[f];
-        double tmp[5] = {WL[0], WL[1], WL[2], WL[3], wl[4]}, out[5];
+        double tmp[5] = {WM[0], WM[1], WM[2], WM[3], wm[4]}, out[5], wg[5];
         ghost(ip, bc, tmp, nx, ny, out);
+        ghost(ip, bc, wm, nx, ny, wg);
 #pragma unroll
-        for (int k = 0; k < 4; k++) { WR[k] = out[k]; grx[k] = gry[k] = 0.0; }
-        ghost(ip, bc, wl, nx, ny, wrc);
-        dr = dl;
+        for (int k = 0; k < 4; k++) WM[k] = out[k];
+#pragma unroll
+        for (int k = 0; k < 5; k++) wm[k] = wg[k];
     }
-
-    // spectral radius of the face for the implicit operator
     {
-        double qi = (wl[1] * nx + wl[2] * ny) / wl[0], qj = (wrc[1] * nx + wrc[2] * ny) / wrc[0];
-        double li = fabs(qi) + sqrt(GAMMA / (2.0 * lam_of(wl)));
-        double lj = fabs(qj) + sqrt(GAMMA / (2.0 * lam_of(wrc)));
-        double lamf = fmax(li, lj);
-        double mi = mu_lam(P.mu_law, ip, lam_of(wl)), mj = mu_lam(P.mu_law, ip, lam_of(wrc));
-        if (P.visc_sr) {
-            double ei = mi, ej = mj;
-            if (ip.sa) {
-                if (wl[4] > 0) ei += wl[0] * wl[4] * sa_fv1(wl[4] * wl[0] / mi);
-                if (wrc[4] > 0) ej += wrc[0] * wrc[4] * sa_fv1(wrc[4] * wrc[0] / mj);
-            }
-            lamf += (ei / wl[0] + ej / wrc[0]) / rn;
-        }
-        P.lam[f] = lamf;
-        if (ip.sa) {
-            double nui = mi / wl[0], nuj = mj / wrc[0];
-            double ti = wl[4], tj = wrc[4];
-            double g = (tj - ti) / rn;
-            double Finv = 0.5 * (qi + fabs(qi)) * ti + 0.5 * (qj - fabs(qj)) * tj;
-            double Fvis = (0.5 / SA_SIGMA) * ((nui + nuj) + (1.0 + SA_CB2) * (ti + tj)) * g;
-            P.saf[f] = (Fvis - Finv) * S;
-            P.sag[f] = g * S;
-            P.sak[f] = (0.5 / SA_SIGMA) * ((nui + nuj) + (1.0 + SA_CB2) * (ti + tj)) * S / rn;
-        }
+        o.q = (wm[1] * nx + wm[2] * ny) / wm[0];
+        const double lm = lam_of(wm);
+        o.ls = fabs(o.q) + sqrt(GAMMA / (2.0 * lm));
+        const double mu = mu_lam(P.mu_law, ip, lm);
+        double ev = mu;
+        if (ip.sa && wm[4] > 0) ev += wm[0] * wm[4] * sa_fv1(wm[4] * wm[0] / mu);
+        o.evr = ev / wm[0];
+        o.nu = mu / wm[0];
+        o.nut = wm[4];
     }
-    // face frame
-    double fwl[4], fwr[4], fwlc[4], fwrc[4], gln[4], glt[4], grn[4], grt[4];
     auto rot = [&](const double *src, double *dst) {
         dst[0] = src[0];
         dst[1] = src[1] * nx + src[2] * ny;
         dst[2] = src[1] * tx + src[2] * ty;
         dst[3] = src[3];
     };
-    rot(WL, fwl); rot(WR, fwr); rot(wl, fwlc); rot(wrc, fwrc);
+    rot(WM, o.fw);
+    rot(wm, o.fwc);
     {
         double tn[4], tt[4];
 #pragma unroll
-        for (int k = 0; k < 4; k++) { tn[k] = glx[k] * nx + gly[k] * ny; tt[k] = glx[k] * tx + gly[k] * ty; }
-        rot(tn, gln); rot(tt, glt);
-#pragma unroll
-        for (int k = 0; k < 4; k++) { tn[k] = grx[k] * nx + gry[k] * ny; tt[k] = grx[k] * tx + gry[k] * ty; }
-        rot(tn, grn); rot(tt, grt);
+        for (int k = 0; k < 4; k++) { tn[k] = gx[k] * nx + gy[k] * ny; tt[k] = gx[k] * tx + gy[k] * ty; }
+        rot(tn, o.gn);
+        rot(tt, o.gt);
     }
-    if (rr < 0) {
+    if (ghost_side) {
         // ghost cell of a symmetry face = mirror image of the interior cell,
         // of a no-slip wall = its point reflection through the face
         // (bounce-back), slopes included: the normal derivative flips, the
         // boundary map acts on the face-frame momentum, and the wall also
-        // flips the tangential derivative.
-        int bc = P.fbc[f];
+        // flips the tangential derivative.  Free-stream and outflow ghosts
+        // have zero slopes.
         if (bc == BC_SYMMETRY || bc == BC_WALL) {
-            double bt = (bc == BC_WALL) ? -1.0 : 1.0;
-            grn[0] = -gln[0]; grn[1] = gln[1]; grn[2] = -bt * gln[2]; grn[3] = -gln[3];
-            grt[0] = bt * glt[0]; grt[1] = -bt * glt[1]; grt[2] = glt[2]; grt[3] = bt * glt[3];
+            const double bt = (bc == BC_WALL) ? -1.0 : 1.0;
+            const double n0 = o.gn[0], n1 = o.gn[1], n2 = o.gn[2], n3 = o.gn[3];
+            const double t0 = o.gt[0], t1 = o.gt[1], t2 = o.gt[2], t3 = o.gt[3];
+            o.gn[0] = -n0; o.gn[1] = n1; o.gn[2] = -bt * n2; o.gn[3] = -n3;
+            o.gt[0] = bt * t0; o.gt[1] = -bt * t1; o.gt[2] = t2; o.gt[3] = bt * t3;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; k++) o.gn[k] = o.gt[k] = 0.0;
         }
     }
-    double nutf = fmax(0.5 * (wl[4] + wrc[4]), 0.0);
-    double Fr[4];
-    gks_flux(P, ip, fwl, gln, glt, fwr, grn, grt, fwlc, fwrc, dl, dr, dt, nutf, Fr);
-    double idt = 1.0 / dt;
-    double Fn = Fr[1] * idt, Ft = Fr[2] * idt;
-    P.flux[f] = Fr[0] * idt * S;
-    P.flux[F + f] = (Fn * nx + Ft * tx) * S;
-    P.flux[2 * F + f] = (Fn * ny + Ft * ty) * S;
-    P.flux[3 * F + f] = Fr[3] * idt * S;
 }
 
+// Spectral radius of the face for the implicit operator and the SA face
+// terms (Eq.28-30) from the two sides' quantities.
+template <typename T>
+__device__ __forceinline__ void face_implicit_terms(const Params<T> &P, const InstParam &ip, int f, double lsl,
+                                                    double lsr, double evl, double evr, double nul, double nur,
+                                                    double ti, double tj, double ql, double qr)
+{
+    const double rn = P.frn[f], S = P.flen[f];
+    double lamf = fmax(lsl, lsr);
+    if (P.visc_sr) lamf += (evl + evr) / rn;
+    P.lam[f] = lamf;
+    if (ip.sa) {
+        double g = (tj - ti) / rn;
+        double Finv = 0.5 * (ql + fabs(ql)) * ti + 0.5 * (qr - fabs(qr)) * tj;
+        double kf = (0.5 / SA_SIGMA) * ((nul + nur) + (1.0 + SA_CB2) * (ti + tj));
+        P.saf[f] = (kf * g - Finv) * S;
+        P.sag[f] = g * S;
+        P.sak[f] = kf * S / rn;
+    }
+}
+
+// face-frame flux integrated over [0, dt] -> F S / dt in the global frame
+__device__ __forceinline__ void flux_global(const double *Fr, double dt, double nx, double ny, double S, double *g)
+{
+    const double tx = -ny, ty = nx, idt = 1.0 / dt;
+    const double Fn = Fr[1] * idt, Ft = Fr[2] * idt;
+    g[0] = Fr[0] * idt * S;
+    g[1] = (Fn * nx + Ft * tx) * S;
+    g[2] = (Fn * ny + Ft * ty) * S;
+    g[3] = Fr[3] * idt * S;
+}
+
+// Per face, one lane: both sides, the GKS flux, the implicit terms.
+template <typename T>
+__device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, double dt)
+{
+    const int F = P.nf;
+    const InstParam &ip = P.ip[inst];
+    const double *W = cur_state(P, inst);
+    FaceSide L, R;
+    face_side(P, ip, W, f, 0, L);
+    face_side(P, ip, W, f, 1, R);
+    face_implicit_terms(P, ip, f, L.ls, R.ls, L.evr, R.evr, L.nu, R.nu, L.nut, R.nut, L.q, R.q);
+    const double nutf = fmax(0.5 * add_sides(L.nut, R.nut), 0.0);
+    double acc[24], accr[24];
+    side_terms(1.0, L.fw, L.gn, L.gt, acc);
+    side_terms(-1.0, R.fw, R.gn, R.gt, accr);
+#pragma unroll
+    for (int k = 0; k < 24; k++) acc[k] = add_sides(acc[k], accr[k]);
+    GksEq q;
+    gks_eq(P, ip, acc, dt, nutf, q);
+    double q2[4], f2[4], q2r[4], f2r[4], gts[4];
+    gks_half(q, 1.0, acc, L.fwc, L.d, q2, f2);
+    gks_half(q, -1.0, acc, R.fwc, R.d, q2r, f2r);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        q2[k] = add_sides(q2[k], q2r[k]);
+        f2[k] = add_sides(f2[k], f2r[k]);
+        gts[k] = add_sides(L.gt[k], R.gt[k]);
+    }
+    double Fr[4], g[4];
+    gks_finish(q, acc, q2, f2, gts, dt, Fr);
+    flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
+#pragma unroll
+    for (int k = 0; k < 4; k++) P.flux[k * F + f] = g[k];
+}
+
+// Per face, on a pair of lanes (side 0 the owner, side 1 the neighbour or
+// ghost): each lane builds its side and integrates its half space; the sums
+// of the two halves are formed on both lanes (a + b is the same number in
+// either order) and the equilibrium part is evaluated on both.  Both lanes
+// of a pair call this together.
+template <typename T>
+__device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int side, int inst, double dt)
+{
+    const int F = P.nf;
+    const InstParam &ip = P.ip[inst];
+    const double *W = cur_state(P, inst);
+    FaceSide M;
+    face_side(P, ip, W, f, side, M);
+    {
+        const double ls_o = pair_other(M.ls), evr_o = pair_other(M.evr), nu_o = pair_other(M.nu);
+        const double t_o = pair_other(M.nut), q_o = pair_other(M.q);
+        if (side == 0) face_implicit_terms(P, ip, f, M.ls, ls_o, M.evr, evr_o, M.nu, nu_o, M.nut, t_o, M.q, q_o);
+    }
+    const double nutf = fmax(0.5 * add_sides(M.nut, pair_other(M.nut)), 0.0);
+    const double sgn = side ? -1.0 : 1.0;
+    double acc[24];
+    side_terms(sgn, M.fw, M.gn, M.gt, acc);
+#pragma unroll
+    for (int k = 0; k < 24; k++) acc[k] = add_sides(acc[k], pair_other(acc[k]));
+    GksEq q;
+    gks_eq(P, ip, acc, dt, nutf, q);
+    double q2[4], f2[4], gts[4];
+    gks_half(q, sgn, acc, M.fwc, M.d, q2, f2);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        q2[k] = add_sides(q2[k], pair_other(q2[k]));
+        f2[k] = add_sides(f2[k], pair_other(f2[k]));
+        gts[k] = add_sides(M.gt[k], pair_other(M.gt[k]));
+    }
+    double Fr[4], g[4];
+    gks_finish(q, acc, q2, f2, gts, dt, Fr);
+    flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
+    // each lane writes two of the four components
+    P.flux[(2 * side) * F + f] = side ? g[2] : g[0];
+    P.flux[(2 * side + 1) * F + f] = side ? g[3] : g[1];
+}
+
+// one lane per face
 template <typename T>
 __global__ __launch_bounds__(256) void k_flux(Params<T> P)
 {
-    int f = xcd_block() * blockDim.x + threadIdx.x;
+    const int f = xcd_block() * blockDim.x + threadIdx.x;
     int inst = -1;
     if (f < P.nf) {
         inst = face_inst(P, f);
@@ -720,6 +824,22 @@ __global__ __launch_bounds__(256) void k_flux(Params<T> P)
     double dt = instance_dt(P.is, inst);
     if (inst < 0) return;
     flux_face(P, f, inst, dt);
+}
+
+// two lanes per face
+template <typename T>
+__global__ __launch_bounds__(256) void k_flux2(Params<T> P)
+{
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
+    const int f = t >> 1, side = t & 1;
+    int inst = -1;
+    if (f < P.nf) {
+        inst = face_inst(P, f);
+        if (P.is[inst].halt) inst = -1;
+    }
+    double dt = instance_dt(P.is, inst);
+    if (inst < 0) return;   // both lanes of a pair leave together
+    flux_face_pair(P, f, side, inst, dt);
 }
 
 // Per cell: residual M (Eq.16) as the signed sum of its face fluxes, the
@@ -1115,7 +1235,8 @@ template <typename T> void launch_commit(const Launch &L, const Params<T> &P, in
 }
 template <typename T> void launch_flux(const Launch &L, const Params<T> &P)
 {
-    hipLaunchKernelGGL(k_flux<T>, dim3(nblk(P.nf, L.block[1])), dim3(L.block[1]), 0, L.s, P);
+    if (L.flux_pair) hipLaunchKernelGGL(k_flux2<T>, dim3(nblk(2 * P.nf, L.block[1])), dim3(L.block[1]), 0, L.s, P);
+    else hipLaunchKernelGGL(k_flux<T>, dim3(nblk(P.nf, L.block[1])), dim3(L.block[1]), 0, L.s, P);
 }
 template <typename T> void launch_gather(const Launch &L, const Params<T> &P)
 {

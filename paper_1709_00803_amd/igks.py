@@ -34,7 +34,7 @@ class igks_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("limiter", C.c_int), ("cfl_init", C.c_double),
                 ("cfl_min", C.c_double), ("cfl_max", C.c_double), ("cfl_mode", C.c_int),
                 ("cfl_flux", C.c_double), ("visc_sr", C.c_int), ("mu_law", C.c_int),
-                ("chunk", C.c_int), ("block", C.c_int), ("sweep", C.c_int)]
+                ("chunk", C.c_int), ("block", C.c_int), ("sweep", C.c_int), ("flux_lanes", C.c_int)]
 
 
 class igks_residual(C.Structure):
@@ -82,6 +82,7 @@ _SIGS = {
     "igks_batch_get_history": (C.c_int, [_P, C.c_int32, _DP, C.c_int32, _IP]),
     "igks_batch_get_state": (C.c_int, [_P, C.c_int32, _DP]),
     "igks_batch_set_state": (C.c_int, [_P, C.c_int32, _DP, C.POINTER(igks_scalars)]),
+    "igks_batch_get_scalars": (C.c_int, [_P, C.c_int32, C.POINTER(igks_scalars)]),
     "igks_batch_compute_residual": (C.c_int, [_P, C.c_int32, _DP]),
     "igks_batch_get_wall_loads": (C.c_int, [_P, C.c_int32, _DP, _DP, _DP, _DP, _DP]),
     "igks_batch_status": (C.c_int, [_P, C.c_int32, _IP]),
@@ -189,12 +190,12 @@ class _Context:
         return dict(zip(KERNEL_CLASSES, t))
 
     def autotune(self, iters=10):
-        s = np.zeros(5, dtype=np.int32)
+        s = np.zeros(6, dtype=np.int32)
         self._chk(igks_autotune(self.ctx, iters, s.ctypes.data_as(_IP)))
         return s
 
     def schedule(self):
-        s = np.zeros(5, dtype=np.int32)
+        s = np.zeros(6, dtype=np.int32)
         self._chk(igks_get_schedule(self.ctx, s.ctypes.data_as(_IP)))
         return s
 
@@ -301,6 +302,11 @@ class BatchSolver(_Context):
     def set_state(self, i, W, scalars: igks_scalars | None = None):
         W, p = _d(np.asarray(W).reshape(5, self.n[i]))
         self._chk(igks_batch_set_state(self.ctx, i, p, C.byref(scalars) if scalars is not None else None))
+
+    def scalars(self, i) -> igks_scalars:
+        s = igks_scalars()
+        self._chk(igks_batch_get_scalars(self.ctx, i, C.byref(s)))
+        return s
 
     def compute_residual(self, i):
         M = np.zeros((5, self.n[i]))

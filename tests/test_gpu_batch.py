@@ -1,10 +1,10 @@
 """GPU batches: many instances of uneven size iterated together in the same
 launches.  Instance i of a batch must give bitwise the iterates of the same
-instance run alone (the per-cell arithmetic, the per-instance reductions and
-their order do not depend on the other instances); each instance's residual
-matches the FP64 oracle to the same 1e-12-of-gross bar as single runs; the
-autotuner leaves state and scalars bitwise as they were and the launch
-schedule it picks does not change any result.
+instance run alone with the same flux kernel (the per-cell arithmetic, the
+per-instance reductions and their order do not depend on the other
+instances); each instance's residual matches the FP64 oracle to the same
+1e-12-of-gross bar as single runs; the autotuner leaves state, scalars and
+history bitwise as they were, and block sizes never change a result.
 """
 import sys
 
@@ -50,10 +50,10 @@ def test_batch_instance_equals_single_run(igks, small_batch):
     say("batch sizes", [m.n_cells for m in meshes], "flows", flows)
     for prec in ("fp64", "mixed"):
         p = igks.IGKS_MIXED if prec == "mixed" else igks.IGKS_FP64
-        b = run_batch(igks, meshes, flows, 12, precision=p, cfl_init=5.0, chunk=4)
+        b = run_batch(igks, meshes, flows, 12, precision=p, cfl_init=5.0, chunk=4, flux_lanes=1)
         say(f"[{prec}] batch: {b.total_cells} cells, {b.nlev} wavefronts")
         for i, (m, f) in enumerate(zip(meshes, flows)):
-            s = igks.Solver(m, precision=p, cfl_init=5.0, chunk=4)
+            s = igks.Solver(m, precision=p, cfl_init=5.0, chunk=4, flux_lanes=1)
             s.set_freestream(*f)
             s.iterate(12)
             Wb, Ws = b.get_state(i), s.get_state()
@@ -96,18 +96,32 @@ def test_batch_residual_parity(igks, small_batch):
 
 
 def test_autotune_keeps_state_and_results(igks, small_batch):
+    """The autotuner restores state, scalars and history bitwise, and the
+    run then continues exactly as a run started with the chosen schedule
+    (block sizes never change results; the flux lane count is part of the
+    schedule and is fixed in the reference run)."""
     meshes, flows = small_batch
-    ref = run_batch(igks, meshes, flows, 16, precision=igks.IGKS_MIXED, cfl_init=5.0, chunk=4)
     b = run_batch(igks, meshes, flows, 8, precision=igks.IGKS_MIXED, cfl_init=5.0, chunk=4)
     before = [b.get_state(i) for i in range(len(meshes))]
     res_before = [b.residual(i) for i in range(len(meshes))]
+    hist_before = [b.history(i) for i in range(len(meshes))]
+    sc_before = [b.scalars(i) for i in range(len(meshes))]
     sched = b.autotune(3)
     say("autotuned schedule", sched.tolist())
-    assert set(sched[:4].tolist()) <= {64, 128, 256} and sched[4] in (1, 2)
+    assert set(sched[:4].tolist()) <= {64, 128, 256} and sched[4] in (1, 2) and sched[5] in (1, 2)
     assert np.array_equal(sched, b.schedule())
     for i in range(len(meshes)):
         assert np.array_equal(b.get_state(i), before[i])
         assert b.residual(i) == res_before[i]
+        assert np.array_equal(b.history(i), hist_before[i])
+    # the reference restarts from the same state and scalars with the chosen
+    # flux kernel and sweep schedule but default block sizes
+    ref = igks.BatchSolver(meshes, precision=igks.IGKS_MIXED, cfl_init=5.0, chunk=4,
+                           sweep=int(sched[4]), flux_lanes=int(sched[5]))
+    for i, f in enumerate(flows):
+        ref.set_freestream(i, *f)
+        ref.set_state(i, before[i], sc_before[i])
+    ref.iterate(8)
     b.iterate(8)
     for i in range(len(meshes)):
         assert np.array_equal(b.get_state(i), ref.get_state(i)), i

@@ -200,6 +200,34 @@ def test_sweep_schedules_match(igks):
     assert np.array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("workload", ["random", "jouk40k"])
+def test_flux_lane_counts_match(igks, workload):
+    """The flux on one lane per face and on two lanes per face agree to
+    rounding: the same operations, except where the compiler fuses a
+    different multiply with an add (measured: a few ulp of the residual)."""
+    if workload == "random":
+        m = mg.colour_order(mg.random_hybrid(12, 9, seed=13, tags=TAGS_SYM))[0]
+        flow, n = (0.3, 1.0, 3e4, 3.0), 8
+    else:
+        m = mg.workload("jouk40k")
+        flow, n = (0.5, 2.0, 5000.0, -1.0), 4
+    out = []
+    for lanes in (1, 2):
+        g = igks.Solver(m, cfl_init=20.0, chunk=4, flux_lanes=lanes)
+        g.set_freestream(*flow)
+        g.iterate(n)
+        W = g.get_state()
+        g.set_state(out[0][0] if out else W)      # the residual of one and the same state
+        out.append((W, g.compute_residual(), g))
+    W1, W2 = out[0][0][:4], out[1][0][:4]
+    sw = (np.abs(W2 - W1) / np.abs(W1).max(axis=1, keepdims=True)).max()
+    M1, M2 = out[0][1], out[1][1]
+    # the residual cancels: compare against its largest magnitude
+    sm = (np.abs(M2[:4] - M1[:4]) / np.abs(M1[:4]).max(axis=1, keepdims=True)).max()
+    say(f"[flux lanes {workload}] state {sw:.2e} residual {sm:.2e}")
+    assert sw <= 1e-12 and sm <= 1e-11
+
+
 def test_mixed_precision_tracks_fp64(igks):
     """FP32 sweeps with the FP64 residual and update: the iterates stay
     within FP32 rounding of the FP64 path, and the residual evaluation

@@ -174,7 +174,8 @@ def test_batch_bookkeeping():
 
 
 def test_call_order_and_option_errors():
-    for bad in (dict(block=96), dict(block=512), dict(sweep=3), dict(precision=5), dict(chunk=-1)):
+    for bad in (dict(block=96), dict(block=512), dict(sweep=3), dict(precision=5), dict(chunk=-1),
+                dict(flux_lanes=3)):
         rc, ctx = ctx_for(**bad)
         assert rc == igks.IGKS_EINVAL, bad
         assert not ctx.value
@@ -196,9 +197,9 @@ def test_call_order_and_option_errors():
         sz = C.c_size_t()
         igks.igks_workspace_size(ctx, C.byref(sz))
         assert igks.igks_bind_workspace(ctx, C.c_void_p(0x101), sz.value) == igks.IGKS_EINVAL   # misaligned
-        s5 = np.zeros(5, np.int32)
-        assert igks.igks_get_schedule(ctx, s5.ctypes.data_as(igks._IP)) == igks.IGKS_OK
-        assert s5.tolist() == [256, 256, 256, 256, 1]
+        s6 = np.zeros(6, np.int32)
+        assert igks.igks_get_schedule(ctx, s6.ctypes.data_as(igks._IP)) == igks.IGKS_OK
+        assert s6.tolist() == [256, 256, 256, 256, 1, 1]
     finally:
         igks.igks_destroy(ctx)
     igks.igks_destroy(None)
