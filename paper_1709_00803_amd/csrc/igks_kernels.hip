@@ -1151,7 +1151,7 @@ __global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
 // next).  Used when wavefronts are many and narrow.  Every thread runs the
 // same number of rounds, so the wave-wide slot updates see full waves.
 template <typename T, bool FWD>
-__global__ __launch_bounds__(1024) void k_sweep_wg(Params<T> P, const int *lev_off, int nlev)
+__global__ __launch_bounds__(512) void k_sweep_wg(Params<T> P, const int *lev_off, int nlev)
 {
     for (int i = 0; i < nlev; i++) {
         int l = FWD ? i : nlev - 1 - i;
@@ -1257,8 +1257,9 @@ template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int
 }
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd)
 {
-    if (fwd) hipLaunchKernelGGL((k_sweep_wg<T, true>), dim3(1), dim3(1024), 0, L.s, P, lev_off, nlev);
-    else hipLaunchKernelGGL((k_sweep_wg<T, false>), dim3(1), dim3(1024), 0, L.s, P, lev_off, nlev);
+    // 512 threads: the backward step with the update fits in registers (1024 spilled)
+    if (fwd) hipLaunchKernelGGL((k_sweep_wg<T, true>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
+    else hipLaunchKernelGGL((k_sweep_wg<T, false>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
 }
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
                           const int *woff, const double *wseg, double *dwall)
