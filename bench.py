@@ -94,19 +94,20 @@ def measured_traffic(workload, kernel):
     return d.get("bytes_per_launch", {}).get(kernel)
 
 
-def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000):
+def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=10.0, chunk=100):
     """Iterations and seconds from the impulsive start to a density-residual
-    drop of `target` on the laminar flat plate (64x32, natural order)."""
+    drop of `target` on the laminar flat plate (64x32, natural order);
+    scheme 1: the explicit scheme (Eq.15, local steps at a fixed CFL)."""
     import torch
     m = mg.flat_plate()
-    s = igks.Solver(m, precision=precision, cfl_init=10.0, chunk=100)
+    s = igks.Solver(m, precision=precision, cfl_init=cfl, chunk=chunk, scheme=scheme)
     s.set_freestream(*WORKLOADS["plate64x32"]["flow"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it = 0
     while it < max_it:
-        s.iterate(100)
-        it += 100
+        s.iterate(chunk)
+        it += chunk
         if s.residual()["res_drop"] <= target:
             break
     torch.cuda.synchronize()
@@ -320,7 +321,9 @@ def main():
         out["time_to_1e-10"] = {"workload": "plate64x32 (natural order), Ma 0.3 Re_L 1e4, CFL 10 -> Eq.25",
                                 "fp64": time_to_drop(igks, mg, igks.IGKS_FP64),
                                 "mixed": time_to_drop(igks, mg, igks.IGKS_MIXED),
-                                "batched_plates": time_to_drop_batch(igks, mg)}
+                                "batched_plates": time_to_drop_batch(igks, mg),
+                                "explicit_fp64_cfl0.9": time_to_drop(igks, mg, igks.IGKS_FP64, scheme=1, cfl=0.9,
+                                                                     chunk=1000, max_it=400000)}
     if not args.no_cpu:
         out["cpu_baseline"] = run_cpu_baseline(list(zip(meshes, flows))[:4])
     print(json.dumps(out), flush=True)

@@ -80,6 +80,9 @@ typedef struct igks_options {
                            2 all wavefronts in one workgroup (barrier between wavefronts) */
     int flux_lanes;     /* lanes per face of the flux kernel: 0 auto (2 from 131072 faces on),
                            1 or 2; the two agree to rounding */
+    int scheme;         /* 0: implicit LU-SGS (Eq.18-22); 1: explicit Eq.15 with local time
+                           steps dt_i = CFL Omega_i / (Lambda_c)_i, CFL = cfl_init fixed
+                           (the paper's explicit GKS baseline) */
 } igks_options;
 
 typedef struct igks_residual {

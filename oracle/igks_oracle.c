@@ -49,6 +49,7 @@ typedef struct {
     double cfl_flux;    /* delta_CFL0 of Eq.23 */
     int visc_sr;        /* viscous term in the LU-SGS spectral radius */
     int mu_law;         /* 0: Sutherland, 1: constant */
+    int scheme;         /* 0: implicit LU-SGS (Eq.18-22); 1: explicit Eq.15 with local time steps */
 } oigks_options;
 
 typedef struct {
@@ -470,7 +471,7 @@ static void free_mesh(oigks_ctx *c)
 
 EXPORT void oigks_default_options(oigks_options *o)
 {
-    o->limiter = 0; o->cfl_init = 1000.0; o->cfl_min = 1.0; o->cfl_max = 1e6; o->cfl_mode = 0;
+    o->limiter = 0; o->cfl_init = 1000.0; o->cfl_min = 1.0; o->cfl_max = 1e6; o->cfl_mode = 0; o->scheme = 0;
     o->cfl_flux = 1.0; o->visc_sr = 1; o->mu_law = 0;
 }
 
@@ -1088,14 +1089,26 @@ EXPORT int oigks_iterate(oigks_ctx *c, int n, int *n_done)
         double inf, l2, sal2;
         norms(c, &inf, &l2, &sal2);
         if (c->iter == 0) { c->res0 = l2; c->cfl = c->opt.cfl_init; }
-        else if (c->opt.cfl_mode == 0) {           /* Eq.25 */
+        else if (c->opt.cfl_mode == 0 && c->opt.scheme == 0) {   /* Eq.25 */
             double cf = c->cfl * c->res_inf_prev / inf;
             if (!(cf >= c->opt.cfl_min)) cf = c->opt.cfl_min;
             if (cf > c->opt.cfl_max) cf = c->opt.cfl_max;
             c->cfl = cf;
         }
         c->res_inf_prev = inf;
-        lusgs(c);
+        if (c->opt.scheme == 1) {
+            /* Eq.15: W^{n+1} = W^n - (1/Omega) sum F S with the flux integrated
+             * over a local step dt_i = CFL Omega_i / (Lambda_c)_i (the cell form
+             * of Eq.21/23), i.e. dW_i = dt_i M_i / Omega_i = CFL M_i / (Lambda_c)_i;
+             * nu-tilde the same way with the SA right-hand side */
+            for (int i = 0; i < c->nc; i++) {
+                double k = c->cfl / c->lamc[i];
+                for (int q = 0; q < 4; q++) c->dW[5 * i + q] = k * c->M[5 * i + q];
+                c->dW[5 * i + 4] = c->sa ? k * c->M[5 * i + 4] : 0.0;
+            }
+        } else {
+            lusgs(c);
+        }
         /* Eq.17 update; nu-tilde clipped at zero; Eq.40 criterion */
         memcpy(Wold, c->W, sizeof(double) * 5 * c->nc);
         double e40 = 0.0;

@@ -114,6 +114,8 @@ template <typename T> void launch_reduce(const Launch &L, const Params<T> &P, in
 template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, int mode);
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd);
 template <typename T> void launch_commit(const Launch &L, const Params<T> &P, int it);
+// explicit step (Eq.15, local time steps) in place of the sweeps
+template <typename T> void launch_explicit(const Launch &L, const Params<T> &P);
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
                           const int *woff, const double *wseg, double *dwall);
 void launch_gather_faces(const Launch &L, int n, const int *faces, const double *flux, int nf, double *out);

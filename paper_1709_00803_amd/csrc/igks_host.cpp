@@ -474,7 +474,8 @@ void fill_params(igks_ctx *c, Params<T> &P)
     auto In = [&](const Buf &x) { return (int *)(b + x.off); };
     P = Params<T>{};
     P.nc = c->g.N; P.nf = c->g.F; P.ninst = (int)c->inst.size();
-    P.limiter = c->opt.limiter; P.visc_sr = c->opt.visc_sr; P.mu_law = c->opt.mu_law; P.cfl_mode = c->opt.cfl_mode;
+    P.limiter = c->opt.limiter; P.visc_sr = c->opt.visc_sr; P.mu_law = c->opt.mu_law;
+    P.cfl_mode = c->opt.scheme == 1 ? 1 : c->opt.cfl_mode;   // the explicit scheme keeps its CFL
     P.cfl_init = c->opt.cfl_init; P.cfl_min = c->opt.cfl_min; P.cfl_max = c->opt.cfl_max; P.cfl_flux = c->opt.cfl_flux;
     P.cinst = In(w.cinst); P.finst = In(w.finst);
     P.ip = (const InstParam *)(b + w.ip.off);
@@ -518,6 +519,14 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev, int it)
     mark(3);
     launch_reduce(L, P, it);
     mark(4);
+    if (c->opt.scheme == 1) {
+        // explicit scheme: one update kernel in place of the sweeps
+        launch_explicit(L, P);
+        mark(5);
+        launch_commit(L, P, it);
+        mark(6);
+        return;
+    }
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, true);
     else
         // forward over all wavefronts; the last one also takes its backward
@@ -759,6 +768,7 @@ void igks_default_options(igks_options *o)
     o->block = 256;
     o->sweep = 0;
     o->flux_lanes = 0;
+    o->scheme = 0;
 }
 
 int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream, int32_t n_inst)
@@ -774,6 +784,7 @@ int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream,
     if (c->opt.block % 64 != 0 || c->opt.block > 256) { delete c; return IGKS_EINVAL; }
     if (c->opt.sweep < 0 || c->opt.sweep > 2 || c->opt.chunk < 0) { delete c; return IGKS_EINVAL; }
     if (c->opt.flux_lanes < 0 || c->opt.flux_lanes > 2) { delete c; return IGKS_EINVAL; }
+    if (c->opt.scheme < 0 || c->opt.scheme > 1) { delete c; return IGKS_EINVAL; }
     for (int k = 0; k < NCLASS; k++) c->block[k] = c->opt.block;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;

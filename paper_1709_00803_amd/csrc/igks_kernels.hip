@@ -1022,6 +1022,60 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
 // sweep modes
 enum { SW_FWD = 0, SW_BWD = 1, SW_TOP = 2 };
 
+// W^{n+1} = W^n + dW (Eq.17) into the instance's other state buffer, nu~
+// clipped at 0; flags a non-physical result; returns the Eq.40 ratio
+// |dW| / |W| over the four flow variables.
+template <typename T>
+__device__ __forceinline__ double apply_update(const Params<T> &P, int c, int inst, const double *w, const double *d)
+{
+    const int N = P.nc;
+    double *Wn = (P.is[inst].ncommit & 1) ? P.Wa : P.Wb;
+    double wn[4], num = 0.0, den = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        num += d[k] * d[k];
+        den += w[k] * w[k];
+        wn[k] = w[k] + d[k];
+        Wn[k * N + c] = wn[k];
+    }
+    double tt = w[4];
+    if (P.ip[inst].sa) tt = fmax(tt + d[4], 0.0);
+    Wn[4 * N + c] = tt;
+    double p = wn[3] - 0.5 * (wn[1] * wn[1] + wn[2] * wn[2]) / wn[0];
+    if (!(wn[0] > 0.0) || !(p > 0.0) || !isfinite(tt) || !isfinite(p)) atomicOr(&P.is[inst].bad, 1);
+    double r = sqrt(num / den);
+    return isfinite(r) ? r : 0.0;
+}
+
+// Explicit step (Eq.15) with the local time step dt_i = CFL Omega_i /
+// (Lambda_c)_i of Eq.21/23: dW_i = dt_i M_i / Omega_i = CFL M_i / (Lambda_c)_i,
+// the SA variable the same way with its right-hand side.
+template <typename T>
+__global__ __launch_bounds__(256) void k_explicit(Params<T> P)
+{
+    const int N = P.nc;
+    int c = xcd_block() * blockDim.x + threadIdx.x;
+    int inst = -1;
+    double e = 0.0;
+    if (c < N) {
+        inst = cell_inst(P, c);
+        if (P.is[inst].halt) {
+            inst = -1;
+        } else {
+            const double *W = cur_state(P, inst);
+            double w[5], d[5];
+#pragma unroll
+            for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
+            const double kc = P.is[inst].cfl / P.lamc[c];
+#pragma unroll
+            for (int k = 0; k < 4; k++) d[k] = kc * P.M[k * N + c];
+            d[4] = P.ip[inst].sa ? kc * P.M[4 * N + c] : 0.0;
+            e = apply_update(P, c, inst, w, d);
+        }
+    }
+    slot_update<false>(&P.is[0].e40_bits[0], inst, e);
+}
+
 // One wavefront of the LU-SGS sweeps (Eq.22); the cells of a wavefront are
 // mutually independent.  Forward:
 //   dW*_i = D^-1 [M_i - sum_{j<i} (J(W_j, n_ij) dW*_j - lam_ij dW*_j) S_ij / 2];
@@ -1095,24 +1149,10 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     d[4] = ip.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
 #pragma unroll
     for (int k = 0; k < 5; k++) P.dW[k * N + c] = d[k];
-    // update (Eq.17) and the Eq.40 ratio
-    double *Wn = (sc.ncommit & 1) ? P.Wa : P.Wb;
-    double wn[4], num = 0.0, den = 0.0;
+    double dd[5];
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-        double dd = double(d[k]);
-        num += dd * dd;
-        den += w[k] * w[k];
-        wn[k] = w[k] + dd;
-        Wn[k * N + c] = wn[k];
-    }
-    double tt = w[4];
-    if (ip.sa) tt = fmax(tt + double(d[4]), 0.0);
-    Wn[4 * N + c] = tt;
-    double p = wn[3] - 0.5 * (wn[1] * wn[1] + wn[2] * wn[2]) / wn[0];
-    if (!(wn[0] > 0.0) || !(p > 0.0) || !isfinite(tt) || !isfinite(p)) atomicOr(&P.is[inst].bad, 1);
-    double r = sqrt(num / den);
-    return isfinite(r) ? r : 0.0;
+    for (int k = 0; k < 5; k++) dd[k] = double(d[k]);
+    return apply_update(P, c, inst, w, dd);
 }
 
 // One wave per instance (block i): accept (flip the state buffer) or reject
@@ -1229,6 +1269,10 @@ template <typename T> void launch_prep(const Launch &L, const Params<T> &P)
 {
     hipLaunchKernelGGL(k_prep<T>, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), 0, L.s, P);
 }
+template <typename T> void launch_explicit(const Launch &L, const Params<T> &P)
+{
+    hipLaunchKernelGGL(k_explicit<T>, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), 0, L.s, P);
+}
 template <typename T> void launch_commit(const Launch &L, const Params<T> &P, int it)
 {
     hipLaunchKernelGGL(k_commit<T>, dim3(P.ninst), dim3(64), 0, L.s, P, it);
@@ -1293,6 +1337,7 @@ void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, cons
     template void launch_reduce<T>(const Launch &, const Params<T> &, int);                        \
     template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, int);               \
     template void launch_commit<T>(const Launch &, const Params<T> &, int);                        \
+    template void launch_explicit<T>(const Launch &, const Params<T> &);                           \
     template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool);
 INST(double)
 INST(float)

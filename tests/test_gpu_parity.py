@@ -49,7 +49,8 @@ def smooth_state(W, xc, yc, amp, seed):
 
 def pair(igks, mesh, flow, **opt):
     o = po.Oracle(mesh, **{k: v for k, v in opt.items() if k in ("limiter", "cfl_init", "cfl_mode", "cfl_flux",
-                                                                   "visc_sr", "mu_law", "cfl_min", "cfl_max")})
+                                                                   "visc_sr", "mu_law", "cfl_min", "cfl_max",
+                                                                   "scheme")})
     o.set_freestream(*flow)
     g = igks.Solver(mesh, **opt)
     g.set_freestream(*flow)
@@ -120,6 +121,29 @@ def test_trajectory_parity(igks, sa, limiter):
         assert abs(rg["cfl"] - ro["cfl"]) <= 1e-8 * ro["cfl"]
         assert abs(rg["res_l2"] - ro["res_l2"]) <= 1e-8 * ro["res_l2"]
         assert abs(rg["dt_flux"] - ro["dt_flux"]) <= 1e-12 * ro["dt_flux"]
+
+
+@pytest.mark.parametrize("sa", [False, True])
+def test_explicit_trajectory_parity(igks, sa):
+    """The explicit scheme (Eq.15, local time steps): GPU and oracle
+    iterates stay together."""
+    m = mg.colour_order(mg.random_hybrid(12, 8, seed=23, tags=TAGS_SYM))[0]
+    flow = (0.35, 2.0, 2e4 if sa else 2e3, 3.0 if sa else -1.0)
+    tag = f"explicit sa={sa}"
+    say("case", tag)
+    o, g = pair(igks, m, flow, scheme=1, cfl_init=0.6, chunk=5)
+    for step in range(4):
+        o.iterate(5)
+        g.iterate(5)
+        Wo, Wg = o.get_state(), g.get_state()
+        rows = 5 if sa else 4
+        scale = np.abs(Wo[:rows]).max(axis=1, keepdims=True)
+        err = (np.abs(Wg[:rows] - Wo[:rows]) / scale).max()
+        ro, rg = o.residual(), g.residual()
+        say(f"[{tag}] it={5 * (step + 1)} state err={err:.3e} res o={ro['res_l2']:.6e} g={rg['res_l2']:.6e}")
+        assert err <= 1e-9
+        assert rg["cfl"] == 0.6 and ro["cfl"] == 0.6
+        assert abs(rg["res_l2"] - ro["res_l2"]) <= 1e-8 * ro["res_l2"]
 
 
 def test_plate_residual_and_wall_loads(igks):

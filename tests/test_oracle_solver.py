@@ -262,6 +262,40 @@ def test_explicit_limit():
     assert np.allclose(dW[:4], want, rtol=1e-7, atol=1e-9 * np.abs(want).max())
 
 
+@pytest.mark.parametrize("sa", [False, True])
+def test_explicit_scheme_is_the_small_cfl_limit(sa):
+    """Eq.15 with local steps (scheme 1) is the CFL -> 0 limit of the LU-SGS
+    iteration: one step of each from the same state at CFL 1e-8 gives the
+    same increment to O(CFL), the SA variable included."""
+    m = mg.random_hybrid(7, 5, seed=21, tags=dict(bottom=mg.WALL, top=mg.OUTFLOW))
+    flow = (0.3, 3.0, 2e4, 3.0 if sa else -1.0)
+    cfl = 1e-8
+    steps = []
+    for scheme in (0, 1):
+        o = po.Oracle(m, cfl_init=cfl, cfl_mode=1, scheme=scheme)
+        o.set_freestream(*flow)
+        W0 = smooth_state(o, 0.05, 8)
+        if sa:
+            W0[4] *= 1.0 + 0.3 * np.cos(3.0 * o.cells()["xc"])
+        o.set_state(W0)
+        o.iterate(1)
+        steps.append(o.get_state() - W0)
+    imp, exp = steps
+    rows = 5 if sa else 4
+    scale = np.abs(exp[:rows]).max(axis=1, keepdims=True)
+    assert np.all(scale > 0)
+    assert np.abs(imp[:rows] - exp[:rows]).max() <= 1e-6 * scale.max()
+
+
+def test_explicit_scheme_keeps_free_stream():
+    m = mg.random_hybrid(6, 5, seed=22)
+    o = po.Oracle(m, cfl_init=0.8, scheme=1)
+    o.set_freestream(0.4, 17.0, 1e4)
+    W0 = o.get_state()
+    o.iterate(3)
+    assert np.abs(o.get_state() - W0).max() <= 1e-13
+
+
 def test_plate_wall_distance():
     """Flat plate from x = 0: d = y downstream of the leading edge and
     sqrt(x^2 + y^2) upstream (closed form)."""
