@@ -620,8 +620,8 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
     c->dwall = malloc(sizeof(double) * n_cells);
     for (int i = 0; i < n_cells; i++) {
         double best = 1e300;
-        for (int q = 0; q < nf; q++) {
-            if (c->ftag[q] != BC_WALL) continue;
+        for (int w = 0; w < c->nwall; w++) {
+            int q = c->wall_faces[w];
             double hx = 0.5 * c->flen[q] * (-c->fny[q]), hy = 0.5 * c->flen[q] * c->fnx[q];
             double dd = seg_dist(c->xc[i], c->yc[i], c->fxm[q] - hx, c->fym[q] - hy, c->fxm[q] + hx, c->fym[q] + hy);
             if (dd < best) best = dd;

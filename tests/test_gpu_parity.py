@@ -172,6 +172,30 @@ def test_joukowski_full_size_residual(igks):
     check_residual(o, g, smooth_state(o.get_state(), c["xc"], c["yc"], 0.03, 7), "jouk40k perturbed")
 
 
+def test_joukowski_sa_250k_full_size(igks):
+    """The 250k-cell SA Joukowski mesh at full size, in the launch
+    configuration the benchmark picks for it (two lanes per face): every
+    cell's residual, then three iterations from the impulsive start."""
+    m = mg.workload("jouk250k")
+    flow = (0.15, 4.0, 6e6, 3.0)
+    say("case jouk250k", m.n_cells, "cells")
+    o, g = pair(igks, m, flow)
+    assert g.schedule()[5] == 2
+    c = o.cells()
+    check_residual(o, g, smooth_state(o.get_state(), c["xc"], c["yc"], 0.02, 17), "jouk250k perturbed")
+    o.set_freestream(*flow)
+    g.set_freestream(*flow)
+    o.iterate(3)
+    g.iterate(3)
+    Wo, Wg = o.get_state(), g.get_state()
+    scale = np.abs(Wo).max(axis=1, keepdims=True)
+    err = (np.abs(Wg - Wo) / scale).max()
+    lo, lg = o.wall_loads(), g.wall_loads()
+    say(f"[jouk250k] 3 iterations: state err {err:.3e}, cl {lg['cl']:.12e} vs {lo['cl']:.12e}")
+    assert err <= 1e-9
+    assert abs(lg["cl"] - lo["cl"]) <= 1e-9 * abs(lo["cl"]) + 1e-12
+
+
 def test_set_state_rejects_nonphysical(igks):
     m = mg.random_hybrid(4, 3, seed=1)
     g = igks.Solver(m)
