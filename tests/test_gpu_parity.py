@@ -4,7 +4,9 @@ on the same seeded inputs.
 Tolerances (floating point): the residual M of Eq.16 is a sum of face
 fluxes that nearly cancel, so it is compared per cell and component
 against 1e-12 times that cell's gross flux sum_faces |F S| (the
-arithmetic error of both sides is a few ulp of the gross flux); the SA
+arithmetic error of both sides is a few ulp of the gross flux), widened
+by AR/200 in cells whose aspect ratio AR exceeds 200 (see
+check_residual); the SA
 right-hand side against 1e-10 of its largest magnitude (source and
 diffusion terms cancel in it as well); states after a few iterations
 against 1e-9 relative; converged lift/drag against 1e-9 relative.
@@ -57,14 +59,33 @@ def pair(igks, mesh, flow, **opt):
     return o, g
 
 
+def aspect_ratio(o):
+    """Longest over shortest face of each cell."""
+    f = o.faces()
+    n = o.n
+    lo, hi = np.full(n, np.inf), np.zeros(n)
+    for side in ("fl", "fr"):
+        cells = f[side]
+        ok = cells >= 0
+        np.minimum.at(lo, cells[ok], f["len"][ok])
+        np.maximum.at(hi, cells[ok], f["len"][ok])
+    return hi / lo
+
+
 def check_residual(o, g, W, tag):
+    """Per cell and component: |M_gpu - M_oracle| <= tol * sum_faces |F S|
+    with tol = 1e-12 max(1, AR / 200).  Both codes form wall-normal
+    differences (W0 - W_c)/d that lose about log10(AR) digits in cells of
+    aspect ratio AR (the first layers of a 2e-6-chord wall mesh, AR ~ 2400,
+    differ by up to 7e-12); on the 40k mesh (AR < 200) the bar is 1e-12."""
     o.set_state(W)
     g.set_state(W)
     Mo, G = o.compute_residual()
     Mg = g.compute_residual()
+    tol = 1e-12 * np.maximum(1.0, aspect_ratio(o) / 200.0)
     err = np.abs(Mg[:4] - Mo[:4]) / G
-    say(f"[{tag}] flow residual max |dM|/gross = {err.max():.3e}")
-    assert err.max() <= 1e-12, tag
+    say(f"[{tag}] flow residual max |dM|/gross = {err.max():.3e}, max over tolerance {(err / tol).max():.3f}")
+    assert np.all(err <= tol), tag
     sa_scale = np.abs(Mo[4]).max()
     if sa_scale > 0:
         e4 = np.abs(Mg[4] - Mo[4]).max() / sa_scale
