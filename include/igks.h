@@ -59,6 +59,7 @@ extern "C" {
 #define IGKS_BC_WALL 3       /* no-slip: momentum and nu-tilde negated */
 #define IGKS_BC_OUTFLOW 4    /* Riemann-invariant outflow, ghost increment 0 */
 #define IGKS_BC_FARFIELD 5   /* FREESTREAM where V_inf . n < 0, else OUTFLOW */
+#define IGKS_BC_MOVING_WALL 6 /* no-slip wall moving with the tangential part of V_inf (a lid) */
 
 /* precision of the implicit sweeps */
 #define IGKS_FP64 0  /* everything in FP64 */

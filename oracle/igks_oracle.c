@@ -28,7 +28,7 @@
 #define KDOF 3
 static const double GAMMA = (KDOF + 4.0) / (KDOF + 2.0);
 
-enum { BC_FREESTREAM = 1, BC_SYMMETRY = 2, BC_WALL = 3, BC_OUTFLOW = 4, BC_FARFIELD = 5 };
+enum { BC_FREESTREAM = 1, BC_SYMMETRY = 2, BC_WALL = 3, BC_OUTFLOW = 4, BC_FARFIELD = 5, BC_MOVING_WALL = 6 };
 
 /* Spalart-Allmaras constants (standard SA, "noft2" variant).  The paper
  * defers the model's constants to its Ref. (Moro et al.); reading: the
@@ -586,7 +586,7 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
             bkey *hit = bsearch(&q, BK, n_bfaces, sizeof(bkey), cmp_bkey);
             if (!hit) { free(E); free(BK); free(bused); seterr(c, "unmatched boundary edge"); return -2; }
             int tag = bface_tag[hit->idx];
-            if (tag < 1 || tag > 5) { free(E); free(BK); free(bused); seterr(c, "bad boundary tag"); return -2; }
+            if (tag < 1 || tag > 6) { free(E); free(BK); free(bused); seterr(c, "bad boundary tag"); return -2; }
             c->ftag[f] = tag; bused[hit - BK] = 1; c->fbidx[f] = hit->idx;
             if (tag == BC_WALL) nwall++;
         }
@@ -656,6 +656,20 @@ static void ghost_state(const oigks_ctx *c, int bc, const double *Wi, double nx,
         Wg[0] = r; Wg[1] = -mx; Wg[2] = -my; Wg[3] = Wi[3]; Wg[4] = -Wi[4];
         return;
     }
+    if (bc == BC_MOVING_WALL) {
+        /* reading: a no-slip wall moving with the tangential part V_w of the
+         * free-stream velocity.  The ghost keeps the interior density and
+         * temperature and takes the velocity 2 V_w - V_i, so that the face
+         * average is V_w; V_w = 0 gives the rule above. */
+        double tx = -ny, ty = nx, vt = (c->Winf[1] * tx + c->Winf[2] * ty) / c->Winf[0];
+        double vwx = vt * tx, vwy = vt * ty;
+        Wg[0] = r;
+        Wg[1] = 2.0 * vwx * r - mx;
+        Wg[2] = 2.0 * vwy * r - my;
+        Wg[3] = Wi[3] + 2.0 * r * (vwx * vwx + vwy * vwy) - 2.0 * (vwx * mx + vwy * my);
+        Wg[4] = -Wi[4];
+        return;
+    }
     /* BC_OUTFLOW: Riemann invariants R+ (inside) and R- (free stream) along
      * the outward normal; U_b = (R+ + R-)/2, rho_b = rho_i, (rho E)_b from
      * U_b, the inside tangential velocity and lam_i; nu-tilde copied.
@@ -678,8 +692,18 @@ static void ghost_state(const oigks_ctx *c, int bc, const double *Wi, double nx,
     Wg[4] = Wi[4];
 }
 /* increments of the ghost values for the implicit sweep (Sec. 2.5) */
-static void ghost_incr(int bc, const double *dWi, double nx, double ny, double *dWg)
+static void ghost_incr(const oigks_ctx *c, int bc, const double *dWi, double nx, double ny, double *dWg)
 {
+    if (bc == BC_MOVING_WALL) {         /* the linear map of the moving-wall ghost state */
+        double tx = -ny, ty = nx, vt = (c->Winf[1] * tx + c->Winf[2] * ty) / c->Winf[0];
+        double vwx = vt * tx, vwy = vt * ty;
+        dWg[0] = dWi[0];
+        dWg[1] = 2.0 * vwx * dWi[0] - dWi[1];
+        dWg[2] = 2.0 * vwy * dWi[0] - dWi[2];
+        dWg[3] = dWi[3] + 2.0 * (vwx * vwx + vwy * vwy) * dWi[0] - 2.0 * (vwx * dWi[1] + vwy * dWi[2]);
+        dWg[4] = -dWi[4];
+        return;
+    }
     if (bc == BC_SYMMETRY) {
         double mn = dWi[1] * nx + dWi[2] * ny;
         dWg[0] = dWi[0]; dWg[1] = dWi[1] - 2.0 * mn * nx; dWg[2] = dWi[2] - 2.0 * mn * ny;
@@ -879,6 +903,30 @@ static int residual(oigks_ctx *c)
             double Bk[4] = {1.0, -1.0, bm_t, 1.0};
             for (int k = 0; k < 4; k++) { grn[k] = sn * Bk[k] * gln[k]; grt[k] = st * Bk[k] * glt[k]; }
         }
+        /* a moving wall (reading): the face is evaluated in the frame of
+         * the wall, where it is a static no-slip wall, and the flux is
+         * transformed back.  The interior face-frame state and slopes are
+         * boosted by -u_w along the face, (rho, m_n, m_t, E) ->
+         * (rho, m_n, m_t - u_w rho, E - u_w m_t + u_w^2 rho / 2), and the
+         * ghost side is their point reflection as for a static wall. */
+        double uw = 0.0;
+        const int moving = j < 0 && c->fbc[f] == BC_MOVING_WALL;
+        if (moving) {
+            uw = (c->Winf[1] * tx + c->Winf[2] * ty) / c->Winf[0];
+            double *bs[4] = {wl, wlc, gln, glt};
+            for (int h = 0; h < 4; h++) {
+                double *v = bs[h];
+                v[3] = v[3] - uw * v[2] + 0.5 * uw * uw * v[0];
+                v[2] = v[2] - uw * v[0];
+            }
+            const double Bk[4] = {1.0, -1.0, -1.0, 1.0};
+            for (int k = 0; k < 4; k++) {
+                wr[k] = Bk[k] * wl[k];
+                wrc[k] = Bk[k] * wlc[k];
+                grn[k] = -Bk[k] * gln[k];
+                grt[k] = -Bk[k] * glt[k];
+            }
+        }
         /* tau from the interface equilibrium (Eq.34); the core needs W0
          * first, which it computes the same way */
         double sl[4], sr[4];
@@ -896,6 +944,10 @@ static int residual(oigks_ctx *c)
         double tau = collision_time(c, W0[0], lam_of(W0), nutf);
         face_detail fd;
         gks_core(wl, gln, glt, wr, grn, grt, wlc, wrc, dl, dr, c->dt_flux, tau, &fd);
+        if (moving) {   /* back to the frame of the mesh */
+            fd.F[3] += uw * fd.F[2] + 0.5 * uw * uw * fd.F[0];
+            fd.F[2] += uw * fd.F[0];
+        }
         double Fn = fd.F[1] / c->dt_flux, Ft = fd.F[2] / c->dt_flux;
         double Fb[4] = {fd.F[0] / c->dt_flux, Fn * nx + Ft * tx, Fn * ny + Ft * ty, fd.F[3] / c->dt_flux};
         for (int k = 0; k < 4; k++) {
@@ -1044,7 +1096,7 @@ static void lusgs(oigks_ctx *c)
             const double *Wj, *dj;
             double dg5[5];
             if (c->fR[f] < 0) {
-                ghost_incr(c->fbc[f], dWs, nx, ny, dg5);
+                ghost_incr(c, c->fbc[f], dWs, nx, ny, dg5);
                 Wj = &c->Wg[5 * f]; dj = dg5;
             } else {
                 int j = c->fL[f] == i ? c->fR[f] : c->fL[f];

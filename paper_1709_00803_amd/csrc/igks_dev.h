@@ -16,7 +16,7 @@ namespace igks {
 constexpr int KDOF = 3;
 constexpr double GAMMA = (KDOF + 4.0) / (KDOF + 2.0);
 
-enum { BC_FREESTREAM = 1, BC_SYMMETRY = 2, BC_WALL = 3, BC_OUTFLOW = 4, BC_FARFIELD = 5 };
+enum { BC_FREESTREAM = 1, BC_SYMMETRY = 2, BC_WALL = 3, BC_OUTFLOW = 4, BC_FARFIELD = 5, BC_MOVING_WALL = 6 };
 
 // cell -> face entry flags
 constexpr int CF_OWNER = 1;   // the cell is the face's owner (normal points outward)

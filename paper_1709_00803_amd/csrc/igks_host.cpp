@@ -191,7 +191,7 @@ int build_instance(igks_ctx *ctx, int n_nodes, const double *xy, int n_cells, co
         long long a = bface_nodes[2 * b], d = bface_nodes[2 * b + 1];
         if (a < 0 || a >= n_nodes || d < 0 || d >= n_nodes) return fail(ctx, IGKS_EMESH, "boundary node out of range");
         int t = bface_tag[b];
-        if (t < 1 || t > 5) return fail(ctx, IGKS_EMESH, "bad boundary tag");
+        if (t < 1 || t > 6) return fail(ctx, IGKS_EMESH, "bad boundary tag");
         if (!bmap.emplace(std::min(a, d) * (long long)(n_nodes + 1) + std::max(a, d), b).second)
             return fail(ctx, IGKS_EMESH, "duplicate boundary edge");
     }

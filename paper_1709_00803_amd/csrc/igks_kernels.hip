@@ -75,6 +75,13 @@ __device__ __forceinline__ void sa_source(double nut, double nu, double d, doubl
 
 // Ghost cell-centre state across a boundary face with outward unit normal n
 // (Sec. 2.5).
+// speed of a moving wall along the face tangent t = (-n_y, n_x): the
+// free-stream velocity's tangential component
+__device__ __forceinline__ double wall_speed(const InstParam &ip, double nx, double ny)
+{
+    return (ip.Winf[1] * -ny + ip.Winf[2] * nx) / ip.Winf[0];
+}
+
 __device__ __forceinline__ void ghost(const InstParam &ip, int bc, const double *w, double nx, double ny, double *g)
 {
     if (bc == BC_FREESTREAM) {
@@ -90,6 +97,17 @@ __device__ __forceinline__ void ghost(const InstParam &ip, int bc, const double 
     }
     if (bc == BC_WALL) {
         g[0] = r; g[1] = -mx; g[2] = -my; g[3] = w[3]; g[4] = -w[4];
+        return;
+    }
+    if (bc == BC_MOVING_WALL) {
+        // no-slip wall moving with the tangential part V_w of the free-stream
+        // velocity: interior density and temperature, velocity 2 V_w - V
+        double vt = wall_speed(ip, nx, ny), vwx = -vt * ny, vwy = vt * nx;
+        g[0] = r;
+        g[1] = 2.0 * vwx * r - mx;
+        g[2] = 2.0 * vwy * r - my;
+        g[3] = w[3] + 2.0 * r * (vwx * vwx + vwy * vwy) - 2.0 * (vwx * mx + vwy * my);
+        g[4] = -w[4];
         return;
     }
     // Riemann-invariant outflow: U_b from R+ (inside) and R- (free stream),
@@ -110,8 +128,17 @@ __device__ __forceinline__ void ghost(const InstParam &ip, int bc, const double 
 
 // ghost increments (Sec. 2.5)
 template <typename V>
-__device__ __forceinline__ void ghost_incr(int bc, const V *d, V nx, V ny, V *g)
+__device__ __forceinline__ void ghost_incr(int bc, const V *d, V nx, V ny, V vw, V *g)
 {
+    if (bc == BC_MOVING_WALL) {   // the linear map of the moving-wall ghost; vw = wall speed along t
+        V vwx = -vw * ny, vwy = vw * nx;
+        g[0] = d[0];
+        g[1] = V(2) * vwx * d[0] - d[1];
+        g[2] = V(2) * vwy * d[0] - d[2];
+        g[3] = d[3] + V(2) * (vwx * vwx + vwy * vwy) * d[0] - V(2) * (vwx * d[1] + vwy * d[2]);
+        g[4] = -d[4];
+        return;
+    }
     if (bc == BC_SYMMETRY) {
         V mn = d[1] * nx + d[2] * ny;
         g[0] = d[0]; g[1] = d[1] - V(2) * mn * nx; g[2] = d[2] - V(2) * mn * ny; g[3] = d[3]; g[4] = d[4];
@@ -644,7 +671,12 @@ __device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &i
     }
     o.d = side ? P.fdr[f] : P.fdl[f];   // fdr = fdl on a boundary face
     const bool ghost_side = bnd && side == 1;
-    const int bc = ghost_side ? P.fbc[f] : 0;
+    const int bc = bnd ? P.fbc[f] : 0;
+    // a moving wall is evaluated in its own frame from the owner's data
+    const bool moving = bc == BC_MOVING_WALL;
+    double WMo[4], wmo[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) { WMo[k] = WM[k]; wmo[k] = wm[k]; }
     if (ghost_side) {
         // boundary map of the reconstructed interior face state; the
         // cell-centre ghost value from the interior cell centre
@@ -673,8 +705,8 @@ __device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &i
         dst[2] = src[1] * tx + src[2] * ty;
         dst[3] = src[3];
     };
-    rot(WM, o.fw);
-    rot(wm, o.fwc);
+    rot(moving ? WMo : WM, o.fw);
+    rot(moving ? wmo : wm, o.fwc);
     {
         double tn[4], tt[4];
 #pragma unroll
@@ -682,7 +714,26 @@ __device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &i
         rot(tn, o.gn);
         rot(tt, o.gt);
     }
-    if (ghost_side) {
+    if (moving) {
+        // the owner's face-frame state and slopes boosted by -u_w along the
+        // face, (rho, m_n, m_t, E) -> (rho, m_n, m_t - u_w rho,
+        // E - u_w m_t + u_w^2 rho / 2); the ghost side is then their point
+        // reflection through a static no-slip wall
+        const double uw = wall_speed(ip, nx, ny);
+        double *bs[4] = {o.fw, o.fwc, o.gn, o.gt};
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+            double *v = bs[h];
+            v[3] = v[3] - uw * v[2] + 0.5 * uw * uw * v[0];
+            v[2] = v[2] - uw * v[0];
+        }
+        if (ghost_side) {
+            o.fw[1] = -o.fw[1]; o.fw[2] = -o.fw[2];
+            o.fwc[1] = -o.fwc[1]; o.fwc[2] = -o.fwc[2];
+            o.gn[0] = -o.gn[0]; o.gn[3] = -o.gn[3];
+            o.gt[0] = -o.gt[0]; o.gt[3] = -o.gt[3];
+        }
+    } else if (ghost_side) {
         // ghost cell of a symmetry face = mirror image of the interior cell,
         // of a no-slip wall = its point reflection through the face
         // (bounce-back), slopes included: the normal derivative flips, the
@@ -721,6 +772,16 @@ __device__ __forceinline__ void face_implicit_terms(const Params<T> &P, const In
         P.sag[f] = g * S;
         P.sak[f] = kf * S / rn;
     }
+}
+
+// flux of a moving-wall face from the wall's frame back to the mesh frame
+template <typename T>
+__device__ __forceinline__ void unboost_flux(const Params<T> &P, const InstParam &ip, int f, double *Fr)
+{
+    if (P.fr[f] >= 0 || P.fbc[f] != BC_MOVING_WALL) return;
+    const double uw = wall_speed(ip, P.fnx[f], P.fny[f]);
+    Fr[3] += uw * Fr[2] + 0.5 * uw * uw * Fr[0];
+    Fr[2] += uw * Fr[0];
 }
 
 // face-frame flux integrated over [0, dt] -> F S / dt in the global frame
@@ -764,6 +825,7 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, d
     }
     double Fr[4], g[4];
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
+    unboost_flux(P, ip, f, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
 #pragma unroll
     for (int k = 0; k < 4; k++) P.flux[k * F + f] = g[k];
@@ -805,6 +867,7 @@ __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int si
     }
     double Fr[4], g[4];
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
+    unboost_flux(P, ip, f, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
     // each lane writes two of the four components
     P.flux[(2 * side) * F + f] = side ? g[2] : g[0];
@@ -1003,7 +1066,7 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
         for (int k = 0; k < 5; k++) { wj[k] = W[k * N + j]; dj[k] = P.dW[k * N + j]; }
     } else {
         ghost(ip, P.fbc[f], w, nx, ny, wj);
-        ghost_incr<T>(P.fbc[f], dws, T(nx), T(ny), dj);
+        ghost_incr<T>(P.fbc[f], dws, T(nx), T(ny), T(wall_speed(ip, nx, ny)), dj);
     }
     T wjt[4] = {T(wj[0]), T(wj[1]), T(wj[2]), T(wj[3])};
     T jv[4];

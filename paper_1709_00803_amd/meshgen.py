@@ -21,7 +21,8 @@ Meshes produced here:
   Gauss-Seidel sweeps run in cell-index order, so this numbering decides how
   many independent wavefronts a sweep has.
 
-Boundary tags: FREESTREAM=1, SYMMETRY=2, WALL=3, OUTFLOW=4, FARFIELD=5.
+Boundary tags: FREESTREAM=1, SYMMETRY=2, WALL=3, OUTFLOW=4, FARFIELD=5,
+MOVING_WALL=6.
 """
 from __future__ import annotations
 
@@ -30,7 +31,7 @@ import math
 
 import numpy as np
 
-FREESTREAM, SYMMETRY, WALL, OUTFLOW, FARFIELD = 1, 2, 3, 4, 5
+FREESTREAM, SYMMETRY, WALL, OUTFLOW, FARFIELD, MOVING_WALL = 1, 2, 3, 4, 5, 6
 
 
 @dataclasses.dataclass
@@ -148,6 +149,28 @@ def flat_plate(nx: int = 64, ny: int = 32, x0: float = -0.2, x1: float = 1.0,
     bn.append(np.stack([nid(nx, j), nid(nx, j + 1)], 1)); bt.append(np.full(ny, OUTFLOW))
     meta = dict(kind="flat_plate", nx=nx, ny=ny, x0=x0, x1=x1, dy1=dy1, ratio=ratio, chord=1.0)
     return _mk_uniform(xy, cells, np.concatenate(bn), np.concatenate(bt), meta)
+
+
+def cavity(n: int = 100) -> Mesh:
+    """Lid-driven cavity: n x n uniform quadrilaterals on the unit square,
+    cells numbered row by row from the bottom; the top edge MOVING_WALL, the
+    other three WALL."""
+    xs = np.arange(n + 1) / n
+    X, Y = np.meshgrid(xs, xs, indexing="xy")
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+
+    def nid(i, j):
+        return j * (n + 1) + i
+
+    I, J = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    I = I.ravel(); J = J.ravel()
+    cells = np.stack([nid(I, J), nid(I + 1, J), nid(I + 1, J + 1), nid(I, J + 1)], axis=1)
+    k = np.arange(n)
+    bn = np.concatenate([np.stack([nid(k, 0), nid(k + 1, 0)], 1), np.stack([nid(k, n), nid(k + 1, n)], 1),
+                         np.stack([nid(0, k), nid(0, k + 1)], 1), np.stack([nid(n, k), nid(n, k + 1)], 1)])
+    bt = np.concatenate([np.full(n, WALL), np.full(n, MOVING_WALL), np.full(n, WALL), np.full(n, WALL)])
+    meta = dict(kind="cavity", n=n, chord=1.0)
+    return _mk_uniform(xy, cells, bn, bt, meta)
 
 
 # ---------------------------------------------------------------------------

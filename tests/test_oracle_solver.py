@@ -120,6 +120,39 @@ def test_closed_box_conserves_mass_and_energy(bc, limiter):
         assert abs(M[k].sum()) <= 1e-13 * G[k].sum(), (k, M[k].sum(), G[k].sum())
 
 
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_lid_driven_box_conserves_mass(limiter):
+    """A box of no-slip walls with a moving lid lets no mass through (the
+    moving-wall ghost keeps the interior density and mirrors the normal
+    momentum), whatever the state."""
+    tags = dict(bottom=mg.WALL, top=mg.MOVING_WALL, left=mg.WALL, right=mg.WALL)
+    m = mg.random_hybrid(8, 7, seed=15, tags=tags, jitter=0.3)
+    o = po.Oracle(m, limiter=limiter)
+    o.set_freestream(0.3, 0.0, 500.0)
+    o.set_state(smooth_state(o, 0.1, 10))
+    M, G = o.compute_residual()
+    assert abs(M[0].sum()) <= 1e-13 * G[0].sum()
+
+
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_walls_moving_with_the_stream_keep_it(limiter):
+    """A channel whose two walls move with the free stream (their velocity is
+    its tangential part) carries the uniform stream unchanged: in the frame
+    of either wall the fluid is at rest, so the walls exert no shear.  The
+    same channel with static walls does not keep it."""
+    tags = dict(bottom=mg.MOVING_WALL, top=mg.MOVING_WALL, left=mg.FREESTREAM, right=mg.OUTFLOW)
+    m = mg.random_hybrid(9, 6, seed=16, tags=tags, jitter=0.3)
+    o = po.Oracle(m, limiter=limiter)
+    o.set_freestream(0.3, 0.0, 500.0)
+    M, G = o.compute_residual()
+    assert (np.abs(M[:4]) / G).max() <= 1e-13
+    tags.update(bottom=mg.WALL, top=mg.WALL)
+    o = po.Oracle(mg.random_hybrid(9, 6, seed=16, tags=tags, jitter=0.3), limiter=limiter)
+    o.set_freestream(0.3, 0.0, 500.0)
+    M, G = o.compute_residual()
+    assert (np.abs(M[:4]) / G).max() > 1e-4
+
+
 def _rotate_state(W, th, mirror=False):
     W = W.copy()
     if mirror:
@@ -178,11 +211,13 @@ def _jac_fd(W, nx, ny):
     return J
 
 
-def test_lusgs_solves_factored_system():
+@pytest.mark.parametrize("top", [mg.OUTFLOW, mg.MOVING_WALL])
+def test_lusgs_solves_factored_system(top):
     """The sweeps solve (L + D) D^-1 (D + U) dW = M with the Euler-flux
     Jacobians of Eq.20 (built here by finite differences) and the lagged
-    ghost increments of Sec. 2.5 in the backward sweep."""
-    tags = dict(bottom=mg.WALL, top=mg.OUTFLOW, left=mg.FREESTREAM, right=mg.SYMMETRY)
+    ghost increments of Sec. 2.5 in the backward sweep (for the moving wall:
+    the Jacobian of its affine ghost map)."""
+    tags = dict(bottom=mg.WALL, top=top, left=mg.FREESTREAM, right=mg.SYMMETRY)
     m = mg.random_hybrid(5, 4, seed=7, tags=tags)
     m, _, _ = mg.colour_order(m)
     o = po.Oracle(m)
@@ -216,6 +251,12 @@ def test_lusgs_solves_factored_system():
             bc = f["bc"][k]
             if bc == mg.WALL:
                 B = np.diag([1.0, -1.0, -1.0, 1.0])
+            elif bc == mg.MOVING_WALL:
+                a = math.radians(5.0)
+                vt = -math.cos(a) * ny + math.sin(a) * nx
+                vw = vt * np.array([-ny, nx])
+                B = np.array([[1.0, 0, 0, 0], [2 * vw[0], -1, 0, 0], [2 * vw[1], 0, -1, 0],
+                              [2 * vw @ vw, -2 * vw[0], -2 * vw[1], 1]])
             elif bc == mg.SYMMETRY:
                 nn = np.array([nx, ny]); B = np.eye(4); B[1:3, 1:3] = np.eye(2) - 2 * np.outer(nn, nn)
             else:
@@ -327,6 +368,18 @@ def test_ghost_states():
     # no-slip wall: momentum and nu-tilde negated
     g = o.ghost_state(mg.WALL, Wi, nx, ny)
     assert np.array_equal(g, [Wi[0], -Wi[1], -Wi[2], Wi[3], -Wi[4]])
+    # moving wall: face-average velocity = the free stream's tangential part,
+    # interior density and temperature, nu-tilde negated
+    g = o.ghost_state(mg.MOVING_WALL, Wi, nx, ny)
+    t = np.array([-ny, nx])
+    vw = (math.cos(a) * t[0] + math.sin(a) * t[1]) * t
+    assert np.allclose(0.5 * (Wi[1:3] / Wi[0] + g[1:3] / g[0]), vw, rtol=0, atol=1e-15)
+    lam_i = (K + 2) * Wi[0] / (4 * (Wi[3] - 0.5 * (Wi[1] ** 2 + Wi[2] ** 2) / Wi[0]))
+    lam_g = (K + 2) * g[0] / (4 * (g[3] - 0.5 * (g[1] ** 2 + g[2] ** 2) / g[0]))
+    assert g[0] == Wi[0] and g[4] == -Wi[4] and lam_g == pytest.approx(lam_i, rel=1e-13)
+    # ... and a wall whose normal is along the free stream does not move
+    assert np.allclose(o.ghost_state(mg.MOVING_WALL, Wi, math.cos(a), math.sin(a)),
+                       o.ghost_state(mg.WALL, Wi, math.cos(a), math.sin(a)), rtol=0, atol=1e-15)
     # Riemann outflow: R+ from inside, R- from the free stream, rho and lam from inside
     g = o.ghost_state(mg.OUTFLOW, Wi, nx, ny)
     r, U, V = Wi[0], Wi[1] / Wi[0], Wi[2] / Wi[0]
