@@ -84,6 +84,11 @@ typedef struct igks_options {
     int scheme;         /* 0: implicit LU-SGS (Eq.18-22); 1: explicit Eq.15 with local time
                            steps dt_i = CFL Omega_i / (Lambda_c)_i, CFL = cfl_init fixed
                            (the paper's explicit GKS baseline) */
+    double wall_temp;   /* 0: adiabatic no-slip walls (the Sec. 2.5 ghost rule); > 0: WALL and
+                           MOVING_WALL faces held at wall_temp x the free-stream temperature:
+                           the same ghost plus the Navier-Stokes heat flux of the BGK model,
+                           mu c_p (T_c - T_w) / d (Pr = 1, mu at the cell-centre temperature,
+                           d the centroid-face distance), treated explicitly */
 } igks_options;
 
 typedef struct igks_residual {

@@ -50,6 +50,8 @@ typedef struct {
     int visc_sr;        /* viscous term in the LU-SGS spectral radius */
     int mu_law;         /* 0: Sutherland, 1: constant */
     int scheme;         /* 0: implicit LU-SGS (Eq.18-22); 1: explicit Eq.15 with local time steps */
+    double wall_temp;   /* 0: adiabatic no-slip walls (Sec. 2.5); > 0: isothermal walls at this
+                           multiple of the free-stream temperature */
 } oigks_options;
 
 typedef struct {
@@ -472,7 +474,7 @@ static void free_mesh(oigks_ctx *c)
 EXPORT void oigks_default_options(oigks_options *o)
 {
     o->limiter = 0; o->cfl_init = 1000.0; o->cfl_min = 1.0; o->cfl_max = 1e6; o->cfl_mode = 0; o->scheme = 0;
-    o->cfl_flux = 1.0; o->visc_sr = 1; o->mu_law = 0;
+    o->cfl_flux = 1.0; o->visc_sr = 1; o->mu_law = 0; o->wall_temp = 0.0;
 }
 
 EXPORT int oigks_create(oigks_ctx **out, const oigks_options *opt)
@@ -481,6 +483,7 @@ EXPORT int oigks_create(oigks_ctx **out, const oigks_options *opt)
     if (!c) return -3;
     if (opt) c->opt = *opt; else oigks_default_options(&c->opt);
     *out = c;
+    if (!(c->opt.wall_temp >= 0.0) || !isfinite(c->opt.wall_temp)) { seterr(c, "wall_temp must be >= 0"); return -1; }
     return 0;
 }
 EXPORT void oigks_destroy(oigks_ctx *c) { if (c) { free_mesh(c); free(c); } }
@@ -643,6 +646,27 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
 /* ======================================================================
  * Boundary conditions (Sec. 2.5): ghost values and ghost increments
  * ==================================================================== */
+/* Cell-centre ghost of an isothermal no-slip wall (reading): the interior
+ * pressure, the temperature mirrored about the wall's, RT_g = 2 RT_w - RT_i
+ * (at least RT_w / 2), the no-slip ghost velocity (ux, uy), nu-tilde
+ * negated.  It serves the least-squares stencil, the limiter bounds, the
+ * spectral radius and the SA face terms; the face flux reflects the
+ * interior states instead (see residual()). */
+static void iso_ghost(const oigks_ctx *c, const double *Wi, double ux, double uy, double *Wg)
+{
+    const double tw = c->opt.wall_temp * c->p_inf / c->Winf[0];
+    const double r = Wi[0];
+    const double p = (GAMMA - 1.0) * (Wi[3] - 0.5 * (Wi[1] * Wi[1] + Wi[2] * Wi[2]) / r);
+    double tg = 2.0 * tw - p / r;
+    if (tg < 0.5 * tw) tg = 0.5 * tw;
+    const double rg = p / tg;
+    Wg[0] = rg;
+    Wg[1] = rg * ux;
+    Wg[2] = rg * uy;
+    Wg[3] = p / (GAMMA - 1.0) + 0.5 * rg * (ux * ux + uy * uy);
+    Wg[4] = -Wi[4];
+}
+
 static void ghost_state(const oigks_ctx *c, int bc, const double *Wi, double nx, double ny, double *Wg)
 {
     if (bc == BC_FREESTREAM) { for (int k = 0; k < 5; k++) Wg[k] = c->Winf[k]; return; }
@@ -652,6 +676,7 @@ static void ghost_state(const oigks_ctx *c, int bc, const double *Wi, double nx,
         Wg[0] = r; Wg[1] = mx - 2.0 * mn * nx; Wg[2] = my - 2.0 * mn * ny; Wg[3] = Wi[3]; Wg[4] = Wi[4];
         return;
     }
+    if (bc == BC_WALL && c->opt.wall_temp > 0.0) { iso_ghost(c, Wi, -mx / r, -my / r, Wg); return; }
     if (bc == BC_WALL) {                /* momentum and nu-tilde negated */
         Wg[0] = r; Wg[1] = -mx; Wg[2] = -my; Wg[3] = Wi[3]; Wg[4] = -Wi[4];
         return;
@@ -663,6 +688,7 @@ static void ghost_state(const oigks_ctx *c, int bc, const double *Wi, double nx,
          * average is V_w; V_w = 0 gives the rule above. */
         double tx = -ny, ty = nx, vt = (c->Winf[1] * tx + c->Winf[2] * ty) / c->Winf[0];
         double vwx = vt * tx, vwy = vt * ty;
+        if (c->opt.wall_temp > 0.0) { iso_ghost(c, Wi, 2.0 * vwx - mx / r, 2.0 * vwy - my / r, Wg); return; }
         Wg[0] = r;
         Wg[1] = 2.0 * vwx * r - mx;
         Wg[2] = 2.0 * vwy * r - my;
@@ -909,10 +935,14 @@ static int residual(oigks_ctx *c)
          * boosted by -u_w along the face, (rho, m_n, m_t, E) ->
          * (rho, m_n, m_t - u_w rho, E - u_w m_t + u_w^2 rho / 2), and the
          * ghost side is their point reflection as for a static wall. */
+        /* An isothermal wall, static or moving, takes the same path with
+         * u_w = 0 for a static one: the reflected states keep its mass and
+         * energy fluxes zero, and the heat flux is added below. */
         double uw = 0.0;
-        const int moving = j < 0 && c->fbc[f] == BC_MOVING_WALL;
+        const int moving = j < 0 && (c->fbc[f] == BC_MOVING_WALL ||
+                                     (c->fbc[f] == BC_WALL && c->opt.wall_temp > 0.0));
         if (moving) {
-            uw = (c->Winf[1] * tx + c->Winf[2] * ty) / c->Winf[0];
+            if (c->fbc[f] == BC_MOVING_WALL) uw = (c->Winf[1] * tx + c->Winf[2] * ty) / c->Winf[0];
             double *bs[4] = {wl, wlc, gln, glt};
             for (int h = 0; h < 4; h++) {
                 double *v = bs[h];
@@ -944,6 +974,18 @@ static int residual(oigks_ctx *c)
         double tau = collision_time(c, W0[0], lam_of(W0), nutf);
         face_detail fd;
         gks_core(wl, gln, glt, wr, grn, grt, wlc, wrc, dl, dr, c->dt_flux, tau, &fd);
+        if (j < 0 && c->opt.wall_temp > 0.0 && (c->fbc[f] == BC_WALL || c->fbc[f] == BC_MOVING_WALL)) {
+            /* isothermal wall (reading): the reflected states above let no
+             * mass or energy through in the wall's frame; a wall held at
+             * temperature T_w adds the Navier-Stokes heat flux of the BGK
+             * model (Pr = 1, kappa = mu c_p, c_p = gamma / (gamma - 1) in
+             * units of R) across the distance d_l from the cell centre,
+             * with mu at the cell-centre temperature */
+            const double thw = c->opt.wall_temp * c->p_inf / c->Winf[0];
+            const double pi = (GAMMA - 1.0) * (Wi[3] - 0.5 * (Wi[1] * Wi[1] + Wi[2] * Wi[2]) / Wi[0]);
+            const double kappa = mu_lam(c, lam_of(Wi)) * GAMMA / (GAMMA - 1.0);
+            fd.F[3] += c->dt_flux * kappa * (pi / Wi[0] - thw) / dl;
+        }
         if (moving) {   /* back to the frame of the mesh */
             fd.F[3] += uw * fd.F[2] + 0.5 * uw * uw * fd.F[0];
             fd.F[2] += uw * fd.F[0];

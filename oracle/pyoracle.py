@@ -15,7 +15,8 @@ _lib = None
 class Options(C.Structure):
     _fields_ = [("limiter", C.c_int), ("cfl_init", C.c_double), ("cfl_min", C.c_double),
                 ("cfl_max", C.c_double), ("cfl_mode", C.c_int), ("cfl_flux", C.c_double),
-                ("visc_sr", C.c_int), ("mu_law", C.c_int), ("scheme", C.c_int)]
+                ("visc_sr", C.c_int), ("mu_law", C.c_int), ("scheme", C.c_int),
+                ("wall_temp", C.c_double)]
 
 
 class Residual(C.Structure):

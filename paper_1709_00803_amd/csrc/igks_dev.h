@@ -33,6 +33,7 @@ constexpr int NCLASS = 4;     // kernel classes with a tunable block size: prep,
 struct InstParam {
     double Winf[5];
     double lam_inf, mu_inf, p_inf;
+    double tw;                 // RT of isothermal walls; 0: adiabatic walls
     int sa;
     int pad;
 };

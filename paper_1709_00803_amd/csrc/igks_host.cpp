@@ -769,6 +769,7 @@ void igks_default_options(igks_options *o)
     o->sweep = 0;
     o->flux_lanes = 0;
     o->scheme = 0;
+    o->wall_temp = 0.0;
 }
 
 int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream, int32_t n_inst)
@@ -785,6 +786,7 @@ int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream,
     if (c->opt.sweep < 0 || c->opt.sweep > 2 || c->opt.chunk < 0) { delete c; return IGKS_EINVAL; }
     if (c->opt.flux_lanes < 0 || c->opt.flux_lanes > 2) { delete c; return IGKS_EINVAL; }
     if (c->opt.scheme < 0 || c->opt.scheme > 1) { delete c; return IGKS_EINVAL; }
+    if (!(c->opt.wall_temp >= 0.0) || !std::isfinite(c->opt.wall_temp)) { delete c; return IGKS_EINVAL; }
     for (int k = 0; k < NCLASS; k++) c->block[k] = c->opt.block;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
@@ -955,6 +957,7 @@ int igks_batch_set_freestream(igks_ctx *c, int32_t inst, double mach, double alp
     std::memset(&ip, 0, sizeof ip);
     const double pinf = 1.0 / (GAMMA * mach * mach);
     ip.p_inf = pinf;
+    ip.tw = c->opt.wall_temp * pinf;   // RT = p / rho with rho_inf = 1
     ip.lam_inf = 1.0 / (2.0 * pinf);
     ip.mu_inf = 1.0 / reynolds;
     ip.sa = nut_ratio >= 0.0;

@@ -82,6 +82,21 @@ __device__ __forceinline__ double wall_speed(const InstParam &ip, double nx, dou
     return (ip.Winf[1] * -ny + ip.Winf[2] * nx) / ip.Winf[0];
 }
 
+// cell-centre ghost of an isothermal no-slip wall: the interior pressure,
+// RT mirrored about the wall's (2 RT_w - RT, at least RT_w / 2), the
+// no-slip ghost velocity (ux, uy), nu-tilde negated
+__device__ __forceinline__ void iso_ghost(const InstParam &ip, const double *w, double ux, double uy, double *g)
+{
+    const double p = (GAMMA - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
+    const double tg = fmax(2.0 * ip.tw - p / w[0], 0.5 * ip.tw);
+    const double rg = p / tg;
+    g[0] = rg;
+    g[1] = rg * ux;
+    g[2] = rg * uy;
+    g[3] = p * (1.0 / (GAMMA - 1.0)) + 0.5 * rg * (ux * ux + uy * uy);
+    g[4] = -w[4];
+}
+
 __device__ __forceinline__ void ghost(const InstParam &ip, int bc, const double *w, double nx, double ny, double *g)
 {
     if (bc == BC_FREESTREAM) {
@@ -96,6 +111,7 @@ __device__ __forceinline__ void ghost(const InstParam &ip, int bc, const double 
         return;
     }
     if (bc == BC_WALL) {
+        if (ip.tw > 0.0) { iso_ghost(ip, w, -mx / r, -my / r, g); return; }
         g[0] = r; g[1] = -mx; g[2] = -my; g[3] = w[3]; g[4] = -w[4];
         return;
     }
@@ -103,6 +119,7 @@ __device__ __forceinline__ void ghost(const InstParam &ip, int bc, const double 
         // no-slip wall moving with the tangential part V_w of the free-stream
         // velocity: interior density and temperature, velocity 2 V_w - V
         double vt = wall_speed(ip, nx, ny), vwx = -vt * ny, vwy = vt * nx;
+        if (ip.tw > 0.0) { iso_ghost(ip, w, 2.0 * vwx - mx / r, 2.0 * vwy - my / r, g); return; }
         g[0] = r;
         g[1] = 2.0 * vwx * r - mx;
         g[2] = 2.0 * vwy * r - my;
@@ -672,8 +689,10 @@ __device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &i
     o.d = side ? P.fdr[f] : P.fdl[f];   // fdr = fdl on a boundary face
     const bool ghost_side = bnd && side == 1;
     const int bc = bnd ? P.fbc[f] : 0;
-    // a moving wall is evaluated in its own frame from the owner's data
-    const bool moving = bc == BC_MOVING_WALL;
+    // a moving wall is evaluated in its own frame from the owner's data, and
+    // so is an isothermal static wall (u_w = 0): the reflected states let no
+    // mass or energy through, the heat flux is added in wall_face_terms
+    const bool moving = bc == BC_MOVING_WALL || (bc == BC_WALL && ip.tw > 0.0);
     double WMo[4], wmo[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) { WMo[k] = WM[k]; wmo[k] = wm[k]; }
@@ -719,7 +738,7 @@ __device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &i
         // face, (rho, m_n, m_t, E) -> (rho, m_n, m_t - u_w rho,
         // E - u_w m_t + u_w^2 rho / 2); the ghost side is then their point
         // reflection through a static no-slip wall
-        const double uw = wall_speed(ip, nx, ny);
+        const double uw = bc == BC_MOVING_WALL ? wall_speed(ip, nx, ny) : 0.0;
         double *bs[4] = {o.fw, o.fwc, o.gn, o.gt};
 #pragma unroll
         for (int h = 0; h < 4; h++) {
@@ -774,14 +793,29 @@ __device__ __forceinline__ void face_implicit_terms(const Params<T> &P, const In
     }
 }
 
-// flux of a moving-wall face from the wall's frame back to the mesh frame
+// Wall faces, on the face-frame flux integrated over [0, dt]: an isothermal
+// wall adds the heat flux mu c_p (T_c - T_w) / d_l of the BGK model (Pr = 1,
+// c_p = gamma / (gamma - 1) in units of R) from the owner's cell centre; a
+// moving wall's flux goes from the wall's frame back to the mesh frame.
 template <typename T>
-__device__ __forceinline__ void unboost_flux(const Params<T> &P, const InstParam &ip, int f, double *Fr)
+__device__ __forceinline__ void wall_face_terms(const Params<T> &P, const InstParam &ip, const double *W, int f,
+                                                double dt, double *Fr)
 {
-    if (P.fr[f] >= 0 || P.fbc[f] != BC_MOVING_WALL) return;
-    const double uw = wall_speed(ip, P.fnx[f], P.fny[f]);
-    Fr[3] += uw * Fr[2] + 0.5 * uw * uw * Fr[0];
-    Fr[2] += uw * Fr[0];
+    if (P.fr[f] >= 0) return;
+    const int bc = P.fbc[f];
+    if (bc != BC_WALL && bc != BC_MOVING_WALL) return;
+    if (ip.tw > 0.0) {
+        const int N = P.nc, l = P.fl[f];
+        const double wc[4] = {W[l], W[N + l], W[2 * N + l], W[3 * N + l]};
+        const double lc = lam_of(wc);
+        const double kappa = mu_lam(P.mu_law, ip, lc) * (GAMMA / (GAMMA - 1.0));
+        Fr[3] += dt * kappa * (0.5 / lc - ip.tw) / P.fdl[f];
+    }
+    if (bc == BC_MOVING_WALL) {
+        const double uw = wall_speed(ip, P.fnx[f], P.fny[f]);
+        Fr[3] += uw * Fr[2] + 0.5 * uw * uw * Fr[0];
+        Fr[2] += uw * Fr[0];
+    }
 }
 
 // face-frame flux integrated over [0, dt] -> F S / dt in the global frame
@@ -825,7 +859,7 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, d
     }
     double Fr[4], g[4];
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
-    unboost_flux(P, ip, f, Fr);
+    wall_face_terms(P, ip, W, f, dt, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
 #pragma unroll
     for (int k = 0; k < 4; k++) P.flux[k * F + f] = g[k];
@@ -867,7 +901,7 @@ __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int si
     }
     double Fr[4], g[4];
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
-    unboost_flux(P, ip, f, Fr);
+    wall_face_terms(P, ip, W, f, dt, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
     // each lane writes two of the four components
     P.flux[(2 * side) * F + f] = side ? g[2] : g[0];

@@ -52,7 +52,7 @@ def smooth_state(W, xc, yc, amp, seed):
 def pair(igks, mesh, flow, **opt):
     o = po.Oracle(mesh, **{k: v for k, v in opt.items() if k in ("limiter", "cfl_init", "cfl_mode", "cfl_flux",
                                                                    "visc_sr", "mu_law", "cfl_min", "cfl_max",
-                                                                   "scheme")})
+                                                                   "scheme", "wall_temp")})
     o.set_freestream(*flow)
     g = igks.Solver(mesh, **opt)
     g.set_freestream(*flow)
@@ -179,17 +179,17 @@ def rest_state(W):
     return W
 
 
-@pytest.mark.parametrize("lanes,limiter", [(1, 0), (2, 1)])
-def test_moving_wall_residual_parity(igks, lanes, limiter):
+@pytest.mark.parametrize("lanes,limiter,wall_temp", [(1, 0, 0.0), (2, 1, 0.0), (1, 1, 1.03), (2, 0, 0.97)])
+def test_moving_wall_residual_parity(igks, lanes, limiter, wall_temp):
     """A box of no-slip walls under a moving lid (wall-frame evaluation of
-    the lid faces): residual parity with both flux kernels on a perturbed
-    state, and no mass through the walls.  (At rest the gross mass and
-    tangential-momentum fluxes of interior cells vanish; the cavity
-    trajectory below covers that start.)"""
+    the lid faces), adiabatic or isothermal: residual parity with both flux
+    kernels on a perturbed state, and no mass through the walls.  (At rest
+    the gross mass and tangential-momentum fluxes of interior cells vanish;
+    the cavity trajectory below covers that start.)"""
     m = mg.random_hybrid(10, 8, seed=31, tags=TAGS_LID, jitter=0.3)
-    tag = f"lid box lanes={lanes} lim={limiter}"
+    tag = f"lid box lanes={lanes} lim={limiter} wall_temp={wall_temp}"
     say("case", tag, m.n_cells, "cells")
-    o, g = pair(igks, m, (0.3, 0.0, 1000.0, -1.0), limiter=limiter, flux_lanes=lanes)
+    o, g = pair(igks, m, (0.3, 0.0, 1000.0, -1.0), limiter=limiter, flux_lanes=lanes, wall_temp=wall_temp)
     c = o.cells()
     W1 = smooth_state(rest_state(o.get_state()), c["xc"], c["yc"], 0.08, 31)
     check_residual(o, g, W1, tag + " perturbed")
@@ -197,13 +197,15 @@ def test_moving_wall_residual_parity(igks, lanes, limiter):
     assert abs(Mg[0].sum()) <= 1e-13 * np.abs(Mg[0]).sum()
 
 
-def test_cavity_trajectory_parity(igks):
-    """The lid-driven cavity started from rest: GPU and oracle iterates stay
-    together (natural order, CFL law on)."""
+@pytest.mark.parametrize("wall_temp", [0.0, 1.0])
+def test_cavity_trajectory_parity(igks, wall_temp):
+    """The lid-driven cavity started from rest, adiabatic or isothermal
+    walls: GPU and oracle iterates stay together (natural order, CFL law
+    on)."""
     m = mg.cavity(16)
-    tag = "cavity 16x16"
+    tag = f"cavity 16x16 wall_temp={wall_temp}"
     say("case", tag)
-    o, g = pair(igks, m, (0.1 * np.sqrt(3.0), 0.0, 1000.0, -1.0), cfl_init=5.0, chunk=5)
+    o, g = pair(igks, m, (0.1 * np.sqrt(3.0), 0.0, 1000.0, -1.0), cfl_init=5.0, chunk=5, wall_temp=wall_temp)
     W0 = rest_state(o.get_state())
     o.set_state(W0)
     g.set_state(W0)

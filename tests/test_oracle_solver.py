@@ -153,6 +153,67 @@ def test_walls_moving_with_the_stream_keep_it(limiter):
     assert (np.abs(M[:4]) / G).max() > 1e-4
 
 
+@pytest.mark.parametrize("mu_law,tol", [(1, 1e-4), (0, 2e-3)])
+def test_isothermal_wall_heat_flux_matches_kinetic_conduction(mu_law, tol):
+    """Gas at rest at constant pressure with a temperature rising linearly
+    from an isothermal bottom wall: the wall's heat flux equals the heat the
+    interior gas-kinetic fluxes conduct across the horizontal faces (the BGK
+    model's conductivity, measured from the kinetic flux, not assumed).
+    Sutherland's law evaluates mu half a cell apart on the two sides."""
+    g = 1.4
+    n, a = 16, 0.02
+    tags = dict(bottom=mg.WALL, top=mg.SYMMETRY, left=mg.SYMMETRY, right=mg.SYMMETRY)
+    m = mg.random_hybrid(n, n, seed=0, tri_frac=0.0, jitter=0.0, ly=1.0, tags=tags)
+    o = po.Oracle(m, mu_law=mu_law, wall_temp=1.0 - 0.5 * a)
+    o.set_freestream(0.3, 0.0, 500.0)
+    c = o.cells()
+    W = o.get_state()
+    p = (g - 1) * (W[3] - 0.5 * (W[1] ** 2 + W[2] ** 2) / W[0])
+    th = p / W[0] * (1 + a * (c["yc"] - 0.5))
+    W[0] = p / th
+    W[1] = W[2] = 0.0
+    W[3] = p / (g - 1)
+    o.set_state(W)
+    o.compute_residual()
+    F, f = o.debug()["flux"][3], o.faces()
+    horiz = (f["fr"] >= 0) & (np.abs(f["ny"]) > 0.99)
+    down = -(F * np.sign(f["ny"]) / f["len"])                             # downward conduction
+    rows = [down[horiz & (np.abs(f["ym"] - k / n) < 1e-9)] for k in (1, 2, 3)]
+    wall = (f["fr"] < 0) & (f["bc"] == mg.WALL)
+    q_wall = (F / f["len"])[wall]                                         # outward = downward
+    assert np.all(q_wall > 0) and all(np.all(r > 0) for r in rows)       # heat flows down into the cold wall
+    if mu_law == 1:                                                       # the first row conducts like the rest
+        assert abs(rows[0].mean() / rows[2].mean() - 1) <= 1e-6
+    q_in = rows[0].mean()
+    assert np.abs(q_wall / q_in - 1).max() <= tol, (q_wall / q_in)
+    # adiabatic walls conduct nothing
+    o2 = po.Oracle(m, mu_law=mu_law)
+    o2.set_freestream(0.3, 0.0, 500.0)
+    o2.set_state(W)
+    o2.compute_residual()
+    assert np.abs(o2.debug()["flux"][3][wall]).max() <= 1e-15
+
+
+def test_isothermal_box_at_wall_temperature_is_steady():
+    """A still gas at the walls' temperature stays put; a hotter one loses
+    energy through the walls and keeps its mass."""
+    tags = dict(bottom=mg.WALL, top=mg.WALL, left=mg.WALL, right=mg.WALL)
+    m = mg.random_hybrid(8, 7, seed=17, tags=tags, jitter=0.3)
+    for wt, sign in ((1.0, 0), (0.9, -1)):
+        o = po.Oracle(m, wall_temp=wt)
+        o.set_freestream(0.3, 0.0, 500.0)
+        W = o.get_state()
+        W[3] -= 0.5 * (W[1] ** 2 + W[2] ** 2) / W[0]
+        W[1] = W[2] = 0.0
+        o.set_state(W)
+        M, G = o.compute_residual()
+        assert abs(M[0].sum()) <= 1e-13 * G[0].sum()
+        if sign == 0:
+            assert np.abs(M[:4]).max() <= 1e-13 * G.max()
+        else:
+            assert M[3].sum() < 0
+
+
 def _rotate_state(W, th, mirror=False):
     W = W.copy()
     if mirror:
