@@ -490,16 +490,17 @@ __device__ __forceinline__ void gks_finish(const GksEq &q, const double *acc, do
 }
 
 // Euler flux Jacobian-vector product J(W, n) d (the linearised flux of the
-// implicit operator, Eq.18-20).
+// implicit operator, Eq.18-20).  One reciprocal of rho: the sweeps run one
+// wavefront after another, and a divide is a long dependent sequence.
 template <typename V>
 __device__ __forceinline__ void jac_vec(const V *W, V nx, V ny, const V *d, V *out)
 {
-    V r = W[0], U = W[1] / r, Vv = W[2] / r, E = W[3];
+    V r = W[0], ir = V(1) / r, U = W[1] * ir, Vv = W[2] * ir, E = W[3];
     V ke = V(0.5) * (U * U + Vv * Vv);
     V p = V(GAMMA - 1.0) * (E - r * ke);
     V q = U * nx + Vv * ny;
     V dmn = d[1] * nx + d[2] * ny;
-    V dq = (dmn - q * d[0]) / r;
+    V dq = (dmn - q * d[0]) * ir;
     V dp = V(GAMMA - 1.0) * (d[3] - (U * d[1] + Vv * d[2]) + ke * d[0]);
     out[0] = dmn;
     out[1] = d[1] * q + W[1] * dq + dp * nx;
@@ -1117,7 +1118,7 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
 }
 
 // sweep modes
-enum { SW_FWD = 0, SW_BWD = 1, SW_TOP = 2 };
+enum { SW_FWD = 0, SW_BWD = 1, SW_TOP = 2, SW_BWD_ONLY = 3 };
 
 // W^{n+1} = W^n + dW (Eq.17) into the instance's other state buffer, nu~
 // clipped at 0; flags a non-physical result; returns the Eq.40 ratio
@@ -1185,12 +1186,13 @@ __global__ __launch_bounds__(256) void k_explicit(Params<T> P)
 // ghosts above them and their backward step needs nothing from other cells.
 // The backward step also applies W^{n+1} = W^n + dW (Eq.17) into the
 // instance's other state buffer (nu~ clipped at 0), flags a non-physical
-// result and returns the Eq.40 ratio.  inst = -1 for a frozen instance.
-template <typename T, int MODE>
+// result and returns the Eq.40 ratio; SW_BWD_ONLY leaves the update to
+// k_update.  inst = -1 for a frozen instance.
+template <typename T, int MODE, bool ONE = false>
 __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &inst)
 {
     const int N = P.nc;
-    inst = cell_inst(P, c);
+    inst = ONE ? 0 : cell_inst(P, c);   // ONE: a single instance, its scalars uniform
     const InstScalars &sc = P.is[inst];
     if (sc.halt) {
         inst = -1;
@@ -1206,7 +1208,7 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     const T odt = T(P.lamc[c]) / cfl;   // Omega / dt_imp with dt_imp = CFL Omega / Lambda_c (Eq.24)
     const T D = odt + T(P.lsum[c]);
     T dws[5], acc[5], t[5];
-    if (MODE != SW_BWD) {
+    if (MODE == SW_FWD || MODE == SW_TOP) {
 #pragma unroll
         for (int k = 0; k < 5; k++) acc[k] = T(P.M[k * N + c]);
 #pragma unroll
@@ -1218,8 +1220,9 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
             for (int m = 0; m < 4; m++) acc[m] -= t[m];
             acc[4] += t[4];
         }
+        const T iD = T(1) / D;
 #pragma unroll
-        for (int k = 0; k < 4; k++) dws[k] = acc[k] / D;
+        for (int k = 0; k < 4; k++) dws[k] = acc[k] * iD;
         dws[4] = ip.sa ? acc[4] / (odt + T(P.sadiag[c])) : T(0);
         if (MODE == SW_FWD) {
 #pragma unroll
@@ -1241,11 +1244,13 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
         for (int m = 0; m < 5; m++) acc[m] += t[m];
     }
     T d[5];
+    const T iD = T(1) / D;
 #pragma unroll
-    for (int k = 0; k < 4; k++) d[k] = dws[k] - acc[k] / D;
+    for (int k = 0; k < 4; k++) d[k] = dws[k] - acc[k] * iD;
     d[4] = ip.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
 #pragma unroll
     for (int k = 0; k < 5; k++) P.dW[k * N + c] = d[k];
+    if (MODE == SW_BWD_ONLY) return 0.0;
     double dd[5];
 #pragma unroll
     for (int k = 0; k < 5; k++) dd[k] = double(d[k]);
@@ -1285,22 +1290,52 @@ __global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
 // The whole sweep in one workgroup: wavefront after wavefront, separated by
 // workgroup barriers (all waves of a workgroup share one CU and its L1, so
 // the barrier orders the dW writes of one wavefront before the reads of the
-// next).  Used when wavefronts are many and narrow.  Every thread runs the
-// same number of rounds, so the wave-wide slot updates see full waves.
-template <typename T, bool FWD>
+// next).  Used when wavefronts are many and narrow: the time per wavefront
+// is latency, so the backward sweep leaves the update (Eq.17, Eq.40) to one
+// parallel pass afterwards (k_update) instead of adding its loads and stores
+// to every step.
+// ONE (a context of one instance) makes the instance index a constant, so
+// its scalars come through scalar loads instead of a dependent vector load
+// chain on every wavefront.
+template <typename T, bool FWD, bool ONE>
 __global__ __launch_bounds__(512) void k_sweep_wg(Params<T> P, const int *lev_off, int nlev)
 {
     for (int i = 0; i < nlev; i++) {
         int l = FWD ? i : nlev - 1 - i;
         int c0 = lev_off[l], c1 = lev_off[l + 1];
-        for (int base = c0; base < c1; base += (int)blockDim.x) {
-            int c = base + (int)threadIdx.x, inst = -1;
-            double e = 0.0;
-            if (c < c1) e = sweep_cell<T, FWD ? SW_FWD : SW_BWD>(P, c, inst);
-            if (!FWD) slot_update<false>(&P.is[0].e40_bits[0], inst, e);
+        for (int c = c0 + (int)threadIdx.x; c < c1; c += (int)blockDim.x) {
+            int inst;
+            (void)sweep_cell<T, FWD ? SW_FWD : SW_BWD_ONLY, ONE>(P, c, inst);
         }
         __syncthreads();
     }
+}
+
+// W^{n+1} = W^n + dW for every cell from the finished backward sweep (the
+// same arithmetic as the fused update of the per-wavefront path)
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(Params<T> P)
+{
+    const int N = P.nc;
+    int c = xcd_block() * blockDim.x + threadIdx.x;
+    int inst = -1;
+    double e = 0.0;
+    if (c < N) {
+        inst = cell_inst(P, c);
+        if (P.is[inst].halt) {
+            inst = -1;
+        } else {
+            const double *W = cur_state(P, inst);
+            double w[5], d[5];
+#pragma unroll
+            for (int k = 0; k < 5; k++) {
+                w[k] = W[k * N + c];
+                d[k] = double(P.dW[k * N + c]);
+            }
+            e = apply_update(P, c, inst, w, d);
+        }
+    }
+    slot_update<false>(&P.is[0].e40_bits[0], inst, e);
 }
 
 // exact distance from each centroid to the nearest wall segment of its instance
@@ -1398,9 +1433,15 @@ template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int
 }
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd)
 {
-    // 512 threads: the backward step with the update fits in registers (1024 spilled)
-    if (fwd) hipLaunchKernelGGL((k_sweep_wg<T, true>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
-    else hipLaunchKernelGGL((k_sweep_wg<T, false>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
+    const bool one = P.ninst == 1;
+    if (fwd) {
+        if (one) hipLaunchKernelGGL((k_sweep_wg<T, true, true>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
+        else hipLaunchKernelGGL((k_sweep_wg<T, true, false>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
+    } else {
+        if (one) hipLaunchKernelGGL((k_sweep_wg<T, false, true>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
+        else hipLaunchKernelGGL((k_sweep_wg<T, false, false>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
+        hipLaunchKernelGGL(k_update<T>, dim3(nblk(P.nc, L.block[3])), dim3(L.block[3]), 0, L.s, P);
+    }
 }
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
                           const int *woff, const double *wseg, double *dwall)
