@@ -14,6 +14,7 @@ Prints one JSON line.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -115,6 +116,35 @@ def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=
     wl = s.wall_loads()
     return dict(iterations=it, seconds=round(dt, 4), drop=s.residual()["res_drop"], cd=wl["cd"],
                 cell_updates_per_s=m.n_cells * it / dt)
+
+
+def time_to_converge_cavity(igks, mg, max_it=20000, chunk=200):
+    """The lid-driven cavity (100x100, Re 1000, Ma 0.1 sqrt 3, isothermal
+    walls) from rest, implicit CFL 1000 growing by Eq.25, to the paper's
+    criterion Eq.40 <= 3e-8."""
+    import torch
+    m = mg.cavity(100)
+    s = igks.Solver(m, cfl_init=1000.0, chunk=chunk, wall_temp=1.0)
+    s.set_freestream(0.1 * math.sqrt(3.0), 0.0, 1000.0)
+    W = s.get_state()
+    W[3] -= 0.5 * (W[1] ** 2 + W[2] ** 2) / W[0]
+    W[1] = W[2] = 0.0
+    s.set_state(W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = 0
+    while it < max_it:
+        s.iterate(chunk)
+        it += chunk
+        if s.residual()["eq40"] <= 3e-8:
+            break
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = s.residual()
+    return dict(workload="cavity100: 100x100 uniform, Re 1000, Ma 0.1 sqrt(3), isothermal walls, from rest",
+                criterion="Eq.40 <= 3e-8", iterations=it, seconds=round(dt, 4), eq40=r["eq40"],
+                drop=r["res_drop"], cfl=r["cfl"], ms_per_iteration=round(1e3 * dt / it, 4),
+                paper_iterations=4430, paper_seconds=543.2)
 
 
 def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000):
@@ -324,6 +354,7 @@ def main():
                                 "batched_plates": time_to_drop_batch(igks, mg),
                                 "explicit_fp64_cfl0.9": time_to_drop(igks, mg, igks.IGKS_FP64, scheme=1, cfl=0.9,
                                                                      chunk=1000, max_it=400000)}
+        out["cavity_to_eq40"] = time_to_converge_cavity(igks, mg)
     if not args.no_cpu:
         out["cpu_baseline"] = run_cpu_baseline(list(zip(meshes, flows))[:4])
     print(json.dumps(out), flush=True)
