@@ -12,8 +12,10 @@
  *   - per iteration, the residual of Eq.16, the implicit CFL law Eq.24-25
  *     and the matrix-free LU-SGS forward/backward sweeps of Eq.18-22 and
  *     Eq.31-32, with the ghost-cell boundary conditions of Sec. 2.5;
- *   on a 2D hybrid (triangle + quadrilateral) mesh given in the node /
- *   per-cell vertex list form of Sec. 2.4, on one GPU.
+ *   on a 2D hybrid mesh (triangles, quadrilaterals and polygons of up to
+ *   eight vertices, such as the pentagons and hexagons that hanging nodes
+ *   of an adaptive quadtree make, Sec. 2.4 and Sec. 4.1) given in the
+ *   node / per-cell vertex list form of Sec. 2.4, on one GPU.
  *
  * Conventions
  *   - Every call returns an int status: IGKS_OK (0) or a negative error
@@ -127,10 +129,11 @@ const char *igks_last_error(const igks_ctx *ctx);
 
 /* Mesh in the form of Sec. 2.4: n_nodes coordinates xy[2*n_nodes]
  * (x0,y0,x1,y1,...); cells as CSR: vertices of cell i are
- * cell_nodes[cell_ptr[i] .. cell_ptr[i+1]-1], 3 or 4 of them, either
- * orientation; n_bfaces boundary edges bface_nodes[2*b], [2*b+1] with tags
+ * cell_nodes[cell_ptr[i] .. cell_ptr[i+1]-1], 3 to 8 of them, either
+ * orientation (a polygon may have collinear vertices: every edge is a
+ * face); n_bfaces boundary edges bface_nodes[2*b], [2*b+1] with tags
  * bface_tag[b] (IGKS_BC_*).  All host memory, copied.
- * IGKS_EMESH: a cell with fewer than 3 or more than 4 nodes, a degenerate
+ * IGKS_EMESH: a cell with fewer than 3 or more than 8 nodes, a degenerate
  * (zero-area) cell, an edge shared by more than two cells, a cell edge on
  * the boundary without a tag, a tagged edge that is not on the boundary, a
  * bad tag, or a node index out of range.  Replaces any previous mesh and

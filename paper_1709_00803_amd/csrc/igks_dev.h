@@ -22,8 +22,13 @@ enum { BC_FREESTREAM = 1, BC_SYMMETRY = 2, BC_WALL = 3, BC_OUTFLOW = 4, BC_FARFI
 constexpr int CF_OWNER = 1;   // the cell is the face's owner (normal points outward)
 constexpr int CF_LOWER = 2;   // interior neighbour with a smaller upload index
 constexpr int CF_VALID = 4;   // the entry exists (triangles leave their fourth entry empty)
+// A polygon's faces and vertices beyond the fourth sit in an overflow block
+// of four more (block nc + o); the last entry of a block carries o + 1 in
+// the flag bits from CF_NEXT_SHIFT on (0: no further block).
+constexpr int CF_NEXT_SHIFT = 8;
 
-constexpr int MAXV = 4;       // vertices per cell (triangles padded by repeating a vertex)
+constexpr int MAXV = 4;       // entries and vertices per block (triangles pad by repeating a vertex)
+constexpr int MAXP = 8;       // vertices of the largest cell (two blocks)
 constexpr int HIST_W = 6;     // doubles per history entry
 constexpr int NSLOT = 64;     // atomic min/max targets of one instance are spread over this many slots
 constexpr int RB = 32;        // blocks per instance in the residual-norm reduction
@@ -75,9 +80,12 @@ struct Params {
     double *sadiag;            // SA diagonal without Omega/dt
     double *r2;                // squares for the norms, M_rho^2 then R_SA^2, at the cell's ipos
     T *dW;                     // LU-SGS increment, 5 x nc
-    const double *xc, *yc, *area, *lsinv, *dwall, *vtx;
-    // cell-face entries, MAXV per cell (entry MAXV c + k): face, neighbour
-    // (-1: ghost cell), flags, centroid offsets to the neighbour (or ghost)
+    const double *xc, *yc, *area, *lsinv, *dwall;
+    const double *vtx;         // vertex offsets from the centroid: (x, y) of slot v of block b at (2v) nb + b
+    int nb;                    // entry / vertex blocks: nc + overflow blocks
+    // cell-face entries, MAXV per block (entry MAXV b + k; block b = c, then
+    // the overflow block of a polygon): face, neighbour (-1: ghost cell),
+    // flags, centroid offsets to the neighbour (or ghost)
     const int *cf_face, *cf_nbr, *cf_flag;
     const double *cf_dx, *cf_dy;
     // face arrays (internal face order)

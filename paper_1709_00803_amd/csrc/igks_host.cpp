@@ -38,12 +38,13 @@ struct InstMesh {
 // All instances concatenated in the internal order.
 struct Global {
     int N = 0, F = 0, nlev = 0, nwall = 0, max_inst_cells = 0;
+    int NB = 0;                      // entry / vertex blocks: N + one overflow block per polygon
     std::vector<int> lev_off;        // wavefront offsets (internal cells)
     std::vector<int> coff;           // first global upload id of each instance
     std::vector<int> g2i;            // global upload id -> internal cell
     std::vector<int> cinst, finst, icell, ioff, ipos;
     std::vector<double> xc, yc, area, lsinv, vtx;
-    std::vector<int> cf_face, cf_nbr, cf_flag;   // MAXV entries per cell
+    std::vector<int> cf_face, cf_nbr, cf_flag;   // MAXV entries per block
     std::vector<double> cf_dx, cf_dy;
     std::vector<int> fl, fr, ftag;
     std::vector<double> fnx, fny, flen, frl, frr, fdl, fdr, frn, fxm;
@@ -138,9 +139,9 @@ int build_instance(igks_ctx *ctx, int n_nodes, const double *xy, int n_cells, co
     m.cptr.assign(cell_ptr, cell_ptr + N + 1);
     for (int i = 0; i < N; i++) {
         int k = m.cptr[i + 1] - m.cptr[i];
-        if (k < 3 || k > MAXV)
+        if (k < 3 || k > MAXP)
             return fail(ctx, IGKS_EMESH, "cell " + std::to_string(i) + " has " + std::to_string(k) +
-                                             " nodes (3 or 4 supported)");
+                                             " nodes (3 to " + std::to_string(MAXP) + " supported)");
     }
     m.cn.resize(m.cptr[N]);
     for (int p = 0; p < m.cptr[N]; p++) {
@@ -359,12 +360,23 @@ int combine(igks_ctx *ctx)
         G.woff[i + 1] = (int)G.wall_faces.size();
     }
     G.nwall = (int)G.wall_faces.size();
-    // cells in internal order
+    // cells in internal order; a polygon with more than MAXV faces gets an
+    // overflow block (blocks N, N + 1, ... in internal cell order)
     G.xc.resize(N); G.yc.resize(N); G.area.resize(N); G.lsinv.resize(3 * (size_t)N);
-    G.vtx.resize(2 * MAXV * (size_t)N);
-    // entries: MAXV per cell, in the order of the cell's faces; unused
+    std::vector<int> ovf(N, -1);
+    int NB = N;
+    for (int c = 0; c < N; c++) {
+        const InstMesh &m = ctx->inst[gi[order[c]]];
+        const int u = gu[order[c]];
+        if (m.cf_ptr[u + 1] - m.cf_ptr[u] > MAXV || m.cptr[u + 1] - m.cptr[u] > MAXV) ovf[c] = NB++;
+    }
+    if (NB - N >= (1 << (31 - CF_NEXT_SHIFT)))
+        return fail(ctx, IGKS_EMESH, "too many cells with more than " + std::to_string(MAXV) + " faces");
+    G.NB = NB;
+    G.vtx.resize(2 * MAXV * (size_t)NB);
+    // entries: MAXV per block, in the order of the cell's faces; unused
     // entries point at the cell's first face with no flags
-    const size_t ne = (size_t)MAXV * N;
+    const size_t ne = (size_t)MAXV * NB;
     G.cf_face.assign(ne, 0); G.cf_nbr.assign(ne, -1); G.cf_flag.assign(ne, 0);
     G.cf_dx.assign(ne, 0.0); G.cf_dy.assign(ne, 0.0);
     for (int c = 0; c < N; c++) {
@@ -372,8 +384,13 @@ int combine(igks_ctx *ctx)
         const InstMesh &m = ctx->inst[i];
         G.xc[c] = m.xc[u]; G.yc[c] = m.yc[u]; G.area[c] = m.area[u];
         double a11 = 0, a12 = 0, a22 = 0;
-        size_t e = (size_t)MAXV * c;
-        for (int k = m.cf_ptr[u]; k < m.cf_ptr[u + 1]; k++) {
+        const int nfc = m.cf_ptr[u + 1] - m.cf_ptr[u];
+        auto slot = [&](int k) {   // entry index of the cell's k-th face
+            return k < MAXV ? (size_t)MAXV * c + k : (size_t)MAXV * ovf[c] + (k - MAXV);
+        };
+        for (int kk = 0; kk < nfc; kk++) {
+            const int k = m.cf_ptr[u] + kk;
+            const size_t e = slot(kk);
             const int q = m.cf_list[k];
             const auto &f = m.uf[q];
             const int qi = fpos[i][q];
@@ -393,9 +410,10 @@ int combine(igks_ctx *ctx)
             G.cf_dx[e] = dx;
             G.cf_dy[e] = dy;
             a11 += dx * dx; a12 += dx * dy; a22 += dy * dy;
-            e++;
         }
-        for (size_t k = e; k < (size_t)MAXV * (c + 1); k++) G.cf_face[k] = G.cf_face[(size_t)MAXV * c];
+        const int nslots = ovf[c] >= 0 ? 2 * MAXV : MAXV;
+        for (int kk = nfc; kk < nslots; kk++) G.cf_face[slot(kk)] = G.cf_face[(size_t)MAXV * c];
+        if (ovf[c] >= 0) G.cf_flag[(size_t)MAXV * c + MAXV - 1] |= (ovf[c] - N + 1) << CF_NEXT_SHIFT;
         double det = a11 * a22 - a12 * a12;
         if (!(det > 0))
             return fail(ctx, IGKS_EMESH, "instance " + std::to_string(i) + ": singular least-squares stencil at cell " +
@@ -404,10 +422,11 @@ int combine(igks_ctx *ctx)
         G.lsinv[(size_t)N + c] = -a12 / det;
         G.lsinv[2 * (size_t)N + c] = a11 / det;
         int p0 = m.cptr[u], k = m.cptr[u + 1] - p0;
-        for (int v = 0; v < MAXV; v++) {
+        for (int v = 0; v < (ovf[c] >= 0 ? 2 * MAXV : MAXV); v++) {
             int node = m.cn[p0 + (v < k ? v : 0)];
-            G.vtx[(2 * v) * (size_t)N + c] = m.xy[2 * node] - m.xc[u];
-            G.vtx[(2 * v + 1) * (size_t)N + c] = m.xy[2 * node + 1] - m.yc[u];
+            const size_t b = v < MAXV ? (size_t)c : (size_t)ovf[c], sv = v % MAXV;
+            G.vtx[(2 * sv) * (size_t)NB + b] = m.xy[2 * node] - m.xc[u];
+            G.vtx[(2 * sv + 1) * (size_t)NB + b] = m.xy[2 * node + 1] - m.yc[u];
         }
     }
     ctx->combined = true;
@@ -430,7 +449,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
 {
     Layout L;
     WsMap w;
-    const size_t N = G.N, F = G.F, E = (size_t)MAXV * G.N, D = sizeof(double),
+    const size_t N = G.N, F = G.F, E = (size_t)MAXV * G.NB, D = sizeof(double),
                  I = sizeof(int), NI = ninst, NW = std::max(1, G.nwall);
     w.ip = L.add(NI * sizeof(InstParam));
     w.is = L.add(NI * sizeof(InstScalars));
@@ -439,7 +458,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.M = L.add(5 * N * D); w.lsum = L.add(N * D); w.sadiag = L.add(N * D); w.r2 = L.add(2 * N * D);
     w.dW = L.add(5 * N * (o.precision == IGKS_MIXED ? sizeof(float) : D));
     w.xc = L.add(N * D); w.yc = L.add(N * D); w.area = L.add(N * D); w.lsinv = L.add(3 * N * D);
-    w.dwall = L.add(N * D); w.vtx = L.add(2 * MAXV * N * D);
+    w.dwall = L.add(N * D); w.vtx = L.add(2 * MAXV * (size_t)G.NB * D);
     w.cinst = L.add(N * I); w.finst = L.add(F * I); w.icell = L.add(N * I); w.ioff = L.add((NI + 1) * I);
     w.g2i = L.add(N * I);
     w.cf_face = L.add(E * I); w.cf_nbr = L.add(E * I); w.cf_flag = L.add(E * I);
@@ -483,6 +502,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.Wa = D(w.Wa); P.Wb = D(w.Wb); P.grad = D(w.grad); P.lamc = D(w.lamc); P.vort = D(w.vort); P.nu = D(w.nu);
     P.M = D(w.M); P.lsum = D(w.lsum); P.sadiag = D(w.sadiag); P.r2 = D(w.r2); P.dW = (T *)(b + w.dW.off);
     P.xc = D(w.xc); P.yc = D(w.yc); P.area = D(w.area); P.lsinv = D(w.lsinv); P.dwall = D(w.dwall); P.vtx = D(w.vtx);
+    P.nb = c->g.NB;
     P.cf_face = In(w.cf_face); P.cf_nbr = In(w.cf_nbr); P.cf_flag = In(w.cf_flag);
     P.cf_dx = D(w.cf_dx); P.cf_dy = D(w.cf_dy);
     P.fl = In(w.fl); P.fr = In(w.fr); P.fbc = In(w.fbc);
@@ -896,10 +916,10 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
         HIPCHK(c, hipMemcpyAsync(b + x.off, src, n, hipMemcpyHostToDevice, c->stream));
         return IGKS_OK;
     };
-    const size_t D = sizeof(double), I = sizeof(int), N = G.N, F = G.F, E = (size_t)MAXV * G.N;
+    const size_t D = sizeof(double), I = sizeof(int), N = G.N, F = G.F, E = (size_t)MAXV * G.NB;
     rc = 0;
     rc |= up(w.xc, G.xc.data(), N * D); rc |= up(w.yc, G.yc.data(), N * D); rc |= up(w.area, G.area.data(), N * D);
-    rc |= up(w.lsinv, G.lsinv.data(), 3 * N * D); rc |= up(w.vtx, G.vtx.data(), 2 * MAXV * N * D);
+    rc |= up(w.lsinv, G.lsinv.data(), 3 * N * D); rc |= up(w.vtx, G.vtx.data(), G.vtx.size() * D);
     rc |= up(w.cinst, G.cinst.data(), N * I); rc |= up(w.finst, G.finst.data(), F * I);
     rc |= up(w.icell, G.icell.data(), N * I); rc |= up(w.ioff, G.ioff.data(), G.ioff.size() * I);
     rc |= up(w.ipos, G.ipos.data(), N * I);

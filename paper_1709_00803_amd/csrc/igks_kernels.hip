@@ -231,18 +231,26 @@ __device__ __forceinline__ double slots_max_serial(const unsigned long long *b)
     return v;
 }
 
-// The (up to) four cell-face entries of cell c: face, neighbour (-1: ghost)
-// and flags, one 16-byte load each.
+// One block of four cell-face entries (block b: the cell's own block b = c,
+// or a polygon's overflow block): face, neighbour (-1: ghost) and flags,
+// one 16-byte load each.
 struct Entries {
     int face[MAXV], nbr[MAXV], flag[MAXV];
 };
 template <typename T>
-__device__ __forceinline__ Entries entries(const Params<T> &P, int c)
+__device__ __forceinline__ Entries entries(const Params<T> &P, int b)
 {
-    const int4 f = reinterpret_cast<const int4 *>(P.cf_face)[c];
-    const int4 n = reinterpret_cast<const int4 *>(P.cf_nbr)[c];
-    const int4 g = reinterpret_cast<const int4 *>(P.cf_flag)[c];
+    const int4 f = reinterpret_cast<const int4 *>(P.cf_face)[b];
+    const int4 n = reinterpret_cast<const int4 *>(P.cf_nbr)[b];
+    const int4 g = reinterpret_cast<const int4 *>(P.cf_flag)[b];
     return Entries{{f.x, f.y, f.z, f.w}, {n.x, n.y, n.z, n.w}, {g.x, g.y, g.z, g.w}};
+}
+// the block after E, or -1 (triangles and quadrilaterals have one block)
+template <typename T>
+__device__ __forceinline__ int next_block(const Params<T> &P, const Entries &E)
+{
+    const int o = E.flag[MAXV - 1] >> CF_NEXT_SHIFT;
+    return o ? P.nc + o - 1 : -1;
 }
 
 // instance of a cell / face (a one-instance context needs no lookup)
@@ -552,29 +560,34 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
     double lc = 0.0, b1[4] = {0, 0, 0, 0}, b2[4] = {0, 0, 0, 0}, wmax[4], wmin[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) wmax[k] = wmin[k] = w[k];
-    const Entries E = entries(P, c);
+    int ovf = -1;   // a polygon's overflow block
+    for (int b = c; b >= 0;) {
+        const Entries E = entries(P, b);
 #pragma unroll
-    for (int k = 0; k < MAXV; k++) {
-        if (!(E.flag[k] & CF_VALID)) continue;
-        const int e = MAXV * c + k, f = E.face[k], j = E.nbr[k];
-        double nx = P.fnx[f], ny = P.fny[f], S = P.flen[f];
-        lc += (fabs(U * nx + V * ny) + cs) * S;
-        double wj[5];
-        if (j >= 0) {
+        for (int k = 0; k < MAXV; k++) {
+            if (!(E.flag[k] & CF_VALID)) continue;
+            const int e = MAXV * b + k, f = E.face[k], j = E.nbr[k];
+            double nx = P.fnx[f], ny = P.fny[f], S = P.flen[f];
+            lc += (fabs(U * nx + V * ny) + cs) * S;
+            double wj[5];
+            if (j >= 0) {
 #pragma unroll
-            for (int k = 0; k < 4; k++) wj[k] = W[k * N + j];
-        } else {
-            ghost(ip, P.fbc[f], w, nx, ny, wj);
+                for (int k = 0; k < 4; k++) wj[k] = W[k * N + j];
+            } else {
+                ghost(ip, P.fbc[f], w, nx, ny, wj);
+            }
+            double dx = P.cf_dx[e], dy = P.cf_dy[e];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                double d = wj[k] - w[k];
+                b1[k] += dx * d;
+                b2[k] += dy * d;
+                wmax[k] = fmax(wmax[k], wj[k]);
+                wmin[k] = fmin(wmin[k], wj[k]);
+            }
         }
-        double dx = P.cf_dx[e], dy = P.cf_dy[e];
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            double d = wj[k] - w[k];
-            b1[k] += dx * d;
-            b2[k] += dy * d;
-            wmax[k] = fmax(wmax[k], wj[k]);
-            wmin[k] = fmin(wmin[k], wj[k]);
-        }
+        b = next_block(P, E);
+        if (b >= 0) ovf = b;
     }
     P.lamc[c] = lc;
     double L11 = P.lsinv[c], L12 = P.lsinv[N + c], L22 = P.lsinv[2 * N + c];
@@ -588,21 +601,29 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
     double dVdx = (gx[2] - V * gx[0]) / r;
     P.vort[c] = fabs(dVdx - dUdy);
     if (P.limiter) {
-        double vx[MAXV], vy[MAXV];
+        const int NB = P.nb;
+        double nmax[4], nmin[4];
 #pragma unroll
-        for (int v = 0; v < MAXV; v++) { vx[v] = P.vtx[(2 * v) * N + c]; vy[v] = P.vtx[(2 * v + 1) * N + c]; }
+        for (int k = 0; k < 4; k++) { nmax[k] = -INFINITY; nmin[k] = INFINITY; }
+        for (int b = c; b >= 0; b = (b == c) ? ovf : -1) {
+            double vx[MAXV], vy[MAXV];
+#pragma unroll
+            for (int v = 0; v < MAXV; v++) { vx[v] = P.vtx[(2 * v) * NB + b]; vy[v] = P.vtx[(2 * v + 1) * NB + b]; }
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+#pragma unroll
+                for (int v = 0; v < MAXV; v++) {
+                    double wv = w[k] + gx[k] * vx[v] + gy[k] * vy[v];
+                    nmax[k] = fmax(nmax[k], wv);
+                    nmin[k] = fmin(nmin[k], wv);
+                }
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            double nmax = -INFINITY, nmin = INFINITY;
-#pragma unroll
-            for (int v = 0; v < MAXV; v++) {
-                double wv = w[k] + gx[k] * vx[v] + gy[k] * vy[v];
-                nmax = fmax(nmax, wv);
-                nmin = fmin(nmin, wv);
-            }
             double phi = 1.0;
-            if (nmax > w[k]) phi = fmin(phi, (wmax[k] - w[k]) / (nmax - w[k]));
-            if (nmin < w[k]) phi = fmin(phi, (wmin[k] - w[k]) / (nmin - w[k]));
+            if (nmax[k] > w[k]) phi = fmin(phi, (wmax[k] - w[k]) / (nmax[k] - w[k]));
+            if (nmin[k] < w[k]) phi = fmin(phi, (wmin[k] - w[k]) / (nmin[k] - w[k]));
             gx[k] *= phi;
             gy[k] *= phi;
         }
@@ -954,22 +975,25 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
     double nuc = P.nu[c];
-    const Entries E = entries(P, c);
+    for (int b = c; b >= 0;) {
+        const Entries E = entries(P, b);
 #pragma unroll
-    for (int k = 0; k < MAXV; k++) {
-        if (!(E.flag[k] & CF_VALID)) continue;
-        const int f = E.face[k];
-        double sg = (E.flag[k] & CF_OWNER) ? 1.0 : -1.0;
+        for (int k = 0; k < MAXV; k++) {
+            if (!(E.flag[k] & CF_VALID)) continue;
+            const int f = E.face[k];
+            double sg = (E.flag[k] & CF_OWNER) ? 1.0 : -1.0;
 #pragma unroll
-        for (int k = 0; k < 4; k++) m[k] -= sg * P.flux[k * F + f];
-        double S = P.flen[f];
-        ls += P.lam[f] * S;
-        if (ip.sa) {
-            saR += sg * P.saf[f];
-            sagS += sg * P.sag[f];
-            double qc = sg * (w[1] * P.fnx[f] + w[2] * P.fny[f]) / w[0];
-            sad += 0.5 * (qc + fabs(qc)) * S + P.sak[f];
+            for (int k = 0; k < 4; k++) m[k] -= sg * P.flux[k * F + f];
+            double S = P.flen[f];
+            ls += P.lam[f] * S;
+            if (ip.sa) {
+                saR += sg * P.saf[f];
+                sagS += sg * P.sag[f];
+                double qc = sg * (w[1] * P.fnx[f] + w[2] * P.fny[f]) / w[0];
+                sad += 0.5 * (qc + fabs(qc)) * S + P.sak[f];
+            }
         }
+        b = next_block(P, E);
     }
 #pragma unroll
     for (int k = 0; k < 4; k++) P.M[k * N + c] = m[k];
@@ -1204,21 +1228,25 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     double w[5];
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
-    const Entries E = entries(P, c);
+    const Entries E0 = entries(P, c);
     const T odt = T(P.lamc[c]) / cfl;   // Omega / dt_imp with dt_imp = CFL Omega / Lambda_c (Eq.24)
     const T D = odt + T(P.lsum[c]);
     T dws[5], acc[5], t[5];
     if (MODE == SW_FWD || MODE == SW_TOP) {
 #pragma unroll
         for (int k = 0; k < 5; k++) acc[k] = T(P.M[k * N + c]);
+        for (int b = c; b >= 0;) {
+            const Entries E = b == c ? E0 : entries(P, b);
 #pragma unroll
-        for (int k = 0; k < MAXV; k++) {
-            const int j = E.nbr[k], fl = E.flag[k];
-            if (!(fl & CF_VALID) || j < 0 || !(fl & CF_LOWER)) continue;
-            sweep_term(P, ip, W, w, E.face[k], j, fl, dws, t);
+            for (int k = 0; k < MAXV; k++) {
+                const int j = E.nbr[k], fl = E.flag[k];
+                if (!(fl & CF_VALID) || j < 0 || !(fl & CF_LOWER)) continue;
+                sweep_term(P, ip, W, w, E.face[k], j, fl, dws, t);
 #pragma unroll
-            for (int m = 0; m < 4; m++) acc[m] -= t[m];
-            acc[4] += t[4];
+                for (int m = 0; m < 4; m++) acc[m] -= t[m];
+                acc[4] += t[4];
+            }
+            b = next_block(P, E);
         }
         const T iD = T(1) / D;
 #pragma unroll
@@ -1235,13 +1263,17 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     }
 #pragma unroll
     for (int k = 0; k < 5; k++) acc[k] = T(0);
+    for (int b = c; b >= 0;) {
+        const Entries E = b == c ? E0 : entries(P, b);
 #pragma unroll
-    for (int k = 0; k < MAXV; k++) {
-        const int j = E.nbr[k], fl = E.flag[k];
-        if (!(fl & CF_VALID) || (j >= 0 && (fl & CF_LOWER))) continue;
-        sweep_term(P, ip, W, w, E.face[k], j, fl, dws, t);
+        for (int k = 0; k < MAXV; k++) {
+            const int j = E.nbr[k], fl = E.flag[k];
+            if (!(fl & CF_VALID) || (j >= 0 && (fl & CF_LOWER))) continue;
+            sweep_term(P, ip, W, w, E.face[k], j, fl, dws, t);
 #pragma unroll
-        for (int m = 0; m < 5; m++) acc[m] += t[m];
+            for (int m = 0; m < 5; m++) acc[m] += t[m];
+        }
+        b = next_block(P, E);
     }
     T d[5];
     const T iD = T(1) / D;

@@ -1,4 +1,4 @@
-"""Seeded synthetic 2D hybrid meshes (quadrilaterals and triangles).
+"""Seeded synthetic 2D hybrid meshes (triangles, quadrilaterals, polygons).
 
 This module only produces *inputs*: node coordinates, per-cell vertex lists
 and tagged boundary edges, i.e. the three parts of the non-manifold hybrid
@@ -16,6 +16,9 @@ Meshes produced here:
   field.
 * ``random_hybrid``   - small jittered quad/triangle meshes for invariance
   and conservation checks.
+* ``quadtree_box`` / ``cavity_adaptive`` - adaptive quadtree meshes whose
+  hanging nodes make pentagons and hexagons (the paper's adaptive cavity
+  mesh is of this kind).
 * ``colour_order``    - renumbers the cells so that cells of one colour of a
   greedy graph colouring of the cell adjacency are contiguous.  The solver's
   Gauss-Seidel sweeps run in cell-index order, so this numbering decides how
@@ -171,6 +174,164 @@ def cavity(n: int = 100) -> Mesh:
     bt = np.concatenate([np.full(n, WALL), np.full(n, MOVING_WALL), np.full(n, WALL), np.full(n, WALL)])
     meta = dict(kind="cavity", n=n, chord=1.0)
     return _mk_uniform(xy, cells, bn, bt, meta)
+
+
+# ---------------------------------------------------------------------------
+# Adaptive quadtree meshes: quadrilaterals, pentagons and hexagons
+# ---------------------------------------------------------------------------
+
+def quadtree_box(n0: int, levels: int, refine, tags=None, lx: float = 1.0, ly: float = 1.0,
+                 meta=None) -> Mesh:
+    """Quadtree refinement of an n0 x n0 grid on [0,lx]x[0,ly]: a leaf of
+    level l < levels is split into four while refine(xc, yc, h) says so
+    (h = its width), then leaves are split until neighbours differ by at
+    most one level.  Every hanging node is a vertex of the coarser cell, so
+    cells are quadrilaterals with up to one extra node per side (pentagons,
+    hexagons, ...).  Cells are numbered row by row by centroid (y, then x);
+    boundary edges are tagged per side (``tags``: bottom/top/left/right, each
+    a tag or a function of the edge midpoint's coordinate along the side)."""
+    S = 1 << levels                       # finest-grid units per level-0 cell
+    leaves = {(0, i, j) for i in range(n0) for j in range(n0)}
+
+    def split(c):
+        l, i, j = c
+        leaves.discard(c)
+        for a in (0, 1):
+            for b in (0, 1):
+                leaves.add((l + 1, 2 * i + a, 2 * j + b))
+
+    for lev in range(levels):
+        h, hy = lx / (n0 << lev), ly / (n0 << lev)
+        for c in sorted(x for x in leaves if x[0] == lev):
+            l, i, j = c
+            if refine((i + 0.5) * h, (j + 0.5) * hy, h):
+                split(c)
+
+    def covering(l, i, j):
+        """The leaf containing cell (l, i, j) of the full tree, or None if
+        that region is refined further."""
+        while l >= 0:
+            if (l, i, j) in leaves:
+                return (l, i, j)
+            l, i, j = l - 1, i >> 1, j >> 1
+        return None
+
+    changed = True
+    while changed:                         # 2:1 balance across edges
+        changed = False
+        for c in sorted(leaves, key=lambda x: -x[0]):
+            l, i, j = c
+            if c not in leaves:
+                continue
+            for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                ii, jj = i + di, j + dj
+                if not (0 <= ii < n0 << l and 0 <= jj < n0 << l):
+                    continue
+                nb = covering(l, ii, jj)
+                if nb is not None and nb[0] < l - 1:
+                    split(nb)
+                    changed = True
+    # corners on the finest integer grid
+    corner = set()
+    for l, i, j in leaves:
+        w = S >> l
+        for a in (0, 1):
+            for b in (0, 1):
+                corner.add(((i + a) * w, (j + b) * w))
+    ids = {p: k for k, p in enumerate(sorted(corner, key=lambda p: (p[1], p[0])))}
+    hx, hy = lx / (n0 * S), ly / (n0 * S)
+    xy = np.array([[p[0] * hx, p[1] * hy] for p in sorted(ids, key=ids.get)], dtype=np.float64)
+    cells, cent = [], []
+    for l, i, j in leaves:
+        w = S >> l
+        x0, y0, x1, y1 = i * w, j * w, (i + 1) * w, (j + 1) * w
+        ring = []
+        for (ax, ay), (bx, by) in (((x0, y0), (x1, y0)), ((x1, y0), (x1, y1)),
+                                   ((x1, y1), (x0, y1)), ((x0, y1), (x0, y0))):
+            ring.append(ids[(ax, ay)])
+            mid = ((ax + bx) // 2, (ay + by) // 2)
+            if w > 1 and mid in ids:
+                ring.append(ids[mid])
+        cells.append(ring)
+        cent.append(((y0 + y1) * 0.5, (x0 + x1) * 0.5))
+    order = sorted(range(len(cells)), key=lambda k: cent[k])
+    cells = [cells[k] for k in order]
+    # boundary edges: cell edges used once
+    count = {}
+    for ring in cells:
+        for a, b in zip(ring, ring[1:] + ring[:1]):
+            key = (min(a, b), max(a, b))
+            count[key] = count.get(key, 0) + 1
+    tags = {**dict(bottom=WALL, top=WALL, left=WALL, right=WALL), **(tags or {})}
+    bn, bt = [], []
+    for (a, b), n in sorted(count.items()):
+        if n != 1:
+            continue
+        (xa, ya), (xb, yb) = xy[a], xy[b]
+        xm, ym = 0.5 * (xa + xb), 0.5 * (ya + yb)
+        if ya == yb == 0.0:
+            side, t = "bottom", xm
+        elif ya == yb:
+            side, t = "top", xm
+        elif xa == xb == 0.0:
+            side, t = "left", ym
+        else:
+            side, t = "right", ym
+        tg = tags[side]
+        bn.append((a, b))
+        bt.append(int(tg(t)) if callable(tg) else int(tg))
+    meta = dict(meta or {}, kind="quadtree", n0=n0, levels=levels)
+    return _mk(xy, cells, np.array(bn, dtype=np.int64), np.array(bt, dtype=np.int64), meta)
+
+
+def cavity_adaptive(n0: int = 40, levels: int = 2) -> Mesh:
+    """Lid-driven cavity on an adaptive quadtree mesh (the kind the paper
+    refines where gradients and vorticity are large): an n0 x n0 base grid
+    refined once within 0.3 of the walls, and again within 0.06 of the lid,
+    0.2 of the two top corners and 0.03 of every wall; with n0 = 40 that is
+    8800 cells: 8464 quadrilaterals, 310 pentagons, 26 hexagons.  The lid
+    MOVING_WALL, the rest WALL."""
+    def refine(x, y, h):
+        dwall = min(x, 1.0 - x, y, 1.0 - y)
+        dcorner = min(math.hypot(x, 1.0 - y), math.hypot(1.0 - x, 1.0 - y))
+        if h > 0.75 / n0:             # a base cell
+            return dwall < 0.3
+        return 1.0 - y < 0.06 or dcorner < 0.2 or dwall < 0.03
+    return quadtree_box(n0, levels, refine, tags=dict(top=MOVING_WALL), meta=dict(name="cavity_adaptive"))
+
+
+def random_quadtree(n0: int = 5, levels: int = 2, seed: int = 0, tags=None, warp: float = 0.02) -> Mesh:
+    """Small seeded quadtree mesh for tests: base cells refined at random
+    (the centre cell kept coarse with its four side neighbours refined, so
+    that one cell has eight vertices), then the unit square warped by a
+    smooth map x += warp sin(2 pi y), y += warp sin(2 pi x) so no two faces
+    are parallel by construction.  Quadrilaterals and polygons up to eight
+    vertices."""
+    rng = np.random.default_rng(seed)
+    c0 = n0 // 2
+    forced = {(c0 + 1, c0), (c0 - 1, c0), (c0, c0 + 1), (c0, c0 - 1)}
+    draws = {}
+
+    def refine(x, y, h):
+        i, j = int(x / h), int(y / h)
+        if abs(h - 1.0 / n0) < 1e-12:
+            if (i, j) == (c0, c0):
+                return False
+            if (i, j) in forced:
+                return True
+        if abs(h - 0.5 / n0) < 1e-12 and (i // 2, j // 2) in forced:
+            return False            # keeps the centre cell's neighbours one level finer, not two
+        key = (round(h, 12), i, j)
+        if key not in draws:
+            draws[key] = rng.uniform() < 0.35
+        return draws[key]
+
+    m = quadtree_box(n0, levels, refine, tags=tags)
+    x, y = m.xy[:, 0].copy(), m.xy[:, 1].copy()
+    m.xy[:, 0] = x + warp * np.sin(2 * np.pi * y)
+    m.xy[:, 1] = y + warp * np.sin(2 * np.pi * x)
+    m.meta.update(kind="random_quadtree", seed=seed)
+    return m
 
 
 # ---------------------------------------------------------------------------

@@ -73,11 +73,12 @@ def broken_meshes():
     b = m.copy(); b.bface_nodes = np.concatenate([b.bface_nodes, [shared]]); \
         b.bface_tag = np.concatenate([b.bface_tag, [mg.WALL]])
     out["tagged interior edge"] = b
-    # a pentagon
-    xy = np.array([[0, 0], [1, 0], [1.3, 0.8], [0.5, 1.3], [-0.3, 0.8]], float)
-    out["five nodes"] = mg.Mesh(xy=xy, cell_ptr=np.array([0, 5], np.int32), cell_nodes=np.arange(5, dtype=np.int32),
-                                bface_nodes=np.array([[k, (k + 1) % 5] for k in range(5)], np.int32),
-                                bface_tag=np.full(5, mg.FREESTREAM, np.int32), meta={})
+    # a nonagon (the library takes up to eight vertices)
+    t = 2 * np.pi * np.arange(9) / 9
+    xy = np.stack([np.cos(t), np.sin(t)], 1)
+    out["nine nodes"] = mg.Mesh(xy=xy, cell_ptr=np.array([0, 9], np.int32), cell_nodes=np.arange(9, dtype=np.int32),
+                                bface_nodes=np.array([[k, (k + 1) % 9] for k in range(9)], np.int32),
+                                bface_tag=np.full(9, mg.FREESTREAM, np.int32), meta={})
     # a zero-area triangle
     xy = np.array([[0, 0], [1, 0], [2, 0]], float)
     out["degenerate"] = mg.Mesh(xy=xy, cell_ptr=np.array([0, 3], np.int32), cell_nodes=np.arange(3, dtype=np.int32),
@@ -107,7 +108,7 @@ def test_mesh_validation_matches_oracle(name):
         assert info(ctx)[0] == igks.IGKS_EINVAL
     finally:
         igks.igks_destroy(ctx)
-    if name != "five nodes":      # the oracle takes any polygon; the library is limited to Sec. 2.4's cells
+    if name != "nine nodes":      # the oracle takes any polygon; the library up to eight vertices
         with pytest.raises(po.OracleError):
             po.Oracle(mesh)
 
@@ -117,6 +118,8 @@ def test_mesh_validation_matches_oracle(name):
     lambda: mg.colour_order(mg.random_hybrid(9, 6, seed=2, tags=dict(bottom=mg.WALL)))[0],
     lambda: mg.flat_plate(16, 8),
     lambda: mg.colour_order(mg.flat_plate(12, 6))[0],
+    lambda: mg.random_quadtree(5, 2, seed=1, tags=dict(top=mg.MOVING_WALL)),
+    lambda: mg.colour_order(mg.random_quadtree(6, 2, seed=2))[0],
 ])
 def test_counts_and_wavefronts(make):
     mesh = make()

@@ -30,12 +30,31 @@ def smooth_state(o, amp=0.05, seed=0):
     return W
 
 
-def test_geometry_closed_cells_and_area():
-    m = mg.random_hybrid(7, 5, seed=11)
+def polygon_mesh(seed, tags=None):
+    """Warped quadtree mesh: quadrilaterals and polygons of 5 to 8 vertices
+    (free-stream boundaries unless tagged otherwise)."""
+    free = dict(bottom=mg.FREESTREAM, top=mg.FREESTREAM, left=mg.FREESTREAM, right=mg.FREESTREAM)
+    return mg.random_quadtree(5, 2, seed=seed, tags={**free, **(tags or {})})
+
+
+def shoelace(m):
+    out = np.empty(m.n_cells)
+    for i, nodes in enumerate(m.cells_as_lists()):
+        x, y = m.xy[nodes, 0], m.xy[nodes, 1]
+        out[i] = 0.5 * abs(np.dot(x, np.roll(y, -1)) - np.dot(np.roll(x, -1), y))
+    return out
+
+
+@pytest.mark.parametrize("kind", ["hybrid", "polygon"])
+def test_geometry_closed_cells_and_area(kind):
+    m = mg.random_hybrid(7, 5, seed=11) if kind == "hybrid" else polygon_mesh(11)
     o = po.Oracle(m)
     f = o.faces()
     c = o.cells()
-    assert c["area"].sum() == pytest.approx(1.0 * 0.75, rel=1e-13)
+    assert np.allclose(c["area"], shoelace(m), rtol=1e-13)
+    if kind == "hybrid":
+        assert c["area"].sum() == pytest.approx(1.0 * 0.75, rel=1e-13)
+    assert o.nf == sum(len(x) for x in m.cells_as_lists()) - (sum(len(x) for x in m.cells_as_lists()) - m.n_bfaces) // 2
     s = np.zeros((o.n, 2))
     for k in range(o.nf):
         v = np.array([f["nx"][k], f["ny"][k]]) * f["len"][k]
@@ -70,8 +89,8 @@ def test_mesh_errors():
 def test_freestream_preservation(alpha):
     """A uniform state is an exact steady solution on any mesh: gradients
     vanish and the face fluxes of every closed cell cancel."""
-    for seed in (1, 2):
-        m = mg.random_hybrid(9, 7, seed=seed, jitter=0.3)
+    for m in (mg.random_hybrid(9, 7, seed=1, jitter=0.3), mg.random_hybrid(9, 7, seed=2, jitter=0.3),
+              polygon_mesh(3)):
         o = po.Oracle(m)
         o.set_freestream(0.4, alpha, 2e3)
         M, G = o.compute_residual()
@@ -90,10 +109,11 @@ def test_slip_wall_and_outflow_preserve_uniform_flow():
     assert np.all(np.abs(M[:4]) <= 1e-13 * G)
 
 
-def test_conservation():
+@pytest.mark.parametrize("kind", ["hybrid", "polygon"])
+def test_conservation(kind):
     """Interior face fluxes telescope: sum_i M_i + sum_boundary F S = 0."""
     tags = dict(bottom=mg.WALL, top=mg.OUTFLOW, left=mg.FREESTREAM, right=mg.SYMMETRY)
-    m = mg.random_hybrid(9, 6, seed=5, tags=tags)
+    m = mg.random_hybrid(9, 6, seed=5, tags=tags) if kind == "hybrid" else polygon_mesh(5, tags)
     o = po.Oracle(m, limiter=1)
     o.set_freestream(0.5, 10.0, 500.0, 3.0)
     o.set_state(smooth_state(o, 0.08, 1))
@@ -455,10 +475,11 @@ def test_ghost_states():
     assert lam_b == pytest.approx(lam, rel=1e-13)
 
 
-def test_ls_gradient_exact_for_linear_fields():
+@pytest.mark.parametrize("kind", ["hybrid", "polygon"])
+def test_ls_gradient_exact_for_linear_fields(kind):
     """Eq.6-7: the least-squares gradient of a linear field is exact on
     every interior cell."""
-    m = mg.random_hybrid(8, 6, seed=12, jitter=0.3)
+    m = mg.random_hybrid(8, 6, seed=12, jitter=0.3) if kind == "hybrid" else polygon_mesh(12)
     o = po.Oracle(m)
     o.set_freestream(0.3, 0.0, 1e3)
     W = o.get_state(); c = o.cells()
@@ -476,10 +497,12 @@ def test_ls_gradient_exact_for_linear_fields():
         assert np.allclose(g[4 + k, interior], gy[k], rtol=1e-10, atol=1e-13)
 
 
-def test_limiter_bounds_vertex_values():
+@pytest.mark.parametrize("kind", ["hybrid", "polygon"])
+def test_limiter_bounds_vertex_values(kind):
     """Eq.9-10: with the limiter on, the reconstruction at every vertex of a
-    cell stays inside the min/max of the cell and its face neighbours."""
-    m = mg.random_hybrid(8, 6, seed=13, jitter=0.3)
+    cell stays inside the min/max of the cell and its face neighbours
+    (polygons: all of their up to eight vertices)."""
+    m = mg.random_hybrid(8, 6, seed=13, jitter=0.3) if kind == "hybrid" else polygon_mesh(13)
     o = po.Oracle(m, limiter=1)
     o.set_freestream(0.3, 0.0, 1e3)
     W = smooth_state(o, 0.2, 6)
