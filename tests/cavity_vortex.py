@@ -17,6 +17,10 @@ from scipy.interpolate import RegularGridInterpolator
 TABLE1 = dict(omega=2.0861, psi=-0.1178, x=0.5335, y=0.5681,
               psi_l=2.2461e-4, x_l=0.0820, y_l=0.0716,
               psi_r=1.7123e-3, x_r=0.8720, y_r=0.1132)
+# Table 1, unstructured-mesh row (the adaptive 8933-cell polygon mesh)
+TABLE1_UNSTRUCTURED = dict(omega=2.0902, psi=-0.1179, x=0.5405, y=0.5721,
+                           psi_l=2.2870e-4, x_l=0.0899, y_l=0.0862,
+                           psi_r=1.7289e-3, x_r=0.8752, y_r=0.1145)
 
 
 def fields(W, n):
@@ -60,17 +64,36 @@ def table(W, n):
                 psi_r=r[0], x_r=r[1], y_r=r[2])
 
 
-def check_table1(t, h):
+def resample(W, xc, yc, n=100):
+    """Cell-centre velocities of any mesh of the unit square, interpolated
+    linearly (nearest value outside the centroids' hull) to the cell centres
+    of an n x n grid, as a state (rho = 1) that table() reads."""
+    from scipy.interpolate import griddata
+    x = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    pts = np.stack([xc, yc], 1)
+    out = np.zeros((5, n * n))
+    out[0] = 1.0
+    for k in (1, 2):
+        u = W[k] / W[0]
+        g = griddata(pts, u, (X, Y), method="linear")
+        gn = griddata(pts, u, (X, Y), method="nearest")
+        out[k] = np.where(np.isnan(g), gn, g).ravel()
+    return out
+
+
+def check_table1(t, h, ref=None, omega_tol=0.02):
     """Table 1 pins: primary psi and omega within 2 % (the paper's own
     differences from the reference solutions it lists reach 2.0 %, and a
     second-order solution at Ma 0.17 carries O(h^2) and O(Ma^2) errors of
     that size), secondary psi within 5 %, every centre within one cell
     width h.  Returns the list of failures."""
+    ref = TABLE1 if ref is None else ref
     bad = []
-    for k, tol in (("omega", 0.02), ("psi", 0.02), ("psi_l", 0.05), ("psi_r", 0.05)):
-        if abs(t[k] - TABLE1[k]) > tol * abs(TABLE1[k]):
-            bad.append((k, t[k], TABLE1[k]))
+    for k, tol in (("omega", omega_tol), ("psi", 0.02), ("psi_l", 0.05), ("psi_r", 0.05)):
+        if abs(t[k] - ref[k]) > tol * abs(ref[k]):
+            bad.append((k, t[k], ref[k]))
     for k in ("x", "y", "x_l", "y_l", "x_r", "y_r"):
-        if abs(t[k] - TABLE1[k]) > h:
-            bad.append((k, t[k], TABLE1[k]))
+        if abs(t[k] - ref[k]) > h:
+            bad.append((k, t[k], ref[k]))
     return bad
