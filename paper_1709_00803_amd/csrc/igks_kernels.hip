@@ -560,9 +560,9 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
     double lc = 0.0, b1[4] = {0, 0, 0, 0}, b2[4] = {0, 0, 0, 0}, wmax[4], wmin[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) wmax[k] = wmin[k] = w[k];
-    int ovf = -1;   // a polygon's overflow block
-    for (int b = c; b >= 0;) {
-        const Entries E = entries(P, b);
+    // the cell's block, then a polygon's overflow block (a rarely taken branch,
+    // so triangles and quadrilaterals run straight-line code)
+    auto block = [&](const Entries &E, int b) {
 #pragma unroll
         for (int k = 0; k < MAXV; k++) {
             if (!(E.flag[k] & CF_VALID)) continue;
@@ -586,9 +586,11 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
                 wmin[k] = fmin(wmin[k], wj[k]);
             }
         }
-        b = next_block(P, E);
-        if (b >= 0) ovf = b;
-    }
+    };
+    const Entries E0 = entries(P, c);
+    block(E0, c);
+    const int ovf = next_block(P, E0);   // a polygon's overflow block, or -1
+    if (ovf >= 0) block(entries(P, ovf), ovf);
     P.lamc[c] = lc;
     double L11 = P.lsinv[c], L12 = P.lsinv[N + c], L22 = P.lsinv[2 * N + c];
     double gx[4], gy[4];
@@ -715,19 +717,30 @@ __device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &i
     // so is an isothermal static wall (u_w = 0): the reflected states let no
     // mass or energy through, the heat flux is added in wall_face_terms
     const bool moving = bc == BC_MOVING_WALL || (bc == BC_WALL && ip.tw > 0.0);
-    double WMo[4], wmo[4];
-#pragma unroll
-    for (int k = 0; k < 4; k++) { WMo[k] = WM[k]; wmo[k] = wm[k]; }
+    auto rot = [&](const double *src, double *dst) {
+        dst[0] = src[0];
+        dst[1] = src[1] * nx + src[2] * ny;
+        dst[2] = src[1] * tx + src[2] * ty;
+        dst[3] = src[3];
+    };
+    // face-frame states: the side's own, or the owner's for a wall-frame face
+    // (reflected below); otherwise the boundary map of the reconstructed
+    // interior face state and of the interior cell centre
+    if (!ghost_side || moving) {
+        rot(WM, o.fw);
+        rot(wm, o.fwc);
+    }
     if (ghost_side) {
-        // boundary map of the reconstructed interior face state; the
-        // cell-centre ghost value from the interior cell centre
-        double tmp[5] = {WM[0], WM[1], WM[2], WM[3], wm[4]}, out[5], wg[5];
-        ghost(ip, bc, tmp, nx, ny, out);
+        double wg[5];
+        if (!moving) {
+            double tmp[5] = {WM[0], WM[1], WM[2], WM[3], wm[4]}, out[5];
+            ghost(ip, bc, tmp, nx, ny, out);
+            rot(out, o.fw);
+        }
         ghost(ip, bc, wm, nx, ny, wg);
 #pragma unroll
-        for (int k = 0; k < 4; k++) WM[k] = out[k];
-#pragma unroll
         for (int k = 0; k < 5; k++) wm[k] = wg[k];
+        if (!moving) rot(wm, o.fwc);
     }
     {
         o.q = (wm[1] * nx + wm[2] * ny) / wm[0];
@@ -740,14 +753,6 @@ __device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &i
         o.nu = mu / wm[0];
         o.nut = wm[4];
     }
-    auto rot = [&](const double *src, double *dst) {
-        dst[0] = src[0];
-        dst[1] = src[1] * nx + src[2] * ny;
-        dst[2] = src[1] * tx + src[2] * ty;
-        dst[3] = src[3];
-    };
-    rot(moving ? WMo : WM, o.fw);
-    rot(moving ? wmo : wm, o.fwc);
     {
         double tn[4], tt[4];
 #pragma unroll
@@ -815,31 +820,6 @@ __device__ __forceinline__ void face_implicit_terms(const Params<T> &P, const In
     }
 }
 
-// Wall faces, on the face-frame flux integrated over [0, dt]: an isothermal
-// wall adds the heat flux mu c_p (T_c - T_w) / d_l of the BGK model (Pr = 1,
-// c_p = gamma / (gamma - 1) in units of R) from the owner's cell centre; a
-// moving wall's flux goes from the wall's frame back to the mesh frame.
-template <typename T>
-__device__ __forceinline__ void wall_face_terms(const Params<T> &P, const InstParam &ip, const double *W, int f,
-                                                double dt, double *Fr)
-{
-    if (P.fr[f] >= 0) return;
-    const int bc = P.fbc[f];
-    if (bc != BC_WALL && bc != BC_MOVING_WALL) return;
-    if (ip.tw > 0.0) {
-        const int N = P.nc, l = P.fl[f];
-        const double wc[4] = {W[l], W[N + l], W[2 * N + l], W[3 * N + l]};
-        const double lc = lam_of(wc);
-        const double kappa = mu_lam(P.mu_law, ip, lc) * (GAMMA / (GAMMA - 1.0));
-        Fr[3] += dt * kappa * (0.5 / lc - ip.tw) / P.fdl[f];
-    }
-    if (bc == BC_MOVING_WALL) {
-        const double uw = wall_speed(ip, P.fnx[f], P.fny[f]);
-        Fr[3] += uw * Fr[2] + 0.5 * uw * uw * Fr[0];
-        Fr[2] += uw * Fr[0];
-    }
-}
-
 // face-frame flux integrated over [0, dt] -> F S / dt in the global frame
 __device__ __forceinline__ void flux_global(const double *Fr, double dt, double nx, double ny, double S, double *g)
 {
@@ -881,7 +861,6 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, d
     }
     double Fr[4], g[4];
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
-    wall_face_terms(P, ip, W, f, dt, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
 #pragma unroll
     for (int k = 0; k < 4; k++) P.flux[k * F + f] = g[k];
@@ -923,7 +902,6 @@ __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int si
     }
     double Fr[4], g[4];
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
-    wall_face_terms(P, ip, W, f, dt, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
     // each lane writes two of the four components
     P.flux[(2 * side) * F + f] = side ? g[2] : g[0];
@@ -961,6 +939,33 @@ __global__ __launch_bounds__(256) void k_flux2(Params<T> P)
     flux_face_pair(P, f, side, inst, dt);
 }
 
+// The flux of a no-slip wall face as stored by the flux kernels (g = F S in
+// the global frame) completed here, where the cell's state is at hand: a
+// moving wall's flux goes from the wall's frame back to the mesh frame
+// (F_E += u_w F_t + u_w^2 F_rho / 2, F_t += u_w F_rho), and an isothermal
+// wall adds the heat flux mu c_p (T_c - T_w) / d_l S of the BGK model
+// (Pr = 1, c_p = gamma / (gamma - 1) in units of R).  Kept out of the flux
+// kernels, whose register budget sets their occupancy.
+template <typename T>
+__device__ __forceinline__ void wall_face_terms(const Params<T> &P, const InstParam &ip, const double *w, int f,
+                                                double *g)
+{
+    const int bc = P.fbc[f];
+    if (bc != BC_WALL && bc != BC_MOVING_WALL) return;
+    if (bc == BC_MOVING_WALL) {
+        const double nx = P.fnx[f], ny = P.fny[f], uw = wall_speed(ip, nx, ny);
+        const double ft = -g[1] * ny + g[2] * nx;
+        g[3] += uw * ft + 0.5 * uw * uw * g[0];
+        g[1] += uw * g[0] * (-ny);
+        g[2] += uw * g[0] * nx;
+    }
+    if (ip.tw > 0.0) {
+        const double lc = lam_of(w);
+        const double kappa = mu_lam(P.mu_law, ip, lc) * (GAMMA / (GAMMA - 1.0));
+        g[3] += kappa * (0.5 / lc - ip.tw) / P.fdl[f] * P.flen[f];
+    }
+}
+
 // Per cell: residual M (Eq.16) as the signed sum of its face fluxes, the
 // LU-SGS diagonal pieces, the SA residual and diagonal (Eq.27-32), the
 // squares for the L2 norms and the max norm.
@@ -975,15 +980,18 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
     double nuc = P.nu[c];
-    for (int b = c; b >= 0;) {
-        const Entries E = entries(P, b);
+    auto block = [&](const Entries &E) {
 #pragma unroll
         for (int k = 0; k < MAXV; k++) {
             if (!(E.flag[k] & CF_VALID)) continue;
             const int f = E.face[k];
             double sg = (E.flag[k] & CF_OWNER) ? 1.0 : -1.0;
+            double g[4];
 #pragma unroll
-            for (int k = 0; k < 4; k++) m[k] -= sg * P.flux[k * F + f];
+            for (int k = 0; k < 4; k++) g[k] = P.flux[k * F + f];
+            if (E.nbr[k] < 0) wall_face_terms(P, ip, w, f, g);
+#pragma unroll
+            for (int k = 0; k < 4; k++) m[k] -= sg * g[k];
             double S = P.flen[f];
             ls += P.lam[f] * S;
             if (ip.sa) {
@@ -993,8 +1001,11 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
                 sad += 0.5 * (qc + fabs(qc)) * S + P.sak[f];
             }
         }
-        b = next_block(P, E);
-    }
+    };
+    const Entries E0 = entries(P, c);
+    block(E0);
+    const int ovf = next_block(P, E0);
+    if (ovf >= 0) block(entries(P, ovf));
 #pragma unroll
     for (int k = 0; k < 4; k++) P.M[k * N + c] = m[k];
     P.lsum[c] = 0.5 * ls;
@@ -1229,14 +1240,14 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
     const Entries E0 = entries(P, c);
+    const int ovf = next_block(P, E0);   // a polygon's overflow block, or -1
     const T odt = T(P.lamc[c]) / cfl;   // Omega / dt_imp with dt_imp = CFL Omega / Lambda_c (Eq.24)
     const T D = odt + T(P.lsum[c]);
     T dws[5], acc[5], t[5];
     if (MODE == SW_FWD || MODE == SW_TOP) {
 #pragma unroll
         for (int k = 0; k < 5; k++) acc[k] = T(P.M[k * N + c]);
-        for (int b = c; b >= 0;) {
-            const Entries E = b == c ? E0 : entries(P, b);
+        auto lower = [&](const Entries &E) {
 #pragma unroll
             for (int k = 0; k < MAXV; k++) {
                 const int j = E.nbr[k], fl = E.flag[k];
@@ -1246,8 +1257,9 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
                 for (int m = 0; m < 4; m++) acc[m] -= t[m];
                 acc[4] += t[4];
             }
-            b = next_block(P, E);
-        }
+        };
+        lower(E0);
+        if (ovf >= 0) lower(entries(P, ovf));
         const T iD = T(1) / D;
 #pragma unroll
         for (int k = 0; k < 4; k++) dws[k] = acc[k] * iD;
@@ -1263,8 +1275,7 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     }
 #pragma unroll
     for (int k = 0; k < 5; k++) acc[k] = T(0);
-    for (int b = c; b >= 0;) {
-        const Entries E = b == c ? E0 : entries(P, b);
+    auto upper = [&](const Entries &E) {
 #pragma unroll
         for (int k = 0; k < MAXV; k++) {
             const int j = E.nbr[k], fl = E.flag[k];
@@ -1273,8 +1284,9 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
 #pragma unroll
             for (int m = 0; m < 5; m++) acc[m] += t[m];
         }
-        b = next_block(P, E);
-    }
+    };
+    upper(E0);
+    if (ovf >= 0) upper(entries(P, ovf));
     T d[5];
     const T iD = T(1) / D;
 #pragma unroll
