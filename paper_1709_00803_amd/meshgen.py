@@ -154,6 +154,47 @@ def flat_plate(nx: int = 64, ny: int = 32, x0: float = -0.2, x1: float = 1.0,
     return _mk_uniform(xy, cells, np.concatenate(bn), np.concatenate(bt), meta)
 
 
+def turbulent_plate(nx_front: int = 24, nx_plate: int = 96, ny: int = 64, x0: float = -0.33,
+                    x1: float = 2.0, dx_le: float = 2e-3, dy1: float = 5e-6, height: float = 1.0) -> Mesh:
+    """Stretched quadrilateral mesh for the turbulent flat plate (plate on
+    [0, x1] at y = 0, domain height ``height``): x-nodes clustered
+    geometrically toward the leading edge from both sides (first spacing
+    ``dx_le``), y-nodes from the wall with first spacing ``dy1`` (y+ about 1
+    at Re 5e6 per unit length) growing geometrically to ``height``.  Tags
+    as for flat_plate: left FREESTREAM, bottom SYMMETRY ahead of the plate
+    and WALL on it, top and right OUTFLOW."""
+    gf = _growth_for(dx_le, nx_front, -x0)
+    front = -dx_le * (gf ** np.arange(nx_front + 1) - 1.0) / (gf - 1.0)
+    front[-1] = x0
+    gp = _growth_for(dx_le, nx_plate, x1)
+    plate = dx_le * (gp ** np.arange(nx_plate + 1) - 1.0) / (gp - 1.0)
+    plate[-1] = x1
+    xs = np.concatenate([front[::-1], plate[1:]])
+    gy = _growth_for(dy1, ny, height)
+    ys = dy1 * (gy ** np.arange(ny + 1) - 1.0) / (gy - 1.0)
+    ys[-1] = height
+    nx = len(xs) - 1
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+
+    def nid(i, j):
+        return j * (nx + 1) + i
+
+    I, J = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    I = I.ravel(); J = J.ravel()
+    cells = np.stack([nid(I, J), nid(I + 1, J), nid(I + 1, J + 1), nid(I, J + 1)], axis=1)
+    bn, bt = [], []
+    i = np.arange(nx)
+    xm = 0.5 * (xs[i] + xs[i + 1])
+    bn.append(np.stack([nid(i, 0), nid(i + 1, 0)], 1)); bt.append(np.where(xm > 0.0, WALL, SYMMETRY))
+    bn.append(np.stack([nid(i, ny), nid(i + 1, ny)], 1)); bt.append(np.full(nx, OUTFLOW))
+    j = np.arange(ny)
+    bn.append(np.stack([nid(0, j), nid(0, j + 1)], 1)); bt.append(np.full(ny, FREESTREAM))
+    bn.append(np.stack([nid(nx, j), nid(nx, j + 1)], 1)); bt.append(np.full(ny, OUTFLOW))
+    meta = dict(kind="turbulent_plate", nx=nx, ny=ny, x0=x0, x1=x1, dy1=dy1, chord=1.0)
+    return _mk_uniform(xy, cells, np.concatenate(bn), np.concatenate(bt), meta)
+
+
 def cavity(n: int = 100) -> Mesh:
     """Lid-driven cavity: n x n uniform quadrilaterals on the unit square,
     cells numbered row by row from the bottom; the top edge MOVING_WALL, the
