@@ -91,6 +91,11 @@ typedef struct igks_options {
                            the same ghost plus the Navier-Stokes heat flux of the BGK model,
                            mu c_p (T_c - T_w) / d (Pr = 1, mu at the cell-centre temperature,
                            d the centroid-face distance), treated explicitly */
+    double limiter_freeze; /* with the limiter on: once an instance's density residual has dropped
+                              to this fraction of its first value, its Eq.9 limiter factors are held
+                              at the values of that iteration (near convergence they otherwise
+                              chatter and hold the residual up); 0 = never; in [0, 1).  The hold
+                              ends with igks_set_freestream / igks_set_state. */
 } igks_options;
 
 typedef struct igks_residual {

@@ -52,6 +52,9 @@ typedef struct {
     int scheme;         /* 0: implicit LU-SGS (Eq.18-22); 1: explicit Eq.15 with local time steps */
     double wall_temp;   /* 0: adiabatic no-slip walls (Sec. 2.5); > 0: isothermal walls at this
                            multiple of the free-stream temperature */
+    double limiter_freeze; /* > 0: once the density residual has dropped to this fraction of its
+                              first value, the limiter factors of Eq.9 are held at their values of
+                              that iteration (0: never) */
 } oigks_options;
 
 typedef struct {
@@ -96,6 +99,8 @@ typedef struct oigks_ctx {
     double *D, *Dsa;
     double *dW;                  /* 5 per cell */
     double *Wg;                  /* 5 per face: ghost (cell-centre) state, boundary faces */
+    double *phi;                 /* 4 per cell: the last computed limiter factors */
+    int phi_frozen;              /* the limiter factors are held (limiter_freeze) */
     double dt_flux;
     /* iteration scalars */
     int iter;
@@ -463,18 +468,18 @@ static void free_mesh(oigks_ctx *c)
     void *ps[] = {c->x, c->y, c->cptr, c->cnod, c->fL, c->fR, c->ftag, c->fbc, c->fbidx, c->wall_faces, c->fnx, c->fny, c->flen,
                   c->fxm, c->fym, c->area, c->xc, c->yc, c->dwall, c->cfp, c->cff, c->W, c->M, c->gx,
                   c->gy, c->ugx, c->ugy, c->lamc, c->vort, c->dtimp, c->ff, c->flam, c->D, c->Dsa,
-                  c->dW, c->Wg};
+                  c->dW, c->Wg, c->phi};
     for (size_t i = 0; i < sizeof ps / sizeof ps[0]; i++) free(ps[i]);
     c->x = c->y = NULL; c->cptr = c->cnod = NULL; c->fL = c->fR = c->ftag = c->fbc = c->fbidx = c->wall_faces = NULL;
     c->fnx = c->fny = c->flen = c->fxm = c->fym = NULL; c->area = c->xc = c->yc = c->dwall = NULL;
     c->cfp = c->cff = NULL; c->W = c->M = c->gx = c->gy = c->ugx = c->ugy = NULL;
-    c->lamc = c->vort = c->dtimp = c->ff = c->flam = c->D = c->Dsa = c->dW = c->Wg = NULL;
+    c->lamc = c->vort = c->dtimp = c->ff = c->flam = c->D = c->Dsa = c->dW = c->Wg = c->phi = NULL;
 }
 
 EXPORT void oigks_default_options(oigks_options *o)
 {
     o->limiter = 0; o->cfl_init = 1000.0; o->cfl_min = 1.0; o->cfl_max = 1e6; o->cfl_mode = 0; o->scheme = 0;
-    o->cfl_flux = 1.0; o->visc_sr = 1; o->mu_law = 0; o->wall_temp = 0.0;
+    o->cfl_flux = 1.0; o->visc_sr = 1; o->mu_law = 0; o->wall_temp = 0.0; o->limiter_freeze = 0.0;
 }
 
 EXPORT int oigks_create(oigks_ctx **out, const oigks_options *opt)
@@ -484,6 +489,10 @@ EXPORT int oigks_create(oigks_ctx **out, const oigks_options *opt)
     if (opt) c->opt = *opt; else oigks_default_options(&c->opt);
     *out = c;
     if (!(c->opt.wall_temp >= 0.0) || !isfinite(c->opt.wall_temp)) { seterr(c, "wall_temp must be >= 0"); return -1; }
+    if (!(c->opt.limiter_freeze >= 0.0) || !(c->opt.limiter_freeze < 1.0)) {
+        seterr(c, "limiter_freeze must be in [0, 1)");
+        return -1;
+    }
     return 0;
 }
 EXPORT void oigks_destroy(oigks_ctx *c) { if (c) { free_mesh(c); free(c); } }
@@ -640,6 +649,7 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
     c->ff = calloc(4 * nf, sizeof(double)); c->flam = calloc(nf, sizeof(double));
     c->D = calloc(n_cells, sizeof(double)); c->Dsa = calloc(n_cells, sizeof(double));
     c->dW = calloc(5 * n_cells, sizeof(double)); c->Wg = calloc(5 * nf, sizeof(double));
+    c->phi = calloc(n4, sizeof(double));
     return 0;
 }
 
@@ -761,6 +771,7 @@ EXPORT int oigks_set_freestream(oigks_ctx *c, double mach, double alpha_deg, dou
     }
     for (int i = 0; i < c->nc; i++) for (int k = 0; k < 5; k++) c->W[5 * i + k] = c->Winf[k];
     c->iter = 0; c->cfl = c->opt.cfl_init; c->res_inf_prev = 0.0; c->res0 = 0.0;
+    c->phi_frozen = 0;
     memset(&c->last, 0, sizeof c->last);
     c->have_flow = 1;
     return 0;
@@ -825,7 +836,9 @@ static int residual(oigks_ctx *c)
     for (int i = 0; i < nc; i++) {
         for (int k = 0; k < 4; k++) {
             double phi = 1.0;
-            if (c->opt.limiter) {
+            if (c->opt.limiter && c->phi_frozen) {
+                phi = c->phi[4 * i + k];
+            } else if (c->opt.limiter) {
                 double wc = W[5 * i + k], wmax = wc, wmin = wc;
                 for (int q = c->cfp[i]; q < c->cfp[i + 1]; q++) {
                     int f = c->cff[q];
@@ -843,6 +856,7 @@ static int residual(oigks_ctx *c)
                 }
                 if (nmax > wc) { double r = (wmax - wc) / (nmax - wc); if (r < phi) phi = r; }
                 if (nmin < wc) { double r = (wmin - wc) / (nmin - wc); if (r < phi) phi = r; }
+                c->phi[4 * i + k] = phi;
             }
             c->gx[4 * i + k] = phi * c->ugx[4 * i + k];
             c->gy[4 * i + k] = phi * c->ugy[4 * i + k];
@@ -1190,6 +1204,11 @@ EXPORT int oigks_iterate(oigks_ctx *c, int n, int *n_done)
             c->cfl = cf;
         }
         c->res_inf_prev = inf;
+        /* limiter freezing (reading: the Eq.9 factors chatter between
+         * iterations near convergence and hold the residual up; from the
+         * next iteration on they keep the values just computed) */
+        if (c->opt.limiter && c->opt.limiter_freeze > 0.0 && !c->phi_frozen && l2 <= c->opt.limiter_freeze * c->res0)
+            c->phi_frozen = 1;
         if (c->opt.scheme == 1) {
             /* Eq.15: W^{n+1} = W^n - (1/Omega) sum F S with the flux integrated
              * over a local step dt_i = CFL Omega_i / (Lambda_c)_i (the cell form
@@ -1238,6 +1257,15 @@ EXPORT int oigks_iterate(oigks_ctx *c, int n, int *n_done)
 
 EXPORT int oigks_get_residual(oigks_ctx *c, oigks_residual *out) { *out = c->last; out->iteration = c->iter; return 0; }
 
+/* the last computed (or held) limiter factors, 4 per cell SoA, and whether
+ * they are held */
+EXPORT int oigks_get_limiter(oigks_ctx *c, double *phi, int *frozen)
+{
+    if (phi) for (int i = 0; i < c->nc; i++) for (int k = 0; k < 4; k++) phi[k * c->nc + i] = c->phi[4 * i + k];
+    if (frozen) *frozen = c->phi_frozen;
+    return 0;
+}
+
 /* state in SoA layout, W[k * n_cells + i] */
 EXPORT int oigks_get_state(oigks_ctx *c, double *W)
 {
@@ -1253,6 +1281,7 @@ EXPORT int oigks_set_state(oigks_ctx *c, const double *W)
         if (!(r > 0) || !(p > 0) || !isfinite(W[4 * c->nc + i])) { seterr(c, "non-physical state"); return -4; }
     }
     for (int i = 0; i < c->nc; i++) for (int k = 0; k < 5; k++) c->W[5 * i + k] = W[k * c->nc + i];
+    c->phi_frozen = 0;
     return 0;
 }
 /* Residual of the current state: M (4 flow components, Eq.16) and the SA

@@ -16,7 +16,7 @@ class Options(C.Structure):
     _fields_ = [("limiter", C.c_int), ("cfl_init", C.c_double), ("cfl_min", C.c_double),
                 ("cfl_max", C.c_double), ("cfl_mode", C.c_int), ("cfl_flux", C.c_double),
                 ("visc_sr", C.c_int), ("mu_law", C.c_int), ("scheme", C.c_int),
-                ("wall_temp", C.c_double)]
+                ("wall_temp", C.c_double), ("limiter_freeze", C.c_double)]
 
 
 class Residual(C.Structure):
@@ -46,6 +46,7 @@ def lib():
         L.oigks_set_freestream.argtypes = [p, d, d, d, d]
         L.oigks_iterate.argtypes = [p, i, C.POINTER(C.c_int)]
         L.oigks_get_residual.argtypes = [p, C.POINTER(Residual)]
+        L.oigks_get_limiter.argtypes = [p, dp, C.POINTER(C.c_int)]
         L.oigks_get_state.argtypes = [p, dp]
         L.oigks_set_state.argtypes = [p, dp]
         L.oigks_compute_residual.argtypes = [p, dp, dp]
@@ -160,6 +161,13 @@ class Oracle:
         dW = np.zeros((5, self.n))
         self._chk(self.L.oigks_lusgs_solve(self.ctx, cfl, dW.ctypes.data_as(C.POINTER(C.c_double))))
         return dW
+
+    def limiter(self):
+        """(phi, frozen): the last computed (or held) Eq.9 factors, 4 x n."""
+        phi = np.zeros((4, self.n))
+        fr = C.c_int()
+        self.L.oigks_get_limiter(self.ctx, phi.ctypes.data_as(C.POINTER(C.c_double)), C.byref(fr))
+        return phi, bool(fr.value)
 
     def wall_loads(self):
         cl, cd = C.c_double(), C.c_double()

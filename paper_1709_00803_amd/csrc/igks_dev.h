@@ -58,7 +58,7 @@ struct InstScalars {
     int ncommit;                            // committed iterations; its parity picks the state buffer
     int bad;                                // the last update produced a non-physical state
     int halt;                               // the instance is frozen (rejected update)
-    int pad;
+    int phi_frozen;                         // limiter factors held (limiter_freeze)
 };
 
 template <typename T>
@@ -66,6 +66,8 @@ struct Params {
     int nc, nf, ninst;
     int limiter, visc_sr, mu_law, cfl_mode;
     double cfl_init, cfl_min, cfl_max, cfl_flux;
+    double limiter_freeze;     // drop at which an instance's limiter factors are held; 0 never
+    double *phi;               // 4 x nc: the last computed limiter factors
     const int *cinst, *finst;  // instance of each cell / face
     const InstParam *ip;
     InstScalars *is;

@@ -60,7 +60,7 @@ struct Buf {
 constexpr int NKT = 6;
 
 struct WsMap {
-    Buf ip, is, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx;
+    Buf ip, is, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx, phi;
     Buf cinst, finst, icell, ioff, g2i, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
     Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, sak, ipart, hist, ipos;
     Buf wall_faces, wall_out, woff, wseg, lev_off, stage, backup;
@@ -455,6 +455,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.is = L.add(NI * sizeof(InstScalars));
     w.Wa = L.add(5 * N * D); w.Wb = L.add(5 * N * D);
     w.grad = L.add(8 * N * D); w.lamc = L.add(N * D); w.vort = L.add(N * D); w.nu = L.add(N * D);
+    w.phi = L.add(4 * N * D);
     w.M = L.add(5 * N * D); w.lsum = L.add(N * D); w.sadiag = L.add(N * D); w.r2 = L.add(2 * N * D);
     w.dW = L.add(5 * N * (o.precision == IGKS_MIXED ? sizeof(float) : D));
     w.xc = L.add(N * D); w.yc = L.add(N * D); w.area = L.add(N * D); w.lsinv = L.add(3 * N * D);
@@ -496,6 +497,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.limiter = c->opt.limiter; P.visc_sr = c->opt.visc_sr; P.mu_law = c->opt.mu_law;
     P.cfl_mode = c->opt.scheme == 1 ? 1 : c->opt.cfl_mode;   // the explicit scheme keeps its CFL
     P.cfl_init = c->opt.cfl_init; P.cfl_min = c->opt.cfl_min; P.cfl_max = c->opt.cfl_max; P.cfl_flux = c->opt.cfl_flux;
+    P.limiter_freeze = c->opt.limiter_freeze; P.phi = D(w.phi);
     P.cinst = In(w.cinst); P.finst = In(w.finst);
     P.ip = (const InstParam *)(b + w.ip.off);
     P.is = (InstScalars *)(b + w.is.off);
@@ -790,6 +792,7 @@ void igks_default_options(igks_options *o)
     o->flux_lanes = 0;
     o->scheme = 0;
     o->wall_temp = 0.0;
+    o->limiter_freeze = 0.0;
 }
 
 int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream, int32_t n_inst)
@@ -807,6 +810,7 @@ int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream,
     if (c->opt.flux_lanes < 0 || c->opt.flux_lanes > 2) { delete c; return IGKS_EINVAL; }
     if (c->opt.scheme < 0 || c->opt.scheme > 1) { delete c; return IGKS_EINVAL; }
     if (!(c->opt.wall_temp >= 0.0) || !std::isfinite(c->opt.wall_temp)) { delete c; return IGKS_EINVAL; }
+    if (!(c->opt.limiter_freeze >= 0.0) || !(c->opt.limiter_freeze < 1.0)) { delete c; return IGKS_EINVAL; }
     for (int k = 0; k < NCLASS; k++) c->block[k] = c->opt.block;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;

@@ -602,7 +602,14 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
     double dUdy = (gy[1] - U * gy[0]) / r;
     double dVdx = (gx[2] - V * gx[0]) / r;
     P.vort[c] = fabs(dVdx - dUdy);
-    if (P.limiter) {
+    if (P.limiter && P.is[inst].phi_frozen) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const double phi = P.phi[k * N + c];
+            gx[k] *= phi;
+            gy[k] *= phi;
+        }
+    } else if (P.limiter) {
         const int NB = P.nb;
         double nmax[4], nmin[4];
 #pragma unroll
@@ -626,6 +633,7 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
             double phi = 1.0;
             if (nmax[k] > w[k]) phi = fmin(phi, (wmax[k] - w[k]) / (nmax[k] - w[k]));
             if (nmin[k] < w[k]) phi = fmin(phi, (wmin[k] - w[k]) / (nmin[k] - w[k]));
+            P.phi[k * N + c] = phi;
             gx[k] *= phi;
             gy[k] *= phi;
         }
@@ -1077,6 +1085,8 @@ __global__ __launch_bounds__(64) void k_reduce(Params<T> P, int it)
         s->cfl = cf;
     }
     s->res_inf_prev = rinf;
+    // limiter freezing: from the next iteration on, the factors just computed
+    if (P.limiter && P.limiter_freeze > 0.0 && !s->phi_frozen && l2 <= P.limiter_freeze * s->res0) s->phi_frozen = 1;
     s->res_l2 = l2;
     s->sa_l2 = sal2;
     s->res_inf = rinf;

@@ -52,7 +52,7 @@ def smooth_state(W, xc, yc, amp, seed):
 def pair(igks, mesh, flow, **opt):
     o = po.Oracle(mesh, **{k: v for k, v in opt.items() if k in ("limiter", "cfl_init", "cfl_mode", "cfl_flux",
                                                                    "visc_sr", "mu_law", "cfl_min", "cfl_max",
-                                                                   "scheme", "wall_temp")})
+                                                                   "scheme", "wall_temp", "limiter_freeze")})
     o.set_freestream(*flow)
     g = igks.Solver(mesh, **opt)
     g.set_freestream(*flow)
@@ -142,6 +142,26 @@ def test_trajectory_parity(igks, sa, limiter):
         assert abs(rg["cfl"] - ro["cfl"]) <= 1e-8 * ro["cfl"]
         assert abs(rg["res_l2"] - ro["res_l2"]) <= 1e-8 * ro["res_l2"]
         assert abs(rg["dt_flux"] - ro["dt_flux"]) <= 1e-12 * ro["dt_flux"]
+
+
+def test_limiter_freeze_trajectory_parity(igks):
+    """With the limiter held from the iteration where the density residual
+    reaches 0.2 of its first value, GPU and oracle iterates stay together
+    across that iteration."""
+    m = mg.random_hybrid(12, 8, seed=21, tags=TAGS_SYM, jitter=0.25)
+    o, g = pair(igks, m, (0.5, 3.0, 2e3, -1.0), limiter=1, cfl_init=5.0, chunk=5, limiter_freeze=0.2)
+    for step in range(5):
+        o.iterate(5)
+        g.iterate(5)
+        Wo, Wg = o.get_state(), g.get_state()
+        scale = np.abs(Wo[:4]).max(axis=1, keepdims=True)
+        err = (np.abs(Wg[:4] - Wo[:4]) / scale).max()
+        ro, rg = o.residual(), g.residual()
+        say(f"[limiter freeze] it={5 * (step + 1)} frozen={o.limiter()[1]} state err={err:.3e} "
+            f"drop o={ro['res_drop']:.4e} g={rg['res_drop']:.4e}")
+        assert err <= 1e-9
+        assert abs(rg["res_l2"] - ro["res_l2"]) <= 1e-8 * ro["res_l2"]
+    assert o.limiter()[1]
 
 
 @pytest.mark.parametrize("sa", [False, True])

@@ -234,6 +234,37 @@ def test_isothermal_box_at_wall_temperature_is_steady():
             assert M[3].sum() < 0
 
 
+def test_limiter_freeze_holds_the_factors():
+    """limiter_freeze: the run is the limited run until the density residual
+    has dropped to the threshold; from the next iteration on the Eq.9
+    factors keep the values of that iteration while the state moves on."""
+    tags = dict(bottom=lambda x: np.where(x < 0.3, mg.SYMMETRY, mg.WALL), top=mg.OUTFLOW, left=mg.FREESTREAM,
+                right=mg.OUTFLOW)
+    m = mg.random_hybrid(12, 8, seed=21, tags=tags, jitter=0.25)
+    a = po.Oracle(m, limiter=1, cfl_init=5.0, limiter_freeze=0.2)
+    b = po.Oracle(m, limiter=1, cfl_init=5.0)
+    for o in (a, b):
+        o.set_freestream(0.5, 3.0, 2e3)
+    held = None
+    for it in range(25):
+        a.iterate(1)
+        b.iterate(1)
+        pa, fa = a.limiter()
+        pb, _ = b.limiter()
+        if held is None:
+            assert np.array_equal(a.get_state(), b.get_state()) and np.array_equal(pa, pb)
+            if fa:
+                assert a.residual()["res_drop"] <= 0.2
+                held = pa.copy()
+        else:
+            assert fa and np.array_equal(pa, held)
+            assert not np.array_equal(a.get_state(), b.get_state())
+    assert held is not None and (held < 1).any()
+    assert not np.array_equal(b.limiter()[0], held)        # the factors of the limited run moved on
+    a.set_state(a.get_state())
+    assert not a.limiter()[1]                               # a new state ends the hold
+
+
 def _rotate_state(W, th, mirror=False):
     W = W.copy()
     if mirror:
