@@ -147,6 +147,31 @@ def time_to_converge_cavity(igks, mg, max_it=20000, chunk=200):
                 paper_iterations=4430, paper_seconds=543.2)
 
 
+def time_to_converge_turbulent_plate(igks, mg, max_it=30000, chunk=500):
+    """The turbulent flat plate (SA, Ma 0.2, Re 5e6 per unit length, 7680
+    cells, natural order) from the free stream at CFL 10 growing by Eq.25,
+    to the paper's criterion Eq.40 <= 3e-8."""
+    import torch
+    m = mg.turbulent_plate()
+    s = igks.Solver(m, cfl_init=10.0, chunk=chunk)
+    s.set_freestream(0.2, 0.0, 5e6, 3.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = 0
+    while it < max_it:
+        s.iterate(chunk)
+        it += chunk
+        if s.residual()["eq40"] <= 3e-8:
+            break
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = s.residual()
+    return dict(workload="turbulent flat plate: 120x64 quads, y+ ~ 1, Ma 0.2, Re 5e6/unit length, SA, from the free stream",
+                criterion="Eq.40 <= 3e-8", iterations=it, seconds=round(dt, 4), eq40=r["eq40"],
+                drop=r["res_drop"], cd=s.wall_loads()["cd"], ms_per_iteration=round(1e3 * dt / it, 4),
+                paper_iterations=5340, paper_seconds=1087.7)
+
+
 def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000):
     """Eight plate flow conditions (DROP_BATCH) to a `target` drop: one mixed-
     precision batch against the eight FP64 single runs one after another."""
@@ -355,6 +380,7 @@ def main():
                                 "explicit_fp64_cfl0.9": time_to_drop(igks, mg, igks.IGKS_FP64, scheme=1, cfl=0.9,
                                                                      chunk=1000, max_it=400000)}
         out["cavity_to_eq40"] = time_to_converge_cavity(igks, mg)
+        out["turbulent_plate_to_eq40"] = time_to_converge_turbulent_plate(igks, mg)
     if not args.no_cpu:
         out["cpu_baseline"] = run_cpu_baseline(list(zip(meshes, flows))[:4])
     print(json.dumps(out), flush=True)

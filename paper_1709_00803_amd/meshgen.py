@@ -918,7 +918,7 @@ def _first_height(re: float) -> float:
     return float(np.clip(1e-4 * (5000.0 / re) ** 0.75, 1e-6, 1e-3))
 
 
-def batch_instance(b: int, base_seed: int = 1000, n_min: float = 5e3, n_max: float = 2e5):
+def batch_instance(b: int, base_seed: int = 1000, n_min: float = 5e3, n_max: float = 2e5, order: str = "colour"):
     """Instance b of the batched sweep: (mesh, (Ma, alpha_deg, Re, nut_ratio)).
 
     Draws from default_rng(base_seed + b): a target cell count log-uniform in
@@ -926,7 +926,8 @@ def batch_instance(b: int, base_seed: int = 1000, n_min: float = 5e3, n_max: flo
     plates at 0), Re log-uniform in [1e4, 1e7], SA (nu~/nu = 3) iff
     Re > 1e5.  Even b: flat plate (nx = 2 ny quads); odd b: Joukowski hybrid
     (wall points ~0.64 sqrt(N), quad layers ~0.15 sqrt(N) reaching 0.05 chord,
-    triangles for the rest).  Colour-ordered.
+    triangles for the rest).  Colour-ordered, or in generation order with
+    order="natural".
     """
     rng = np.random.default_rng(base_seed + b)
     n = float(np.exp(rng.uniform(math.log(n_min), math.log(n_max))))
@@ -945,12 +946,12 @@ def batch_instance(b: int, base_seed: int = 1000, n_min: float = 5e3, n_max: flo
         nl = max(6, int(round(0.15 * math.sqrt(n))))
         m = joukowski_hybrid(nw, nl, h1, _growth_for(h1, nl, 0.05), seed=base_seed + b,
                              target_cells=int(n))
-    out, _, _ = colour_order(m)
+    out = colour_order(m)[0] if order == "colour" else m
     out.meta.update(batch_index=b, target_cells=int(n))
     return out, (ma, alpha, re, nut)
 
 
-def batch(n_inst: int = 64, base_seed: int = 1000, n_min: float = 5e3, n_max: float = 2e5):
+def batch(n_inst: int = 64, base_seed: int = 1000, n_min: float = 5e3, n_max: float = 2e5, order: str = "colour"):
     """The batched sweep: lists of meshes and flow conditions."""
-    items = [batch_instance(b, base_seed, n_min, n_max) for b in range(n_inst)]
+    items = [batch_instance(b, base_seed, n_min, n_max, order) for b in range(n_inst)]
     return [m for m, _ in items], [f for _, f in items]
