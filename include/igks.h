@@ -96,6 +96,9 @@ typedef struct igks_options {
                               at the values of that iteration (near convergence they otherwise
                               chatter and hold the residual up); 0 = never; in [0, 1).  The hold
                               ends with igks_set_freestream / igks_set_state. */
+    int tau_jump;       /* 1: add dt |p_l - p_r| / (p_l + p_r) (reconstructed face pressures) to the
+                           collision time of Eq.34, the usual gas-kinetic extra dissipation at
+                           discontinuities (not in the paper); 0 (default): Eq.34 as printed */
 } igks_options;
 
 typedef struct igks_residual {

@@ -55,6 +55,7 @@ typedef struct {
     double limiter_freeze; /* > 0: once the density residual has dropped to this fraction of its
                               first value, the limiter factors of Eq.9 are held at their values of
                               that iteration (0: never) */
+    int tau_jump;       /* 1: add dt |p_l - p_r| / (p_l + p_r) to the collision time of Eq.34 */
 } oigks_options;
 
 typedef struct {
@@ -479,7 +480,7 @@ static void free_mesh(oigks_ctx *c)
 EXPORT void oigks_default_options(oigks_options *o)
 {
     o->limiter = 0; o->cfl_init = 1000.0; o->cfl_min = 1.0; o->cfl_max = 1e6; o->cfl_mode = 0; o->scheme = 0;
-    o->cfl_flux = 1.0; o->visc_sr = 1; o->mu_law = 0; o->wall_temp = 0.0; o->limiter_freeze = 0.0;
+    o->cfl_flux = 1.0; o->visc_sr = 1; o->mu_law = 0; o->wall_temp = 0.0; o->limiter_freeze = 0.0; o->tau_jump = 0;
 }
 
 EXPORT int oigks_create(oigks_ctx **out, const oigks_options *opt)
@@ -489,6 +490,7 @@ EXPORT int oigks_create(oigks_ctx **out, const oigks_options *opt)
     if (opt) c->opt = *opt; else oigks_default_options(&c->opt);
     *out = c;
     if (!(c->opt.wall_temp >= 0.0) || !isfinite(c->opt.wall_temp)) { seterr(c, "wall_temp must be >= 0"); return -1; }
+    if (c->opt.tau_jump < 0 || c->opt.tau_jump > 1) { seterr(c, "tau_jump must be 0 or 1"); return -1; }
     if (!(c->opt.limiter_freeze >= 0.0) || !(c->opt.limiter_freeze < 1.0)) {
         seterr(c, "limiter_freeze must be in [0, 1)");
         return -1;
@@ -986,6 +988,14 @@ static int residual(oigks_ctx *c)
         double nutf = 0.5 * (Wi[4] + WjC[4]);
         if (nutf < 0) nutf = 0;
         double tau = collision_time(c, W0[0], lam_of(W0), nutf);
+        if (c->opt.tau_jump) {
+            /* option (not in the paper; the usual gas-kinetic practice for
+             * discontinuities): extra dissipation from the jump of the two
+             * reconstructed pressures across the face */
+            double pl = wl[3] - 0.5 * (wl[1] * wl[1] + wl[2] * wl[2]) / wl[0];
+            double pr = wr[3] - 0.5 * (wr[1] * wr[1] + wr[2] * wr[2]) / wr[0];
+            tau += c->dt_flux * fabs(pl - pr) / (pl + pr);
+        }
         face_detail fd;
         gks_core(wl, gln, glt, wr, grn, grt, wlc, wrc, dl, dr, c->dt_flux, tau, &fd);
         if (j < 0 && c->opt.wall_temp > 0.0 && (c->fbc[f] == BC_WALL || c->fbc[f] == BC_MOVING_WALL)) {

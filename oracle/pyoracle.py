@@ -16,7 +16,8 @@ class Options(C.Structure):
     _fields_ = [("limiter", C.c_int), ("cfl_init", C.c_double), ("cfl_min", C.c_double),
                 ("cfl_max", C.c_double), ("cfl_mode", C.c_int), ("cfl_flux", C.c_double),
                 ("visc_sr", C.c_int), ("mu_law", C.c_int), ("scheme", C.c_int),
-                ("wall_temp", C.c_double), ("limiter_freeze", C.c_double)]
+                ("wall_temp", C.c_double), ("limiter_freeze", C.c_double),
+                ("tau_jump", C.c_int)]
 
 
 class Residual(C.Structure):

@@ -67,6 +67,7 @@ struct Params {
     int limiter, visc_sr, mu_law, cfl_mode;
     double cfl_init, cfl_min, cfl_max, cfl_flux;
     double limiter_freeze;     // drop at which an instance's limiter factors are held; 0 never
+    int tau_jump;              // add dt |p_l - p_r| / (p_l + p_r) to the collision time
     double *phi;               // 4 x nc: the last computed limiter factors
     const int *cinst, *finst;  // instance of each cell / face
     const InstParam *ip;

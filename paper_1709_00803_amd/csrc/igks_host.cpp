@@ -497,7 +497,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.limiter = c->opt.limiter; P.visc_sr = c->opt.visc_sr; P.mu_law = c->opt.mu_law;
     P.cfl_mode = c->opt.scheme == 1 ? 1 : c->opt.cfl_mode;   // the explicit scheme keeps its CFL
     P.cfl_init = c->opt.cfl_init; P.cfl_min = c->opt.cfl_min; P.cfl_max = c->opt.cfl_max; P.cfl_flux = c->opt.cfl_flux;
-    P.limiter_freeze = c->opt.limiter_freeze; P.phi = D(w.phi);
+    P.limiter_freeze = c->opt.limiter_freeze; P.phi = D(w.phi); P.tau_jump = c->opt.tau_jump;
     P.cinst = In(w.cinst); P.finst = In(w.finst);
     P.ip = (const InstParam *)(b + w.ip.off);
     P.is = (InstScalars *)(b + w.is.off);
@@ -793,6 +793,7 @@ void igks_default_options(igks_options *o)
     o->scheme = 0;
     o->wall_temp = 0.0;
     o->limiter_freeze = 0.0;
+    o->tau_jump = 0;
 }
 
 int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream, int32_t n_inst)
@@ -811,6 +812,7 @@ int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream,
     if (c->opt.scheme < 0 || c->opt.scheme > 1) { delete c; return IGKS_EINVAL; }
     if (!(c->opt.wall_temp >= 0.0) || !std::isfinite(c->opt.wall_temp)) { delete c; return IGKS_EINVAL; }
     if (!(c->opt.limiter_freeze >= 0.0) || !(c->opt.limiter_freeze < 1.0)) { delete c; return IGKS_EINVAL; }
+    if (c->opt.tau_jump < 0 || c->opt.tau_jump > 1) { delete c; return IGKS_EINVAL; }
     for (int k = 0; k < NCLASS; k++) c->block[k] = c->opt.block;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;

@@ -430,13 +430,14 @@ struct GksEq {
 };
 template <typename T>
 __device__ __forceinline__ void gks_eq(const Params<T> &P, const InstParam &ip, const double *w0, double dt,
-                                       double nut_f, GksEq &q)
+                                       double nut_f, double jump, GksEq &q)
 {
     q.r0 = w0[0]; q.U0 = w0[1] / q.r0; q.V0 = w0[2] / q.r0; q.lam0 = lam_of(w0);
     q.ir0 = 1.0 / q.r0;
     double mul = mu_lam(P.mu_law, ip, q.lam0), mut = 0.0;
     if (ip.sa && nut_f > 0.0) mut = q.r0 * nut_f * sa_fv1(nut_f * q.r0 / mul);
     double tau = (mul + mut) * 2.0 * q.lam0 / q.r0;
+    if (P.tau_jump) tau += dt * jump;
     double eta = exp(-dt / tau), ome = -expm1(-dt / tau);
     q.T1 = dt - tau * ome;
     q.T2 = -tau * dt * (1.0 + eta) + 2.0 * tau * tau * ome;
@@ -856,8 +857,15 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, d
     side_terms(-1.0, R.fw, R.gn, R.gt, accr);
 #pragma unroll
     for (int k = 0; k < 24; k++) acc[k] = add_sides(acc[k], accr[k]);
+    // optional collision-time term from the pressure jump across the face
+    double jump = 0.0;
+    if (P.tau_jump) {
+        const double pl = L.fw[3] - 0.5 * (L.fw[1] * L.fw[1] + L.fw[2] * L.fw[2]) / L.fw[0];
+        const double pr = R.fw[3] - 0.5 * (R.fw[1] * R.fw[1] + R.fw[2] * R.fw[2]) / R.fw[0];
+        jump = fabs(pl - pr) / (pl + pr);
+    }
     GksEq q;
-    gks_eq(P, ip, acc, dt, nutf, q);
+    gks_eq(P, ip, acc, dt, nutf, jump, q);
     double q2[4], f2[4], q2r[4], f2r[4], gts[4];
     gks_half(q, 1.0, acc, L.fwc, L.d, q2, f2);
     gks_half(q, -1.0, acc, R.fwc, R.d, q2r, f2r);
@@ -898,8 +906,15 @@ __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int si
     side_terms(sgn, M.fw, M.gn, M.gt, acc);
 #pragma unroll
     for (int k = 0; k < 24; k++) acc[k] = add_sides(acc[k], pair_other(acc[k]));
+    double jump = 0.0;
+    if (P.tau_jump) {
+        const double ps = M.fw[3] - 0.5 * (M.fw[1] * M.fw[1] + M.fw[2] * M.fw[2]) / M.fw[0];
+        const double po = pair_other(ps);
+        const double pl = side ? po : ps, pr = side ? ps : po;
+        jump = fabs(pl - pr) / (pl + pr);
+    }
     GksEq q;
-    gks_eq(P, ip, acc, dt, nutf, q);
+    gks_eq(P, ip, acc, dt, nutf, jump, q);
     double q2[4], f2[4], gts[4];
     gks_half(q, sgn, acc, M.fwc, M.d, q2, f2);
 #pragma unroll

@@ -56,3 +56,4 @@ def test_default_options_without_gpu(lib):
     o = igks.default_options()
     assert o.precision == igks.IGKS_FP64 and o.cfl_init == 1000.0 and o.chunk == 20 and o.block == 256
     assert o.sweep == 0 and o.flux_lanes == 0 and o.scheme == 0 and o.wall_temp == 0.0 and o.limiter_freeze == 0.0
+    assert o.tau_jump == 0

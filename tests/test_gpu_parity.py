@@ -52,7 +52,8 @@ def smooth_state(W, xc, yc, amp, seed):
 def pair(igks, mesh, flow, **opt):
     o = po.Oracle(mesh, **{k: v for k, v in opt.items() if k in ("limiter", "cfl_init", "cfl_mode", "cfl_flux",
                                                                    "visc_sr", "mu_law", "cfl_min", "cfl_max",
-                                                                   "scheme", "wall_temp", "limiter_freeze")})
+                                                                   "scheme", "wall_temp", "limiter_freeze",
+                                                                   "tau_jump")})
     o.set_freestream(*flow)
     g = igks.Solver(mesh, **opt)
     g.set_freestream(*flow)
@@ -142,6 +143,26 @@ def test_trajectory_parity(igks, sa, limiter):
         assert abs(rg["cfl"] - ro["cfl"]) <= 1e-8 * ro["cfl"]
         assert abs(rg["res_l2"] - ro["res_l2"]) <= 1e-8 * ro["res_l2"]
         assert abs(rg["dt_flux"] - ro["dt_flux"]) <= 1e-12 * ro["dt_flux"]
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_pressure_jump_tau_parity(igks, lanes):
+    """The optional pressure-jump collision time: residual parity on a
+    perturbed state with both flux kernels, and a few iterations."""
+    m = mg.random_hybrid(10, 8, seed=27, tags=TAGS_ALL, jitter=0.3)
+    tag = f"tau_jump lanes={lanes}"
+    o, g = pair(igks, m, (0.6, 4.0, 5e3, -1.0), tau_jump=1, flux_lanes=lanes, cfl_init=5.0, chunk=5)
+    c = o.cells()
+    W = smooth_state(o.get_state(), c["xc"], c["yc"], 0.1, 27)
+    check_residual(o, g, W, tag)
+    o.set_state(W)
+    g.set_state(W)
+    o.iterate(10)
+    g.iterate(10)
+    Wo, Wg = o.get_state(), g.get_state()
+    err = (np.abs(Wg[:4] - Wo[:4]) / np.abs(Wo[:4]).max(axis=1, keepdims=True)).max()
+    say(f"[{tag}] 10 iterations: state err {err:.3e}")
+    assert err <= 1e-9
 
 
 def test_limiter_freeze_trajectory_parity(igks):

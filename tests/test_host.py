@@ -179,7 +179,7 @@ def test_batch_bookkeeping():
 def test_call_order_and_option_errors():
     for bad in (dict(block=96), dict(block=512), dict(sweep=3), dict(precision=5), dict(chunk=-1),
                 dict(flux_lanes=3), dict(wall_temp=-1.0), dict(wall_temp=float("nan")), dict(limiter_freeze=-0.1),
-                dict(limiter_freeze=1.0)):
+                dict(limiter_freeze=1.0), dict(tau_jump=2)):
         rc, ctx = ctx_for(**bad)
         assert rc == igks.IGKS_EINVAL, bad
         assert not ctx.value

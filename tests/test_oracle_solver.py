@@ -234,6 +234,36 @@ def test_isothermal_box_at_wall_temperature_is_steady():
             assert M[3].sum() < 0
 
 
+def test_pressure_jump_collision_time():
+    """tau_jump adds dissipation only where the reconstructed pressures of a
+    face differ: gas at rest with uniform energy (so uniform pressure in
+    every reconstruction) and a varying density (so a heat-conducting,
+    non-zero residual) in a box of symmetry faces has bitwise the same
+    residual with and without it; a state with pressure variations does
+    not."""
+    tags = dict(bottom=mg.SYMMETRY, top=mg.SYMMETRY, left=mg.SYMMETRY, right=mg.SYMMETRY)
+    m = mg.random_hybrid(9, 7, seed=25, tags=tags, jitter=0.3)
+    a, b = po.Oracle(m), po.Oracle(m, tau_jump=1)
+    for o in (a, b):
+        o.set_freestream(0.4, 5.0, 3e3)
+    c = a.cells()
+    W = a.get_state()
+    W[3] -= 0.5 * (W[1] ** 2 + W[2] ** 2) / W[0]
+    W[1] = W[2] = 0.0
+    W[0] *= 1 + 0.1 * np.sin(3 * c["xc"]) * np.cos(2 * c["yc"])
+    for o in (a, b):
+        o.set_state(W)
+    Ma, G = a.compute_residual()
+    assert np.abs(Ma[3]).max() > 1e-6 * G.max()
+    assert np.array_equal(Ma, b.compute_residual()[0])
+    W2 = smooth_state(a, 0.08, 25)
+    for o in (a, b):
+        o.set_state(W2)
+    Ma, G = a.compute_residual()
+    Mb, _ = b.compute_residual()
+    assert np.abs(Mb[:4] - Ma[:4]).max() > 1e-8 * G.max()
+
+
 def test_limiter_freeze_holds_the_factors():
     """limiter_freeze: the run is the limited run until the density residual
     has dropped to the threshold; from the next iteration on the Eq.9
