@@ -104,7 +104,7 @@ typedef struct igks_options {
 typedef struct igks_residual {
     int32_t iteration;  /* iterations committed so far */
     double res_l2;      /* ||M_rho||_2 of the last residual evaluation (Eq.16) */
-    double res_drop;    /* res_l2 / res_l2 of the first iteration */
+    double res_drop;    /* res_l2 / the largest res_l2 so far */
     double res_inf;     /* max over cells and the 4 flow components of |M| */
     double eq40;        /* max_i ||W_i^{n+1} - W_i^n||_2 / ||W_i^n||_2 (Eq.40) */
     double cfl;         /* implicit CFL used by the last update (Eq.25) */
@@ -117,7 +117,7 @@ typedef struct igks_scalars {
     int32_t iteration;
     double cfl;          /* CFL of the last committed iteration */
     double res_inf_prev; /* ||M||_inf of the last committed iteration */
-    double res0;         /* ||M_rho||_2 of the first iteration */
+    double res0;         /* the largest ||M_rho||_2 so far (the drop's reference) */
 } igks_scalars;
 
 typedef struct igks_ctx igks_ctx;
@@ -125,7 +125,7 @@ typedef struct igks_ctx igks_ctx;
 /* Fill *opt with the defaults: FP64, limiter off, cfl_init 1000 (Sec. 3.1),
  * cfl_min 1, cfl_max 1e6, Eq.25 law, cfl_flux 1, visc_sr on, Sutherland,
  * chunk 20, block 256, sweep auto (one workgroup when the wavefronts are many and
- * narrow: more than 16 of them averaging under 4096 cells), flux_lanes auto. */
+ * narrow: more than 16 of them averaging under 1024 cells), flux_lanes auto. */
 void igks_default_options(igks_options *opt);
 
 /* Create a context.  opt may be NULL (defaults).  hip_stream is a

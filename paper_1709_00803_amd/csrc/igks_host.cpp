@@ -94,6 +94,7 @@ struct igks_ctx {
     std::vector<std::vector<double>> hist;
     // graph of one chunk
     hipGraphExec_t gexec = nullptr;
+    int gexec_k = 0;                   // iterations captured in gexec
     // profiling
     bool profiling = false;
     double ktimes[NKT] = {0, 0, 0, 0, 0, 0};
@@ -119,6 +120,24 @@ void destroy_graph(igks_ctx *c)
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
     }
+    c->gexec_k = 0;
+}
+
+// Iterations per captured graph: the requested chunk, cut so that a graph
+// holds at most MAX_GRAPH_NODES launches (one launch per wavefront and sweep
+// direction makes an iteration of a many-wavefront batch thousands of
+// launches long); 0 = no graphs.
+constexpr int MAX_GRAPH_NODES = 8192;
+int launches_per_iteration(const igks_ctx *c)
+{
+    const int nlev = std::max(1, c->g.nlev);
+    const int sweeps = c->opt.scheme == 1 ? 1 : (c->sweep_wg ? 3 : 2 * nlev - 1);
+    return 6 + sweeps;   // prep, flux, gather, isum, reduce, commit + the update / sweep launches
+}
+int graph_chunk(const igks_ctx *c)
+{
+    if (c->opt.chunk <= 0) return 0;
+    return std::max(1, std::min(c->opt.chunk, MAX_GRAPH_NODES / launches_per_iteration(c)));
 }
 
 // ------------------------------------------------------------------ ingest
@@ -599,7 +618,8 @@ int run_chunk(igks_ctx *c, const Params<T> &P, int k)
             }
         }
         for (auto &e : ev) (void)hipEventDestroy(e);
-    } else if (c->opt.chunk > 0 && k == c->opt.chunk) {
+    } else if (k > 0 && k == graph_chunk(c)) {
+        if (c->gexec && c->gexec_k != k) destroy_graph(c);
         if (!c->gexec) {
             hipGraph_t g;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -611,6 +631,7 @@ int run_chunk(igks_ctx *c, const Params<T> &P, int k)
                 c->gexec = nullptr;
                 return fail(c, IGKS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
             }
+            c->gexec_k = k;
         }
         HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
     } else {
@@ -733,7 +754,8 @@ int iterate_impl(igks_ctx *c, const Params<T> &P, int n, int *n_done)
     const int start0 = c->hs[0].ncommit;
     int executed = 0;
     while (executed < n) {
-        int k = c->opt.chunk > 0 ? std::min(c->opt.chunk, n - executed) : n - executed;
+        const int gc = graph_chunk(c);
+        int k = gc > 0 ? std::min(gc, n - executed) : n - executed;
         if (c->profiling) k = std::min(k, 64);
         int rc = run_chunk(c, P, k);
         if (rc) return rc;
@@ -944,7 +966,9 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     if (rc) return rc;
     {
         double width = (double)G.N / std::max(1, G.nlev);
-        c->sweep_wg = c->opt.sweep == 2 || (c->opt.sweep == 0 && G.nlev > 16 && width < 4096.0);
+        // one workgroup of 512 threads takes a wavefront per round of 512 cells, a launch per
+        // wavefront costs a few microseconds: the workgroup wins up to about two rounds
+        c->sweep_wg = c->opt.sweep == 2 || (c->opt.sweep == 0 && G.nlev > 16 && width < 1024.0);
         // one lane per face leaves SIMDs idle on small meshes; two lanes pay
         // off once a lane per face would already give two waves per SIMD
         c->flux_pair = c->opt.flux_lanes == 2 || (c->opt.flux_lanes == 0 && G.F >= 131072);

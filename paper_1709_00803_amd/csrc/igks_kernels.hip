@@ -1090,8 +1090,9 @@ __global__ __launch_bounds__(64) void k_reduce(Params<T> P, int it)
     if (lane != 0) return;
     double l2 = sqrt(x), sal2 = sqrt(y);
     s->dt = dt;
+    // the drop is measured from the largest ||M_rho||_2 so far
+    if (s->ncommit == 0 || l2 > s->res0) s->res0 = l2;
     if (s->ncommit == 0) {
-        s->res0 = l2;
         s->cfl = P.cfl_init;
     } else if (P.cfl_mode == 0) {
         double cf = s->cfl * s->res_inf_prev / rinf;
