@@ -274,9 +274,10 @@ __device__ __forceinline__ const double *cur_state(const Params<T> &P, int inst)
 // ------------------------------------------------------- kinetic building blocks
 
 // <u^k>, k = 0..7, of the normalised Maxwellian exp(-lam (u-U)^2) on the
-// whole line (S = 0), on u > 0 (S = +1) or on u < 0 (S = -1).
+// whole line (S = 0), on u > 0 (S = +1) or on u < 0 (S = -1); hl = 1/(2 lam)
+// (the moment helpers take it precomputed: one divide per Maxwellian).
 template <int S>
-__device__ __forceinline__ void mom_u(double U, double lam, double *m)
+__device__ __forceinline__ void mom_u(double U, double lam, double hl, double *m)
 {
     if (S == 0) {
         m[0] = 1.0; m[1] = U;
@@ -286,13 +287,12 @@ __device__ __forceinline__ void mom_u(double U, double lam, double *m)
         if (S > 0) { m[0] = 0.5 * erfc(-x); m[1] = U * m[0] + e; }
         else { m[0] = 0.5 * erfc(x); m[1] = U * m[0] - e; }
     }
-    double h = 0.5 / lam;
 #pragma unroll
-    for (int k = 0; k < 6; k++) m[k + 2] = U * m[k + 1] + (k + 1) * h * m[k];
+    for (int k = 0; k < 6; k++) m[k + 2] = U * m[k + 1] + (k + 1) * hl * m[k];
 }
 // The same half-space moments with the half chosen at run time: sgn = +1
 // for u > 0, -1 for u < 0 (the two lanes of a face take opposite halves).
-__device__ __forceinline__ void mom_u_half(double U, double lam, double sgn, double *m)
+__device__ __forceinline__ void mom_u_half(double U, double lam, double hl, double sgn, double *m)
 {
     double x = sqrt(lam) * U;
     double e = exp(-x * x) * (0.5 / sqrt(M_PI * lam));
@@ -301,16 +301,15 @@ __device__ __forceinline__ void mom_u_half(double U, double lam, double sgn, dou
     double es = sgn > 0.0 ? e : -e, xs = sgn > 0.0 ? -x : x;
     m[0] = 0.5 * erfc(xs);
     m[1] = U * m[0] + es;
-    double h = 0.5 / lam;
 #pragma unroll
-    for (int k = 0; k < 6; k++) m[k + 2] = U * m[k + 1] + (k + 1) * h * m[k];
+    for (int k = 0; k < 6; k++) m[k + 2] = U * m[k + 1] + (k + 1) * hl * m[k];
 }
 // <xi^0>, <xi^2>, <xi^4> over K internal dimensions
-__device__ __forceinline__ void mom_xi(double lam, double *x)
+__device__ __forceinline__ void mom_xi(double hl, double *x)
 {
     x[0] = 1.0;
-    x[1] = KDOF / (2.0 * lam);
-    x[2] = x[1] * (KDOF + 2.0) / (2.0 * lam);
+    x[1] = KDOF * hl;
+    x[2] = x[1] * (KDOF + 2.0) * hl;
 }
 
 // out = < u^A v^B (c0 + c1 u + c2 v + c3 (u^2+v^2+xi^2)/2) psi > with
@@ -342,11 +341,11 @@ __device__ __forceinline__ void pmom1(const double *mu, const double *mv, const 
 
 // Closed-form solution of M(g) a = b for the Maxwellian moment matrix
 // M_ij = <psi_i psi_j> (Eq.101 divided by rho).
-__device__ __forceinline__ void msolve(double U, double V, double lam, const double *b, double *a)
+__device__ __forceinline__ void msolve(double U, double V, double lam, double hl, const double *b, double *a)
 {
-    double B = U * U + V * V + (KDOF + 2.0) / (2.0 * lam);
+    double B = U * U + V * V + (KDOF + 2.0) * hl;
     double R2 = b[1] - U * b[0], R3 = b[2] - V * b[0], R4 = 2.0 * b[3] - B * b[0];
-    a[3] = 4.0 * lam * lam / (KDOF + 2.0) * (R4 - 2.0 * U * R2 - 2.0 * V * R3);
+    a[3] = lam * lam * (4.0 / (KDOF + 2.0)) * (R4 - 2.0 * U * R2 - 2.0 * V * R3);
     a[2] = 2.0 * lam * R3 - V * a[3];
     a[1] = 2.0 * lam * R2 - U * a[3];
     a[0] = b[0] - U * a[1] - V * a[2] - 0.5 * a[3] * B;
@@ -374,28 +373,29 @@ __device__ __forceinline__ double add_sides(double a, double b)
 __device__ __forceinline__ void side_terms(double sgn, const double *w, const double *gn, const double *gt,
                                            double *acc)
 {
-    double r = w[0], U = w[1] / r, V = w[2] / r, lam = lam_of(w);
+    // one reciprocal per denominator: an FP64 divide is a long sequence,
+    // and the flux kernels are bound by their FP64 instruction stream
+    double r = w[0], ir = 1.0 / r, U = w[1] * ir, V = w[2] * ir, lam = lam_of(w), hl = 0.5 / lam;
     double an[4], at[4], A[4], b[4];
-    double ir = 1.0 / r;
 #pragma unroll
     for (int k = 0; k < 4; k++) b[k] = gn[k] * ir;
-    msolve(U, V, lam, b, an);
+    msolve(U, V, lam, hl, b, an);
 #pragma unroll
     for (int k = 0; k < 4; k++) b[k] = gt[k] * ir;
-    msolve(U, V, lam, b, at);
+    msolve(U, V, lam, hl, b, at);
     double mv[8], mx[3], mu[8];
-    mom_u<0>(V, lam, mv);
-    mom_xi(lam, mx);
+    mom_u<0>(V, lam, hl, mv);
+    mom_xi(hl, mx);
     {
         double mf[8], t1[4], t2[4];
-        mom_u<0>(U, lam, mf);
+        mom_u<0>(U, lam, hl, mf);
         pmom<1, 0>(mf, mv, mx, an, t1);
         pmom<0, 1>(mf, mv, mx, at, t2);
 #pragma unroll
         for (int k = 0; k < 4; k++) b[k] = -(t1[k] + t2[k]);
-        msolve(U, V, lam, b, A);
+        msolve(U, V, lam, hl, b, A);
     }
-    mom_u_half(U, lam, sgn, mu);
+    mom_u_half(U, lam, hl, sgn, mu);
     double t[4], s[4];
     pmom1<0>(mu, mv, mx, t);
 #pragma unroll
@@ -424,7 +424,7 @@ __device__ __forceinline__ void side_terms(double sgn, const double *w, const do
 // face.  gks_eq: g0 from the summed side moments, the Eq.34 collision time
 // and the time integrals of the six Eq.13 factors over [0, dt].
 struct GksEq {
-    double r0, U0, V0, lam0, ir0;
+    double r0, U0, V0, lam0, ir0, hl0;
     double T1, T2, T3, T4, T5, T6;
     double mv[8], mx[3];
 };
@@ -432,11 +432,12 @@ template <typename T>
 __device__ __forceinline__ void gks_eq(const Params<T> &P, const InstParam &ip, const double *w0, double dt,
                                        double nut_f, double jump, GksEq &q)
 {
-    q.r0 = w0[0]; q.U0 = w0[1] / q.r0; q.V0 = w0[2] / q.r0; q.lam0 = lam_of(w0);
+    q.r0 = w0[0];
     q.ir0 = 1.0 / q.r0;
+    q.U0 = w0[1] * q.ir0; q.V0 = w0[2] * q.ir0; q.lam0 = lam_of(w0); q.hl0 = 0.5 / q.lam0;
     double mul = mu_lam(P.mu_law, ip, q.lam0), mut = 0.0;
     if (ip.sa && nut_f > 0.0) mut = q.r0 * nut_f * sa_fv1(nut_f * q.r0 / mul);
-    double tau = (mul + mut) * 2.0 * q.lam0 / q.r0;
+    double tau = (mul + mut) * 2.0 * q.lam0 * q.ir0;
     if (P.tau_jump) tau += dt * jump;
     double eta = exp(-dt / tau), ome = -expm1(-dt / tau);
     q.T1 = dt - tau * ome;
@@ -445,8 +446,8 @@ __device__ __forceinline__ void gks_eq(const Params<T> &P, const InstParam &ip, 
     q.T4 = tau * ome;
     q.T5 = tau * dt * eta - 2.0 * tau * tau * ome;
     q.T6 = -tau * tau * ome;
-    mom_u<0>(q.V0, q.lam0, q.mv);
-    mom_xi(q.lam0, q.mx);
+    mom_u<0>(q.V0, q.lam0, q.hl0, q.mv);
+    mom_xi(q.hl0, q.mx);
 }
 // One half space of q2 = <psi (abar_n H u + abar_n' (1-H) u)> and of its flux
 // moment f2 = <u psi (...)>: left (sgn = +1) with the slope (W0 - W_l)/d_l
@@ -455,13 +456,14 @@ __device__ __forceinline__ void gks_half(const GksEq &q, double sgn, const doubl
                                          double *q2, double *f2)
 {
     double b[4], a[4], mh[8];
+    const double sd = q.ir0 / d;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         double dw = sgn > 0.0 ? w0[k] - wc[k] : wc[k] - w0[k];
-        b[k] = dw / d * q.ir0;
+        b[k] = dw * sd;
     }
-    msolve(q.U0, q.V0, q.lam0, b, a);
-    mom_u_half(q.U0, q.lam0, sgn, mh);
+    msolve(q.U0, q.V0, q.lam0, q.hl0, b, a);
+    mom_u_half(q.U0, q.lam0, q.hl0, sgn, mh);
     pmom<1, 0>(mh, q.mv, q.mx, a, q2);
     pmom<2, 0>(mh, q.mv, q.mx, a, f2);
 }
@@ -473,10 +475,10 @@ __device__ __forceinline__ void gks_finish(const GksEq &q, const double *acc, do
 {
     const double *q5 = acc + 4, *q6 = acc + 8, *f4 = acc + 12, *f5 = acc + 16, *f6 = acc + 20;
     double mf[8], a[4], b[4], t[4];
-    mom_u<0>(q.U0, q.lam0, mf);
+    mom_u<0>(q.U0, q.lam0, q.hl0, mf);
 #pragma unroll
     for (int k = 0; k < 4; k++) b[k] = 0.5 * gt_sum[k] * q.ir0;
-    msolve(q.U0, q.V0, q.lam0, b, a);
+    msolve(q.U0, q.V0, q.lam0, q.hl0, b, a);
     pmom<0, 1>(mf, q.mv, q.mx, a, t);
 #pragma unroll
     for (int k = 0; k < 4; k++) q2[k] = q.r0 * (q2[k] + t[k]);
@@ -484,10 +486,10 @@ __device__ __forceinline__ void gks_finish(const GksEq &q, const double *acc, do
 #pragma unroll
     for (int k = 0; k < 4; k++) f2[k] += t[k];
     // Eq.12 -> Abar
-    double den = q.r0 * (0.5 * dt * dt - q.T3);
+    const double iden = 1.0 / (q.r0 * (0.5 * dt * dt - q.T3));
 #pragma unroll
-    for (int k = 0; k < 4; k++) b[k] = (q.T2 * q2[k] + q.T5 * q5[k] + q.T6 * q6[k]) / den;
-    msolve(q.U0, q.V0, q.lam0, b, a);
+    for (int k = 0; k < 4; k++) b[k] = (q.T2 * q2[k] + q.T5 * q5[k] + q.T6 * q6[k]) * iden;
+    msolve(q.U0, q.V0, q.lam0, q.hl0, b, a);
     // Eq.14
     double e1[4];
     pmom1<1>(mf, q.mv, q.mx, e1);
@@ -752,14 +754,15 @@ __device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &i
         if (!moving) rot(wm, o.fwc);
     }
     {
-        o.q = (wm[1] * nx + wm[2] * ny) / wm[0];
+        const double irm = 1.0 / wm[0];
+        o.q = (wm[1] * nx + wm[2] * ny) * irm;
         const double lm = lam_of(wm);
         o.ls = fabs(o.q) + sqrt(GAMMA / (2.0 * lm));
         const double mu = mu_lam(P.mu_law, ip, lm);
         double ev = mu;
         if (ip.sa && wm[4] > 0) ev += wm[0] * wm[4] * sa_fv1(wm[4] * wm[0] / mu);
-        o.evr = ev / wm[0];
-        o.nu = mu / wm[0];
+        o.evr = ev * irm;
+        o.nu = mu * irm;
         o.nut = wm[4];
     }
     {
