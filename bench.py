@@ -44,7 +44,7 @@ FP64_VALU_PEAK_TFS = 78.6   # MI355X FP64 vector
 # FP64 operations per face of k_flux, counted with rocprofv3: FP64 VALU
 # instructions per wave (2 x FMA + MUL + ADD + TRANS); one face per lane, so
 # this is also the operation count of one face.
-FLUX_FLOP_PER_FACE = 3798.0
+FLUX_FLOP_PER_FACE = 3488.0
 KSRC = os.path.join(ROOT, "paper_1709_00803_amd", "csrc", "igks_kernels.hip")
 
 
