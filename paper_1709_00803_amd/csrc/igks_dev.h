@@ -30,7 +30,13 @@ constexpr int CF_NEXT_SHIFT = 8;
 constexpr int MAXV = 4;       // entries and vertices per block (triangles pad by repeating a vertex)
 constexpr int MAXP = 8;       // vertices of the largest cell (two blocks)
 constexpr int HIST_W = 6;     // doubles per history entry
-constexpr int NSLOT = 64;     // atomic min/max targets of one instance are spread over this many slots
+// Atomic min / max targets: NSLOT slots per instance and quantity, each on
+// a 128-byte line of its own (atomics on one line are carried out one after
+// another), holding non-negative doubles as integers (they compare like
+// their bit patterns, so min / max of them is exact and order independent).
+constexpr int NSLOT = 64;
+constexpr int SLOT_STRIDE = 16;   // unsigned long longs from one slot to the next
+enum { SL_DTMIN = 0, SL_RESINF = 1, SL_E40 = 2, NSL = 3 };   // Eq.23 minimum, max |M|, Eq.40 maximum
 constexpr int RB = 32;        // blocks per instance in the residual-norm reduction
 constexpr int NCLASS = 4;     // kernel classes with a tunable block size: prep, flux, gather, sweep
 
@@ -43,13 +49,8 @@ struct InstParam {
     int pad;
 };
 
-// Scalars of one instance, updated on the device.  Integer atomics only:
-// non-negative doubles compare like their bit patterns, so min/max of them
-// is exact and order independent.
+// Scalars of one instance, updated on the device.
 struct InstScalars {
-    unsigned long long dtmin_bits[NSLOT];   // Eq.23 minimum over cells (min over slots)
-    unsigned long long resinf_bits[NSLOT];  // max |M| (max over slots)
-    unsigned long long e40_bits[NSLOT];     // Eq.40 maximum (max over slots)
     double dt;                              // Eq.23 time step of the current iteration
     double cfl;                             // implicit CFL of the current iteration
     double res_inf_prev;                    // ||M||_inf of the previous iteration
@@ -72,6 +73,7 @@ struct Params {
     const int *cinst, *finst;  // instance of each cell / face
     const InstParam *ip;
     InstScalars *is;
+    unsigned long long *slot;  // ninst x NSL x NSLOT slots, SLOT_STRIDE apart
     // cell arrays (SoA, internal order)
     double *Wa, *Wb;           // state ping-pong, 5 x nc
     double *grad;              // limited gradients: d/dx of rho, rhoU, rhoV, rhoE, then d/dy
@@ -122,8 +124,10 @@ template <typename T> void launch_reduce(const Launch &L, const Params<T> &P, in
 // one wavefront of cells [c0, c1) of the sweeps; mode 0 forward, 1 backward,
 // 2 both (the last wavefront).  Backward steps also update the state
 // (Eq.17); launch_commit then accepts or rejects the iteration of every
-// instance
-template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, int mode);
+// instance.  Cells below lev1 form the first wavefront, whose forward step
+// is not launched (its increments are formed where they are read); 0: every
+// forward increment is stored.
+template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, int mode, int lev1);
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd);
 template <typename T> void launch_commit(const Launch &L, const Params<T> &P, int it);
 // explicit step (Eq.15, local time steps) in place of the sweeps

@@ -60,7 +60,7 @@ struct Buf {
 constexpr int NKT = 6;
 
 struct WsMap {
-    Buf ip, is, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx, phi;
+    Buf ip, is, slot, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx, phi;
     Buf cinst, finst, icell, ioff, g2i, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
     Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, sak, ipart, hist, ipos;
     Buf wall_faces, wall_out, woff, wseg, lev_off, stage, backup;
@@ -131,8 +131,10 @@ constexpr int MAX_GRAPH_NODES = 8192;
 int launches_per_iteration(const igks_ctx *c)
 {
     const int nlev = std::max(1, c->g.nlev);
-    const int sweeps = c->opt.scheme == 1 ? 1 : (c->sweep_wg ? 3 : 2 * nlev - 1);
-    return 6 + sweeps;   // prep, flux, gather, isum, reduce, commit + the update / sweep launches
+    // per-wavefront sweeps: forward steps of wavefronts 1 .. nlev-2, the last
+    // wavefront's two steps, backward steps of nlev-2 .. 0
+    const int sweeps = c->opt.scheme == 1 ? 1 : (c->sweep_wg ? 3 : std::max(1, 2 * nlev - 2));
+    return 5 + sweeps;   // prep, flux, gather, reduce, commit + the update / sweep launches
 }
 int graph_chunk(const igks_ctx *c)
 {
@@ -472,6 +474,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
                  I = sizeof(int), NI = ninst, NW = std::max(1, G.nwall);
     w.ip = L.add(NI * sizeof(InstParam));
     w.is = L.add(NI * sizeof(InstScalars));
+    w.slot = L.add(NI * NSL * NSLOT * SLOT_STRIDE * sizeof(unsigned long long));
     w.Wa = L.add(5 * N * D); w.Wb = L.add(5 * N * D);
     w.grad = L.add(8 * N * D); w.lamc = L.add(N * D); w.vort = L.add(N * D); w.nu = L.add(N * D);
     w.phi = L.add(4 * N * D);
@@ -520,6 +523,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.cinst = In(w.cinst); P.finst = In(w.finst);
     P.ip = (const InstParam *)(b + w.ip.off);
     P.is = (InstScalars *)(b + w.is.off);
+    P.slot = (unsigned long long *)(b + w.slot.off);
     P.Wa = D(w.Wa); P.Wb = D(w.Wb); P.grad = D(w.grad); P.lamc = D(w.lamc); P.vort = D(w.vort); P.nu = D(w.nu);
     P.M = D(w.M); P.lsum = D(w.lsum); P.sadiag = D(w.sadiag); P.r2 = D(w.r2); P.dW = (T *)(b + w.dW.off);
     P.xc = D(w.xc); P.yc = D(w.yc); P.area = D(w.area); P.lsinv = D(w.lsinv); P.dwall = D(w.dwall); P.vtx = D(w.vtx);
@@ -550,6 +554,7 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev, int it)
     Launch L = launch_of(c);
     const int *lev = (const int *)(c->ws + c->w.lev_off.off);
     const Global &G = c->g;
+    const int lev1 = G.nlev > 1 ? G.lev_off[1] : 0;   // cells of the first wavefront
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], c->stream); };
     mark(0);
     launch_prep(L, P);
@@ -570,15 +575,16 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev, int it)
     }
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, true);
     else
-        // forward over all wavefronts; the last one also takes its backward
-        // step (only ghosts lie above it)
-        for (int l = 0; l < G.nlev; l++)
-            launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], l + 1 < G.nlev ? 0 : 2);
+        // forward over the wavefronts after the first (whose forward
+        // increments D^-1 M are formed where they are read); the last one
+        // also takes its backward step (only ghosts lie above it)
+        for (int l = G.nlev > 1 ? 1 : 0; l < G.nlev; l++)
+            launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], l + 1 < G.nlev ? 0 : 2, lev1);
     mark(5);
     // backward sweep with the update
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, false);
     else
-        for (int l = G.nlev - 2; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], 1);
+        for (int l = G.nlev - 2; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], 1, lev1);
     launch_commit(L, P, it);
     mark(6);
 }
@@ -733,7 +739,6 @@ InstScalars fresh_scalars(const igks_scalars *sc)
 {
     InstScalars s;
     std::memset(&s, 0, sizeof s);
-    for (int k = 0; k < NSLOT; k++) s.dtmin_bits[k] = 0x7ff0000000000000ull;   // +inf
     if (sc) {
         s.ncommit = sc->iteration;
         s.cfl = sc->cfl;
@@ -1022,6 +1027,7 @@ int igks_batch_set_freestream(igks_ctx *c, int32_t inst, double mach, double alp
     InstScalars s = fresh_scalars(nullptr);   // iteration 0 -> state buffer A
     HIPCHK(c, hipMemcpyAsync(c->P64.is + inst, &s, sizeof s, hipMemcpyHostToDevice, c->stream));
     Launch L = launch_of(c);
+    launch_reset(L, c->P64, 1, inst);
     launch_fill_instance(L, m.nc, inst_cells(c, inst), c->g.N, ip.Winf, c->P64.Wa);
     HIPCHK(c, hipGetLastError());
     m.have_flow = true;
@@ -1119,6 +1125,7 @@ int igks_batch_set_state(igks_ctx *c, int32_t inst, const double *W, const igks_
     HIPCHK(c, hipMemcpyAsync(c->P64.is + inst, &s, sizeof s, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(stage_buffer(c), W, sizeof(double) * 5 * n, hipMemcpyHostToDevice, c->stream));
     Launch L = launch_of(c);
+    launch_reset(L, c->P64, 1, inst);
     launch_copy_instance(L, n, inst_cells(c, inst), c->g.N, stage_buffer(c), (s.ncommit & 1) ? c->P64.Wb : c->P64.Wa,
                          true);
     HIPCHK(c, hipGetLastError());
@@ -1289,6 +1296,7 @@ int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s6)
     HIPCHK(c, hipMemcpyAsync(c->P64.Wa, bk, SB, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P64.Wb, bk + SB, SB, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P64.is, bk + 2 * SB, ni * sizeof(InstScalars), hipMemcpyDeviceToDevice, c->stream));
+    launch_reset(launch_of(c), c->P64, 1, -1);
     c->hist = hist_keep;
     for (double &x : c->ktimes) x = 0.0;
     int rc2 = sync_scalars(c);

@@ -190,44 +190,50 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// slot s of quantity `kind` of instance `inst`
+__device__ __forceinline__ unsigned long long *slot_at(unsigned long long *slot, int inst, int kind, int s)
+{
+    return slot + ((size_t)(inst * NSL + kind) * NSLOT + s) * SLOT_STRIDE;
+}
+// the lane's slot (lane mod NSLOT) of quantity `kind` of instance `inst`, as a double
+__device__ __forceinline__ double slot_lane(const unsigned long long *slot, int inst, int kind)
+{
+    const int lane = (int)(threadIdx.x & (warpSize - 1)) & (NSLOT - 1);
+    return __longlong_as_double((long long)slot[((size_t)(inst * NSL + kind) * NSLOT + lane) * SLOT_STRIDE]);
+}
+
 // Atomic min / max of a non-negative double into one of the NSLOT slots of
 // the lane's instance.  Lanes with inst < 0 take no part.  When the whole
 // wave belongs to one instance it combines first and issues one atomic.
 template <bool MIN>
-__device__ __forceinline__ void slot_update(unsigned long long *slots0, int inst, double v)
+__device__ __forceinline__ void slot_update(unsigned long long *slot, int kind, int inst, double v)
 {
     unsigned long long act = __ballot(inst >= 0);
     if (act == 0ull) return;
     int src = __ffsll((long long)act) - 1;
     int i0 = __shfl(inst, src);
     int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) / warpSize);
-    unsigned slot = (unsigned)wave & (NSLOT - 1);
-    size_t stride = sizeof(InstScalars) / sizeof(unsigned long long);
+    int s = wave & (NSLOT - 1);
     if (__all(inst < 0 || inst == i0)) {
         double x = (inst >= 0) ? v : (MIN ? INFINITY : 0.0);
         x = MIN ? wave_min(x) : wave_max(x);
         if ((int)(threadIdx.x & (warpSize - 1)) == src) {
-            unsigned long long *p = slots0 + (size_t)i0 * stride + slot;
+            unsigned long long *p = slot_at(slot, i0, kind, s);
             if (MIN) atomicMin(p, (unsigned long long)__double_as_longlong(x));
             else atomicMax(p, (unsigned long long)__double_as_longlong(x));
         }
     } else if (inst >= 0) {
-        unsigned long long *p = slots0 + (size_t)inst * stride + slot;
+        unsigned long long *p = slot_at(slot, inst, kind, s);
         if (MIN) atomicMin(p, (unsigned long long)__double_as_longlong(v));
         else atomicMax(p, (unsigned long long)__double_as_longlong(v));
     }
 }
 
-__device__ __forceinline__ double slots_min_serial(const unsigned long long *b)
+__device__ __forceinline__ double slots_min_serial(const unsigned long long *slot, int inst, int kind)
 {
     double v = INFINITY;
-    for (int i = 0; i < NSLOT; i++) v = fmin(v, __longlong_as_double((long long)b[i]));
-    return v;
-}
-__device__ __forceinline__ double slots_max_serial(const unsigned long long *b)
-{
-    double v = 0.0;
-    for (int i = 0; i < NSLOT; i++) v = fmax(v, __longlong_as_double((long long)b[i]));
+    for (int i = 0; i < NSLOT; i++)
+        v = fmin(v, __longlong_as_double((long long)slot[((size_t)(inst * NSL + kind) * NSLOT + i) * SLOT_STRIDE]));
     return v;
 }
 
@@ -258,6 +264,20 @@ template <typename T>
 __device__ __forceinline__ int cell_inst(const Params<T> &P, int c)
 {
     return P.ninst == 1 ? 0 : P.cinst[c];
+}
+// The instance a cell (or face) works for, -1 if it is frozen.  ONE: a
+// context of one instance.  Its index is the constant 0, so the instance's
+// scalars come through scalar loads, and the frozen flag is not consulted:
+// a frozen instance's current state buffer is never written again (the
+// update goes to the other buffer and the commit does not flip it), so
+// recomputing its residual and increment changes nothing, while the check
+// would put a dependent load in front of every other load of the kernel.
+template <bool ONE, typename T>
+__device__ __forceinline__ int live_inst(const Params<T> &P, const int *idx, int i)
+{
+    if (ONE) return 0;
+    const int inst = P.ninst == 1 ? 0 : idx[i];
+    return P.is[inst].halt ? -1 : inst;
 }
 template <typename T>
 __device__ __forceinline__ int face_inst(const Params<T> &P, int f)
@@ -536,9 +556,9 @@ __global__ void k_reset(Params<T> P, int mode, int inst)
         }
         if (mode & (1 | 8))
             for (int k = 0; k < NSLOT; k++) {
-                s->dtmin_bits[k] = 0x7ff0000000000000ull;   // +inf
-                s->resinf_bits[k] = 0ull;
-                s->e40_bits[k] = 0ull;
+                *slot_at(P.slot, i, SL_DTMIN, k) = 0x7ff0000000000000ull;   // +inf
+                *slot_at(P.slot, i, SL_RESINF, k) = 0ull;
+                *slot_at(P.slot, i, SL_E40, k) = 0ull;
             }
         if (mode & (2 | 8)) { s->bad = 0; s->halt = 0; }
     }
@@ -649,33 +669,28 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
     return P.cfl_flux * P.area[c] / lc;
 }
 
-template <typename T>
+template <typename T, bool ONE>
 __global__ __launch_bounds__(256) void k_prep(Params<T> P)
 {
     int c = xcd_block() * blockDim.x + threadIdx.x;
     int inst = -1;
     double dt = INFINITY;
     if (c < P.nc) {
-        inst = cell_inst(P, c);
-        if (P.is[inst].halt) inst = -1;
-        else dt = prep_cell(P, c, inst);
+        inst = live_inst<ONE>(P, P.cinst, c);
+        if (inst >= 0) dt = prep_cell(P, c, inst);
     }
-    slot_update<true>(&P.is[0].dtmin_bits[0], inst, dt);   // Eq.23: minimum over the instance's cells
+    slot_update<true>(P.slot, SL_DTMIN, inst, dt);   // Eq.23: minimum over the instance's cells
 }
 
 // The Eq.23 time step of the lane's instance: the minimum over its slots.
 // A wave whose lanes share one instance reads the 64 slots one per lane.
-__device__ __forceinline__ double instance_dt(const InstScalars *is, int inst)
+__device__ __forceinline__ double instance_dt(const unsigned long long *slot, int inst)
 {
-    int lane = (int)(threadIdx.x & (warpSize - 1));
     unsigned long long act = __ballot(inst >= 0);
     if (act == 0ull) return 0.0;
     int i0 = __shfl(inst, __ffsll((long long)act) - 1);
-    if (__all(inst < 0 || inst == i0)) {
-        double v = __longlong_as_double((long long)is[i0].dtmin_bits[lane & (NSLOT - 1)]);
-        return wave_min(v);
-    }
-    return inst >= 0 ? slots_min_serial(is[inst].dtmin_bits) : 0.0;
+    if (__all(inst < 0 || inst == i0)) return wave_min(slot_lane(slot, i0, SL_DTMIN));
+    return inst >= 0 ? slots_min_serial(slot, inst, SL_DTMIN) : 0.0;
 }
 
 __device__ __forceinline__ bool physical(const double *w)
@@ -935,32 +950,26 @@ __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int si
 }
 
 // one lane per face
-template <typename T>
+template <typename T, bool ONE>
 __global__ __launch_bounds__(256) void k_flux(Params<T> P)
 {
     const int f = xcd_block() * blockDim.x + threadIdx.x;
     int inst = -1;
-    if (f < P.nf) {
-        inst = face_inst(P, f);
-        if (P.is[inst].halt) inst = -1;
-    }
-    double dt = instance_dt(P.is, inst);
+    if (f < P.nf) inst = live_inst<ONE>(P, P.finst, f);
+    double dt = instance_dt(P.slot, inst);
     if (inst < 0) return;
     flux_face(P, f, inst, dt);
 }
 
 // two lanes per face
-template <typename T>
+template <typename T, bool ONE>
 __global__ __launch_bounds__(256) void k_flux2(Params<T> P)
 {
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     const int f = t >> 1, side = t & 1;
     int inst = -1;
-    if (f < P.nf) {
-        inst = face_inst(P, f);
-        if (P.is[inst].halt) inst = -1;
-    }
-    double dt = instance_dt(P.is, inst);
+    if (f < P.nf) inst = live_inst<ONE>(P, P.finst, f);
+    double dt = instance_dt(P.slot, inst);
     if (inst < 0) return;   // both lanes of a pair leave together
     flux_face_pair(P, f, side, inst, dt);
 }
@@ -1052,18 +1061,17 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
     return fmax(fmax(fabs(m[0]), fabs(m[1])), fmax(fabs(m[2]), fabs(m[3])));
 }
 
-template <typename T>
+template <typename T, bool ONE>
 __global__ __launch_bounds__(256) void k_gather(Params<T> P)
 {
     int c = xcd_block() * blockDim.x + threadIdx.x;
     int inst = -1;
     double rinf = 0.0;
     if (c < P.nc) {
-        inst = cell_inst(P, c);
-        if (P.is[inst].halt) inst = -1;
-        else rinf = gather_cell(P, c, inst);
+        inst = live_inst<ONE>(P, P.cinst, c);
+        if (inst >= 0) rinf = gather_cell(P, c, inst);
     }
-    slot_update<false>(&P.is[0].resinf_bits[0], inst, rinf);
+    slot_update<false>(P.slot, SL_RESINF, inst, rinf);
 }
 
 // Sum over the wave by butterfly: every lane ends with the same value (each
@@ -1074,55 +1082,14 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// One wave per instance (block i): the Eq.23 time step the flux used, L2
-// norms from the partial sums and the max norm, both in a fixed order, the
-// Eq.25 CFL law, history entry `it` of the chunk.
-template <typename T>
-__global__ __launch_bounds__(64) void k_reduce(Params<T> P, int it)
-{
-    const int i = blockIdx.x, lane = threadIdx.x;
-    InstScalars *s = &P.is[i];
-    if (s->halt) return;
-    double dt = wave_min(__longlong_as_double((long long)s->dtmin_bits[lane]));
-    double rinf = wave_max(__longlong_as_double((long long)s->resinf_bits[lane]));
-    double x = lane < RB ? P.ipart[2 * (i * RB + lane)] : 0.0;
-    double y = lane < RB ? P.ipart[2 * (i * RB + lane) + 1] : 0.0;
-    x = wave_sum(x);
-    y = wave_sum(y);
-    s->resinf_bits[lane] = 0ull;
-    if (lane != 0) return;
-    double l2 = sqrt(x), sal2 = sqrt(y);
-    s->dt = dt;
-    // the drop is measured from the largest ||M_rho||_2 so far
-    if (s->ncommit == 0 || l2 > s->res0) s->res0 = l2;
-    if (s->ncommit == 0) {
-        s->cfl = P.cfl_init;
-    } else if (P.cfl_mode == 0) {
-        double cf = s->cfl * s->res_inf_prev / rinf;
-        if (!(cf >= P.cfl_min)) cf = P.cfl_min;
-        if (cf > P.cfl_max) cf = P.cfl_max;
-        s->cfl = cf;
-    }
-    s->res_inf_prev = rinf;
-    // limiter freezing: from the next iteration on, the factors just computed
-    if (P.limiter && P.limiter_freeze > 0.0 && !s->phi_frozen && l2 <= P.limiter_freeze * s->res0) s->phi_frozen = 1;
-    s->res_l2 = l2;
-    s->sa_l2 = sal2;
-    s->res_inf = rinf;
-    if (it < P.hist_cap) {
-        double *e = P.hist + (size_t)HIST_W * ((size_t)it * P.ninst + i);
-        e[0] = l2; e[1] = rinf; e[2] = s->cfl; e[3] = dt; e[4] = 0.0; e[5] = sal2;
-    }
-}
-
 // Norm partial sums: block (i, b) sums slice b of instance i's squares
 // (contiguous, instance-grouped) in a fixed order, so the L2 norms are
-// deterministic without float atomics.
+// deterministic without float atomics; k_commit adds the RB partial sums.
 template <typename T>
-__global__ __launch_bounds__(256) void k_isum(Params<T> P)
+__device__ __forceinline__ void norm_partial(const Params<T> &P, int blk)
 {
     __shared__ double a[256], b[256];
-    int i = blockIdx.x / RB, part = blockIdx.x % RB;
+    int i = blk / RB, part = blk % RB;
     int lo = P.ioff[i], n = P.ioff[i + 1] - lo;
     int per = (n + RB - 1) / RB;
     int s0 = lo + part * per, s1 = min(lo + n, s0 + per);
@@ -1141,18 +1108,117 @@ __global__ __launch_bounds__(256) void k_isum(Params<T> P)
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        P.ipart[2 * blockIdx.x] = a[0];
-        P.ipart[2 * blockIdx.x + 1] = b[0];
+        P.ipart[2 * blk] = a[0];
+        P.ipart[2 * blk + 1] = b[0];
     }
+}
+
+// Blocks [0, ninst RB): the norm partial sums.  Block ninst RB + i, first
+// wave: the Eq.23 time step the flux used, the max norm, the Eq.25 CFL law
+// (the L2 norms are not needed before the commit), history entry `it` of
+// the chunk.
+template <typename T>
+__global__ __launch_bounds__(256) void k_reduce(Params<T> P, int it)
+{
+    if ((int)blockIdx.x < P.ninst * RB) {
+        norm_partial(P, blockIdx.x);
+        return;
+    }
+    const int i = blockIdx.x - P.ninst * RB, lane = threadIdx.x;
+    if (lane >= 64) return;
+    InstScalars *s = &P.is[i];
+    if (s->halt) return;
+    double dt = wave_min(slot_lane(P.slot, i, SL_DTMIN));
+    double rinf = wave_max(slot_lane(P.slot, i, SL_RESINF));
+    *slot_at(P.slot, i, SL_RESINF, lane) = 0ull;
+    if (lane != 0) return;
+    s->dt = dt;
+    if (s->ncommit == 0) {
+        s->cfl = P.cfl_init;
+    } else if (P.cfl_mode == 0) {
+        double cf = s->cfl * s->res_inf_prev / rinf;
+        if (!(cf >= P.cfl_min)) cf = P.cfl_min;
+        if (cf > P.cfl_max) cf = P.cfl_max;
+        s->cfl = cf;
+    }
+    s->res_inf_prev = rinf;
+    s->res_inf = rinf;
+    if (it < P.hist_cap) {
+        double *e = P.hist + (size_t)HIST_W * ((size_t)it * P.ninst + i);
+        e[1] = rinf; e[2] = s->cfl; e[3] = dt;
+    }
+}
+
+// Accumulation of the sweeps' neighbour terms, never fused with the
+// product that formed a term: the one-lane and the quad-lane sweeps then
+// form the same numbers.
+template <typename V>
+__device__ __forceinline__ V acc_sub(V a, V b)
+{
+#pragma clang fp contract(off)
+    return a - b;
+}
+template <typename V>
+__device__ __forceinline__ V acc_add(V a, V b)
+{
+#pragma clang fp contract(off)
+    return a + b;
+}
+
+// Value of lane K of the lane's quad (a DPP quad permutation; every lane of
+// the quad must be active).
+template <int K>
+__device__ __forceinline__ int quad_get(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, K * 0x55, 0xf, 0xf, false);
+}
+template <int K>
+__device__ __forceinline__ float quad_get(float v)
+{
+    return __int_as_float(quad_get<K>(__float_as_int(v)));
+}
+template <int K>
+__device__ __forceinline__ double quad_get(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = quad_get<K>((int)(b & 0xffffffffll)), hi = quad_get<K>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// a -= t_0, t_1, t_2, t_3 (SUB) or a += them, in lane order, t_k the value
+// on lane k of the quad: the order of the one-lane loop over four entries
+template <bool SUB, typename V>
+__device__ __forceinline__ V quad_fold(V a, V t)
+{
+    const V t0 = quad_get<0>(t), t1 = quad_get<1>(t), t2 = quad_get<2>(t), t3 = quad_get<3>(t);
+    if (SUB) return acc_sub(acc_sub(acc_sub(acc_sub(a, t0), t1), t2), t3);
+    return acc_add(acc_add(acc_add(acc_add(a, t0), t1), t2), t3);
+}
+
+// Forward-sweep increment dW*_j of a cell of the first wavefront: it has no
+// lower neighbours, so Eq.22 reduces to dW*_j = D_j^-1 M_j (the expressions
+// of sweep_cell with nothing subtracted, hence the same numbers).  Formed
+// where it is needed instead of in a launch of its own.
+template <typename T>
+__device__ __forceinline__ void first_front_incr(const Params<T> &P, const InstParam &ip, int j, T cfl, T *d)
+{
+    const int N = P.nc;
+    const T odt = T(P.lamc[j]) / cfl;
+    const T iD = T(1) / (odt + T(P.lsum[j]));
+#pragma unroll
+    for (int k = 0; k < 4; k++) d[k] = T(P.M[k * N + j]) * iD;
+    d[4] = ip.sa ? T(P.M[4 * N + j]) / (odt + T(P.sadiag[j])) : T(0);
 }
 
 // Neighbour term of one cell-face entry in the LU-SGS sweeps (Eq.22 and
 // Eq.31-32): t[0..3] = (J(W_j, n) dW_j - lam dW_j) S / 2 with n pointing out
 // of the cell, t[4] = the SA off-diagonal coefficient times dnu~_j.  j < 0:
 // the ghost cell, whose increment follows from the cell's own dW* (Sec. 2.5).
+// Neighbours j < lev1 belong to the first wavefront, whose forward
+// increments are not stored (first_front_incr).
 template <typename T>
 __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &ip, const double *W,
-                                           const double *w, int f, int j, int fl, const T *dws, T *t)
+                                           const double *w, int f, int j, int fl, const T *dws, T cfl, int lev1,
+                                           T *t)
 {
     const int N = P.nc;
     double sg = (fl & CF_OWNER) ? 1.0 : -1.0;
@@ -1162,7 +1228,13 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
     T dj[5];
     if (j >= 0) {
 #pragma unroll
-        for (int k = 0; k < 5; k++) { wj[k] = W[k * N + j]; dj[k] = P.dW[k * N + j]; }
+        for (int k = 0; k < 5; k++) wj[k] = W[k * N + j];
+        if (j < lev1) {
+            first_front_incr(P, ip, j, cfl, dj);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 5; k++) dj[k] = P.dW[k * N + j];
+        }
     } else {
         ghost(ip, P.fbc[f], w, nx, ny, wj);
         ghost_incr<T>(P.fbc[f], dws, T(nx), T(ny), T(wall_speed(ip, nx, ny)), dj);
@@ -1212,7 +1284,7 @@ __device__ __forceinline__ double apply_update(const Params<T> &P, int c, int in
 // Explicit step (Eq.15) with the local time step dt_i = CFL Omega_i /
 // (Lambda_c)_i of Eq.21/23: dW_i = dt_i M_i / Omega_i = CFL M_i / (Lambda_c)_i,
 // the SA variable the same way with its right-hand side.
-template <typename T>
+template <typename T, bool ONE>
 __global__ __launch_bounds__(256) void k_explicit(Params<T> P)
 {
     const int N = P.nc;
@@ -1220,10 +1292,8 @@ __global__ __launch_bounds__(256) void k_explicit(Params<T> P)
     int inst = -1;
     double e = 0.0;
     if (c < N) {
-        inst = cell_inst(P, c);
-        if (P.is[inst].halt) {
-            inst = -1;
-        } else {
+        inst = live_inst<ONE>(P, P.cinst, c);
+        if (inst >= 0) {
             const double *W = cur_state(P, inst);
             double w[5], d[5];
 #pragma unroll
@@ -1235,7 +1305,7 @@ __global__ __launch_bounds__(256) void k_explicit(Params<T> P)
             e = apply_update(P, c, inst, w, d);
         }
     }
-    slot_update<false>(&P.is[0].e40_bits[0], inst, e);
+    slot_update<false>(P.slot, SL_E40, inst, e);
 }
 
 // One wavefront of the LU-SGS sweeps (Eq.22); the cells of a wavefront are
@@ -1256,12 +1326,9 @@ template <typename T, int MODE, bool ONE = false>
 __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &inst)
 {
     const int N = P.nc;
-    inst = ONE ? 0 : cell_inst(P, c);   // ONE: a single instance, its scalars uniform
+    inst = live_inst<ONE>(P, P.cinst, c);
+    if (inst < 0) return 0.0;
     const InstScalars &sc = P.is[inst];
-    if (sc.halt) {
-        inst = -1;
-        return 0.0;
-    }
     const InstParam &ip = P.ip[inst];
     const double *W = cur_state(P, inst);
     const T cfl = T(sc.cfl);
@@ -1281,10 +1348,10 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
             for (int k = 0; k < MAXV; k++) {
                 const int j = E.nbr[k], fl = E.flag[k];
                 if (!(fl & CF_VALID) || j < 0 || !(fl & CF_LOWER)) continue;
-                sweep_term(P, ip, W, w, E.face[k], j, fl, dws, t);
+                sweep_term(P, ip, W, w, E.face[k], j, fl, dws, cfl, 0, t);
 #pragma unroll
-                for (int m = 0; m < 4; m++) acc[m] -= t[m];
-                acc[4] += t[4];
+                for (int m = 0; m < 4; m++) acc[m] = acc_sub(acc[m], t[m]);
+                acc[4] = acc_add(acc[4], t[4]);
             }
         };
         lower(E0);
@@ -1309,9 +1376,9 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
         for (int k = 0; k < MAXV; k++) {
             const int j = E.nbr[k], fl = E.flag[k];
             if (!(fl & CF_VALID) || (j >= 0 && (fl & CF_LOWER))) continue;
-            sweep_term(P, ip, W, w, E.face[k], j, fl, dws, t);
+            sweep_term(P, ip, W, w, E.face[k], j, fl, dws, cfl, 0, t);
 #pragma unroll
-            for (int m = 0; m < 5; m++) acc[m] += t[m];
+            for (int m = 0; m < 5; m++) acc[m] = acc_add(acc[m], t[m]);
         }
     };
     upper(E0);
@@ -1330,34 +1397,133 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     return apply_update(P, c, inst, w, dd);
 }
 
-// One wave per instance (block i): accept (flip the state buffer) or reject
-// and freeze the instance, the Eq.40 maximum, slots reset for the next
-// iteration.
+// sweep_cell on a quad of lanes (q = 0..3, one cell per aligned quad): lane
+// q takes entry q of each of the cell's entry blocks, so a cell's neighbour
+// terms are formed side by side instead of one after another, and the
+// terms are combined on every lane of the quad in entry order (quad_fold),
+// which gives the same numbers as sweep_cell.  Lane 0 stores and returns
+// the Eq.40 ratio; the other lanes return 0.  Cells below lev1 (the first
+// wavefront) have no stored forward increment: their own and their
+// neighbours' are formed by first_front_incr.
+template <typename T, int MODE, bool ONE>
+__device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, int lev1, int &inst)
+{
+    const int N = P.nc;
+    inst = live_inst<ONE>(P, P.cinst, c);   // the same on the four lanes
+    if (inst < 0) return 0.0;
+    const InstScalars &sc = P.is[inst];
+    const InstParam &ip = P.ip[inst];
+    const double *W = cur_state(P, inst);
+    const T cfl = T(sc.cfl);
+    double w[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
+    const int f0 = P.cf_face[MAXV * c + q], j0 = P.cf_nbr[MAXV * c + q], fl0 = P.cf_flag[MAXV * c + q];
+    const int nxt = quad_get<3>(fl0) >> CF_NEXT_SHIFT;
+    const int ovf = nxt ? N + nxt - 1 : -1;   // a polygon's overflow block, or -1
+    const T odt = T(P.lamc[c]) / cfl;
+    const T D = odt + T(P.lsum[c]);
+    T dws[5], acc[5], t[5];
+    if (MODE == SW_FWD || MODE == SW_TOP) {
+#pragma unroll
+        for (int k = 0; k < 5; k++) acc[k] = T(P.M[k * N + c]);
+        auto lower = [&](int f, int j, int fl) {
+#pragma unroll
+            for (int m = 0; m < 5; m++) t[m] = T(0);
+            if ((fl & CF_VALID) && j >= 0 && (fl & CF_LOWER)) sweep_term(P, ip, W, w, f, j, fl, dws, cfl, lev1, t);
+#pragma unroll
+            for (int m = 0; m < 4; m++) acc[m] = quad_fold<true>(acc[m], t[m]);
+            acc[4] = quad_fold<false>(acc[4], t[4]);
+        };
+        lower(f0, j0, fl0);
+        if (ovf >= 0) lower(P.cf_face[MAXV * ovf + q], P.cf_nbr[MAXV * ovf + q], P.cf_flag[MAXV * ovf + q]);
+        const T iD = T(1) / D;
+#pragma unroll
+        for (int k = 0; k < 4; k++) dws[k] = acc[k] * iD;
+        dws[4] = ip.sa ? acc[4] / (odt + T(P.sadiag[c])) : T(0);
+        if (MODE == SW_FWD) {
+            if (q == 0) {
+#pragma unroll
+                for (int k = 0; k < 5; k++) P.dW[k * N + c] = dws[k];
+            }
+            return 0.0;
+        }
+    } else if (c < lev1) {
+        first_front_incr(P, ip, c, cfl, dws);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; k++) dws[k] = P.dW[k * N + c];
+    }
+#pragma unroll
+    for (int k = 0; k < 5; k++) acc[k] = T(0);
+    auto upper = [&](int f, int j, int fl) {
+#pragma unroll
+        for (int m = 0; m < 5; m++) t[m] = T(0);
+        if ((fl & CF_VALID) && !(j >= 0 && (fl & CF_LOWER))) sweep_term(P, ip, W, w, f, j, fl, dws, cfl, lev1, t);
+#pragma unroll
+        for (int m = 0; m < 5; m++) acc[m] = quad_fold<false>(acc[m], t[m]);
+    };
+    upper(f0, j0, fl0);
+    if (ovf >= 0) upper(P.cf_face[MAXV * ovf + q], P.cf_nbr[MAXV * ovf + q], P.cf_flag[MAXV * ovf + q]);
+    if (q != 0) return 0.0;
+    T d[5];
+    const T iD = T(1) / D;
+#pragma unroll
+    for (int k = 0; k < 4; k++) d[k] = dws[k] - acc[k] * iD;
+    d[4] = ip.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
+#pragma unroll
+    for (int k = 0; k < 5; k++) P.dW[k * N + c] = d[k];
+    double dd[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) dd[k] = double(d[k]);
+    return apply_update(P, c, inst, w, dd);
+}
+
+// One wave per instance (block i): the L2 norms from the partial sums (in
+// a fixed order), the drop reference and limiter freezing, then accept
+// (flip the state buffer) or reject and freeze the instance, the Eq.40
+// maximum, slots reset for the next iteration.
 template <typename T>
 __global__ __launch_bounds__(64) void k_commit(Params<T> P, int it)
 {
     const int i = blockIdx.x, lane = threadIdx.x;
     InstScalars *s = &P.is[i];
     if (s->halt) return;
-    double e40 = wave_max(__longlong_as_double((long long)s->e40_bits[lane]));
+    double e40 = wave_max(slot_lane(P.slot, i, SL_E40));
+    double x = lane < RB ? P.ipart[2 * (i * RB + lane)] : 0.0;
+    double y = lane < RB ? P.ipart[2 * (i * RB + lane) + 1] : 0.0;
+    x = wave_sum(x);
+    y = wave_sum(y);
     int bad = s->bad;
-    s->dtmin_bits[lane] = 0x7ff0000000000000ull;
-    s->e40_bits[lane] = 0ull;
+    *slot_at(P.slot, i, SL_DTMIN, lane) = 0x7ff0000000000000ull;
+    *slot_at(P.slot, i, SL_E40, lane) = 0ull;
     if (lane != 0) return;
+    const double l2 = sqrt(x), sal2 = sqrt(y);
+    // the drop is measured from the largest ||M_rho||_2 so far
+    if (s->ncommit == 0 || l2 > s->res0) s->res0 = l2;
+    // limiter freezing: from the next iteration on, the factors just computed
+    if (P.limiter && P.limiter_freeze > 0.0 && !s->phi_frozen && l2 <= P.limiter_freeze * s->res0) s->phi_frozen = 1;
+    s->res_l2 = l2;
+    s->sa_l2 = sal2;
     s->e40 = e40;
-    if (it < P.hist_cap) P.hist[(size_t)HIST_W * ((size_t)it * P.ninst + i) + 4] = e40;
+    if (it < P.hist_cap) {
+        double *e = P.hist + (size_t)HIST_W * ((size_t)it * P.ninst + i);
+        e[0] = l2; e[4] = e40; e[5] = sal2;
+    }
     if (bad) s->halt = 1;
     else s->ncommit += 1;
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1)
+// One wavefront of cells [c0, c1), four lanes per cell (sweep_quad)
+template <typename T, int MODE, bool ONE>
+__global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1, int lev1)
 {
-    int c = c0 + xcd_block() * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
+    const int c = c0 + (t >> 2);
     int inst = -1;
     double e = 0.0;
-    if (c < c1) e = sweep_cell<T, MODE>(P, c, inst);
-    if (MODE != SW_FWD) slot_update<false>(&P.is[0].e40_bits[0], inst, e);
+    if (c < c1) e = sweep_quad<T, MODE, ONE>(P, c, t & 3, lev1, inst);
+    if (MODE != SW_FWD) slot_update<false>(P.slot, SL_E40, inst, e);
 }
 
 // The whole sweep in one workgroup: wavefront after wavefront, separated by
@@ -1386,7 +1552,7 @@ __global__ __launch_bounds__(512) void k_sweep_wg(Params<T> P, const int *lev_of
 
 // W^{n+1} = W^n + dW for every cell from the finished backward sweep (the
 // same arithmetic as the fused update of the per-wavefront path)
-template <typename T>
+template <typename T, bool ONE>
 __global__ __launch_bounds__(256) void k_update(Params<T> P)
 {
     const int N = P.nc;
@@ -1394,10 +1560,8 @@ __global__ __launch_bounds__(256) void k_update(Params<T> P)
     int inst = -1;
     double e = 0.0;
     if (c < N) {
-        inst = cell_inst(P, c);
-        if (P.is[inst].halt) {
-            inst = -1;
-        } else {
+        inst = live_inst<ONE>(P, P.cinst, c);
+        if (inst >= 0) {
             const double *W = cur_state(P, inst);
             double w[5], d[5];
 #pragma unroll
@@ -1408,7 +1572,7 @@ __global__ __launch_bounds__(256) void k_update(Params<T> P)
             e = apply_update(P, c, inst, w, d);
         }
     }
-    slot_update<false>(&P.is[0].e40_bits[0], inst, e);
+    slot_update<false>(P.slot, SL_E40, inst, e);
 }
 
 // exact distance from each centroid to the nearest wall segment of its instance
@@ -1470,13 +1634,21 @@ template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int
 {
     hipLaunchKernelGGL(k_reset<T>, dim3(1), dim3(64), 0, L.s, P, mode, inst);
 }
+// ONE-instance variants of the cell and face kernels for contexts of one
+// instance (see live_inst)
+#define LAUNCH_ONE(K, T, grid, block, ...)                                            \
+    do {                                                                              \
+        if (P.ninst == 1) hipLaunchKernelGGL((K<T, true>), grid, block, 0, L.s, __VA_ARGS__); \
+        else hipLaunchKernelGGL((K<T, false>), grid, block, 0, L.s, __VA_ARGS__);     \
+    } while (0)
+
 template <typename T> void launch_prep(const Launch &L, const Params<T> &P)
 {
-    hipLaunchKernelGGL(k_prep<T>, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), 0, L.s, P);
+    LAUNCH_ONE(k_prep, T, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), P);
 }
 template <typename T> void launch_explicit(const Launch &L, const Params<T> &P)
 {
-    hipLaunchKernelGGL(k_explicit<T>, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), 0, L.s, P);
+    LAUNCH_ONE(k_explicit, T, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), P);
 }
 template <typename T> void launch_commit(const Launch &L, const Params<T> &P, int it)
 {
@@ -1484,25 +1656,32 @@ template <typename T> void launch_commit(const Launch &L, const Params<T> &P, in
 }
 template <typename T> void launch_flux(const Launch &L, const Params<T> &P)
 {
-    if (L.flux_pair) hipLaunchKernelGGL(k_flux2<T>, dim3(nblk(2 * P.nf, L.block[1])), dim3(L.block[1]), 0, L.s, P);
-    else hipLaunchKernelGGL(k_flux<T>, dim3(nblk(P.nf, L.block[1])), dim3(L.block[1]), 0, L.s, P);
+    if (L.flux_pair) LAUNCH_ONE(k_flux2, T, dim3(nblk(2 * P.nf, L.block[1])), dim3(L.block[1]), P);
+    else LAUNCH_ONE(k_flux, T, dim3(nblk(P.nf, L.block[1])), dim3(L.block[1]), P);
 }
 template <typename T> void launch_gather(const Launch &L, const Params<T> &P)
 {
-    hipLaunchKernelGGL(k_gather<T>, dim3(nblk(P.nc, L.block[2])), dim3(L.block[2]), 0, L.s, P);
+    LAUNCH_ONE(k_gather, T, dim3(nblk(P.nc, L.block[2])), dim3(L.block[2]), P);
 }
 template <typename T> void launch_reduce(const Launch &L, const Params<T> &P, int it)
 {
-    hipLaunchKernelGGL(k_isum<T>, dim3(P.ninst * RB), dim3(256), 0, L.s, P);
-    hipLaunchKernelGGL(k_reduce<T>, dim3(P.ninst), dim3(64), 0, L.s, P, it);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(P.ninst * (RB + 1)), dim3(256), 0, L.s, P, it);
 }
-template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, int mode)
+template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, int mode, int lev1)
 {
     if (c1 <= c0) return;
-    dim3 g(nblk(c1 - c0, L.block[3])), b(L.block[3]);
-    if (mode == SW_FWD) hipLaunchKernelGGL((k_sweep<T, SW_FWD>), g, b, 0, L.s, P, c0, c1);
-    else if (mode == SW_BWD) hipLaunchKernelGGL((k_sweep<T, SW_BWD>), g, b, 0, L.s, P, c0, c1);
-    else hipLaunchKernelGGL((k_sweep<T, SW_TOP>), g, b, 0, L.s, P, c0, c1);
+    dim3 g(nblk(4 * (c1 - c0), L.block[3])), b(L.block[3]);
+    const bool one = P.ninst == 1;
+    if (mode == SW_FWD) {
+        if (one) hipLaunchKernelGGL((k_sweep<T, SW_FWD, true>), g, b, 0, L.s, P, c0, c1, lev1);
+        else hipLaunchKernelGGL((k_sweep<T, SW_FWD, false>), g, b, 0, L.s, P, c0, c1, lev1);
+    } else if (mode == SW_BWD) {
+        if (one) hipLaunchKernelGGL((k_sweep<T, SW_BWD, true>), g, b, 0, L.s, P, c0, c1, lev1);
+        else hipLaunchKernelGGL((k_sweep<T, SW_BWD, false>), g, b, 0, L.s, P, c0, c1, lev1);
+    } else {
+        if (one) hipLaunchKernelGGL((k_sweep<T, SW_TOP, true>), g, b, 0, L.s, P, c0, c1, lev1);
+        else hipLaunchKernelGGL((k_sweep<T, SW_TOP, false>), g, b, 0, L.s, P, c0, c1, lev1);
+    }
 }
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd)
 {
@@ -1513,7 +1692,7 @@ template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, 
     } else {
         if (one) hipLaunchKernelGGL((k_sweep_wg<T, false, true>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
         else hipLaunchKernelGGL((k_sweep_wg<T, false, false>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
-        hipLaunchKernelGGL(k_update<T>, dim3(nblk(P.nc, L.block[3])), dim3(L.block[3]), 0, L.s, P);
+        LAUNCH_ONE(k_update, T, dim3(nblk(P.nc, L.block[3])), dim3(L.block[3]), P);
     }
 }
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
@@ -1546,7 +1725,7 @@ void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, cons
     template void launch_flux<T>(const Launch &, const Params<T> &);                               \
     template void launch_gather<T>(const Launch &, const Params<T> &);                             \
     template void launch_reduce<T>(const Launch &, const Params<T> &, int);                        \
-    template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, int);               \
+    template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, int, int);          \
     template void launch_commit<T>(const Launch &, const Params<T> &, int);                        \
     template void launch_explicit<T>(const Launch &, const Params<T> &);                           \
     template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool);

@@ -21,12 +21,12 @@ KSRC = os.path.join(HERE, "csrc", "igks_kernels.hip")
 def kernel_class(name: str):
     """Kernel class of a (demangled) kernel name, as bench.py reports them."""
     table = [("k_prep", "prep"), ("k_flux2", "flux2"), ("k_flux", "flux"), ("k_gather", "gather"),
-             ("k_isum", "reduce"), ("k_reduce", "reduce"), ("k_commit", "commit"),
+             ("k_reduce", "reduce"), ("k_commit", "commit"),
              ("k_sweep_wg<double, true", "sweep_fwd"), ("k_sweep_wg<double, false", "sweep_bwd"),
              ("k_sweep_wg<float, true", "sweep_fwd"), ("k_sweep_wg<float, false", "sweep_bwd"),
-             ("k_sweep<double, 0>", "sweep_fwd"), ("k_sweep<double, 2>", "sweep_top"),
-             ("k_sweep<double, 1>", "sweep_bwd"), ("k_sweep<float, 0>", "sweep_fwd"),
-             ("k_sweep<float, 2>", "sweep_top"), ("k_sweep<float, 1>", "sweep_bwd"), ("k_update", "update"),
+             ("k_sweep<double, 0,", "sweep_fwd"), ("k_sweep<double, 2,", "sweep_top"),
+             ("k_sweep<double, 1,", "sweep_bwd"), ("k_sweep<float, 0,", "sweep_fwd"),
+             ("k_sweep<float, 2,", "sweep_top"), ("k_sweep<float, 1,", "sweep_bwd"), ("k_update", "update"),
              ("k_explicit", "update"), ("k_reset", "reset")]
     for key, cls in table:
         if key in name:
