@@ -37,7 +37,7 @@ constexpr int HIST_W = 6;     // doubles per history entry
 constexpr int NSLOT = 64;
 constexpr int SLOT_STRIDE = 16;   // unsigned long longs from one slot to the next
 enum { SL_DTMIN = 0, SL_RESINF = 1, SL_E40 = 2, NSL = 3 };   // Eq.23 minimum, max |M|, Eq.40 maximum
-constexpr int RB = 32;        // blocks per instance in the residual-norm reduction
+constexpr int NORM_SLICE = 1024;   // squares per block of the residual-norm partial sums
 constexpr int NCLASS = 4;     // kernel classes with a tunable block size: prep, flux, gather, sweep
 
 // Free stream of one instance (read-only while iterating).
@@ -104,7 +104,8 @@ struct Params {
     // per-instance cell lists (internal ids, ascending) for the norms
     const int *icell, *ioff;
     const int *ipos;           // position of each cell in icell
-    double *ipart;             // ninst x RB x 2 partial sums
+    double *ipart;             // ninst x rb x 2 partial sums
+    int rb;                    // partial sums per instance: slices of NORM_SLICE squares
     double *hist;              // HIST_W x ninst x hist_cap
     int hist_cap;
 };

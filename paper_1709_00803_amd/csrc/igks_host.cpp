@@ -466,6 +466,9 @@ struct Layout {
     }
 };
 
+// residual-norm partial sums per instance (slices of NORM_SLICE squares)
+int norm_rb(const Global &G) { return std::max(1, (G.max_inst_cells + NORM_SLICE - 1) / NORM_SLICE); }
+
 WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
 {
     Layout L;
@@ -491,7 +494,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.frr = L.add(2 * F * D); w.fdl = L.add(F * D); w.fdr = L.add(F * D); w.frn = L.add(F * D);
     w.flux = L.add(4 * F * D); w.lam = L.add(F * D); w.saf = L.add(F * D); w.sag = L.add(F * D);
     w.sak = L.add(F * D);
-    w.ipart = L.add(2 * NI * RB * D);
+    w.ipart = L.add(2 * NI * (size_t)norm_rb(G) * D);
     w.ipos = L.add(N * I);
     w.hist = L.add((size_t)HIST_W * NI * hist_cap * D);
     w.wall_faces = L.add(NW * I);
@@ -534,7 +537,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.fnx = D(w.fnx); P.fny = D(w.fny); P.flen = D(w.flen); P.frl = D(w.frl); P.frr = D(w.frr);
     P.fdl = D(w.fdl); P.fdr = D(w.fdr); P.frn = D(w.frn);
     P.flux = D(w.flux); P.lam = D(w.lam); P.saf = D(w.saf); P.sag = D(w.sag); P.sak = D(w.sak);
-    P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipos = In(w.ipos); P.ipart = D(w.ipart);
+    P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipos = In(w.ipos); P.ipart = D(w.ipart); P.rb = norm_rb(c->g);
     P.hist = D(w.hist); P.hist_cap = c->hist_cap;
 }
 

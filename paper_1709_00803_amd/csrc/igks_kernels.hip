@@ -1082,17 +1082,18 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Norm partial sums: block (i, b) sums slice b of instance i's squares
+// Norm partial sums: block (i, b) sums slice b (NORM_SLICE squares; the
+// slices past the instance's end are empty) of instance i's squares
 // (contiguous, instance-grouped) in a fixed order, so the L2 norms are
-// deterministic without float atomics; k_commit adds the RB partial sums.
+// deterministic without float atomics and the same whatever the other
+// instances of the context; k_commit adds the rb partial sums.
 template <typename T>
 __device__ __forceinline__ void norm_partial(const Params<T> &P, int blk)
 {
     __shared__ double a[256], b[256];
-    int i = blk / RB, part = blk % RB;
+    int i = blk / P.rb, part = blk % P.rb;
     int lo = P.ioff[i], n = P.ioff[i + 1] - lo;
-    int per = (n + RB - 1) / RB;
-    int s0 = lo + part * per, s1 = min(lo + n, s0 + per);
+    int s0 = lo + min(n, part * NORM_SLICE), s1 = lo + min(n, (part + 1) * NORM_SLICE);
     double x = 0.0, y = 0.0;
     const double *r2a = P.r2, *r2b = P.r2 + P.nc;
 #pragma unroll 4
@@ -1113,18 +1114,18 @@ __device__ __forceinline__ void norm_partial(const Params<T> &P, int blk)
     }
 }
 
-// Blocks [0, ninst RB): the norm partial sums.  Block ninst RB + i, first
+// Blocks [0, ninst rb): the norm partial sums.  Block ninst rb + i, first
 // wave: the Eq.23 time step the flux used, the max norm, the Eq.25 CFL law
 // (the L2 norms are not needed before the commit), history entry `it` of
 // the chunk.
 template <typename T>
 __global__ __launch_bounds__(256) void k_reduce(Params<T> P, int it)
 {
-    if ((int)blockIdx.x < P.ninst * RB) {
+    if ((int)blockIdx.x < P.ninst * P.rb) {
         norm_partial(P, blockIdx.x);
         return;
     }
-    const int i = blockIdx.x - P.ninst * RB, lane = threadIdx.x;
+    const int i = blockIdx.x - P.ninst * P.rb, lane = threadIdx.x;
     if (lane >= 64) return;
     InstScalars *s = &P.is[i];
     if (s->halt) return;
@@ -1490,8 +1491,11 @@ __global__ __launch_bounds__(64) void k_commit(Params<T> P, int it)
     InstScalars *s = &P.is[i];
     if (s->halt) return;
     double e40 = wave_max(slot_lane(P.slot, i, SL_E40));
-    double x = lane < RB ? P.ipart[2 * (i * RB + lane)] : 0.0;
-    double y = lane < RB ? P.ipart[2 * (i * RB + lane) + 1] : 0.0;
+    double x = 0.0, y = 0.0;
+    for (int k = lane; k < P.rb; k += warpSize) {
+        x += P.ipart[2 * (i * P.rb + k)];
+        y += P.ipart[2 * (i * P.rb + k) + 1];
+    }
     x = wave_sum(x);
     y = wave_sum(y);
     int bad = s->bad;
@@ -1665,7 +1669,7 @@ template <typename T> void launch_gather(const Launch &L, const Params<T> &P)
 }
 template <typename T> void launch_reduce(const Launch &L, const Params<T> &P, int it)
 {
-    hipLaunchKernelGGL(k_reduce<T>, dim3(P.ninst * (RB + 1)), dim3(256), 0, L.s, P, it);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(P.ninst * (P.rb + 1)), dim3(256), 0, L.s, P, it);
 }
 template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, int mode, int lev1)
 {
