@@ -154,6 +154,12 @@ int igks_mesh_upload(igks_ctx *ctx, int32_t n_nodes, const double *xy, int32_t n
 int igks_mesh_info(const igks_ctx *ctx, int32_t *n_cells, int32_t *n_faces, int32_t *n_wall_faces,
                    int32_t *n_levels);
 
+/* Cells in each sweep wavefront (Sec. 2.3, Eq.22: the cells of a wavefront
+ * depend only on cells of earlier ones), over all instances.  sizes: host
+ * array of cap entries; min(cap, n_levels) are written, in sweep order.
+ * IGKS_EINVAL for a null pointer, cap < 1 or an instance without a mesh. */
+int igks_wavefront_sizes(const igks_ctx *ctx, int32_t *sizes, int32_t cap);
+
 /* Device bytes the library needs for the uploaded mesh and options. */
 int igks_workspace_size(const igks_ctx *ctx, size_t *bytes);
 
@@ -264,10 +270,25 @@ int igks_get_schedule(const igks_ctx *ctx, int32_t *schedule6);
  * directly, not through graphs, and times each kernel class with HIP events
  * on the context's stream; igks_get_kernel_times then gives the average ms
  * per iteration of: prep (with the Eq.23 time step), flux, gather, norms
- * (with the Eq.25 CFL), sweep_fwd (all wavefronts), sweep_bwd (all
- * wavefronts, with the update and commit).  0 when profiling was off. */
+ * (with the Eq.25 CFL), sweep_fwd (the forward steps of the wavefronts
+ * after the first, and the last one's backward step), sweep_bwd (the other
+ * backward steps, with the Eq.17 update; the commit belongs to no class).
+ * 0 when profiling was off.  Each interval includes the cost of its two
+ * events (a few microseconds). */
 int igks_set_profiling(igks_ctx *ctx, int on);
 int igks_get_kernel_times(igks_ctx *ctx, double *ms6);
+
+/* Average ms per launch of one residual-phase kernel class (klass 0 prep
+ * with the Eq.23 time step, 1 flux (Eq.4-14), 2 gather (Eq.16)), from reps
+ * back-to-back launches between two HIP events on the context's stream,
+ * preceded by the launches that produce its inputs from the current state.
+ * These kernels write only derived arrays, so the state, the iteration
+ * count and the next iteration are unchanged.  Synchronises the stream.
+ * IGKS_EINVAL for a null pointer, klass outside 0..2, reps outside
+ * 1..10000, or before the workspace and every free stream are set;
+ * IGKS_ENONPHYS when an instance is frozen; IGKS_EHIP when a HIP call
+ * fails. */
+int igks_time_kernel(igks_ctx *ctx, int32_t klass, int32_t reps, double *ms);
 
 #ifdef __cplusplus
 }

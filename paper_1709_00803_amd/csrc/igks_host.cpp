@@ -588,8 +588,8 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev, int it)
     if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, false);
     else
         for (int l = G.nlev - 2; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], 1, lev1);
+    mark(6);   // the backward sweeps' class ends here; the commit belongs to no class
     launch_commit(L, P, it);
-    mark(6);
 }
 
 template <typename T>
@@ -802,6 +802,42 @@ int tune_run(igks_ctx *c, const Params<T> &P, int iters)
 
 // ====================================================================== C ABI
 
+// `reps` launches of one residual-phase kernel class back to back between
+// two events, after the launches that produce its inputs; the classes timed
+// here read the state and write only derived arrays and idempotent min/max
+// slots, which are cleared afterwards, so the iteration is unaffected
+template <typename T>
+static int time_class(igks_ctx *c, const Params<T> &P, int klass, int reps, double *ms)
+{
+    Launch L = launch_of(c);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, IGKS_EHIP, "hipEventCreate failed");
+    }
+    launch_reset(L, P, 1, -1);
+    if (klass >= 1) launch_prep(L, P);
+    if (klass >= 2) launch_flux(L, P);
+    (void)hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps; r++) {
+        if (klass == 0) launch_prep(L, P);
+        else if (klass == 1) launch_flux(L, P);
+        else launch_gather(L, P);
+    }
+    (void)hipEventRecord(e1, c->stream);
+    launch_reset(L, P, 1, -1);
+    hipError_t err = hipGetLastError();
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(c, IGKS_EHIP, std::string("kernel timing: ") + hipGetErrorString(err));
+    *ms = (double)t / reps;
+    return IGKS_OK;
+}
+
 extern "C" {
 
 void igks_default_options(igks_options *o)
@@ -905,6 +941,17 @@ int igks_mesh_info(const igks_ctx *cc, int32_t *nc, int32_t *nf, int32_t *nw, in
     if (nf) *nf = c->g.F;
     if (nw) *nw = c->g.nwall;
     if (nl) *nl = c->g.nlev;
+    return IGKS_OK;
+}
+
+int igks_wavefront_sizes(const igks_ctx *cc, int32_t *sizes, int32_t cap)
+{
+    igks_ctx *c = const_cast<igks_ctx *>(cc);
+    if (!c || !sizes || cap < 1) return IGKS_EINVAL;
+    int rc = ensure_combined(c);
+    if (rc) return rc;
+    const int n = std::min<int>(cap, c->g.nlev);
+    for (int l = 0; l < n; l++) sizes[l] = c->g.lev_off[l + 1] - c->g.lev_off[l];
     return IGKS_OK;
 }
 
@@ -1225,6 +1272,17 @@ int igks_set_profiling(igks_ctx *c, int on)
     if (!c) return IGKS_EINVAL;
     c->profiling = on != 0;
     return IGKS_OK;
+}
+
+int igks_time_kernel(igks_ctx *c, int32_t klass, int32_t reps, double *ms)
+{
+    if (!c || !ms || klass < 0 || klass > 2 || reps < 1 || reps > 10000) return IGKS_EINVAL;
+    int rc = check_ready(c, true);
+    if (rc) return rc;
+    for (size_t i = 0; i < c->inst.size(); i++)
+        if (c->hs[i].halt) return fail(c, IGKS_ENONPHYS, "instance " + std::to_string(i) + " is frozen");
+    return (c->opt.precision == IGKS_MIXED) ? time_class(c, c->P32, klass, reps, ms)
+                                            : time_class(c, c->P64, klass, reps, ms);
 }
 
 int igks_get_kernel_times(igks_ctx *c, double *ms6)

@@ -63,6 +63,7 @@ _SIGS = {
     "igks_last_error": (C.c_char_p, [_P]),
     "igks_mesh_upload": (C.c_int, [_P, C.c_int32, _DP, C.c_int32, _IP, _IP, C.c_int32, _IP, _IP]),
     "igks_mesh_info": (C.c_int, [_P, _IP, _IP, _IP, _IP]),
+    "igks_wavefront_sizes": (C.c_int, [_P, _IP, C.c_int32]),
     "igks_workspace_size": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "igks_bind_workspace": (C.c_int, [_P, _P, C.c_size_t]),
     "igks_set_freestream": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double]),
@@ -76,6 +77,7 @@ _SIGS = {
     "igks_get_wall_loads": (C.c_int, [_P, _DP, _DP, _DP, _DP, _DP]),
     "igks_set_profiling": (C.c_int, [_P, C.c_int]),
     "igks_get_kernel_times": (C.c_int, [_P, _DP]),
+    "igks_time_kernel": (C.c_int, [_P, C.c_int32, C.c_int32, _DP]),
     "igks_batch_create": (C.c_int, [C.POINTER(_P), C.POINTER(igks_options), _P, C.c_int32]),
     "igks_batch_mesh_upload": (C.c_int, [_P, C.c_int32, C.c_int32, _DP, C.c_int32, _IP, _IP, C.c_int32, _IP, _IP]),
     "igks_batch_mesh_info": (C.c_int, [_P, C.c_int32, _IP, _IP, _IP]),
@@ -185,6 +187,19 @@ class _Context:
 
     def set_profiling(self, on=True):
         self._chk(igks_set_profiling(self.ctx, 1 if on else 0))
+
+    def wavefront_sizes(self):
+        """Cells per sweep wavefront (all instances), in sweep order."""
+        out = np.zeros(max(1, self.nlev), dtype=np.int32)
+        self._chk(igks_wavefront_sizes(self.ctx, out.ctypes.data_as(_IP), len(out)))
+        return out
+
+    def time_kernel(self, klass, reps=50):
+        """ms per launch of kernel class klass ("prep", "flux" or "gather"),
+        from back-to-back launches between two events."""
+        ms = C.c_double()
+        self._chk(igks_time_kernel(self.ctx, ("prep", "flux", "gather").index(klass), reps, C.byref(ms)))
+        return ms.value
 
     def kernel_times(self):
         t = np.zeros(len(KERNEL_CLASSES))

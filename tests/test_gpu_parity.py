@@ -411,6 +411,59 @@ def test_deterministic_runs(igks):
     assert np.array_equal(runs[0], runs[1])
 
 
+def dependency_levels(mesh):
+    """Sweep wavefront of each cell in upload order: 0 without a lower-numbered
+    neighbour, else one more than the largest wavefront of those."""
+    _, nb = mg.cell_adjacency(mesh)
+    lev = np.zeros(mesh.n_cells, dtype=np.int64)
+    for c in range(mesh.n_cells):
+        lower = nb[c][(nb[c] >= 0) & (nb[c] < c)]
+        lev[c] = 1 + lev[lower].max() if len(lower) else 0
+    return lev
+
+
+def test_wavefront_sizes(igks):
+    """igks_wavefront_sizes against the dependency levels computed here, for
+    a natural and a colour order and for a batch (wavefront l of a batch holds
+    wavefront l of every instance)."""
+    m = mg.random_hybrid(12, 9, seed=12, tags=TAGS_SYM)
+    mc = mg.colour_order(m)[0]
+    for mesh in (m, mc):
+        lev = dependency_levels(mesh)
+        g = igks.Solver(mesh)
+        sizes = g.wavefront_sizes()
+        say("wavefronts", g.nlev, "sizes", sizes[:6], "...")
+        assert g.nlev == lev.max() + 1
+        assert np.array_equal(sizes, np.bincount(lev))
+    b = igks.BatchSolver([m, mc])
+    want = np.zeros(b.nlev, dtype=np.int64)
+    for mesh in (m, mc):
+        bc = np.bincount(dependency_levels(mesh))
+        want[:len(bc)] += bc
+    assert np.array_equal(b.wavefront_sizes(), want)
+
+
+def test_time_kernel_leaves_iteration_unchanged(igks):
+    """igks_time_kernel between two chunks of iterations: the same states,
+    scalars and history as without it."""
+    m = mg.random_hybrid(10, 8, seed=31, tags=TAGS_SYM)
+    runs = []
+    for timed in (False, True):
+        g = igks.Solver(m, cfl_init=20.0, chunk=4)
+        g.set_freestream(0.3, 1.0, 3e4, 3.0)
+        g.iterate(4)
+        if timed:
+            for k in ("prep", "flux", "gather"):
+                ms = g.time_kernel(k, 5)
+                say(f"[time_kernel] {k}: {ms * 1e3:.2f} us per launch")
+                assert ms > 0.0
+        g.iterate(4)
+        runs.append((g.get_state(), g.residual(), g.history()))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1] == runs[1][1]
+    assert np.array_equal(runs[0][2], runs[1][2])
+
+
 def test_graph_chunks_match_direct_launches(igks):
     m = mg.random_hybrid(10, 8, seed=10, tags=TAGS_ALL)
     m, _, _ = mg.colour_order(m)
