@@ -96,7 +96,7 @@ struct Params {
     // face arrays (internal face order)
     const int *fl, *fr, *fbc;
     const double *fnx, *fny, *flen, *frl, *frr, *fdl, *fdr, *frn;
-    double *flux;              // 4 x nf: time-averaged flux times length, global frame
+    double *flux;              // nf x 4 (the four components of a face together): time-averaged flux times length, global frame
     double *lam;               // spectral radius per face
     double *saf;               // SA: (-F_inv + F_vis) S
     double *sag;               // SA: (nu~_r - nu~_l)/|r.n| S

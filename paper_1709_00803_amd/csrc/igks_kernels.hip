@@ -862,7 +862,6 @@ __device__ __forceinline__ void flux_global(const double *Fr, double dt, double 
 template <typename T>
 __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, double dt)
 {
-    const int F = P.nf;
     const InstParam &ip = P.ip[inst];
     const double *W = cur_state(P, inst);
     FaceSide L, R;
@@ -897,7 +896,7 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, d
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
 #pragma unroll
-    for (int k = 0; k < 4; k++) P.flux[k * F + f] = g[k];
+    for (int k = 0; k < 4; k++) P.flux[4 * (size_t)f + k] = g[k];
 }
 
 // Per face, on a pair of lanes (side 0 the owner, side 1 the neighbour or
@@ -908,7 +907,6 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, d
 template <typename T>
 __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int side, int inst, double dt)
 {
-    const int F = P.nf;
     const InstParam &ip = P.ip[inst];
     const double *W = cur_state(P, inst);
     FaceSide M;
@@ -945,8 +943,8 @@ __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int si
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
     // each lane writes two of the four components
-    P.flux[(2 * side) * F + f] = side ? g[2] : g[0];
-    P.flux[(2 * side + 1) * F + f] = side ? g[3] : g[1];
+    P.flux[4 * (size_t)f + 2 * side] = side ? g[2] : g[0];
+    P.flux[4 * (size_t)f + 2 * side + 1] = side ? g[3] : g[1];
 }
 
 // one lane per face
@@ -1007,7 +1005,7 @@ __device__ __forceinline__ void wall_face_terms(const Params<T> &P, const InstPa
 template <typename T>
 __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int inst)
 {
-    const int N = P.nc, F = P.nf;
+    const int N = P.nc;
     const InstParam &ip = P.ip[inst];
     const double *W = cur_state(P, inst);
     double m[4] = {0, 0, 0, 0}, ls = 0.0, saR = 0.0, sagS = 0.0, sad = 0.0;
@@ -1023,7 +1021,7 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
             double sg = (E.flag[k] & CF_OWNER) ? 1.0 : -1.0;
             double g[4];
 #pragma unroll
-            for (int k = 0; k < 4; k++) g[k] = P.flux[k * F + f];
+            for (int k = 0; k < 4; k++) g[k] = P.flux[4 * (size_t)f + k];
             if (E.nbr[k] < 0) wall_face_terms(P, ip, w, f, g);
 #pragma unroll
             for (int k = 0; k < 4; k++) m[k] -= sg * g[k];
@@ -1604,7 +1602,7 @@ __global__ void k_gather_faces(int n, const int *faces, const double *flux, int 
     if (i >= n) return;
     int f = faces[i];
 #pragma unroll
-    for (int k = 0; k < 4; k++) out[4 * i + k] = flux[k * nf + f];
+    for (int k = 0; k < 4; k++) out[4 * i + k] = flux[4 * (size_t)f + k];
 }
 
 __global__ void k_fill_instance(int n, const int *cells, int nc, double w0, double w1, double w2, double w3,
