@@ -1,0 +1,42 @@
+"""bench.py on the CPU: the one-GPU guard and the algorithmic byte model
+(no GPU is touched: the guard exits before anything is imported)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_more_than_one_gpu_is_refused(n):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_kernel_bytes_model():
+    n, f, e = 1000, 1550, 3100
+    lam = bench.kernel_bytes(n, f, e, False, False)
+    sa = bench.kernel_bytes(n, f, e, True, False)
+    mixed = bench.kernel_bytes(n, f, e, False, True)
+    assert set(lam) == {"prep", "flux", "gather", "reduce", "sweep_fwd", "sweep_bwd"}
+    assert all(v > 0 for v in lam.values())
+    # the backward step also reads its own increment and writes the new state
+    assert lam["sweep_bwd"] > lam["sweep_fwd"]
+    # SA adds face and cell terms to the flux, gather and sweeps; FP32 increments shrink the sweeps only
+    for k in ("flux", "gather", "sweep_fwd", "sweep_bwd"):
+        assert sa[k] > lam[k]
+    for k in ("sweep_fwd", "sweep_bwd"):
+        assert mixed[k] < lam[k]
+    for k in ("prep", "flux", "gather", "reduce"):
+        assert mixed[k] == lam[k]
+    # linear in the sizes
+    dbl = bench.kernel_bytes(2 * n, 2 * f, 2 * e, False, False)
+    for k in lam:
+        assert dbl[k] == 2 * lam[k]
