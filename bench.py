@@ -244,11 +244,13 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=100,
+                    help="untimed iterations; at least --chunk, so the timed chunks replay an already captured graph")
     ap.add_argument("--workload", default="jouk40k", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64, mixed for batch64")
-    ap.add_argument("--chunk", type=int, default=20)
+    ap.add_argument("--chunk", type=int, default=100,
+                    help="iterations per captured HIP graph (one host synchronisation per chunk)")
     ap.add_argument("--profile-iters", type=int, default=20)
     ap.add_argument("--autotune", type=int, default=None, help="autotuner iterations per candidate (default 5, 0: off)")
     ap.add_argument("--cfl-init", type=float, default=None, help="initial implicit CFL (default: 1000, 10 for batch64)")
