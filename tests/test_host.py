@@ -39,7 +39,7 @@ def info(ctx):
     return rc, [x.value for x in v]
 
 
-def levels_by_hand(mesh):
+def cell_levels(mesh):
     """Wavefront of each cell: 1 + the largest wavefront among its
     neighbours of smaller index (0 without any)."""
     _, nb = mg.cell_adjacency(mesh)
@@ -47,7 +47,17 @@ def levels_by_hand(mesh):
     for i in range(mesh.n_cells):
         lower = nb[i][(nb[i] >= 0) & (nb[i] < i)]
         lev[i] = 1 + lev[lower].max() if len(lower) else 0
-    return int(lev.max()) + 1
+    return lev
+
+
+def levels_by_hand(mesh):
+    return int(cell_levels(mesh).max()) + 1
+
+
+def wavefront_sizes(ctx, cap):
+    out = np.full(cap + 2, -7, dtype=np.int32)
+    rc = igks.igks_wavefront_sizes(ctx, out.ctypes.data_as(C.POINTER(C.c_int32)), cap)
+    return rc, out
 
 
 def broken_meshes():
@@ -131,6 +141,14 @@ def test_counts_and_wavefronts(make):
         o = po.Oracle(mesh)
         assert (nc, nf, nw) == (o.n, o.nf, o.nwall)
         assert nl == levels_by_hand(mesh)
+        rc, sizes = wavefront_sizes(ctx, nl)
+        assert rc == igks.IGKS_OK
+        assert np.array_equal(sizes[:nl], np.bincount(cell_levels(mesh)))
+        assert (sizes[nl:] == -7).all()
+        rc, part = wavefront_sizes(ctx, 1)            # a short array gets the first wavefronts only
+        assert rc == igks.IGKS_OK and part[0] == sizes[0] and (part[1:] == -7).all()
+        assert wavefront_sizes(ctx, 0)[0] == igks.IGKS_EINVAL
+        assert igks.igks_wavefront_sizes(ctx, None, 4) == igks.IGKS_EINVAL
         sz = C.c_size_t()
         assert igks.igks_workspace_size(ctx, C.byref(sz)) == igks.IGKS_OK
         assert sz.value >= (2 * 5 + 5) * 8 * nc      # two state buffers and the residual at least
@@ -162,6 +180,12 @@ def test_batch_bookkeeping():
             per.append((o.n, o.nf, o.nwall, levels_by_hand(m)))
         assert nc == sum(p[0] for p in per) and nf == sum(p[1] for p in per) and nw == sum(p[2] for p in per)
         assert nl == max(p[3] for p in per)      # wavefronts of different instances run together
+        want = np.zeros(nl, dtype=np.int64)
+        for m in meshes:
+            bc = np.bincount(cell_levels(m))
+            want[:len(bc)] += bc
+        rc, sizes = wavefront_sizes(ctx, nl)
+        assert rc == igks.IGKS_OK and np.array_equal(sizes[:nl], want)
         assert igks.igks_workspace_size(ctx, C.byref(sz)) == igks.IGKS_OK
         one = []
         for m in meshes:
@@ -191,8 +215,14 @@ def test_call_order_and_option_errors():
         assert igks.igks_iterate(ctx, 1, C.byref(done)) == igks.IGKS_EINVAL
         assert done.value == 0
         assert igks.igks_set_freestream(ctx, 0.3, 0.0, 1e4, -1.0) == igks.IGKS_EINVAL
+        ms = C.c_double()
+        assert igks.igks_wavefront_sizes(ctx, (C.c_int32 * 4)(), 4) == igks.IGKS_EINVAL   # no mesh yet
         assert upload(ctx, mg.random_hybrid(3, 3, seed=4)) == igks.IGKS_OK
         # no workspace bound yet
+        assert igks.igks_time_kernel(ctx, 1, 5, C.byref(ms)) == igks.IGKS_EINVAL
+        for klass, reps in ((-1, 5), (3, 5), (0, 0), (2, 10001)):
+            assert igks.igks_time_kernel(ctx, klass, reps, C.byref(ms)) == igks.IGKS_EINVAL
+        assert igks.igks_time_kernel(ctx, 0, 5, None) == igks.IGKS_EINVAL
         assert igks.igks_set_freestream(ctx, 0.3, 0.0, 1e4, -1.0) == igks.IGKS_EINVAL
         assert igks.igks_autotune(ctx, 3, None) == igks.IGKS_EINVAL
         r = igks.igks_residual()
