@@ -431,6 +431,39 @@ def test_level_schedule_invariance():
     assert np.allclose(dW2, dW[:, perm], rtol=1e-11, atol=1e-13 * np.abs(dW).max())
 
 
+def test_cfl_law_telescopes():
+    """Eq.25 scales the implicit CFL number by the ratio of successive max
+    norms of the residual, so CFL^n ||M^n||_inf keeps its first value while
+    no clamp engages (an inverted ratio, a lagged one or another norm breaks
+    this); with clamps the number stays inside them and the first iteration
+    uses the initial value."""
+    m = mg.random_hybrid(8, 6, seed=41, tags=dict(bottom=mg.WALL, top=mg.FARFIELD, left=mg.FREESTREAM,
+                                                   right=mg.OUTFLOW), jitter=0.3)
+    rows = {}
+    for name, lo, hi in (("free", 1e-12, 1e12), ("clamped", 1.5, 2.5)):
+        o = po.Oracle(m, cfl_init=2.0, cfl_min=lo, cfl_max=hi)
+        o.set_freestream(0.4, 3.0, 800.0, -1.0)
+        c = o.cells()
+        W = o.get_state()
+        rng = np.random.default_rng(41)
+        W[0] *= 1.0 + 0.05 * np.sin(4.0 * c["xc"] + rng.uniform(0, 6)) * np.cos(3.0 * c["yc"])
+        o.set_state(W)
+        out = []
+        for _ in range(12):
+            o.iterate(1)
+            r = o.residual()
+            out.append((r["iteration"], r["cfl"], r["res_inf"]))
+        rows[name] = np.array(out)
+    free = rows["free"]
+    assert free[0, 1] == 2.0
+    prod = free[:, 1] * free[:, 2]
+    assert np.allclose(prod, prod[0], rtol=1e-12, atol=0)
+    assert np.ptp(free[:, 2]) > 0.1 * free[:, 2].max()      # the residual does change
+    cl = rows["clamped"][:, 1]
+    assert cl[0] == 2.0 and (cl >= 1.5).all() and (cl <= 2.5).all()
+    assert ((cl == 1.5) | (cl == 2.5)).any()
+
+
 def test_explicit_limit():
     """CFL -> 0: dW -> (dt_imp / Omega) M = (CFL / Lambda_c) M (Eq.18-24)."""
     m = mg.random_hybrid(6, 5, seed=9, tags=dict(bottom=mg.WALL))
