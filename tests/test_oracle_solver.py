@@ -431,6 +431,22 @@ def test_level_schedule_invariance():
     assert np.allclose(dW2, dW[:, perm], rtol=1e-11, atol=1e-13 * np.abs(dW).max())
 
 
+@pytest.mark.parametrize("mach,alpha,cfl_flux", [(0.5, 30.0, 1.0), (0.2, -70.0, 0.4)])
+def test_time_step_on_a_uniform_mesh(mach, alpha, cfl_flux):
+    """Eq.21 and Eq.23 in closed form: for a uniform state on squares of side
+    h, Lambda_c = 2 h (|U| + |V| + 2 c) with c = 1/Ma the free-stream sound
+    speed (|V_inf| = 1), so dt = cfl_flux h^2 / Lambda_c in every cell."""
+    n = 8
+    h = 1.0 / n
+    o = po.Oracle(mg.cavity(n), cfl_flux=cfl_flux)
+    o.set_freestream(mach, alpha, 1e3, -1.0)
+    o.iterate(1)
+    a = np.radians(alpha)
+    lamc = 2.0 * h * (abs(np.cos(a)) + abs(np.sin(a)) + 2.0 / mach)
+    assert np.allclose(o.debug()["lamc"], lamc, rtol=1e-13)
+    assert o.residual()["dt_flux"] == pytest.approx(cfl_flux * h * h / lamc, rel=1e-13)
+
+
 def test_cfl_law_telescopes():
     """Eq.25 scales the implicit CFL number by the ratio of successive max
     norms of the residual, so CFL^n ||M^n||_inf keeps its first value while
