@@ -447,6 +447,23 @@ def test_time_step_on_a_uniform_mesh(mach, alpha, cfl_flux):
     assert o.residual()["dt_flux"] == pytest.approx(cfl_flux * h * h / lamc, rel=1e-13)
 
 
+def test_eq40_from_successive_states():
+    """The reported Eq.40 value is the largest per-cell |W^{n+1} - W^n| / |W^n|
+    (2-norm over the four conservative variables, reading R10) of the states
+    the iteration actually produced."""
+    m = mg.random_hybrid(7, 5, seed=43, tags=dict(bottom=mg.WALL, top=mg.FARFIELD, left=mg.FREESTREAM,
+                                                   right=mg.OUTFLOW), jitter=0.3)
+    o = po.Oracle(m, cfl_init=3.0)
+    o.set_freestream(0.3, 2.0, 500.0, -1.0)
+    for _ in range(4):
+        W0 = o.get_state()
+        o.iterate(1)
+        W1 = o.get_state()
+        want = (np.linalg.norm(W1[:4] - W0[:4], axis=0) / np.linalg.norm(W0[:4], axis=0)).max()
+        assert want > 0.0
+        assert o.residual()["eq40"] == pytest.approx(want, rel=1e-12)
+
+
 def test_cfl_law_telescopes():
     """Eq.25 scales the implicit CFL number by the ratio of successive max
     norms of the residual, so CFL^n ||M^n||_inf keeps its first value while
