@@ -447,6 +447,27 @@ def test_time_step_on_a_uniform_mesh(mach, alpha, cfl_flux):
     assert o.residual()["dt_flux"] == pytest.approx(cfl_flux * h * h / lamc, rel=1e-13)
 
 
+def test_update_adds_the_lusgs_increment():
+    """Eq.17: an iteration from a fresh start moves the state by the LU-SGS
+    increment at the initial CFL number (the solve that
+    test_lusgs_solves_factored_system pins), nu~ clipped at zero."""
+    m = mg.random_hybrid(7, 5, seed=44, tags=dict(bottom=mg.WALL, top=mg.FARFIELD, left=mg.FREESTREAM,
+                                                   right=mg.OUTFLOW), jitter=0.3)
+    o = po.Oracle(m, cfl_init=4.0)
+    o.set_freestream(0.3, 2.0, 2e4, 3.0)
+    c = o.cells()
+    W0 = o.get_state()
+    W0[0] *= 1.0 + 0.05 * np.sin(5.0 * c["xc"]) * np.cos(3.0 * c["yc"])
+    W0[4] *= np.where(np.arange(o.n) % 3 == 0, 1e-3, 1.0)     # an uneven nu~ field
+    o.set_state(W0)
+    dW = o.lusgs_solve(4.0)
+    o.iterate(1)
+    W1 = o.get_state()
+    assert np.array_equal(W1[:4], W0[:4] + dW[:4])
+    assert np.array_equal(W1[4], np.maximum(W0[4] + dW[4], 0.0))
+    assert np.abs(dW[:4]).max() > 0.0
+
+
 def test_eq40_from_successive_states():
     """The reported Eq.40 value is the largest per-cell |W^{n+1} - W^n| / |W^n|
     (2-norm over the four conservative variables, reading R10) of the states
