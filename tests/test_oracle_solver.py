@@ -411,6 +411,60 @@ def test_lusgs_solves_factored_system(top):
     assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
 
 
+def test_sa_lusgs_solves_factored_system():
+    """The SA sweeps (Eq.31-32) solve (D - L) D^-1 (D - U - G) dnu~ = R_SA,
+    where the off-diagonal coefficient of neighbour j seen from cell i is the
+    upwind inflow -u_j^- S plus the diffusion coefficient k S / |r.n| of the
+    face, D is the SA diagonal and G holds the lagged ghost increments of
+    Sec. 2.5 (nu~ negated at walls, kept at symmetry faces, zero elsewhere);
+    the diagonal holds at least its time and face parts."""
+    sigma, cb2 = 2.0 / 3.0, 0.622
+    tags = dict(bottom=mg.WALL, top=mg.FARFIELD, left=mg.FREESTREAM, right=mg.SYMMETRY)
+    m = mg.colour_order(mg.random_hybrid(5, 4, seed=9, tags=tags))[0]
+    o = po.Oracle(m)
+    o.set_freestream(0.3, 3.0, 5e5, 3.0)
+    W = smooth_state(o, 0.1, 4)
+    o.set_state(W)
+    cfl = 50.0
+    M, _ = o.compute_residual()
+    dW = o.lusgs_solve(cfl)
+    dbg = o.debug(); f = o.faces(); c = o.cells(); n = o.n
+    Dsa, wg = dbg["Dsa"], dbg["wg"]
+
+    def nu_lam(w):
+        lam = 5.0 * w[0] / (4.0 * (w[3] - 0.5 * (w[1] ** 2 + w[2] ** 2) / w[0]))
+        return o.mu(lam) / w[0]
+
+    def coef(wa, wb, nx, ny, S, rn):
+        qa = (wa[1] * nx + wa[2] * ny) / wa[0]
+        qb = (wb[1] * nx + wb[2] * ny) / wb[0]
+        k = (0.5 * (nu_lam(wa) + nu_lam(wb)) + (1.0 + cb2) * 0.5 * (wa[4] + wb[4])) / sigma
+        return 0.5 * (qa + abs(qa)) * S + k * S / rn, -0.5 * (qb - abs(qb)) * S + k * S / rn
+
+    L = np.zeros((n, n)); U = np.zeros((n, n)); G = np.zeros(n); diag_faces = np.zeros(n)
+    for q in range(o.nf):
+        i, j = f["fl"][q], f["fr"][q]
+        nx, ny, S = f["nx"][q], f["ny"][q], f["len"][q]
+        if j >= 0:
+            rn = abs((c["xc"][j] - c["xc"][i]) * nx + (c["yc"][j] - c["yc"][i]) * ny)
+            for a, b, sg in ((i, j, 1.0), (j, i, -1.0)):
+                dg, off = coef(W[:, a], W[:, b], sg * nx, sg * ny, S, rn)
+                diag_faces[a] += dg
+                (L if b < a else U)[a, b] += off
+        else:
+            rn = 2.0 * ((f["xm"][q] - c["xc"][i]) * nx + (f["ym"][q] - c["yc"][i]) * ny)
+            dg, off = coef(W[:, i], wg[:, q], nx, ny, S, rn)
+            diag_faces[i] += dg
+            B = {mg.WALL: -1.0, mg.MOVING_WALL: -1.0, mg.SYMMETRY: 1.0}.get(int(f["bc"][q]), 0.0)
+            G[i] += off * B
+    assert (Dsa >= dbg["lamc"] / cfl + diag_faces - 1e-12 * Dsa).all()
+    D = np.diag(Dsa)
+    dws = np.linalg.solve(D - L, M[4])
+    want = np.linalg.solve(D - U, (D + np.diag(G)) @ dws)
+    assert np.abs(want).max() > 0.0 and np.abs(G).max() > 0.0
+    assert np.abs(dW[4] - want).max() <= 1e-10 * np.abs(want).max()
+
+
 def test_level_schedule_invariance():
     """Cells of one colour are independent in the sweeps: renumbering cells
     inside a colour does not change the update."""
