@@ -766,6 +766,28 @@ def test_sa_source_limits():
     assert s_lo[1] > 0
 
 
+def test_sa_convection_exact_for_linear_field():
+    """Eq.29 with a uniform stream along x: the first-order upwind transport
+    of nu~ = a + b x on a uniform mesh gives an interior cell -Omega U b
+    exactly, on top of the diffusion term of the same linear field (see the
+    next test); reversing the stream reverses the convective part."""
+    tags = dict(bottom=mg.SYMMETRY, top=mg.SYMMETRY, left=mg.FREESTREAM, right=mg.FREESTREAM)
+    m = mg.random_hybrid(10, 6, seed=0, tri_frac=0.0, jitter=0.0, tags=tags)
+    a, b = 2e-3, 5e-3
+    for alpha, U in ((0.0, 1.0), (180.0, -1.0)):
+        o = po.Oracle(m, mu_law=1)
+        o.set_freestream(0.2, alpha, 1e3, 3.0)
+        W = o.get_state(); c = o.cells()
+        W[4] = a + b * c["xc"]
+        o.set_state(W)
+        M, _ = o.compute_residual()
+        f = o.faces()
+        interior = np.ones(o.n, bool)
+        interior[f["fl"][f["fr"] < 0]] = False
+        want = c["area"] * (-U * b + (1 + SA_CB2) * b * b / SA_SIG)
+        assert np.allclose(M[4, interior], want[interior], rtol=1e-9)
+
+
 def test_sa_diffusion_exact_for_linear_field():
     """Eq.28-30 with zero velocity: for nu~ = a + b x on a uniform mesh the
     discrete residual of an interior cell is Omega (1 + c_b2) b^2 / sigma,
