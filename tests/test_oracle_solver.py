@@ -234,6 +234,28 @@ def test_isothermal_box_at_wall_temperature_is_steady():
             assert M[3].sum() < 0
 
 
+def test_collision_time_limits():
+    """Eq.33-34: tau = (mu + mu_t) / p with p = rho / (2 lambda): without
+    nu~ (or laminar) tau = mu / p; mu_t = rho nu~ f_v1 grows with nu~, and for
+    nu~ much larger than nu the damping f_v1 -> 1 leaves mu_t = rho nu~."""
+    m = mg.random_hybrid(3, 3, seed=1)
+    o = po.Oracle(m)
+    o.set_freestream(0.3, 0.0, 1e4, 3.0)
+    rho, lam = 1.3, 0.07
+    p = rho / (2.0 * lam)
+    mu = o.mu(lam)
+    assert o.collision_time(rho, lam, 0.0) == pytest.approx(mu / p, rel=1e-15)
+    big = 1e7 * mu / rho
+    assert o.collision_time(rho, lam, big) == pytest.approx((mu + rho * big) / p, rel=1e-12)
+    taus = [o.collision_time(rho, lam, x * mu / rho) for x in (0.1, 1.0, 7.1, 30.0, 100.0)]
+    assert all(b > a for a, b in zip(taus, taus[1:]))
+    # a chi of 7.1 (= c_v1) halves the damping: mu_t = rho nu~ / 2
+    assert taus[2] == pytest.approx((mu + 0.5 * 7.1 * mu) / p, rel=1e-12)
+    lamo = po.Oracle(m)
+    lamo.set_freestream(0.3, 0.0, 1e4, -1.0)
+    assert lamo.collision_time(rho, lam, big) == pytest.approx(mu / p, rel=1e-15)
+
+
 def test_pressure_jump_collision_time():
     """tau_jump adds dissipation only where the reconstructed pressures of a
     face differ: gas at rest with uniform energy (so uniform pressure in
