@@ -14,7 +14,7 @@
  *     Eq.31-32, with the ghost-cell boundary conditions of Sec. 2.5;
  *   on a 2D hybrid mesh (triangles, quadrilaterals and polygons of up to
  *   eight vertices, such as the pentagons and hexagons that hanging nodes
- *   of an adaptive quadtree make, Sec. 2.4 and Sec. 4.1) given in the
+ *   of an adaptive quadtree make, Sec. 2.4 and Sec. 3.1) given in the
  *   node / per-cell vertex list form of Sec. 2.4, on one GPU.
  *
  * Conventions
@@ -142,7 +142,11 @@ const char *igks_last_error(const igks_ctx *ctx);
  * face); n_bfaces boundary edges bface_nodes[2*b], [2*b+1] with tags
  * bface_tag[b] (IGKS_BC_*).  All host memory, copied.
  * IGKS_EMESH: a cell with fewer than 3 or more than 8 nodes, a degenerate
- * (zero-area) cell, an edge shared by more than two cells, a cell edge on
+ * (zero-area) cell, a non-convex cell (a vertex where the boundary turns
+ * back by more than asin(0.1), about 5.7 degrees: the slight reflex turn of
+ * a hanging node on a curved edge is accepted) or one whose centroid is not
+ * strictly inside the half plane of each of its faces (the centroid-face
+ * distances of Eq.5 divide), an edge shared by more than two cells, a cell edge on
  * the boundary without a tag, a tagged edge that is not on the boundary, a
  * bad tag, or a node index out of range.  Replaces any previous mesh and
  * unbinds the workspace. */
@@ -154,7 +158,7 @@ int igks_mesh_upload(igks_ctx *ctx, int32_t n_nodes, const double *xy, int32_t n
 int igks_mesh_info(const igks_ctx *ctx, int32_t *n_cells, int32_t *n_faces, int32_t *n_wall_faces,
                    int32_t *n_levels);
 
-/* Cells in each sweep wavefront (Sec. 2.3, Eq.22: the cells of a wavefront
+/* Cells in each sweep wavefront (Sec. 2.2, Eq.22: the cells of a wavefront
  * depend only on cells of earlier ones), over all instances.  sizes: host
  * array of cap entries; min(cap, n_levels) are written, in sweep order.
  * IGKS_EINVAL for a null pointer, cap < 1 or an instance without a mesh. */
@@ -170,13 +174,19 @@ int igks_workspace_size(const igks_ctx *ctx, size_t *bytes);
 int igks_bind_workspace(igks_ctx *ctx, void *dptr, size_t bytes);
 
 /* Free stream (Mach, angle of attack in degrees, Reynolds number per unit
- * reference length, nu-tilde_inf / nu_inf).  nut_ratio < 0 runs laminar
+ * reference length, nu-tilde_inf / nu_inf): the state W_inf of the
+ * free-stream boundary condition (Sec. 2.5) and of the impulsive start, in
+ * the non-dimensionalisation above; nu-tilde_inf is the SA inflow value
+ * (Sec. 2.3, Sec. 3.3).  nut_ratio < 0 runs laminar
  * (no SA equation).  Sets every cell to the free stream (impulsive start),
  * the iteration counter to 0 and the CFL to cfl_init.  IGKS_EINVAL if
  * Ma <= 0 or Re <= 0 or no workspace is bound. */
 int igks_set_freestream(igks_ctx *ctx, double mach, double alpha_deg, double reynolds, double nut_ratio);
 
-/* Run n nonlinear iterations (residual, CFL law, LU-SGS sweeps, update).
+/* Run n nonlinear iterations of Sec. 2.2: the residual of Eq.16 (GKS face
+ * fluxes Eq.4-14 with the Eq.23 time step, SA right-hand side Eq.27-30),
+ * the CFL law Eq.24-25, the LU-SGS sweeps Eq.18-22 and Eq.31-32 and the
+ * update Eq.17, plus the Eq.40 convergence measure.
  * Work is queued in chunks of opt.chunk iterations (one HIP graph launch
  * each) and the stream is synchronised at each chunk end.  *n_done (may be
  * NULL) = iterations committed (instance 0).  IGKS_ENONPHYS: an update

@@ -113,7 +113,8 @@ static void seterr(oigks_ctx *c, const char *m) { snprintf(c->err, sizeof c->err
 
 /* ======================================================================
  * Velocity-space polynomials and Maxwellian moments (Sec. 2.1, Eq.2,
- * Eq.100-101).  A polynomial is a list of monomials c * u^pu v^pv (xi^2)^px.
+ * and the slope expansion and moment relations between Eq.4 and Eq.5).
+ * A polynomial is a list of monomials c * u^pu v^pv (xi^2)^px.
  * ==================================================================== */
 #define PMAX 64
 typedef struct { double c; int pu, pv, px; } mono;
@@ -140,7 +141,7 @@ static void p_axpy(double s, const poly *a, poly *y)
 {
     for (int i = 0; i < a->n; i++) p_add_mono(y, s * a->m[i].c, a->m[i].pu, a->m[i].pv, a->m[i].px);
 }
-/* collision invariants psi = (1, u, v, (u^2+v^2+xi^2)/2) (Sec. 2.1 after Eq.101) */
+/* collision invariants psi = (1, u, v, (u^2+v^2+xi^2)/2) (Sec. 2.1, the moment relations after Eq.4) */
 static void p_psi(int i, poly *p)
 {
     p_zero(p);
@@ -149,7 +150,8 @@ static void p_psi(int i, poly *p)
     else if (i == 2) p_add_mono(p, 1.0, 0, 1, 0);
     else { p_add_mono(p, 0.5, 2, 0, 0); p_add_mono(p, 0.5, 0, 2, 0); p_add_mono(p, 0.5, 0, 0, 1); }
 }
-/* Taylor-coefficient form a = a1 + a2 u + a3 v + a4 (u^2+v^2+xi^2)/2 (Eq.100) */
+/* Taylor-coefficient form a = a1 + a2 u + a3 v + a4 (u^2+v^2+xi^2)/2 (Sec. 2.1, the
+ * slope expansion after Eq.4) */
 static void p_coef(const double a[4], poly *p)
 {
     p_zero(p);
@@ -210,7 +212,8 @@ static void p_int_psi(const poly *p, const moms *m, double out[4])
         out[3] += 0.5 * t->c * (mu[2] * mv[0] * mx[0] + mu[0] * mv[2] * mx[0] + mu[0] * mv[0] * mx[1]);
     }
 }
-/* moment matrix M_ij = <psi_i psi_j> (left side of Eq.101 divided by rho) */
+/* moment matrix M_ij = <psi_i psi_j> (left side of the Sec. 2.1 moment
+ * relations after Eq.4, divided by rho) */
 static void moment_matrix(const moms *m, double M[16])
 {
     for (int j = 0; j < 4; j++) {
@@ -243,7 +246,7 @@ static int gauss4(const double Min[16], const double b[4], double x[4])
     }
     return 0;
 }
-/* Eq.101: integral of g a psi = dW  ->  M(g) a = dW / rho */
+/* Sec. 2.1 moment relations (after Eq.4): integral of g a psi = dW  ->  M(g) a = dW / rho */
 static void solve_slope(const moms *full, double rho, const double dW[4], double a[4])
 {
     double M[16], b[4];
@@ -303,7 +306,7 @@ static void gks_core(const double Wl[4], const double Gln[4], const double Glt[4
     mk_moms(U0, V0, lam0, +1, &m0p);
     mk_moms(U0, V0, lam0, -1, &m0m);
 
-    /* Eq.4 slopes from the reconstructed derivatives (Eq.101) */
+    /* Eq.4 slopes from the reconstructed derivatives (the Sec. 2.1 moment relations) */
     solve_slope(&mlf, rl, Gln, o->aln);
     solve_slope(&mlf, rl, Glt, o->alt);
     solve_slope(&mrf, rr, Grn, o->arn);
@@ -546,6 +549,22 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
         }
         if (!(a > 0)) { seterr(c, "degenerate cell"); return -2; }
         c->area[i] = 0.5 * a; c->xc[i] = ox + sx / (3.0 * a); c->yc[i] = oy + sy / (3.0 * a);
+        /* convexity (Sec. 2.4 cells are convex polygons; reading: a vertex
+         * where the counter-clockwise boundary turns clockwise by more than
+         * asin(0.1), about 5.7 degrees, makes the cell non-convex, while the
+         * slight reflex turn of a hanging node on a curved edge is accepted),
+         * and every face must see the centroid on its inner side, since the
+         * centroid-to-face distance d of Eq.5 divides */
+        for (int j = 0; j < k; j++) {
+            int nm = c->cnod[p0 + (j + k - 1) % k], n0 = c->cnod[p0 + j], np = c->cnod[p0 + (j + 1) % k];
+            double e1x = c->x[n0] - c->x[nm], e1y = c->y[n0] - c->y[nm];
+            double e2x = c->x[np] - c->x[n0], e2y = c->y[np] - c->y[n0];
+            double turn = (e1x * e2y - e1y * e2x) / (sqrt(e1x * e1x + e1y * e1y) * sqrt(e2x * e2x + e2y * e2y));
+            if (!(turn >= -0.1)) { seterr(c, "non-convex cell"); return -2; }
+            double ax = c->x[n0] - c->xc[i], ay = c->y[n0] - c->yc[i];
+            double bx = c->x[np] - c->xc[i], by = c->y[np] - c->yc[i];
+            if (!(ax * by - ay * bx > 0)) { seterr(c, "cell centroid outside a face's half plane"); return -2; }
+        }
     }
     /* edges: sort (min node, max node) keys and pair them */
     edge_rec *E = malloc(sizeof(edge_rec) * nv);

@@ -7,7 +7,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboigks.so")
+# OIGKS_LIB names another build of the same source (the mutation tests load
+# copies with a planted mistake this way)
+LIB_PATH = os.environ.get("OIGKS_LIB") or os.path.join(HERE, "liboigks.so")
 
 _lib = None
 

@@ -18,6 +18,10 @@ using namespace igks;
 
 namespace {
 
+// A cell is non-convex where its counter-clockwise boundary turns clockwise
+// by more than asin(MAX_REFLEX_SIN), about 5.7 degrees.
+constexpr double MAX_REFLEX_SIN = 0.1;
+
 // One instance, in its upload order.
 struct InstMesh {
     bool ok = false;
@@ -193,6 +197,19 @@ int build_instance(igks_ctx *ctx, int n_nodes, const double *xy, int n_cells, co
         m.area[i] = 0.5 * a2;
         m.xc[i] = x0 + sx / (3.0 * a2);
         m.yc[i] = y0 + sy / (3.0 * a2);
+        // convex: no vertex turns clockwise by more than asin(MAX_REFLEX_SIN)
+        // (hanging nodes on curved edges turn back slightly), and the
+        // centroid lies strictly inside every face's half plane (the
+        // centroid-face distances d_l, d_r divide in the face flux)
+        for (int j = 0; j < k; j++) {
+            const double *pa = &xy[2 * m.cn[p0 + (j + k - 1) % k]], *pb = &xy[2 * m.cn[p0 + j]],
+                         *pc = &xy[2 * m.cn[p0 + (j + 1) % k]];
+            const double ux = pb[0] - pa[0], uy = pb[1] - pa[1], vx = pc[0] - pb[0], vy = pc[1] - pb[1];
+            const double sn = (ux * vy - uy * vx) / (std::hypot(ux, uy) * std::hypot(vx, vy));
+            if (!(sn >= -MAX_REFLEX_SIN)) return fail(ctx, IGKS_EMESH, "non-convex cell " + std::to_string(i));
+            const double cr = (pb[0] - m.xc[i]) * (pc[1] - m.yc[i]) - (pb[1] - m.yc[i]) * (pc[0] - m.xc[i]);
+            if (!(cr > 0)) return fail(ctx, IGKS_EMESH, "cell " + std::to_string(i) + ": centroid outside a face");
+        }
     }
     // edges -> faces
     struct E { long long key; int cell, loc; };

@@ -360,7 +360,8 @@ __device__ __forceinline__ void pmom1(const double *mu, const double *mv, const 
 }
 
 // Closed-form solution of M(g) a = b for the Maxwellian moment matrix
-// M_ij = <psi_i psi_j> (Eq.101 divided by rho).
+// M_ij = <psi_i psi_j> (the Sec. 2.1 moment relations after Eq.4, divided
+// by rho), in the closed form of Xu's BGK scheme (Xu 2001, J. Comput. Phys.).
 __device__ __forceinline__ void msolve(double U, double V, double lam, double hl, const double *b, double *a)
 {
     double B = U * U + V * V + (KDOF + 2.0) * hl;
@@ -385,7 +386,7 @@ __device__ __forceinline__ double add_sides(double a, double b)
 }
 
 // One side's part of the interface distribution that does not depend on the
-// equilibrium state: slopes a_n, a_t (Eq.4, Eq.101), A (Eq.11) and the
+// equilibrium state: slopes a_n, a_t (Eq.4 and the moment relations after it), A (Eq.11) and the
 // half-space moments that multiply them, for the left state on u > 0
 // (sgn = +1) or the right state on u < 0 (sgn = -1).  Writes (rho-weighted)
 //   acc[0..3] = <psi>, acc[4..7] = <(u a_n + v a_t) psi>, acc[8..11] = <A psi>,

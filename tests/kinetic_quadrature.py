@@ -1,5 +1,5 @@
 """Brute-force velocity-space and time quadrature of the paper's kinetic
-expressions (Sec. 2.1: Eq.2, Eq.100-101, Eq.11-14), independent of the
+expressions (Sec. 2.1: Eq.2, the slope expansion and moment relations after Eq.4, Eq.11-14), independent of the
 oracle's moment recursions and closed-form time integrals.
 
 A Maxwellian g = rho (lam/pi)^((K+2)/2) exp(-lam((u-U)^2 + (v-V)^2 + xi^2))
@@ -59,7 +59,7 @@ def psi(u, v, x2):
 
 
 def poly(a, u, v, x2):
-    """Eq.100: a1 + a2 u + a3 v + a4 (u^2 + v^2 + xi^2) / 2"""
+    """Slope expansion of Sec. 2.1 (after Eq.4): a1 + a2 u + a3 v + a4 (u^2 + v^2 + xi^2) / 2"""
     return a[0] + a[1] * u + a[2] * v + 0.5 * a[3] * (u * u + v * v + x2)
 
 

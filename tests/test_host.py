@@ -94,6 +94,18 @@ def broken_meshes():
     out["degenerate"] = mg.Mesh(xy=xy, cell_ptr=np.array([0, 3], np.int32), cell_nodes=np.arange(3, dtype=np.int32),
                                 bface_nodes=np.array([[0, 1], [1, 2], [2, 0]], np.int32),
                                 bface_tag=np.full(3, mg.FREESTREAM, np.int32), meta={})
+    # a non-convex quadrilateral (an arrowhead: the vertex (1, 1) turns back by 90 degrees)
+    xy = np.array([[0, 0], [2, 0], [1, 1], [1, 2]], float)
+    out["non-convex"] = mg.Mesh(xy=xy, cell_ptr=np.array([0, 4], np.int32), cell_nodes=np.arange(4, dtype=np.int32),
+                                bface_nodes=np.array([[0, 1], [1, 2], [2, 3], [3, 0]], np.int32),
+                                bface_tag=np.full(4, mg.FREESTREAM, np.int32), meta={})
+    # a reflex turn of 11.4 degrees (sine -0.198) at a middle vertex of a pentagon
+    h = 0.05
+    xy = np.array([[0, 0], [1, 0], [1, 1], [0.5, 1 - h], [0, 1]], float)
+    out["reflex pentagon"] = mg.Mesh(xy=xy, cell_ptr=np.array([0, 5], np.int32),
+                                     cell_nodes=np.arange(5, dtype=np.int32),
+                                     bface_nodes=np.array([[k, (k + 1) % 5] for k in range(5)], np.int32),
+                                     bface_tag=np.full(5, mg.FREESTREAM, np.int32), meta={})
     # three triangles on one edge
     xy = np.array([[0, 0], [1, 0], [0.5, 1], [0.5, -1], [0.6, 0.5]], float)
     cells = np.array([0, 1, 2, 0, 3, 1, 0, 1, 4], np.int32)
@@ -119,6 +131,34 @@ def test_mesh_validation_matches_oracle(name):
     finally:
         igks.igks_destroy(ctx)
     if name != "nine nodes":      # the oracle takes any polygon; the library up to eight vertices
+        with pytest.raises(po.OracleError):
+            po.Oracle(mesh)
+
+
+def reflex_pentagon(h):
+    """A unit square whose top edge has a middle vertex pushed down by h:
+    its boundary turns back there by asin(h / (0.25 + h^2))."""
+    xy = np.array([[0, 0], [1, 0], [1, 1], [0.5, 1 - h], [0, 1]], float)
+    return mg.Mesh(xy=xy, cell_ptr=np.array([0, 5], np.int32), cell_nodes=np.arange(5, dtype=np.int32),
+                   bface_nodes=np.array([[k, (k + 1) % 5] for k in range(5)], np.int32),
+                   bface_tag=np.full(5, mg.FREESTREAM, np.int32), meta={})
+
+
+@pytest.mark.parametrize("h,ok", [(0.0, True), (0.02, True), (0.024, True), (0.0255, False), (0.05, False)])
+def test_convexity_threshold(h, ok):
+    """A hanging node on a curved edge turns the boundary back slightly and is
+    accepted; a turn back by more than asin(0.1) (h above 0.02506 here) makes
+    the cell non-convex.  Library and oracle agree."""
+    mesh = reflex_pentagon(h)
+    rc, ctx = ctx_for()
+    try:
+        rc = upload(ctx, mesh)
+        assert rc == (igks.IGKS_OK if ok else igks.IGKS_EMESH), (h, rc, igks.igks_last_error(ctx).decode())
+    finally:
+        igks.igks_destroy(ctx)
+    if ok:
+        po.Oracle(mesh)
+    else:
         with pytest.raises(po.OracleError):
             po.Oracle(mesh)
 

@@ -102,7 +102,7 @@ def _rand_face(rng, scale=1.0):
 @pytest.mark.parametrize("seed,dt,tau", [(3, 0.01, 0.004), (4, 0.002, 0.02), (5, 0.05, 0.001)])
 def test_face_flux_by_brute_force(seed, dt, tau):
     """Every coefficient of the interface distribution satisfies its
-    defining integral (Eq.101, Eq.11, Eq.12), W0 is the moment of
+    defining integral (the Sec. 2.1 moment relations after Eq.4, Eq.11, Eq.12), W0 is the moment of
     H g^l + (1-H) g^r, and F equals the (t, u, v, xi) quadrature of Eq.14."""
     rng = np.random.default_rng(seed)
     Wl, Gln, Glt, Wr, Grn, Grt, Wlc, Wrc = _rand_face(rng)
