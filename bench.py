@@ -1,14 +1,18 @@
 """Benchmark: implicit gas-kinetic scheme iterations on one MI355X.
 
 A step is one full nonlinear iteration (Eq.16 residual with the GKS face
-flux, Eq.25 CFL law, LU-SGS forward and backward sweeps, update) over
+flux, Eq.25 CFL law, LU-SGS forward and backward sweeps, Eq.17 update) over
 every cell of the workload mesh; the metric is cell-updates per second
 (cells x iterations / wall time), inputs resident in HBM.
 
-Default workload: Joukowski airfoil hybrid mesh (128 wall points, 30 quad
-layers, first height 1e-4 chord, growth 1.12, seeded Delaunay triangles out
-to 20 chords, ~40k cells, colour-ordered), Ma 0.5, Re 5000, alpha 2 deg,
-laminar, FP64.
+Default workload: the 2M-cell SA Joukowski hybrid mesh (2048 wall points,
+90 quad layers from 1e-6 chord growing by 1.10, seeded Delaunay triangles out
+to 20 chords, colour-ordered), Ma 0.15, Re 6e6, alpha 4 deg, SA with
+nu~_inf = 3 nu_inf, FP64; also measured on it: the mixed-precision form, and
+beside it the 64-instance batch (mixed), the time to a 1e-10 residual drop
+of the laminar plate (FP64, mixed, batched, explicit), the lid-driven
+cavity and the turbulent plate to the Eq.40 criterion, and the CPU oracle
+on a sample of the same workload.
 
 Prints one JSON line.
 """
@@ -30,22 +34,31 @@ WORKLOADS = {
     "jouk250k": dict(flow=(0.15, 4.0, 6e6, 3.0), desc="Joukowski hybrid, 512 wall pts, 60 quad layers (2e-6, 1.15), "
                                                       "Ma 0.15 Re 6e6 alpha 4, SA nu~/nu = 3"),
     "jouk2m": dict(flow=(0.15, 4.0, 6e6, 3.0), desc="Joukowski hybrid, 2048 wall pts, 90 quad layers (1e-6, 1.10), "
-                                                    "Ma 0.15 Re 6e6 alpha 4, SA nu~/nu = 3"),
+                                                    "seeded Delaunay to r=20 chords, Ma 0.15 Re 6e6 alpha 4, SA nu~/nu = 3"),
     "plate64x32": dict(flow=(0.3, 0.0, 1e4, -1.0), desc="laminar flat plate 64x32 quads, Ma 0.3 Re_L 1e4"),
     "batch64": dict(flow=None, desc="64 seeded instances (default_rng(1000+b)): even b flat plate, odd b Joukowski "
                                     "hybrid, cells log-uniform 5e3-2e5, Ma U[0.1,0.6], alpha U[-4,12] (airfoils), "
-                                    "Re log-uniform 1e4-1e7, SA iff Re>1e5; one graph launch per chunk, autotuned"),
+                                    "Re log-uniform 1e4-1e7, SA iff Re>1e5; one graph launch per chunk"),
 }
+# launch schedules (block sizes of prep, flux, gather, sweep; sweep schedule;
+# lanes per face) found by igks_autotune on these workloads; block sizes never
+# change results
+SCHEDULES = {"jouk2m": [256, 128, 64, 256, 1, 2], "batch64": [256, 128, 256, 64, 1, 2],
+             "jouk40k": [128, 64, 64, 64, 1, 1]}
 # plate variants of the batched time-to-1e-10 comparison: (Ma, Re_L)
 DROP_BATCH = [(0.2, 5e3), (0.25, 8e3), (0.3, 1e4), (0.35, 1.5e4), (0.4, 2e4), (0.3, 6e3), (0.2, 1.2e4), (0.4, 1e4)]
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
-FP64_VALU_PEAK_TFS = 78.6   # MI355X FP64 vector
-# FP64 operations per face of k_flux, counted with rocprofv3: FP64 VALU
-# instructions per wave (2 x FMA + MUL + ADD + TRANS); one face per lane, so
-# this is also the operation count of one face.
+FP64_VALU_PEAK_TFS = 78.6   # MI355X FP64 vector: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+# FP64 operations per face of the face flux, counted with rocprofv3 on the
+# one-lane kernel: FP64 VALU instructions per wave (2 x FMA + MUL + ADD +
+# TRANS), one face per lane.  The algorithmic figure for either flux kernel.
 FLUX_FLOP_PER_FACE = 3488.0
 KSRC = os.path.join(ROOT, "paper_1709_00803_amd", "csrc", "igks_kernels.hip")
+
+
+def say(*a):
+    print("#", *a, file=sys.stderr, flush=True)
 
 
 def kernel_bytes(n, f, e, sa, mixed):
@@ -82,7 +95,7 @@ def kernel_source_hash():
     return hashlib.sha256(open(KSRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(workload, kernel):
+def measured_traffic(workload, cls):
     """HBM bytes per launch of a kernel class from the committed counter
     summary (profiles/traffic_<workload>.json), or None when the kernels
     changed since the counters were taken."""
@@ -92,7 +105,183 @@ def measured_traffic(workload, kernel):
     d = json.load(open(path))
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch", {}).get(kernel)
+    return d.get("bytes_per_launch", {}).get(cls)
+
+
+def load_meshes(mg, name, cache):
+    """The workload's meshes and flow conditions, generated from their seeds
+    or, with a cache directory, read back from an earlier generation."""
+    path = os.path.join(cache, f"{name}.npz") if cache else None
+    if path and os.path.exists(path):
+        d = np.load(path, allow_pickle=False)
+        n = int(d["n"])
+        meshes = [mg.Mesh(xy=d[f"xy{i}"], cell_ptr=d[f"cp{i}"], cell_nodes=d[f"cn{i}"], bface_nodes=d[f"bn{i}"],
+                          bface_tag=d[f"bt{i}"], meta={}) for i in range(n)]
+        return meshes, [tuple(f) for f in d["flows"]]
+    if name == "batch64":
+        meshes, flows = mg.batch(64)
+    else:
+        meshes, flows = [mg.workload(name)], [WORKLOADS[name]["flow"]]
+    if path:
+        os.makedirs(cache, exist_ok=True)
+        arrs = {"n": len(meshes), "flows": np.array(flows, dtype=float)}
+        for i, m in enumerate(meshes):
+            arrs.update({f"xy{i}": m.xy, f"cp{i}": m.cell_ptr, f"cn{i}": m.cell_nodes, f"bn{i}": m.bface_nodes,
+                         f"bt{i}": m.bface_tag})
+        np.savez(path + ".tmp.npz", **arrs)
+        os.replace(path + ".tmp.npz", path)
+    return meshes, flows
+
+
+def graph_chunk(chunk, steps, warmup):
+    """Iterations per captured graph: at most `chunk`, `steps` and (when there
+    is a warm-up) `warmup`, and a divisor of `steps`, so that the warm-up
+    captures the graph and every timed iteration is a graph replay."""
+    c = max(1, min(chunk, steps, warmup if warmup > 0 else steps))
+    while steps % c:
+        c -= 1
+    return c
+
+
+def time_windows(solver, steps, repeats, batched):
+    """`repeats` windows of exactly `steps` iterations, each bracketed by a
+    device synchronisation; returns the seconds of each window."""
+    import torch
+    times = []
+    for r in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(solver, steps, batched)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return times
+
+
+def run(solver, k, batched):
+    """k iterations; a batch instance frozen by a rejected update is
+    reported, not fatal: the others go on."""
+    from paper_1709_00803_amd import igks
+    try:
+        solver.iterate(k)
+    except igks.IgksError as e:
+        if not batched or e.code != igks.IGKS_ENONPHYS:
+            raise
+        say(str(e))
+
+
+def committed(solver, batched, n_inst):
+    if batched:
+        return [solver.residual(i)["iteration"] for i in range(n_inst)]
+    return [solver.residual()["iteration"]]
+
+
+def measure(igks, meshes, flows, precision, args, schedule, label):
+    """Throughput of one context: warm-up, `repeats` timed windows of `steps`
+    iterations (median reported), then a profiling pass of direct launches
+    timed per kernel class with HIP events on the library's stream."""
+    import torch
+    batched = len(meshes) > 1
+    mixed = precision == igks.IGKS_MIXED
+    cfl0 = args.cfl_init if args.cfl_init is not None else (10.0 if batched else 1000.0)
+    chunk = graph_chunk(args.chunk, args.steps, args.warmup)
+    t = time.perf_counter()
+    if batched:
+        solver = igks.BatchSolver(meshes, precision=precision, chunk=chunk, cfl_init=cfl0)
+        for i, f in enumerate(flows):
+            solver.set_freestream(i, *f)
+        nfs = solver.nf
+    else:
+        solver = igks.Solver(meshes[0], precision=precision, chunk=chunk, cfl_init=cfl0)
+        solver.set_freestream(*flows[0])
+        nfs = [solver.nf]
+    torch.cuda.synchronize()
+    say(f"{label}: {len(meshes)} instance(s), {solver.total_cells} cells, {solver.total_faces} faces, "
+        f"{solver.nlev} wavefronts, set up in {time.perf_counter() - t:.1f}s")
+    if args.autotune > 0:
+        schedule = solver.autotune(args.autotune).tolist()
+    elif schedule is not None:
+        solver.set_schedule(schedule)
+    schedule = solver.schedule().tolist()
+    gc_iters, launches_per_it = solver.graph_chunk()
+    run(solver, args.warmup, batched)
+    c0 = committed(solver, batched, len(meshes))
+    times = time_windows(solver, args.steps, args.repeats, batched)
+    c1 = committed(solver, batched, len(meshes))
+    # updates committed over all windows (frozen instances do not count)
+    updates = sum(m.n_cells * (b - a) for m, a, b in zip(meshes, c0, c1))
+    per_window = updates / args.repeats
+    med = float(np.median(times))
+    value = per_window / med
+    say(f"{label}: windows of {args.steps} iterations: {[round(x * 1e3, 3) for x in times]} ms, "
+        f"{value:.4g} cell-updates/s")
+    if batched:
+        drops = [solver.residual(i)["res_drop"] for i in range(len(meshes))]
+        frozen = [i for i in range(len(meshes)) if solver.status(i)]
+        res_info = dict(res_drop_after_min=min(drops), res_drop_after_median=float(np.median(drops)),
+                        res_drop_after_max=max(drops), frozen_instances=frozen)
+    else:
+        res_info = dict(res_drop_after=solver.residual()["res_drop"])
+    # per-kernel durations inside iterations: HIP events on the library's
+    # stream around each kernel class, direct launches
+    solver.set_profiling(True)
+    run(solver, args.profile_iters, batched)
+    kt = solver.kernel_times()      # ms per iteration, per kernel class
+    solver.set_profiling(False)
+    kb = {}
+    for m, f, nf in zip(meshes, flows, nfs):
+        e = int(np.sum(np.diff(m.cell_ptr)))
+        for k, v in kernel_bytes(m.n_cells, nf, e, f[3] >= 0, mixed).items():
+            kb[k] = kb.get(k, 0) + v
+    sweep_wg = schedule[4] == 2
+    if not sweep_wg and solver.nlev > 1:
+        # one launch per wavefront: the forward class covers wavefronts
+        # 1 .. nlev-1 (the first wavefront's forward increments are formed
+        # where they are read), the backward class wavefronts nlev-2 .. 0 (the
+        # last one's backward step runs in the forward class's last launch);
+        # their bytes are the per-cell model over the cells they process
+        sizes = solver.wavefront_sizes()
+        ntot = float(sizes.sum())
+        kb["sweep_fwd"] *= (ntot - sizes[0]) / ntot
+        kb["sweep_bwd"] *= (ntot - sizes[-1]) / ntot
+    out = dict(value=value, ms_per_step=1e3 * med / args.steps, window_ms=[round(x * 1e3, 4) for x in times],
+               cells=solver.total_cells, faces=solver.total_faces, wavefronts=solver.nlev, schedule=schedule,
+               chunk=chunk, graph_replays_per_window=args.steps // gc_iters if gc_iters else 0,
+               launches_per_iteration=launches_per_it, cfl_init=cfl0, cell_updates_timed=updates, **res_info)
+    return solver, out, kt, kb
+
+
+def roofline_of(args, solver, kt, kb, out, mixed):
+    """The dominant kernel class against its roofline, from its launch
+    duration inside the iterations of the profiling pass."""
+    faces = solver.total_faces
+    schedule = out["schedule"]
+    dom = max(kt, key=lambda k: kt[k])
+    sweep_wg = schedule[4] == 2
+    launches = {"sweep_fwd": 1 if sweep_wg else max(solver.nlev - 1, 1),
+                "sweep_bwd": 1 if sweep_wg else max(solver.nlev - 1, 1)}.get(dom, 1)
+    launch_ms = kt[dom] / launches
+    if dom == "flux":
+        achieved = FLUX_FLOP_PER_FACE * faces / (launch_ms * 1e-3) / 1e12
+        r = dict(kernel="k_flux2" if schedule[5] == 2 else "k_flux", bound="alu", achieved=achieved,
+                 peak=FP64_VALU_PEAK_TFS, unit="TFLOP/s", frac=achieved / FP64_VALU_PEAK_TFS,
+                 algorithmic_flop_per_launch=FLUX_FLOP_PER_FACE * faces)
+        cls = "flux2" if schedule[5] == 2 else "flux"
+    else:
+        achieved = kb[dom] / launches / (launch_ms * 1e-3) / 1e9
+        r = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                 frac=achieved / HBM_PEAK_GBS, algorithmic_bytes_per_launch=kb[dom] / launches)
+        cls = dom
+    tr = measured_traffic(args.workload, cls)
+    r.update(traffic=tr, traffic_unit="HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+             launch_ms=launch_ms, launches_per_step=launches,
+             algorithmic_bytes_per_launch_of_its_arrays=kb.get(dom, 0.0) / launches,
+             kernel_ms_per_step={k: round(v, 5) for k, v in kt.items()},
+             hbm_gbs_per_kernel={k: round(kb[k] / (kt[k] * 1e-3) / 1e9, 1) for k in kb if kt.get(k, 0) > 0})
+    total = sum(kb.values())
+    it_gbs = total / (out["ms_per_step"] * 1e-3) / 1e9
+    r["iteration"] = dict(algorithmic_bytes=total, achieved_gbs=it_gbs, frac_of_hbm_peak=it_gbs / HBM_PEAK_GBS,
+                          note="all kernel classes of one iteration: compulsory bytes over the timed ms per step")
+    return r
 
 
 def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=10.0, chunk=100):
@@ -212,181 +401,135 @@ def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000):
                 fp64_iterations_to_target=its_seq, speedup=round(t_seq / t_batch, 3))
 
 
-def run_cpu_baseline(cases, budget_s=12.0, max_it=60):
-    """The oracle on a bounded sample: iterations of the given (mesh, flow)
-    cases in turn after one untimed start iteration each, ~budget_s."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def host_threads():
+    """Host cores this process may use, at most 16 (the CPU share of one GPU
+    on the benchmark machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def run_cpu_baseline(mesh, flow, name, budget_s=25.0):
+    """The oracle on a bounded sample of the workload: the mesh ingest and the
+    impulsive-start iteration untimed (on all threads), then iterations on
+    one thread and on all host threads (the oracle's per-cell and per-face
+    loops; its sweeps stay sequential; results are bitwise the same).  About
+    budget_s of CPU work."""
     from oracle import pyoracle as po
-    cells, its, dt = 0, 0, 0.0
-    names = []
-    for mesh, flow in cases:
-        o = po.Oracle(mesh)
-        o.set_freestream(*flow)
-        o.iterate(1)     # the impulsive-start iteration, untimed
+    nt = host_threads()
+    t = time.perf_counter()
+    o = po.Oracle(mesh, threads=nt)
+    o.set_freestream(*flow)
+    o.iterate(1)
+    setup = time.perf_counter() - t
+    res = {}
+    for threads, share in ((1, 0.6), (nt, 0.4)):
+        o.set_threads(threads)
         t0 = time.perf_counter()
         it = 0
-        while it < max_it:
+        while True:
             o.iterate(1)
             it += 1
-            if dt + time.perf_counter() - t0 > budget_s:
+            if time.perf_counter() - t0 > share * budget_s:
                 break
-        dt += time.perf_counter() - t0
-        cells += mesh.n_cells * it
-        its += it
-        names.append(f"{mesh.n_cells} cells x {it}")
-        if dt > budget_s:
-            break
-    return dict(value=cells / dt, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=f"iterations of the same workload ({'; '.join(names)}) after one untimed start iteration "
-                       f"each, single-threaded FP64 C oracle, {dt:.1f} s")
+        dt = time.perf_counter() - t0
+        res[threads] = (mesh.n_cells * it / dt, it, dt)
+        say(f"cpu oracle, {threads} thread(s): {it} iterations in {dt:.1f}s")
+    v1, i1, d1 = res[1]
+    vn, i_n, dn = res[nt]
+    return dict(value=vn, unit="cell-updates/s", cores=nt, kind="oracle", cpu_model=cpu_model(),
+                single_thread=dict(value=v1, cores=1, iterations=i1, seconds=round(d1, 2)),
+                sample=f"{name} ({mesh.n_cells} cells): after the untimed mesh ingest and impulsive-start iteration "
+                       f"({setup:.1f}s on {nt} threads), {i_n} iteration(s) on {nt} threads in {dn:.1f}s (value) and "
+                       f"{i1} on one thread in {d1:.1f}s; FP64 C oracle, OpenMP over its cell and face loops, "
+                       f"sequential sweeps, results independent of the thread count")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=100,
-                    help="untimed iterations; at least --chunk, so the timed chunks replay an already captured graph")
-    ap.add_argument("--workload", default="jouk40k", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=20, help="iterations per timed window")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed iterations before the timed windows")
+    ap.add_argument("--repeats", type=int, default=5, help="timed windows of --steps iterations (median reported)")
+    ap.add_argument("--workload", default="jouk2m", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64, mixed for batch64")
-    ap.add_argument("--chunk", type=int, default=100,
-                    help="iterations per captured HIP graph (one host synchronisation per chunk)")
-    ap.add_argument("--profile-iters", type=int, default=20)
-    ap.add_argument("--autotune", type=int, default=None, help="autotuner iterations per candidate (default 5, 0: off)")
+    ap.add_argument("--chunk", type=int, default=20,
+                    help="largest number of iterations per captured HIP graph; cut to divide --steps and to "
+                         "at most --warmup, so the timed iterations replay a graph the warm-up captured")
+    ap.add_argument("--profile-iters", type=int, default=10)
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="autotuner iterations per candidate (0: the stored schedule of the workload)")
     ap.add_argument("--cfl-init", type=float, default=None, help="initial implicit CFL (default: 1000, 10 for batch64)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 runs")
+    ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 and Eq.40 runs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision and batch64 extra measurements")
+    ap.add_argument("--mesh-cache", default=None,
+                    help="directory where generated meshes are stored and read back (the seeded generation "
+                         "of the 2M-cell mesh takes about a minute)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the batched and single-mesh paths are single-GPU).", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.repeats < 1 or args.warmup < 0:
+        print("bench.py: --steps and --repeats must be >= 1, --warmup >= 0", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_1709_00803_amd import igks
     from paper_1709_00803_amd import meshgen as mg
 
+    torch.cuda.set_device(0)
     wl = WORKLOADS[args.workload]
     batched = args.workload == "batch64"
     precision = args.precision or ("mixed" if batched else "fp64")
     mixed = precision == "mixed"
-    tune = args.autotune if args.autotune is not None else 5
     t = time.perf_counter()
-    if batched:
-        meshes, flows = mg.batch(64)
-    else:
-        meshes, flows = [mg.workload(args.workload)], [wl["flow"]]
-    t_mesh = time.perf_counter() - t
-    torch.cuda.set_device(0)
+    meshes, flows = load_meshes(mg, args.workload, args.mesh_cache)
+    say(f"{args.workload}: meshes ready in {time.perf_counter() - t:.1f}s")
     prec = igks.IGKS_MIXED if mixed else igks.IGKS_FP64
-    cfl0 = args.cfl_init if args.cfl_init is not None else (10.0 if batched else 1000.0)
-    if batched:
-        solver = igks.BatchSolver(meshes, precision=prec, chunk=args.chunk, cfl_init=cfl0)
-        for i, f in enumerate(flows):
-            solver.set_freestream(i, *f)
-        nfs = solver.nf
-    else:
-        solver = igks.Solver(meshes[0], precision=prec, chunk=args.chunk, cfl_init=cfl0)
-        solver.set_freestream(*flows[0])
-        nfs = [solver.nf]
-    n = solver.total_cells
-    print(f"# {args.workload}: {len(meshes)} instance(s), {n} cells, {solver.total_faces} faces, "
-          f"{solver.nlev} wavefronts, generated in {t_mesh:.1f}s", file=sys.stderr, flush=True)
-    schedule = solver.autotune(tune).tolist() if tune > 0 else solver.schedule().tolist()
-
-    def run(k):
-        """k iterations; a batch instance frozen by a rejected update is
-        reported, not fatal: the others go on."""
-        try:
-            solver.iterate(k)
-        except igks.IgksError as e:
-            if not batched or e.code != igks.IGKS_ENONPHYS:
-                raise
-            print(f"# {e}", file=sys.stderr, flush=True)
-
-    def committed():
-        if batched:
-            return [solver.residual(i)["iteration"] for i in range(len(meshes))]
-        return [solver.residual()["iteration"]]
-
-    run(args.warmup)
-    c0 = committed()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    # cell updates actually committed (frozen instances do not count)
-    updates = sum(m.n_cells * (b - a) for m, a, b in zip(meshes, c0, committed()))
-    value = updates / elapsed
-    if batched:
-        drops = [solver.residual(i)["res_drop"] for i in range(len(meshes))]
-        frozen = [i for i in range(len(meshes)) if solver.status(i)]
-        res_info = dict(res_drop_after_min=min(drops), res_drop_after_median=float(np.median(drops)),
-                        res_drop_after_max=max(drops), frozen_instances=frozen)
-    else:
-        res_info = dict(res_drop_after=solver.residual()["res_drop"])
-    print(f"# timed {args.steps} iterations in {elapsed:.3f}s, {res_info}", file=sys.stderr, flush=True)
-
-    # per-kernel durations: HIP events on the library's stream, direct launches
-    solver.set_profiling(True)
-    run(args.profile_iters)
-    kt = solver.kernel_times()      # ms per iteration, per kernel class
-    solver.set_profiling(False)
-    kb = {}
-    for m, f, nf in zip(meshes, flows, nfs):
-        e = int(np.sum(np.diff(m.cell_ptr)))
-        for k, v in kernel_bytes(m.n_cells, nf, e, f[3] >= 0, mixed).items():
-            kb[k] = kb.get(k, 0) + v
-    faces = solver.total_faces
-    dom = max(kt, key=lambda k: kt[k])
-    sweep_wg = schedule[4] == 2
-    if not sweep_wg and solver.nlev > 1:
-        # one launch per wavefront: the forward class covers wavefronts
-        # 1 .. nlev-1 (the first wavefront's forward increments are formed
-        # where they are read), the backward class wavefronts nlev-2 .. 0 (the
-        # last one's backward step runs in the forward class's last launch);
-        # their bytes are the per-cell model over the cells they process
-        sizes = solver.wavefront_sizes()
-        ntot = float(sizes.sum())
-        kb["sweep_fwd"] *= (ntot - sizes[0]) / ntot
-        kb["sweep_bwd"] *= (ntot - sizes[-1]) / ntot
-    launches = {"sweep_fwd": 1 if sweep_wg else max(solver.nlev - 1, 1),
-                "sweep_bwd": 1 if sweep_wg else max(solver.nlev - 1, 1)}.get(dom, 1)
-    t_ms = kt[dom]
-    # the launch duration of the dominant kernel: the residual-phase kernels
-    # (which only write derived arrays) are timed over back-to-back launches
-    # between two events, so the events' own cost is spread over them; the
-    # sweeps (which change the state) by their event interval in the pass above
-    launch_ms = solver.time_kernel(dom, 50) if dom in ("prep", "flux", "gather") else t_ms / launches
-    if dom == "flux":
-        achieved = FLUX_FLOP_PER_FACE * faces / (launch_ms * 1e-3) / 1e12 if launch_ms > 0 else 0.0
-        roofline = dict(kernel=dom, bound="alu", achieved=achieved, peak=FP64_VALU_PEAK_TFS, unit="TFLOP/s",
-                        frac=achieved / FP64_VALU_PEAK_TFS)
-    else:
-        achieved = kb[dom] / launches / (launch_ms * 1e-3) / 1e9 if launch_ms > 0 else 0.0
-        roofline = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=achieved / HBM_PEAK_GBS)
-    tr = measured_traffic(args.workload, dom) if not mixed or batched else None
-    roofline.update(traffic=tr, launches_per_step=launches, ms_per_step=t_ms, ms_per_launch=launch_ms,
-                    algorithmic_bytes_per_step=kb.get(dom),
-                    kernel_ms_per_step={k: round(v, 5) for k, v in kt.items()})
-    tf = launch_ms if dom == "flux" else solver.time_kernel("flux", 50)
-    roofline["flux_fp64_tflops"] = FLUX_FLOP_PER_FACE * faces / (tf * 1e-3) / 1e12 if tf > 0 else 0.0
-    roofline["hbm_gbs_per_kernel"] = {k: round(kb[k] / (kt[k] * 1e-3) / 1e9, 1) for k in kb if kt.get(k, 0) > 0}
+    sched = SCHEDULES.get(args.workload)
+    solver, main_out, kt, kb = measure(igks, meshes, flows, prec, args, sched, args.workload)
+    roofline = roofline_of(args, solver, kt, kb, main_out, mixed)
+    del solver
+    torch.cuda.empty_cache()
 
     out = {
-        "metric": "cell-updates/s", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "metric": "cell-updates/s", "value": main_out["value"], "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_out["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64", "data": "synthetic",
-        "config": dict({"workload": f"{args.workload}: {wl['desc']}", "instances": len(meshes), "cells": n,
-                        "faces": faces, "wavefronts": solver.nlev, "precision": precision, "ordering": "colour",
-                        "cfl_init": cfl0, "chunk": args.chunk, "schedule": schedule,
-                        "cell_updates_timed": updates}, **res_info),
+        "config": dict({"workload": f"{args.workload}: {wl['desc']}", "instances": len(meshes), "precision": precision,
+                        "ordering": "colour", "repeats": args.repeats, "value_from": "median window"},
+                       **{k: v for k, v in main_out.items() if k not in ("value", "ms_per_step")}),
         "roofline": roofline,
     }
+    if not args.no_extra:
+        if not batched and not mixed:
+            _, mo, mkt, _ = measure(igks, meshes, flows, igks.IGKS_MIXED, args, sched, args.workload + " mixed")
+            out["mixed"] = dict(mo, dtype="f32+f64", kernel_ms_per_step={k: round(v, 5) for k, v in mkt.items()})
+            torch.cuda.empty_cache()
+        if not batched:
+            bm, bf = load_meshes(mg, "batch64", args.mesh_cache)
+            _, bo, bkt, _ = measure(igks, bm, bf, igks.IGKS_MIXED, args, SCHEDULES["batch64"], "batch64 mixed")
+            out["batch64_mixed"] = dict(bo, dtype="f32+f64", workload=WORKLOADS["batch64"]["desc"],
+                                        kernel_ms_per_step={k: round(v, 5) for k, v in bkt.items()})
+            del bm
+            torch.cuda.empty_cache()
     if not args.no_drop:
         out["time_to_1e-10"] = {"workload": "plate64x32 (natural order), Ma 0.3 Re_L 1e4, CFL 10 -> Eq.25",
                                 "fp64": time_to_drop(igks, mg, igks.IGKS_FP64),
@@ -394,10 +537,15 @@ def main():
                                 "batched_plates": time_to_drop_batch(igks, mg),
                                 "explicit_fp64_cfl0.9": time_to_drop(igks, mg, igks.IGKS_FP64, scheme=1, cfl=0.9,
                                                                      chunk=1000, max_it=400000)}
+        say("time to 1e-10 done")
         out["cavity_to_eq40"] = time_to_converge_cavity(igks, mg)
         out["turbulent_plate_to_eq40"] = time_to_converge_turbulent_plate(igks, mg)
+        say("Eq.40 runs done")
     if not args.no_cpu:
-        out["cpu_baseline"] = run_cpu_baseline(list(zip(meshes, flows))[:4])
+        if batched:
+            out["cpu_baseline"] = run_cpu_baseline(meshes[1], flows[1], "batch64 instance 1")
+        else:
+            out["cpu_baseline"] = run_cpu_baseline(meshes[0], flows[0], args.workload)
     print(json.dumps(out), flush=True)
 
 

@@ -275,6 +275,21 @@ int igks_batch_status(igks_ctx *ctx, int32_t inst, int32_t *halted);
  * 1 <= iters <= 1000; IGKS_ENONPHYS if an instance is frozen. */
 int igks_autotune(igks_ctx *ctx, int32_t iters, int32_t *schedule6);
 int igks_get_schedule(const igks_ctx *ctx, int32_t *schedule6);
+/* Apply a schedule in the layout igks_get_schedule reports (for example one
+ * an earlier igks_autotune found for the same mesh): block sizes 64, 128 or
+ * 256 for the four classes, sweep 1 or 2, lanes per face 1 or 2.  Needs a
+ * bound workspace (binding picks the automatic schedule again).  Block
+ * sizes and the sweep schedule never change results; the two flux kernels
+ * agree to rounding.  IGKS_EINVAL for a value outside those sets. */
+int igks_set_schedule(igks_ctx *ctx, const int32_t *schedule6);
+
+/* Iterations per captured HIP graph and kernel launches per iteration of the
+ * current schedule (before binding: of the schedule binding will pick).  A
+ * graph holds at most 8192 launches: with one launch per wavefront and sweep
+ * direction an iteration of a many-wavefront batch is thousands of launches
+ * long, and the chunk is cut to fit; 0 iterations: no graphs (chunk 0).
+ * Works without a GPU once every instance has a mesh. */
+int igks_graph_chunk(const igks_ctx *ctx, int32_t *iters_per_graph, int32_t *launches_per_iteration);
 
 /* With profiling on (igks_set_profiling(ctx, 1)) igks_iterate launches
  * directly, not through graphs, and times each kernel class with HIP events

@@ -1,5 +1,6 @@
 """Builds oracle/liboigks.so from igks_oracle.c with gcc (plain C99, -O2,
-no fast-math).  Test infrastructure: the GPU library does not link it."""
+no fast-math, OpenMP for the optional threads of its per-cell and per-face
+loops).  Test infrastructure: the GPU library does not link it."""
 import os
 import subprocess
 import sys
@@ -10,7 +11,7 @@ LIB = os.path.join(HERE, "liboigks.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fno-fast-math", "-fPIC", "-shared",
+    cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
            "-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

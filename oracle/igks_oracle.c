@@ -15,6 +15,13 @@
  *
  * Citations name the paper's section and equation.  Points where the paper
  * is silent, and the reading taken there, are marked "reading:".
+ *
+ * Threads: the per-cell and per-face loops of a residual evaluation may run
+ * on several OpenMP threads (oigks_set_threads; one by default).  Each
+ * thread writes only its own cells' or faces' entries, the face results are
+ * summed into the cells afterwards in face order on one thread, and the
+ * Gauss-Seidel sweeps stay sequential, so the results do not depend on the
+ * thread count, bit for bit.
  */
 #include <math.h>
 #include <stdio.h>
@@ -101,6 +108,8 @@ typedef struct oigks_ctx {
     double *dW;                  /* 5 per cell */
     double *Wg;                  /* 5 per face: ghost (cell-centre) state, boundary faces */
     double *phi;                 /* 4 per cell: the last computed limiter factors */
+    double *fsa;                 /* 2 per face: the face's SA residual terms of owner and neighbour */
+    int threads;                 /* OpenMP threads of the per-cell and per-face loops */
     int phi_frozen;              /* the limiter factors are held (limiter_freeze) */
     double dt_flux;
     /* iteration scalars */
@@ -472,12 +481,12 @@ static void free_mesh(oigks_ctx *c)
     void *ps[] = {c->x, c->y, c->cptr, c->cnod, c->fL, c->fR, c->ftag, c->fbc, c->fbidx, c->wall_faces, c->fnx, c->fny, c->flen,
                   c->fxm, c->fym, c->area, c->xc, c->yc, c->dwall, c->cfp, c->cff, c->W, c->M, c->gx,
                   c->gy, c->ugx, c->ugy, c->lamc, c->vort, c->dtimp, c->ff, c->flam, c->D, c->Dsa,
-                  c->dW, c->Wg, c->phi};
+                  c->dW, c->Wg, c->phi, c->fsa};
     for (size_t i = 0; i < sizeof ps / sizeof ps[0]; i++) free(ps[i]);
     c->x = c->y = NULL; c->cptr = c->cnod = NULL; c->fL = c->fR = c->ftag = c->fbc = c->fbidx = c->wall_faces = NULL;
     c->fnx = c->fny = c->flen = c->fxm = c->fym = NULL; c->area = c->xc = c->yc = c->dwall = NULL;
     c->cfp = c->cff = NULL; c->W = c->M = c->gx = c->gy = c->ugx = c->ugy = NULL;
-    c->lamc = c->vort = c->dtimp = c->ff = c->flam = c->D = c->Dsa = c->dW = c->Wg = c->phi = NULL;
+    c->lamc = c->vort = c->dtimp = c->ff = c->flam = c->D = c->Dsa = c->dW = c->Wg = c->phi = c->fsa = NULL;
 }
 
 EXPORT void oigks_default_options(oigks_options *o)
@@ -491,6 +500,7 @@ EXPORT int oigks_create(oigks_ctx **out, const oigks_options *opt)
     oigks_ctx *c = calloc(1, sizeof *c);
     if (!c) return -3;
     if (opt) c->opt = *opt; else oigks_default_options(&c->opt);
+    c->threads = 1;
     *out = c;
     if (!(c->opt.wall_temp >= 0.0) || !isfinite(c->opt.wall_temp)) { seterr(c, "wall_temp must be >= 0"); return -1; }
     if (c->opt.tau_jump < 0 || c->opt.tau_jump > 1) { seterr(c, "tau_jump must be 0 or 1"); return -1; }
@@ -651,6 +661,7 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
     free(fill);
     /* wall distance: exact distance from each centroid to the closest wall edge */
     c->dwall = malloc(sizeof(double) * n_cells);
+#pragma omp parallel for num_threads(c->threads) schedule(static)
     for (int i = 0; i < n_cells; i++) {
         double best = 1e300;
         for (int w = 0; w < c->nwall; w++) {
@@ -671,6 +682,7 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
     c->D = calloc(n_cells, sizeof(double)); c->Dsa = calloc(n_cells, sizeof(double));
     c->dW = calloc(5 * n_cells, sizeof(double)); c->Wg = calloc(5 * nf, sizeof(double));
     c->phi = calloc(n4, sizeof(double));
+    c->fsa = calloc(2 * nf, sizeof(double));
     return 0;
 }
 
@@ -817,11 +829,14 @@ static int residual(oigks_ctx *c)
 {
     int nc = c->nc, nf = c->nf;
     double *W = c->W;
+    const int nt = c->threads;
     /* ghost cell-centre states */
+#pragma omp parallel for num_threads(nt) schedule(static)
     for (int f = 0; f < nf; f++)
         if (c->fR[f] < 0) ghost_state(c, c->fbc[f], &W[5 * c->fL[f]], c->fnx[f], c->fny[f], &c->Wg[5 * f]);
     /* Eq.21: (Lambda_c)_i = sum_faces (|V_i . n| + C_i) S; Eq.23 dt = min */
     double dtmin = 1e300;
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(min : dtmin)
     for (int i = 0; i < nc; i++) {
         const double *Wi = &W[5 * i];
         double U = Wi[1] / Wi[0], V = Wi[2] / Wi[0], ci = sound(Wi), s = 0.0;
@@ -836,6 +851,7 @@ static int residual(oigks_ctx *c)
     c->dt_flux = dtmin;
     /* Eq.6-7: unweighted least squares over the face neighbours, ghost cells
      * at the reflected centroids included; 2x2 normal equations by Cramer. */
+#pragma omp parallel for num_threads(nt) schedule(static)
     for (int i = 0; i < nc; i++) {
         double a11 = 0, a12 = 0, a22 = 0, b1[4] = {0}, b2[4] = {0};
         for (int q = c->cfp[i]; q < c->cfp[i + 1]; q++) {
@@ -854,6 +870,7 @@ static int residual(oigks_ctx *c)
         }
     }
     /* Eq.9-10 limiter, per cell and variable */
+#pragma omp parallel for num_threads(nt) schedule(static)
     for (int i = 0; i < nc; i++) {
         for (int k = 0; k < 4; k++) {
             double phi = 1.0;
@@ -888,8 +905,9 @@ static int residual(oigks_ctx *c)
         double dVdx = (c->ugx[4 * i + 2] - V * c->ugx[4 * i + 0]) / r;
         c->vort[i] = fabs(dVdx - dUdy);
     }
-    for (int k = 0; k < 5 * nc; k++) c->M[k] = 0.0;
-    /* face loop */
+    /* face loop: each face's flux, spectral radius and SA terms (summed
+     * into the cells below) */
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 256)
     for (int f = 0; f < nf; f++) {
         int i = c->fL[f], j = c->fR[f];
         double nx = c->fnx[f], ny = c->fny[f], S = c->flen[f];
@@ -1035,11 +1053,7 @@ static int residual(oigks_ctx *c)
         }
         double Fn = fd.F[1] / c->dt_flux, Ft = fd.F[2] / c->dt_flux;
         double Fb[4] = {fd.F[0] / c->dt_flux, Fn * nx + Ft * tx, Fn * ny + Ft * ty, fd.F[3] / c->dt_flux};
-        for (int k = 0; k < 4; k++) {
-            c->ff[4 * f + k] = Fb[k] * S;
-            c->M[5 * i + k] -= Fb[k] * S;                 /* Eq.16: M = -sum F . S (outward) */
-            if (j >= 0) c->M[5 * j + k] += Fb[k] * S;
-        }
+        for (int k = 0; k < 4; k++) c->ff[4 * f + k] = Fb[k] * S;
         /* LU-SGS spectral radius on the face (reading: max of the two sides'
          * |V.n| + C plus, optionally, a viscous term 2 nu_eff / |r.n|) */
         {
@@ -1064,12 +1078,27 @@ static int residual(oigks_ctx *c)
             double g = (tj - ti) / rn;
             double Finv = 0.5 * (qi + fabs(qi)) * ti + 0.5 * (qj - fabs(qj)) * tj;
             double Fvis = (1.0 / (2.0 * SA_SIGMA)) * ((nui + nuj) + (1.0 + SA_CB2) * (ti + tj)) * g;
-            c->M[5 * i + 4] += -Finv * S + Fvis * S - (SA_CB2 / SA_SIGMA) * ti * g * S;
-            if (j >= 0) c->M[5 * j + 4] += Finv * S - Fvis * S - (SA_CB2 / SA_SIGMA) * tj * (-g) * S;
+            c->fsa[2 * f] = -Finv * S + Fvis * S - (SA_CB2 / SA_SIGMA) * ti * g * S;
+            c->fsa[2 * f + 1] = j >= 0 ? Finv * S - Fvis * S - (SA_CB2 / SA_SIGMA) * tj * (-g) * S : 0.0;
+        }
+    }
+    /* Eq.16: M = -sum F . S over the cell's faces (outward), summed in face
+     * order; the SA right-hand side Eq.27 likewise */
+    for (int k = 0; k < 5 * nc; k++) c->M[k] = 0.0;
+    for (int f = 0; f < nf; f++) {
+        int i = c->fL[f], j = c->fR[f];
+        for (int k = 0; k < 4; k++) {
+            c->M[5 * i + k] -= c->ff[4 * f + k];
+            if (j >= 0) c->M[5 * j + k] += c->ff[4 * f + k];
+        }
+        if (c->sa) {
+            c->M[5 * i + 4] += c->fsa[2 * f];
+            if (j >= 0) c->M[5 * j + 4] += c->fsa[2 * f + 1];
         }
     }
     /* SA source, Omega Sr (Eq.27) */
     if (c->sa) {
+#pragma omp parallel for num_threads(nt) schedule(static)
         for (int i = 0; i < nc; i++) {
             double nu = mu_lam(c, lam_of(&W[5 * i])) / W[5 * i];
             double so[4];
@@ -1125,6 +1154,7 @@ static void lusgs(oigks_ctx *c)
 {
     int nc = c->nc;
     double *W = c->W, *dW = c->dW;
+#pragma omp parallel for num_threads(c->threads) schedule(static)
     for (int i = 0; i < nc; i++) {
         c->dtimp[i] = c->cfl * c->area[i] / c->lamc[i];             /* Eq.24 */
         double s = 0.0;
@@ -1285,6 +1315,14 @@ EXPORT int oigks_iterate(oigks_ctx *c, int n, int *n_done)
         if (n_done) *n_done = it + 1;
     }
     free(Wold);
+    return 0;
+}
+
+/* threads of the per-cell and per-face loops (results do not depend on it) */
+EXPORT int oigks_set_threads(oigks_ctx *c, int n)
+{
+    if (n < 1) { seterr(c, "thread count must be at least 1"); return -1; }
+    c->threads = n;
     return 0;
 }
 

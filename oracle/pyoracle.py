@@ -71,6 +71,7 @@ def lib():
         L.oigks_collision_time.argtypes = [p, d, d, d]; L.oigks_collision_time.restype = d
         L.oigks_ghost_state.argtypes = [p, i, dp, d, d, dp]
         L.oigks_mu.argtypes = [p, d]; L.oigks_mu.restype = d
+        L.oigks_set_threads.argtypes = [p, i]
         _lib = L
     return _lib
 
@@ -100,11 +101,13 @@ class OracleError(RuntimeError):
 class Oracle:
     """FP64 CPU oracle bound to one mesh and one flow condition."""
 
-    def __init__(self, mesh, options: Options | None = None, **kw):
+    def __init__(self, mesh, options: Options | None = None, threads: int = 1, **kw):
         self.L = lib()
         self.opt = options or default_options(**kw)
         self.ctx = C.c_void_p()
         self._chk(self.L.oigks_create(C.byref(self.ctx), C.byref(self.opt)))
+        if threads != 1:
+            self.set_threads(threads)
         self.mesh = mesh
         xy, pxy = _d(mesh.xy.reshape(-1))
         cp, pcp = _i(mesh.cell_ptr)
@@ -129,6 +132,11 @@ class Oracle:
                 self.ctx = C.c_void_p()
         except Exception:
             pass
+
+    def set_threads(self, n):
+        """OpenMP threads of the per-cell and per-face loops (1 by default);
+        the results are the same bit for bit whatever the count."""
+        self._chk(self.L.oigks_set_threads(self.ctx, int(n)))
 
     def set_freestream(self, mach, alpha_deg, reynolds, nut_ratio=-1.0):
         self._chk(self.L.oigks_set_freestream(self.ctx, mach, alpha_deg, reynolds, nut_ratio))

@@ -132,19 +132,33 @@ void destroy_graph(igks_ctx *c)
 // direction makes an iteration of a many-wavefront batch thousands of
 // launches long); 0 = no graphs.
 constexpr int MAX_GRAPH_NODES = 8192;
-int launches_per_iteration(const igks_ctx *c)
+int launches_per_iteration(const igks_ctx *c, bool sweep_wg)
 {
     const int nlev = std::max(1, c->g.nlev);
     // per-wavefront sweeps: forward steps of wavefronts 1 .. nlev-2, the last
     // wavefront's two steps, backward steps of nlev-2 .. 0
-    const int sweeps = c->opt.scheme == 1 ? 1 : (c->sweep_wg ? 3 : std::max(1, 2 * nlev - 2));
+    const int sweeps = c->opt.scheme == 1 ? 1 : (sweep_wg ? 3 : std::max(1, 2 * nlev - 2));
     return 5 + sweeps;   // prep, flux, gather, reduce, commit + the update / sweep launches
 }
-int graph_chunk(const igks_ctx *c)
+int graph_chunk_for(const igks_ctx *c, bool sweep_wg)
 {
     if (c->opt.chunk <= 0) return 0;
-    return std::max(1, std::min(c->opt.chunk, MAX_GRAPH_NODES / launches_per_iteration(c)));
+    return std::max(1, std::min(c->opt.chunk, MAX_GRAPH_NODES / launches_per_iteration(c, sweep_wg)));
 }
+int graph_chunk(const igks_ctx *c) { return graph_chunk_for(c, c->sweep_wg); }
+
+// The schedule chosen at binding time from the sizes: one workgroup for the
+// sweeps when wavefronts are many and narrow (one workgroup of 512 threads
+// takes a wavefront per round of 512 cells and a launch per wavefront costs
+// a few microseconds, so the workgroup wins up to about two rounds); two
+// lanes per face once one lane per face would already give two waves per
+// SIMD (one lane leaves SIMDs idle on small meshes).
+bool auto_sweep_wg(const igks_ctx *c)
+{
+    const double width = (double)c->g.N / std::max(1, c->g.nlev);
+    return c->opt.sweep == 2 || (c->opt.sweep == 0 && c->g.nlev > 16 && width < 1024.0);
+}
+bool auto_flux_pair(const igks_ctx *c) { return c->opt.flux_lanes == 2 || (c->opt.flux_lanes == 0 && c->g.F >= 131072); }
 
 // ------------------------------------------------------------------ ingest
 
@@ -1036,15 +1050,8 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     rc |= up(w.wseg, G.wseg.data(), G.wseg.size() * D);
     rc |= up(w.lev_off, G.lev_off.data(), G.lev_off.size() * I);
     if (rc) return rc;
-    {
-        double width = (double)G.N / std::max(1, G.nlev);
-        // one workgroup of 512 threads takes a wavefront per round of 512 cells, a launch per
-        // wavefront costs a few microseconds: the workgroup wins up to about two rounds
-        c->sweep_wg = c->opt.sweep == 2 || (c->opt.sweep == 0 && G.nlev > 16 && width < 1024.0);
-        // one lane per face leaves SIMDs idle on small meshes; two lanes pay
-        // off once a lane per face would already give two waves per SIMD
-        c->flux_pair = c->opt.flux_lanes == 2 || (c->opt.flux_lanes == 0 && G.F >= 131072);
-    }
+    c->sweep_wg = auto_sweep_wg(c);
+    c->flux_pair = auto_flux_pair(c);
     // instance parameters and scalars start zeroed (no free stream yet)
     std::vector<InstParam> ip0(c->inst.size());
     std::memset(ip0.data(), 0, sizeof(InstParam) * ip0.size());
@@ -1315,6 +1322,35 @@ int igks_get_schedule(const igks_ctx *c, int32_t *s6)
     for (int k = 0; k < NCLASS; k++) s6[k] = c->block[k];
     s6[NCLASS] = c->sweep_wg ? 2 : 1;
     s6[NCLASS + 1] = c->flux_pair ? 2 : 1;
+    return IGKS_OK;
+}
+
+int igks_set_schedule(igks_ctx *c, const int32_t *s6)
+{
+    int rc = check_ready(c, false);
+    if (rc) return rc;
+    if (!s6) return fail(c, IGKS_EINVAL, "null schedule");
+    for (int k = 0; k < NCLASS; k++)
+        if (s6[k] != 64 && s6[k] != 128 && s6[k] != 256)
+            return fail(c, IGKS_EINVAL, "block sizes must be 64, 128 or 256");
+    if ((s6[NCLASS] != 1 && s6[NCLASS] != 2) || (s6[NCLASS + 1] != 1 && s6[NCLASS + 1] != 2))
+        return fail(c, IGKS_EINVAL, "sweep schedule and lanes per face must be 1 or 2");
+    destroy_graph(c);
+    for (int k = 0; k < NCLASS; k++) c->block[k] = s6[k];
+    c->sweep_wg = s6[NCLASS] == 2;
+    c->flux_pair = s6[NCLASS + 1] == 2;
+    return IGKS_OK;
+}
+
+int igks_graph_chunk(const igks_ctx *cc, int32_t *iters, int32_t *launches)
+{
+    igks_ctx *c = const_cast<igks_ctx *>(cc);
+    if (!c) return IGKS_EINVAL;
+    int rc = ensure_combined(c);
+    if (rc) return rc;
+    const bool wg = c->bound ? c->sweep_wg : auto_sweep_wg(c);
+    if (iters) *iters = graph_chunk_for(c, wg);
+    if (launches) *launches = launches_per_iteration(c, wg);
     return IGKS_OK;
 }
 

@@ -92,6 +92,8 @@ _SIGS = {
     "igks_batch_status": (C.c_int, [_P, C.c_int32, _IP]),
     "igks_autotune": (C.c_int, [_P, C.c_int32, _IP]),
     "igks_get_schedule": (C.c_int, [_P, _IP]),
+    "igks_set_schedule": (C.c_int, [_P, _IP]),
+    "igks_graph_chunk": (C.c_int, [_P, _IP, _IP]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -215,6 +217,16 @@ class _Context:
         s = np.zeros(6, dtype=np.int32)
         self._chk(igks_get_schedule(self.ctx, s.ctypes.data_as(_IP)))
         return s
+
+    def set_schedule(self, s6):
+        s = np.ascontiguousarray(s6, dtype=np.int32)
+        self._chk(igks_set_schedule(self.ctx, s.ctypes.data_as(_IP)))
+
+    def graph_chunk(self):
+        """(iterations per captured graph, kernel launches per iteration)."""
+        it, nl = C.c_int32(), C.c_int32()
+        self._chk(igks_graph_chunk(self.ctx, C.byref(it), C.byref(nl)))
+        return it.value, nl.value
 
 
 class Solver(_Context):

@@ -4,6 +4,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -40,3 +41,23 @@ def test_kernel_bytes_model():
     dbl = bench.kernel_bytes(2 * n, 2 * f, 2 * e, False, False)
     for k in lam:
         assert dbl[k] == 2 * lam[k]
+
+
+@pytest.mark.parametrize("chunk,steps,warmup,want", [(20, 20, 5, 5), (100, 20, 10, 10), (20, 7, 10, 7),
+                                                     (20, 20, 0, 20), (6, 20, 10, 5), (20, 20, 20, 20)])
+def test_graph_chunk_divides_the_timed_steps(chunk, steps, warmup, want):
+    """The timed iterations are whole graph replays of a graph the warm-up
+    captured: the chunk divides --steps and is at most --warmup."""
+    c = bench.graph_chunk(chunk, steps, warmup)
+    assert c == want
+    assert steps % c == 0 and c <= chunk and (warmup == 0 or c <= warmup)
+
+
+def test_mesh_cache_round_trip(tmp_path):
+    from paper_1709_00803_amd import meshgen as mg
+    m1, f1 = bench.load_meshes(mg, "plate64x32", str(tmp_path))
+    m2, f2 = bench.load_meshes(mg, "plate64x32", str(tmp_path))
+    assert f1 == f2
+    for a, b in zip(m1, m2):
+        for k in ("xy", "cell_ptr", "cell_nodes", "bface_nodes", "bface_tag"):
+            assert np.array_equal(getattr(a, k), getattr(b, k))

@@ -277,3 +277,29 @@ def test_call_order_and_option_errors():
     finally:
         igks.igks_destroy(ctx)
     igks.igks_destroy(None)
+
+
+@pytest.mark.parametrize("sweep,chunk", [(1, 100), (1, 2), (0, 100), (2, 7)])
+def test_graph_chunk_bounds_the_captured_launches(sweep, chunk):
+    """A captured HIP graph holds at most 8192 kernel launches: with one
+    launch per wavefront and sweep direction, a batch whose instances have
+    about 900 wavefronts (natural order) runs 5 + 2 (L - 1) launches per
+    iteration, and the iterations per graph are cut to fit; the
+    one-workgroup sweep (chosen automatically for such narrow wavefronts)
+    needs 3 sweep launches per iteration and keeps the requested chunk."""
+    strip = mg.flat_plate(8, 915)                 # row by row: one wavefront per row and column step
+    other = mg.random_hybrid(9, 6, seed=3)
+    rc, ctx = ctx_for(2, sweep=sweep, chunk=chunk)
+    assert rc == igks.IGKS_OK
+    try:
+        assert upload(ctx, strip, 0) == igks.IGKS_OK and upload(ctx, other, 1) == igks.IGKS_OK
+        nlev = max(levels_by_hand(strip), levels_by_hand(other))
+        assert nlev >= 900
+        it, nl = C.c_int32(), C.c_int32()
+        assert igks.igks_graph_chunk(ctx, C.byref(it), C.byref(nl)) == igks.IGKS_OK
+        per_wavefront = sweep == 1
+        assert nl.value == (5 + 2 * (nlev - 1) if per_wavefront else 8)
+        assert it.value * nl.value <= 8192
+        assert it.value == min(chunk, 8192 // nl.value) >= 1
+    finally:
+        igks.igks_destroy(ctx)

@@ -71,7 +71,7 @@ def test_planted_mistake_fails_its_pins(name, tmp_path):
     mutant = tmp_path / "mutant.c"
     mutant.write_text(src.replace(old, new))
     lib = tmp_path / "libmutant.so"
-    subprocess.run(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fno-fast-math", "-fPIC", "-shared",
+    subprocess.run(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
                     "-o", str(lib), str(mutant), "-lm"], check=True)
     env = dict(os.environ, OIGKS_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider", *pins],

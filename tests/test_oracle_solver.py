@@ -829,3 +829,22 @@ def test_sa_diffusion_exact_for_linear_field():
     interior[f["fl"][f["fr"] < 0]] = False
     want = c["area"] * (1 + SA_CB2) * b * b / SA_SIG
     assert np.allclose(M[4, interior], want[interior], rtol=1e-10)
+
+
+@pytest.mark.parametrize("sa,limiter", [(False, 1), (True, 0)])
+def test_thread_count_does_not_change_results(sa, limiter):
+    """The oracle's per-cell and per-face loops on several threads give the
+    single-threaded iterates bit for bit (face results are summed into the
+    cells in face order on one thread; the sweeps stay sequential)."""
+    tags = dict(bottom=mg.WALL, top=mg.FARFIELD, left=mg.FREESTREAM, right=mg.OUTFLOW)
+    m = mg.colour_order(mg.random_hybrid(16, 12, seed=4, tags=tags))[0]
+    out = []
+    for threads in (1, 4):
+        o = po.Oracle(m, limiter=limiter, cfl_init=5.0)
+        o.set_threads(threads)
+        o.set_freestream(0.4, 3.0, 3e4 if sa else 3e3, 3.0 if sa else -1.0)
+        o.iterate(6)
+        out.append((o.get_state(), o.compute_residual()[0], o.residual()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
