@@ -109,6 +109,8 @@ typedef struct oigks_ctx {
     double *Wg;                  /* 5 per face: ghost (cell-centre) state, boundary faces */
     double *phi;                 /* 4 per cell: the last computed limiter factors */
     double *fsa;                 /* 2 per face: the face's SA residual terms of owner and neighbour */
+    double *fsag;                /* 2 per face: the magnitudes of those terms' parts (|F_inv| + |F_vis| + |F_ad|) S */
+    double *sasrc;               /* per cell: Omega Sr, the SA source part of the right-hand side */
     int threads;                 /* OpenMP threads of the per-cell and per-face loops */
     int phi_frozen;              /* the limiter factors are held (limiter_freeze) */
     double dt_flux;
@@ -481,12 +483,13 @@ static void free_mesh(oigks_ctx *c)
     void *ps[] = {c->x, c->y, c->cptr, c->cnod, c->fL, c->fR, c->ftag, c->fbc, c->fbidx, c->wall_faces, c->fnx, c->fny, c->flen,
                   c->fxm, c->fym, c->area, c->xc, c->yc, c->dwall, c->cfp, c->cff, c->W, c->M, c->gx,
                   c->gy, c->ugx, c->ugy, c->lamc, c->vort, c->dtimp, c->ff, c->flam, c->D, c->Dsa,
-                  c->dW, c->Wg, c->phi, c->fsa};
+                  c->dW, c->Wg, c->phi, c->fsa, c->fsag, c->sasrc};
     for (size_t i = 0; i < sizeof ps / sizeof ps[0]; i++) free(ps[i]);
     c->x = c->y = NULL; c->cptr = c->cnod = NULL; c->fL = c->fR = c->ftag = c->fbc = c->fbidx = c->wall_faces = NULL;
     c->fnx = c->fny = c->flen = c->fxm = c->fym = NULL; c->area = c->xc = c->yc = c->dwall = NULL;
     c->cfp = c->cff = NULL; c->W = c->M = c->gx = c->gy = c->ugx = c->ugy = NULL;
     c->lamc = c->vort = c->dtimp = c->ff = c->flam = c->D = c->Dsa = c->dW = c->Wg = c->phi = c->fsa = NULL;
+    c->fsag = c->sasrc = NULL;
 }
 
 EXPORT void oigks_default_options(oigks_options *o)
@@ -683,6 +686,8 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
     c->dW = calloc(5 * n_cells, sizeof(double)); c->Wg = calloc(5 * nf, sizeof(double));
     c->phi = calloc(n4, sizeof(double));
     c->fsa = calloc(2 * nf, sizeof(double));
+    c->fsag = calloc(2 * nf, sizeof(double));
+    c->sasrc = calloc(n_cells, sizeof(double));
     return 0;
 }
 
@@ -1080,6 +1085,8 @@ static int residual(oigks_ctx *c)
             double Fvis = (1.0 / (2.0 * SA_SIGMA)) * ((nui + nuj) + (1.0 + SA_CB2) * (ti + tj)) * g;
             c->fsa[2 * f] = -Finv * S + Fvis * S - (SA_CB2 / SA_SIGMA) * ti * g * S;
             c->fsa[2 * f + 1] = j >= 0 ? Finv * S - Fvis * S - (SA_CB2 / SA_SIGMA) * tj * (-g) * S : 0.0;
+            c->fsag[2 * f] = (fabs(Finv) + fabs(Fvis) + (SA_CB2 / SA_SIGMA) * fabs(ti * g)) * S;
+            c->fsag[2 * f + 1] = j >= 0 ? (fabs(Finv) + fabs(Fvis) + (SA_CB2 / SA_SIGMA) * fabs(tj * g)) * S : 0.0;
         }
     }
     /* Eq.16: M = -sum F . S over the cell's faces (outward), summed in face
@@ -1104,6 +1111,7 @@ static int residual(oigks_ctx *c)
             double so[4];
             sa_source(W[5 * i + 4], nu, c->dwall[i], c->vort[i], so);
             c->M[5 * i + 4] += c->area[i] * so[0];
+            c->sasrc[i] = c->area[i] * so[0];
         }
     }
     return 0;
@@ -1373,6 +1381,22 @@ EXPORT int oigks_compute_residual(oigks_ctx *c, double *M, double *gross)
                 if (c->fR[f] >= 0) gross[k * c->nc + c->fR[f]] += a;
             }
     }
+    return 0;
+}
+/* Gross size of the SA right-hand side of each cell at the current state:
+ * the sum over its faces of the magnitudes of the convective, diffusive and
+ * anti-diffusive terms of Eq.29 (times S) plus Omega |Sr| (Eq.28a), the
+ * scale its residual cancels from (0 in laminar runs). */
+EXPORT int oigks_sa_gross(oigks_ctx *c, double *out)
+{
+    if (!c->have_flow) { seterr(c, "set_freestream first"); return -1; }
+    residual(c);
+    for (int i = 0; i < c->nc; i++) out[i] = c->sa ? fabs(c->sasrc[i]) : 0.0;
+    if (c->sa)
+        for (int f = 0; f < c->nf; f++) {
+            out[c->fL[f]] += c->fsag[2 * f];
+            if (c->fR[f] >= 0) out[c->fR[f]] += c->fsag[2 * f + 1];
+        }
     return 0;
 }
 /* One LU-SGS solve at the current state with the given CFL: returns dW

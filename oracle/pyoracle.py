@@ -72,6 +72,7 @@ def lib():
         L.oigks_ghost_state.argtypes = [p, i, dp, d, d, dp]
         L.oigks_mu.argtypes = [p, d]; L.oigks_mu.restype = d
         L.oigks_set_threads.argtypes = [p, i]
+        L.oigks_sa_gross.argtypes = [p, dp]
         _lib = L
     return _lib
 
@@ -140,6 +141,7 @@ class Oracle:
 
     def set_freestream(self, mach, alpha_deg, reynolds, nut_ratio=-1.0):
         self._chk(self.L.oigks_set_freestream(self.ctx, mach, alpha_deg, reynolds, nut_ratio))
+        self.flow = (mach, alpha_deg, reynolds, nut_ratio)
 
     def iterate(self, n):
         done = C.c_int(0)
@@ -167,6 +169,13 @@ class Oracle:
         self._chk(self.L.oigks_compute_residual(self.ctx, M.ctypes.data_as(C.POINTER(C.c_double)),
                                                 G.ctypes.data_as(C.POINTER(C.c_double))))
         return M, G
+
+    def sa_gross(self):
+        """Per cell, the gross size of the SA right-hand side (sum of the
+        magnitudes of its face terms times S, plus Omega |Sr|)."""
+        out = np.zeros(self.n)
+        self._chk(self.L.oigks_sa_gross(self.ctx, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
 
     def lusgs_solve(self, cfl):
         dW = np.zeros((5, self.n))
