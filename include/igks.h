@@ -173,6 +173,22 @@ int igks_workspace_size(const igks_ctx *ctx, size_t *bytes);
  * context is destroyed or rebound.  IGKS_ENOMEM if too small. */
 int igks_bind_workspace(igks_ctx *ctx, void *dptr, size_t bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): bind the
+ * library's own workspace, a static device array of 64 MiB (67108864 bytes)
+ * on the current device, which must be the device of the context's stream,
+ * in place of a caller's buffer.  Otherwise as igks_bind_workspace (mesh
+ * data uploaded, wall distance computed, state to be set by
+ * igks_set_freestream); no device memory is allocated or freed.
+ * IGKS_ENOMEM (nothing bound) if igks_workspace_size exceeds 64 MiB (about
+ * 70 000 cells).  The array is one per GPU and shared: binding it to a
+ * context overwrites what it held for an earlier context on that GPU, which
+ * then gets IGKS_EINVAL from every call that needs its workspace until it
+ * binds one again; calls of different contexts on the same GPU that
+ * overlap in time race on it.  IGKS_EHIP if its device address cannot be
+ * obtained. */
+int igks_bind_static_workspace(igks_ctx *ctx);
+
 /* Free stream (Mach, angle of attack in degrees, Reynolds number per unit
  * reference length, nu-tilde_inf / nu_inf): the state W_inf of the
  * free-stream boundary condition (Sec. 2.5) and of the impulsive start, in

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <unordered_map>
@@ -85,6 +86,8 @@ struct igks_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     bool bound = false;
+    int static_dev = -1;               // device whose static workspace is bound, -1: a caller's buffer
+    unsigned long long static_gen = 0; // binding generation of that static workspace
     WsMap w{};
     Params<double> P64{};
     Params<float> P32{};
@@ -104,7 +107,23 @@ struct igks_ctx {
     double ktimes[NKT] = {0, 0, 0, 0, 0, 0};
 };
 
+// The library's own workspace for callers that cannot allocate device
+// memory (igks_bind_static_workspace): one array per GPU, which each GPU the
+// library runs on holds until the process ends.  In host code `scratch` only
+// names the array; its device address comes from hipGetSymbolAddress, once
+// per device, with that device current.
+constexpr size_t STATIC_WS_BYTES = size_t(64) << 20;
+static __device__ __align__(256) char scratch[STATIC_WS_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+struct StaticWs {
+    void *ptr = nullptr;          // device address of `scratch` on this device
+    unsigned long long gen = 0;   // bumped by every binding: a context holds the array while its gen is current
+};
+std::mutex static_mu;
+StaticWs static_ws[MAX_DEVICES];
 
 int fail(igks_ctx *c, int code, const std::string &msg)
 {
@@ -716,6 +735,13 @@ int check_ready(igks_ctx *c, bool need_flow)
     for (size_t i = 0; i < c->inst.size(); i++)
         if (!c->inst[i].ok) return fail(c, IGKS_EINVAL, "no mesh uploaded for instance " + std::to_string(i));
     if (!c->bound) return fail(c, IGKS_EINVAL, "no workspace bound");
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(static_mu);
+        if (static_ws[c->static_dev].gen != c->static_gen) {
+            c->bound = false;
+            return fail(c, IGKS_EINVAL, "the static workspace was bound to another context since; bind a workspace again");
+        }
+    }
     if (need_flow)
         for (size_t i = 0; i < c->inst.size(); i++)
             if (!c->inst[i].have_flow)
@@ -1018,6 +1044,7 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     if (((uintptr_t)dptr) % 256 != 0) return fail(c, IGKS_EINVAL, "workspace must be 256-byte aligned");
     destroy_graph(c);
     c->bound = false;
+    c->static_dev = -1;
     c->ws = (char *)dptr;
     c->ws_bytes = bytes;
     c->w = w;
@@ -1068,6 +1095,39 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     for (auto &m : c->inst) m.have_flow = false;
     for (auto &h : c->hist) h.clear();
     return sync_scalars(c);
+}
+
+int igks_bind_static_workspace(igks_ctx *c)
+{
+    if (!c) return IGKS_EINVAL;
+    int rc = ensure_combined(c);
+    if (rc) return rc;
+    const size_t need = layout(c->g, (int)c->inst.size(), c->opt, c->hist_cap).total;
+    if (need > STATIC_WS_BYTES)
+        return fail(c, IGKS_ENOMEM, "the mesh needs a workspace of " + std::to_string(need) +
+                                        " bytes; the static workspace holds " + std::to_string(STATIC_WS_BYTES));
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(c, IGKS_EINVAL, "device index out of range");
+    void *ptr = nullptr;
+    unsigned long long gen = 0;
+    {
+        std::lock_guard<std::mutex> lk(static_mu);
+        if (!static_ws[dev].ptr) {
+            void *p = nullptr;
+            hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail(c, IGKS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            static_ws[dev].ptr = p;
+        }
+        ptr = static_ws[dev].ptr;
+        gen = ++static_ws[dev].gen;
+    }
+    rc = igks_bind_workspace(c, ptr, STATIC_WS_BYTES);
+    if (rc) return rc;
+    c->static_dev = dev;
+    c->static_gen = gen;
+    return IGKS_OK;
 }
 
 int igks_batch_set_freestream(igks_ctx *c, int32_t inst, double mach, double alpha_deg, double reynolds,

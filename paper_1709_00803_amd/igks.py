@@ -66,6 +66,7 @@ _SIGS = {
     "igks_wavefront_sizes": (C.c_int, [_P, _IP, C.c_int32]),
     "igks_workspace_size": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "igks_bind_workspace": (C.c_int, [_P, _P, C.c_size_t]),
+    "igks_bind_static_workspace": (C.c_int, [_P]),
     "igks_set_freestream": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double]),
     "igks_iterate": (C.c_int, [_P, C.c_int32, _IP]),
     "igks_get_residual": (C.c_int, [_P, C.POINTER(igks_residual)]),

@@ -303,3 +303,19 @@ def test_graph_chunk_bounds_the_captured_launches(sweep, chunk):
         assert it.value == min(chunk, 8192 // nl.value) >= 1
     finally:
         igks.igks_destroy(ctx)
+
+
+def test_static_workspace_rejects_large_meshes():
+    """The allocation-free binding holds at most 64 MiB: a mesh whose
+    workspace is larger is refused before any device call, nothing bound."""
+    m = mg.flat_plate(400, 200)
+    rc, ctx = ctx_for()
+    try:
+        assert upload(ctx, m) == igks.IGKS_OK
+        sz = C.c_size_t()
+        assert igks.igks_workspace_size(ctx, C.byref(sz)) == igks.IGKS_OK and sz.value > 64 << 20
+        assert igks.igks_bind_static_workspace(ctx) == igks.IGKS_ENOMEM
+        assert b"static workspace holds 67108864" in igks.igks_last_error(ctx)
+        assert igks.igks_set_freestream(ctx, 0.3, 0.0, 1e4, -1.0) == igks.IGKS_EINVAL
+    finally:
+        igks.igks_destroy(ctx)
