@@ -84,12 +84,14 @@ typedef struct oigks_ctx {
     double *x, *y;
     int *cptr, *cnod;            /* counter-clockwise vertex lists */
     int *fL, *fR, *ftag;         /* fR = -1 on boundary faces; ftag = input tag (0 interior) */
+    int *fa, *fb;                /* end nodes of each face (counter-clockwise for the owner) */
     int *fbc;                    /* boundary type in use (FARFIELD resolved) */
     int *fbidx;                  /* input boundary-edge index of a boundary face, -1 interior */
     int *wall_faces;             /* WALL faces in the order of the input boundary edges */
     double *fnx, *fny, *flen, *fxm, *fym;
     double *area, *xc, *yc, *dwall;
     int *cfp, *cff;              /* cell -> face lists */
+    int *sblk;                   /* sweep block of each cell (NULL: the whole mesh is one block) */
     int nwall;                   /* number of WALL faces */
     /* flow parameters */
     int have_flow, sa;
@@ -480,12 +482,14 @@ static int cmp_bkey(const void *a, const void *b)
 
 static void free_mesh(oigks_ctx *c)
 {
-    void *ps[] = {c->x, c->y, c->cptr, c->cnod, c->fL, c->fR, c->ftag, c->fbc, c->fbidx, c->wall_faces, c->fnx, c->fny, c->flen,
+    void *ps[] = {c->x, c->y, c->cptr, c->cnod, c->fL, c->fR, c->ftag, c->fa, c->fb, c->fbc, c->fbidx, c->wall_faces, c->fnx, c->fny, c->flen,
                   c->fxm, c->fym, c->area, c->xc, c->yc, c->dwall, c->cfp, c->cff, c->W, c->M, c->gx,
                   c->gy, c->ugx, c->ugy, c->lamc, c->vort, c->dtimp, c->ff, c->flam, c->D, c->Dsa,
                   c->dW, c->Wg, c->phi, c->fsa, c->fsag, c->sasrc};
     for (size_t i = 0; i < sizeof ps / sizeof ps[0]; i++) free(ps[i]);
-    c->x = c->y = NULL; c->cptr = c->cnod = NULL; c->fL = c->fR = c->ftag = c->fbc = c->fbidx = c->wall_faces = NULL;
+    free(c->sblk);
+    c->sblk = NULL;
+    c->x = c->y = NULL; c->cptr = c->cnod = NULL; c->fa = c->fb = NULL; c->fL = c->fR = c->ftag = c->fbc = c->fbidx = c->wall_faces = NULL;
     c->fnx = c->fny = c->flen = c->fxm = c->fym = NULL; c->area = c->xc = c->yc = c->dwall = NULL;
     c->cfp = c->cff = NULL; c->W = c->M = c->gx = c->gy = c->ugx = c->ugy = NULL;
     c->lamc = c->vort = c->dtimp = c->ff = c->flam = c->D = c->Dsa = c->dW = c->Wg = c->phi = c->fsa = NULL;
@@ -599,6 +603,7 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
     }
     c->nf = nf;
     c->fL = malloc(sizeof(int) * nf); c->fR = malloc(sizeof(int) * nf); c->ftag = calloc(nf, sizeof(int));
+    c->fa = malloc(sizeof(int) * nf); c->fb = malloc(sizeof(int) * nf);
     c->fbc = calloc(nf, sizeof(int));
     c->fbidx = malloc(sizeof(int) * nf);
     c->fnx = malloc(sizeof(double) * nf); c->fny = malloc(sizeof(double) * nf);
@@ -621,6 +626,7 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
         int a = c->cnod[p0 + lo_], b = c->cnod[p0 + (lo_ + 1) % k];
         double dx = c->x[b] - c->x[a], dy = c->y[b] - c->y[a], L = sqrt(dx * dx + dy * dy);
         c->fL[f] = ow;
+        c->fa[f] = a; c->fb[f] = b;
         c->fbidx[f] = -1;
         c->fnx[f] = dy / L; c->fny[f] = -dx / L; c->flen[f] = L;   /* outward normal of a CCW edge */
         c->fxm[f] = 0.5 * (c->x[a] + c->x[b]); c->fym[f] = 0.5 * (c->y[a] + c->y[b]);
@@ -662,15 +668,15 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
         if (c->fR[q] >= 0) c->cff[c->cfp[c->fR[q]] + fill[c->fR[q]]++] = q;
     }
     free(fill);
-    /* wall distance: exact distance from each centroid to the closest wall edge */
+    /* wall distance: exact distance from each centroid to the closest wall
+     * edge, the segment between the edge's two nodes */
     c->dwall = malloc(sizeof(double) * n_cells);
 #pragma omp parallel for num_threads(c->threads) schedule(static)
     for (int i = 0; i < n_cells; i++) {
         double best = 1e300;
         for (int w = 0; w < c->nwall; w++) {
             int q = c->wall_faces[w];
-            double hx = 0.5 * c->flen[q] * (-c->fny[q]), hy = 0.5 * c->flen[q] * c->fnx[q];
-            double dd = seg_dist(c->xc[i], c->yc[i], c->fxm[q] - hx, c->fym[q] - hy, c->fxm[q] + hx, c->fym[q] + hy);
+            double dd = seg_dist(c->xc[i], c->yc[i], c->x[c->fa[q]], c->y[c->fa[q]], c->x[c->fb[q]], c->y[c->fb[q]]);
             if (dd < best) best = dd;
         }
         c->dwall[i] = best;
@@ -1193,6 +1199,7 @@ static void lusgs(oigks_ctx *c)
             if (c->fR[f] < 0) continue;
             int j = c->fL[f] == i ? c->fR[f] : c->fL[f];
             if (j >= i) continue;
+            if (c->sblk && c->sblk[j] != c->sblk[i]) continue;   /* another sweep block */
             double sg = c->fL[f] == i ? 1.0 : -1.0;
             double nx = sg * c->fnx[f], ny = sg * c->fny[f], S = c->flen[f];
             double jv[4];
@@ -1224,6 +1231,7 @@ static void lusgs(oigks_ctx *c)
             } else {
                 int j = c->fL[f] == i ? c->fR[f] : c->fL[f];
                 if (j <= i) continue;
+                if (c->sblk && c->sblk[j] != c->sblk[i]) continue;   /* another sweep block */
                 Wj = &W[5 * j]; dj = &dW[5 * j];
             }
             double jv[4];
@@ -1323,6 +1331,26 @@ EXPORT int oigks_iterate(oigks_ctx *c, int n, int *n_done)
         if (n_done) *n_done = it + 1;
     }
     free(Wold);
+    return 0;
+}
+
+/* Sweep blocks (reading, the block form of LU-SGS used on partitioned
+ * meshes): blk[i] is the block of cell i; the sweeps of Eq.22 (and Eq.31-32)
+ * then couple only cells of one block, visiting them in index order, and
+ * leave the neighbours in other blocks out of the lower and upper parts
+ * (their increments taken as zero); the diagonal keeps every face.  NULL:
+ * one block, the plain sweeps. */
+EXPORT int oigks_set_sweep_blocks(oigks_ctx *c, const int *blk)
+{
+    if (!c->cptr) { seterr(c, "no mesh"); return -1; }
+    free(c->sblk);
+    c->sblk = NULL;
+    if (!blk) return 0;
+    c->sblk = malloc(sizeof(int) * c->nc);
+    for (int i = 0; i < c->nc; i++) {
+        if (blk[i] < 0) { free(c->sblk); c->sblk = NULL; seterr(c, "negative sweep block"); return -1; }
+        c->sblk[i] = blk[i];
+    }
     return 0;
 }
 

@@ -73,6 +73,7 @@ def lib():
         L.oigks_mu.argtypes = [p, d]; L.oigks_mu.restype = d
         L.oigks_set_threads.argtypes = [p, i]
         L.oigks_sa_gross.argtypes = [p, dp]
+        L.oigks_set_sweep_blocks.argtypes = [p, C.POINTER(C.c_int)]
         _lib = L
     return _lib
 
@@ -169,6 +170,14 @@ class Oracle:
         self._chk(self.L.oigks_compute_residual(self.ctx, M.ctypes.data_as(C.POINTER(C.c_double)),
                                                 G.ctypes.data_as(C.POINTER(C.c_double))))
         return M, G
+
+    def set_sweep_blocks(self, blk):
+        """Sweep block of each cell (None: one block)."""
+        if blk is None:
+            self._chk(self.L.oigks_set_sweep_blocks(self.ctx, None))
+            return
+        b, p = _i(np.asarray(blk).reshape(self.n))
+        self._chk(self.L.oigks_set_sweep_blocks(self.ctx, p))
 
     def sa_gross(self):
         """Per cell, the gross size of the SA right-hand side (sum of the

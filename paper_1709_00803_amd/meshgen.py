@@ -858,6 +858,40 @@ def colour_order(mesh: Mesh, seed: int = 0):
     return m, order, colour[order]
 
 
+def sweep_blocks(mesh: Mesh, max_cells: int = 1024) -> np.ndarray:
+    """Sweep block of each cell: recursive coordinate bisection of the vertex
+    averages (split at the median of the longer extent) until every block
+    holds at most ``max_cells`` cells.  The cells keep their numbering, so
+    inside a block the sweeps visit them in the mesh's own order."""
+    pts = mesh.centroids_approx()
+    blk = np.zeros(mesh.n_cells, dtype=np.int32)
+    stack = [np.arange(mesh.n_cells)]
+    nb = 0
+    while stack:
+        idx = stack.pop()
+        if len(idx) <= max_cells:
+            blk[idx] = nb
+            nb += 1
+            continue
+        p = pts[idx]
+        ax = int(np.argmax(p.max(axis=0) - p.min(axis=0)))
+        order = idx[np.argsort(p[:, ax], kind="stable")]
+        h = len(order) // 2
+        stack.append(order[h:])
+        stack.append(order[:h])
+    return blk
+
+
+def block_order(mesh: Mesh, max_cells: int = 1024):
+    """Renumber cells block by block (sweep_blocks), each block keeping the
+    mesh's own order inside it; returns (mesh, block of each new cell)."""
+    blk = sweep_blocks(mesh, max_cells)
+    order = np.lexsort((np.arange(mesh.n_cells), blk))
+    m = renumber(mesh, order)
+    m.meta = dict(mesh.meta, ordering="blocks", max_block_cells=max_cells, n_blocks=int(blk.max() + 1))
+    return m, blk[order]
+
+
 def sfc_order(mesh: Mesh):
     """Renumber cells along a Morton curve (a natural, many-wavefront order)."""
     order = np.argsort(_morton(mesh.centroids_approx()), kind="stable")

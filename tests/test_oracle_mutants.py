@@ -57,6 +57,14 @@ MUTANTS = {
     "SA wall increment not negated": (
         "dWg[3] = dWi[3]; dWg[4] = -dWi[4];\n    } else {", "dWg[3] = dWi[3]; dWg[4] = dWi[4];\n    } else {",
         ["tests/test_oracle_solver.py::test_sa_lusgs_solves_factored_system"]),
+    "sweep blocks ignored in the forward sweep": (
+        "if (j >= i) continue;\n            if (c->sblk && c->sblk[j] != c->sblk[i]) continue;",
+        "if (j >= i) continue;",
+        ["tests/test_oracle_solver.py::test_lusgs_solves_factored_system"]),
+    "sweep blocks ignored in the backward sweep": (
+        "if (j <= i) continue;\n                if (c->sblk && c->sblk[j] != c->sblk[i]) continue;",
+        "if (j <= i) continue;",
+        ["tests/test_oracle_solver.py::test_lusgs_solves_factored_system"]),
     "SA lower neighbour subtracted": (
         "acc[4] += of * dW[5 * j + 4];", "acc[4] -= of * dW[5 * j + 4];",
         ["tests/test_oracle_solver.py::test_sa_lusgs_solves_factored_system"]),

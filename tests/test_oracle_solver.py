@@ -375,17 +375,22 @@ def _jac_fd(W, nx, ny):
     return J
 
 
-@pytest.mark.parametrize("top", [mg.OUTFLOW, mg.MOVING_WALL])
-def test_lusgs_solves_factored_system(top):
+@pytest.mark.parametrize("top,blocks", [(mg.OUTFLOW, False), (mg.MOVING_WALL, False), (mg.OUTFLOW, True)])
+def test_lusgs_solves_factored_system(top, blocks):
     """The sweeps solve (L + D) D^-1 (D + U) dW = M with the Euler-flux
     Jacobians of Eq.20 (built here by finite differences) and the lagged
     ghost increments of Sec. 2.5 in the backward sweep (for the moving wall:
-    the Jacobian of its affine ghost map)."""
+    the Jacobian of its affine ghost map).  With sweep blocks L and U hold
+    only the pairs of cells in the same block; D keeps every face."""
     tags = dict(bottom=mg.WALL, top=top, left=mg.FREESTREAM, right=mg.SYMMETRY)
     m = mg.random_hybrid(5, 4, seed=7, tags=tags)
     m, _, _ = mg.colour_order(m)
     o = po.Oracle(m)
     o.set_freestream(0.4, 5.0, 1e3)
+    blk = mg.sweep_blocks(m, 7) if blocks else np.zeros(m.n_cells, dtype=np.int32)
+    if blocks:
+        assert blk.max() >= 3
+        o.set_sweep_blocks(blk)
     W = smooth_state(o, 0.1, 3)
     o.set_state(W)
     cfl = 50.0
@@ -408,9 +413,11 @@ def test_lusgs_solves_factored_system(top):
         i, j = f["fl"][k], f["fr"][k]
         nx, ny, S = f["nx"][k], f["ny"][k], f["len"][k]
         if j >= 0:
+            if blk[i] != blk[j]:
+                continue
             for a, b, sg in ((i, j, 1.0), (j, i, -1.0)):
-                blk = 0.5 * (_jac_fd(W[:, b], sg * nx, sg * ny) - lam[k] * np.eye(4)) * S
-                (L if b < a else U)[4 * a:4 * a + 4, 4 * b:4 * b + 4] += blk
+                jb = 0.5 * (_jac_fd(W[:, b], sg * nx, sg * ny) - lam[k] * np.eye(4)) * S
+                (L if b < a else U)[4 * a:4 * a + 4, 4 * b:4 * b + 4] += jb
         else:
             bc = f["bc"][k]
             if bc == mg.WALL:
@@ -431,6 +438,11 @@ def test_lusgs_solves_factored_system(top):
     want = np.linalg.solve(Dm + U, (Dm - G) @ dws)
     got = dW[:4].T.reshape(-1)
     assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
+    if blocks:
+        # the same system with the cross-block pairs kept is another one
+        o.set_sweep_blocks(None)
+        full = o.lusgs_solve(cfl)[:4].T.reshape(-1)
+        assert np.abs(full - want).max() > 1e-6 * np.abs(want).max()
 
 
 def test_sa_lusgs_solves_factored_system():
