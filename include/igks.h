@@ -80,7 +80,8 @@ typedef struct igks_options {
     int chunk;          /* iterations per captured HIP graph launch; 0 = no graph */
     int block;          /* threads per block of the cell/face kernels; 0 = 256 */
     int sweep;          /* LU-SGS sweep schedule: 0 auto, 1 one launch per wavefront,
-                           2 all wavefronts in one workgroup (barrier between wavefronts) */
+                           2 all wavefronts in one workgroup (barrier between wavefronts),
+                           3 one wave per sweep block (igks_set_sweep_blocks), all blocks at once */
     int flux_lanes;     /* lanes per face of the flux kernel: 0 auto (2 from 131072 faces on),
                            1 or 2; the two agree to rounding */
     int scheme;         /* 0: implicit LU-SGS (Eq.18-22); 1: explicit Eq.15 with local time
@@ -124,8 +125,9 @@ typedef struct igks_ctx igks_ctx;
 
 /* Fill *opt with the defaults: FP64, limiter off, cfl_init 1000 (Sec. 3.1),
  * cfl_min 1, cfl_max 1e6, Eq.25 law, cfl_flux 1, visc_sr on, Sutherland,
- * chunk 20, block 256, sweep auto (one workgroup when the wavefronts are many and
- * narrow: more than 16 of them averaging under 1024 cells), flux_lanes auto. */
+ * chunk 20, block 256, sweep auto (a wave per sweep block when an instance has
+ * sweep blocks, else one workgroup when the wavefronts are many and narrow:
+ * more than 16 of them averaging under 1024 cells), flux_lanes auto. */
 void igks_default_options(igks_options *opt);
 
 /* Create a context.  opt may be NULL (defaults).  hip_stream is a
@@ -153,6 +155,24 @@ const char *igks_last_error(const igks_ctx *ctx);
 int igks_mesh_upload(igks_ctx *ctx, int32_t n_nodes, const double *xy, int32_t n_cells,
                      const int32_t *cell_ptr, const int32_t *cell_nodes, int32_t n_bfaces,
                      const int32_t *bface_nodes, const int32_t *bface_tag);
+
+/* Sweep blocks of instance inst (0 for a single-instance context):
+ * block_of_cell[i] >= 0 is the block of cell i (upload order, host array,
+ * copied); NULL restores one block.  The LU-SGS sweeps of Eq.22 and Eq.31-32
+ * then couple only cells of one block, each block swept in increasing
+ * (forward) and decreasing (backward) cell index, with the neighbours in
+ * other blocks left out of the lower and upper parts (their increments taken
+ * as zero), as the sweeps of a partitioned mesh do; the diagonal keeps every
+ * face and the residual is unchanged, so only the path to the steady state
+ * changes.  Blocks cut the number of wavefronts (within a block of the
+ * mesh's own order a few tens) while each block keeps the ordered
+ * Gauss-Seidel coupling that carries information along the flow; a
+ * colouring of the whole mesh, by contrast, leaves 3 wavefronts but a
+ * sweep that converges poorly.  Call after the instance's mesh upload;
+ * like an upload it unbinds the workspace (bind again, then set the free
+ * streams).  IGKS_EINVAL for a negative block or an instance without a
+ * mesh. */
+int igks_set_sweep_blocks(igks_ctx *ctx, int32_t inst, const int32_t *block_of_cell);
 
 /* Sizes of the uploaded mesh: cells, faces, wall faces, sweep wavefronts. */
 int igks_mesh_info(const igks_ctx *ctx, int32_t *n_cells, int32_t *n_faces, int32_t *n_wall_faces,
@@ -280,20 +300,22 @@ int igks_batch_status(igks_ctx *ctx, int32_t inst, int32_t *halted);
  * (threads per block 64/128/256 for the prep, flux, gather and sweep
  * kernels, the face flux on one or two lanes per face; for the sweeps also
  * one workgroup for all wavefronts, tried while wavefronts average under
- * 16384 cells), keeps the fastest per kernel class, and then restores both
+ * 16384 cells, and a wave per sweep block when there are sweep blocks),
+ * keeps the fastest per kernel class, and then restores both
  * state buffers, the scalars and the history bitwise.  Block sizes and the
  * sweep schedule never change results; the one- and two-lane flux kernels
  * agree to rounding (the compiler fuses a few multiply-adds differently).
  * schedule6 (may be NULL) receives the
  * block sizes of the four classes, the sweep schedule (1: one launch per
- * wavefront, 2: one workgroup) and the lanes per face of the flux (1 or 2;
+ * wavefront, 2: one workgroup, 3: a wave per sweep block) and the lanes per
+ * face of the flux (1 or 2;
  * before any tuning 2 from 131072 faces on).  IGKS_EINVAL unless
  * 1 <= iters <= 1000; IGKS_ENONPHYS if an instance is frozen. */
 int igks_autotune(igks_ctx *ctx, int32_t iters, int32_t *schedule6);
 int igks_get_schedule(const igks_ctx *ctx, int32_t *schedule6);
 /* Apply a schedule in the layout igks_get_schedule reports (for example one
  * an earlier igks_autotune found for the same mesh): block sizes 64, 128 or
- * 256 for the four classes, sweep 1 or 2, lanes per face 1 or 2.  Needs a
+ * 256 for the four classes, sweep 1, 2 or 3, lanes per face 1 or 2.  Needs a
  * bound workspace (binding picks the automatic schedule again).  Block
  * sizes and the sweep schedule never change results; the two flux kernels
  * agree to rounding.  IGKS_EINVAL for a value outside those sets. */

@@ -20,8 +20,9 @@ enum { BC_FREESTREAM = 1, BC_SYMMETRY = 2, BC_WALL = 3, BC_OUTFLOW = 4, BC_FARFI
 
 // cell -> face entry flags
 constexpr int CF_OWNER = 1;   // the cell is the face's owner (normal points outward)
-constexpr int CF_LOWER = 2;   // interior neighbour with a smaller upload index
+constexpr int CF_LOWER = 2;   // interior neighbour of the same sweep block with a smaller upload index
 constexpr int CF_VALID = 4;   // the entry exists (triangles leave their fourth entry empty)
+constexpr int CF_OTHER = 16;  // interior neighbour in another sweep block (left out of the sweeps)
 // A polygon's faces and vertices beyond the fourth sit in an overflow block
 // of four more (block nc + o); the last entry of a block carries o + 1 in
 // the flag bits from CF_NEXT_SHIFT on (0: no further block).
@@ -93,6 +94,9 @@ struct Params {
     // flags, centroid offsets to the neighbour (or ghost)
     const int *cf_face, *cf_nbr, *cf_flag;
     const double *cf_dx, *cf_dy;
+    // per entry, the face seen from the entry's cell: the normal pointing out
+    // of the cell and the face length (a cell's entries are contiguous)
+    const double *enx, *eny, *es;
     // face arrays (internal face order)
     const int *fl, *fr, *fbc;
     const double *fnx, *fny, *flen, *frl, *frr, *fdl, *fdr, *frn;
@@ -130,6 +134,12 @@ template <typename T> void launch_reduce(const Launch &L, const Params<T> &P, in
 // forward increment is stored.
 template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, int mode, int lev1);
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd);
+// the whole sweep, one wave per sweep block (ngb blocks; block gb's k-th
+// wavefront = cells [bl_lo[bl_off[gb] + k], bl_hi[bl_off[gb] + k])); the
+// backward sweep is followed by the update of every cell
+template <typename T>
+void launch_sweep_blk(const Launch &L, const Params<T> &P, const int *bl_off, const int *bl_lo, const int *bl_hi,
+                      int ngb, bool fwd);
 template <typename T> void launch_commit(const Launch &L, const Params<T> &P, int it);
 // explicit step (Eq.15, local time steps) in place of the sweeps
 template <typename T> void launch_explicit(const Launch &L, const Params<T> &P);

@@ -34,6 +34,7 @@ struct InstMesh {
     std::vector<UF> uf;
     std::vector<int> cf_ptr, cf_list;          // cell -> faces (in the order of uf), CSR
     std::vector<int> level;                    // sweep wavefront of each cell
+    std::vector<int> sblk;                     // sweep block of each cell (empty: one block)
     std::vector<int> wall_uf;                  // WALL faces in the input order of the boundary edges
     bool have_flow = false;
     double alpha = 0;
@@ -45,12 +46,17 @@ struct Global {
     int N = 0, F = 0, nlev = 0, nwall = 0, max_inst_cells = 0;
     int NB = 0;                      // entry / vertex blocks: N + one overflow block per polygon
     std::vector<int> lev_off;        // wavefront offsets (internal cells)
+    // sweep blocks of all instances (an instance without blocks is one):
+    // block gb's cells of its k-th wavefront are the internal cells
+    // [bl_lo[bl_off[gb] + k], bl_hi[bl_off[gb] + k])
+    std::vector<int> bl_off, bl_lo, bl_hi;
     std::vector<int> coff;           // first global upload id of each instance
     std::vector<int> g2i;            // global upload id -> internal cell
     std::vector<int> cinst, finst, icell, ioff, ipos;
     std::vector<double> xc, yc, area, lsinv, vtx;
     std::vector<int> cf_face, cf_nbr, cf_flag;   // MAXV entries per block
     std::vector<double> cf_dx, cf_dy;
+    std::vector<double> enx, eny, es;    // per entry: normal out of the entry's cell, face length
     std::vector<int> fl, fr, ftag;
     std::vector<double> fnx, fny, flen, frl, frr, fdl, fdr, frn, fxm;
     std::vector<int> wall_faces, woff;   // internal face ids per instance (input order); offsets
@@ -67,8 +73,9 @@ constexpr int NKT = 6;
 struct WsMap {
     Buf ip, is, slot, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx, phi;
     Buf cinst, finst, icell, ioff, g2i, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
-    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, flux, lam, saf, sag, sak, ipart, hist, ipos;
-    Buf wall_faces, wall_out, woff, wseg, lev_off, stage, backup;
+    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, ipart, hist, ipos;
+    Buf flux, lam, saf, sag, sak, enx, eny, es;
+    Buf wall_faces, wall_out, woff, wseg, lev_off, bl_off, bl_lo, bl_hi, stage, backup;
     size_t total;
 };
 
@@ -94,7 +101,7 @@ struct igks_ctx {
     int hist_cap = 0;
     // launch schedule
     int block[NCLASS] = {256, 256, 256, 256};
-    bool sweep_wg = false;
+    int sweep_mode = 1;       // LU-SGS sweeps: 1 a launch per wavefront, 2 one workgroup, 3 a wave per sweep block
     bool flux_pair = false;   // face flux on two lanes per face
     // host copies of the device scalars and the history of the last iterate call
     std::vector<InstScalars> hs;
@@ -151,20 +158,21 @@ void destroy_graph(igks_ctx *c)
 // direction makes an iteration of a many-wavefront batch thousands of
 // launches long); 0 = no graphs.
 constexpr int MAX_GRAPH_NODES = 8192;
-int launches_per_iteration(const igks_ctx *c, bool sweep_wg)
+int launches_per_iteration(const igks_ctx *c, int sweep_mode)
 {
     const int nlev = std::max(1, c->g.nlev);
     // per-wavefront sweeps: forward steps of wavefronts 1 .. nlev-2, the last
-    // wavefront's two steps, backward steps of nlev-2 .. 0
-    const int sweeps = c->opt.scheme == 1 ? 1 : (sweep_wg ? 3 : std::max(1, 2 * nlev - 2));
+    // wavefront's two steps, backward steps of nlev-2 .. 0; the other
+    // schedules: forward, backward, update
+    const int sweeps = c->opt.scheme == 1 ? 1 : (sweep_mode >= 2 ? 3 : std::max(1, 2 * nlev - 2));
     return 5 + sweeps;   // prep, flux, gather, reduce, commit + the update / sweep launches
 }
-int graph_chunk_for(const igks_ctx *c, bool sweep_wg)
+int graph_chunk_for(const igks_ctx *c, int sweep_mode)
 {
     if (c->opt.chunk <= 0) return 0;
-    return std::max(1, std::min(c->opt.chunk, MAX_GRAPH_NODES / launches_per_iteration(c, sweep_wg)));
+    return std::max(1, std::min(c->opt.chunk, MAX_GRAPH_NODES / launches_per_iteration(c, sweep_mode)));
 }
-int graph_chunk(const igks_ctx *c) { return graph_chunk_for(c, c->sweep_wg); }
+int graph_chunk(const igks_ctx *c) { return graph_chunk_for(c, c->sweep_mode); }
 
 // The schedule chosen at binding time from the sizes: one workgroup for the
 // sweeps when wavefronts are many and narrow (one workgroup of 512 threads
@@ -172,14 +180,48 @@ int graph_chunk(const igks_ctx *c) { return graph_chunk_for(c, c->sweep_wg); }
 // a few microseconds, so the workgroup wins up to about two rounds); two
 // lanes per face once one lane per face would already give two waves per
 // SIMD (one lane leaves SIMDs idle on small meshes).
-bool auto_sweep_wg(const igks_ctx *c)
+//
+// With sweep blocks the cells of different blocks never wait for each other,
+// so one wave sweeps each block on its own (no launch per wavefront, no
+// barrier across blocks).
+bool any_sweep_blocks(const igks_ctx *c)
 {
+    for (const auto &m : c->inst)
+        if (!m.sblk.empty()) return true;
+    return false;
+}
+int auto_sweep_mode(const igks_ctx *c)
+{
+    if (c->opt.sweep > 0) return c->opt.sweep;
+    if (any_sweep_blocks(c)) return 3;
     const double width = (double)c->g.N / std::max(1, c->g.nlev);
-    return c->opt.sweep == 2 || (c->opt.sweep == 0 && c->g.nlev > 16 && width < 1024.0);
+    return (c->g.nlev > 16 && width < 1024.0) ? 2 : 1;
 }
 bool auto_flux_pair(const igks_ctx *c) { return c->opt.flux_lanes == 2 || (c->opt.flux_lanes == 0 && c->g.F >= 131072); }
 
 // ------------------------------------------------------------------ ingest
+
+// neighbours the sweeps couple: interior, and in the same sweep block
+bool same_block(const InstMesh &m, int a, int b) { return m.sblk.empty() || m.sblk[a] == m.sblk[b]; }
+
+// sweep wavefronts: level(i) = 1 + max level of the coupled neighbours with a
+// smaller index (0 without any)
+void compute_levels(InstMesh &m)
+{
+    const int N = m.nc;
+    m.level.assign(N, 0);
+    m.nlev = 0;
+    for (int i = 0; i < N; i++) {
+        int lv = 0;
+        for (int e = m.cf_ptr[i]; e < m.cf_ptr[i + 1]; e++) {
+            const auto &f = m.uf[m.cf_list[e]];
+            int o = f.l == i ? f.r : f.l;
+            if (o >= 0 && o < i && same_block(m, i, o)) lv = std::max(lv, m.level[o] + 1);
+        }
+        m.level[i] = lv;
+        m.nlev = std::max(m.nlev, lv + 1);
+    }
+}
 
 int build_instance(igks_ctx *ctx, int n_nodes, const double *xy, int n_cells, const int32_t *cell_ptr,
                    const int32_t *cell_nodes, int n_bfaces, const int32_t *bface_nodes, const int32_t *bface_tag,
@@ -307,19 +349,7 @@ int build_instance(igks_ctx *ctx, int n_nodes, const double *xy, int n_cells, co
             if (m.uf[q].r >= 0) m.cf_list[m.cf_ptr[m.uf[q].r] + fill[m.uf[q].r]++] = q;
         }
     }
-    // sweep wavefronts: level(i) = 1 + max level of the neighbours with a smaller index
-    m.level.assign(N, 0);
-    m.nlev = 0;
-    for (int i = 0; i < N; i++) {
-        int lv = 0;
-        for (int e = m.cf_ptr[i]; e < m.cf_ptr[i + 1]; e++) {
-            const auto &f = m.uf[m.cf_list[e]];
-            int o = f.l == i ? f.r : f.l;
-            if (o >= 0 && o < i) lv = std::max(lv, m.level[o] + 1);
-        }
-        m.level[i] = lv;
-        m.nlev = std::max(m.nlev, lv + 1);
-    }
+    compute_levels(m);
     m.ok = true;
     return IGKS_OK;
 }
@@ -340,20 +370,45 @@ int combine(igks_ctx *ctx)
     }
     const int N = G.coff[ni];
     G.N = N;
-    std::vector<int> gi(N), gu(N), glev(N);
-    for (int i = 0; i < ni; i++)
-        for (int u = 0; u < ctx->inst[i].nc; u++) {
+    std::vector<int> gi(N), gu(N), glev(N), gblk(N);
+    int ngb = 0;   // sweep blocks over all instances
+    for (int i = 0; i < ni; i++) {
+        const InstMesh &m = ctx->inst[i];
+        int nb = 1;
+        for (int u = 0; u < m.nc; u++) {
             int gid = G.coff[i] + u;
-            gi[gid] = i; gu[gid] = u; glev[gid] = ctx->inst[i].level[u];
+            gi[gid] = i; gu[gid] = u; glev[gid] = m.level[u];
+            gblk[gid] = ngb + (m.sblk.empty() ? 0 : m.sblk[u]);
+            if (!m.sblk.empty()) nb = std::max(nb, m.sblk[u] + 1);
         }
-    std::vector<int> order(N);   // internal cell -> global upload id
+        ngb += nb;
+    }
+    std::vector<int> order(N);   // internal cell -> global upload id: by wavefront, instance, sweep block, upload index
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return glev[a] < glev[b]; });
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return glev[a] != glev[b] ? glev[a] < glev[b] : gblk[a] < gblk[b]; });
     G.g2i.resize(N);
     for (int c = 0; c < N; c++) G.g2i[order[c]] = c;
     G.lev_off.assign(G.nlev + 1, 0);
     for (int c = 0; c < N; c++) G.lev_off[glev[order[c]] + 1]++;
     for (int l = 0; l < G.nlev; l++) G.lev_off[l + 1] += G.lev_off[l];
+    {
+        // per sweep block, its wavefronts in order: each a contiguous range of
+        // internal cells (the internal order is by wavefront, then block)
+        std::vector<std::vector<std::pair<int, int>>> rng(ngb);
+        for (int c = 0; c < N; c++) {
+            auto &r = rng[gblk[order[c]]];
+            const int lv = glev[order[c]];
+            if ((int)r.size() == lv) r.push_back({c, c + 1});
+            else r.back().second = c + 1;   // cells of one block and wavefront are adjacent
+        }
+        G.bl_off.assign(ngb + 1, 0);
+        G.bl_lo.clear(); G.bl_hi.clear();
+        for (int b = 0; b < ngb; b++) {
+            for (auto &p : rng[b]) { G.bl_lo.push_back(p.first); G.bl_hi.push_back(p.second); }
+            G.bl_off[b + 1] = (int)G.bl_lo.size();
+        }
+    }
     G.cinst.resize(N);
     for (int c = 0; c < N; c++) G.cinst[c] = gi[order[c]];
     G.ioff.assign(ni + 1, 0);
@@ -450,6 +505,7 @@ int combine(igks_ctx *ctx)
     const size_t ne = (size_t)MAXV * NB;
     G.cf_face.assign(ne, 0); G.cf_nbr.assign(ne, -1); G.cf_flag.assign(ne, 0);
     G.cf_dx.assign(ne, 0.0); G.cf_dy.assign(ne, 0.0);
+    G.enx.assign(ne, 0.0); G.eny.assign(ne, 0.0); G.es.assign(ne, 0.0);
     for (int c = 0; c < N; c++) {
         const int i = gi[order[c]], u = gu[order[c]], off = G.coff[i];
         const InstMesh &m = ctx->inst[i];
@@ -476,8 +532,13 @@ int combine(igks_ctx *ctx)
                 dy = 2.0 * G.fdl[qi] * G.fny[qi];
             }
             G.cf_face[e] = qi;
+            G.enx[e] = own ? G.fnx[qi] : -G.fnx[qi];
+            G.eny[e] = own ? G.fny[qi] : -G.fny[qi];
+            G.es[e] = G.flen[qi];
             G.cf_nbr[e] = other >= 0 ? G.g2i[off + other] : -1;
-            G.cf_flag[e] = CF_VALID | (own ? CF_OWNER : 0) | ((other >= 0 && other < u) ? CF_LOWER : 0);
+            const bool coupled = other >= 0 && same_block(m, u, other);
+            G.cf_flag[e] = CF_VALID | (own ? CF_OWNER : 0) | ((coupled && other < u) ? CF_LOWER : 0) |
+                           ((other >= 0 && !coupled) ? CF_OTHER : 0);
             G.cf_dx[e] = dx;
             G.cf_dy[e] = dy;
             a11 += dx * dx; a12 += dx * dy; a22 += dy * dy;
@@ -544,6 +605,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.frr = L.add(2 * F * D); w.fdl = L.add(F * D); w.fdr = L.add(F * D); w.frn = L.add(F * D);
     w.flux = L.add(4 * F * D); w.lam = L.add(F * D); w.saf = L.add(F * D); w.sag = L.add(F * D);
     w.sak = L.add(F * D);
+    w.enx = L.add(E * D); w.eny = L.add(E * D); w.es = L.add(E * D);
     w.ipart = L.add(2 * NI * (size_t)norm_rb(G) * D);
     w.ipos = L.add(N * I);
     w.hist = L.add((size_t)HIST_W * NI * hist_cap * D);
@@ -552,6 +614,9 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.woff = L.add((NI + 1) * I);
     w.wseg = L.add(4 * NW * D);
     w.lev_off = L.add((size_t)(G.nlev + 1) * I);
+    w.bl_off = L.add(G.bl_off.size() * I);
+    w.bl_lo = L.add(std::max<size_t>(1, G.bl_lo.size()) * I);
+    w.bl_hi = L.add(std::max<size_t>(1, G.bl_hi.size()) * I);
     w.stage = L.add(5 * (size_t)std::max(1, G.max_inst_cells) * D);
     w.backup = L.add(10 * N * D + NI * sizeof(InstScalars));
     w.total = L.total;
@@ -587,6 +652,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.fnx = D(w.fnx); P.fny = D(w.fny); P.flen = D(w.flen); P.frl = D(w.frl); P.frr = D(w.frr);
     P.fdl = D(w.fdl); P.fdr = D(w.fdr); P.frn = D(w.frn);
     P.flux = D(w.flux); P.lam = D(w.lam); P.saf = D(w.saf); P.sag = D(w.sag); P.sak = D(w.sak);
+    P.enx = D(w.enx); P.eny = D(w.eny); P.es = D(w.es);
     P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipos = In(w.ipos); P.ipart = D(w.ipart); P.rb = norm_rb(c->g);
     P.hist = D(w.hist); P.hist_cap = c->hist_cap;
 }
@@ -626,7 +692,11 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev, int it)
         mark(6);
         return;
     }
-    if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, true);
+    const int *blo = (const int *)(c->ws + c->w.bl_off.off), *bll = (const int *)(c->ws + c->w.bl_lo.off),
+              *blh = (const int *)(c->ws + c->w.bl_hi.off);
+    const int ngb = (int)G.bl_off.size() - 1;
+    if (c->sweep_mode == 3) launch_sweep_blk(L, P, blo, bll, blh, ngb, true);
+    else if (c->sweep_mode == 2) launch_sweep_wg(L, P, lev, G.nlev, true);
     else
         // forward over the wavefronts after the first (whose forward
         // increments D^-1 M are formed where they are read); the last one
@@ -635,7 +705,8 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev, int it)
             launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], l + 1 < G.nlev ? 0 : 2, lev1);
     mark(5);
     // backward sweep with the update
-    if (c->sweep_wg) launch_sweep_wg(L, P, lev, G.nlev, false);
+    if (c->sweep_mode == 3) launch_sweep_blk(L, P, blo, bll, blh, ngb, false);
+    else if (c->sweep_mode == 2) launch_sweep_wg(L, P, lev, G.nlev, false);
     else
         for (int l = G.nlev - 2; l >= 0; l--) launch_sweep(L, P, G.lev_off[l], G.lev_off[l + 1], 1, lev1);
     mark(6);   // the backward sweeps' class ends here; the commit belongs to no class
@@ -930,7 +1001,7 @@ int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream,
     if (c->opt.precision != IGKS_FP64 && c->opt.precision != IGKS_MIXED) { delete c; return IGKS_EINVAL; }
     if (c->opt.block <= 0) c->opt.block = 256;
     if (c->opt.block % 64 != 0 || c->opt.block > 256) { delete c; return IGKS_EINVAL; }
-    if (c->opt.sweep < 0 || c->opt.sweep > 2 || c->opt.chunk < 0) { delete c; return IGKS_EINVAL; }
+    if (c->opt.sweep < 0 || c->opt.sweep > 3 || c->opt.chunk < 0) { delete c; return IGKS_EINVAL; }
     if (c->opt.flux_lanes < 0 || c->opt.flux_lanes > 2) { delete c; return IGKS_EINVAL; }
     if (c->opt.scheme < 0 || c->opt.scheme > 1) { delete c; return IGKS_EINVAL; }
     if (!(c->opt.wall_temp >= 0.0) || !std::isfinite(c->opt.wall_temp)) { delete c; return IGKS_EINVAL; }
@@ -986,6 +1057,25 @@ int igks_mesh_upload(igks_ctx *c, int32_t n_nodes, const double *xy, int32_t n_c
                      const int32_t *bface_tag)
 {
     return igks_batch_mesh_upload(c, 0, n_nodes, xy, n_cells, cell_ptr, cell_nodes, n_bfaces, bface_nodes, bface_tag);
+}
+
+int igks_set_sweep_blocks(igks_ctx *c, int32_t inst, const int32_t *block_of_cell)
+{
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    InstMesh &m = c->inst[inst];
+    if (!m.ok) return fail(c, IGKS_EINVAL, "no mesh uploaded for instance " + std::to_string(inst));
+    if (block_of_cell)
+        for (int i = 0; i < m.nc; i++)
+            if (block_of_cell[i] < 0) return fail(c, IGKS_EINVAL, "negative sweep block at cell " + std::to_string(i));
+    destroy_graph(c);
+    c->bound = false;
+    c->combined = false;
+    for (auto &x : c->inst) x.have_flow = false;
+    if (block_of_cell) m.sblk.assign(block_of_cell, block_of_cell + m.nc);
+    else m.sblk.clear();
+    compute_levels(m);
+    return IGKS_OK;
 }
 
 int igks_mesh_info(const igks_ctx *cc, int32_t *nc, int32_t *nf, int32_t *nw, int32_t *nl)
@@ -1068,6 +1158,7 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     rc |= up(w.cf_face, G.cf_face.data(), E * I);
     rc |= up(w.cf_nbr, G.cf_nbr.data(), E * I); rc |= up(w.cf_flag, G.cf_flag.data(), E * I);
     rc |= up(w.cf_dx, G.cf_dx.data(), E * D); rc |= up(w.cf_dy, G.cf_dy.data(), E * D);
+    rc |= up(w.enx, G.enx.data(), E * D); rc |= up(w.eny, G.eny.data(), E * D); rc |= up(w.es, G.es.data(), E * D);
     rc |= up(w.fl, G.fl.data(), F * I); rc |= up(w.fr, G.fr.data(), F * I); rc |= up(w.fbc, G.ftag.data(), F * I);
     rc |= up(w.fnx, G.fnx.data(), F * D); rc |= up(w.fny, G.fny.data(), F * D); rc |= up(w.flen, G.flen.data(), F * D);
     rc |= up(w.frl, G.frl.data(), 2 * F * D); rc |= up(w.frr, G.frr.data(), 2 * F * D);
@@ -1076,8 +1167,11 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     rc |= up(w.woff, G.woff.data(), G.woff.size() * I);
     rc |= up(w.wseg, G.wseg.data(), G.wseg.size() * D);
     rc |= up(w.lev_off, G.lev_off.data(), G.lev_off.size() * I);
+    rc |= up(w.bl_off, G.bl_off.data(), G.bl_off.size() * I);
+    rc |= up(w.bl_lo, G.bl_lo.data(), G.bl_lo.size() * I);
+    rc |= up(w.bl_hi, G.bl_hi.data(), G.bl_hi.size() * I);
     if (rc) return rc;
-    c->sweep_wg = auto_sweep_wg(c);
+    c->sweep_mode = auto_sweep_mode(c);
     c->flux_pair = auto_flux_pair(c);
     // instance parameters and scalars start zeroed (no free stream yet)
     std::vector<InstParam> ip0(c->inst.size());
@@ -1380,7 +1474,7 @@ int igks_get_schedule(const igks_ctx *c, int32_t *s6)
 {
     if (!c || !s6) return IGKS_EINVAL;
     for (int k = 0; k < NCLASS; k++) s6[k] = c->block[k];
-    s6[NCLASS] = c->sweep_wg ? 2 : 1;
+    s6[NCLASS] = c->sweep_mode;
     s6[NCLASS + 1] = c->flux_pair ? 2 : 1;
     return IGKS_OK;
 }
@@ -1393,11 +1487,11 @@ int igks_set_schedule(igks_ctx *c, const int32_t *s6)
     for (int k = 0; k < NCLASS; k++)
         if (s6[k] != 64 && s6[k] != 128 && s6[k] != 256)
             return fail(c, IGKS_EINVAL, "block sizes must be 64, 128 or 256");
-    if ((s6[NCLASS] != 1 && s6[NCLASS] != 2) || (s6[NCLASS + 1] != 1 && s6[NCLASS + 1] != 2))
-        return fail(c, IGKS_EINVAL, "sweep schedule and lanes per face must be 1 or 2");
+    if (s6[NCLASS] < 1 || s6[NCLASS] > 3 || (s6[NCLASS + 1] != 1 && s6[NCLASS + 1] != 2))
+        return fail(c, IGKS_EINVAL, "the sweep schedule must be 1, 2 or 3 and the lanes per face 1 or 2");
     destroy_graph(c);
     for (int k = 0; k < NCLASS; k++) c->block[k] = s6[k];
-    c->sweep_wg = s6[NCLASS] == 2;
+    c->sweep_mode = s6[NCLASS];
     c->flux_pair = s6[NCLASS + 1] == 2;
     return IGKS_OK;
 }
@@ -1408,9 +1502,9 @@ int igks_graph_chunk(const igks_ctx *cc, int32_t *iters, int32_t *launches)
     if (!c) return IGKS_EINVAL;
     int rc = ensure_combined(c);
     if (rc) return rc;
-    const bool wg = c->bound ? c->sweep_wg : auto_sweep_wg(c);
-    if (iters) *iters = graph_chunk_for(c, wg);
-    if (launches) *launches = launches_per_iteration(c, wg);
+    const int mode = c->bound ? c->sweep_mode : auto_sweep_mode(c);
+    if (iters) *iters = graph_chunk_for(c, mode);
+    if (launches) *launches = launches_per_iteration(c, mode);
     return IGKS_OK;
 }
 
@@ -1437,11 +1531,12 @@ int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s6)
     double best_t[NCLASS];
     for (int k = 0; k < NCLASS; k++) { best[k] = c->block[k]; best_t[k] = 1e300; }
     bool best_pair = c->flux_pair;
-    const bool wg_auto = c->sweep_wg, pair_auto = c->flux_pair;
+    const int mode_auto = c->sweep_mode;
+    const bool pair_auto = c->flux_pair;
     for (int pair = 0; pair < 2 && !rc; pair++)
         for (int b : cand) {
             for (int k = 0; k < NCLASS; k++) c->block[k] = b;
-            c->sweep_wg = false;
+            c->sweep_mode = 1;
             c->flux_pair = pair != 0;
             rc = (c->opt.precision == IGKS_MIXED) ? tune_run(c, c->P32, iters) : tune_run(c, c->P64, iters);
             if (rc) break;
@@ -1456,16 +1551,22 @@ int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s6)
         }
     for (int k = 0; k < NCLASS; k++) c->block[k] = best[k];
     c->flux_pair = rc ? pair_auto : best_pair;
-    if (!rc && (double)c->g.N / std::max(1, c->g.nlev) < 16384.0) {
-        // sweeps: one launch per wavefront (timed above) or one workgroup
-        // (a candidate only while wavefronts are narrow)
-        c->sweep_wg = true;
+    // sweeps: one launch per wavefront (timed above), one workgroup (a
+    // candidate only while wavefronts are narrow), a wave per sweep block
+    // (with sweep blocks)
+    int best_mode = 1;
+    double best_sweep = best_t[3];
+    for (int mode = 2; mode <= 3 && !rc; mode++) {
+        if (mode == 2 && !((double)c->g.N / std::max(1, c->g.nlev) < 16384.0)) continue;
+        if (mode == 3 && !any_sweep_blocks(c)) continue;
+        c->sweep_mode = mode;
         rc = (c->opt.precision == IGKS_MIXED) ? tune_run(c, c->P32, iters) : tune_run(c, c->P64, iters);
-        if (!rc) c->sweep_wg = c->ktimes[4] + c->ktimes[5] < best_t[3];
-    } else if (!rc) {
-        c->sweep_wg = false;
+        if (!rc && c->ktimes[4] + c->ktimes[5] < best_sweep) {
+            best_sweep = c->ktimes[4] + c->ktimes[5];
+            best_mode = mode;
+        }
     }
-    if (rc) c->sweep_wg = wg_auto;
+    c->sweep_mode = rc ? mode_auto : best_mode;
     c->profiling = prof;
     HIPCHK(c, hipMemcpyAsync(c->P64.Wa, bk, SB, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->P64.Wb, bk + SB, SB, hipMemcpyDeviceToDevice, c->stream));

@@ -372,8 +372,20 @@ __device__ __forceinline__ void msolve(double U, double V, double lam, double hl
     a[0] = b[0] - U * a[1] - V * a[2] - 0.5 * a[3] * B;
 }
 
-// Value of the partner lane of a face's lane pair.
-__device__ __forceinline__ double pair_other(double v) { return __shfl_xor(v, 1); }
+// Value of the partner lane of a face's lane pair (lanes 2m and 2m + 1): a
+// DPP quad permutation [1, 0, 3, 2] on each 32-bit half, which moves the
+// value between neighbouring lanes inside the VALU instead of through the
+// LDS crossbar.  Both lanes of a pair are active together.
+__device__ __forceinline__ int pair_swap(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);
+}
+__device__ __forceinline__ double pair_other(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = pair_swap((int)(b & 0xffffffffll)), hi = pair_swap((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 
 // a + b rounded once and never fused with the product that produced a or b:
 // the sum of a face's two sides is then the same number on either lane of a
@@ -591,7 +603,7 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
         for (int k = 0; k < MAXV; k++) {
             if (!(E.flag[k] & CF_VALID)) continue;
             const int e = MAXV * b + k, f = E.face[k], j = E.nbr[k];
-            double nx = P.fnx[f], ny = P.fny[f], S = P.flen[f];
+            double nx = P.enx[e], ny = P.eny[e], S = P.es[e];   // the outward normal of a boundary face
             lc += (fabs(U * nx + V * ny) + cs) * S;
             double wj[5];
             if (j >= 0) {
@@ -828,23 +840,40 @@ __device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &i
 }
 
 // Spectral radius of the face for the implicit operator and the SA face
-// terms (Eq.28-30) from the two sides' quantities.
+// terms (Eq.28-30) from the two sides' quantities (l the owner, r the
+// neighbour or ghost).
+struct FaceTerms {
+    double lam, saf, sag, sak;   // saf = (-F_inv + F_vis) S, sag = g S out of the owner, sak = k S / |r.n|
+};
 template <typename T>
-__device__ __forceinline__ void face_implicit_terms(const Params<T> &P, const InstParam &ip, int f, double lsl,
-                                                    double lsr, double evl, double evr, double nul, double nur,
-                                                    double ti, double tj, double ql, double qr)
+__device__ __forceinline__ FaceTerms face_implicit_terms(const Params<T> &P, const InstParam &ip, int f, double lsl,
+                                                         double lsr, double evl, double evr, double nul, double nur,
+                                                         double ti, double tj, double ql, double qr)
 {
     const double rn = P.frn[f], S = P.flen[f];
-    double lamf = fmax(lsl, lsr);
-    if (P.visc_sr) lamf += (evl + evr) / rn;
-    P.lam[f] = lamf;
+    FaceTerms o{fmax(lsl, lsr), 0.0, 0.0, 0.0};
+    if (P.visc_sr) o.lam += (evl + evr) / rn;
     if (ip.sa) {
         double g = (tj - ti) / rn;
         double Finv = 0.5 * (ql + fabs(ql)) * ti + 0.5 * (qr - fabs(qr)) * tj;
         double kf = (0.5 / SA_SIGMA) * ((nul + nur) + (1.0 + SA_CB2) * (ti + tj));
-        P.saf[f] = (kf * g - Finv) * S;
-        P.sag[f] = g * S;
-        P.sak[f] = kf * S / rn;
+        o.saf = (kf * g - Finv) * S;
+        o.sag = g * S;
+        o.sak = kf * S / rn;
+    }
+    return o;
+}
+
+// The face terms into the face arrays, stored as soon as they are formed
+// so that they do not stay live across the flux.
+template <typename T>
+__device__ __forceinline__ void store_terms(const Params<T> &P, const InstParam &ip, int f, const FaceTerms &t)
+{
+    P.lam[f] = t.lam;
+    if (ip.sa) {
+        P.saf[f] = t.saf;
+        P.sag[f] = t.sag;
+        P.sak[f] = t.sak;
     }
 }
 
@@ -868,7 +897,7 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, d
     FaceSide L, R;
     face_side(P, ip, W, f, 0, L);
     face_side(P, ip, W, f, 1, R);
-    face_implicit_terms(P, ip, f, L.ls, R.ls, L.evr, R.evr, L.nu, R.nu, L.nut, R.nut, L.q, R.q);
+    store_terms(P, ip, f, face_implicit_terms(P, ip, f, L.ls, R.ls, L.evr, R.evr, L.nu, R.nu, L.nut, R.nut, L.q, R.q));
     const double nutf = fmax(0.5 * add_sides(L.nut, R.nut), 0.0);
     double acc[24], accr[24];
     side_terms(1.0, L.fw, L.gn, L.gt, acc);
@@ -913,9 +942,11 @@ __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int si
     FaceSide M;
     face_side(P, ip, W, f, side, M);
     {
+        // the owner's lane forms and stores the face terms
         const double ls_o = pair_other(M.ls), evr_o = pair_other(M.evr), nu_o = pair_other(M.nu);
         const double t_o = pair_other(M.nut), q_o = pair_other(M.q);
-        if (side == 0) face_implicit_terms(P, ip, f, M.ls, ls_o, M.evr, evr_o, M.nu, nu_o, M.nut, t_o, M.q, q_o);
+        if (side == 0)
+            store_terms(P, ip, f, face_implicit_terms(P, ip, f, M.ls, ls_o, M.evr, evr_o, M.nu, nu_o, M.nut, t_o, M.q, q_o));
     }
     const double nutf = fmax(0.5 * add_sides(M.nut, pair_other(M.nut)), 0.0);
     const double sgn = side ? -1.0 : 1.0;
@@ -1014,11 +1045,11 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
     double nuc = P.nu[c];
-    auto block = [&](const Entries &E) {
+    auto block = [&](const Entries &E, int b) {
 #pragma unroll
         for (int k = 0; k < MAXV; k++) {
             if (!(E.flag[k] & CF_VALID)) continue;
-            const int f = E.face[k];
+            const int e = MAXV * b + k, f = E.face[k];
             double sg = (E.flag[k] & CF_OWNER) ? 1.0 : -1.0;
             double g[4];
 #pragma unroll
@@ -1026,20 +1057,20 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
             if (E.nbr[k] < 0) wall_face_terms(P, ip, w, f, g);
 #pragma unroll
             for (int k = 0; k < 4; k++) m[k] -= sg * g[k];
-            double S = P.flen[f];
+            double S = P.es[e];
             ls += P.lam[f] * S;
             if (ip.sa) {
                 saR += sg * P.saf[f];
                 sagS += sg * P.sag[f];
-                double qc = sg * (w[1] * P.fnx[f] + w[2] * P.fny[f]) / w[0];
+                double qc = (w[1] * P.enx[e] + w[2] * P.eny[e]) / w[0];   // the normal out of the cell
                 sad += 0.5 * (qc + fabs(qc)) * S + P.sak[f];
             }
         }
     };
     const Entries E0 = entries(P, c);
-    block(E0);
+    block(E0, c);
     const int ovf = next_block(P, E0);
-    if (ovf >= 0) block(entries(P, ovf));
+    if (ovf >= 0) block(entries(P, ovf), ovf);
 #pragma unroll
     for (int k = 0; k < 4; k++) P.M[k * N + c] = m[k];
     P.lsum[c] = 0.5 * ls;
@@ -1217,13 +1248,12 @@ __device__ __forceinline__ void first_front_incr(const Params<T> &P, const InstP
 // increments are not stored (first_front_incr).
 template <typename T>
 __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &ip, const double *W,
-                                           const double *w, int f, int j, int fl, const T *dws, T cfl, int lev1,
+                                           const double *w, int f, int e, int j, const T *dws, T cfl, int lev1,
                                            T *t)
 {
     const int N = P.nc;
-    double sg = (fl & CF_OWNER) ? 1.0 : -1.0;
-    double nx = sg * P.fnx[f], ny = sg * P.fny[f];
-    T S = T(P.flen[f]), lam = T(P.lam[f]);
+    double nx = P.enx[e], ny = P.eny[e];   // out of the cell
+    T S = T(P.es[e]), lam = T(P.lam[f]);
     double wj[5];
     T dj[5];
     if (j >= 0) {
@@ -1248,7 +1278,7 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
     t[4] = T(0);
     if (ip.sa) {
         double qj = (wj[1] * nx + wj[2] * ny) / wj[0];
-        double off = -0.5 * (qj - fabs(qj)) * P.flen[f] + P.sak[f];
+        double off = -0.5 * (qj - fabs(qj)) * P.es[e] + P.sak[f];
         t[4] = T(off) * dj[4];
     }
 }
@@ -1343,19 +1373,19 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     if (MODE == SW_FWD || MODE == SW_TOP) {
 #pragma unroll
         for (int k = 0; k < 5; k++) acc[k] = T(P.M[k * N + c]);
-        auto lower = [&](const Entries &E) {
+        auto lower = [&](const Entries &E, int b) {
 #pragma unroll
             for (int k = 0; k < MAXV; k++) {
                 const int j = E.nbr[k], fl = E.flag[k];
                 if (!(fl & CF_VALID) || j < 0 || !(fl & CF_LOWER)) continue;
-                sweep_term(P, ip, W, w, E.face[k], j, fl, dws, cfl, 0, t);
+                sweep_term(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t);
 #pragma unroll
                 for (int m = 0; m < 4; m++) acc[m] = acc_sub(acc[m], t[m]);
                 acc[4] = acc_add(acc[4], t[4]);
             }
         };
-        lower(E0);
-        if (ovf >= 0) lower(entries(P, ovf));
+        lower(E0, c);
+        if (ovf >= 0) lower(entries(P, ovf), ovf);
         const T iD = T(1) / D;
 #pragma unroll
         for (int k = 0; k < 4; k++) dws[k] = acc[k] * iD;
@@ -1371,18 +1401,18 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     }
 #pragma unroll
     for (int k = 0; k < 5; k++) acc[k] = T(0);
-    auto upper = [&](const Entries &E) {
+    auto upper = [&](const Entries &E, int b) {
 #pragma unroll
         for (int k = 0; k < MAXV; k++) {
             const int j = E.nbr[k], fl = E.flag[k];
-            if (!(fl & CF_VALID) || (j >= 0 && (fl & CF_LOWER))) continue;
-            sweep_term(P, ip, W, w, E.face[k], j, fl, dws, cfl, 0, t);
+            if (!(fl & CF_VALID) || (j >= 0 && (fl & (CF_LOWER | CF_OTHER)))) continue;
+            sweep_term(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t);
 #pragma unroll
             for (int m = 0; m < 5; m++) acc[m] = acc_add(acc[m], t[m]);
         }
     };
-    upper(E0);
-    if (ovf >= 0) upper(entries(P, ovf));
+    upper(E0, c);
+    if (ovf >= 0) upper(entries(P, ovf), ovf);
     T d[5];
     const T iD = T(1) / D;
 #pragma unroll
@@ -1427,16 +1457,17 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
     if (MODE == SW_FWD || MODE == SW_TOP) {
 #pragma unroll
         for (int k = 0; k < 5; k++) acc[k] = T(P.M[k * N + c]);
-        auto lower = [&](int f, int j, int fl) {
+        auto lower = [&](int f, int e, int j, int fl) {
 #pragma unroll
             for (int m = 0; m < 5; m++) t[m] = T(0);
-            if ((fl & CF_VALID) && j >= 0 && (fl & CF_LOWER)) sweep_term(P, ip, W, w, f, j, fl, dws, cfl, lev1, t);
+            if ((fl & CF_VALID) && j >= 0 && (fl & CF_LOWER)) sweep_term(P, ip, W, w, f, e, j, dws, cfl, lev1, t);
 #pragma unroll
             for (int m = 0; m < 4; m++) acc[m] = quad_fold<true>(acc[m], t[m]);
             acc[4] = quad_fold<false>(acc[4], t[4]);
         };
-        lower(f0, j0, fl0);
-        if (ovf >= 0) lower(P.cf_face[MAXV * ovf + q], P.cf_nbr[MAXV * ovf + q], P.cf_flag[MAXV * ovf + q]);
+        lower(f0, MAXV * c + q, j0, fl0);
+        if (ovf >= 0)
+            lower(P.cf_face[MAXV * ovf + q], MAXV * ovf + q, P.cf_nbr[MAXV * ovf + q], P.cf_flag[MAXV * ovf + q]);
         const T iD = T(1) / D;
 #pragma unroll
         for (int k = 0; k < 4; k++) dws[k] = acc[k] * iD;
@@ -1456,15 +1487,17 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
     }
 #pragma unroll
     for (int k = 0; k < 5; k++) acc[k] = T(0);
-    auto upper = [&](int f, int j, int fl) {
+    auto upper = [&](int f, int e, int j, int fl) {
 #pragma unroll
         for (int m = 0; m < 5; m++) t[m] = T(0);
-        if ((fl & CF_VALID) && !(j >= 0 && (fl & CF_LOWER))) sweep_term(P, ip, W, w, f, j, fl, dws, cfl, lev1, t);
+        if ((fl & CF_VALID) && !(j >= 0 && (fl & (CF_LOWER | CF_OTHER))))
+            sweep_term(P, ip, W, w, f, e, j, dws, cfl, lev1, t);
 #pragma unroll
         for (int m = 0; m < 5; m++) acc[m] = quad_fold<false>(acc[m], t[m]);
     };
-    upper(f0, j0, fl0);
-    if (ovf >= 0) upper(P.cf_face[MAXV * ovf + q], P.cf_nbr[MAXV * ovf + q], P.cf_flag[MAXV * ovf + q]);
+    upper(f0, MAXV * c + q, j0, fl0);
+    if (ovf >= 0)
+        upper(P.cf_face[MAXV * ovf + q], MAXV * ovf + q, P.cf_nbr[MAXV * ovf + q], P.cf_flag[MAXV * ovf + q]);
     if (q != 0) return 0.0;
     T d[5];
     const T iD = T(1) / D;
@@ -1545,6 +1578,28 @@ __global__ __launch_bounds__(512) void k_sweep_wg(Params<T> P, const int *lev_of
     for (int i = 0; i < nlev; i++) {
         int l = FWD ? i : nlev - 1 - i;
         int c0 = lev_off[l], c1 = lev_off[l + 1];
+        for (int c = c0 + (int)threadIdx.x; c < c1; c += (int)blockDim.x) {
+            int inst;
+            (void)sweep_cell<T, FWD ? SW_FWD : SW_BWD_ONLY, ONE>(P, c, inst);
+        }
+        __syncthreads();
+    }
+}
+
+// The whole sweep of one sweep block per wave: the block's wavefronts one
+// after another, cells of a wavefront on the lanes.  Blocks do not couple in
+// the sweeps, so no wave waits for another; inside the one-wave workgroup
+// the barrier after each wavefront orders its dW writes before the next
+// wavefront's reads.  As in the one-workgroup sweep, the backward pass
+// leaves the update to k_update.
+template <typename T, bool FWD, bool ONE>
+__global__ __launch_bounds__(64) void k_sweep_blk(Params<T> P, const int *bl_off, const int *bl_lo, const int *bl_hi)
+{
+    const int gb = blockIdx.x;
+    const int k0 = bl_off[gb], k1 = bl_off[gb + 1];
+    for (int i = 0; i < k1 - k0; i++) {
+        const int k = FWD ? k0 + i : k1 - 1 - i;
+        const int c0 = bl_lo[k], c1 = bl_hi[k];
         for (int c = c0 + (int)threadIdx.x; c < c1; c += (int)blockDim.x) {
             int inst;
             (void)sweep_cell<T, FWD ? SW_FWD : SW_BWD_ONLY, ONE>(P, c, inst);
@@ -1698,6 +1753,21 @@ template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, 
         LAUNCH_ONE(k_update, T, dim3(nblk(P.nc, L.block[3])), dim3(L.block[3]), P);
     }
 }
+template <typename T>
+void launch_sweep_blk(const Launch &L, const Params<T> &P, const int *bl_off, const int *bl_lo, const int *bl_hi,
+                      int ngb, bool fwd)
+{
+    if (ngb <= 0) return;
+    const bool one = P.ninst == 1;
+    if (fwd) {
+        if (one) hipLaunchKernelGGL((k_sweep_blk<T, true, true>), dim3(ngb), dim3(64), 0, L.s, P, bl_off, bl_lo, bl_hi);
+        else hipLaunchKernelGGL((k_sweep_blk<T, true, false>), dim3(ngb), dim3(64), 0, L.s, P, bl_off, bl_lo, bl_hi);
+    } else {
+        if (one) hipLaunchKernelGGL((k_sweep_blk<T, false, true>), dim3(ngb), dim3(64), 0, L.s, P, bl_off, bl_lo, bl_hi);
+        else hipLaunchKernelGGL((k_sweep_blk<T, false, false>), dim3(ngb), dim3(64), 0, L.s, P, bl_off, bl_lo, bl_hi);
+        LAUNCH_ONE(k_update, T, dim3(nblk(P.nc, L.block[3])), dim3(L.block[3]), P);
+    }
+}
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
                           const int *woff, const double *wseg, double *dwall)
 {
@@ -1731,7 +1801,9 @@ void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, cons
     template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, int, int);          \
     template void launch_commit<T>(const Launch &, const Params<T> &, int);                        \
     template void launch_explicit<T>(const Launch &, const Params<T> &);                           \
-    template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool);
+    template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool);                 \
+    template void launch_sweep_blk<T>(const Launch &, const Params<T> &, const int *, const int *, const int *,  \
+                                      int, bool);
 INST(double)
 INST(float)
 

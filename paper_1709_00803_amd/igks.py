@@ -63,6 +63,7 @@ _SIGS = {
     "igks_last_error": (C.c_char_p, [_P]),
     "igks_mesh_upload": (C.c_int, [_P, C.c_int32, _DP, C.c_int32, _IP, _IP, C.c_int32, _IP, _IP]),
     "igks_mesh_info": (C.c_int, [_P, _IP, _IP, _IP, _IP]),
+    "igks_set_sweep_blocks": (C.c_int, [_P, C.c_int32, _IP]),
     "igks_wavefront_sizes": (C.c_int, [_P, _IP, C.c_int32]),
     "igks_workspace_size": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "igks_bind_workspace": (C.c_int, [_P, _P, C.c_size_t]),
@@ -235,12 +236,18 @@ class Solver(_Context):
 
     ``mesh`` needs xy, cell_ptr, cell_nodes, bface_nodes, bface_tag (see
     meshgen.Mesh).  ``stream``: a torch.cuda.Stream (default: a new one).
+    ``sweep_blocks``: the sweep block of each cell (igks_set_sweep_blocks),
+    None for one block.
     """
 
-    def __init__(self, mesh, options: igks_options | None = None, stream=None, device="cuda", **kw):
+    def __init__(self, mesh, options: igks_options | None = None, stream=None, device="cuda", sweep_blocks=None,
+                 **kw):
         self._open(1, options, stream, device, kw)
         keep, args = _mesh_args(mesh)
         self._chk(igks_mesh_upload(self.ctx, *args))
+        if sweep_blocks is not None:
+            b, pb = _i(np.asarray(sweep_blocks).reshape(mesh.n_cells))
+            self._chk(igks_set_sweep_blocks(self.ctx, 0, pb))
         self._bind()
         self.n, self.nf, self.nwall = self.total_cells, self.total_faces, self.total_wall
 
@@ -290,12 +297,16 @@ class BatchSolver(_Context):
     """Many independent instances (meshes of any sizes, one flow condition
     each) iterated together in the same kernel launches."""
 
-    def __init__(self, meshes, options: igks_options | None = None, stream=None, device="cuda", **kw):
+    def __init__(self, meshes, options: igks_options | None = None, stream=None, device="cuda", sweep_blocks=None,
+                 **kw):
         self._open(len(meshes), options, stream, device, kw)
         self.ninst = len(meshes)
         for i, m in enumerate(meshes):
             keep, args = _mesh_args(m)
             self._chk(igks_batch_mesh_upload(self.ctx, i, *args))
+            if sweep_blocks is not None and sweep_blocks[i] is not None:
+                b, pb = _i(np.asarray(sweep_blocks[i]).reshape(m.n_cells))
+                self._chk(igks_set_sweep_blocks(self.ctx, i, pb))
         self._bind()
         self.n, self.nf, self.nwall = [], [], []
         for i in range(self.ninst):

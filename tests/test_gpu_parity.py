@@ -602,3 +602,69 @@ def test_converged_plate_drag_matches_oracle(igks):
             f"cd gpu={lg['cd']:.15e} oracle={lo['cd']:.15e} rel={rel:.2e} state={dW:.2e}")
         assert g.residual()["res_drop"] < 1e-10
         assert rel <= 1e-9
+
+
+@pytest.mark.parametrize("sa", [False, True])
+def test_sweep_blocks_trajectory_parity(igks, sa):
+    """Sweep blocks (the sweeps couple only cells of one block): the GPU's
+    three sweep schedules (a launch per wavefront, one workgroup, a wave per
+    block) give bitwise the same iterates, and they follow the oracle with
+    the same blocks."""
+    m0 = mg.random_hybrid(16, 12, seed=17, tags=TAGS_SYM, jitter=0.25)
+    m, blk = mg.block_order(m0, 24)
+    flow = (0.3, 2.0, 3e4 if sa else 3e3, 3.0 if sa else -1.0)
+    tag = f"sweep blocks sa={sa}"
+    say("case", tag, m.n_cells, "cells,", int(blk.max()) + 1, "blocks")
+    o = po.Oracle(m, threads=sens.host_threads(), cfl_init=5.0)
+    o.set_sweep_blocks(blk)
+    o.set_freestream(*flow)
+    runs = []
+    for sweep in (1, 2, 3):
+        g = igks.Solver(m, cfl_init=5.0, chunk=5, sweep=sweep, sweep_blocks=blk)
+        assert g.schedule()[4] == sweep
+        g.set_freestream(*flow)
+        runs.append(g)
+    for step in range(4):
+        o.iterate(5)
+        Wo = o.get_state()
+        states = []
+        for g in runs:
+            g.iterate(5)
+            states.append(g.get_state())
+        assert all(np.array_equal(states[0], s) for s in states[1:]), tag
+        scale = np.abs(Wo).max(axis=1, keepdims=True)
+        err = (np.abs(states[0] - Wo) / np.maximum(scale, 1e-300)).max()
+        ro, rg = o.residual(), runs[0].residual()
+        say(f"[{tag}] it={5 * (step + 1)} state err={err:.3e} res o={ro['res_l2']:.6e} g={rg['res_l2']:.6e}")
+        assert err <= 1e-9
+        assert abs(rg["res_l2"] - ro["res_l2"]) <= 1e-8 * ro["res_l2"]
+
+
+def test_sweep_blocks_batch_parity(igks):
+    """A batch whose instances have their own sweep blocks (one instance
+    without any): each instance follows the oracle with its blocks."""
+    ms, blks, flows = [], [], []
+    for k, (seed, mc) in enumerate(((21, 20), (22, 40), (23, None))):
+        m0 = mg.random_hybrid(12, 9, seed=seed, tags=TAGS_SYM, jitter=0.25)
+        if mc:
+            m, b = mg.block_order(m0, mc)
+        else:
+            m, b = m0, None
+        ms.append(m)
+        blks.append(b)
+        flows.append((0.3 + 0.05 * k, 1.0 + k, 2e3 * (k + 1), -1.0 if k != 1 else 3.0))
+    g = igks.BatchSolver(ms, cfl_init=5.0, chunk=4, sweep_blocks=blks)
+    assert g.schedule()[4] == 3
+    for i, f in enumerate(flows):
+        g.set_freestream(i, *f)
+    g.iterate(8)
+    for i, (m, b, f) in enumerate(zip(ms, blks, flows)):
+        o = po.Oracle(m, cfl_init=5.0)
+        if b is not None:
+            o.set_sweep_blocks(b)
+        o.set_freestream(*f)
+        o.iterate(8)
+        Wo, Wg = o.get_state(), g.get_state(i)
+        err = (np.abs(Wg - Wo) / np.maximum(np.abs(Wo).max(axis=1, keepdims=True), 1e-300)).max()
+        say(f"[sweep blocks batch] instance {i}: state err {err:.3e}")
+        assert err <= 1e-9

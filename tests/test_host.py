@@ -241,7 +241,7 @@ def test_batch_bookkeeping():
 
 
 def test_call_order_and_option_errors():
-    for bad in (dict(block=96), dict(block=512), dict(sweep=3), dict(precision=5), dict(chunk=-1),
+    for bad in (dict(block=96), dict(block=512), dict(sweep=4), dict(precision=5), dict(chunk=-1),
                 dict(flux_lanes=3), dict(wall_temp=-1.0), dict(wall_temp=float("nan")), dict(limiter_freeze=-0.1),
                 dict(limiter_freeze=1.0), dict(tau_jump=2)):
         rc, ctx = ctx_for(**bad)
@@ -317,5 +317,48 @@ def test_static_workspace_rejects_large_meshes():
         assert igks.igks_bind_static_workspace(ctx) == igks.IGKS_ENOMEM
         assert b"static workspace holds 67108864" in igks.igks_last_error(ctx)
         assert igks.igks_set_freestream(ctx, 0.3, 0.0, 1e4, -1.0) == igks.IGKS_EINVAL
+    finally:
+        igks.igks_destroy(ctx)
+
+
+def block_levels(mesh, blk):
+    """Wavefront of each cell when the sweeps couple only cells of one block:
+    1 + the largest wavefront among its same-block neighbours of smaller
+    index (0 without any)."""
+    _, nb = mg.cell_adjacency(mesh)
+    lev = np.zeros(mesh.n_cells, dtype=np.int64)
+    for i in range(mesh.n_cells):
+        lower = [j for j in nb[i] if 0 <= j < i and blk[j] == blk[i]]
+        lev[i] = 1 + lev[lower].max() if lower else 0
+    return lev
+
+
+@pytest.mark.parametrize("max_cells", [16, 64])
+def test_sweep_blocks_wavefronts(max_cells):
+    """Sweep blocks cut the wavefronts: the library's count and sizes match
+    the levels computed here with coupling inside blocks only; blocks of a
+    batch add up per wavefront; NULL restores one block; a negative block is
+    refused."""
+    m = mg.random_hybrid(14, 10, seed=8, tags=dict(bottom=mg.WALL))
+    mb, blk = mg.block_order(m, max_cells)
+    assert blk.max() >= 3
+    lev = block_levels(mb, blk)
+    rc, ctx = ctx_for(2)
+    try:
+        assert upload(ctx, mb, 0) == igks.IGKS_OK and upload(ctx, m, 1) == igks.IGKS_OK
+        b = np.ascontiguousarray(blk, np.int32)
+        assert igks.igks_set_sweep_blocks(ctx, 0, b.ctypes.data_as(C.POINTER(C.c_int32))) == igks.IGKS_OK
+        rc, (nc, nf, nw, nl) = info(ctx)
+        want = np.zeros(max(lev.max() + 1, levels_by_hand(m)), dtype=np.int64)
+        want[:lev.max() + 1] += np.bincount(lev)
+        want[:levels_by_hand(m)] += np.bincount(cell_levels(m))
+        assert nl == len(want)
+        rc, sizes = wavefront_sizes(ctx, nl)
+        assert np.array_equal(sizes[:nl], want)
+        assert lev.max() + 1 < levels_by_hand(mb)
+        assert igks.igks_set_sweep_blocks(ctx, 0, None) == igks.IGKS_OK
+        assert info(ctx)[1][3] == max(levels_by_hand(mb), levels_by_hand(m))
+        b[3] = -1
+        assert igks.igks_set_sweep_blocks(ctx, 0, b.ctypes.data_as(C.POINTER(C.c_int32))) == igks.IGKS_EINVAL
     finally:
         igks.igks_destroy(ctx)
