@@ -39,6 +39,8 @@ constexpr int NSLOT = 64;
 constexpr int SLOT_STRIDE = 16;   // unsigned long longs from one slot to the next
 enum { SL_DTMIN = 0, SL_RESINF = 1, SL_E40 = 2, NSL = 3 };   // Eq.23 minimum, max |M|, Eq.40 maximum
 constexpr int NORM_SLICE = 1024;   // squares per block of the residual-norm partial sums
+// face record layout (Params::frec)
+constexpr int FR_STRIDE = 8, FR_F = 0, FR_LAM = 4, FR_SAF = 5, FR_SAG = 6, FR_SAK = 7;
 constexpr int NCLASS = 4;     // kernel classes with a tunable block size: prep, flux, gather, sweep
 
 // Free stream of one instance (read-only while iterating).
@@ -100,11 +102,13 @@ struct Params {
     // face arrays (internal face order)
     const int *fl, *fr, *fbc;
     const double *fnx, *fny, *flen, *frl, *frr, *fdl, *fdr, *frn;
-    double *flux;              // nf x 4 (the four components of a face together): time-averaged flux times length, global frame
-    double *lam;               // spectral radius per face
-    double *saf;               // SA: (-F_inv + F_vis) S
-    double *sag;               // SA: (nu~_r - nu~_l)/|r.n| S
-    double *sak;               // SA: diffusion coefficient of the face times S/|r.n|
+    // nf x FR_STRIDE face records, one 64-byte record per face, so that a
+    // cell reading a face's outputs through its entries touches one cache
+    // line: FR_F..FR_F+3 the time-averaged flux times length (global frame),
+    // FR_LAM the spectral radius, FR_SAF the SA (-F_inv + F_vis) S, FR_SAG
+    // (nu~_r - nu~_l)/|r.n| S, FR_SAK the SA diffusion coefficient of the
+    // face times S/|r.n|
+    double *frec;
     // per-instance cell lists (internal ids, ascending) for the norms
     const int *icell, *ioff;
     const int *ipos;           // position of each cell in icell
@@ -145,7 +149,7 @@ template <typename T> void launch_commit(const Launch &L, const Params<T> &P, in
 template <typename T> void launch_explicit(const Launch &L, const Params<T> &P);
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
                           const int *woff, const double *wseg, double *dwall);
-void launch_gather_faces(const Launch &L, int n, const int *faces, const double *flux, int nf, double *out);
+void launch_gather_faces(const Launch &L, int n, const int *faces, const double *frec, int nf, double *out);
 void launch_fill_instance(const Launch &L, int n, const int *cells, int nc, const double *Winf, double *W);
 void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, const double *src, double *dst,
                           bool to_instance);

@@ -74,7 +74,7 @@ struct WsMap {
     Buf ip, is, slot, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx, phi;
     Buf cinst, finst, icell, ioff, g2i, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
     Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, ipart, hist, ipos;
-    Buf flux, lam, saf, sag, sak, enx, eny, es;
+    Buf frec, enx, eny, es;
     Buf wall_faces, wall_out, woff, wseg, lev_off, bl_off, bl_lo, bl_hi, stage, backup;
     size_t total;
 };
@@ -603,8 +603,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.fl = L.add(F * I); w.fr = L.add(F * I); w.fbc = L.add(F * I);
     w.fnx = L.add(F * D); w.fny = L.add(F * D); w.flen = L.add(F * D); w.frl = L.add(2 * F * D);
     w.frr = L.add(2 * F * D); w.fdl = L.add(F * D); w.fdr = L.add(F * D); w.frn = L.add(F * D);
-    w.flux = L.add(4 * F * D); w.lam = L.add(F * D); w.saf = L.add(F * D); w.sag = L.add(F * D);
-    w.sak = L.add(F * D);
+    w.frec = L.add(FR_STRIDE * F * D);
     w.enx = L.add(E * D); w.eny = L.add(E * D); w.es = L.add(E * D);
     w.ipart = L.add(2 * NI * (size_t)norm_rb(G) * D);
     w.ipos = L.add(N * I);
@@ -651,7 +650,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.fl = In(w.fl); P.fr = In(w.fr); P.fbc = In(w.fbc);
     P.fnx = D(w.fnx); P.fny = D(w.fny); P.flen = D(w.flen); P.frl = D(w.frl); P.frr = D(w.frr);
     P.fdl = D(w.fdl); P.fdr = D(w.fdr); P.frn = D(w.frn);
-    P.flux = D(w.flux); P.lam = D(w.lam); P.saf = D(w.saf); P.sag = D(w.sag); P.sak = D(w.sak);
+    P.frec = D(w.frec);
     P.enx = D(w.enx); P.eny = D(w.eny); P.es = D(w.es);
     P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipos = In(w.ipos); P.ipart = D(w.ipart); P.rb = norm_rb(c->g);
     P.hist = D(w.hist); P.hist_cap = c->hist_cap;
@@ -1416,7 +1415,7 @@ int igks_batch_get_wall_loads(igks_ctx *c, int32_t inst, double *cl, double *cd,
     const int w0 = c->g.woff[inst], nw = c->g.woff[inst + 1] - w0;
     double *wout = (double *)(c->ws + c->w.wall_out.off);
     Launch L = launch_of(c);
-    launch_gather_faces(L, nw, (const int *)(c->ws + c->w.wall_faces.off) + w0, c->P64.flux, c->g.F, wout);
+    launch_gather_faces(L, nw, (const int *)(c->ws + c->w.wall_faces.off) + w0, c->P64.frec, c->g.F, wout);
     HIPCHK(c, hipGetLastError());
     std::vector<double> fw(4 * (size_t)std::max(nw, 1));
     if (nw > 0) HIPCHK(c, hipMemcpyAsync(fw.data(), wout, sizeof(double) * 4 * nw, hipMemcpyDeviceToHost, c->stream));

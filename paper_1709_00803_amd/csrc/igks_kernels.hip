@@ -869,11 +869,12 @@ __device__ __forceinline__ FaceTerms face_implicit_terms(const Params<T> &P, con
 template <typename T>
 __device__ __forceinline__ void store_terms(const Params<T> &P, const InstParam &ip, int f, const FaceTerms &t)
 {
-    P.lam[f] = t.lam;
+    double *r = P.frec + FR_STRIDE * (size_t)f;
+    r[FR_LAM] = t.lam;
     if (ip.sa) {
-        P.saf[f] = t.saf;
-        P.sag[f] = t.sag;
-        P.sak[f] = t.sak;
+        r[FR_SAF] = t.saf;
+        r[FR_SAG] = t.sag;
+        r[FR_SAK] = t.sak;
     }
 }
 
@@ -926,7 +927,7 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, d
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
 #pragma unroll
-    for (int k = 0; k < 4; k++) P.flux[4 * (size_t)f + k] = g[k];
+    for (int k = 0; k < 4; k++) P.frec[FR_STRIDE * (size_t)f + FR_F + k] = g[k];
 }
 
 // Per face, on a pair of lanes (side 0 the owner, side 1 the neighbour or
@@ -975,8 +976,8 @@ __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int si
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
     // each lane writes two of the four components
-    P.flux[4 * (size_t)f + 2 * side] = side ? g[2] : g[0];
-    P.flux[4 * (size_t)f + 2 * side + 1] = side ? g[3] : g[1];
+    P.frec[FR_STRIDE * (size_t)f + FR_F + 2 * side] = side ? g[2] : g[0];
+    P.frec[FR_STRIDE * (size_t)f + FR_F + 2 * side + 1] = side ? g[3] : g[1];
 }
 
 // one lane per face
@@ -1051,19 +1052,20 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
             if (!(E.flag[k] & CF_VALID)) continue;
             const int e = MAXV * b + k, f = E.face[k];
             double sg = (E.flag[k] & CF_OWNER) ? 1.0 : -1.0;
+            const double *r = P.frec + FR_STRIDE * (size_t)f;
             double g[4];
 #pragma unroll
-            for (int k = 0; k < 4; k++) g[k] = P.flux[4 * (size_t)f + k];
+            for (int k = 0; k < 4; k++) g[k] = r[FR_F + k];
             if (E.nbr[k] < 0) wall_face_terms(P, ip, w, f, g);
 #pragma unroll
             for (int k = 0; k < 4; k++) m[k] -= sg * g[k];
             double S = P.es[e];
-            ls += P.lam[f] * S;
+            ls += r[FR_LAM] * S;
             if (ip.sa) {
-                saR += sg * P.saf[f];
-                sagS += sg * P.sag[f];
+                saR += sg * r[FR_SAF];
+                sagS += sg * r[FR_SAG];
                 double qc = (w[1] * P.enx[e] + w[2] * P.eny[e]) / w[0];   // the normal out of the cell
-                sad += 0.5 * (qc + fabs(qc)) * S + P.sak[f];
+                sad += 0.5 * (qc + fabs(qc)) * S + r[FR_SAK];
             }
         }
     };
@@ -1253,7 +1255,7 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
 {
     const int N = P.nc;
     double nx = P.enx[e], ny = P.eny[e];   // out of the cell
-    T S = T(P.es[e]), lam = T(P.lam[f]);
+    T S = T(P.es[e]), lam = T(P.frec[FR_STRIDE * (size_t)f + FR_LAM]);
     double wj[5];
     T dj[5];
     if (j >= 0) {
@@ -1278,7 +1280,7 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
     t[4] = T(0);
     if (ip.sa) {
         double qj = (wj[1] * nx + wj[2] * ny) / wj[0];
-        double off = -0.5 * (qj - fabs(qj)) * P.es[e] + P.sak[f];
+        double off = -0.5 * (qj - fabs(qj)) * P.es[e] + P.frec[FR_STRIDE * (size_t)f + FR_SAK];
         t[4] = T(off) * dj[4];
     }
 }
@@ -1652,13 +1654,13 @@ __global__ __launch_bounds__(256) void k_wall_distance(int nc, const double *xc,
     d[c] = best;
 }
 
-__global__ void k_gather_faces(int n, const int *faces, const double *flux, int nf, double *out)
+__global__ void k_gather_faces(int n, const int *faces, const double *frec, int nf, double *out)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int f = faces[i];
 #pragma unroll
-    for (int k = 0; k < 4; k++) out[4 * i + k] = flux[4 * (size_t)f + k];
+    for (int k = 0; k < 4; k++) out[4 * i + k] = frec[FR_STRIDE * (size_t)f + FR_F + k];
 }
 
 __global__ void k_fill_instance(int n, const int *cells, int nc, double w0, double w1, double w2, double w3,
@@ -1773,10 +1775,10 @@ void launch_wall_distance(const Launch &L, int nc, const double *xc, const doubl
 {
     hipLaunchKernelGGL(k_wall_distance, dim3(nblk(nc, 256)), dim3(256), 0, L.s, nc, xc, yc, cinst, woff, wseg, dwall);
 }
-void launch_gather_faces(const Launch &L, int n, const int *faces, const double *flux, int nf, double *out)
+void launch_gather_faces(const Launch &L, int n, const int *faces, const double *frec, int nf, double *out)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_gather_faces, dim3(nblk(n, 256)), dim3(256), 0, L.s, n, faces, flux, nf, out);
+    hipLaunchKernelGGL(k_gather_faces, dim3(nblk(n, 256)), dim3(256), 0, L.s, n, faces, frec, nf, out);
 }
 void launch_fill_instance(const Launch &L, int n, const int *cells, int nc, const double *Winf, double *W)
 {
