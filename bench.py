@@ -74,7 +74,7 @@ def kernel_bytes(n, f, e, sa, mixed):
     # lsinv, area; writes nu, lamc, vort, gradients
     b["prep"] = 5 * d * n + 2 * i4 * n + (2 * i4 + 2 * d) * e + 3 * d * f + 4 * d * n + (3 + 8) * d * n
     # fl, fr, finst; normal, length, face-centre offsets, distances; W and
-    # gradients of both sides; writes flux, lam (+ SA saf, sag, sak)
+    # gradients of both sides; writes the face record: flux, lam (+ SA saf, sag, sak)
     b["flux"] = (3 * i4 + 10 * d) * f + (5 + 8) * d * n + (4 + 1 + 3 * s) * d * f
     # cinst, cf_ptr, ipos; cf_face/cf_flag; flux, lam, length (+ SA: saf, sag,
     # sak, normal); W (+ SA: nu, wall distance, vorticity, area); writes M,
@@ -307,6 +307,50 @@ def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=
                 cell_updates_per_s=m.n_cells * it / dt)
 
 
+def run_to_drop(igks, mesh, flow, precision, blocks=None, target=1e-10, max_it=40000, chunk=200, scheme=0,
+                cfl=1000.0, max_s=60.0):
+    """Iterations and seconds from the impulsive start to a density-residual
+    drop of `target` (or to max_it iterations / about max_s seconds)."""
+    import torch
+    s = igks.Solver(mesh, precision=precision, cfl_init=cfl, chunk=chunk, scheme=scheme, sweep_blocks=blocks)
+    s.set_freestream(*flow)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = 0
+    while it < max_it and time.perf_counter() - t0 < max_s:
+        s.iterate(chunk)
+        it += chunk
+        if s.residual()["res_drop"] <= target:
+            break
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = s.residual()
+    wl = s.wall_loads()
+    return dict(iterations=it, seconds=round(dt, 4), drop=r["res_drop"], reached=r["res_drop"] <= target,
+                cl=wl["cl"], cd=wl["cd"], ms_per_iteration=round(1e3 * dt / max(it, 1), 4),
+                wavefronts=s.nlev, sweep_schedule=int(s.schedule()[4]))
+
+
+def time_to_drop_joukowski(igks, mg):
+    """The 40k-cell laminar Joukowski (Ma 0.5, Re 5000, alpha 2) from the
+    impulsive start to a 1e-10 drop: block LU-SGS (blocks of at most 512
+    cells grown along the strongest couplings, generation order inside, a
+    wave per block) in FP64 and mixed precision, against the colour order
+    (3 wavefronts, fast sweeps that do not converge) and the explicit
+    scheme."""
+    flow = WORKLOADS["jouk40k"]["flow"]
+    mb, blk = mg.workload_blocks("jouk40k", 512)
+    mc = mg.workload("jouk40k")
+    out = dict(workload="jouk40k: " + WORKLOADS["jouk40k"]["desc"], target=1e-10, blocks=int(blk.max()) + 1,
+               block_cells=512)
+    out["blocks_fp64"] = run_to_drop(igks, mb, flow, igks.IGKS_FP64, blk, max_it=60000)
+    out["blocks_mixed"] = run_to_drop(igks, mb, flow, igks.IGKS_MIXED, blk, max_it=60000)
+    out["colour_fp64"] = run_to_drop(igks, mc, flow, igks.IGKS_FP64, None, max_it=10000, max_s=15.0)
+    out["explicit_fp64_cfl0.9"] = run_to_drop(igks, mc, flow, igks.IGKS_FP64, None, max_it=2000000, chunk=2000,
+                                             scheme=1, cfl=0.9, max_s=40.0)
+    return out
+
+
 def time_to_converge_cavity(igks, mg, max_it=20000, chunk=200):
     """The lid-driven cavity (100x100, Re 1000, Ma 0.1 sqrt 3, isothermal
     walls) from rest, implicit CFL 1000 growing by Eq.25, to the paper's
@@ -537,6 +581,7 @@ def main():
                                 "batched_plates": time_to_drop_batch(igks, mg),
                                 "explicit_fp64_cfl0.9": time_to_drop(igks, mg, igks.IGKS_FP64, scheme=1, cfl=0.9,
                                                                      chunk=1000, max_it=400000)}
+        out["time_to_1e-10"]["jouk40k"] = time_to_drop_joukowski(igks, mg)
         say("time to 1e-10 done")
         out["cavity_to_eq40"] = time_to_converge_cavity(igks, mg)
         out["turbulent_plate_to_eq40"] = time_to_converge_turbulent_plate(igks, mg)

@@ -900,20 +900,21 @@ def _interior_faces(mesh: Mesh):
     return cid[i0], cid[i1], lo[i0], hi[i0]
 
 
-def coupled_blocks(mesh: Mesh, max_cells: int = 1024) -> np.ndarray:
-    """Sweep block of each cell, grown along the strongest geometric
-    couplings first: interior faces sorted by S / |x_c1 - x_c0| (face length
-    over centroid distance: large across the long faces of thin cells, so the
-    wall-normal stacks of a boundary layer stay in one block), two cells'
-    blocks merged while the result holds at most ``max_cells`` cells; then a
-    block of fewer than max_cells / 4 cells joins the neighbouring block it
-    shares its strongest face with, up to 3 max_cells / 2 cells."""
+def coupled_blocks(mesh: Mesh, max_cells: int = 1024, strong: float = 4.0) -> np.ndarray:
+    """Sweep block of each cell: cells joined across their strongly coupled
+    faces stay in one block, and the rest is cut by coordinate bisection.
+    A face couples its two cells with weight S / |x_c1 - x_c0| (face length
+    over centroid distance), large across the long faces of thin cells; the
+    cells across faces of weight above ``strong`` are merged first (strongest
+    first, groups of at most ``max_cells``), so the wall-normal stacks of a
+    boundary layer become single groups.  The groups are then split by
+    recursive bisection of their centroids along the longer extent at the
+    cell-count median, until a part holds at most ``max_cells`` cells."""
     c0, c1, na, nbn = _interior_faces(mesh)
     ctr = mesh.centroids_approx()
     S = np.linalg.norm(mesh.xy[nbn] - mesh.xy[na], axis=1)
     d = np.linalg.norm(ctr[c1] - ctr[c0], axis=1)
     w = S / np.maximum(d, 1e-300)
-    order = np.argsort(-w, kind="stable")
     parent = np.arange(mesh.n_cells)
     size = np.ones(mesh.n_cells, dtype=np.int64)
 
@@ -925,20 +926,38 @@ def coupled_blocks(mesh: Mesh, max_cells: int = 1024) -> np.ndarray:
             parent[x], x = r, parent[x]
         return r
 
-    for cap, small in ((max_cells, None), (3 * max_cells // 2, max_cells // 4)):
-        for f in order:
-            ra, rb = find(c0[f]), find(c1[f])
-            if ra == rb or size[ra] + size[rb] > cap:
-                continue
-            if small is not None and min(size[ra], size[rb]) >= small:
-                continue
-            if size[ra] < size[rb]:
-                ra, rb = rb, ra
-            parent[rb] = ra
-            size[ra] += size[rb]
+    for f in np.argsort(-w, kind="stable"):
+        if w[f] <= strong:
+            break
+        ra, rb = find(c0[f]), find(c1[f])
+        if ra == rb or size[ra] + size[rb] > max_cells:
+            continue
+        if size[ra] < size[rb]:
+            ra, rb = rb, ra
+        parent[rb] = ra
+        size[ra] += size[rb]
     roots = np.array([find(x) for x in range(mesh.n_cells)])
-    _, blk = np.unique(roots, return_inverse=True)
-    return blk.astype(np.int32)
+    _, grp = np.unique(roots, return_inverse=True)
+    ng = int(grp.max()) + 1
+    gsize = np.bincount(grp, minlength=ng)
+    gc = np.stack([np.bincount(grp, weights=ctr[:, k], minlength=ng) for k in range(2)], 1) / gsize[:, None]
+    gblk = np.zeros(ng, dtype=np.int64)
+    stack = [np.arange(ng)]
+    nb = 0
+    while stack:
+        idx = stack.pop()
+        if gsize[idx].sum() <= max_cells or len(idx) == 1:
+            gblk[idx] = nb
+            nb += 1
+            continue
+        p = gc[idx]
+        ax = int(np.argmax(p.max(axis=0) - p.min(axis=0)))
+        order = idx[np.argsort(p[:, ax], kind="stable")]
+        cum = np.cumsum(gsize[order])
+        h = int(np.clip(np.searchsorted(cum, cum[-1] / 2.0), 1, len(order) - 1))
+        stack.append(order[h:])
+        stack.append(order[:h])
+    return gblk[grp].astype(np.int32)
 
 
 def block_order(mesh: Mesh, max_cells: int = 1024, method: str = "rcb"):
@@ -964,8 +983,9 @@ def sfc_order(mesh: Mesh):
 # Named workloads
 # ---------------------------------------------------------------------------
 
-def workload(name: str) -> Mesh:
-    """The named synthetic workloads, colour-ordered.
+def workload(name: str, order: str = "colour") -> Mesh:
+    """The named synthetic workloads, colour-ordered (``order`` "natural":
+    in generation order).
 
     plate64x32   laminar flat plate, 64x32 quads
     jouk40k      Joukowski, 128 wall points, 30 quad layers (1e-4, 1.12), ~40k cells, seed 2
@@ -982,9 +1002,17 @@ def workload(name: str) -> Mesh:
         m = joukowski_hybrid(2048, 90, 1e-6, 1.10, seed=4, target_cells=2000000)
     else:
         raise KeyError(name)
-    out, _, _ = colour_order(m)
+    out = colour_order(m)[0] if order == "colour" else m
     out.meta["workload"] = name
     return out
+
+
+def workload_blocks(name: str, max_cells: int = 512):
+    """The named workload renumbered block by block (coupled_blocks, each
+    block in generation order): (mesh, sweep block of each cell)."""
+    m, blk = block_order(workload(name, order="natural"), max_cells, "coupled")
+    m.meta["workload"] = name
+    return m, blk
 
 
 # ---------------------------------------------------------------------------

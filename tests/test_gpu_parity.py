@@ -604,6 +604,53 @@ def test_converged_plate_drag_matches_oracle(igks):
         assert rel <= 1e-9
 
 
+def test_converged_sa_joukowski_loads_match_oracle(igks):
+    """Converged lift/drag parity on an SA Joukowski aerofoil (8k cells, Ma
+    0.3, alpha 4, Re 5e4, inflow nu-tilde 3 nu): the GPU runs from the
+    impulsive start to a 1e-11 density-residual drop (block LU-SGS) in FP64
+    and in mixed precision.  At each GPU state the oracle's C_L and C_D agree
+    with the GPU's to 1e-9 relative, and 50 oracle iterations from that state
+    (its own plain LU-SGS at a fixed CFL of 1e6) move them by less than 1e-9
+    relative: the state is a converged state of the oracle as well.  No GPU
+    state is stored; the mixed-precision loads are reported against FP64."""
+    m0 = mg.joukowski_hybrid(64, 16, 2e-4, 1.15, seed=11, target_cells=8000)
+    m, blk = mg.block_order(m0, 512, "coupled")
+    flow = (0.3, 4.0, 5e4, 3.0)
+    say("case converged SA Joukowski", m.n_cells, "cells,", int(blk.max()) + 1, "blocks")
+    loads = {}
+    for prec in (igks.IGKS_FP64, igks.IGKS_MIXED):
+        g = igks.Solver(m, precision=prec, cfl_init=10.0, chunk=200, sweep_blocks=blk)
+        g.set_freestream(*flow)
+        it = 0
+        while it < 60000:
+            g.iterate(1000)
+            it += 1000
+            if g.residual()["res_drop"] < 1e-11:
+                break
+        drop = g.residual()["res_drop"]
+        lg = g.wall_loads()
+        W = g.get_state()
+        del g
+        o = po.Oracle(m, threads=sens.host_threads(), cfl_init=1e6, cfl_mode=1)
+        o.set_freestream(*flow)
+        o.set_state(W)
+        lo = o.wall_loads()
+        o.iterate(50)
+        l50 = o.wall_loads()
+        rel = {k: abs(lg[k] - lo[k]) / abs(lo[k]) for k in ("cl", "cd")}
+        mv = {k: abs(l50[k] - lo[k]) / abs(lo[k]) for k in ("cl", "cd")}
+        say(f"[converged SA joukowski prec={prec}] {it} its drop={drop:.2e} cl={lg['cl']:.15e} cd={lg['cd']:.15e} "
+            f"gpu-vs-oracle cl {rel['cl']:.2e} cd {rel['cd']:.2e}; 50 oracle its move cl {mv['cl']:.2e} "
+            f"cd {mv['cd']:.2e} (oracle ||M_rho||_2 {o.residual()['res_l2']:.2e})")
+        loads[prec] = lg
+        assert drop < 1e-11
+        assert max(rel.values()) <= 1e-9
+        assert max(mv.values()) <= 1e-9
+    d = {k: abs(loads[igks.IGKS_MIXED][k] - loads[igks.IGKS_FP64][k]) / abs(loads[igks.IGKS_FP64][k])
+         for k in ("cl", "cd")}
+    say(f"[converged SA joukowski] mixed against FP64: cl {d['cl']:.2e} cd {d['cd']:.2e}")
+
+
 @pytest.mark.parametrize("sa", [False, True])
 def test_sweep_blocks_trajectory_parity(igks, sa):
     """Sweep blocks (the sweeps couple only cells of one block): the GPU's
