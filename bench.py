@@ -53,7 +53,7 @@ FP64_VALU_PEAK_TFS = 78.6   # MI355X FP64 vector: 256 CUs x 4 SIMDs x 16 lanes x
 # FP64 operations per face of the face flux, counted with rocprofv3 on the
 # one-lane kernel: FP64 VALU instructions per wave (2 x FMA + MUL + ADD +
 # TRANS), one face per lane.  The algorithmic figure for either flux kernel.
-FLUX_FLOP_PER_FACE = 3488.0
+FLUX_FLOP_PER_FACE = 3498.6   # profiles/flops_flux_jouk40k.json
 KSRC = os.path.join(ROOT, "paper_1709_00803_amd", "csrc", "igks_kernels.hip")
 
 
@@ -74,8 +74,10 @@ def kernel_bytes(n, f, e, sa, mixed):
     # lsinv, area; writes nu, lamc, vort, gradients
     b["prep"] = 5 * d * n + 2 * i4 * n + (2 * i4 + 2 * d) * e + 3 * d * f + 4 * d * n + (3 + 8) * d * n
     # fl, fr, finst; normal, length, face-centre offsets, distances; W and
-    # gradients of both sides; writes the face record: flux, lam (+ SA saf, sag, sak)
-    b["flux"] = (3 * i4 + 10 * d) * f + (5 + 8) * d * n + (4 + 1 + 3 * s) * d * f
+    # gradients of both sides; writes the 64-byte face record (flux, lam,
+    # SA saf, sag, sak; zeros for the SA terms when laminar) and the packed
+    # lam (+ SA sak) the sweeps read
+    b["flux"] = (3 * i4 + 10 * d) * f + (5 + 8) * d * n + (8 + 1 + s) * d * f
     # cinst, cf_ptr, ipos; cf_face/cf_flag; flux, lam, length (+ SA: saf, sag,
     # sak, normal); W (+ SA: nu, wall distance, vorticity, area); writes M,
     # lsum, r2 (+ SA diagonal)
@@ -95,17 +97,39 @@ def kernel_source_hash():
     return hashlib.sha256(open(KSRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(workload, cls):
-    """HBM bytes per launch of a kernel class from the committed counter
-    summary (profiles/traffic_<workload>.json), or None when the kernels
-    changed since the counters were taken."""
+def traffic_summary(workload):
+    """The committed counter summary (profiles/traffic_<workload>.json), or
+    None when it is missing or the kernels changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch", {}).get(cls)
+    return d
+
+
+def measured_traffic(workload, cls):
+    """HBM bytes per launch of a kernel class from the counter summary, or
+    None."""
+    d = traffic_summary(workload)
+    return None if d is None else d.get("bytes_per_launch", {}).get(cls)
+
+
+ITERATION_CLASSES = ("prep", "flux", "flux2", "gather", "reduce", "sweep_fwd", "sweep_top", "sweep_bwd", "update",
+                     "commit")
+
+
+def measured_iteration_bytes(workload):
+    """Counted bytes (FETCH_SIZE + WRITE_SIZE, copy-calibrated) of one whole
+    iteration: every kernel class of the iteration times its dispatches per
+    iteration (dispatches over those of k_prep, one per iteration), or None."""
+    d = traffic_summary(workload)
+    if d is None or not d.get("dispatches", {}).get("prep"):
+        return None
+    n = d["dispatches"]["prep"]
+    return sum(d["bytes_per_launch"][c] * d["dispatches"][c] / n for c in ITERATION_CLASSES
+               if c in d["bytes_per_launch"] and c in d["dispatches"])
 
 
 def load_meshes(mg, name, cache):
@@ -281,6 +305,12 @@ def roofline_of(args, solver, kt, kb, out, mixed):
     it_gbs = total / (out["ms_per_step"] * 1e-3) / 1e9
     r["iteration"] = dict(algorithmic_bytes=total, achieved_gbs=it_gbs, frac_of_hbm_peak=it_gbs / HBM_PEAK_GBS,
                           note="all kernel classes of one iteration: compulsory bytes over the timed ms per step")
+    counted = measured_iteration_bytes(args.workload)
+    if counted is not None:
+        c_gbs = counted / (out["ms_per_step"] * 1e-3) / 1e9
+        r["iteration"].update(counted_bytes=counted, counted_gbs=c_gbs, counted_frac_of_hbm_peak=c_gbs / HBM_PEAK_GBS,
+                              counted_note="FETCH_SIZE + WRITE_SIZE of every kernel of one iteration (L2 fills and "
+                                           "write-backs, some served by the Infinity Cache) over the timed ms per step")
     return r
 
 

@@ -40,7 +40,7 @@ constexpr int SLOT_STRIDE = 16;   // unsigned long longs from one slot to the ne
 enum { SL_DTMIN = 0, SL_RESINF = 1, SL_E40 = 2, NSL = 3 };   // Eq.23 minimum, max |M|, Eq.40 maximum
 constexpr int NORM_SLICE = 1024;   // squares per block of the residual-norm partial sums
 // face record layout (Params::frec)
-constexpr int FR_STRIDE = 8, FR_F = 0, FR_LAM = 4, FR_SAF = 5, FR_SAG = 6, FR_SAK = 7;
+constexpr int FR_STRIDE = 8, FR_F0 = 0, FR_F1 = 1, FR_LAM = 2, FR_SAF = 3, FR_F2 = 4, FR_F3 = 5, FR_SAG = 6, FR_SAK = 7;
 constexpr int NCLASS = 4;     // kernel classes with a tunable block size: prep, flux, gather, sweep
 
 // Free stream of one instance (read-only while iterating).
@@ -104,11 +104,16 @@ struct Params {
     const double *fnx, *fny, *flen, *frl, *frr, *fdl, *fdr, *frn;
     // nf x FR_STRIDE face records, one 64-byte record per face, so that a
     // cell reading a face's outputs through its entries touches one cache
-    // line: FR_F..FR_F+3 the time-averaged flux times length (global frame),
-    // FR_LAM the spectral radius, FR_SAF the SA (-F_inv + F_vis) S, FR_SAG
-    // (nu~_r - nu~_l)/|r.n| S, FR_SAK the SA diffusion coefficient of the
-    // face times S/|r.n|
+    // line: FR_F0, FR_F1, FR_F2, FR_F3 the time-averaged flux times length
+    // (global frame), FR_LAM the spectral radius, FR_SAF the SA
+    // (-F_inv + F_vis) S, FR_SAG (nu~_r - nu~_l)/|r.n| S, FR_SAK the SA
+    // diffusion coefficient of the face times S/|r.n|.  Each half of a record
+    // is written by one 16-byte store per pair of values.
     double *frec;
+    // the spectral radius and the SA diffusion coefficient again, packed
+    // one value per face: the sweeps read only these two, and a packed
+    // array puts sixteen faces in a cache line where the records put two
+    double *flam, *fsak;
     // per-instance cell lists (internal ids, ascending) for the norms
     const int *icell, *ioff;
     const int *ipos;           // position of each cell in icell

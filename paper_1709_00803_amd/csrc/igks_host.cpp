@@ -74,7 +74,7 @@ struct WsMap {
     Buf ip, is, slot, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx, phi;
     Buf cinst, finst, icell, ioff, g2i, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
     Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, ipart, hist, ipos;
-    Buf frec, enx, eny, es;
+    Buf frec, flam, fsak, enx, eny, es;
     Buf wall_faces, wall_out, woff, wseg, lev_off, bl_off, bl_lo, bl_hi, stage, backup;
     size_t total;
 };
@@ -603,7 +603,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.fl = L.add(F * I); w.fr = L.add(F * I); w.fbc = L.add(F * I);
     w.fnx = L.add(F * D); w.fny = L.add(F * D); w.flen = L.add(F * D); w.frl = L.add(2 * F * D);
     w.frr = L.add(2 * F * D); w.fdl = L.add(F * D); w.fdr = L.add(F * D); w.frn = L.add(F * D);
-    w.frec = L.add(FR_STRIDE * F * D);
+    w.frec = L.add(FR_STRIDE * F * D); w.flam = L.add(F * D); w.fsak = L.add(F * D);
     w.enx = L.add(E * D); w.eny = L.add(E * D); w.es = L.add(E * D);
     w.ipart = L.add(2 * NI * (size_t)norm_rb(G) * D);
     w.ipos = L.add(N * I);
@@ -650,7 +650,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.fl = In(w.fl); P.fr = In(w.fr); P.fbc = In(w.fbc);
     P.fnx = D(w.fnx); P.fny = D(w.fny); P.flen = D(w.flen); P.frl = D(w.frl); P.frr = D(w.frr);
     P.fdl = D(w.fdl); P.fdr = D(w.fdr); P.frn = D(w.frn);
-    P.frec = D(w.frec);
+    P.frec = D(w.frec); P.flam = D(w.flam); P.fsak = D(w.fsak);
     P.enx = D(w.enx); P.eny = D(w.eny); P.es = D(w.es);
     P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipos = In(w.ipos); P.ipart = D(w.ipart); P.rb = norm_rb(c->g);
     P.hist = D(w.hist); P.hist_cap = c->hist_cap;

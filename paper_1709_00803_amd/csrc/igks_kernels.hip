@@ -864,17 +864,26 @@ __device__ __forceinline__ FaceTerms face_implicit_terms(const Params<T> &P, con
     return o;
 }
 
-// The face terms into the face arrays, stored as soon as they are formed
-// so that they do not stay live across the flux.
+// Two values into a face record with one 16-byte store (k even).
+__device__ __forceinline__ void rec_store2(double *r, int k, double a, double b)
+{
+    *reinterpret_cast<double2 *>(r + k) = make_double2(a, b);
+}
+// The face terms into the face record and the packed arrays, stored as soon
+// as they are formed so that they do not stay live across the flux.  half
+// 0: lam and saf, half 1: sag and sak, -1: all four (the one-lane kernel).
 template <typename T>
-__device__ __forceinline__ void store_terms(const Params<T> &P, const InstParam &ip, int f, const FaceTerms &t)
+__device__ __forceinline__ void store_terms(const Params<T> &P, const InstParam &ip, int f, const FaceTerms &t,
+                                            int half)
 {
     double *r = P.frec + FR_STRIDE * (size_t)f;
-    r[FR_LAM] = t.lam;
-    if (ip.sa) {
-        r[FR_SAF] = t.saf;
-        r[FR_SAG] = t.sag;
-        r[FR_SAK] = t.sak;
+    if (half <= 0) {
+        rec_store2(r, FR_LAM, t.lam, t.saf);
+        P.flam[f] = t.lam;
+    }
+    if (half != 0) {
+        rec_store2(r, FR_SAG, t.sag, t.sak);
+        if (ip.sa) P.fsak[f] = t.sak;
     }
 }
 
@@ -898,7 +907,8 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, d
     FaceSide L, R;
     face_side(P, ip, W, f, 0, L);
     face_side(P, ip, W, f, 1, R);
-    store_terms(P, ip, f, face_implicit_terms(P, ip, f, L.ls, R.ls, L.evr, R.evr, L.nu, R.nu, L.nut, R.nut, L.q, R.q));
+    store_terms(P, ip, f, face_implicit_terms(P, ip, f, L.ls, R.ls, L.evr, R.evr, L.nu, R.nu, L.nut, R.nut, L.q, R.q),
+                -1);
     const double nutf = fmax(0.5 * add_sides(L.nut, R.nut), 0.0);
     double acc[24], accr[24];
     side_terms(1.0, L.fw, L.gn, L.gt, acc);
@@ -926,8 +936,9 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, d
     double Fr[4], g[4];
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
-#pragma unroll
-    for (int k = 0; k < 4; k++) P.frec[FR_STRIDE * (size_t)f + FR_F + k] = g[k];
+    double *r = P.frec + FR_STRIDE * (size_t)f;
+    rec_store2(r, FR_F0, g[0], g[1]);
+    rec_store2(r, FR_F2, g[2], g[3]);
 }
 
 // Per face, on a pair of lanes (side 0 the owner, side 1 the neighbour or
@@ -943,11 +954,16 @@ __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int si
     FaceSide M;
     face_side(P, ip, W, f, side, M);
     {
-        // the owner's lane forms and stores the face terms
+        // both lanes form the face terms (owner's values first) and each
+        // stores half of them
         const double ls_o = pair_other(M.ls), evr_o = pair_other(M.evr), nu_o = pair_other(M.nu);
         const double t_o = pair_other(M.nut), q_o = pair_other(M.q);
-        if (side == 0)
-            store_terms(P, ip, f, face_implicit_terms(P, ip, f, M.ls, ls_o, M.evr, evr_o, M.nu, nu_o, M.nut, t_o, M.q, q_o));
+        const double lsl = side ? ls_o : M.ls, lsr = side ? M.ls : ls_o;
+        const double evl = side ? evr_o : M.evr, evr = side ? M.evr : evr_o;
+        const double nul = side ? nu_o : M.nu, nur = side ? M.nu : nu_o;
+        const double til = side ? t_o : M.nut, tir = side ? M.nut : t_o;
+        const double ql = side ? q_o : M.q, qr = side ? M.q : q_o;
+        store_terms(P, ip, f, face_implicit_terms(P, ip, f, lsl, lsr, evl, evr, nul, nur, til, tir, ql, qr), side);
     }
     const double nutf = fmax(0.5 * add_sides(M.nut, pair_other(M.nut)), 0.0);
     const double sgn = side ? -1.0 : 1.0;
@@ -975,9 +991,8 @@ __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int si
     double Fr[4], g[4];
     gks_finish(q, acc, q2, f2, gts, dt, Fr);
     flux_global(Fr, dt, P.fnx[f], P.fny[f], P.flen[f], g);
-    // each lane writes two of the four components
-    P.frec[FR_STRIDE * (size_t)f + FR_F + 2 * side] = side ? g[2] : g[0];
-    P.frec[FR_STRIDE * (size_t)f + FR_F + 2 * side + 1] = side ? g[3] : g[1];
+    // each lane writes two of the four components, one 16-byte store
+    rec_store2(P.frec + FR_STRIDE * (size_t)f, side ? FR_F2 : FR_F0, side ? g[2] : g[0], side ? g[3] : g[1]);
 }
 
 // one lane per face
@@ -1053,9 +1068,7 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
             const int e = MAXV * b + k, f = E.face[k];
             double sg = (E.flag[k] & CF_OWNER) ? 1.0 : -1.0;
             const double *r = P.frec + FR_STRIDE * (size_t)f;
-            double g[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) g[k] = r[FR_F + k];
+            double g[4] = {r[FR_F0], r[FR_F1], r[FR_F2], r[FR_F3]};
             if (E.nbr[k] < 0) wall_face_terms(P, ip, w, f, g);
 #pragma unroll
             for (int k = 0; k < 4; k++) m[k] -= sg * g[k];
@@ -1255,7 +1268,7 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
 {
     const int N = P.nc;
     double nx = P.enx[e], ny = P.eny[e];   // out of the cell
-    T S = T(P.es[e]), lam = T(P.frec[FR_STRIDE * (size_t)f + FR_LAM]);
+    T S = T(P.es[e]), lam = T(P.flam[f]);
     double wj[5];
     T dj[5];
     if (j >= 0) {
@@ -1280,7 +1293,7 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
     t[4] = T(0);
     if (ip.sa) {
         double qj = (wj[1] * nx + wj[2] * ny) / wj[0];
-        double off = -0.5 * (qj - fabs(qj)) * P.es[e] + P.frec[FR_STRIDE * (size_t)f + FR_SAK];
+        double off = -0.5 * (qj - fabs(qj)) * P.es[e] + P.fsak[f];
         t[4] = T(off) * dj[4];
     }
 }
@@ -1659,8 +1672,11 @@ __global__ void k_gather_faces(int n, const int *faces, const double *frec, int 
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int f = faces[i];
-#pragma unroll
-    for (int k = 0; k < 4; k++) out[4 * i + k] = frec[FR_STRIDE * (size_t)f + FR_F + k];
+    const double *r = frec + FR_STRIDE * (size_t)f;
+    out[4 * i] = r[FR_F0];
+    out[4 * i + 1] = r[FR_F1];
+    out[4 * i + 2] = r[FR_F2];
+    out[4 * i + 3] = r[FR_F3];
 }
 
 __global__ void k_fill_instance(int n, const int *cells, int nc, double w0, double w1, double w2, double w3,
