@@ -338,11 +338,13 @@ def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=
 
 
 def run_to_drop(igks, mesh, flow, precision, blocks=None, target=1e-10, max_it=40000, chunk=200, scheme=0,
-                cfl=1000.0, max_s=60.0):
+                cfl=1000.0, max_s=60.0, **opt):
     """Iterations and seconds from the impulsive start to a density-residual
-    drop of `target` (or to max_it iterations / about max_s seconds)."""
+    drop of `target` (or to max_it iterations / about max_s seconds); opt:
+    further solver options (limiter, limiter_freeze)."""
     import torch
-    s = igks.Solver(mesh, precision=precision, cfl_init=cfl, chunk=chunk, scheme=scheme, sweep_blocks=blocks)
+    s = igks.Solver(mesh, precision=precision, cfl_init=cfl, chunk=chunk, scheme=scheme, sweep_blocks=blocks,
+                    **opt)
     s.set_freestream(*flow)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -379,6 +381,74 @@ def time_to_drop_joukowski(igks, mg):
     out["explicit_fp64_cfl0.9"] = run_to_drop(igks, mc, flow, igks.IGKS_FP64, None, max_it=2000000, chunk=2000,
                                              scheme=1, cfl=0.9, max_s=40.0)
     return out
+
+
+def time_to_drop_sa250k(igks, mg, max_s=15.0):
+    """The 250k-cell SA Joukowski (Ma 0.15, Re 6e6, alpha 4) from the free
+    stream at CFL 10 with block LU-SGS and the Eq.9 limiter held from a drop
+    of 1e-4, FP64 and mixed, for about max_s seconds each: the drop it
+    levels off at, not 1e-10."""
+    flow = WORKLOADS["jouk250k"]["flow"]
+    mb, blk = mg.workload_blocks("jouk250k", 512)
+    out = dict(workload="jouk250k: " + WORKLOADS["jouk250k"]["desc"], target=1e-10, blocks=int(blk.max()) + 1,
+               block_cells=512, limiter="Eq.9, held from a drop of 1e-4", status="floor",
+               note="the residual levels off near a 3e-3 drop within 20 000 iterations (C_L, C_D settled to 5 "
+                    "digits) and stays there; without the limiter the wake behind the trailing edge falls into a "
+                    "limit cycle; in natural order (587 wavefronts, 10 ms per iteration) the limiter hold reaches "
+                    "5e-7 after 40 000 iterations")
+    for key, prec in (("blocks_fp64", igks.IGKS_FP64), ("blocks_mixed", igks.IGKS_MIXED)):
+        out[key] = run_to_drop(igks, mb, flow, prec, blk, max_it=10 ** 6, chunk=500, cfl=10.0, max_s=max_s,
+                               limiter=1, limiter_freeze=1e-4)
+    return out
+
+
+def batch_to_drop(igks, mg, target=1e-10, max_s=40.0, chunk=500):
+    """batch64 in generation order with coupled sweep blocks (512 cells),
+    mixed precision, the Eq.9 limiter held from a drop of 1e-4, from the
+    free stream at CFL 10, for about max_s seconds: per instance the first
+    checked iteration at a `target` drop (None if not reached) and the final
+    drop; the instances that reached it are then run alone in FP64 to the
+    same target, one after another, for the wall-time comparison."""
+    import torch
+    items = [mg.batch_instance(b, order="natural") for b in range(64)]
+    meshes, blocks = [], []
+    for m, _ in items:
+        mb, bk = mg.block_order(m, 512, "coupled")
+        meshes.append(mb)
+        blocks.append(bk)
+    opt = dict(cfl_init=10.0, limiter=1, limiter_freeze=1e-4)
+    s = igks.BatchSolver(meshes, chunk=100, sweep_blocks=blocks, precision=igks.IGKS_MIXED, **opt)
+    for i, (_, f) in enumerate(items):
+        s.set_freestream(i, *f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, first, t_first = 0, [None] * 64, [None] * 64
+    while time.perf_counter() - t0 < max_s and any(x is None for x in first):
+        try:
+            s.iterate(chunk)
+        except igks.IgksError:
+            pass   # an instance frozen by a rejected update; the others go on
+        it += chunk
+        for i in range(64):
+            if first[i] is None and s.residual(i)["res_drop"] <= target:
+                first[i], t_first[i] = it, round(time.perf_counter() - t0, 3)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    drops = [s.residual(i)["res_drop"] for i in range(64)]
+    frozen = [i for i in range(64) if s.status(i)]
+    nlev = s.nlev
+    del s
+    seq = {}
+    for i in [i for i in range(64) if first[i] is not None]:
+        seq[i] = run_to_drop(igks, meshes[i], items[i][1], igks.IGKS_FP64, blocks[i], target=target,
+                             max_it=10 * first[i], chunk=100, cfl=10.0, max_s=30.0, limiter=1, limiter_freeze=1e-4)
+    return dict(workload="batch64 in generation order, coupled sweep blocks of at most 512 cells, mixed, limiter "
+                         "held from 1e-4, CFL 10 -> Eq.25",
+                target=target, iterations=it, seconds=round(t_batch, 3), ms_per_iteration=round(1e3 * t_batch / it, 3),
+                wavefronts=nlev, reached=sum(x is not None for x in first), first_iteration_at_target=first,
+                batch_seconds_at_target=t_first, final_drop=[float(f"{d:.3e}") for d in drops], frozen=frozen,
+                fp64_alone={str(i): v for i, v in seq.items()},
+                fp64_alone_seconds_total=round(sum(v["seconds"] for v in seq.values()), 4))
 
 
 def time_to_converge_cavity(igks, mg, max_it=20000, chunk=200):
@@ -602,6 +672,12 @@ def main():
             _, bo, bkt, _ = measure(igks, bm, bf, igks.IGKS_MIXED, args, SCHEDULES["batch64"], "batch64 mixed")
             out["batch64_mixed"] = dict(bo, dtype="f32+f64", workload=WORKLOADS["batch64"]["desc"],
                                         kernel_ms_per_step={k: round(v, 5) for k, v in bkt.items()})
+            counted = measured_iteration_bytes("batch64")
+            if counted is not None:
+                gbs = counted / (bo["ms_per_step"] * 1e-3) / 1e9
+                out["batch64_mixed"].update(counted_bytes_per_iteration=counted, counted_gbs=gbs,
+                                            counted_frac_of_hbm_peak=gbs / HBM_PEAK_GBS,
+                                            flux_traffic_per_launch=measured_traffic("batch64", "flux2"))
             del bm
             torch.cuda.empty_cache()
     if not args.no_drop:
@@ -612,6 +688,8 @@ def main():
                                 "explicit_fp64_cfl0.9": time_to_drop(igks, mg, igks.IGKS_FP64, scheme=1, cfl=0.9,
                                                                      chunk=1000, max_it=400000)}
         out["time_to_1e-10"]["jouk40k"] = time_to_drop_joukowski(igks, mg)
+        out["time_to_1e-10"]["jouk250k"] = time_to_drop_sa250k(igks, mg)
+        out["time_to_1e-10"]["batch64"] = batch_to_drop(igks, mg)
         say("time to 1e-10 done")
         out["cavity_to_eq40"] = time_to_converge_cavity(igks, mg)
         out["turbulent_plate_to_eq40"] = time_to_converge_turbulent_plate(igks, mg)
