@@ -525,6 +525,62 @@ def test_sweep_schedules_match(igks):
     assert np.array_equal(out[0], out[1])
 
 
+def test_sweep_schedules_full_size(igks):
+    """The 41k-cell Joukowski mesh in generation order (its many wavefronts
+    in full): one launch per wavefront and one workgroup for all of them give
+    bitwise the same iterates, and both follow the oracle for 4 iterations
+    (1e-9 of each component's scale)."""
+    m = mg.workload("jouk40k", order="natural")
+    flow = (0.5, 2.0, 5000.0, -1.0)
+    say("case jouk40k natural", m.n_cells, "cells")
+    o = po.Oracle(m, threads=sens.host_threads(), cfl_init=1000.0)
+    o.set_freestream(*flow)
+    o.iterate(4)
+    Wo = o.get_state()
+    out = []
+    for sweep in (1, 2):
+        g = igks.Solver(m, cfl_init=1000.0, chunk=4, sweep=sweep)
+        assert g.schedule()[4] == sweep
+        g.set_freestream(*flow)
+        g.iterate(4)
+        out.append(g.get_state())
+    err = (np.abs(out[0][:4] - Wo[:4]) / np.abs(Wo[:4]).max(axis=1, keepdims=True)).max()
+    say(f"[jouk40k natural] wavefronts {g.nlev}; 4 iterations: state err {err:.3e}")
+    assert g.nlev > 100
+    assert np.array_equal(out[0], out[1])
+    assert err <= 1e-9
+
+
+def test_sweep_blocks_full_size(igks):
+    """The 250k-cell SA Joukowski mesh with coupled sweep blocks of at most
+    512 cells (one wave per block): 3 iterations from the free stream in
+    FP64 against the oracle with the same blocks (1e-9 of each component's
+    scale, C_L to 1e-9), and the one-workgroup and per-wavefront schedules
+    give bitwise the same iterates as the wave-per-block one."""
+    m, blk = mg.workload_blocks("jouk250k", 512)
+    flow = (0.15, 4.0, 6e6, 3.0)
+    say("case jouk250k blocks", m.n_cells, "cells,", int(blk.max()) + 1, "blocks")
+    o = po.Oracle(m, threads=sens.host_threads(), cfl_init=10.0)
+    o.set_sweep_blocks(blk)
+    o.set_freestream(*flow)
+    o.iterate(3)
+    Wo, lo = o.get_state(), o.wall_loads()
+    out = []
+    for sweep in (3, 1):
+        g = igks.Solver(m, cfl_init=10.0, chunk=3, sweep=sweep, sweep_blocks=blk)
+        assert g.schedule()[4] == sweep
+        g.set_freestream(*flow)
+        g.iterate(3)
+        out.append((g.get_state(), g.wall_loads()))
+        del g
+    Wg, lg = out[0]
+    err = (np.abs(Wg - Wo) / np.abs(Wo).max(axis=1, keepdims=True)).max()
+    say(f"[jouk250k blocks] 3 iterations: state err {err:.3e}, cl {lg['cl']:.12e} vs {lo['cl']:.12e}")
+    assert np.array_equal(out[0][0], out[1][0])
+    assert err <= 1e-9
+    assert abs(lg["cl"] - lo["cl"]) <= 1e-9 * abs(lo["cl"]) + 1e-12
+
+
 @pytest.mark.parametrize("workload", ["random", "jouk40k"])
 def test_flux_lane_counts_match(igks, workload):
     """The flux on one lane per face and on two lanes per face agree to
