@@ -100,6 +100,14 @@ typedef struct igks_options {
     int tau_jump;       /* 1: add dt |p_l - p_r| / (p_l + p_r) (reconstructed face pressures) to the
                            collision time of Eq.34, the usual gas-kinetic extra dissipation at
                            discontinuities (not in the paper); 0 (default): Eq.34 as printed */
+    int block_passes;   /* with sweep blocks (igks_set_sweep_blocks): 1 (default; 0 means 1) one
+                           block LU-SGS pass, the coupling across blocks left out of L and U;
+                           2: a second pass solves the same block system again with the cross-block
+                           terms of the first pass's increments moved to its right-hand side (one
+                           block-Jacobi correction of the coupling the blocks leave out; not in the
+                           paper).  Two passes run on the wave-per-block schedule (sweep 0 or 3;
+                           1 or 2 with block_passes 2 is IGKS_EINVAL) and take a second increment
+                           array in the workspace. */
 } igks_options;
 
 typedef struct igks_residual {
@@ -318,7 +326,9 @@ int igks_get_schedule(const igks_ctx *ctx, int32_t *schedule6);
  * 256 for the four classes, sweep 1, 2 or 3, lanes per face 1 or 2.  Needs a
  * bound workspace (binding picks the automatic schedule again).  Block
  * sizes and the sweep schedule never change results; the two flux kernels
- * agree to rounding.  IGKS_EINVAL for a value outside those sets. */
+ * agree to rounding.  IGKS_EINVAL for a value outside those sets, and for a
+ * sweep schedule other than 3 in a context with two block passes and sweep
+ * blocks. */
 int igks_set_schedule(igks_ctx *ctx, const int32_t *schedule6);
 
 /* Iterations per captured HIP graph and kernel launches per iteration of the

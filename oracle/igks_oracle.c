@@ -92,6 +92,8 @@ typedef struct oigks_ctx {
     double *area, *xc, *yc, *dwall;
     int *cfp, *cff;              /* cell -> face lists */
     int *sblk;                   /* sweep block of each cell (NULL: the whole mesh is one block) */
+    int block_passes;            /* 1, or 2: a second block pass with the cross-block terms of the first */
+    double *dW1;                 /* the first pass's increments (two passes) */
     int nwall;                   /* number of WALL faces */
     /* flow parameters */
     int have_flow, sa;
@@ -489,6 +491,8 @@ static void free_mesh(oigks_ctx *c)
     for (size_t i = 0; i < sizeof ps / sizeof ps[0]; i++) free(ps[i]);
     free(c->sblk);
     c->sblk = NULL;
+    free(c->dW1);
+    c->dW1 = NULL;
     c->x = c->y = NULL; c->cptr = c->cnod = NULL; c->fa = c->fb = NULL; c->fL = c->fR = c->ftag = c->fbc = c->fbidx = c->wall_faces = NULL;
     c->fnx = c->fny = c->flen = c->fxm = c->fym = NULL; c->area = c->xc = c->yc = c->dwall = NULL;
     c->cfp = c->cff = NULL; c->W = c->M = c->gx = c->gy = c->ugx = c->ugy = NULL;
@@ -1164,33 +1168,14 @@ static double face_rn(const oigks_ctx *c, int f)
 /* Eq.19-22 matrix-free LU-SGS: forward sweep in increasing cell index,
  * backward sweep in decreasing index.  Boundary ghost increments (Sec. 2.5)
  * enter the backward sweep from the forward-sweep increment of the owner. */
-static void lusgs(oigks_ctx *c)
+/* One forward and backward sweep of Eq.22 (and Eq.31-32) over the cells in
+ * index order, with the D of lusgs().  dWx (NULL: none): the increments of a
+ * first block pass, whose cross-block terms then join the forward
+ * right-hand side. */
+static void lusgs_pass(oigks_ctx *c, const double *dWx)
 {
     int nc = c->nc;
     double *W = c->W, *dW = c->dW;
-#pragma omp parallel for num_threads(c->threads) schedule(static)
-    for (int i = 0; i < nc; i++) {
-        c->dtimp[i] = c->cfl * c->area[i] / c->lamc[i];             /* Eq.24 */
-        double s = 0.0;
-        for (int q = c->cfp[i]; q < c->cfp[i + 1]; q++) { int f = c->cff[q]; s += c->flam[f] * c->flen[f]; }
-        c->D[i] = c->area[i] / c->dtimp[i] + 0.5 * s;                  /* Eq.20 */
-        if (c->sa) {
-            double ds = 0.0;
-            for (int q = c->cfp[i]; q < c->cfp[i + 1]; q++) {
-                int f = c->cff[q];
-                int other = c->fR[f] < 0 ? -1 : (c->fL[f] == i ? c->fR[f] : c->fL[f]);
-                double sg = c->fL[f] == i ? 1.0 : -1.0;
-                const double *Wj = other >= 0 ? &W[5 * other] : &c->Wg[5 * f];
-                double dg, of;
-                sa_face_coef(c, &W[5 * i], Wj, sg * c->fnx[f], sg * c->fny[f], c->flen[f], face_rn(c, f), &dg, &of);
-                ds += dg;
-            }
-            double nu = mu_lam(c, lam_of(&W[5 * i])) / W[5 * i];
-            double so[4];
-            sa_source(W[5 * i + 4], nu, c->dwall[i], c->vort[i], so);
-            c->Dsa[i] = c->area[i] / c->dtimp[i] + ds + c->area[i] * so[3];
-        }
-    }
     /* forward: dW*_i = D^-1 [M_i - sum_{j<i} (J(W_j, n_ij) dW*_j - lam_ij dW*_j) S_ij / 2] */
     for (int i = 0; i < nc; i++) {
         double acc[5] = {c->M[5 * i], c->M[5 * i + 1], c->M[5 * i + 2], c->M[5 * i + 3], c->M[5 * i + 4]};
@@ -1198,17 +1183,21 @@ static void lusgs(oigks_ctx *c)
             int f = c->cff[q];
             if (c->fR[f] < 0) continue;
             int j = c->fL[f] == i ? c->fR[f] : c->fL[f];
-            if (j >= i) continue;
-            if (c->sblk && c->sblk[j] != c->sblk[i]) continue;   /* another sweep block */
+            /* a neighbour in another sweep block: left out, or on a second pass
+             * taken with the first pass's increment, whether below or above */
+            const int cross = c->sblk && c->sblk[j] != c->sblk[i];
+            if (cross && !dWx) continue;
+            if (!cross && j >= i) continue;
+            const double *dj = cross ? &dWx[5 * j] : &dW[5 * j];
             double sg = c->fL[f] == i ? 1.0 : -1.0;
             double nx = sg * c->fnx[f], ny = sg * c->fny[f], S = c->flen[f];
             double jv[4];
-            jac_vec(&W[5 * j], nx, ny, &dW[5 * j], jv);
-            for (int k = 0; k < 4; k++) acc[k] -= 0.5 * (jv[k] - c->flam[f] * dW[5 * j + k]) * S;
+            jac_vec(&W[5 * j], nx, ny, dj, jv);
+            for (int k = 0; k < 4; k++) acc[k] -= 0.5 * (jv[k] - c->flam[f] * dj[k]) * S;
             if (c->sa) {
                 double dg, of;
                 sa_face_coef(c, &W[5 * i], &W[5 * j], nx, ny, S, face_rn(c, f), &dg, &of);
-                acc[4] += of * dW[5 * j + 4];
+                acc[4] += of * dj[4];
             }
         }
         for (int k = 0; k < 4; k++) dW[5 * i + k] = acc[k] / c->D[i];
@@ -1245,6 +1234,48 @@ static void lusgs(oigks_ctx *c)
         }
         for (int k = 0; k < 4; k++) dW[5 * i + k] = dWs[k] - acc[k] / c->D[i];
         dW[5 * i + 4] = c->sa ? dWs[4] + acc[4] / c->Dsa[i] : 0.0;
+    }
+}
+
+static void lusgs(oigks_ctx *c)
+{
+    int nc = c->nc;
+    double *W = c->W, *dW = c->dW;
+#pragma omp parallel for num_threads(c->threads) schedule(static)
+    for (int i = 0; i < nc; i++) {
+        c->dtimp[i] = c->cfl * c->area[i] / c->lamc[i];             /* Eq.24 */
+        double s = 0.0;
+        for (int q = c->cfp[i]; q < c->cfp[i + 1]; q++) { int f = c->cff[q]; s += c->flam[f] * c->flen[f]; }
+        c->D[i] = c->area[i] / c->dtimp[i] + 0.5 * s;                  /* Eq.20 */
+        if (c->sa) {
+            double ds = 0.0;
+            for (int q = c->cfp[i]; q < c->cfp[i + 1]; q++) {
+                int f = c->cff[q];
+                int other = c->fR[f] < 0 ? -1 : (c->fL[f] == i ? c->fR[f] : c->fL[f]);
+                double sg = c->fL[f] == i ? 1.0 : -1.0;
+                const double *Wj = other >= 0 ? &W[5 * other] : &c->Wg[5 * f];
+                double dg, of;
+                sa_face_coef(c, &W[5 * i], Wj, sg * c->fnx[f], sg * c->fny[f], c->flen[f], face_rn(c, f), &dg, &of);
+                ds += dg;
+            }
+            double nu = mu_lam(c, lam_of(&W[5 * i])) / W[5 * i];
+            double so[4];
+            sa_source(W[5 * i + 4], nu, c->dwall[i], c->vort[i], so);
+            c->Dsa[i] = c->area[i] / c->dtimp[i] + ds + c->area[i] * so[3];
+        }
+    }
+    /* block LU-SGS (sweep blocks): with two passes the second solves the
+     * block-factored system again with the right-hand side
+     * M - (L_o + U_o) dW1, L_o and U_o the cross-block terms and dW1 the first
+     * pass's result: one block-Jacobi correction of the coupling the blocks
+     * leave out */
+    if (c->sblk && c->block_passes == 2) {
+        if (!c->dW1) c->dW1 = malloc(sizeof(double) * 5 * nc);
+        lusgs_pass(c, NULL);
+        memcpy(c->dW1, c->dW, sizeof(double) * 5 * nc);
+        lusgs_pass(c, c->dW1);
+    } else {
+        lusgs_pass(c, NULL);
     }
 }
 
@@ -1340,6 +1371,14 @@ EXPORT int oigks_iterate(oigks_ctx *c, int n, int *n_done)
  * leave the neighbours in other blocks out of the lower and upper parts
  * (their increments taken as zero); the diagonal keeps every face.  NULL:
  * one block, the plain sweeps. */
+/* passes of the block sweeps: 1, or 2 (see lusgs) */
+EXPORT int oigks_set_block_passes(oigks_ctx *c, int n)
+{
+    if (n != 1 && n != 2) { seterr(c, "block passes must be 1 or 2"); return -1; }
+    c->block_passes = n;
+    return 0;
+}
+
 EXPORT int oigks_set_sweep_blocks(oigks_ctx *c, const int *blk)
 {
     if (!c->cptr) { seterr(c, "no mesh"); return -1; }

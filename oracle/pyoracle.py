@@ -74,6 +74,7 @@ def lib():
         L.oigks_set_threads.argtypes = [p, i]
         L.oigks_sa_gross.argtypes = [p, dp]
         L.oigks_set_sweep_blocks.argtypes = [p, C.POINTER(C.c_int)]
+        L.oigks_set_block_passes.argtypes = [p, i]
         _lib = L
     return _lib
 
@@ -178,6 +179,11 @@ class Oracle:
             return
         b, p = _i(np.asarray(blk).reshape(self.n))
         self._chk(self.L.oigks_set_sweep_blocks(self.ctx, p))
+
+    def set_block_passes(self, n):
+        """Passes of the block sweeps: 1, or 2 (the second with the first's
+        cross-block terms on its right-hand side)."""
+        self._chk(self.L.oigks_set_block_passes(self.ctx, int(n)))
 
     def sa_gross(self):
         """Per cell, the gross size of the SA right-hand side (sum of the

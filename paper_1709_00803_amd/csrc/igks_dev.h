@@ -88,6 +88,8 @@ struct Params {
     double *sadiag;            // SA diagonal without Omega/dt
     double *r2;                // squares for the norms, M_rho^2 then R_SA^2, at the cell's ipos
     T *dW;                     // LU-SGS increment, 5 x nc
+    const T *dWx;              // a first block pass's increments, whose cross-block terms the
+                               // forward sweep takes (two block passes); null otherwise
     const double *xc, *yc, *area, *lsinv, *dwall;
     const double *vtx;         // vertex offsets from the centroid: (x, y) of slot v of block b at (2v) nb + b
     int nb;                    // entry / vertex blocks: nc + overflow blocks
@@ -145,10 +147,11 @@ template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd);
 // the whole sweep, one wave per sweep block (ngb blocks; block gb's k-th
 // wavefront = cells [bl_lo[bl_off[gb] + k], bl_hi[bl_off[gb] + k])); the
-// backward sweep is followed by the update of every cell
+// backward sweep is followed by the update of every cell unless `update` is
+// false (the first of two block passes)
 template <typename T>
 void launch_sweep_blk(const Launch &L, const Params<T> &P, const int *bl_off, const int *bl_lo, const int *bl_hi,
-                      int ngb, bool fwd);
+                      int ngb, bool fwd, bool update = true);
 template <typename T> void launch_commit(const Launch &L, const Params<T> &P, int it);
 // explicit step (Eq.15, local time steps) in place of the sweeps
 template <typename T> void launch_explicit(const Launch &L, const Params<T> &P);

@@ -71,7 +71,7 @@ struct Buf {
 constexpr int NKT = 6;
 
 struct WsMap {
-    Buf ip, is, slot, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, xc, yc, area, lsinv, dwall, vtx, phi;
+    Buf ip, is, slot, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, dW1, xc, yc, area, lsinv, dwall, vtx, phi;
     Buf cinst, finst, icell, ioff, g2i, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
     Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, ipart, hist, ipos;
     Buf frec, flam, fsak, enx, eny, es;
@@ -158,13 +158,15 @@ void destroy_graph(igks_ctx *c)
 // direction makes an iteration of a many-wavefront batch thousands of
 // launches long); 0 = no graphs.
 constexpr int MAX_GRAPH_NODES = 8192;
+bool two_block_passes(const igks_ctx *c);
 int launches_per_iteration(const igks_ctx *c, int sweep_mode)
 {
     const int nlev = std::max(1, c->g.nlev);
     // per-wavefront sweeps: forward steps of wavefronts 1 .. nlev-2, the last
     // wavefront's two steps, backward steps of nlev-2 .. 0; the other
     // schedules: forward, backward, update
-    const int sweeps = c->opt.scheme == 1 ? 1 : (sweep_mode >= 2 ? 3 : std::max(1, 2 * nlev - 2));
+    int sweeps = c->opt.scheme == 1 ? 1 : (sweep_mode >= 2 ? 3 : std::max(1, 2 * nlev - 2));
+    if (c->opt.scheme != 1 && sweep_mode == 3 && two_block_passes(c)) sweeps += 2;   // the first pass
     return 5 + sweeps;   // prep, flux, gather, reduce, commit + the update / sweep launches
 }
 int graph_chunk_for(const igks_ctx *c, int sweep_mode)
@@ -190,6 +192,8 @@ bool any_sweep_blocks(const igks_ctx *c)
         if (!m.sblk.empty()) return true;
     return false;
 }
+// two block passes (option block_passes = 2 and some instance has blocks)
+bool two_block_passes(const igks_ctx *c) { return c->opt.block_passes == 2 && any_sweep_blocks(c); }
 int auto_sweep_mode(const igks_ctx *c)
 {
     if (c->opt.sweep > 0) return c->opt.sweep;
@@ -594,6 +598,8 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.phi = L.add(4 * N * D);
     w.M = L.add(5 * N * D); w.lsum = L.add(N * D); w.sadiag = L.add(N * D); w.r2 = L.add(2 * N * D);
     w.dW = L.add(5 * N * (o.precision == IGKS_MIXED ? sizeof(float) : D));
+    // the first pass's increments (two block passes)
+    w.dW1 = L.add(o.block_passes == 2 ? 5 * N * (o.precision == IGKS_MIXED ? sizeof(float) : D) : 0);
     w.xc = L.add(N * D); w.yc = L.add(N * D); w.area = L.add(N * D); w.lsinv = L.add(3 * N * D);
     w.dwall = L.add(N * D); w.vtx = L.add(2 * MAXV * (size_t)G.NB * D);
     w.cinst = L.add(N * I); w.finst = L.add(F * I); w.icell = L.add(N * I); w.ioff = L.add((NI + 1) * I);
@@ -643,6 +649,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.slot = (unsigned long long *)(b + w.slot.off);
     P.Wa = D(w.Wa); P.Wb = D(w.Wb); P.grad = D(w.grad); P.lamc = D(w.lamc); P.vort = D(w.vort); P.nu = D(w.nu);
     P.M = D(w.M); P.lsum = D(w.lsum); P.sadiag = D(w.sadiag); P.r2 = D(w.r2); P.dW = (T *)(b + w.dW.off);
+    P.dWx = nullptr;
     P.xc = D(w.xc); P.yc = D(w.yc); P.area = D(w.area); P.lsinv = D(w.lsinv); P.dwall = D(w.dwall); P.vtx = D(w.vtx);
     P.nb = c->g.NB;
     P.cf_face = In(w.cf_face); P.cf_nbr = In(w.cf_nbr); P.cf_flag = In(w.cf_flag);
@@ -694,7 +701,19 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev, int it)
     const int *blo = (const int *)(c->ws + c->w.bl_off.off), *bll = (const int *)(c->ws + c->w.bl_lo.off),
               *blh = (const int *)(c->ws + c->w.bl_hi.off);
     const int ngb = (int)G.bl_off.size() - 1;
-    if (c->sweep_mode == 3) launch_sweep_blk(L, P, blo, bll, blh, ngb, true);
+    if (c->sweep_mode == 3 && two_block_passes(c)) {
+        // a first block pass into the second increment array, then the
+        // second pass with its cross-block terms (the forward class holds
+        // the first pass and the second forward sweep)
+        Params<T> P1 = P;
+        P1.dW = (T *)(c->ws + c->w.dW1.off);
+        P1.dWx = nullptr;
+        launch_sweep_blk(L, P1, blo, bll, blh, ngb, true);
+        launch_sweep_blk(L, P1, blo, bll, blh, ngb, false, false);
+        Params<T> P2 = P;
+        P2.dWx = P1.dW;
+        launch_sweep_blk(L, P2, blo, bll, blh, ngb, true);
+    } else if (c->sweep_mode == 3) launch_sweep_blk(L, P, blo, bll, blh, ngb, true);
     else if (c->sweep_mode == 2) launch_sweep_wg(L, P, lev, G.nlev, true);
     else
         // forward over the wavefronts after the first (whose forward
@@ -987,6 +1006,7 @@ void igks_default_options(igks_options *o)
     o->wall_temp = 0.0;
     o->limiter_freeze = 0.0;
     o->tau_jump = 0;
+    o->block_passes = 1;
 }
 
 int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream, int32_t n_inst)
@@ -1006,6 +1026,9 @@ int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream,
     if (!(c->opt.wall_temp >= 0.0) || !std::isfinite(c->opt.wall_temp)) { delete c; return IGKS_EINVAL; }
     if (!(c->opt.limiter_freeze >= 0.0) || !(c->opt.limiter_freeze < 1.0)) { delete c; return IGKS_EINVAL; }
     if (c->opt.tau_jump < 0 || c->opt.tau_jump > 1) { delete c; return IGKS_EINVAL; }
+    if (c->opt.block_passes == 0) c->opt.block_passes = 1;
+    if (c->opt.block_passes < 1 || c->opt.block_passes > 2) { delete c; return IGKS_EINVAL; }
+    if (c->opt.block_passes == 2 && c->opt.sweep != 0 && c->opt.sweep != 3) { delete c; return IGKS_EINVAL; }
     for (int k = 0; k < NCLASS; k++) c->block[k] = c->opt.block;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
@@ -1488,6 +1511,8 @@ int igks_set_schedule(igks_ctx *c, const int32_t *s6)
             return fail(c, IGKS_EINVAL, "block sizes must be 64, 128 or 256");
     if (s6[NCLASS] < 1 || s6[NCLASS] > 3 || (s6[NCLASS + 1] != 1 && s6[NCLASS + 1] != 2))
         return fail(c, IGKS_EINVAL, "the sweep schedule must be 1, 2 or 3 and the lanes per face 1 or 2");
+    if (two_block_passes(c) && s6[NCLASS] != 3)
+        return fail(c, IGKS_EINVAL, "two block passes run on the wave-per-block sweep schedule (3)");
     destroy_graph(c);
     for (int k = 0; k < NCLASS; k++) c->block[k] = s6[k];
     c->sweep_mode = s6[NCLASS];
@@ -1553,9 +1578,9 @@ int igks_autotune(igks_ctx *c, int32_t iters, int32_t *s6)
     // sweeps: one launch per wavefront (timed above), one workgroup (a
     // candidate only while wavefronts are narrow), a wave per sweep block
     // (with sweep blocks)
-    int best_mode = 1;
+    int best_mode = two_block_passes(c) ? 3 : 1;   // two passes run on the wave-per-block schedule only
     double best_sweep = best_t[3];
-    for (int mode = 2; mode <= 3 && !rc; mode++) {
+    for (int mode = 2; mode <= 3 && !rc && !two_block_passes(c); mode++) {
         if (mode == 2 && !((double)c->g.N / std::max(1, c->g.nlev) < 16384.0)) continue;
         if (mode == 3 && !any_sweep_blocks(c)) continue;
         c->sweep_mode = mode;

@@ -1257,14 +1257,14 @@ __device__ __forceinline__ void first_front_incr(const Params<T> &P, const InstP
 
 // Neighbour term of one cell-face entry in the LU-SGS sweeps (Eq.22 and
 // Eq.31-32): t[0..3] = (J(W_j, n) dW_j - lam dW_j) S / 2 with n pointing out
-// of the cell, t[4] = the SA off-diagonal coefficient times dnu~_j.  j < 0:
-// the ghost cell, whose increment follows from the cell's own dW* (Sec. 2.5).
-// Neighbours j < lev1 belong to the first wavefront, whose forward
-// increments are not stored (first_front_incr).
+// of the cell, t[4] = the SA off-diagonal coefficient times dnu~_j, dW_j read
+// from dsrc.  j < 0: the ghost cell, whose increment follows from the cell's
+// own dW* (Sec. 2.5).  Neighbours j < lev1 belong to the first wavefront,
+// whose forward increments are not stored (first_front_incr).
 template <typename T>
 __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &ip, const double *W,
                                            const double *w, int f, int e, int j, const T *dws, T cfl, int lev1,
-                                           T *t)
+                                           T *t, const T *dsrc)
 {
     const int N = P.nc;
     double nx = P.enx[e], ny = P.eny[e];   // out of the cell
@@ -1278,7 +1278,7 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
             first_front_incr(P, ip, j, cfl, dj);
         } else {
 #pragma unroll
-            for (int k = 0; k < 5; k++) dj[k] = P.dW[k * N + j];
+            for (int k = 0; k < 5; k++) dj[k] = dsrc[k * N + j];
         }
     } else {
         ghost(ip, P.fbc[f], w, nx, ny, wj);
@@ -1388,12 +1388,17 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     if (MODE == SW_FWD || MODE == SW_TOP) {
 #pragma unroll
         for (int k = 0; k < 5; k++) acc[k] = T(P.M[k * N + c]);
+        // lower neighbours of the cell's block; with two block passes, the
+        // second also takes every neighbour in another block, with the first
+        // pass's increment
         auto lower = [&](const Entries &E, int b) {
 #pragma unroll
             for (int k = 0; k < MAXV; k++) {
                 const int j = E.nbr[k], fl = E.flag[k];
-                if (!(fl & CF_VALID) || j < 0 || !(fl & CF_LOWER)) continue;
-                sweep_term(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t);
+                if (!(fl & CF_VALID) || j < 0) continue;
+                const bool cross = (fl & CF_OTHER) && P.dWx;
+                if (!(fl & CF_LOWER) && !cross) continue;
+                sweep_term(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t, cross ? P.dWx : P.dW);
 #pragma unroll
                 for (int m = 0; m < 4; m++) acc[m] = acc_sub(acc[m], t[m]);
                 acc[4] = acc_add(acc[4], t[4]);
@@ -1421,7 +1426,7 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
         for (int k = 0; k < MAXV; k++) {
             const int j = E.nbr[k], fl = E.flag[k];
             if (!(fl & CF_VALID) || (j >= 0 && (fl & (CF_LOWER | CF_OTHER)))) continue;
-            sweep_term(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t);
+            sweep_term(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t, P.dW);
 #pragma unroll
             for (int m = 0; m < 5; m++) acc[m] = acc_add(acc[m], t[m]);
         }
@@ -1475,7 +1480,7 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
         auto lower = [&](int f, int e, int j, int fl) {
 #pragma unroll
             for (int m = 0; m < 5; m++) t[m] = T(0);
-            if ((fl & CF_VALID) && j >= 0 && (fl & CF_LOWER)) sweep_term(P, ip, W, w, f, e, j, dws, cfl, lev1, t);
+            if ((fl & CF_VALID) && j >= 0 && (fl & CF_LOWER)) sweep_term(P, ip, W, w, f, e, j, dws, cfl, lev1, t, P.dW);
 #pragma unroll
             for (int m = 0; m < 4; m++) acc[m] = quad_fold<true>(acc[m], t[m]);
             acc[4] = quad_fold<false>(acc[4], t[4]);
@@ -1506,7 +1511,7 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
 #pragma unroll
         for (int m = 0; m < 5; m++) t[m] = T(0);
         if ((fl & CF_VALID) && !(j >= 0 && (fl & (CF_LOWER | CF_OTHER))))
-            sweep_term(P, ip, W, w, f, e, j, dws, cfl, lev1, t);
+            sweep_term(P, ip, W, w, f, e, j, dws, cfl, lev1, t, P.dW);
 #pragma unroll
         for (int m = 0; m < 5; m++) acc[m] = quad_fold<false>(acc[m], t[m]);
     };
@@ -1773,7 +1778,7 @@ template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, 
 }
 template <typename T>
 void launch_sweep_blk(const Launch &L, const Params<T> &P, const int *bl_off, const int *bl_lo, const int *bl_hi,
-                      int ngb, bool fwd)
+                      int ngb, bool fwd, bool update)
 {
     if (ngb <= 0) return;
     const bool one = P.ninst == 1;
@@ -1783,7 +1788,7 @@ void launch_sweep_blk(const Launch &L, const Params<T> &P, const int *bl_off, co
     } else {
         if (one) hipLaunchKernelGGL((k_sweep_blk<T, false, true>), dim3(ngb), dim3(64), 0, L.s, P, bl_off, bl_lo, bl_hi);
         else hipLaunchKernelGGL((k_sweep_blk<T, false, false>), dim3(ngb), dim3(64), 0, L.s, P, bl_off, bl_lo, bl_hi);
-        LAUNCH_ONE(k_update, T, dim3(nblk(P.nc, L.block[3])), dim3(L.block[3]), P);
+        if (update) LAUNCH_ONE(k_update, T, dim3(nblk(P.nc, L.block[3])), dim3(L.block[3]), P);
     }
 }
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
@@ -1821,7 +1826,7 @@ void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, cons
     template void launch_explicit<T>(const Launch &, const Params<T> &);                           \
     template void launch_sweep_wg<T>(const Launch &, const Params<T> &, const int *, int, bool);                 \
     template void launch_sweep_blk<T>(const Launch &, const Params<T> &, const int *, const int *, const int *,  \
-                                      int, bool);
+                                      int, bool, bool);
 INST(double)
 INST(float)
 

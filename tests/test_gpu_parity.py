@@ -551,23 +551,25 @@ def test_sweep_schedules_full_size(igks):
     assert err <= 1e-9
 
 
-def test_sweep_blocks_full_size(igks):
+@pytest.mark.parametrize("passes", [1, 2])
+def test_sweep_blocks_full_size(igks, passes):
     """The 250k-cell SA Joukowski mesh with coupled sweep blocks of at most
     512 cells (one wave per block): 3 iterations from the free stream in
-    FP64 against the oracle with the same blocks (1e-9 of each component's
-    scale, C_L to 1e-9), and the one-workgroup and per-wavefront schedules
-    give bitwise the same iterates as the wave-per-block one."""
+    FP64 against the oracle with the same blocks and passes (1e-9 of each
+    component's scale, C_L to 1e-9); with one pass the per-wavefront
+    schedule gives bitwise the same iterates as the wave-per-block one."""
     m, blk = mg.workload_blocks("jouk250k", 512)
     flow = (0.15, 4.0, 6e6, 3.0)
-    say("case jouk250k blocks", m.n_cells, "cells,", int(blk.max()) + 1, "blocks")
+    say("case jouk250k blocks", m.n_cells, "cells,", int(blk.max()) + 1, "blocks,", passes, "pass(es)")
     o = po.Oracle(m, threads=sens.host_threads(), cfl_init=10.0)
     o.set_sweep_blocks(blk)
+    o.set_block_passes(passes)
     o.set_freestream(*flow)
     o.iterate(3)
     Wo, lo = o.get_state(), o.wall_loads()
     out = []
-    for sweep in (3, 1):
-        g = igks.Solver(m, cfl_init=10.0, chunk=3, sweep=sweep, sweep_blocks=blk)
+    for sweep in ((3, 1) if passes == 1 else (3, 3)):
+        g = igks.Solver(m, cfl_init=10.0, chunk=3, sweep=sweep, sweep_blocks=blk, block_passes=passes)
         assert g.schedule()[4] == sweep
         g.set_freestream(*flow)
         g.iterate(3)
@@ -575,7 +577,7 @@ def test_sweep_blocks_full_size(igks):
         del g
     Wg, lg = out[0]
     err = (np.abs(Wg - Wo) / np.abs(Wo).max(axis=1, keepdims=True)).max()
-    say(f"[jouk250k blocks] 3 iterations: state err {err:.3e}, cl {lg['cl']:.12e} vs {lo['cl']:.12e}")
+    say(f"[jouk250k blocks, {passes} pass(es)] 3 iterations: state err {err:.3e}, cl {lg['cl']:.12e} vs {lo['cl']:.12e}")
     assert np.array_equal(out[0][0], out[1][0])
     assert err <= 1e-9
     assert abs(lg["cl"] - lo["cl"]) <= 1e-9 * abs(lo["cl"]) + 1e-12
@@ -707,23 +709,25 @@ def test_converged_sa_joukowski_loads_match_oracle(igks):
     say(f"[converged SA joukowski] mixed against FP64: cl {d['cl']:.2e} cd {d['cd']:.2e}")
 
 
-@pytest.mark.parametrize("sa", [False, True])
-def test_sweep_blocks_trajectory_parity(igks, sa):
+@pytest.mark.parametrize("sa,passes", [(False, 1), (True, 1), (False, 2), (True, 2)])
+def test_sweep_blocks_trajectory_parity(igks, sa, passes):
     """Sweep blocks (the sweeps couple only cells of one block): the GPU's
     three sweep schedules (a launch per wavefront, one workgroup, a wave per
     block) give bitwise the same iterates, and they follow the oracle with
-    the same blocks."""
+    the same blocks; with two block passes (wave per block only) the GPU
+    follows the oracle's two passes."""
     m0 = mg.random_hybrid(16, 12, seed=17, tags=TAGS_SYM, jitter=0.25)
     m, blk = mg.block_order(m0, 24)
     flow = (0.3, 2.0, 3e4 if sa else 3e3, 3.0 if sa else -1.0)
-    tag = f"sweep blocks sa={sa}"
+    tag = f"sweep blocks sa={sa} passes={passes}"
     say("case", tag, m.n_cells, "cells,", int(blk.max()) + 1, "blocks")
     o = po.Oracle(m, threads=sens.host_threads(), cfl_init=5.0)
     o.set_sweep_blocks(blk)
+    o.set_block_passes(passes)
     o.set_freestream(*flow)
     runs = []
-    for sweep in (1, 2, 3):
-        g = igks.Solver(m, cfl_init=5.0, chunk=5, sweep=sweep, sweep_blocks=blk)
+    for sweep in ((1, 2, 3) if passes == 1 else (3,)):
+        g = igks.Solver(m, cfl_init=5.0, chunk=5, sweep=sweep, sweep_blocks=blk, block_passes=passes)
         assert g.schedule()[4] == sweep
         g.set_freestream(*flow)
         runs.append(g)

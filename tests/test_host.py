@@ -243,7 +243,8 @@ def test_batch_bookkeeping():
 def test_call_order_and_option_errors():
     for bad in (dict(block=96), dict(block=512), dict(sweep=4), dict(precision=5), dict(chunk=-1),
                 dict(flux_lanes=3), dict(wall_temp=-1.0), dict(wall_temp=float("nan")), dict(limiter_freeze=-0.1),
-                dict(limiter_freeze=1.0), dict(tau_jump=2)):
+                dict(limiter_freeze=1.0), dict(tau_jump=2), dict(block_passes=3), dict(block_passes=-1),
+                dict(block_passes=2, sweep=1), dict(block_passes=2, sweep=2)):
         rc, ctx = ctx_for(**bad)
         assert rc == igks.IGKS_EINVAL, bad
         assert not ctx.value
@@ -362,3 +363,37 @@ def test_sweep_blocks_wavefronts(max_cells):
         assert igks.igks_set_sweep_blocks(ctx, 0, b.ctypes.data_as(C.POINTER(C.c_int32))) == igks.IGKS_EINVAL
     finally:
         igks.igks_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_two_block_passes_workspace_and_launches(precision):
+    """Two block passes keep the first pass's increments in an array of
+    their own (5 values per cell, FP64 or, mixed, FP32) and add a forward
+    and a backward block sweep to each iteration: 10 launches instead of 8
+    with sweep blocks; without blocks the option changes no launch."""
+    m = mg.random_hybrid(14, 10, seed=8, tags=dict(bottom=mg.WALL))
+    mb, blk = mg.block_order(m, 24)
+    sizes, launches = {}, {}
+    for passes in (1, 2):
+        for blocks in (False, True):
+            rc, ctx = ctx_for(block_passes=passes, precision=precision)
+            assert rc == igks.IGKS_OK
+            try:
+                assert upload(ctx, mb) == igks.IGKS_OK
+                if blocks:
+                    b = np.ascontiguousarray(blk, dtype=np.int32)
+                    assert igks.igks_set_sweep_blocks(ctx, 0, b.ctypes.data_as(C.POINTER(C.c_int32))) == igks.IGKS_OK
+                sz = C.c_size_t()
+                assert igks.igks_workspace_size(ctx, C.byref(sz)) == igks.IGKS_OK
+                it, nl = C.c_int32(), C.c_int32()
+                assert igks.igks_graph_chunk(ctx, C.byref(it), C.byref(nl)) == igks.IGKS_OK
+                sizes[passes, blocks] = sz.value
+                launches[passes, blocks] = nl.value
+            finally:
+                igks.igks_destroy(ctx)
+    per = 8 if precision == 0 else 4
+    extra = -(-5 * mb.n_cells * per // 256) * 256
+    assert sizes[2, True] - sizes[1, True] == extra
+    assert launches[1, True] == 8 and launches[2, True] == 10
+    assert launches[2, False] == launches[1, False]
+

@@ -58,15 +58,22 @@ MUTANTS = {
         "dWg[3] = dWi[3]; dWg[4] = -dWi[4];\n    } else {", "dWg[3] = dWi[3]; dWg[4] = dWi[4];\n    } else {",
         ["tests/test_oracle_solver.py::test_sa_lusgs_solves_factored_system"]),
     "sweep blocks ignored in the forward sweep": (
-        "if (j >= i) continue;\n            if (c->sblk && c->sblk[j] != c->sblk[i]) continue;",
-        "if (j >= i) continue;",
+        "const int cross = c->sblk && c->sblk[j] != c->sblk[i];",
+        "const int cross = 0;",
+        ["tests/test_oracle_solver.py::test_lusgs_solves_factored_system"]),
+    "second block pass without the cross-block terms": (
+        "lusgs_pass(c, c->dW1);", "lusgs_pass(c, NULL);",
+        ["tests/test_oracle_solver.py::test_lusgs_solves_factored_system"]),
+    "second block pass takes its own cross-block increments": (
+        "const double *dj = cross ? &dWx[5 * j] : &dW[5 * j];", "const double *dj = &dW[5 * j];",
         ["tests/test_oracle_solver.py::test_lusgs_solves_factored_system"]),
     "sweep blocks ignored in the backward sweep": (
         "if (j <= i) continue;\n                if (c->sblk && c->sblk[j] != c->sblk[i]) continue;",
         "if (j <= i) continue;",
         ["tests/test_oracle_solver.py::test_lusgs_solves_factored_system"]),
     "SA lower neighbour subtracted": (
-        "acc[4] += of * dW[5 * j + 4];", "acc[4] -= of * dW[5 * j + 4];",
+        "&W[5 * j], nx, ny, S, face_rn(c, f), &dg, &of);\n                acc[4] += of * dj[4];",
+        "&W[5 * j], nx, ny, S, face_rn(c, f), &dg, &of);\n                acc[4] -= of * dj[4];",
         ["tests/test_oracle_solver.py::test_sa_lusgs_solves_factored_system"]),
 }
 

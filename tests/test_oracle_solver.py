@@ -375,13 +375,17 @@ def _jac_fd(W, nx, ny):
     return J
 
 
-@pytest.mark.parametrize("top,blocks", [(mg.OUTFLOW, False), (mg.MOVING_WALL, False), (mg.OUTFLOW, True)])
+@pytest.mark.parametrize("top,blocks", [(mg.OUTFLOW, False), (mg.MOVING_WALL, False), (mg.OUTFLOW, True),
+                                        (mg.OUTFLOW, 2)], ids=["outflow", "moving_wall", "blocks", "blocks2"])
 def test_lusgs_solves_factored_system(top, blocks):
     """The sweeps solve (L + D) D^-1 (D + U) dW = M with the Euler-flux
     Jacobians of Eq.20 (built here by finite differences) and the lagged
     ghost increments of Sec. 2.5 in the backward sweep (for the moving wall:
     the Jacobian of its affine ghost map).  With sweep blocks L and U hold
-    only the pairs of cells in the same block; D keeps every face."""
+    only the pairs of cells in the same block; D keeps every face.  With two
+    block passes (blocks = 2) the result is the same block system solved
+    again with M - X dW1 on the right, X the cross-block pairs' blocks (below
+    and above) and dW1 the one-pass result."""
     tags = dict(bottom=mg.WALL, top=top, left=mg.FREESTREAM, right=mg.SYMMETRY)
     m = mg.random_hybrid(5, 4, seed=7, tags=tags)
     m, _, _ = mg.colour_order(m)
@@ -391,6 +395,8 @@ def test_lusgs_solves_factored_system(top, blocks):
     if blocks:
         assert blk.max() >= 3
         o.set_sweep_blocks(blk)
+    if blocks == 2:
+        o.set_block_passes(2)
     W = smooth_state(o, 0.1, 3)
     o.set_state(W)
     cfl = 50.0
@@ -408,12 +414,15 @@ def test_lusgs_solves_factored_system(top, blocks):
             ls[f["fr"][k]] += lam[k] * f["len"][k]
     assert np.allclose(D, dbg["lamc"] / cfl + 0.5 * ls, rtol=1e-13)
     L = np.zeros((4 * n, 4 * n)); U = np.zeros((4 * n, 4 * n)); G = np.zeros((4 * n, 4 * n))
+    X = np.zeros((4 * n, 4 * n))
     Dm = np.kron(np.diag(D), np.eye(4))
     for k in range(o.nf):
         i, j = f["fl"][k], f["fr"][k]
         nx, ny, S = f["nx"][k], f["ny"][k], f["len"][k]
         if j >= 0:
             if blk[i] != blk[j]:
+                for a, b, sg in ((i, j, 1.0), (j, i, -1.0)):
+                    X[4 * a:4 * a + 4, 4 * b:4 * b + 4] += 0.5 * (_jac_fd(W[:, b], sg * nx, sg * ny) - lam[k] * np.eye(4)) * S
                 continue
             for a, b, sg in ((i, j, 1.0), (j, i, -1.0)):
                 jb = 0.5 * (_jac_fd(W[:, b], sg * nx, sg * ny) - lam[k] * np.eye(4)) * S
@@ -436,9 +445,17 @@ def test_lusgs_solves_factored_system(top, blocks):
     Mv = M[:4].T.reshape(-1)
     dws = np.linalg.solve(L + Dm, Mv)
     want = np.linalg.solve(Dm + U, (Dm - G) @ dws)
+    if blocks == 2:
+        dws = np.linalg.solve(L + Dm, Mv - X @ want)
+        want = np.linalg.solve(Dm + U, (Dm - G) @ dws)
     got = dW[:4].T.reshape(-1)
     assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
-    if blocks:
+    if blocks == 2:
+        # one pass is another system
+        o.set_block_passes(1)
+        one = o.lusgs_solve(cfl)[:4].T.reshape(-1)
+        assert np.abs(one - want).max() > 1e-6 * np.abs(want).max()
+    elif blocks:
         # the same system with the cross-block pairs kept is another one
         o.set_sweep_blocks(None)
         full = o.lusgs_solve(cfl)[:4].T.reshape(-1)
