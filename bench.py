@@ -349,10 +349,16 @@ def run_to_drop(igks, mesh, flow, precision, blocks=None, target=1e-10, max_it=4
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it = 0
+    marks = {}   # first checked iteration (and seconds) at drops 1e-4, 1e-6, 1e-8 and at Eq.40 <= 3e-8
     while it < max_it and time.perf_counter() - t0 < max_s:
         s.iterate(chunk)
         it += chunk
-        if s.residual()["res_drop"] <= target:
+        r = s.residual()
+        for key, hit in (("drop_1e-4", r["res_drop"] <= 1e-4), ("drop_1e-6", r["res_drop"] <= 1e-6),
+                         ("drop_1e-8", r["res_drop"] <= 1e-8), ("eq40_3e-8", r["eq40"] <= 3e-8)):
+            if hit and key not in marks:
+                marks[key] = dict(iterations=it, seconds=round(time.perf_counter() - t0, 3))
+        if r["res_drop"] <= target:
             break
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -360,21 +366,21 @@ def run_to_drop(igks, mesh, flow, precision, blocks=None, target=1e-10, max_it=4
     wl = s.wall_loads()
     return dict(iterations=it, seconds=round(dt, 4), drop=r["res_drop"], reached=r["res_drop"] <= target,
                 cl=wl["cl"], cd=wl["cd"], ms_per_iteration=round(1e3 * dt / max(it, 1), 4),
-                wavefronts=s.nlev, sweep_schedule=int(s.schedule()[4]))
+                wavefronts=s.nlev, sweep_schedule=int(s.schedule()[4]), milestones=marks)
 
 
 def time_to_drop_joukowski(igks, mg):
     """The 40k-cell laminar Joukowski (Ma 0.5, Re 5000, alpha 2) from the
-    impulsive start to a 1e-10 drop: block LU-SGS (blocks of at most 512
+    impulsive start to a 1e-10 drop: block LU-SGS (blocks of at most 256
     cells grown along the strongest couplings, generation order inside, a
     wave per block) in FP64 and mixed precision, against the colour order
     (3 wavefronts, fast sweeps that do not converge) and the explicit
     scheme."""
     flow = WORKLOADS["jouk40k"]["flow"]
-    mb, blk = mg.workload_blocks("jouk40k", 512)
+    mb, blk = mg.workload_blocks("jouk40k", 256)
     mc = mg.workload("jouk40k")
     out = dict(workload="jouk40k: " + WORKLOADS["jouk40k"]["desc"], target=1e-10, blocks=int(blk.max()) + 1,
-               block_cells=512)
+               block_cells=256)
     out["blocks_fp64"] = run_to_drop(igks, mb, flow, igks.IGKS_FP64, blk, max_it=60000)
     out["blocks_mixed"] = run_to_drop(igks, mb, flow, igks.IGKS_MIXED, blk, max_it=60000)
     out["colour_fp64"] = run_to_drop(igks, mc, flow, igks.IGKS_FP64, None, max_it=10000, max_s=15.0)
@@ -383,29 +389,29 @@ def time_to_drop_joukowski(igks, mg):
     return out
 
 
-def time_to_drop_sa250k(igks, mg, max_s=15.0):
+def time_to_drop_sa250k(igks, mg, max_s=40.0):
     """The 250k-cell SA Joukowski (Ma 0.15, Re 6e6, alpha 4) from the free
-    stream at CFL 10 with block LU-SGS and the Eq.9 limiter held from a drop
-    of 1e-4, FP64 and mixed, for about max_s seconds each: the drop it
-    levels off at, not 1e-10."""
+    stream at CFL 10 with block LU-SGS in two passes (the second with the
+    first's cross-block terms) and the Eq.9 limiter held from a drop of
+    1e-4, FP64 and mixed, for about max_s seconds each: the milestones on
+    the way (drops 1e-4, 1e-6, 1e-8, Eq.40 <= 3e-8) and the drop reached."""
     flow = WORKLOADS["jouk250k"]["flow"]
     mb, blk = mg.workload_blocks("jouk250k", 512)
     out = dict(workload="jouk250k: " + WORKLOADS["jouk250k"]["desc"], target=1e-10, blocks=int(blk.max()) + 1,
-               block_cells=512, limiter="Eq.9, held from a drop of 1e-4", status="floor",
-               note="the residual levels off near a 3e-3 drop within 20 000 iterations (C_L, C_D settled to 5 "
-                    "digits) and stays there; without the limiter the wake behind the trailing edge falls into a "
-                    "limit cycle; in natural order (587 wavefronts, 10 ms per iteration) the limiter hold reaches "
-                    "5e-7 after 40 000 iterations")
+               block_cells=512, block_passes=2, limiter="Eq.9, held from a drop of 1e-4",
+               note="two block passes reach 5e-7 in 40 000 iterations and 1.5e-9 in 200 000 (200 s), below 1e-8 "
+                    "the rate slows; without the limiter the wake behind the trailing edge holds a limit cycle "
+                    "near 4e-2; one block pass levels off near 3e-3")
     for key, prec in (("blocks_fp64", igks.IGKS_FP64), ("blocks_mixed", igks.IGKS_MIXED)):
         out[key] = run_to_drop(igks, mb, flow, prec, blk, max_it=10 ** 6, chunk=500, cfl=10.0, max_s=max_s,
-                               limiter=1, limiter_freeze=1e-4)
+                               limiter=1, limiter_freeze=1e-4, block_passes=2)
     return out
 
 
-def batch_to_drop(igks, mg, target=1e-10, max_s=40.0, chunk=500):
-    """batch64 in generation order with coupled sweep blocks (512 cells),
-    mixed precision, the Eq.9 limiter held from a drop of 1e-4, from the
-    free stream at CFL 10, for about max_s seconds: per instance the first
+def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
+    """batch64 in generation order with coupled sweep blocks (512 cells) in
+    two block passes, mixed precision, the Eq.9 limiter held from a drop of
+    1e-4, from the free stream at CFL 10, for about max_s seconds: per instance the first
     checked iteration at a `target` drop (None if not reached) and the final
     drop; the instances that reached it are then run alone in FP64 to the
     same target, one after another, for the wall-time comparison."""
@@ -416,7 +422,7 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=40.0, chunk=500):
         mb, bk = mg.block_order(m, 512, "coupled")
         meshes.append(mb)
         blocks.append(bk)
-    opt = dict(cfl_init=10.0, limiter=1, limiter_freeze=1e-4)
+    opt = dict(cfl_init=10.0, limiter=1, limiter_freeze=1e-4, block_passes=2)
     s = igks.BatchSolver(meshes, chunk=100, sweep_blocks=blocks, precision=igks.IGKS_MIXED, **opt)
     for i, (_, f) in enumerate(items):
         s.set_freestream(i, *f)
@@ -441,9 +447,10 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=40.0, chunk=500):
     seq = {}
     for i in [i for i in range(64) if first[i] is not None]:
         seq[i] = run_to_drop(igks, meshes[i], items[i][1], igks.IGKS_FP64, blocks[i], target=target,
-                             max_it=10 * first[i], chunk=100, cfl=10.0, max_s=30.0, limiter=1, limiter_freeze=1e-4)
-    return dict(workload="batch64 in generation order, coupled sweep blocks of at most 512 cells, mixed, limiter "
-                         "held from 1e-4, CFL 10 -> Eq.25",
+                             max_it=10 * first[i], chunk=100, cfl=10.0, max_s=30.0, limiter=1, limiter_freeze=1e-4,
+                             block_passes=2)
+    return dict(workload="batch64 in generation order, coupled sweep blocks of at most 512 cells, two block "
+                         "passes, mixed, limiter held from 1e-4, CFL 10 -> Eq.25",
                 target=target, iterations=it, seconds=round(t_batch, 3), ms_per_iteration=round(1e3 * t_batch / it, 3),
                 wavefronts=nlev, reached=sum(x is not None for x in first), first_iteration_at_target=first,
                 batch_seconds_at_target=t_first, final_drop=[float(f"{d:.3e}") for d in drops], frozen=frozen,
