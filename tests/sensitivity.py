@@ -1,17 +1,20 @@
-"""How far the oracle's own residual moves when the mesh geometry moves by
-rounding: the scale against which two independent FP64 codes (the GPU
-library and the oracle compute the geometry and the flux with different
-formulas) can be compared cell by cell.
+"""How far the oracle's own residual moves when its inputs move by rounding:
+the scale against which two independent FP64 codes (the GPU library and the
+oracle compute the geometry, the state's derived quantities and the flux with
+different formulas) can be compared cell by cell.
 
-Every node coordinate is moved by one unit in the last place, with a seeded
-random sign, and the oracle evaluates the residual of the same cell state on
-the moved mesh.  Per cell, the largest change over the four flow components
-relative to the cell's gross flux sum_faces |F S| (and for the SA
-right-hand side relative to its own gross size) is the cell's measured
-sensitivity.  In exact arithmetic the change is zero for the free stream; in
-thin high-aspect-ratio cells the wall-normal differences (W0 - W_c) / d of
-Eq.5 lose about log10(aspect ratio) digits, and at a cusp the coordinates'
-rounding is a sizeable part of a cell's width, which is where it grows.
+Two kinds of one-ulp perturbation, each with seeded random signs: every node
+coordinate of the mesh (the codes compute centroids, normals, lengths and
+distances from the nodes differently), and every component of the cell
+state (the codes derive velocity, lambda, pressure and viscosity from the
+conservative state with different formulas, which acts like a rounding of
+the state).  The oracle evaluates the residual of the perturbed input.  Per
+cell, the largest change over the four flow components relative to the
+cell's gross flux sum_faces |F S| (and for the SA right-hand side relative to
+its own gross size) is the cell's measured sensitivity.  It grows in thin
+high-aspect-ratio cells, where the wall-normal differences (W0 - W_c) / d of
+Eq.5 lose about log10(aspect ratio) digits, and at a cusp, where the
+coordinates' rounding is a sizeable part of a cell's width.
 """
 import os
 
@@ -38,10 +41,18 @@ def nudged(mesh, seed):
     return m
 
 
+def nudged_state(W, seed):
+    """The state with every component moved by one ulp (seeded sign)."""
+    rng = np.random.default_rng(seed)
+    sgn = rng.choice([-1.0, 1.0], size=W.shape)
+    return W + sgn * np.spacing(np.abs(W))
+
+
 def residual_sensitivity(mesh, flow, W, options=None, seeds=(101, 202), threads=None):
-    """Per cell: max over the seeds of max_k |M_k(nudged) - M_k| / gross_k
-    (flow) and |R(nudged) - R| / gross_SA (SA right-hand side, 0 in laminar
-    runs), with M, gross and R of the unmoved mesh; `options` the oracle's
+    """Per cell: max over the seeds and the two kinds of perturbation (the
+    mesh's nodes, the state) of max_k |M_k(nudged) - M_k| / gross_k (flow)
+    and |R(nudged) - R| / gross_SA (SA right-hand side, 0 in laminar runs),
+    with M, gross and R of the unperturbed input; `options` the oracle's
     options (pyoracle.Options)."""
     threads = threads or host_threads()
     o = po.Oracle(mesh, options=options, threads=threads)
@@ -52,15 +63,24 @@ def residual_sensitivity(mesh, flow, W, options=None, seeds=(101, 202), threads=
     del o
     s_flow = np.zeros(mesh.n_cells)
     s_sa = np.zeros(mesh.n_cells)
+    def take(Mp):
+        nonlocal s_flow, s_sa
+        s_flow = np.maximum(s_flow, (np.abs(Mp[:4] - M[:4]) / G).max(axis=0))
+        if Gsa.any():
+            s_sa = np.maximum(s_sa, np.abs(Mp[4] - M[4]) / np.where(Gsa > 0, Gsa, 1.0))
+
     for seed in seeds:
         p = po.Oracle(nudged(mesh, seed), options=options, threads=threads)
         p.set_freestream(*flow)
         p.set_state(W)
-        Mp, _ = p.compute_residual()
+        take(p.compute_residual()[0])
         del p
-        s_flow = np.maximum(s_flow, (np.abs(Mp[:4] - M[:4]) / G).max(axis=0))
-        if Gsa.any():
-            s_sa = np.maximum(s_sa, np.abs(Mp[4] - M[4]) / np.where(Gsa > 0, Gsa, 1.0))
+    o = po.Oracle(mesh, options=options, threads=threads)
+    o.set_freestream(*flow)
+    for seed in seeds:
+        o.set_state(nudged_state(W, seed + 1))
+        take(o.compute_residual()[0])
+    del o
     return s_flow, s_sa
 
 

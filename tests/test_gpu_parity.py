@@ -5,10 +5,11 @@ Tolerances (floating point): the residual M of Eq.16 is a sum of face
 fluxes that nearly cancel, so it is compared per cell and component
 against that cell's gross flux sum_faces |F S|: within 1e-12 of it (the
 arithmetic error of both sides is a few ulp of the gross flux), or within
-a fixed multiple of the cell's measured sensitivity to rounding of the
-geometry where that is larger (tests/sensitivity.py: the oracle's own
-residual change when every node moves by one ulp; the two codes compute
-the geometry with different formulas); the SA right-hand side per cell in
+a fixed multiple of the cell's measured sensitivity to rounding of its
+inputs where that is larger (tests/sensitivity.py: the oracle's own
+residual change when every node, or every state component, moves by one
+ulp; the two codes compute the geometry and the state's derived quantities
+with different formulas); the SA right-hand side per cell in
 the same way against its own gross size (the magnitudes of its face terms
 plus Omega |Sr|); away from convergence also the whole residual,
 ||M_gpu - M_oracle||_2 <= 1e-12 ||M_oracle||_2; states after a few
@@ -94,10 +95,11 @@ def check_residual(o, g, W, tag, away=True):
     """Per cell: max_k |M_gpu,k - M_oracle,k| / gross_k <= tol and, with SA,
     |R_gpu - R_oracle| / gross_SA <= tol_SA, where tol = max(1e-12,
     SENS_FACTOR s) with s the cell's measured sensitivity of the oracle's
-    residual to rounding of the geometry (sensitivity.py).  The two codes
-    compute the geometry independently, and both form wall-normal
-    differences (W0 - W_c)/d, which in thin cells far from the origin, and
-    at the trailing-edge cusp, lose digits to the coordinates' rounding.
+    residual to rounding of the geometry and of the state (sensitivity.py).
+    The two codes compute the geometry and the state's derived quantities
+    (velocity, lambda, pressure) with different formulas, and both form
+    wall-normal differences (W0 - W_c)/d, which in thin cells far from the
+    origin, and at the trailing-edge cusp, lose digits to rounding.
     away: the state is away from convergence, so the whole residual is
     compared too, ||M_gpu - M_oracle||_2 <= 1e-12 ||M_oracle||_2."""
     o.set_state(W)
