@@ -43,7 +43,7 @@ WORKLOADS = {
 # launch schedules (block sizes of prep, flux, gather, sweep; sweep schedule;
 # lanes per face) found by igks_autotune on these workloads; block sizes never
 # change results
-SCHEDULES = {"jouk2m": [256, 128, 64, 256, 1, 2], "batch64": [256, 128, 256, 64, 1, 2],
+SCHEDULES = {"jouk2m": [256, 128, 64, 256, 1, 1], "batch64": [256, 256, 256, 128, 1, 1],
              "jouk40k": [128, 64, 64, 64, 1, 1]}
 # plate variants of the batched time-to-1e-10 comparison: (Ma, Re_L)
 DROP_BATCH = [(0.2, 5e3), (0.25, 8e3), (0.3, 1e4), (0.35, 1.5e4), (0.4, 2e4), (0.3, 6e3), (0.2, 1.2e4), (0.4, 1e4)]
@@ -59,6 +59,20 @@ KSRC = os.path.join(ROOT, "paper_1709_00803_amd", "csrc", "igks_kernels.hip")
 
 def say(*a):
     print("#", *a, file=sys.stderr, flush=True)
+
+
+class Progress:
+    """A line on stderr at most every `every` seconds from a long run (the
+    runs to a residual drop print nothing else for minutes)."""
+
+    def __init__(self, label, every=20.0):
+        self.label, self.every, self.t = label, every, time.perf_counter()
+
+    def __call__(self, it, drop):
+        now = time.perf_counter()
+        if now - self.t >= self.every:
+            self.t = now
+            say(f"{self.label}: iteration {it}, drop {drop:.3e}")
 
 
 def kernel_bytes(n, f, e, sa, mixed):
@@ -325,20 +339,24 @@ def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it = 0
+    prog = Progress(f"plate to {target:g} (scheme {scheme}, precision {precision})")
     while it < max_it:
         s.iterate(chunk)
         it += chunk
-        if s.residual()["res_drop"] <= target:
+        d = s.residual()["res_drop"]
+        prog(it, d)
+        if d <= target:
             break
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     wl = s.wall_loads()
+    say(f"plate to {target:g} (scheme {scheme}, precision {precision}): {it} iterations, {dt:.1f}s")
     return dict(iterations=it, seconds=round(dt, 4), drop=s.residual()["res_drop"], cd=wl["cd"],
                 cell_updates_per_s=m.n_cells * it / dt)
 
 
 def run_to_drop(igks, mesh, flow, precision, blocks=None, target=1e-10, max_it=40000, chunk=200, scheme=0,
-                cfl=1000.0, max_s=60.0, **opt):
+                cfl=1000.0, max_s=60.0, label="run", **opt):
     """Iterations and seconds from the impulsive start to a density-residual
     drop of `target` (or to max_it iterations / about max_s seconds); opt:
     further solver options (limiter, limiter_freeze)."""
@@ -350,10 +368,12 @@ def run_to_drop(igks, mesh, flow, precision, blocks=None, target=1e-10, max_it=4
     t0 = time.perf_counter()
     it = 0
     marks = {}   # first checked iteration (and seconds) at drops 1e-4, 1e-6, 1e-8 and at Eq.40 <= 3e-8
+    prog = Progress(label)
     while it < max_it and time.perf_counter() - t0 < max_s:
         s.iterate(chunk)
         it += chunk
         r = s.residual()
+        prog(it, r["res_drop"])
         for key, hit in (("drop_1e-4", r["res_drop"] <= 1e-4), ("drop_1e-6", r["res_drop"] <= 1e-6),
                          ("drop_1e-8", r["res_drop"] <= 1e-8), ("eq40_3e-8", r["eq40"] <= 3e-8)):
             if hit and key not in marks:
@@ -364,6 +384,7 @@ def run_to_drop(igks, mesh, flow, precision, blocks=None, target=1e-10, max_it=4
     dt = time.perf_counter() - t0
     r = s.residual()
     wl = s.wall_loads()
+    say(f"{label}: {it} iterations, {dt:.1f}s, drop {r['res_drop']:.3e}")
     return dict(iterations=it, seconds=round(dt, 4), drop=r["res_drop"], reached=r["res_drop"] <= target,
                 cl=wl["cl"], cd=wl["cd"], ms_per_iteration=round(1e3 * dt / max(it, 1), 4),
                 wavefronts=s.nlev, sweep_schedule=int(s.schedule()[4]), milestones=marks)
@@ -381,11 +402,12 @@ def time_to_drop_joukowski(igks, mg):
     mc = mg.workload("jouk40k")
     out = dict(workload="jouk40k: " + WORKLOADS["jouk40k"]["desc"], target=1e-10, blocks=int(blk.max()) + 1,
                block_cells=256)
-    out["blocks_fp64"] = run_to_drop(igks, mb, flow, igks.IGKS_FP64, blk, max_it=60000)
-    out["blocks_mixed"] = run_to_drop(igks, mb, flow, igks.IGKS_MIXED, blk, max_it=60000)
-    out["colour_fp64"] = run_to_drop(igks, mc, flow, igks.IGKS_FP64, None, max_it=10000, max_s=15.0)
+    out["blocks_fp64"] = run_to_drop(igks, mb, flow, igks.IGKS_FP64, blk, max_it=60000, label="jouk40k blocks fp64")
+    out["blocks_mixed"] = run_to_drop(igks, mb, flow, igks.IGKS_MIXED, blk, max_it=60000, label="jouk40k blocks mixed")
+    out["colour_fp64"] = run_to_drop(igks, mc, flow, igks.IGKS_FP64, None, max_it=10000, max_s=15.0,
+                                     label="jouk40k colour fp64")
     out["explicit_fp64_cfl0.9"] = run_to_drop(igks, mc, flow, igks.IGKS_FP64, None, max_it=2000000, chunk=2000,
-                                             scheme=1, cfl=0.9, max_s=40.0)
+                                             scheme=1, cfl=0.9, max_s=40.0, label="jouk40k explicit")
     return out
 
 
@@ -404,7 +426,7 @@ def time_to_drop_sa250k(igks, mg, max_s=40.0):
                     "near 4e-2; one block pass levels off near 3e-3")
     for key, prec in (("blocks_fp64", igks.IGKS_FP64), ("blocks_mixed", igks.IGKS_MIXED)):
         out[key] = run_to_drop(igks, mb, flow, prec, blk, max_it=10 ** 6, chunk=500, cfl=10.0, max_s=max_s,
-                               limiter=1, limiter_freeze=1e-4, block_passes=2)
+                               limiter=1, limiter_freeze=1e-4, block_passes=2, label=f"jouk250k {key}")
     return out
 
 
@@ -429,6 +451,7 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it, first, t_first = 0, [None] * 64, [None] * 64
+    prog = Progress("batch64 blocks")
     while time.perf_counter() - t0 < max_s and any(x is None for x in first):
         try:
             s.iterate(chunk)
@@ -438,6 +461,7 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
         for i in range(64):
             if first[i] is None and s.residual(i)["res_drop"] <= target:
                 first[i], t_first[i] = it, round(time.perf_counter() - t0, 3)
+        prog(it, float(np.median([s.residual(i)["res_drop"] for i in range(64)])))
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     drops = [s.residual(i)["res_drop"] for i in range(64)]
@@ -448,7 +472,7 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
     for i in [i for i in range(64) if first[i] is not None]:
         seq[i] = run_to_drop(igks, meshes[i], items[i][1], igks.IGKS_FP64, blocks[i], target=target,
                              max_it=10 * first[i], chunk=100, cfl=10.0, max_s=30.0, limiter=1, limiter_freeze=1e-4,
-                             block_passes=2)
+                             block_passes=2, label=f"batch64 instance {i} alone")
     return dict(workload="batch64 in generation order, coupled sweep blocks of at most 512 cells, two block "
                          "passes, mixed, limiter held from 1e-4, CFL 10 -> Eq.25",
                 target=target, iterations=it, seconds=round(t_batch, 3), ms_per_iteration=round(1e3 * t_batch / it, 3),
@@ -458,7 +482,7 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
                 fp64_alone_seconds_total=round(sum(v["seconds"] for v in seq.values()), 4))
 
 
-def time_to_converge_cavity(igks, mg, max_it=20000, chunk=200):
+def time_to_converge_cavity(igks, mg, max_it=20000, chunk=200, label="cavity"):
     """The lid-driven cavity (100x100, Re 1000, Ma 0.1 sqrt 3, isothermal
     walls) from rest, implicit CFL 1000 growing by Eq.25, to the paper's
     criterion Eq.40 <= 3e-8."""
@@ -473,10 +497,13 @@ def time_to_converge_cavity(igks, mg, max_it=20000, chunk=200):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it = 0
+    prog = Progress(f"{label} to Eq.40")
     while it < max_it:
         s.iterate(chunk)
         it += chunk
-        if s.residual()["eq40"] <= 3e-8:
+        r = s.residual()
+        prog(it, r["res_drop"])
+        if r["eq40"] <= 3e-8:
             break
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -487,7 +514,7 @@ def time_to_converge_cavity(igks, mg, max_it=20000, chunk=200):
                 paper_iterations=4430, paper_seconds=543.2)
 
 
-def time_to_converge_turbulent_plate(igks, mg, max_it=30000, chunk=500):
+def time_to_converge_turbulent_plate(igks, mg, max_it=30000, chunk=500, label="turbulent plate"):
     """The turbulent flat plate (SA, Ma 0.2, Re 5e6 per unit length, 7680
     cells, natural order) from the free stream at CFL 10 growing by Eq.25,
     to the paper's criterion Eq.40 <= 3e-8."""
@@ -498,10 +525,13 @@ def time_to_converge_turbulent_plate(igks, mg, max_it=30000, chunk=500):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it = 0
+    prog = Progress(f"{label} to Eq.40")
     while it < max_it:
         s.iterate(chunk)
         it += chunk
-        if s.residual()["eq40"] <= 3e-8:
+        r = s.residual()
+        prog(it, r["res_drop"])
+        if r["eq40"] <= 3e-8:
             break
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -524,9 +554,11 @@ def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it, first = 0, [None] * len(flows)
+    prog = Progress("batched plates")
     while it < max_it and any(x is None for x in first):
         b.iterate(100)
         it += 100
+        prog(it, max(b.residual(i)["res_drop"] for i in range(len(flows))))
         for i in range(len(flows)):
             if first[i] is None and b.residual(i)["res_drop"] <= target:
                 first[i] = it
@@ -547,6 +579,7 @@ def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000):
         torch.cuda.synchronize()
         t_seq += time.perf_counter() - t0
         its_seq.append(k)
+        say(f"plate {f[:3]} alone: {k} iterations")
     return dict(instances=len(flows), flows_ma_re=DROP_BATCH, batch_mixed_seconds=round(t_batch, 4),
                 batch_iterations_to_target=first, fp64_sequential_seconds=round(t_seq, 4),
                 fp64_iterations_to_target=its_seq, speedup=round(t_seq / t_batch, 3))

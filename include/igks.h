@@ -82,7 +82,7 @@ typedef struct igks_options {
     int sweep;          /* LU-SGS sweep schedule: 0 auto, 1 one launch per wavefront,
                            2 all wavefronts in one workgroup (barrier between wavefronts),
                            3 one wave per sweep block (igks_set_sweep_blocks), all blocks at once */
-    int flux_lanes;     /* lanes per face of the flux kernel: 0 auto (2 from 131072 faces on),
+    int flux_lanes;     /* lanes per face of the flux kernel: 0 auto (2 below 32768 faces),
                            1 or 2; the two agree to rounding */
     int scheme;         /* 0: implicit LU-SGS (Eq.18-22); 1: explicit Eq.15 with local time
                            steps dt_i = CFL Omega_i / (Lambda_c)_i, CFL = cfl_init fixed
@@ -317,7 +317,7 @@ int igks_batch_status(igks_ctx *ctx, int32_t inst, int32_t *halted);
  * block sizes of the four classes, the sweep schedule (1: one launch per
  * wavefront, 2: one workgroup, 3: a wave per sweep block) and the lanes per
  * face of the flux (1 or 2;
- * before any tuning 2 from 131072 faces on).  IGKS_EINVAL unless
+ * before any tuning 2 below 32768 faces).  IGKS_EINVAL unless
  * 1 <= iters <= 1000; IGKS_ENONPHYS if an instance is frozen. */
 int igks_autotune(igks_ctx *ctx, int32_t iters, int32_t *schedule6);
 int igks_get_schedule(const igks_ctx *ctx, int32_t *schedule6);

@@ -103,7 +103,9 @@ struct Params {
     const double *enx, *eny, *es;
     // face arrays (internal face order)
     const int *fl, *fr, *fbc;
-    const double *fnx, *fny, *flen, *frl, *frr, *fdl, *fdr, *frn;
+    // fidl, fidr, firn: 1/d_l, 1/d_r (centroid-face normal distances; d_r = d_l
+    // on a boundary face) and 1/|r.n| (centroid to centroid, 2 d_l on a boundary)
+    const double *fnx, *fny, *flen, *frl, *frr, *fidl, *fidr, *firn;
     // nf x FR_STRIDE face records, one 64-byte record per face, so that a
     // cell reading a face's outputs through its entries touches one cache
     // line: FR_F0, FR_F1, FR_F2, FR_F3 the time-averaged flux times length

@@ -73,7 +73,7 @@ constexpr int NKT = 6;
 struct WsMap {
     Buf ip, is, slot, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, dW1, xc, yc, area, lsinv, dwall, vtx, phi;
     Buf cinst, finst, icell, ioff, g2i, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
-    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fdl, fdr, frn, ipart, hist, ipos;
+    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fidl, fidr, firn, ipart, hist, ipos;
     Buf frec, flam, fsak, enx, eny, es;
     Buf wall_faces, wall_out, woff, wseg, lev_off, bl_off, bl_lo, bl_hi, stage, backup;
     size_t total;
@@ -179,9 +179,10 @@ int graph_chunk(const igks_ctx *c) { return graph_chunk_for(c, c->sweep_mode); }
 // The schedule chosen at binding time from the sizes: one workgroup for the
 // sweeps when wavefronts are many and narrow (one workgroup of 512 threads
 // takes a wavefront per round of 512 cells and a launch per wavefront costs
-// a few microseconds, so the workgroup wins up to about two rounds); two
-// lanes per face once one lane per face would already give two waves per
-// SIMD (one lane leaves SIMDs idle on small meshes).
+// a few microseconds, so the workgroup wins up to about two rounds); one
+// lane per face (its kernel holds two waves per SIMD and executes the
+// fewest instructions per face) except on small meshes, where two lanes
+// per face give the SIMDs twice as many waves to switch between.
 //
 // With sweep blocks the cells of different blocks never wait for each other,
 // so one wave sweeps each block on its own (no launch per wavefront, no
@@ -201,7 +202,7 @@ int auto_sweep_mode(const igks_ctx *c)
     const double width = (double)c->g.N / std::max(1, c->g.nlev);
     return (c->g.nlev > 16 && width < 1024.0) ? 2 : 1;
 }
-bool auto_flux_pair(const igks_ctx *c) { return c->opt.flux_lanes == 2 || (c->opt.flux_lanes == 0 && c->g.F >= 131072); }
+bool auto_flux_pair(const igks_ctx *c) { return c->opt.flux_lanes == 2 || (c->opt.flux_lanes == 0 && c->g.F < 32768); }
 
 // ------------------------------------------------------------------ ingest
 
@@ -608,7 +609,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.cf_dx = L.add(E * D); w.cf_dy = L.add(E * D);
     w.fl = L.add(F * I); w.fr = L.add(F * I); w.fbc = L.add(F * I);
     w.fnx = L.add(F * D); w.fny = L.add(F * D); w.flen = L.add(F * D); w.frl = L.add(2 * F * D);
-    w.frr = L.add(2 * F * D); w.fdl = L.add(F * D); w.fdr = L.add(F * D); w.frn = L.add(F * D);
+    w.frr = L.add(2 * F * D); w.fidl = L.add(F * D); w.fidr = L.add(F * D); w.firn = L.add(F * D);
     w.frec = L.add(FR_STRIDE * F * D); w.flam = L.add(F * D); w.fsak = L.add(F * D);
     w.enx = L.add(E * D); w.eny = L.add(E * D); w.es = L.add(E * D);
     w.ipart = L.add(2 * NI * (size_t)norm_rb(G) * D);
@@ -656,7 +657,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.cf_dx = D(w.cf_dx); P.cf_dy = D(w.cf_dy);
     P.fl = In(w.fl); P.fr = In(w.fr); P.fbc = In(w.fbc);
     P.fnx = D(w.fnx); P.fny = D(w.fny); P.flen = D(w.flen); P.frl = D(w.frl); P.frr = D(w.frr);
-    P.fdl = D(w.fdl); P.fdr = D(w.fdr); P.frn = D(w.frn);
+    P.fidl = D(w.fidl); P.fidr = D(w.fidr); P.firn = D(w.firn);
     P.frec = D(w.frec); P.flam = D(w.flam); P.fsak = D(w.fsak);
     P.enx = D(w.enx); P.eny = D(w.eny); P.es = D(w.es);
     P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipos = In(w.ipos); P.ipart = D(w.ipart); P.rb = norm_rb(c->g);
@@ -1184,7 +1185,12 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     rc |= up(w.fl, G.fl.data(), F * I); rc |= up(w.fr, G.fr.data(), F * I); rc |= up(w.fbc, G.ftag.data(), F * I);
     rc |= up(w.fnx, G.fnx.data(), F * D); rc |= up(w.fny, G.fny.data(), F * D); rc |= up(w.flen, G.flen.data(), F * D);
     rc |= up(w.frl, G.frl.data(), 2 * F * D); rc |= up(w.frr, G.frr.data(), 2 * F * D);
-    rc |= up(w.fdl, G.fdl.data(), F * D); rc |= up(w.fdr, G.fdr.data(), F * D); rc |= up(w.frn, G.frn.data(), F * D);
+    {
+        // the kernels multiply by the inverse distances
+        std::vector<double> idl(F), idr(F), irn(F);
+        for (int q = 0; q < F; q++) { idl[q] = 1.0 / G.fdl[q]; idr[q] = 1.0 / G.fdr[q]; irn[q] = 1.0 / G.frn[q]; }
+        rc |= up(w.fidl, idl.data(), F * D); rc |= up(w.fidr, idr.data(), F * D); rc |= up(w.firn, irn.data(), F * D);
+    }
     rc |= up(w.wall_faces, G.wall_faces.data(), G.wall_faces.size() * I);
     rc |= up(w.woff, G.woff.data(), G.woff.size() * I);
     rc |= up(w.wseg, G.wseg.data(), G.wseg.size() * D);

@@ -24,6 +24,76 @@ namespace igks {
 
 // ---------------------------------------------------------------- helpers
 
+// 1/b for a positive finite b: the hardware reciprocal estimate refined by
+// two Newton steps (each squares the relative error), to within about an
+// ulp.  The flux kernels are bound by their FP64 instruction stream, and an
+// IEEE FP64 divide is a sequence of about eleven instructions, this one of
+// five.
+__device__ __forceinline__ double frcp(double b)
+{
+    double x = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, x, 1.0);
+    x = fma(e, x, x);
+    e = fma(-b, x, 1.0);
+    return fma(e, x, x);
+}
+// a/b (b positive, finite) from frcp with one residual correction
+__device__ __forceinline__ double fdiv(double a, double b)
+{
+    const double x = frcp(b), q = a * x;
+    return fma(fma(-b, q, a), x, q);
+}
+// 1/sqrt(a) for a positive finite a: the hardware estimate refined by two
+// Newton steps of y <- y + y (1 - a y^2) / 2
+__device__ __forceinline__ double frsq(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    double e = fma(-a * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-a * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+// erfc(x).  For |x| <= 1 (every face of a subsonic flow: x = sqrt(lambda) U
+// is about 0.84 times the local normal Mach number) from the Maclaurin series
+// of erf (Abramowitz & Stegun 7.1.5), erf(x) = 2/sqrt(pi) sum_n (-1)^n
+// x^(2n+1) / (n! (2n+1)), 18 terms summed by Horner's rule in x^2 (the first
+// term left out is below 5e-18 of erf(1)); erfc = 1 - erf lies in [0.15, 1.85]
+// there, so nothing cancels.  Beyond, the library erfc.  The series costs a
+// seventh of the library's instruction sequence.
+struct ErfSeries {
+    double c[18];
+};
+constexpr ErfSeries erf_series()
+{
+    ErfSeries s{};
+    double f = 1.0;   // n!, exact up to 18!
+    for (int n = 0; n < 18; n++) {
+        if (n > 0) f *= n;
+        s.c[n] = (n % 2 ? -M_2_SQRTPI : M_2_SQRTPI) / (f * (2 * n + 1));
+    }
+    return s;
+}
+__device__ __forceinline__ double erfc_s(double x)
+{
+    if (fabs(x) <= 1.0) {
+        constexpr ErfSeries S = erf_series();
+        const double z = x * x;
+        double p = S.c[17];
+#pragma unroll
+        for (int n = 16; n >= 0; n--) p = fma(p, z, S.c[n]);
+        return 1.0 - x * p;
+    }
+    return erfc(x);
+}
+
+// 1/(2 lambda) of a conservative state (rho, rho U, rho V, rho E) from its
+// 1/rho: lambda = (K+2) rho / (4 (rho E - rho |U|^2 / 2)) (Sec. 2.1, Eq.2),
+// so 1/(2 lambda) = 2 (rho E - rho |U|^2 / 2) / ((K+2) rho), no divide.
+__device__ __forceinline__ double half_inv_lam(const double *w, double ir)
+{
+    return (2.0 / (KDOF + 2.0)) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) * ir) * ir;
+}
+
 // Sutherland's law relative to the 288.15 K free stream, T/T_inf = lam_inf/lam.
 __device__ __forceinline__ double mu_lam(int law, const InstParam &ip, double lam)
 {
@@ -43,6 +113,21 @@ __device__ __forceinline__ double sa_fv1(double chi)
 {
     double c3 = chi * chi * chi;
     return c3 / (c3 + 7.1 * 7.1 * 7.1);
+}
+// The same two laws for the flux kernels: the viscosity from hl = 1/(2
+// lambda) (T/T_inf = 2 lam_inf hl), and f_v1, with frcp / frsq in place of
+// the IEEE divides and square roots.
+__device__ __forceinline__ double mu_hl(int law, const InstParam &ip, double hl)
+{
+    if (law) return ip.mu_inf;
+    const double S = 110.4 / 288.15;
+    const double th = 2.0 * ip.lam_inf * hl;
+    return ip.mu_inf * (1.0 + S) * (th * th * frsq(th)) * frcp(th + S);
+}
+__device__ __forceinline__ double sa_fv1_f(double chi)
+{
+    double c3 = chi * chi * chi;
+    return c3 * frcp(c3 + 7.1 * 7.1 * 7.1);
 }
 
 // SA constants (standard model without the f_t2 term)
@@ -312,14 +397,21 @@ __device__ __forceinline__ void mom_u(double U, double lam, double hl, double *m
 }
 // The same half-space moments with the half chosen at run time: sgn = +1
 // for u > 0, -1 for u < 0 (the two lanes of a face take opposite halves).
+// SERIES: erfc from erfc_s (the sides' Maxwellians); otherwise the library
+// erfc (the equilibrium state's half spaces: the series there too raised the
+// one-lane flux kernel from 242 to 283 registers, one wave per SIMD instead
+// of two).
+template <bool SERIES>
 __device__ __forceinline__ void mom_u_half(double U, double lam, double hl, double sgn, double *m)
 {
-    double x = sqrt(lam) * U;
-    double e = exp(-x * x) * (0.5 / sqrt(M_PI * lam));
+    // one refined 1/sqrt(lam) gives both sqrt(lam) and 1/sqrt(pi lam)
+    const double s = frsq(lam);
+    double x = lam * s * U;
+    double e = exp(-x * x) * (0.5 / sqrt(M_PI)) * s;
     // the sign is applied by selection, not by a product, so that m[1] is
     // formed the same way whether sgn is known at compile time or not
     double es = sgn > 0.0 ? e : -e, xs = sgn > 0.0 ? -x : x;
-    m[0] = 0.5 * erfc(xs);
+    m[0] = 0.5 * (SERIES ? erfc_s(xs) : erfc(xs));
     m[1] = U * m[0] + es;
 #pragma unroll
     for (int k = 0; k < 6; k++) m[k + 2] = U * m[k + 1] + (k + 1) * hl * m[k];
@@ -332,23 +424,51 @@ __device__ __forceinline__ void mom_xi(double hl, double *x)
     x[2] = x[1] * (KDOF + 2.0) * hl;
 }
 
-// out = < u^A v^B (c0 + c1 u + c2 v + c3 (u^2+v^2+xi^2)/2) psi > with
-// psi = (1, u, v, (u^2+v^2+xi^2)/2); the exponents are compile-time so the
-// moment arrays stay in registers.
-template <int A, int B>
-__device__ __forceinline__ void pmom(const double *mu, const double *mv, const double *mx, const double *c,
-                                     double *out)
+// Moments out = < u^A v^B (c0 + c1 u + c2 v + c3 (u^2+v^2+xi^2)/2) psi > with
+// psi = (1, u, v, (u^2+v^2+xi^2)/2) of a Maxwellian, from its u, v and xi
+// moment arrays mu, mv, mx (exponents compile-time, so the arrays stay in
+// registers).  The velocity-space sums are regrouped by powers of u: with
+// G0 = c0 + c2 v + c3 H, G1 = c1, G2 = c3 / 2 and H = (v^2 + xi^2) / 2 the
+// weight is sum_k u^k G_k and psi_3 = u^2 / 2 + H, so
+//   out0 = sum_k <u^(A+k)> <v^B G_k>,      out1 = sum_k <u^(A+1+k)> <v^B G_k>,
+//   out2 = sum_k <u^(A+k)> <v^(B+1) G_k>,
+//   out3 = sum_k (<u^(A+2+k)> <v^B G_k> / 2 + <u^(A+k)> <v^B H G_k>).
+// The nine v, xi factors depend on the Maxwellian's v and xi moments and on
+// c only, so one set serves the u-moments of both half spaces and of the
+// whole line, and every exponent A: vx_coef forms them once, vx_apply
+// combines them with one set of u-moments (15 multiply-adds).
+struct VX {
+    double g[3], gp[3], h[3];   // <v^B G_k>, <v^(B+1) G_k>, <v^B H G_k>
+};
+template <int B>
+__device__ __forceinline__ VX vx_coef(const double *mv, const double *mx, const double *c)
 {
-    auto h = [&](int a, int b, int x) { return mu[a] * mv[b] * mx[x]; };
-    auto t = [&](int a, int b, int x) {
-        return c[0] * h(a, b, x) + c[1] * h(a + 1, b, x) + c[2] * h(a, b + 1, x) +
-               0.5 * c[3] * (h(a + 2, b, x) + h(a, b + 2, x) + h(a, b, x + 1));
-    };
-    out[0] = t(A, B, 0);
-    out[1] = t(A + 1, B, 0);
-    out[2] = t(A, B + 1, 0);
-    out[3] = 0.5 * (t(A + 2, B, 0) + t(A, B + 2, 0) + t(A, B, 1));
+    // <v^B H>, <v^(B+1) H>, <v^B H^2>
+    const double e0 = 0.5 * (mv[B + 2] + mv[B] * mx[1]);
+    const double e1 = 0.5 * (mv[B + 3] + mv[B + 1] * mx[1]);
+    const double e2 = 0.25 * (mv[B + 4] + 2.0 * mv[B + 2] * mx[1] + mv[B] * mx[2]);
+    VX o;
+    o.g[0] = c[0] * mv[B] + c[2] * mv[B + 1] + c[3] * e0;
+    o.g[1] = c[1] * mv[B];
+    o.g[2] = 0.5 * c[3] * mv[B];
+    o.gp[0] = c[0] * mv[B + 1] + c[2] * mv[B + 2] + c[3] * e1;
+    o.gp[1] = c[1] * mv[B + 1];
+    o.gp[2] = 0.5 * c[3] * mv[B + 1];
+    o.h[0] = c[0] * e0 + c[2] * e1 + c[3] * e2;
+    o.h[1] = c[1] * e0;
+    o.h[2] = 0.5 * c[3] * e0;
+    return o;
 }
+template <int A>
+__device__ __forceinline__ void vx_apply(const double *mu, const VX &o, double *out)
+{
+    out[0] = mu[A] * o.g[0] + mu[A + 1] * o.g[1] + mu[A + 2] * o.g[2];
+    out[1] = mu[A + 1] * o.g[0] + mu[A + 2] * o.g[1] + mu[A + 3] * o.g[2];
+    out[2] = mu[A] * o.gp[0] + mu[A + 1] * o.gp[1] + mu[A + 2] * o.gp[2];
+    out[3] = 0.5 * (mu[A + 2] * o.g[0] + mu[A + 3] * o.g[1] + mu[A + 4] * o.g[2]) + mu[A] * o.h[0] +
+             mu[A + 1] * o.h[1] + mu[A + 2] * o.h[2];
+}
+
 // <u^A psi>
 template <int A>
 __device__ __forceinline__ void pmom1(const double *mu, const double *mv, const double *mx, double *out)
@@ -408,7 +528,7 @@ __device__ __forceinline__ void side_terms(double sgn, const double *w, const do
 {
     // one reciprocal per denominator: an FP64 divide is a long sequence,
     // and the flux kernels are bound by their FP64 instruction stream
-    double r = w[0], ir = 1.0 / r, U = w[1] * ir, V = w[2] * ir, lam = lam_of(w), hl = 0.5 / lam;
+    double r = w[0], ir = frcp(r), U = w[1] * ir, V = w[2] * ir, hl = half_inv_lam(w, ir), lam = 0.5 * frcp(hl);
     double an[4], at[4], A[4], b[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) b[k] = gn[k] * ir;
@@ -416,40 +536,52 @@ __device__ __forceinline__ void side_terms(double sgn, const double *w, const do
 #pragma unroll
     for (int k = 0; k < 4; k++) b[k] = gt[k] * ir;
     msolve(U, V, lam, hl, b, at);
-    double mv[8], mx[3], mu[8];
+    double mv[8], mx[3], mu[8], mf[8];
     mom_u<0>(V, lam, hl, mv);
     mom_xi(hl, mx);
+    mom_u<0>(U, lam, hl, mf);
+    mom_u_half<true>(U, lam, hl, sgn, mu);
+    double t[4], s[4], t4[4], t16[4];
     {
-        double mf[8], t1[4], t2[4];
-        mom_u<0>(U, lam, hl, mf);
-        pmom<1, 0>(mf, mv, mx, an, t1);
-        pmom<0, 1>(mf, mv, mx, at, t2);
-#pragma unroll
-        for (int k = 0; k < 4; k++) b[k] = -(t1[k] + t2[k]);
-        msolve(U, V, lam, hl, b, A);
+        // a_n: <u a_n psi> over the whole line (for A) and on the half
+        // space, <u^2 a_n psi> on the half space
+        const VX x = vx_coef<0>(mv, mx, an);
+        vx_apply<1>(mf, x, b);
+        vx_apply<1>(mu, x, t4);
+        vx_apply<2>(mu, x, t16);
     }
-    mom_u_half(U, lam, hl, sgn, mu);
-    double t[4], s[4];
+    {
+        // a_t: the same with v in place of u
+        const VX x = vx_coef<1>(mv, mx, at);
+        vx_apply<0>(mf, x, t);
+#pragma unroll
+        for (int k = 0; k < 4; k++) b[k] = -(b[k] + t[k]);
+        vx_apply<0>(mu, x, t);
+        vx_apply<1>(mu, x, s);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            acc[4 + k] = r * (t4[k] + t[k]);
+            acc[16 + k] = r * (t16[k] + s[k]);
+        }
+    }
+    msolve(U, V, lam, hl, b, A);
+    {
+        const VX x = vx_coef<0>(mv, mx, A);
+        vx_apply<0>(mu, x, t);
+        vx_apply<1>(mu, x, s);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            acc[8 + k] = r * t[k];
+            acc[20 + k] = r * s[k];
+        }
+    }
     pmom1<0>(mu, mv, mx, t);
+    pmom1<1>(mu, mv, mx, s);
 #pragma unroll
-    for (int k = 0; k < 4; k++) acc[k] = r * t[k];
-    pmom1<1>(mu, mv, mx, t);
-#pragma unroll
-    for (int k = 0; k < 4; k++) acc[12 + k] = r * t[k];
-    pmom<1, 0>(mu, mv, mx, an, t);
-    pmom<0, 1>(mu, mv, mx, at, s);
-#pragma unroll
-    for (int k = 0; k < 4; k++) acc[4 + k] = r * (t[k] + s[k]);
-    pmom<2, 0>(mu, mv, mx, an, t);
-    pmom<1, 1>(mu, mv, mx, at, s);
-#pragma unroll
-    for (int k = 0; k < 4; k++) acc[16 + k] = r * (t[k] + s[k]);
-    pmom<0, 0>(mu, mv, mx, A, t);
-#pragma unroll
-    for (int k = 0; k < 4; k++) acc[8 + k] = r * t[k];
-    pmom<1, 0>(mu, mv, mx, A, t);
-#pragma unroll
-    for (int k = 0; k < 4; k++) acc[20 + k] = r * t[k];
+    for (int k = 0; k < 4; k++) {
+        acc[k] = r * t[k];
+        acc[12 + k] = r * s[k];
+    }
 }
 
 // Equilibrium part of the interface (Eq.4-5, Eq.11-14), split so that the
@@ -466,13 +598,14 @@ __device__ __forceinline__ void gks_eq(const Params<T> &P, const InstParam &ip, 
                                        double nut_f, double jump, GksEq &q)
 {
     q.r0 = w0[0];
-    q.ir0 = 1.0 / q.r0;
-    q.U0 = w0[1] * q.ir0; q.V0 = w0[2] * q.ir0; q.lam0 = lam_of(w0); q.hl0 = 0.5 / q.lam0;
-    double mul = mu_lam(P.mu_law, ip, q.lam0), mut = 0.0;
-    if (ip.sa && nut_f > 0.0) mut = q.r0 * nut_f * sa_fv1(nut_f * q.r0 / mul);
+    q.ir0 = frcp(q.r0);
+    q.U0 = w0[1] * q.ir0; q.V0 = w0[2] * q.ir0; q.hl0 = half_inv_lam(w0, q.ir0); q.lam0 = 0.5 * frcp(q.hl0);
+    double mul = mu_hl(P.mu_law, ip, q.hl0), mut = 0.0;
+    if (ip.sa && nut_f > 0.0) mut = q.r0 * nut_f * sa_fv1_f(nut_f * q.r0 * frcp(mul));
     double tau = (mul + mut) * 2.0 * q.lam0 * q.ir0;
     if (P.tau_jump) tau += dt * jump;
-    double eta = exp(-dt / tau), ome = -expm1(-dt / tau);
+    const double x = dt * frcp(tau);
+    double eta = exp(-x), ome = -expm1(-x);
     q.T1 = dt - tau * ome;
     q.T2 = -tau * dt * (1.0 + eta) + 2.0 * tau * tau * ome;
     q.T3 = 0.5 * dt * dt - tau * dt + tau * tau * ome;
@@ -485,20 +618,21 @@ __device__ __forceinline__ void gks_eq(const Params<T> &P, const InstParam &ip, 
 // One half space of q2 = <psi (abar_n H u + abar_n' (1-H) u)> and of its flux
 // moment f2 = <u psi (...)>: left (sgn = +1) with the slope (W0 - W_l)/d_l
 // on u > 0, right (sgn = -1) with (W_r - W0)/d_r on u < 0.
-__device__ __forceinline__ void gks_half(const GksEq &q, double sgn, const double *w0, const double *wc, double d,
+__device__ __forceinline__ void gks_half(const GksEq &q, double sgn, const double *w0, const double *wc, double id,
                                          double *q2, double *f2)
 {
     double b[4], a[4], mh[8];
-    const double sd = q.ir0 / d;
+    const double sd = q.ir0 * id;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         double dw = sgn > 0.0 ? w0[k] - wc[k] : wc[k] - w0[k];
         b[k] = dw * sd;
     }
     msolve(q.U0, q.V0, q.lam0, q.hl0, b, a);
-    mom_u_half(q.U0, q.lam0, q.hl0, sgn, mh);
-    pmom<1, 0>(mh, q.mv, q.mx, a, q2);
-    pmom<2, 0>(mh, q.mv, q.mx, a, f2);
+    mom_u_half<false>(q.U0, q.lam0, q.hl0, sgn, mh);
+    const VX x = vx_coef<0>(q.mv, q.mx, a);
+    vx_apply<1>(mh, x, q2);
+    vx_apply<2>(mh, x, f2);
 }
 // The rest, from the summed side moments acc, the summed half-space q2 and
 // f2, and the sum of the two sides' tangential slopes: the abar_t term,
@@ -512,21 +646,24 @@ __device__ __forceinline__ void gks_finish(const GksEq &q, const double *acc, do
 #pragma unroll
     for (int k = 0; k < 4; k++) b[k] = 0.5 * gt_sum[k] * q.ir0;
     msolve(q.U0, q.V0, q.lam0, q.hl0, b, a);
-    pmom<0, 1>(mf, q.mv, q.mx, a, t);
+    {
+        const VX x = vx_coef<1>(q.mv, q.mx, a);
+        vx_apply<0>(mf, x, t);
 #pragma unroll
-    for (int k = 0; k < 4; k++) q2[k] = q.r0 * (q2[k] + t[k]);
-    pmom<1, 1>(mf, q.mv, q.mx, a, t);
+        for (int k = 0; k < 4; k++) q2[k] = q.r0 * (q2[k] + t[k]);
+        vx_apply<1>(mf, x, t);
 #pragma unroll
-    for (int k = 0; k < 4; k++) f2[k] += t[k];
+        for (int k = 0; k < 4; k++) f2[k] += t[k];
+    }
     // Eq.12 -> Abar
-    const double iden = 1.0 / (q.r0 * (0.5 * dt * dt - q.T3));
+    const double iden = frcp(q.r0 * (0.5 * dt * dt - q.T3));
 #pragma unroll
     for (int k = 0; k < 4; k++) b[k] = (q.T2 * q2[k] + q.T5 * q5[k] + q.T6 * q6[k]) * iden;
     msolve(q.U0, q.V0, q.lam0, q.hl0, b, a);
     // Eq.14
     double e1[4];
     pmom1<1>(mf, q.mv, q.mx, e1);
-    pmom<1, 0>(mf, q.mv, q.mx, a, t);
+    vx_apply<1>(mf, vx_coef<0>(q.mv, q.mx, a), t);
 #pragma unroll
     for (int k = 0; k < 4; k++)
         F[k] = q.T1 * q.r0 * e1[k] + q.T2 * q.r0 * f2[k] + q.T3 * q.r0 * t[k] + q.T4 * f4[k] + q.T5 * f5[k] +
@@ -579,8 +716,10 @@ __global__ void k_reset(Params<T> P, int mode, int inst)
 
 // Per cell: Eq.21 spectral radius and the Eq.23 time step, least-squares
 // gradients (Eq.6-7, ghost cells included), the Eq.9-10 limiter,
-// vorticity and the laminar viscosity.
-template <typename T>
+// vorticity and the laminar viscosity.  LIM: the limiter is on (a
+// template parameter, so that the kernel without it needs fewer registers
+// and holds more waves in flight).
+template <typename T, bool LIM>
 __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
 {
     const int N = P.nc;
@@ -589,10 +728,10 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
     double w[5];
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
-    double r = w[0], U = w[1] / r, V = w[2] / r;
-    double lam = lam_of(w);
-    double cs = sqrt(GAMMA / (2.0 * lam));
-    P.nu[c] = mu_lam(P.mu_law, ip, lam) / r;
+    const double r = w[0], ir = frcp(r), U = w[1] * ir, V = w[2] * ir;
+    const double hl = half_inv_lam(w, ir), c2 = GAMMA * hl;   // c^2 = gamma / (2 lambda)
+    const double cs = c2 * frsq(c2);
+    P.nu[c] = mu_hl(P.mu_law, ip, hl) * ir;
     double lc = 0.0, b1[4] = {0, 0, 0, 0}, b2[4] = {0, 0, 0, 0}, wmax[4], wmin[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) wmax[k] = wmin[k] = w[k];
@@ -635,17 +774,17 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
         gx[k] = L11 * b1[k] + L12 * b2[k];
         gy[k] = L12 * b1[k] + L22 * b2[k];
     }
-    double dUdy = (gy[1] - U * gy[0]) / r;
-    double dVdx = (gx[2] - V * gx[0]) / r;
+    double dUdy = (gy[1] - U * gy[0]) * ir;
+    double dVdx = (gx[2] - V * gx[0]) * ir;
     P.vort[c] = fabs(dVdx - dUdy);
-    if (P.limiter && P.is[inst].phi_frozen) {
+    if (LIM && P.is[inst].phi_frozen) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const double phi = P.phi[k * N + c];
             gx[k] *= phi;
             gy[k] *= phi;
         }
-    } else if (P.limiter) {
+    } else if (LIM) {
         const int NB = P.nb;
         double nmax[4], nmin[4];
 #pragma unroll
@@ -679,10 +818,10 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
         P.grad[k * N + c] = gx[k];
         P.grad[(4 + k) * N + c] = gy[k];
     }
-    return P.cfl_flux * P.area[c] / lc;
+    return P.cfl_flux * P.area[c] * frcp(lc);
 }
 
-template <typename T, bool ONE>
+template <typename T, bool ONE, bool LIM>
 __global__ __launch_bounds__(256) void k_prep(Params<T> P)
 {
     int c = xcd_block() * blockDim.x + threadIdx.x;
@@ -690,7 +829,7 @@ __global__ __launch_bounds__(256) void k_prep(Params<T> P)
     double dt = INFINITY;
     if (c < P.nc) {
         inst = live_inst<ONE>(P, P.cinst, c);
-        if (inst >= 0) dt = prep_cell(P, c, inst);
+        if (inst >= 0) dt = prep_cell<T, LIM>(P, c, inst);
     }
     slot_update<true>(P.slot, SL_DTMIN, inst, dt);   // Eq.23: minimum over the instance's cells
 }
@@ -706,9 +845,11 @@ __device__ __forceinline__ double instance_dt(const unsigned long long *slot, in
     return inst >= 0 ? slots_min_serial(slot, inst, SL_DTMIN) : 0.0;
 }
 
+// rho > 0 and rho E - |rho U|^2 / (2 rho) > 0, the second tested as
+// 2 rho (rho E) - |rho U|^2 > 0 (no divide)
 __device__ __forceinline__ bool physical(const double *w)
 {
-    return w[0] > 0.0 && (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]) > 0.0;
+    return w[0] > 0.0 && 2.0 * w[0] * w[3] - (w[1] * w[1] + w[2] * w[2]) > 0.0;
 }
 
 // One side of a face (side 0: the owner cell; side 1: the neighbour, or on
@@ -720,7 +861,7 @@ __device__ __forceinline__ bool physical(const double *w)
 struct FaceSide {
     double fw[4], gn[4], gt[4], fwc[4];
     double nut;               // nu~ of the cell-centre state
-    double d;                 // centroid-face distance (d_l or d_r)
+    double id;                // 1 / centroid-face distance (d_l or d_r)
     double ls, evr, nu, q;    // |V.n| + c, (mu + mu_t)/rho, nu, V.n
 };
 template <typename T>
@@ -749,7 +890,7 @@ __device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &i
 #pragma unroll
         for (int k = 0; k < 4; k++) { WM[k] = wm[k]; gx[k] = gy[k] = 0.0; }
     }
-    o.d = side ? P.fdr[f] : P.fdl[f];   // fdr = fdl on a boundary face
+    o.id = side ? P.fidr[f] : P.fidl[f];   // fidr = fidl on a boundary face
     const bool ghost_side = bnd && side == 1;
     const int bc = bnd ? P.fbc[f] : 0;
     // a moving wall is evaluated in its own frame from the owner's data, and
@@ -782,13 +923,13 @@ __device__ __forceinline__ void face_side(const Params<T> &P, const InstParam &i
         if (!moving) rot(wm, o.fwc);
     }
     {
-        const double irm = 1.0 / wm[0];
+        const double irm = frcp(wm[0]);
         o.q = (wm[1] * nx + wm[2] * ny) * irm;
-        const double lm = lam_of(wm);
-        o.ls = fabs(o.q) + sqrt(GAMMA / (2.0 * lm));
-        const double mu = mu_lam(P.mu_law, ip, lm);
+        const double hm = half_inv_lam(wm, irm), c2 = GAMMA * hm;   // c^2 = gamma / (2 lambda)
+        o.ls = fabs(o.q) + c2 * frsq(c2);
+        const double mu = mu_hl(P.mu_law, ip, hm);
         double ev = mu;
-        if (ip.sa && wm[4] > 0) ev += wm[0] * wm[4] * sa_fv1(wm[4] * wm[0] / mu);
+        if (ip.sa && wm[4] > 0) ev += wm[0] * wm[4] * sa_fv1_f(wm[4] * wm[0] * frcp(mu));
         o.evr = ev * irm;
         o.nu = mu * irm;
         o.nut = wm[4];
@@ -850,16 +991,16 @@ __device__ __forceinline__ FaceTerms face_implicit_terms(const Params<T> &P, con
                                                          double lsr, double evl, double evr, double nul, double nur,
                                                          double ti, double tj, double ql, double qr)
 {
-    const double rn = P.frn[f], S = P.flen[f];
+    const double irn = P.firn[f], S = P.flen[f];
     FaceTerms o{fmax(lsl, lsr), 0.0, 0.0, 0.0};
-    if (P.visc_sr) o.lam += (evl + evr) / rn;
+    if (P.visc_sr) o.lam += (evl + evr) * irn;
     if (ip.sa) {
-        double g = (tj - ti) / rn;
+        double g = (tj - ti) * irn;
         double Finv = 0.5 * (ql + fabs(ql)) * ti + 0.5 * (qr - fabs(qr)) * tj;
         double kf = (0.5 / SA_SIGMA) * ((nul + nur) + (1.0 + SA_CB2) * (ti + tj));
         o.saf = (kf * g - Finv) * S;
         o.sag = g * S;
-        o.sak = kf * S / rn;
+        o.sak = kf * S * irn;
     }
     return o;
 }
@@ -890,7 +1031,7 @@ __device__ __forceinline__ void store_terms(const Params<T> &P, const InstParam 
 // face-frame flux integrated over [0, dt] -> F S / dt in the global frame
 __device__ __forceinline__ void flux_global(const double *Fr, double dt, double nx, double ny, double S, double *g)
 {
-    const double tx = -ny, ty = nx, idt = 1.0 / dt;
+    const double tx = -ny, ty = nx, idt = frcp(dt);
     const double Fn = Fr[1] * idt, Ft = Fr[2] * idt;
     g[0] = Fr[0] * idt * S;
     g[1] = (Fn * nx + Ft * tx) * S;
@@ -925,8 +1066,8 @@ __device__ __forceinline__ void flux_face(const Params<T> &P, int f, int inst, d
     GksEq q;
     gks_eq(P, ip, acc, dt, nutf, jump, q);
     double q2[4], f2[4], q2r[4], f2r[4], gts[4];
-    gks_half(q, 1.0, acc, L.fwc, L.d, q2, f2);
-    gks_half(q, -1.0, acc, R.fwc, R.d, q2r, f2r);
+    gks_half(q, 1.0, acc, L.fwc, L.id, q2, f2);
+    gks_half(q, -1.0, acc, R.fwc, R.id, q2r, f2r);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         q2[k] = add_sides(q2[k], q2r[k]);
@@ -981,7 +1122,7 @@ __device__ __forceinline__ void flux_face_pair(const Params<T> &P, int f, int si
     GksEq q;
     gks_eq(P, ip, acc, dt, nutf, jump, q);
     double q2[4], f2[4], gts[4];
-    gks_half(q, sgn, acc, M.fwc, M.d, q2, f2);
+    gks_half(q, sgn, acc, M.fwc, M.id, q2, f2);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         q2[k] = add_sides(q2[k], pair_other(q2[k]));
@@ -1043,7 +1184,7 @@ __device__ __forceinline__ void wall_face_terms(const Params<T> &P, const InstPa
     if (ip.tw > 0.0) {
         const double lc = lam_of(w);
         const double kappa = mu_lam(P.mu_law, ip, lc) * (GAMMA / (GAMMA - 1.0));
-        g[3] += kappa * (0.5 / lc - ip.tw) / P.fdl[f] * P.flen[f];
+        g[3] += kappa * (0.5 / lc - ip.tw) * P.fidl[f] * P.flen[f];
     }
 }
 
@@ -1725,7 +1866,14 @@ template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int
 
 template <typename T> void launch_prep(const Launch &L, const Params<T> &P)
 {
-    LAUNCH_ONE(k_prep, T, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), P);
+    const dim3 g(nblk(P.nc, L.block[0])), b(L.block[0]);
+    if (P.limiter) {
+        if (P.ninst == 1) hipLaunchKernelGGL((k_prep<T, true, true>), g, b, 0, L.s, P);
+        else hipLaunchKernelGGL((k_prep<T, false, true>), g, b, 0, L.s, P);
+    } else {
+        if (P.ninst == 1) hipLaunchKernelGGL((k_prep<T, true, false>), g, b, 0, L.s, P);
+        else hipLaunchKernelGGL((k_prep<T, false, false>), g, b, 0, L.s, P);
+    }
 }
 template <typename T> void launch_explicit(const Launch &L, const Params<T> &P)
 {
