@@ -716,10 +716,8 @@ __global__ void k_reset(Params<T> P, int mode, int inst)
 
 // Per cell: Eq.21 spectral radius and the Eq.23 time step, least-squares
 // gradients (Eq.6-7, ghost cells included), the Eq.9-10 limiter,
-// vorticity and the laminar viscosity.  LIM: the limiter is on (a
-// template parameter, so that the kernel without it needs fewer registers
-// and holds more waves in flight).
-template <typename T, bool LIM>
+// vorticity and the laminar viscosity.
+template <typename T>
 __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
 {
     const int N = P.nc;
@@ -728,10 +726,10 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
     double w[5];
 #pragma unroll
     for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
-    const double r = w[0], ir = frcp(r), U = w[1] * ir, V = w[2] * ir;
-    const double hl = half_inv_lam(w, ir), c2 = GAMMA * hl;   // c^2 = gamma / (2 lambda)
-    const double cs = c2 * frsq(c2);
-    P.nu[c] = mu_hl(P.mu_law, ip, hl) * ir;
+    double r = w[0], U = w[1] / r, V = w[2] / r;
+    double lam = lam_of(w);
+    double cs = sqrt(GAMMA / (2.0 * lam));
+    P.nu[c] = mu_lam(P.mu_law, ip, lam) / r;
     double lc = 0.0, b1[4] = {0, 0, 0, 0}, b2[4] = {0, 0, 0, 0}, wmax[4], wmin[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) wmax[k] = wmin[k] = w[k];
@@ -774,17 +772,17 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
         gx[k] = L11 * b1[k] + L12 * b2[k];
         gy[k] = L12 * b1[k] + L22 * b2[k];
     }
-    double dUdy = (gy[1] - U * gy[0]) * ir;
-    double dVdx = (gx[2] - V * gx[0]) * ir;
+    double dUdy = (gy[1] - U * gy[0]) / r;
+    double dVdx = (gx[2] - V * gx[0]) / r;
     P.vort[c] = fabs(dVdx - dUdy);
-    if (LIM && P.is[inst].phi_frozen) {
+    if (P.limiter && P.is[inst].phi_frozen) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const double phi = P.phi[k * N + c];
             gx[k] *= phi;
             gy[k] *= phi;
         }
-    } else if (LIM) {
+    } else if (P.limiter) {
         const int NB = P.nb;
         double nmax[4], nmin[4];
 #pragma unroll
@@ -818,10 +816,10 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
         P.grad[k * N + c] = gx[k];
         P.grad[(4 + k) * N + c] = gy[k];
     }
-    return P.cfl_flux * P.area[c] * frcp(lc);
+    return P.cfl_flux * P.area[c] / lc;
 }
 
-template <typename T, bool ONE, bool LIM>
+template <typename T, bool ONE>
 __global__ __launch_bounds__(256) void k_prep(Params<T> P)
 {
     int c = xcd_block() * blockDim.x + threadIdx.x;
@@ -829,7 +827,7 @@ __global__ __launch_bounds__(256) void k_prep(Params<T> P)
     double dt = INFINITY;
     if (c < P.nc) {
         inst = live_inst<ONE>(P, P.cinst, c);
-        if (inst >= 0) dt = prep_cell<T, LIM>(P, c, inst);
+        if (inst >= 0) dt = prep_cell(P, c, inst);
     }
     slot_update<true>(P.slot, SL_DTMIN, inst, dt);   // Eq.23: minimum over the instance's cells
 }
@@ -1866,14 +1864,7 @@ template <typename T> void launch_reset(const Launch &L, const Params<T> &P, int
 
 template <typename T> void launch_prep(const Launch &L, const Params<T> &P)
 {
-    const dim3 g(nblk(P.nc, L.block[0])), b(L.block[0]);
-    if (P.limiter) {
-        if (P.ninst == 1) hipLaunchKernelGGL((k_prep<T, true, true>), g, b, 0, L.s, P);
-        else hipLaunchKernelGGL((k_prep<T, false, true>), g, b, 0, L.s, P);
-    } else {
-        if (P.ninst == 1) hipLaunchKernelGGL((k_prep<T, true, false>), g, b, 0, L.s, P);
-        else hipLaunchKernelGGL((k_prep<T, false, false>), g, b, 0, L.s, P);
-    }
+    LAUNCH_ONE(k_prep, T, dim3(nblk(P.nc, L.block[0])), dim3(L.block[0]), P);
 }
 template <typename T> void launch_explicit(const Launch &L, const Params<T> &P)
 {
