@@ -121,6 +121,11 @@ struct Params {
     // per-instance cell lists (internal ids, ascending) for the norms
     const int *icell, *ioff;
     const int *ipos;           // position of each cell in icell
+    // processing order of the cell kernels k_prep and k_gather: cells grouped
+    // in spatial tiles, each tile's wavefronts one after another, so that a
+    // cell and its neighbours (which lie in other wavefronts) are read by the
+    // same XCD close together in time
+    const int *cperm;
     double *ipart;             // ninst x rb x 2 partial sums
     int rb;                    // partial sums per instance: slices of NORM_SLICE squares
     double *hist;              // HIST_W x ninst x hist_cap

@@ -52,7 +52,7 @@ struct Global {
     std::vector<int> bl_off, bl_lo, bl_hi;
     std::vector<int> coff;           // first global upload id of each instance
     std::vector<int> g2i;            // global upload id -> internal cell
-    std::vector<int> cinst, finst, icell, ioff, ipos;
+    std::vector<int> cinst, finst, icell, ioff, ipos, cperm;
     std::vector<double> xc, yc, area, lsinv, vtx;
     std::vector<int> cf_face, cf_nbr, cf_flag;   // MAXV entries per block
     std::vector<double> cf_dx, cf_dy;
@@ -73,7 +73,7 @@ constexpr int NKT = 6;
 struct WsMap {
     Buf ip, is, slot, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, dW1, xc, yc, area, lsinv, dwall, vtx, phi;
     Buf cinst, finst, icell, ioff, g2i, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
-    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fidl, fidr, firn, ipart, hist, ipos;
+    Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fidl, fidr, firn, ipart, hist, ipos, cperm;
     Buf frec, flam, fsak, enx, eny, es;
     Buf wall_faces, wall_out, woff, wseg, lev_off, bl_off, bl_lo, bl_hi, stage, backup;
     size_t total;
@@ -362,6 +362,57 @@ int build_instance(igks_ctx *ctx, int n_nodes, const double *xy, int n_cells, co
 // Concatenate the instances in the internal order: cells by (wavefront,
 // instance, upload index); interior faces by internal owner, then boundary
 // faces by internal owner.
+// Processing order of the cell kernels (Global::cperm): per instance, its
+// cells ranked along a Morton curve of their centroids and cut into tiles
+// of TILE_CELLS; each tile's cells by wavefront, then internal index.  In a
+// colour order every neighbour of a cell lies in another wavefront; the
+// internal order keeps the wavefronts apart, while this order puts a tile's
+// wavefronts one after another, so a cell and its neighbours are read by
+// the same XCD (the launch gives each XCD a contiguous range of it) close
+// together in time.
+#ifndef IGKS_TILE_CELLS
+#define IGKS_TILE_CELLS 4096
+#endif
+constexpr int TILE_CELLS = IGKS_TILE_CELLS;
+void cell_tiles(Global &G, int ni)
+{
+    const int N = G.N;
+    std::vector<uint32_t> key(N);
+    std::vector<int> lev(N);
+    for (int l = 0; l < G.nlev; l++)
+        for (int c = G.lev_off[l]; c < G.lev_off[l + 1]; c++) lev[c] = l;
+    G.cperm.clear();
+    G.cperm.reserve(N);
+    for (int i = 0; i < ni; i++) {
+        const int *cells = G.icell.data() + G.ioff[i];
+        const int n = G.ioff[i + 1] - G.ioff[i];
+        double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+        for (int k = 0; k < n; k++) {
+            const int c = cells[k];
+            x0 = std::min(x0, G.xc[c]); x1 = std::max(x1, G.xc[c]);
+            y0 = std::min(y0, G.yc[c]); y1 = std::max(y1, G.yc[c]);
+        }
+        const double sx = 65535.0 / std::max(x1 - x0, 1e-300), sy = 65535.0 / std::max(y1 - y0, 1e-300);
+        auto spread = [](uint32_t v) {   // the 16 bits of v to the even bit positions
+            v &= 0xffffu;
+            v = (v | (v << 8)) & 0x00ff00ffu;
+            v = (v | (v << 4)) & 0x0f0f0f0fu;
+            v = (v | (v << 2)) & 0x33333333u;
+            return (v | (v << 1)) & 0x55555555u;
+        };
+        std::vector<int> r(cells, cells + n);
+        for (int c : r)
+            key[c] = spread((uint32_t)((G.xc[c] - x0) * sx)) | (spread((uint32_t)((G.yc[c] - y0) * sy)) << 1);
+        std::stable_sort(r.begin(), r.end(), [&](int a, int b) { return key[a] < key[b]; });
+        for (int t0 = 0; t0 < n; t0 += TILE_CELLS) {
+            const int t1 = std::min(n, t0 + TILE_CELLS);
+            std::sort(r.begin() + t0, r.begin() + t1,
+                      [&](int a, int b) { return lev[a] != lev[b] ? lev[a] < lev[b] : a < b; });
+        }
+        G.cperm.insert(G.cperm.end(), r.begin(), r.end());
+    }
+}
+
 int combine(igks_ctx *ctx)
 {
     Global &G = ctx->g;
@@ -566,6 +617,7 @@ int combine(igks_ctx *ctx)
             G.vtx[(2 * sv + 1) * (size_t)NB + b] = m.xy[2 * node + 1] - m.yc[u];
         }
     }
+    cell_tiles(G, ni);
     ctx->combined = true;
     return IGKS_OK;
 }
@@ -614,6 +666,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.enx = L.add(E * D); w.eny = L.add(E * D); w.es = L.add(E * D);
     w.ipart = L.add(2 * NI * (size_t)norm_rb(G) * D);
     w.ipos = L.add(N * I);
+    w.cperm = L.add(N * I);
     w.hist = L.add((size_t)HIST_W * NI * hist_cap * D);
     w.wall_faces = L.add(NW * I);
     w.wall_out = L.add(4 * NW * D);
@@ -660,7 +713,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.fidl = D(w.fidl); P.fidr = D(w.fidr); P.firn = D(w.firn);
     P.frec = D(w.frec); P.flam = D(w.flam); P.fsak = D(w.fsak);
     P.enx = D(w.enx); P.eny = D(w.eny); P.es = D(w.es);
-    P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipos = In(w.ipos); P.ipart = D(w.ipart); P.rb = norm_rb(c->g);
+    P.icell = In(w.icell); P.ioff = In(w.ioff); P.ipos = In(w.ipos); P.cperm = In(w.cperm); P.ipart = D(w.ipart); P.rb = norm_rb(c->g);
     P.hist = D(w.hist); P.hist_cap = c->hist_cap;
 }
 
@@ -1177,6 +1230,7 @@ int igks_bind_workspace(igks_ctx *c, void *dptr, size_t bytes)
     rc |= up(w.cinst, G.cinst.data(), N * I); rc |= up(w.finst, G.finst.data(), F * I);
     rc |= up(w.icell, G.icell.data(), N * I); rc |= up(w.ioff, G.ioff.data(), G.ioff.size() * I);
     rc |= up(w.ipos, G.ipos.data(), N * I);
+    rc |= up(w.cperm, G.cperm.data(), N * I);
     rc |= up(w.g2i, G.g2i.data(), N * I);
     rc |= up(w.cf_face, G.cf_face.data(), E * I);
     rc |= up(w.cf_nbr, G.cf_nbr.data(), E * I); rc |= up(w.cf_flag, G.cf_flag.data(), E * I);

@@ -822,7 +822,8 @@ __device__ __forceinline__ double prep_cell(const Params<T> &P, int c, int inst)
 template <typename T, bool ONE>
 __global__ __launch_bounds__(256) void k_prep(Params<T> P)
 {
-    int c = xcd_block() * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
+    const int c = t < P.nc ? P.cperm[t] : P.nc;
     int inst = -1;
     double dt = INFINITY;
     if (c < P.nc) {
@@ -1248,7 +1249,8 @@ __device__ __forceinline__ double gather_cell(const Params<T> &P, int c, int ins
 template <typename T, bool ONE>
 __global__ __launch_bounds__(256) void k_gather(Params<T> P)
 {
-    int c = xcd_block() * blockDim.x + threadIdx.x;
+    const int t = xcd_block() * blockDim.x + threadIdx.x;
+    const int c = t < P.nc ? P.cperm[t] : P.nc;
     int inst = -1;
     double rinf = 0.0;
     if (c < P.nc) {
