@@ -338,13 +338,28 @@ def roofline_of(args, solver, kt, kb, out, mixed):
     return r
 
 
-def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=10.0, chunk=100):
-    """Iterations and seconds from the impulsive start to a density-residual
-    drop of `target` on the laminar flat plate (64x32, natural order);
-    scheme 1: the explicit scheme (Eq.15, local steps at a fixed CFL)."""
-    import torch
+# sweep blocks (cells, coupled_blocks) of the small time-to-solution workloads:
+# the smallest that kept the iteration count (block sizes of 64-1024
+# measured on each; a wave sweeps each block, all blocks at once)
+SMALL_BLOCKS = 128
+
+
+def plate_mesh(mg, blocks):
+    """The 64x32 plate in natural order (blocks None) or renumbered block by
+    block: (mesh, sweep block of each cell or None)."""
     m = mg.flat_plate()
-    s = igks.Solver(m, precision=precision, cfl_init=cfl, chunk=chunk, scheme=scheme)
+    return (m, None) if blocks is None else mg.block_order(m, blocks, "coupled")
+
+
+def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=10.0, chunk=100,
+                 blocks=SMALL_BLOCKS):
+    """Iterations and seconds from the impulsive start to a density-residual
+    drop of `target` on the laminar flat plate (64x32) with sweep blocks of
+    `blocks` cells (None: natural order, one workgroup per sweep); scheme 1:
+    the explicit scheme (Eq.15, local steps at a fixed CFL)."""
+    import torch
+    m, blk = plate_mesh(mg, blocks if scheme == 0 else None)
+    s = igks.Solver(m, precision=precision, cfl_init=cfl, chunk=chunk, scheme=scheme, sweep_blocks=blk)
     s.set_freestream(*WORKLOADS["plate64x32"]["flow"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -362,7 +377,9 @@ def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=
     wl = s.wall_loads()
     say(f"plate to {target:g} (scheme {scheme}, precision {precision}): {it} iterations, {dt:.1f}s")
     return dict(iterations=it, seconds=round(dt, 4), drop=s.residual()["res_drop"], cd=wl["cd"],
-                cell_updates_per_s=m.n_cells * it / dt)
+                cell_updates_per_s=m.n_cells * it / dt, ms_per_iteration=round(1e3 * dt / it, 4),
+                schedule=("explicit" if scheme else
+                          f"sweep blocks of {blocks} cells" if blocks else "natural order, one workgroup per sweep"))
 
 
 def run_to_drop(igks, mesh, flow, precision, blocks=None, target=1e-10, max_it=40000, chunk=200, scheme=0,
@@ -492,13 +509,16 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
                 fp64_alone_seconds_total=round(sum(v["seconds"] for v in seq.values()), 4))
 
 
-def time_to_converge_cavity(igks, mg, max_it=20000, chunk=200, label="cavity"):
+def time_to_converge_cavity(igks, mg, max_it=30000, chunk=200, label="cavity", blocks=SMALL_BLOCKS):
     """The lid-driven cavity (100x100, Re 1000, Ma 0.1 sqrt 3, isothermal
-    walls) from rest, implicit CFL 1000 growing by Eq.25, to the paper's
-    criterion Eq.40 <= 3e-8."""
+    walls) from rest, implicit CFL 1000 growing by Eq.25, sweep blocks of
+    `blocks` cells (None: natural order), to the paper's criterion Eq.40 <=
+    3e-8."""
     import torch
-    m = mg.cavity(100)
-    s = igks.Solver(m, cfl_init=1000.0, chunk=chunk, wall_temp=1.0)
+    m, blk = mg.cavity(100), None
+    if blocks:
+        m, blk = mg.block_order(m, blocks, "coupled")
+    s = igks.Solver(m, cfl_init=1000.0, chunk=chunk, wall_temp=1.0, sweep_blocks=blk)
     s.set_freestream(0.1 * math.sqrt(3.0), 0.0, 1000.0)
     W = s.get_state()
     W[3] -= 0.5 * (W[1] ** 2 + W[2] ** 2) / W[0]
@@ -518,19 +538,25 @@ def time_to_converge_cavity(igks, mg, max_it=20000, chunk=200, label="cavity"):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     r = s.residual()
+    say(f"{label}: {it} iterations, {dt:.1f}s")
     return dict(workload="cavity100: 100x100 uniform, Re 1000, Ma 0.1 sqrt(3), isothermal walls, from rest",
+                schedule=f"sweep blocks of {blocks} cells" if blocks else "natural order, one workgroup per sweep",
                 criterion="Eq.40 <= 3e-8", iterations=it, seconds=round(dt, 4), eq40=r["eq40"],
                 drop=r["res_drop"], cfl=r["cfl"], ms_per_iteration=round(1e3 * dt / it, 4),
                 paper_iterations=4430, paper_seconds=543.2)
 
 
-def time_to_converge_turbulent_plate(igks, mg, max_it=30000, chunk=500, label="turbulent plate"):
+def time_to_converge_turbulent_plate(igks, mg, max_it=30000, chunk=500, label="turbulent plate",
+                                     blocks=SMALL_BLOCKS):
     """The turbulent flat plate (SA, Ma 0.2, Re 5e6 per unit length, 7680
-    cells, natural order) from the free stream at CFL 10 growing by Eq.25,
-    to the paper's criterion Eq.40 <= 3e-8."""
+    cells, sweep blocks of `blocks` cells, None: natural order) from the free
+    stream at CFL 10 growing by Eq.25, to the paper's criterion Eq.40 <=
+    3e-8."""
     import torch
-    m = mg.turbulent_plate()
-    s = igks.Solver(m, cfl_init=10.0, chunk=chunk)
+    m, blk = mg.turbulent_plate(), None
+    if blocks:
+        m, blk = mg.block_order(m, blocks, "coupled")
+    s = igks.Solver(m, cfl_init=10.0, chunk=chunk, sweep_blocks=blk)
     s.set_freestream(0.2, 0.0, 5e6, 3.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -546,19 +572,23 @@ def time_to_converge_turbulent_plate(igks, mg, max_it=30000, chunk=500, label="t
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     r = s.residual()
+    say(f"{label}: {it} iterations, {dt:.1f}s")
     return dict(workload="turbulent flat plate: 120x64 quads, y+ ~ 1, Ma 0.2, Re 5e6/unit length, SA, from the free stream",
+                schedule=f"sweep blocks of {blocks} cells" if blocks else "natural order, one workgroup per sweep",
                 criterion="Eq.40 <= 3e-8", iterations=it, seconds=round(dt, 4), eq40=r["eq40"],
                 drop=r["res_drop"], cd=s.wall_loads()["cd"], ms_per_iteration=round(1e3 * dt / it, 4),
                 paper_iterations=5340, paper_seconds=1087.7)
 
 
-def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000):
-    """Eight plate flow conditions (DROP_BATCH) to a `target` drop: one mixed-
-    precision batch against the eight FP64 single runs one after another."""
+def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000, blocks=SMALL_BLOCKS):
+    """Eight plate flow conditions (DROP_BATCH) to a `target` drop with sweep
+    blocks of `blocks` cells: one mixed-precision batch against the eight
+    FP64 single runs one after another."""
     import torch
-    m = mg.flat_plate()
+    m, blk = plate_mesh(mg, blocks)
     flows = [(ma, 0.0, re, -1.0) for ma, re in DROP_BATCH]
-    b = igks.BatchSolver([m] * len(flows), precision=igks.IGKS_MIXED, cfl_init=10.0, chunk=100)
+    b = igks.BatchSolver([m] * len(flows), precision=igks.IGKS_MIXED, cfl_init=10.0, chunk=100,
+                         sweep_blocks=None if blk is None else [blk] * len(flows))
     for i, f in enumerate(flows):
         b.set_freestream(i, *f)
     torch.cuda.synchronize()
@@ -576,7 +606,7 @@ def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000):
     t_batch = time.perf_counter() - t0
     t_seq, its_seq = 0.0, []
     for f in flows:
-        s = igks.Solver(m, precision=igks.IGKS_FP64, cfl_init=10.0, chunk=100)
+        s = igks.Solver(m, precision=igks.IGKS_FP64, cfl_init=10.0, chunk=100, sweep_blocks=blk)
         s.set_freestream(*f)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -590,7 +620,7 @@ def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000):
         t_seq += time.perf_counter() - t0
         its_seq.append(k)
         say(f"plate {f[:3]} alone: {k} iterations")
-    return dict(instances=len(flows), flows_ma_re=DROP_BATCH, batch_mixed_seconds=round(t_batch, 4),
+    return dict(instances=len(flows), flows_ma_re=DROP_BATCH, sweep_blocks=blocks, batch_mixed_seconds=round(t_batch, 4),
                 batch_iterations_to_target=first, fp64_sequential_seconds=round(t_seq, 4),
                 fp64_iterations_to_target=its_seq, speedup=round(t_seq / t_batch, 3))
 
@@ -731,9 +761,11 @@ def main():
             del bm
             torch.cuda.empty_cache()
     if not args.no_drop:
-        out["time_to_1e-10"] = {"workload": "plate64x32 (natural order), Ma 0.3 Re_L 1e4, CFL 10 -> Eq.25",
+        out["time_to_1e-10"] = {"workload": f"plate64x32, Ma 0.3 Re_L 1e4, CFL 10 -> Eq.25, sweep blocks of "
+                                            f"{SMALL_BLOCKS} cells (coupled_blocks, generation order inside)",
                                 "fp64": time_to_drop(igks, mg, igks.IGKS_FP64),
                                 "mixed": time_to_drop(igks, mg, igks.IGKS_MIXED),
+                                "fp64_natural_order": time_to_drop(igks, mg, igks.IGKS_FP64, blocks=None),
                                 "batched_plates": time_to_drop_batch(igks, mg),
                                 "explicit_fp64_cfl0.9": time_to_drop(igks, mg, igks.IGKS_FP64, scheme=1, cfl=0.9,
                                                                      chunk=1000, max_it=400000)}

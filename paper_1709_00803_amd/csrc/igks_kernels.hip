@@ -1618,10 +1618,15 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
     if (MODE == SW_FWD || MODE == SW_TOP) {
 #pragma unroll
         for (int k = 0; k < 5; k++) acc[k] = T(P.M[k * N + c]);
+        // lower neighbours of the cell's block; with two block passes, the
+        // second also takes every neighbour in another block, with the first
+        // pass's increment
         auto lower = [&](int f, int e, int j, int fl) {
 #pragma unroll
             for (int m = 0; m < 5; m++) t[m] = T(0);
-            if ((fl & CF_VALID) && j >= 0 && (fl & CF_LOWER)) sweep_term(P, ip, W, w, f, e, j, dws, cfl, lev1, t, P.dW);
+            const bool cross = (fl & CF_OTHER) && P.dWx;
+            if ((fl & CF_VALID) && j >= 0 && ((fl & CF_LOWER) || cross))
+                sweep_term(P, ip, W, w, f, e, j, dws, cfl, cross ? 0 : lev1, t, cross ? P.dWx : P.dW);
 #pragma unroll
             for (int m = 0; m < 4; m++) acc[m] = quad_fold<true>(acc[m], t[m]);
             acc[4] = quad_fold<false>(acc[4], t[4]);
@@ -1667,6 +1672,7 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
     d[4] = ip.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
 #pragma unroll
     for (int k = 0; k < 5; k++) P.dW[k * N + c] = d[k];
+    if (MODE == SW_BWD_ONLY) return 0.0;
     double dd[5];
 #pragma unroll
     for (int k = 0; k < 5; k++) dd[k] = double(d[k]);
@@ -1748,22 +1754,25 @@ __global__ __launch_bounds__(512) void k_sweep_wg(Params<T> P, const int *lev_of
 }
 
 // The whole sweep of one sweep block per wave: the block's wavefronts one
-// after another, cells of a wavefront on the lanes.  Blocks do not couple in
-// the sweeps, so no wave waits for another; inside the one-wave workgroup
-// the barrier after each wavefront orders its dW writes before the next
-// wavefront's reads.  As in the one-workgroup sweep, the backward pass
-// leaves the update to k_update.
+// after another, each cell of a wavefront on a quad of lanes (lane q forms
+// the term of entry q, sweep_quad; 16 cells per step, and a block's
+// wavefront holds a few cells).  Blocks do not couple in the sweeps, so no
+// wave waits for another; inside the one-wave workgroup the barrier after
+// each wavefront orders its dW writes before the next wavefront's reads.
+// As in the one-workgroup sweep, the backward pass leaves the update to
+// k_update.
 template <typename T, bool FWD, bool ONE>
 __global__ __launch_bounds__(64) void k_sweep_blk(Params<T> P, const int *bl_off, const int *bl_lo, const int *bl_hi)
 {
     const int gb = blockIdx.x;
     const int k0 = bl_off[gb], k1 = bl_off[gb + 1];
+    const int q = (int)threadIdx.x & 3, cell = (int)threadIdx.x >> 2;
     for (int i = 0; i < k1 - k0; i++) {
         const int k = FWD ? k0 + i : k1 - 1 - i;
         const int c0 = bl_lo[k], c1 = bl_hi[k];
-        for (int c = c0 + (int)threadIdx.x; c < c1; c += (int)blockDim.x) {
+        for (int c = c0 + cell; c < c1; c += 16) {   // the four lanes of a quad take the same cell
             int inst;
-            (void)sweep_cell<T, FWD ? SW_FWD : SW_BWD_ONLY, ONE>(P, c, inst);
+            (void)sweep_quad<T, FWD ? SW_FWD : SW_BWD_ONLY, ONE>(P, c, q, 0, inst);
         }
         __syncthreads();
     }
