@@ -1691,6 +1691,9 @@ __global__ __launch_bounds__(64) void k_commit(Params<T> P, int it)
     if (s->halt) return;
     double e40 = wave_max(slot_lane(P.slot, i, SL_E40));
     double x = 0.0, y = 0.0;
+    // unrolled so that the loads of several slices are in flight together
+    // (the sums keep their order)
+#pragma unroll 8
     for (int k = lane; k < P.rb; k += warpSize) {
         x += P.ipart[2 * (i * P.rb + k)];
         y += P.ipart[2 * (i * P.rb + k) + 1];
