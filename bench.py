@@ -365,8 +365,11 @@ def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=
     t0 = time.perf_counter()
     it = 0
     prog = Progress(f"plate to {target:g} (scheme {scheme}, precision {precision})")
+    l2_first = None
     while it < max_it:
         s.iterate(chunk)
+        if l2_first is None:
+            l2_first = float(s.history()[0, 0])   # ||M_rho||_2 of the impulsive-start iteration
         it += chunk
         d = s.residual()["res_drop"]
         prog(it, d)
@@ -376,7 +379,8 @@ def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=
     dt = time.perf_counter() - t0
     wl = s.wall_loads()
     say(f"plate to {target:g} (scheme {scheme}, precision {precision}): {it} iterations, {dt:.1f}s")
-    return dict(iterations=it, seconds=round(dt, 4), drop=s.residual()["res_drop"], cd=wl["cd"],
+    return dict(iterations=it, seconds=round(dt, 4), drop=s.residual()["res_drop"],
+                drop_from_first=s.residual()["res_l2"] / l2_first, cd=wl["cd"],
                 cell_updates_per_s=m.n_cells * it / dt, ms_per_iteration=round(1e3 * dt / it, 4),
                 schedule=("explicit" if scheme else
                           f"sweep blocks of {blocks} cells" if blocks else "natural order, one workgroup per sweep"))
@@ -396,8 +400,11 @@ def run_to_drop(igks, mesh, flow, precision, blocks=None, target=1e-10, max_it=4
     it = 0
     marks = {}   # first checked iteration (and seconds) at drops 1e-4, 1e-6, 1e-8 and at Eq.40 <= 3e-8
     prog = Progress(label)
+    l2_first = None
     while it < max_it and time.perf_counter() - t0 < max_s:
         s.iterate(chunk)
+        if l2_first is None:
+            l2_first = float(s.history()[0, 0])   # ||M_rho||_2 of the impulsive-start iteration
         it += chunk
         r = s.residual()
         prog(it, r["res_drop"])
@@ -413,6 +420,7 @@ def run_to_drop(igks, mesh, flow, precision, blocks=None, target=1e-10, max_it=4
     wl = s.wall_loads()
     say(f"{label}: {it} iterations, {dt:.1f}s, drop {r['res_drop']:.3e}")
     return dict(iterations=it, seconds=round(dt, 4), drop=r["res_drop"], reached=r["res_drop"] <= target,
+                drop_from_first=r["res_l2"] / l2_first,
                 cl=wl["cl"], cd=wl["cd"], ms_per_iteration=round(1e3 * dt / max(it, 1), 4),
                 wavefronts=s.nlev, sweep_schedule=int(s.schedule()[4]), milestones=marks)
 
@@ -479,11 +487,14 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
     t0 = time.perf_counter()
     it, first, t_first = 0, [None] * 64, [None] * 64
     prog = Progress("batch64 blocks")
+    l2_first = None
     while time.perf_counter() - t0 < max_s and any(x is None for x in first):
         try:
             s.iterate(chunk)
         except igks.IgksError:
             pass   # an instance frozen by a rejected update; the others go on
+        if l2_first is None:
+            l2_first = [float(s.history(i)[0, 0]) for i in range(64)]
         it += chunk
         for i in range(64):
             if first[i] is None and s.residual(i)["res_drop"] <= target:
@@ -492,6 +503,7 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     drops = [s.residual(i)["res_drop"] for i in range(64)]
+    drops_first = [s.residual(i)["res_l2"] / l2_first[i] for i in range(64)]
     frozen = [i for i in range(64) if s.status(i)]
     nlev = s.nlev
     del s
@@ -504,7 +516,8 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
                          "passes, mixed, limiter held from 1e-4, CFL 10 -> Eq.25",
                 target=target, iterations=it, seconds=round(t_batch, 3), ms_per_iteration=round(1e3 * t_batch / it, 3),
                 wavefronts=nlev, reached=sum(x is not None for x in first), first_iteration_at_target=first,
-                batch_seconds_at_target=t_first, final_drop=[float(f"{d:.3e}") for d in drops], frozen=frozen,
+                batch_seconds_at_target=t_first, final_drop=[float(f"{d:.3e}") for d in drops],
+                final_drop_from_first=[float(f"{d:.3e}") for d in drops_first], frozen=frozen,
                 fp64_alone={str(i): v for i, v in seq.items()},
                 fp64_alone_seconds_total=round(sum(v["seconds"] for v in seq.values()), 4))
 
