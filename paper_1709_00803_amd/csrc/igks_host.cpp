@@ -480,7 +480,17 @@ int combine(igks_ctx *ctx)
             G.ipos[c] = k;
         }
     }
-    // faces
+    // the cell kernels' processing order (needs the centroids in internal order)
+    G.xc.resize(N); G.yc.resize(N);
+    for (int c = 0; c < N; c++) {
+        const InstMesh &m = ctx->inst[gi[order[c]]];
+        G.xc[c] = m.xc[gu[order[c]]]; G.yc[c] = m.yc[gu[order[c]]];
+    }
+    cell_tiles(G, ni);
+    std::vector<int> trank(N);   // position of each cell in that order
+    for (int k = 0; k < N; k++) trank[G.cperm[k]] = k;
+    // faces: interior faces, then boundary faces, each sorted by their owner's
+    // position in the cell kernels' order (the faces of a spatial tile together)
     struct FRef { int inst, q; };
     std::vector<FRef> all;
     for (int i = 0; i < ni; i++)
@@ -490,7 +500,7 @@ int combine(igks_ctx *ctx)
     std::stable_sort(all.begin(), all.end(), [&](const FRef &a, const FRef &b) {
         bool ba = boundary(a), bb = boundary(b);
         if (ba != bb) return bb;
-        return owner(a) < owner(b);
+        return trank[owner(a)] < trank[owner(b)];
     });
     const int F = (int)all.size();
     G.F = F;
@@ -617,7 +627,6 @@ int combine(igks_ctx *ctx)
             G.vtx[(2 * sv + 1) * (size_t)NB + b] = m.xy[2 * node + 1] - m.yc[u];
         }
     }
-    cell_tiles(G, ni);
     ctx->combined = true;
     return IGKS_OK;
 }

@@ -10,8 +10,9 @@
 // inside a kernel would write back the XCD's whole L2).
 //
 // Data are structure-of-arrays in the library's internal cell order
-// (wavefront, then instance, then upload index) and face order (owner
-// cell).  Face results go to per-face arrays and every cell sums its faces
+// (wavefront, then instance, then upload index) and face order (interior
+// faces, then boundary faces, each by their owner cell's position in the
+// spatial-tile order of the cell kernels).  Face results go to per-face arrays and every cell sums its faces
 // in a fixed order, so results are deterministic without floating-point
 // atomics; the only atomics are integer min/max on the bit patterns of
 // non-negative doubles.  Several independent instances (meshes and flow
