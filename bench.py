@@ -43,7 +43,7 @@ WORKLOADS = {
 # launch schedules (block sizes of prep, flux, gather, sweep; sweep schedule;
 # lanes per face) found by igks_autotune on these workloads; block sizes never
 # change results
-SCHEDULES = {"jouk2m": [256, 128, 64, 256, 1, 1], "batch64": [256, 256, 256, 128, 1, 1],
+SCHEDULES = {"jouk2m": [256, 64, 64, 256, 1, 1], "batch64": [256, 256, 256, 128, 1, 1],
              "jouk40k": [128, 64, 64, 64, 1, 1]}
 # plate variants of the batched time-to-1e-10 comparison: (Ma, Re_L)
 DROP_BATCH = [(0.2, 5e3), (0.25, 8e3), (0.3, 1e4), (0.35, 1.5e4), (0.4, 2e4), (0.3, 6e3), (0.2, 1.2e4), (0.4, 1e4)]
