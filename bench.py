@@ -67,6 +67,12 @@ def say(*a):
     print("#", *a, file=sys.stderr, flush=True)
 
 
+def ratio(a, b):
+    """a / b, or None when b is 0 (an impulsive start whose mass residual is
+    exactly zero)."""
+    return a / b if b else None
+
+
 class Progress:
     """A line on stderr at most every `every` seconds from a long run (the
     runs to a residual drop print nothing else for minutes)."""
@@ -380,7 +386,7 @@ def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=
     wl = s.wall_loads()
     say(f"plate to {target:g} (scheme {scheme}, precision {precision}): {it} iterations, {dt:.1f}s")
     return dict(iterations=it, seconds=round(dt, 4), drop=s.residual()["res_drop"],
-                drop_from_first=s.residual()["res_l2"] / l2_first, cd=wl["cd"],
+                drop_from_first=ratio(s.residual()["res_l2"], l2_first), cd=wl["cd"],
                 cell_updates_per_s=m.n_cells * it / dt, ms_per_iteration=round(1e3 * dt / it, 4),
                 schedule=("explicit" if scheme else
                           f"sweep blocks of {blocks} cells" if blocks else "natural order, one workgroup per sweep"))
@@ -420,7 +426,7 @@ def run_to_drop(igks, mesh, flow, precision, blocks=None, target=1e-10, max_it=4
     wl = s.wall_loads()
     say(f"{label}: {it} iterations, {dt:.1f}s, drop {r['res_drop']:.3e}")
     return dict(iterations=it, seconds=round(dt, 4), drop=r["res_drop"], reached=r["res_drop"] <= target,
-                drop_from_first=r["res_l2"] / l2_first,
+                drop_from_first=ratio(r["res_l2"], l2_first),
                 cl=wl["cl"], cd=wl["cd"], ms_per_iteration=round(1e3 * dt / max(it, 1), 4),
                 wavefronts=s.nlev, sweep_schedule=int(s.schedule()[4]), milestones=marks)
 
@@ -494,7 +500,8 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
         except igks.IgksError:
             pass   # an instance frozen by a rejected update; the others go on
         if l2_first is None:
-            l2_first = [float(s.history(i)[0, 0]) for i in range(64)]
+            hs = [s.history(i) for i in range(64)]
+            l2_first = [float(h[0, 0]) if len(h) else 0.0 for h in hs]
         it += chunk
         for i in range(64):
             if first[i] is None and s.residual(i)["res_drop"] <= target:
@@ -503,7 +510,7 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     drops = [s.residual(i)["res_drop"] for i in range(64)]
-    drops_first = [s.residual(i)["res_l2"] / l2_first[i] for i in range(64)]
+    drops_first = [ratio(s.residual(i)["res_l2"], l2_first[i]) for i in range(64)]
     frozen = [i for i in range(64) if s.status(i)]
     nlev = s.nlev
     del s
@@ -517,7 +524,7 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
                 target=target, iterations=it, seconds=round(t_batch, 3), ms_per_iteration=round(1e3 * t_batch / it, 3),
                 wavefronts=nlev, reached=sum(x is not None for x in first), first_iteration_at_target=first,
                 batch_seconds_at_target=t_first, final_drop=[float(f"{d:.3e}") for d in drops],
-                final_drop_from_first=[float(f"{d:.3e}") for d in drops_first], frozen=frozen,
+                final_drop_from_first=[None if d is None else float(f"{d:.3e}") for d in drops_first], frozen=frozen,
                 fp64_alone={str(i): v for i, v in seq.items()},
                 fp64_alone_seconds_total=round(sum(v["seconds"] for v in seq.values()), 4))
 
