@@ -722,9 +722,9 @@ def main():
     ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 and Eq.40 runs")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision and batch64 extra measurements")
     ap.add_argument("--sa250k-only", type=float, default=None, metavar="SECONDS",
-                    help="run only the 250k SA Joukowski from the free stream toward a 1e-10 drop (FP64, two-pass "
-                         "coupled blocks of 512 cells, limiter held from 1e-4) for at most SECONDS and print its "
-                         "JSON (the full default run gives it 40 s per precision)")
+                    help="run only the 250k SA Joukowski from the free stream toward a 1e-10 drop (--precision, "
+                         "default fp64; two-pass coupled blocks of 512 cells, limiter held from 1e-4) for at most "
+                         "SECONDS and print its JSON (the full default run gives it 40 s per precision)")
     ap.add_argument("--mesh-cache", default=None,
                     help="directory where generated meshes are stored and read back (the seeded generation "
                          "of the 2M-cell mesh takes about a minute)")
@@ -745,10 +745,11 @@ def main():
     if args.sa250k_only is not None:
         flow = WORKLOADS["jouk250k"]["flow"]
         mb, blk = mg.workload_blocks("jouk250k", 512)
-        r = run_to_drop(igks, mb, flow, igks.IGKS_FP64, blk, max_it=10 ** 7, chunk=1000, cfl=10.0,
-                        max_s=args.sa250k_only, limiter=1, limiter_freeze=1e-4, block_passes=2,
-                        label="jouk250k to 1e-10")
-        print(json.dumps(dict(workload="jouk250k: " + WORKLOADS["jouk250k"]["desc"], precision="fp64",
+        prec = args.precision or "fp64"
+        r = run_to_drop(igks, mb, flow, igks.IGKS_MIXED if prec == "mixed" else igks.IGKS_FP64, blk,
+                        max_it=10 ** 7, chunk=1000, cfl=10.0, max_s=args.sa250k_only, limiter=1, limiter_freeze=1e-4,
+                        block_passes=2, label=f"jouk250k to 1e-10 ({prec})")
+        print(json.dumps(dict(workload="jouk250k: " + WORKLOADS["jouk250k"]["desc"], precision=prec,
                               schedule="coupled sweep blocks of 512 cells, two passes, Eq.9 limiter held from a "
                                        "drop of 1e-4, CFL 10 -> Eq.25", target=1e-10, **r)), flush=True)
         return
