@@ -63,6 +63,8 @@ typedef struct {
                               first value, the limiter factors of Eq.9 are held at their values of
                               that iteration (0: never) */
     int tau_jump;       /* 1: add dt |p_l - p_r| / (p_l + p_r) to the collision time of Eq.34 */
+    int lusgs_op;       /* dissipation of the LU-SGS operator: 0 the scalar spectral radius of Eq.20
+                           (lambda_ij I); 1 the first-order Roe matrix |A_ij| (Eq.18) */
 } oigks_options;
 
 typedef struct {
@@ -108,6 +110,8 @@ typedef struct oigks_ctx {
     double *lamc, *vort, *dtimp;
     double *ff;                  /* 4 per face: Fbar * S, global frame, owner -> neighbour */
     double *flam;                /* per face: lambda_ij (spectral radius) */
+    double *fabsA;               /* per face (lusgs_op 1): |A_ij| + lambda_visc I, 16 values row by row */
+    double *Dm;                  /* per cell (lusgs_op 1): the 4x4 diagonal block of Eq.20 */
     double *D, *Dsa;
     double *dW;                  /* 5 per cell */
     double *Wg;                  /* 5 per face: ghost (cell-centre) state, boundary faces */
@@ -487,7 +491,7 @@ static void free_mesh(oigks_ctx *c)
     void *ps[] = {c->x, c->y, c->cptr, c->cnod, c->fL, c->fR, c->ftag, c->fa, c->fb, c->fbc, c->fbidx, c->wall_faces, c->fnx, c->fny, c->flen,
                   c->fxm, c->fym, c->area, c->xc, c->yc, c->dwall, c->cfp, c->cff, c->W, c->M, c->gx,
                   c->gy, c->ugx, c->ugy, c->lamc, c->vort, c->dtimp, c->ff, c->flam, c->D, c->Dsa,
-                  c->dW, c->Wg, c->phi, c->fsa, c->fsag, c->sasrc};
+                  c->dW, c->Wg, c->phi, c->fsa, c->fsag, c->sasrc, c->fabsA, c->Dm};
     for (size_t i = 0; i < sizeof ps / sizeof ps[0]; i++) free(ps[i]);
     free(c->sblk);
     c->sblk = NULL;
@@ -497,13 +501,14 @@ static void free_mesh(oigks_ctx *c)
     c->fnx = c->fny = c->flen = c->fxm = c->fym = NULL; c->area = c->xc = c->yc = c->dwall = NULL;
     c->cfp = c->cff = NULL; c->W = c->M = c->gx = c->gy = c->ugx = c->ugy = NULL;
     c->lamc = c->vort = c->dtimp = c->ff = c->flam = c->D = c->Dsa = c->dW = c->Wg = c->phi = c->fsa = NULL;
-    c->fsag = c->sasrc = NULL;
+    c->fsag = c->sasrc = c->fabsA = c->Dm = NULL;
 }
 
 EXPORT void oigks_default_options(oigks_options *o)
 {
     o->limiter = 0; o->cfl_init = 1000.0; o->cfl_min = 1.0; o->cfl_max = 1e6; o->cfl_mode = 0; o->scheme = 0;
     o->cfl_flux = 1.0; o->visc_sr = 1; o->mu_law = 0; o->wall_temp = 0.0; o->limiter_freeze = 0.0; o->tau_jump = 0;
+    o->lusgs_op = 0;
 }
 
 EXPORT int oigks_create(oigks_ctx **out, const oigks_options *opt)
@@ -515,6 +520,7 @@ EXPORT int oigks_create(oigks_ctx **out, const oigks_options *opt)
     *out = c;
     if (!(c->opt.wall_temp >= 0.0) || !isfinite(c->opt.wall_temp)) { seterr(c, "wall_temp must be >= 0"); return -1; }
     if (c->opt.tau_jump < 0 || c->opt.tau_jump > 1) { seterr(c, "tau_jump must be 0 or 1"); return -1; }
+    if (c->opt.lusgs_op < 0 || c->opt.lusgs_op > 1) { seterr(c, "lusgs_op must be 0 or 1"); return -1; }
     if (!(c->opt.limiter_freeze >= 0.0) || !(c->opt.limiter_freeze < 1.0)) {
         seterr(c, "limiter_freeze must be in [0, 1)");
         return -1;
@@ -692,6 +698,7 @@ EXPORT int oigks_mesh_upload(oigks_ctx *c, int n_nodes, const double *xy, int n_
     c->lamc = calloc(n_cells, sizeof(double)); c->vort = calloc(n_cells, sizeof(double));
     c->dtimp = calloc(n_cells, sizeof(double));
     c->ff = calloc(4 * nf, sizeof(double)); c->flam = calloc(nf, sizeof(double));
+    if (c->opt.lusgs_op) { c->fabsA = calloc(16 * (size_t)nf, sizeof(double)); c->Dm = calloc(16 * (size_t)n_cells, sizeof(double)); }
     c->D = calloc(n_cells, sizeof(double)); c->Dsa = calloc(n_cells, sizeof(double));
     c->dW = calloc(5 * n_cells, sizeof(double)); c->Wg = calloc(5 * nf, sizeof(double));
     c->phi = calloc(n4, sizeof(double));
@@ -839,6 +846,47 @@ static void ghost_centroid(const oigks_ctx *c, int f, double *gx, double *gy)
  * (residual M), Eq.21/23 (spectral radius and dt), Eq.27-30 (SA).
  * ==================================================================== */
 static double sound(const double *W) { return sqrt(GAMMA / (2.0 * lam_of(W))); }
+
+/* Entropy fix of the Roe dissipation (reading: the paper gives none): each
+ * eigenvalue's magnitude is held at least at this fraction of the
+ * Roe-averaged sound speed. */
+static const double ROE_DELTA = 0.1;
+
+/* |A| = R |Lambda| L of the Euler flux Jacobian in direction n at the Roe
+ * average of the states Wl, Wr (the first-order Roe scheme's dissipation
+ * matrix, Eq.18), with the eigenvalues q - c, q, q, q + c limited below by
+ * ROE_DELTA c, plus vis times the identity (the viscous part of the
+ * spectral radius).  Written out as the product of the right eigenvectors,
+ * the eigenvalue magnitudes and the left eigenvectors of the conservative
+ * variables (rho, rho u, rho v, rho E). */
+static void roe_abs(const double *Wl, const double *Wr, double nx, double ny, double vis, double *A)
+{
+    const double b = GAMMA - 1.0;
+    double rl = Wl[0], rr = Wr[0];
+    double ul = Wl[1] / rl, vl = Wl[2] / rl, ur = Wr[1] / rr, vr = Wr[2] / rr;
+    double pl = b * (Wl[3] - 0.5 * rl * (ul * ul + vl * vl)), pr = b * (Wr[3] - 0.5 * rr * (ur * ur + vr * vr));
+    double Hl = (Wl[3] + pl) / rl, Hr = (Wr[3] + pr) / rr;
+    double sl = sqrt(rl), sr = sqrt(rr);
+    double u = (sl * ul + sr * ur) / (sl + sr), v = (sl * vl + sr * vr) / (sl + sr), H = (sl * Hl + sr * Hr) / (sl + sr);
+    double k = 0.5 * (u * u + v * v), c2 = b * (H - k), c = sqrt(c2);
+    double q = u * nx + v * ny, qt = -u * ny + v * nx;
+    double lm[4] = {fabs(q - c), fabs(q), fabs(q), fabs(q + c)};
+    for (int m = 0; m < 4; m++) if (lm[m] < ROE_DELTA * c) lm[m] = ROE_DELTA * c;
+    double R[4][4] = {{1.0, 1.0, 0.0, 1.0},
+                      {u - c * nx, u, -ny, u + c * nx},
+                      {v - c * ny, v, nx, v + c * ny},
+                      {H - q * c, k, qt, H + q * c}};
+    double L[4][4] = {{0.5 * (b * k / c2 + q / c), -0.5 * (b * u / c2 + nx / c), -0.5 * (b * v / c2 + ny / c), 0.5 * b / c2},
+                      {1.0 - b * k / c2, b * u / c2, b * v / c2, -b / c2},
+                      {-qt, -ny, nx, 0.0},
+                      {0.5 * (b * k / c2 - q / c), -0.5 * (b * u / c2 - nx / c), -0.5 * (b * v / c2 - ny / c), 0.5 * b / c2}};
+    for (int a = 0; a < 4; a++)
+        for (int d = 0; d < 4; d++) {
+            double s = 0.0;
+            for (int m = 0; m < 4; m++) s += R[a][m] * lm[m] * L[m][d];
+            A[4 * a + d] = s + (a == d ? vis : 0.0);
+        }
+}
 
 static int residual(oigks_ctx *c)
 {
@@ -1084,6 +1132,7 @@ static int residual(oigks_ctx *c)
                 lam += 2.0 * 0.5 * (mi / Wi[0] + mj / WjC[0]) / rn;
             }
             c->flam[f] = lam;
+            if (c->opt.lusgs_op) roe_abs(Wi, WjC, nx, ny, lam - (li > lj ? li : lj), &c->fabsA[16 * f]);
         }
         /* SA face terms (Eq.28-30) from cell-centre values */
         if (c->sa) {
@@ -1157,6 +1206,29 @@ static void sa_face_coef(const oigks_ctx *c, const double *Wi, const double *Wj,
     *off = -0.5 * (qj - fabs(qj)) * S + kf * S / rn;
 }
 
+/* the dissipation of face f applied to an increment d: lambda_ij d for the
+ * scalar operator, |A_ij| d for the Roe matrix (the same from either side:
+ * |A(-n)| = |A(n)|) */
+static void face_diss(const oigks_ctx *c, int f, const double *d, double *out)
+{
+    if (!c->opt.lusgs_op) {
+        for (int k = 0; k < 4; k++) out[k] = c->flam[f] * d[k];
+        return;
+    }
+    const double *A = &c->fabsA[16 * f];
+    for (int a = 0; a < 4; a++) out[a] = A[4 * a] * d[0] + A[4 * a + 1] * d[1] + A[4 * a + 2] * d[2] + A[4 * a + 3] * d[3];
+}
+
+/* D_i^-1 r: the scalar D of Eq.20, or its 4x4 block with the Roe matrix */
+static void diag_solve(const oigks_ctx *c, int i, const double *r, double *x)
+{
+    if (!c->opt.lusgs_op) {
+        for (int k = 0; k < 4; k++) x[k] = r[k] / c->D[i];
+        return;
+    }
+    gauss4(&c->Dm[16 * i], r, x);
+}
+
 static double face_rn(const oigks_ctx *c, int f)
 {
     int i = c->fL[f], j = c->fR[f];
@@ -1191,16 +1263,17 @@ static void lusgs_pass(oigks_ctx *c, const double *dWx)
             const double *dj = cross ? &dWx[5 * j] : &dW[5 * j];
             double sg = c->fL[f] == i ? 1.0 : -1.0;
             double nx = sg * c->fnx[f], ny = sg * c->fny[f], S = c->flen[f];
-            double jv[4];
+            double jv[4], dv[4];
             jac_vec(&W[5 * j], nx, ny, dj, jv);
-            for (int k = 0; k < 4; k++) acc[k] -= 0.5 * (jv[k] - c->flam[f] * dj[k]) * S;
+            face_diss(c, f, dj, dv);
+            for (int k = 0; k < 4; k++) acc[k] -= 0.5 * (jv[k] - dv[k]) * S;
             if (c->sa) {
                 double dg, of;
                 sa_face_coef(c, &W[5 * i], &W[5 * j], nx, ny, S, face_rn(c, f), &dg, &of);
                 acc[4] += of * dj[4];
             }
         }
-        for (int k = 0; k < 4; k++) dW[5 * i + k] = acc[k] / c->D[i];
+        diag_solve(c, i, acc, &dW[5 * i]);
         dW[5 * i + 4] = c->sa ? acc[4] / c->Dsa[i] : 0.0;
     }
     /* backward: dW_i = dW*_i - D^-1 sum_{j>i} (...) S / 2, ghosts included */
@@ -1223,16 +1296,19 @@ static void lusgs_pass(oigks_ctx *c, const double *dWx)
                 if (c->sblk && c->sblk[j] != c->sblk[i]) continue;   /* another sweep block */
                 Wj = &W[5 * j]; dj = &dW[5 * j];
             }
-            double jv[4];
+            double jv[4], dv[4];
             jac_vec(Wj, nx, ny, dj, jv);
-            for (int k = 0; k < 4; k++) acc[k] += 0.5 * (jv[k] - c->flam[f] * dj[k]) * S;
+            face_diss(c, f, dj, dv);
+            for (int k = 0; k < 4; k++) acc[k] += 0.5 * (jv[k] - dv[k]) * S;
             if (c->sa) {
                 double dg, of;
                 sa_face_coef(c, &W[5 * i], Wj, nx, ny, S, face_rn(c, f), &dg, &of);
                 acc[4] += of * dj[4];
             }
         }
-        for (int k = 0; k < 4; k++) dW[5 * i + k] = dWs[k] - acc[k] / c->D[i];
+        double corr[4];
+        diag_solve(c, i, acc, corr);
+        for (int k = 0; k < 4; k++) dW[5 * i + k] = dWs[k] - corr[k];
         dW[5 * i + 4] = c->sa ? dWs[4] + acc[4] / c->Dsa[i] : 0.0;
     }
 }
@@ -1247,6 +1323,14 @@ static void lusgs(oigks_ctx *c)
         double s = 0.0;
         for (int q = c->cfp[i]; q < c->cfp[i + 1]; q++) { int f = c->cff[q]; s += c->flam[f] * c->flen[f]; }
         c->D[i] = c->area[i] / c->dtimp[i] + 0.5 * s;                  /* Eq.20 */
+        if (c->opt.lusgs_op) {   /* the block form: Omega / dt I + 1/2 sum |A_ij| S_ij */
+            double *Dm = &c->Dm[16 * i];
+            for (int k = 0; k < 16; k++) Dm[k] = k % 5 == 0 ? c->area[i] / c->dtimp[i] : 0.0;
+            for (int q = c->cfp[i]; q < c->cfp[i + 1]; q++) {
+                int f = c->cff[q];
+                for (int k = 0; k < 16; k++) Dm[k] += 0.5 * c->fabsA[16 * f + k] * c->flen[f];
+            }
+        }
         if (c->sa) {
             double ds = 0.0;
             for (int q = c->cfp[i]; q < c->cfp[i + 1]; q++) {
@@ -1550,7 +1634,20 @@ EXPORT int oigks_get_debug(const oigks_ctx *c, double *flux, double *lam, double
     return 0;
 }
 
+/* the Roe dissipation matrices of the last residual (lusgs_op 1): 16 values
+ * per face, row by row; -1 when the scalar operator is in use */
+EXPORT int oigks_get_roe(const oigks_ctx *c, double *absA)
+{
+    if (!c->opt.lusgs_op || !c->fabsA) return -1;
+    memcpy(absA, c->fabsA, sizeof(double) * 16 * (size_t)c->nf);
+    return 0;
+}
+
 /* ---------------- kernel-level entry points used by the pins ---------------- */
+EXPORT void oigks_roe_abs(const double *Wl, const double *Wr, double nx, double ny, double vis, double *A)
+{
+    roe_abs(Wl, Wr, nx, ny, vis, A);
+}
 EXPORT void oigks_moments(double U, double lam, int kind, int n, double *out)
 {
     double m[MOMN];

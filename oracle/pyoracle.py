@@ -19,7 +19,7 @@ class Options(C.Structure):
                 ("cfl_max", C.c_double), ("cfl_mode", C.c_int), ("cfl_flux", C.c_double),
                 ("visc_sr", C.c_int), ("mu_law", C.c_int), ("scheme", C.c_int),
                 ("wall_temp", C.c_double), ("limiter_freeze", C.c_double),
-                ("tau_jump", C.c_int)]
+                ("tau_jump", C.c_int), ("lusgs_op", C.c_int)]
 
 
 class Residual(C.Structure):
@@ -75,6 +75,8 @@ def lib():
         L.oigks_sa_gross.argtypes = [p, dp]
         L.oigks_set_sweep_blocks.argtypes = [p, C.POINTER(C.c_int)]
         L.oigks_set_block_passes.argtypes = [p, i]
+        L.oigks_get_roe.argtypes = [p, dp]
+        L.oigks_roe_abs.argtypes = [dp, dp, d, d, d, dp]
         _lib = L
     return _lib
 
@@ -237,6 +239,14 @@ class Oracle:
         out["dt_flux"] = self.L.oigks_dt_flux(self.ctx)
         return out
 
+    def roe(self):
+        """The per-face Roe dissipation matrices |A| (+ viscous part) of the
+        last residual, shape (nf, 4, 4); needs lusgs_op = 1."""
+        out = np.zeros((self.nf, 4, 4))
+        if self.L.oigks_get_roe(self.ctx, out.ctypes.data_as(C.POINTER(C.c_double))) != 0:
+            raise OracleError("the Roe operator is not in use (lusgs_op = 0)")
+        return out
+
     def collision_time(self, rho0, lam0, nut_f=0.0):
         return self.L.oigks_collision_time(self.ctx, rho0, lam0, nut_f)
 
@@ -291,6 +301,13 @@ def sa_source(nut, nu, d, omega):
     out = np.zeros(4)
     lib().oigks_sa_source(nut, nu, d, omega, out.ctypes.data_as(C.POINTER(C.c_double)))
     return out
+
+
+def roe_abs(Wl, Wr, nx, ny, vis=0.0):
+    Wl, pl = _d(Wl); Wr, pr = _d(Wr)
+    out = np.zeros(16)
+    lib().oigks_roe_abs(pl, pr, nx, ny, vis, out.ctypes.data_as(C.POINTER(C.c_double)))
+    return out.reshape(4, 4)
 
 
 def jac_vec(W, nx, ny, d):
