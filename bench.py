@@ -358,14 +358,15 @@ def plate_mesh(mg, blocks):
 
 
 def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=10.0, chunk=100,
-                 blocks=SMALL_BLOCKS):
+                 blocks=SMALL_BLOCKS, **opt):
     """Iterations and seconds from the impulsive start to a density-residual
     drop of `target` on the laminar flat plate (64x32) with sweep blocks of
     `blocks` cells (None: natural order, one workgroup per sweep); scheme 1:
-    the explicit scheme (Eq.15, local steps at a fixed CFL)."""
+    the explicit scheme (Eq.15, local steps at a fixed CFL); opt: further
+    solver options (lusgs_op)."""
     import torch
     m, blk = plate_mesh(mg, blocks if scheme == 0 else None)
-    s = igks.Solver(m, precision=precision, cfl_init=cfl, chunk=chunk, scheme=scheme, sweep_blocks=blk)
+    s = igks.Solver(m, precision=precision, cfl_init=cfl, chunk=chunk, scheme=scheme, sweep_blocks=blk, **opt)
     s.set_freestream(*WORKLOADS["plate64x32"]["flow"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -384,8 +385,8 @@ def time_to_drop(igks, mg, precision, target=1e-10, max_it=20000, scheme=0, cfl=
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     wl = s.wall_loads()
-    say(f"plate to {target:g} (scheme {scheme}, precision {precision}): {it} iterations, {dt:.1f}s")
-    return dict(iterations=it, seconds=round(dt, 4), drop=s.residual()["res_drop"],
+    say(f"plate to {target:g} (scheme {scheme}, precision {precision}, {opt}): {it} iterations, {dt:.1f}s")
+    return dict(**opt, iterations=it, seconds=round(dt, 4), drop=s.residual()["res_drop"],
                 drop_from_first=ratio(s.residual()["res_l2"], l2_first), cd=wl["cd"],
                 cell_updates_per_s=m.n_cells * it / dt, ms_per_iteration=round(1e3 * dt / it, 4),
                 schedule=("explicit" if scheme else
@@ -450,6 +451,33 @@ def time_to_drop_joukowski(igks, mg):
     out["explicit_fp64_cfl0.9"] = run_to_drop(igks, mc, flow, igks.IGKS_FP64, None, max_it=2000000, chunk=2000,
                                              scheme=1, cfl=0.9, max_s=40.0, label="jouk40k explicit")
     return out
+
+
+def roe_time_to_solution(igks, mg):
+    """The small cases again with the Roe-matrix LU-SGS operator
+    (lusgs_op = 1): the plate to a 1e-10 drop (sweep blocks and natural
+    order), the cavity and the turbulent plate to Eq.40 <= 3e-8, the 40k
+    Joukowski to 1e-10 (blocks of 256)."""
+    flow = WORKLOADS["jouk40k"]["flow"]
+    mb, blk = mg.workload_blocks("jouk40k", 256)
+    return {"operator": "Roe matrix |A| = R|Lambda|L at the Roe average, |lambda| >= 0.1 c, 4x4 diagonal blocks",
+            "plate_fp64": time_to_drop(igks, mg, igks.IGKS_FP64, lusgs_op=1),
+            "plate_fp64_natural_order": time_to_drop(igks, mg, igks.IGKS_FP64, blocks=None, lusgs_op=1),
+            "cavity_to_eq40": time_to_converge_cavity(igks, mg, label="cavity roe", lusgs_op=1),
+            "turbulent_plate_to_eq40": time_to_converge_turbulent_plate(igks, mg, label="turbulent plate roe",
+                                                                        lusgs_op=1),
+            "jouk40k_blocks_fp64": guarded(run_to_drop, igks, mb, flow, igks.IGKS_FP64, blk, max_it=60000,
+                                           label="jouk40k blocks fp64 roe", lusgs_op=1)}
+
+
+def guarded(fn, igks, *a, **kw):
+    """fn's result, or the solver's error where it rejected a non-physical
+    update (the instance is frozen and the run ends there)."""
+    try:
+        return fn(igks, *a, **kw)
+    except igks.IgksError as e:
+        say(f"{kw.get('label', fn.__name__)}: {e}")
+        return dict(error=str(e))
 
 
 def time_to_drop_sa250k(igks, mg, max_s=40.0):
@@ -529,16 +557,16 @@ def batch_to_drop(igks, mg, target=1e-10, max_s=60.0, chunk=500):
                 fp64_alone_seconds_total=round(sum(v["seconds"] for v in seq.values()), 4))
 
 
-def time_to_converge_cavity(igks, mg, max_it=30000, chunk=200, label="cavity", blocks=SMALL_BLOCKS):
+def time_to_converge_cavity(igks, mg, max_it=30000, chunk=200, label="cavity", blocks=SMALL_BLOCKS, **opt):
     """The lid-driven cavity (100x100, Re 1000, Ma 0.1 sqrt 3, isothermal
     walls) from rest, implicit CFL 1000 growing by Eq.25, sweep blocks of
     `blocks` cells (None: natural order), to the paper's criterion Eq.40 <=
-    3e-8."""
+    3e-8; opt: further solver options (lusgs_op)."""
     import torch
     m, blk = mg.cavity(100), None
     if blocks:
         m, blk = mg.block_order(m, blocks, "coupled")
-    s = igks.Solver(m, cfl_init=1000.0, chunk=chunk, wall_temp=1.0, sweep_blocks=blk)
+    s = igks.Solver(m, cfl_init=1000.0, chunk=chunk, wall_temp=1.0, sweep_blocks=blk, **opt)
     s.set_freestream(0.1 * math.sqrt(3.0), 0.0, 1000.0)
     W = s.get_state()
     W[3] -= 0.5 * (W[1] ** 2 + W[2] ** 2) / W[0]
@@ -559,7 +587,7 @@ def time_to_converge_cavity(igks, mg, max_it=30000, chunk=200, label="cavity", b
     dt = time.perf_counter() - t0
     r = s.residual()
     say(f"{label}: {it} iterations, {dt:.1f}s")
-    return dict(workload="cavity100: 100x100 uniform, Re 1000, Ma 0.1 sqrt(3), isothermal walls, from rest",
+    return dict(**opt, workload="cavity100: 100x100 uniform, Re 1000, Ma 0.1 sqrt(3), isothermal walls, from rest",
                 schedule=f"sweep blocks of {blocks} cells" if blocks else "natural order, one workgroup per sweep",
                 criterion="Eq.40 <= 3e-8", iterations=it, seconds=round(dt, 4), eq40=r["eq40"],
                 drop=r["res_drop"], cfl=r["cfl"], ms_per_iteration=round(1e3 * dt / it, 4),
@@ -567,16 +595,16 @@ def time_to_converge_cavity(igks, mg, max_it=30000, chunk=200, label="cavity", b
 
 
 def time_to_converge_turbulent_plate(igks, mg, max_it=30000, chunk=500, label="turbulent plate",
-                                     blocks=SMALL_BLOCKS):
+                                     blocks=SMALL_BLOCKS, **opt):
     """The turbulent flat plate (SA, Ma 0.2, Re 5e6 per unit length, 7680
     cells, sweep blocks of `blocks` cells, None: natural order) from the free
     stream at CFL 10 growing by Eq.25, to the paper's criterion Eq.40 <=
-    3e-8."""
+    3e-8; opt: further solver options (lusgs_op)."""
     import torch
     m, blk = mg.turbulent_plate(), None
     if blocks:
         m, blk = mg.block_order(m, blocks, "coupled")
-    s = igks.Solver(m, cfl_init=10.0, chunk=chunk, sweep_blocks=blk)
+    s = igks.Solver(m, cfl_init=10.0, chunk=chunk, sweep_blocks=blk, **opt)
     s.set_freestream(0.2, 0.0, 5e6, 3.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -593,7 +621,7 @@ def time_to_converge_turbulent_plate(igks, mg, max_it=30000, chunk=500, label="t
     dt = time.perf_counter() - t0
     r = s.residual()
     say(f"{label}: {it} iterations, {dt:.1f}s")
-    return dict(workload="turbulent flat plate: 120x64 quads, y+ ~ 1, Ma 0.2, Re 5e6/unit length, SA, from the free stream",
+    return dict(**opt, workload="turbulent flat plate: 120x64 quads, y+ ~ 1, Ma 0.2, Re 5e6/unit length, SA, from the free stream",
                 schedule=f"sweep blocks of {blocks} cells" if blocks else "natural order, one workgroup per sweep",
                 criterion="Eq.40 <= 3e-8", iterations=it, seconds=round(dt, 4), eq40=r["eq40"],
                 drop=r["res_drop"], cd=s.wall_loads()["cd"], ms_per_iteration=round(1e3 * dt / it, 4),
@@ -725,6 +753,10 @@ def main():
                     help="run only the 250k SA Joukowski from the free stream toward a 1e-10 drop (--precision, "
                          "default fp64; two-pass coupled blocks of 512 cells, limiter held from 1e-4) for at most "
                          "SECONDS and print its JSON (the full default run gives it 40 s per precision)")
+    ap.add_argument("--lusgs-op", type=int, default=0, choices=[0, 1],
+                    help="LU-SGS operator of the --sa250k-only run: 0 the scalar spectral radius, 1 the Roe matrix")
+    ap.add_argument("--roe-only", action="store_true",
+                    help="run only the time-to-solution cases with the Roe-matrix LU-SGS operator and print their JSON")
     ap.add_argument("--mesh-cache", default=None,
                     help="directory where generated meshes are stored and read back (the seeded generation "
                          "of the 2M-cell mesh takes about a minute)")
@@ -748,10 +780,14 @@ def main():
         prec = args.precision or "fp64"
         r = run_to_drop(igks, mb, flow, igks.IGKS_MIXED if prec == "mixed" else igks.IGKS_FP64, blk,
                         max_it=10 ** 7, chunk=1000, cfl=10.0, max_s=args.sa250k_only, limiter=1, limiter_freeze=1e-4,
-                        block_passes=2, label=f"jouk250k to 1e-10 ({prec})")
+                        block_passes=2, lusgs_op=args.lusgs_op, label=f"jouk250k to 1e-10 ({prec})")
         print(json.dumps(dict(workload="jouk250k: " + WORKLOADS["jouk250k"]["desc"], precision=prec,
+                              lusgs_op=args.lusgs_op,
                               schedule="coupled sweep blocks of 512 cells, two passes, Eq.9 limiter held from a "
                                        "drop of 1e-4, CFL 10 -> Eq.25", target=1e-10, **r)), flush=True)
+        return
+    if args.roe_only:
+        print(json.dumps(roe_time_to_solution(igks, mg)), flush=True)
         return
     wl = WORKLOADS[args.workload]
     batched = args.workload == "batch64"

@@ -108,6 +108,14 @@ typedef struct igks_options {
                            paper).  Two passes run on the wave-per-block schedule (sweep 0 or 3;
                            1 or 2 with block_passes 2 is IGKS_EINVAL) and take a second increment
                            array in the workspace. */
+    int lusgs_op;       /* dissipation of the LU-SGS operator (Eq.18-22): 0 (default) the scalar
+                           spectral radius lambda_ij I of Eq.20; 1 the first-order Roe matrix
+                           |A_ij| = R |Lambda| L of the Euler flux Jacobian at the Roe average of the
+                           two cell-centre states (eigenvalue magnitudes held at least at 0.1 c) plus
+                           the viscous part of lambda_ij times I, so that D becomes a 4x4 block per
+                           cell (inverted once per iteration, 16 values per cell in the workspace).
+                           The steady answer is the same; the implicit iteration converges in fewer
+                           steps.  The SA equation keeps its scalar form.  Other values: IGKS_EINVAL. */
 } igks_options;
 
 typedef struct igks_residual {

@@ -90,6 +90,9 @@ struct Params {
     T *dW;                     // LU-SGS increment, 5 x nc
     const T *dWx;              // a first block pass's increments, whose cross-block terms the
                                // forward sweep takes (two block passes); null otherwise
+    T *dinv;                   // Roe-matrix operator: the inverse of each cell's 4x4 LU-SGS
+                               // diagonal block, entry (r, k) at (4 r + k) nc + c; null with
+                               // the scalar operator
     const double *xc, *yc, *area, *lsinv, *dwall;
     const double *vtx;         // vertex offsets from the centroid: (x, y) of slot v of block b at (2v) nb + b
     int nb;                    // entry / vertex blocks: nc + overflow blocks
@@ -144,6 +147,7 @@ template <typename T> void launch_flux(const Launch &L, const Params<T> &P);
 template <typename T> void launch_gather(const Launch &L, const Params<T> &P);
 // it: the iteration's index in the current chunk (its history entry)
 template <typename T> void launch_reduce(const Launch &L, const Params<T> &P, int it);
+template <typename T> void launch_roe_diag(const Launch &L, const Params<T> &P);
 // one wavefront of cells [c0, c1) of the sweeps; mode 0 forward, 1 backward,
 // 2 both (the last wavefront).  Backward steps also update the state
 // (Eq.17); launch_commit then accepts or rejects the iteration of every

@@ -71,7 +71,7 @@ struct Buf {
 constexpr int NKT = 6;
 
 struct WsMap {
-    Buf ip, is, slot, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, dW1, xc, yc, area, lsinv, dwall, vtx, phi;
+    Buf ip, is, slot, Wa, Wb, grad, lamc, vort, nu, M, lsum, sadiag, r2, dW, dW1, dinv, xc, yc, area, lsinv, dwall, vtx, phi;
     Buf cinst, finst, icell, ioff, g2i, cf_face, cf_nbr, cf_flag, cf_dx, cf_dy;
     Buf fl, fr, fbc, fnx, fny, flen, frl, frr, fidl, fidr, firn, ipart, hist, ipos, cperm;
     Buf frec, flam, fsak, enx, eny, es;
@@ -662,6 +662,8 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     w.dW = L.add(5 * N * (o.precision == IGKS_MIXED ? sizeof(float) : D));
     // the first pass's increments (two block passes)
     w.dW1 = L.add(o.block_passes == 2 ? 5 * N * (o.precision == IGKS_MIXED ? sizeof(float) : D) : 0);
+    // the inverted 4x4 LU-SGS diagonal blocks (Roe-matrix operator)
+    w.dinv = L.add(o.lusgs_op == 1 && o.scheme == 0 ? 16 * N * (o.precision == IGKS_MIXED ? sizeof(float) : D) : 0);
     w.xc = L.add(N * D); w.yc = L.add(N * D); w.area = L.add(N * D); w.lsinv = L.add(3 * N * D);
     w.dwall = L.add(N * D); w.vtx = L.add(2 * MAXV * (size_t)G.NB * D);
     w.cinst = L.add(N * I); w.finst = L.add(F * I); w.icell = L.add(N * I); w.ioff = L.add((NI + 1) * I);
@@ -713,6 +715,7 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.Wa = D(w.Wa); P.Wb = D(w.Wb); P.grad = D(w.grad); P.lamc = D(w.lamc); P.vort = D(w.vort); P.nu = D(w.nu);
     P.M = D(w.M); P.lsum = D(w.lsum); P.sadiag = D(w.sadiag); P.r2 = D(w.r2); P.dW = (T *)(b + w.dW.off);
     P.dWx = nullptr;
+    P.dinv = c->opt.lusgs_op == 1 && c->opt.scheme == 0 ? (T *)(b + w.dinv.off) : nullptr;
     P.xc = D(w.xc); P.yc = D(w.yc); P.area = D(w.area); P.lsinv = D(w.lsinv); P.dwall = D(w.dwall); P.vtx = D(w.vtx);
     P.nb = c->g.NB;
     P.cf_face = In(w.cf_face); P.cf_nbr = In(w.cf_nbr); P.cf_flag = In(w.cf_flag);
@@ -761,6 +764,9 @@ void queue_iteration(igks_ctx *c, const Params<T> &P, hipEvent_t *ev, int it)
         mark(6);
         return;
     }
+    // Roe-matrix operator: the inverted diagonal blocks, which need the CFL
+    // number the reduction has just set (timed with the forward sweep)
+    if (P.dinv) launch_roe_diag(L, P);
     const int *blo = (const int *)(c->ws + c->w.bl_off.off), *bll = (const int *)(c->ws + c->w.bl_lo.off),
               *blh = (const int *)(c->ws + c->w.bl_hi.off);
     const int ngb = (int)G.bl_off.size() - 1;
@@ -1070,6 +1076,7 @@ void igks_default_options(igks_options *o)
     o->limiter_freeze = 0.0;
     o->tau_jump = 0;
     o->block_passes = 1;
+    o->lusgs_op = 0;
 }
 
 int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream, int32_t n_inst)
@@ -1092,6 +1099,7 @@ int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream,
     if (c->opt.block_passes == 0) c->opt.block_passes = 1;
     if (c->opt.block_passes < 1 || c->opt.block_passes > 2) { delete c; return IGKS_EINVAL; }
     if (c->opt.block_passes == 2 && c->opt.sweep != 0 && c->opt.sweep != 3) { delete c; return IGKS_EINVAL; }
+    if (c->opt.lusgs_op < 0 || c->opt.lusgs_op > 1) { delete c; return IGKS_EINVAL; }
     for (int k = 0; k < NCLASS; k++) c->block[k] = c->opt.block;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;

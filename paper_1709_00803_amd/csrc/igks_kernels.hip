@@ -1382,18 +1382,181 @@ __device__ __forceinline__ V quad_fold(V a, V t)
     return acc_add(acc_add(acc_add(acc_add(a, t0), t1), t2), t3);
 }
 
+// ---- Roe-matrix LU-SGS operator (option lusgs_op = 1) ----
+// The dissipation of the first-order Roe flux (Eq.18) in place of the
+// scalar spectral radius of Eq.20: |A| = R |Lambda| L of the Euler flux
+// Jacobian at the Roe average of the two cell-centre states, the eigenvalue
+// magnitudes |q - c|, |q|, |q|, |q + c| held at least at ROE_DELTA c.
+
+constexpr double ROE_DELTA = 0.1;
+
+// Roe average of states a (the cell) and b (the neighbour or ghost) for the
+// normal n out of the cell; smax = max(|q_a| + c_a, |q_b| + c_b), the
+// inviscid part of the face's spectral radius
+struct RoeAvg {
+    double u, v, H, k, c, q, qt, smax;
+};
+
+__device__ __forceinline__ RoeAvg roe_avg(const double *a, const double *b, double nx, double ny)
+{
+    const double g1 = GAMMA - 1.0;
+    const double ra = a[0], rb = b[0];
+    const double ua = a[1] / ra, va = a[2] / ra, ub = b[1] / rb, vb = b[2] / rb;
+    const double pa = g1 * (a[3] - 0.5 * (a[1] * ua + a[2] * va)), pb = g1 * (b[3] - 0.5 * (b[1] * ub + b[2] * vb));
+    const double sa = sqrt(ra), sb = sqrt(rb), iw = 1.0 / (sa + sb);
+    RoeAvg R;
+    R.u = (sa * ua + sb * ub) * iw;
+    R.v = (sa * va + sb * vb) * iw;
+    R.H = (sa * (a[3] + pa) / ra + sb * (b[3] + pb) / rb) * iw;
+    R.k = 0.5 * (R.u * R.u + R.v * R.v);
+    R.c = sqrt(g1 * (R.H - R.k));
+    R.q = R.u * nx + R.v * ny;
+    R.qt = -R.u * ny + R.v * nx;
+    R.smax = fmax(fabs(ua * nx + va * ny) + sqrt(GAMMA * pa / ra), fabs(ub * nx + vb * ny) + sqrt(GAMMA * pb / rb));
+    return R;
+}
+
+// out = |A| d by the wave decomposition: wave strengths alpha = L d (a
+// pressure part dp / c^2 and a normal-velocity part), each scaled by its
+// eigenvalue magnitude, summed over the right eigenvectors
+__device__ __forceinline__ void roe_apply(const RoeAvg &R, double nx, double ny, const double *d, double *out)
+{
+    const double ic = 1.0 / R.c, g1c2 = (GAMMA - 1.0) * ic * ic;
+    const double dpc = g1c2 * (R.k * d[0] - R.u * d[1] - R.v * d[2] + d[3]);
+    const double dun = (-R.q * d[0] + nx * d[1] + ny * d[2]) * ic;
+    const double fl = ROE_DELTA * R.c;
+    const double a0 = 0.5 * (dpc - dun) * fmax(fabs(R.q - R.c), fl);
+    const double a3 = 0.5 * (dpc + dun) * fmax(fabs(R.q + R.c), fl);
+    const double m1 = fmax(fabs(R.q), fl);
+    const double a1 = (d[0] - dpc) * m1;
+    const double a2 = (-R.qt * d[0] - ny * d[1] + nx * d[2]) * m1;
+    out[0] = a0 + a1 + a3;
+    out[1] = a0 * (R.u - R.c * nx) + a1 * R.u - a2 * ny + a3 * (R.u + R.c * nx);
+    out[2] = a0 * (R.v - R.c * ny) + a1 * R.v + a2 * nx + a3 * (R.v + R.c * ny);
+    out[3] = a0 * (R.H - R.q * R.c) + a1 * R.k + a2 * R.qt + a3 * (R.H + R.q * R.c);
+}
+
+// inverse of a 4x4 matrix (row-major) by cofactors: the 2x2 minors of the
+// top two rows (s) and of the bottom two rows (c) give the determinant by
+// Laplace expansion and every cofactor
+__device__ __forceinline__ void inv4x4(const double *a, double *b)
+{
+    const double s0 = a[0] * a[5] - a[4] * a[1], s1 = a[0] * a[6] - a[4] * a[2], s2 = a[0] * a[7] - a[4] * a[3];
+    const double s3 = a[1] * a[6] - a[5] * a[2], s4 = a[1] * a[7] - a[5] * a[3], s5 = a[2] * a[7] - a[6] * a[3];
+    const double c5 = a[10] * a[15] - a[14] * a[11], c4 = a[9] * a[15] - a[13] * a[11];
+    const double c3 = a[9] * a[14] - a[13] * a[10], c2 = a[8] * a[15] - a[12] * a[11];
+    const double c1 = a[8] * a[14] - a[12] * a[10], c0 = a[8] * a[13] - a[12] * a[9];
+    const double id = 1.0 / (s0 * c5 - s1 * c4 + s2 * c3 + s3 * c2 - s4 * c1 + s5 * c0);
+    b[0] = (a[5] * c5 - a[6] * c4 + a[7] * c3) * id;
+    b[1] = (-a[1] * c5 + a[2] * c4 - a[3] * c3) * id;
+    b[2] = (a[13] * s5 - a[14] * s4 + a[15] * s3) * id;
+    b[3] = (-a[9] * s5 + a[10] * s4 - a[11] * s3) * id;
+    b[4] = (-a[4] * c5 + a[6] * c2 - a[7] * c1) * id;
+    b[5] = (a[0] * c5 - a[2] * c2 + a[3] * c1) * id;
+    b[6] = (-a[12] * s5 + a[14] * s2 - a[15] * s1) * id;
+    b[7] = (a[8] * s5 - a[10] * s2 + a[11] * s1) * id;
+    b[8] = (a[4] * c4 - a[5] * c2 + a[7] * c0) * id;
+    b[9] = (-a[0] * c4 + a[1] * c2 - a[3] * c0) * id;
+    b[10] = (a[12] * s4 - a[13] * s2 + a[15] * s0) * id;
+    b[11] = (-a[8] * s4 + a[9] * s2 - a[11] * s0) * id;
+    b[12] = (-a[4] * c3 + a[5] * c1 - a[6] * c0) * id;
+    b[13] = (a[0] * c3 - a[1] * c1 + a[2] * c0) * id;
+    b[14] = (-a[12] * s3 + a[13] * s1 - a[14] * s0) * id;
+    b[15] = (a[8] * s3 - a[9] * s1 + a[10] * s0) * id;
+}
+
+// Per cell, once the CFL number of the iteration is known: the LU-SGS
+// diagonal block D = (Omega/dt) I + 1/2 sum (|A_f| + (lambda_f - smax_f) I) S_f
+// (lambda_f - smax_f, the viscous part of the spectral radius, enters as
+// before; 1/2 sum lambda_f S_f is lsum), inverted and stored for the sweeps.
+template <typename T, bool ONE>
+__global__ __launch_bounds__(256) void k_roe_diag(Params<T> P)
+{
+    const int N = P.nc;
+    const int c = xcd_block() * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    const int inst = live_inst<ONE>(P, P.cinst, c);
+    if (inst < 0) return;
+    const InstParam &ip = P.ip[inst];
+    const double *W = cur_state(P, inst);
+    double w[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) w[k] = W[k * N + c];
+    double a[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) a[k] = 0.0;
+    auto block = [&](const Entries &E, int b) {
+#pragma unroll
+        for (int k = 0; k < MAXV; k++) {
+            if (!(E.flag[k] & CF_VALID)) continue;
+            const int e = MAXV * b + k, f = E.face[k], j = E.nbr[k];
+            const double nx = P.enx[e], ny = P.eny[e], hS = 0.5 * P.es[e];
+            double wj[5];
+            if (j >= 0) {
+#pragma unroll
+                for (int m = 0; m < 5; m++) wj[m] = W[m * N + j];
+            } else {
+                ghost(ip, P.fbc[f], w, nx, ny, wj);
+            }
+            const RoeAvg R = roe_avg(w, wj, nx, ny);
+#pragma unroll
+            for (int col = 0; col < 4; col++) {
+                double d[4] = {0.0, 0.0, 0.0, 0.0}, o[4];
+                d[col] = 1.0;
+                roe_apply(R, nx, ny, d, o);
+#pragma unroll
+                for (int r = 0; r < 4; r++) a[4 * r + col] += hS * o[r];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++) a[5 * r] -= hS * R.smax;
+        }
+    };
+    const Entries E0 = entries(P, c);
+    block(E0, c);
+    const int ovf = next_block(P, E0);
+    if (ovf >= 0) block(entries(P, ovf), ovf);
+    const double dg = P.lamc[c] / P.is[inst].cfl + P.lsum[c];
+#pragma unroll
+    for (int r = 0; r < 4; r++) a[5 * r] += dg;
+    double b[16];
+    inv4x4(a, b);
+#pragma unroll
+    for (int k = 0; k < 16; k++) P.dinv[k * N + c] = T(b[k]);
+}
+
+// y = D_c^-1 x with the stored inverse block (fixed order of operations)
+template <typename T>
+__device__ __forceinline__ void dinv_apply(const Params<T> &P, int c, const T *x, T *y)
+{
+    const int N = P.nc;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        T s = T(P.dinv[(4 * r) * N + c]) * x[0];
+        s = fma(T(P.dinv[(4 * r + 1) * N + c]), x[1], s);
+        s = fma(T(P.dinv[(4 * r + 2) * N + c]), x[2], s);
+        y[r] = fma(T(P.dinv[(4 * r + 3) * N + c]), x[3], s);
+    }
+}
+
 // Forward-sweep increment dW*_j of a cell of the first wavefront: it has no
 // lower neighbours, so Eq.22 reduces to dW*_j = D_j^-1 M_j (the expressions
 // of sweep_cell with nothing subtracted, hence the same numbers).  Formed
 // where it is needed instead of in a launch of its own.
-template <typename T>
+template <typename T, bool ROE>
 __device__ __forceinline__ void first_front_incr(const Params<T> &P, const InstParam &ip, int j, T cfl, T *d)
 {
     const int N = P.nc;
     const T odt = T(P.lamc[j]) / cfl;
-    const T iD = T(1) / (odt + T(P.lsum[j]));
+    if (ROE) {
+        T m[4];
 #pragma unroll
-    for (int k = 0; k < 4; k++) d[k] = T(P.M[k * N + j]) * iD;
+        for (int k = 0; k < 4; k++) m[k] = T(P.M[k * N + j]);
+        dinv_apply(P, j, m, d);
+    } else {
+        const T iD = T(1) / (odt + T(P.lsum[j]));
+#pragma unroll
+        for (int k = 0; k < 4; k++) d[k] = T(P.M[k * N + j]) * iD;
+    }
     d[4] = ip.sa ? T(P.M[4 * N + j]) / (odt + T(P.sadiag[j])) : T(0);
 }
 
@@ -1403,7 +1566,7 @@ __device__ __forceinline__ void first_front_incr(const Params<T> &P, const InstP
 // from dsrc.  j < 0: the ghost cell, whose increment follows from the cell's
 // own dW* (Sec. 2.5).  Neighbours j < lev1 belong to the first wavefront,
 // whose forward increments are not stored (first_front_incr).
-template <typename T>
+template <typename T, bool ROE>
 __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &ip, const double *W,
                                            const double *w, int f, int e, int j, const T *dws, T cfl, int lev1,
                                            T *t, const T *dsrc)
@@ -1417,7 +1580,7 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
 #pragma unroll
         for (int k = 0; k < 5; k++) wj[k] = W[k * N + j];
         if (j < lev1) {
-            first_front_incr(P, ip, j, cfl, dj);
+            first_front_incr<T, ROE>(P, ip, j, cfl, dj);
         } else {
 #pragma unroll
             for (int k = 0; k < 5; k++) dj[k] = dsrc[k * N + j];
@@ -1430,8 +1593,20 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
     T jv[4];
     jac_vec<T>(wjt, T(nx), T(ny), dj, jv);
     T h = T(0.5) * S;
+    if (ROE) {
+        // (|A| + (lambda - smax) I) dW_j: the Roe matrix plus the viscous
+        // part of the spectral radius
+        const RoeAvg R = roe_avg(w, wj, nx, ny);
+        const double dd[4] = {double(dj[0]), double(dj[1]), double(dj[2]), double(dj[3])};
+        double ad[4];
+        roe_apply(R, nx, ny, dd, ad);
+        const T lv = lam - T(R.smax);
 #pragma unroll
-    for (int k = 0; k < 4; k++) t[k] = h * (jv[k] - lam * dj[k]);
+        for (int k = 0; k < 4; k++) t[k] = h * (jv[k] - lv * dj[k] - T(ad[k]));
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) t[k] = h * (jv[k] - lam * dj[k]);
+    }
     t[4] = T(0);
     if (ip.sa) {
         double qj = (wj[1] * nx + wj[2] * ny) / wj[0];
@@ -1509,7 +1684,7 @@ __global__ __launch_bounds__(256) void k_explicit(Params<T> P)
 // instance's other state buffer (nu~ clipped at 0), flags a non-physical
 // result and returns the Eq.40 ratio; SW_BWD_ONLY leaves the update to
 // k_update.  inst = -1 for a frozen instance.
-template <typename T, int MODE, bool ONE = false>
+template <typename T, int MODE, bool ONE, bool ROE>
 __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &inst)
 {
     const int N = P.nc;
@@ -1540,7 +1715,7 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
                 if (!(fl & CF_VALID) || j < 0) continue;
                 const bool cross = (fl & CF_OTHER) && P.dWx;
                 if (!(fl & CF_LOWER) && !cross) continue;
-                sweep_term(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t, cross ? P.dWx : P.dW);
+                sweep_term<T, ROE>(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t, cross ? P.dWx : P.dW);
 #pragma unroll
                 for (int m = 0; m < 4; m++) acc[m] = acc_sub(acc[m], t[m]);
                 acc[4] = acc_add(acc[4], t[4]);
@@ -1548,9 +1723,13 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
         };
         lower(E0, c);
         if (ovf >= 0) lower(entries(P, ovf), ovf);
-        const T iD = T(1) / D;
+        if (ROE) {
+            dinv_apply(P, c, acc, dws);
+        } else {
+            const T iD = T(1) / D;
 #pragma unroll
-        for (int k = 0; k < 4; k++) dws[k] = acc[k] * iD;
+            for (int k = 0; k < 4; k++) dws[k] = acc[k] * iD;
+        }
         dws[4] = ip.sa ? acc[4] / (odt + T(P.sadiag[c])) : T(0);
         if (MODE == SW_FWD) {
 #pragma unroll
@@ -1568,7 +1747,7 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
         for (int k = 0; k < MAXV; k++) {
             const int j = E.nbr[k], fl = E.flag[k];
             if (!(fl & CF_VALID) || (j >= 0 && (fl & (CF_LOWER | CF_OTHER)))) continue;
-            sweep_term(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t, P.dW);
+            sweep_term<T, ROE>(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t, P.dW);
 #pragma unroll
             for (int m = 0; m < 5; m++) acc[m] = acc_add(acc[m], t[m]);
         }
@@ -1576,9 +1755,16 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
     upper(E0, c);
     if (ovf >= 0) upper(entries(P, ovf), ovf);
     T d[5];
-    const T iD = T(1) / D;
+    if (ROE) {
+        T y[4];
+        dinv_apply(P, c, acc, y);
 #pragma unroll
-    for (int k = 0; k < 4; k++) d[k] = dws[k] - acc[k] * iD;
+        for (int k = 0; k < 4; k++) d[k] = dws[k] - y[k];
+    } else {
+        const T iD = T(1) / D;
+#pragma unroll
+        for (int k = 0; k < 4; k++) d[k] = dws[k] - acc[k] * iD;
+    }
     d[4] = ip.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
 #pragma unroll
     for (int k = 0; k < 5; k++) P.dW[k * N + c] = d[k];
@@ -1597,7 +1783,7 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
 // the Eq.40 ratio; the other lanes return 0.  Cells below lev1 (the first
 // wavefront) have no stored forward increment: their own and their
 // neighbours' are formed by first_front_incr.
-template <typename T, int MODE, bool ONE>
+template <typename T, int MODE, bool ONE, bool ROE>
 __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, int lev1, int &inst)
 {
     const int N = P.nc;
@@ -1627,7 +1813,7 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
             for (int m = 0; m < 5; m++) t[m] = T(0);
             const bool cross = (fl & CF_OTHER) && P.dWx;
             if ((fl & CF_VALID) && j >= 0 && ((fl & CF_LOWER) || cross))
-                sweep_term(P, ip, W, w, f, e, j, dws, cfl, cross ? 0 : lev1, t, cross ? P.dWx : P.dW);
+                sweep_term<T, ROE>(P, ip, W, w, f, e, j, dws, cfl, cross ? 0 : lev1, t, cross ? P.dWx : P.dW);
 #pragma unroll
             for (int m = 0; m < 4; m++) acc[m] = quad_fold<true>(acc[m], t[m]);
             acc[4] = quad_fold<false>(acc[4], t[4]);
@@ -1635,9 +1821,13 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
         lower(f0, MAXV * c + q, j0, fl0);
         if (ovf >= 0)
             lower(P.cf_face[MAXV * ovf + q], MAXV * ovf + q, P.cf_nbr[MAXV * ovf + q], P.cf_flag[MAXV * ovf + q]);
-        const T iD = T(1) / D;
+        if (ROE) {
+            dinv_apply(P, c, acc, dws);
+        } else {
+            const T iD = T(1) / D;
 #pragma unroll
-        for (int k = 0; k < 4; k++) dws[k] = acc[k] * iD;
+            for (int k = 0; k < 4; k++) dws[k] = acc[k] * iD;
+        }
         dws[4] = ip.sa ? acc[4] / (odt + T(P.sadiag[c])) : T(0);
         if (MODE == SW_FWD) {
             if (q == 0) {
@@ -1647,7 +1837,7 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
             return 0.0;
         }
     } else if (c < lev1) {
-        first_front_incr(P, ip, c, cfl, dws);
+        first_front_incr<T, ROE>(P, ip, c, cfl, dws);
     } else {
 #pragma unroll
         for (int k = 0; k < 5; k++) dws[k] = P.dW[k * N + c];
@@ -1658,7 +1848,7 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
 #pragma unroll
         for (int m = 0; m < 5; m++) t[m] = T(0);
         if ((fl & CF_VALID) && !(j >= 0 && (fl & (CF_LOWER | CF_OTHER))))
-            sweep_term(P, ip, W, w, f, e, j, dws, cfl, lev1, t, P.dW);
+            sweep_term<T, ROE>(P, ip, W, w, f, e, j, dws, cfl, lev1, t, P.dW);
 #pragma unroll
         for (int m = 0; m < 5; m++) acc[m] = quad_fold<false>(acc[m], t[m]);
     };
@@ -1667,9 +1857,16 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
         upper(P.cf_face[MAXV * ovf + q], MAXV * ovf + q, P.cf_nbr[MAXV * ovf + q], P.cf_flag[MAXV * ovf + q]);
     if (q != 0) return 0.0;
     T d[5];
-    const T iD = T(1) / D;
+    if (ROE) {
+        T y[4];
+        dinv_apply(P, c, acc, y);
 #pragma unroll
-    for (int k = 0; k < 4; k++) d[k] = dws[k] - acc[k] * iD;
+        for (int k = 0; k < 4; k++) d[k] = dws[k] - y[k];
+    } else {
+        const T iD = T(1) / D;
+#pragma unroll
+        for (int k = 0; k < 4; k++) d[k] = dws[k] - acc[k] * iD;
+    }
     d[4] = ip.sa ? dws[4] + acc[4] / (odt + T(P.sadiag[c])) : T(0);
 #pragma unroll
     for (int k = 0; k < 5; k++) P.dW[k * N + c] = d[k];
@@ -1722,14 +1919,14 @@ __global__ __launch_bounds__(64) void k_commit(Params<T> P, int it)
 }
 
 // One wavefront of cells [c0, c1), four lanes per cell (sweep_quad)
-template <typename T, int MODE, bool ONE>
+template <typename T, int MODE, bool ONE, bool ROE>
 __global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1, int lev1)
 {
     const int t = xcd_block() * blockDim.x + threadIdx.x;
     const int c = c0 + (t >> 2);
     int inst = -1;
     double e = 0.0;
-    if (c < c1) e = sweep_quad<T, MODE, ONE>(P, c, t & 3, lev1, inst);
+    if (c < c1) e = sweep_quad<T, MODE, ONE, ROE>(P, c, t & 3, lev1, inst);
     if (MODE != SW_FWD) slot_update<false>(P.slot, SL_E40, inst, e);
 }
 
@@ -1743,7 +1940,7 @@ __global__ __launch_bounds__(256) void k_sweep(Params<T> P, int c0, int c1, int 
 // ONE (a context of one instance) makes the instance index a constant, so
 // its scalars come through scalar loads instead of a dependent vector load
 // chain on every wavefront.
-template <typename T, bool FWD, bool ONE>
+template <typename T, bool FWD, bool ONE, bool ROE>
 __global__ __launch_bounds__(512) void k_sweep_wg(Params<T> P, const int *lev_off, int nlev)
 {
     for (int i = 0; i < nlev; i++) {
@@ -1751,7 +1948,7 @@ __global__ __launch_bounds__(512) void k_sweep_wg(Params<T> P, const int *lev_of
         int c0 = lev_off[l], c1 = lev_off[l + 1];
         for (int c = c0 + (int)threadIdx.x; c < c1; c += (int)blockDim.x) {
             int inst;
-            (void)sweep_cell<T, FWD ? SW_FWD : SW_BWD_ONLY, ONE>(P, c, inst);
+            (void)sweep_cell<T, FWD ? SW_FWD : SW_BWD_ONLY, ONE, ROE>(P, c, inst);
         }
         __syncthreads();
     }
@@ -1765,7 +1962,7 @@ __global__ __launch_bounds__(512) void k_sweep_wg(Params<T> P, const int *lev_of
 // each wavefront orders its dW writes before the next wavefront's reads.
 // As in the one-workgroup sweep, the backward pass leaves the update to
 // k_update.
-template <typename T, bool FWD, bool ONE>
+template <typename T, bool FWD, bool ONE, bool ROE>
 __global__ __launch_bounds__(64) void k_sweep_blk(Params<T> P, const int *bl_off, const int *bl_lo, const int *bl_hi)
 {
     const int gb = blockIdx.x;
@@ -1776,7 +1973,7 @@ __global__ __launch_bounds__(64) void k_sweep_blk(Params<T> P, const int *bl_off
         const int c0 = bl_lo[k], c1 = bl_hi[k];
         for (int c = c0 + cell; c < c1; c += 16) {   // the four lanes of a quad take the same cell
             int inst;
-            (void)sweep_quad<T, FWD ? SW_FWD : SW_BWD_ONLY, ONE>(P, c, q, 0, inst);
+            (void)sweep_quad<T, FWD ? SW_FWD : SW_BWD_ONLY, ONE, ROE>(P, c, q, 0, inst);
         }
         __syncthreads();
     }
@@ -1902,31 +2099,31 @@ template <typename T> void launch_reduce(const Launch &L, const Params<T> &P, in
 {
     hipLaunchKernelGGL(k_reduce<T>, dim3(P.ninst * (P.rb + 1)), dim3(256), 0, L.s, P, it);
 }
+// the sweep kernels K<T, X, ONE, ROE> come in four variants: one instance or
+// several (ONE), the scalar or the Roe-matrix operator (ROE)
+#define LAUNCH_SWEEP(K, X, grid, block, ...)                                                         \
+    do {                                                                                             \
+        const bool one_ = P.ninst == 1, roe_ = P.dinv != nullptr;                                    \
+        if (one_ && !roe_) hipLaunchKernelGGL((K<T, X, true, false>), grid, block, 0, L.s, __VA_ARGS__); \
+        else if (!roe_) hipLaunchKernelGGL((K<T, X, false, false>), grid, block, 0, L.s, __VA_ARGS__);   \
+        else if (one_) hipLaunchKernelGGL((K<T, X, true, true>), grid, block, 0, L.s, __VA_ARGS__);      \
+        else hipLaunchKernelGGL((K<T, X, false, true>), grid, block, 0, L.s, __VA_ARGS__);               \
+    } while (0)
+
 template <typename T> void launch_sweep(const Launch &L, const Params<T> &P, int c0, int c1, int mode, int lev1)
 {
     if (c1 <= c0) return;
     dim3 g(nblk(4 * (c1 - c0), L.block[3])), b(L.block[3]);
-    const bool one = P.ninst == 1;
-    if (mode == SW_FWD) {
-        if (one) hipLaunchKernelGGL((k_sweep<T, SW_FWD, true>), g, b, 0, L.s, P, c0, c1, lev1);
-        else hipLaunchKernelGGL((k_sweep<T, SW_FWD, false>), g, b, 0, L.s, P, c0, c1, lev1);
-    } else if (mode == SW_BWD) {
-        if (one) hipLaunchKernelGGL((k_sweep<T, SW_BWD, true>), g, b, 0, L.s, P, c0, c1, lev1);
-        else hipLaunchKernelGGL((k_sweep<T, SW_BWD, false>), g, b, 0, L.s, P, c0, c1, lev1);
-    } else {
-        if (one) hipLaunchKernelGGL((k_sweep<T, SW_TOP, true>), g, b, 0, L.s, P, c0, c1, lev1);
-        else hipLaunchKernelGGL((k_sweep<T, SW_TOP, false>), g, b, 0, L.s, P, c0, c1, lev1);
-    }
+    if (mode == SW_FWD) LAUNCH_SWEEP(k_sweep, SW_FWD, g, b, P, c0, c1, lev1);
+    else if (mode == SW_BWD) LAUNCH_SWEEP(k_sweep, SW_BWD, g, b, P, c0, c1, lev1);
+    else LAUNCH_SWEEP(k_sweep, SW_TOP, g, b, P, c0, c1, lev1);
 }
 template <typename T> void launch_sweep_wg(const Launch &L, const Params<T> &P, const int *lev_off, int nlev, bool fwd)
 {
-    const bool one = P.ninst == 1;
     if (fwd) {
-        if (one) hipLaunchKernelGGL((k_sweep_wg<T, true, true>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
-        else hipLaunchKernelGGL((k_sweep_wg<T, true, false>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
+        LAUNCH_SWEEP(k_sweep_wg, true, dim3(1), dim3(512), P, lev_off, nlev);
     } else {
-        if (one) hipLaunchKernelGGL((k_sweep_wg<T, false, true>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
-        else hipLaunchKernelGGL((k_sweep_wg<T, false, false>), dim3(1), dim3(512), 0, L.s, P, lev_off, nlev);
+        LAUNCH_SWEEP(k_sweep_wg, false, dim3(1), dim3(512), P, lev_off, nlev);
         LAUNCH_ONE(k_update, T, dim3(nblk(P.nc, L.block[3])), dim3(L.block[3]), P);
     }
 }
@@ -1935,15 +2132,16 @@ void launch_sweep_blk(const Launch &L, const Params<T> &P, const int *bl_off, co
                       int ngb, bool fwd, bool update)
 {
     if (ngb <= 0) return;
-    const bool one = P.ninst == 1;
     if (fwd) {
-        if (one) hipLaunchKernelGGL((k_sweep_blk<T, true, true>), dim3(ngb), dim3(64), 0, L.s, P, bl_off, bl_lo, bl_hi);
-        else hipLaunchKernelGGL((k_sweep_blk<T, true, false>), dim3(ngb), dim3(64), 0, L.s, P, bl_off, bl_lo, bl_hi);
+        LAUNCH_SWEEP(k_sweep_blk, true, dim3(ngb), dim3(64), P, bl_off, bl_lo, bl_hi);
     } else {
-        if (one) hipLaunchKernelGGL((k_sweep_blk<T, false, true>), dim3(ngb), dim3(64), 0, L.s, P, bl_off, bl_lo, bl_hi);
-        else hipLaunchKernelGGL((k_sweep_blk<T, false, false>), dim3(ngb), dim3(64), 0, L.s, P, bl_off, bl_lo, bl_hi);
+        LAUNCH_SWEEP(k_sweep_blk, false, dim3(ngb), dim3(64), P, bl_off, bl_lo, bl_hi);
         if (update) LAUNCH_ONE(k_update, T, dim3(nblk(P.nc, L.block[3])), dim3(L.block[3]), P);
     }
+}
+template <typename T> void launch_roe_diag(const Launch &L, const Params<T> &P)
+{
+    LAUNCH_ONE(k_roe_diag, T, dim3(nblk(P.nc, L.block[2])), dim3(L.block[2]), P);
 }
 void launch_wall_distance(const Launch &L, int nc, const double *xc, const double *yc, const int *cinst,
                           const int *woff, const double *wseg, double *dwall)
@@ -1975,6 +2173,7 @@ void launch_copy_instance(const Launch &L, int n, const int *cells, int nc, cons
     template void launch_flux<T>(const Launch &, const Params<T> &);                               \
     template void launch_gather<T>(const Launch &, const Params<T> &);                             \
     template void launch_reduce<T>(const Launch &, const Params<T> &, int);                        \
+    template void launch_roe_diag<T>(const Launch &, const Params<T> &);                           \
     template void launch_sweep<T>(const Launch &, const Params<T> &, int, int, int, int);          \
     template void launch_commit<T>(const Launch &, const Params<T> &, int);                        \
     template void launch_explicit<T>(const Launch &, const Params<T> &);                           \

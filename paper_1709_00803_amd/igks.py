@@ -36,7 +36,7 @@ class igks_options(C.Structure):
                 ("cfl_flux", C.c_double), ("visc_sr", C.c_int), ("mu_law", C.c_int),
                 ("chunk", C.c_int), ("block", C.c_int), ("sweep", C.c_int), ("flux_lanes", C.c_int),
                 ("scheme", C.c_int), ("wall_temp", C.c_double), ("limiter_freeze", C.c_double),
-                ("tau_jump", C.c_int), ("block_passes", C.c_int)]
+                ("tau_jump", C.c_int), ("block_passes", C.c_int), ("lusgs_op", C.c_int)]
 
 
 class igks_residual(C.Structure):
