@@ -64,7 +64,8 @@ typedef struct {
                               that iteration (0: never) */
     int tau_jump;       /* 1: add dt |p_l - p_r| / (p_l + p_r) to the collision time of Eq.34 */
     int lusgs_op;       /* dissipation of the LU-SGS operator: 0 the scalar spectral radius of Eq.20
-                           (lambda_ij I); 1 the first-order Roe matrix |A_ij| (Eq.18) */
+                           (lambda_ij I); 1 the first-order Roe matrix |A_ij| (Eq.18), except on
+                           faces between sweep blocks, which keep lambda_ij I */
 } oigks_options;
 
 typedef struct {
@@ -1206,12 +1207,20 @@ static void sa_face_coef(const oigks_ctx *c, const double *Wi, const double *Wj,
     *off = -0.5 * (qj - fabs(qj)) * S + kf * S / rn;
 }
 
+/* a face between two sweep blocks (reading: the coupling the block sweeps
+ * leave out; with the Roe operator such faces keep the scalar dissipation,
+ * whose larger diagonal keeps the dropped coupling dominated) */
+static int block_face(const oigks_ctx *c, int f)
+{
+    return c->sblk && c->fR[f] >= 0 && c->sblk[c->fL[f]] != c->sblk[c->fR[f]];
+}
+
 /* the dissipation of face f applied to an increment d: lambda_ij d for the
- * scalar operator, |A_ij| d for the Roe matrix (the same from either side:
- * |A(-n)| = |A(n)|) */
+ * scalar operator (and for faces between sweep blocks), |A_ij| d for the Roe
+ * matrix (the same from either side: |A(-n)| = |A(n)|) */
 static void face_diss(const oigks_ctx *c, int f, const double *d, double *out)
 {
-    if (!c->opt.lusgs_op) {
+    if (!c->opt.lusgs_op || block_face(c, f)) {
         for (int k = 0; k < 4; k++) out[k] = c->flam[f] * d[k];
         return;
     }
@@ -1328,6 +1337,10 @@ static void lusgs(oigks_ctx *c)
             for (int k = 0; k < 16; k++) Dm[k] = k % 5 == 0 ? c->area[i] / c->dtimp[i] : 0.0;
             for (int q = c->cfp[i]; q < c->cfp[i + 1]; q++) {
                 int f = c->cff[q];
+                if (block_face(c, f)) {   /* lambda_ij I between sweep blocks */
+                    for (int k = 0; k < 4; k++) Dm[5 * k] += 0.5 * c->flam[f] * c->flen[f];
+                    continue;
+                }
                 for (int k = 0; k < 16; k++) Dm[k] += 0.5 * c->fabsA[16 * f + k] * c->flen[f];
             }
         }

@@ -1469,6 +1469,9 @@ __device__ __forceinline__ void inv4x4(const double *a, double *b)
 // diagonal block D = (Omega/dt) I + 1/2 sum (|A_f| + (lambda_f - smax_f) I) S_f
 // (lambda_f - smax_f, the viscous part of the spectral radius, enters as
 // before; 1/2 sum lambda_f S_f is lsum), inverted and stored for the sweeps.
+// A face to another sweep block keeps lambda_f I: the block sweeps leave its
+// coupling out, and the scalar operator's larger diagonal keeps that
+// omission dominated (with |A| there the block iteration stalls).
 template <typename T, bool ONE>
 __global__ __launch_bounds__(256) void k_roe_diag(Params<T> P)
 {
@@ -1488,7 +1491,7 @@ __global__ __launch_bounds__(256) void k_roe_diag(Params<T> P)
     auto block = [&](const Entries &E, int b) {
 #pragma unroll
         for (int k = 0; k < MAXV; k++) {
-            if (!(E.flag[k] & CF_VALID)) continue;
+            if (!(E.flag[k] & CF_VALID) || (E.flag[k] & CF_OTHER)) continue;
             const int e = MAXV * b + k, f = E.face[k], j = E.nbr[k];
             const double nx = P.enx[e], ny = P.eny[e], hS = 0.5 * P.es[e];
             double wj[5];
@@ -1562,14 +1565,15 @@ __device__ __forceinline__ void first_front_incr(const Params<T> &P, const InstP
 
 // Neighbour term of one cell-face entry in the LU-SGS sweeps (Eq.22 and
 // Eq.31-32): t[0..3] = (J(W_j, n) dW_j - lam dW_j) S / 2 with n pointing out
-// of the cell, t[4] = the SA off-diagonal coefficient times dnu~_j, dW_j read
-// from dsrc.  j < 0: the ghost cell, whose increment follows from the cell's
+// of the cell (the Roe operator: |A| + (lam - smax) I in place of lam,
+// except across sweep blocks, cross), t[4] = the SA off-diagonal coefficient
+// times dnu~_j, dW_j read from dsrc.  j < 0: the ghost cell, whose increment follows from the cell's
 // own dW* (Sec. 2.5).  Neighbours j < lev1 belong to the first wavefront,
 // whose forward increments are not stored (first_front_incr).
 template <typename T, bool ROE>
 __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &ip, const double *W,
                                            const double *w, int f, int e, int j, const T *dws, T cfl, int lev1,
-                                           T *t, const T *dsrc)
+                                           T *t, const T *dsrc, bool cross = false)
 {
     const int N = P.nc;
     double nx = P.enx[e], ny = P.eny[e];   // out of the cell
@@ -1593,7 +1597,7 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
     T jv[4];
     jac_vec<T>(wjt, T(nx), T(ny), dj, jv);
     T h = T(0.5) * S;
-    if (ROE) {
+    if (ROE && !cross) {
         // (|A| + (lambda - smax) I) dW_j: the Roe matrix plus the viscous
         // part of the spectral radius
         const RoeAvg R = roe_avg(w, wj, nx, ny);
@@ -1715,7 +1719,8 @@ __device__ __forceinline__ double sweep_cell(const Params<T> &P, int c, int &ins
                 if (!(fl & CF_VALID) || j < 0) continue;
                 const bool cross = (fl & CF_OTHER) && P.dWx;
                 if (!(fl & CF_LOWER) && !cross) continue;
-                sweep_term<T, ROE>(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t, cross ? P.dWx : P.dW);
+                sweep_term<T, ROE>(P, ip, W, w, E.face[k], MAXV * b + k, j, dws, cfl, 0, t, cross ? P.dWx : P.dW,
+                                   cross);
 #pragma unroll
                 for (int m = 0; m < 4; m++) acc[m] = acc_sub(acc[m], t[m]);
                 acc[4] = acc_add(acc[4], t[4]);
@@ -1813,7 +1818,7 @@ __device__ __forceinline__ double sweep_quad(const Params<T> &P, int c, int q, i
             for (int m = 0; m < 5; m++) t[m] = T(0);
             const bool cross = (fl & CF_OTHER) && P.dWx;
             if ((fl & CF_VALID) && j >= 0 && ((fl & CF_LOWER) || cross))
-                sweep_term<T, ROE>(P, ip, W, w, f, e, j, dws, cfl, cross ? 0 : lev1, t, cross ? P.dWx : P.dW);
+                sweep_term<T, ROE>(P, ip, W, w, f, e, j, dws, cfl, cross ? 0 : lev1, t, cross ? P.dWx : P.dW, cross);
 #pragma unroll
             for (int m = 0; m < 4; m++) acc[m] = quad_fold<true>(acc[m], t[m]);
             acc[4] = quad_fold<false>(acc[4], t[4]);

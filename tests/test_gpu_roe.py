@@ -74,7 +74,8 @@ def test_roe_trajectory_parity(igks, sa):
 @pytest.mark.parametrize("passes", [1, 2])
 def test_roe_sweep_blocks_parity(igks, passes):
     """Sweep blocks on the wave-per-block schedule, one and two block passes
-    (the second takes the cross-block terms with the Roe matrix too)."""
+    (faces between blocks keep the scalar dissipation, in the diagonal
+    blocks and in the second pass's cross-block terms)."""
     m0 = mg.random_hybrid(16, 12, seed=17, tags=TAGS_SYM, jitter=0.25)
     m, blk = mg.block_order(m0, 24)
     flow = (0.3, 2.0, 3e4, 3.0)
@@ -147,14 +148,19 @@ def test_roe_mixed_precision_tracks_fp64(igks):
     assert 0.0 < err < 1e-5
 
 
-def test_roe_plate_converges_faster_to_the_same_answer(igks):
+@pytest.mark.parametrize("blocks", [None, 64])
+def test_roe_plate_converges_faster_to_the_same_answer(igks, blocks):
     """The laminar plate (24x12) from the impulsive start to a 1e-10 drop
-    with either operator: the same state and drag, the Roe operator in at
-    most a third of the iterations."""
-    m = mg.flat_plate(24, 12)
+    with either operator, in natural order and with coupled sweep blocks of
+    64 cells (where the faces between blocks keep the scalar dissipation):
+    the same state and drag, the Roe operator in at most a third of the
+    iterations."""
+    m, blk = mg.flat_plate(24, 12), None
+    if blocks:
+        m, blk = mg.block_order(m, blocks, "coupled")
     runs = {}
     for op in (0, 1):
-        g = igks.Solver(m, cfl_init=10.0, chunk=50, lusgs_op=op)
+        g = igks.Solver(m, cfl_init=10.0, chunk=50, lusgs_op=op, sweep_blocks=blk)
         g.set_freestream(0.3, 0.0, 1e4)
         it = 0
         while it < 20000:
@@ -164,7 +170,7 @@ def test_roe_plate_converges_faster_to_the_same_answer(igks):
                 break
         assert g.residual()["res_drop"] <= 1e-10
         runs[op] = (it, g.get_state(), g.wall_loads()["cd"])
-        say(f"[roe plate] lusgs_op={op}: {it} iterations, cd {runs[op][2]:.12f}")
+        say(f"[roe plate blocks={blocks}] lusgs_op={op}: {it} iterations, cd {runs[op][2]:.12f}")
     (n0, W0, d0), (n1, W1, d1) = runs[0], runs[1]
     assert state_err(W1[:4], W0[:4]) <= 1e-8
     assert d1 == pytest.approx(d0, rel=1e-7)

@@ -113,18 +113,27 @@ def test_roe_abs_of_equal_states_is_abs_jacobian():
     assert np.allclose(ev, np.sort([abs(q - c), abs(q), abs(q), abs(q + c)]), rtol=1e-10)
 
 
-@pytest.mark.parametrize("top", [mg.OUTFLOW, mg.MOVING_WALL], ids=["outflow", "moving_wall"])
-def test_roe_lusgs_solves_factored_system(top):
+@pytest.mark.parametrize("top,blocks", [(mg.OUTFLOW, 0), (mg.MOVING_WALL, 0), (mg.OUTFLOW, 1), (mg.OUTFLOW, 2)],
+                         ids=["outflow", "moving_wall", "blocks", "blocks2"])
+def test_roe_lusgs_solves_factored_system(top, blocks):
     """With the Roe operator the sweeps solve (L + D) D^-1 (D + U) dW = M with
     4x4 blocks D_i = Omega/dt I + 1/2 sum |A_ij| S_ij (dt of Eq.24) and
     off-diagonal blocks 1/2 (J_j - |A_ij|) S_ij, the lagged ghost increments
     of Sec. 2.5 in the backward sweep as in the scalar form.  The stored
     |A_ij| of each face is the Roe matrix of its two cell-centre states (the
     ghost state at a boundary) plus the viscous part of the spectral radius
-    times the identity."""
+    times the identity.  With sweep blocks a face between two blocks keeps
+    lambda_ij I in D, its pair is left out of L and U, and with two passes
+    the second solves again with M - X dW1 on the right (X: those pairs'
+    1/2 (J_j - lambda_ij I) S_ij)."""
     tags = dict(bottom=mg.WALL, top=top, left=mg.FREESTREAM, right=mg.SYMMETRY)
     m = mg.colour_order(mg.random_hybrid(5, 4, seed=7, tags=tags))[0]
     o = po.Oracle(m, lusgs_op=1)
+    blk = mg.sweep_blocks(m, 7) if blocks else np.zeros(m.n_cells, dtype=np.int32)
+    if blocks:
+        assert blk.max() >= 3
+        o.set_sweep_blocks(blk)
+        o.set_block_passes(blocks)
     o.set_freestream(0.4, 5.0, 1e3)
     W = smooth_state(o, 0.1, 3)
     o.set_state(W)
@@ -147,11 +156,17 @@ def test_roe_lusgs_solves_factored_system(top):
         want, _ = _abs_by_eig(W[:, i], Wj, nx, ny)
         assert np.abs(A[k] - vis * np.eye(4) - want).max() <= 1e-12 * np.abs(want).max()
     Dm = np.zeros((4 * n, 4 * n)); L = np.zeros_like(Dm); U = np.zeros_like(Dm); G = np.zeros_like(Dm)
+    X = np.zeros_like(Dm)
     for i in range(n):
         Dm[4 * i:4 * i + 4, 4 * i:4 * i + 4] = dbg["lamc"][i] / cfl * np.eye(4)
     for k in range(o.nf):
         i, j = f["fl"][k], f["fr"][k]
         nx, ny, S = f["nx"][k], f["ny"][k], f["len"][k]
+        if j >= 0 and blk[i] != blk[j]:
+            for a, b, sg in ((i, j, 1.0), (j, i, -1.0)):
+                Dm[4 * a:4 * a + 4, 4 * a:4 * a + 4] += 0.5 * lam[k] * S * np.eye(4)
+                X[4 * a:4 * a + 4, 4 * b:4 * b + 4] += 0.5 * (_jac_fd(W[:, b], sg * nx, sg * ny) - lam[k] * np.eye(4)) * S
+            continue
         for a in (i, j):
             if a >= 0:
                 Dm[4 * a:4 * a + 4, 4 * a:4 * a + 4] += 0.5 * A[k] * S
@@ -177,10 +192,16 @@ def test_roe_lusgs_solves_factored_system(top):
     Mv = M[:4].T.reshape(-1)
     dws = np.linalg.solve(L + Dm, Mv)
     want = np.linalg.solve(Dm + U, (Dm - G) @ dws)
+    if blocks == 2:
+        dws = np.linalg.solve(L + Dm, Mv - X @ want)
+        want = np.linalg.solve(Dm + U, (Dm - G) @ dws)
     got = dW[:4].T.reshape(-1)
     assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
     # the scalar operator solves another system
     s = po.Oracle(m)
+    if blocks:
+        s.set_sweep_blocks(blk)
+        s.set_block_passes(blocks)
     s.set_freestream(0.4, 5.0, 1e3)
     s.set_state(W)
     other = s.lusgs_solve(cfl)[:4].T.reshape(-1)
