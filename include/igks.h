@@ -115,7 +115,9 @@ typedef struct igks_options {
                            the viscous part of lambda_ij times I, so that D becomes a 4x4 block per
                            cell (inverted once per iteration, 16 values per cell in the workspace).
                            The steady answer is the same; the implicit iteration converges in fewer
-                           steps.  The SA equation keeps its scalar form.  Other values: IGKS_EINVAL. */
+                           steps.  The SA equation keeps its scalar form, and faces between sweep
+                           blocks keep lambda_ij I (with |A| there the block iteration stalls).
+                           Ignored by the explicit scheme.  Other values: IGKS_EINVAL. */
 } igks_options;
 
 typedef struct igks_residual {

@@ -240,11 +240,37 @@ def test_batch_bookkeeping():
         igks.igks_destroy(ctx)
 
 
+def test_roe_operator_workspace():
+    """The Roe-matrix LU-SGS option adds the inverted 4x4 diagonal blocks to
+    the workspace, 16 values per cell in the sweeps' precision (rounded up
+    to the workspace's 256-byte alignment), and nothing for the explicit
+    scheme, which has no sweeps."""
+    m = mg.random_hybrid(9, 7, seed=3, tags=dict(bottom=mg.WALL))
+    sizes = {}
+    for key, opt in (("scalar", {}), ("roe", dict(lusgs_op=1)), ("roe_mixed", dict(lusgs_op=1, precision=1)),
+                     ("mixed", dict(precision=1)), ("explicit", dict(scheme=1)),
+                     ("explicit_roe", dict(scheme=1, lusgs_op=1))):
+        rc, ctx = ctx_for(**opt)
+        assert rc == igks.IGKS_OK
+        try:
+            assert upload(ctx, m) == igks.IGKS_OK
+            nc = info(ctx)[1][0]
+            sz = C.c_size_t()
+            assert igks.igks_workspace_size(ctx, C.byref(sz)) == igks.IGKS_OK
+            sizes[key] = sz.value
+        finally:
+            igks.igks_destroy(ctx)
+    pad = lambda b: (b + 255) // 256 * 256
+    assert sizes["roe"] - sizes["scalar"] == pad(16 * nc * 8)
+    assert sizes["roe_mixed"] - sizes["mixed"] == pad(16 * nc * 4)
+    assert sizes["explicit_roe"] == sizes["explicit"]
+
+
 def test_call_order_and_option_errors():
     for bad in (dict(block=96), dict(block=512), dict(sweep=4), dict(precision=5), dict(chunk=-1),
                 dict(flux_lanes=3), dict(wall_temp=-1.0), dict(wall_temp=float("nan")), dict(limiter_freeze=-0.1),
                 dict(limiter_freeze=1.0), dict(tau_jump=2), dict(block_passes=3), dict(block_passes=-1),
-                dict(block_passes=2, sweep=1), dict(block_passes=2, sweep=2)):
+                dict(block_passes=2, sweep=1), dict(block_passes=2, sweep=2), dict(lusgs_op=2), dict(lusgs_op=-1)):
         rc, ctx = ctx_for(**bad)
         assert rc == igks.IGKS_EINVAL, bad
         assert not ctx.value
