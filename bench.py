@@ -456,7 +456,7 @@ def time_to_drop_joukowski(igks, mg):
 def roe_time_to_solution(igks, mg):
     """The small cases again with the Roe-matrix LU-SGS operator
     (lusgs_op = 1): the plate to a 1e-10 drop (sweep blocks and natural
-    order), the cavity and the turbulent plate to Eq.40 <= 3e-8, the 40k
+    order), the cavity (both) and the turbulent plate to Eq.40 <= 3e-8, the 40k
     Joukowski to 1e-10 (blocks of 256).  The last two do not converge with
     it (the iteration stalls and the Eq.25 law holds the CFL number low;
     the 40k Joukowski's impulsive start at CFL 1000 gives a non-physical
@@ -467,6 +467,8 @@ def roe_time_to_solution(igks, mg):
             "plate_fp64": time_to_drop(igks, mg, igks.IGKS_FP64, lusgs_op=1),
             "plate_fp64_natural_order": time_to_drop(igks, mg, igks.IGKS_FP64, blocks=None, lusgs_op=1),
             "cavity_to_eq40": time_to_converge_cavity(igks, mg, label="cavity roe", lusgs_op=1),
+            "cavity_to_eq40_natural_order": time_to_converge_cavity(igks, mg, label="cavity roe natural order",
+                                                                    blocks=None, lusgs_op=1),
             "turbulent_plate_to_eq40": time_to_converge_turbulent_plate(igks, mg, label="turbulent plate roe",
                                                                         lusgs_op=1),
             "jouk40k_blocks_fp64": guarded(run_to_drop, igks, mb, flow, igks.IGKS_FP64, blk, max_it=60000,
