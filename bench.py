@@ -466,6 +466,7 @@ def roe_time_to_solution(igks, mg):
     return {"operator": "Roe matrix |A| = R|Lambda|L at the Roe average, |lambda| >= 0.1 c, 4x4 diagonal blocks",
             "plate_fp64": time_to_drop(igks, mg, igks.IGKS_FP64, lusgs_op=1),
             "plate_fp64_natural_order": time_to_drop(igks, mg, igks.IGKS_FP64, blocks=None, lusgs_op=1),
+            "batched_plates": time_to_drop_batch(igks, mg, lusgs_op=1),
             "cavity_to_eq40": time_to_converge_cavity(igks, mg, label="cavity roe", lusgs_op=1),
             "cavity_to_eq40_natural_order": time_to_converge_cavity(igks, mg, label="cavity roe natural order",
                                                                     blocks=None, lusgs_op=1),
@@ -633,15 +634,16 @@ def time_to_converge_turbulent_plate(igks, mg, max_it=30000, chunk=500, label="t
                 paper_iterations=5340, paper_seconds=1087.7)
 
 
-def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000, blocks=SMALL_BLOCKS):
+def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000, blocks=SMALL_BLOCKS, **opt):
     """Eight plate flow conditions (DROP_BATCH) to a `target` drop with sweep
     blocks of `blocks` cells: one mixed-precision batch against the eight
-    FP64 single runs one after another."""
+    FP64 single runs one after another; opt: further solver options
+    (lusgs_op), the same for both."""
     import torch
     m, blk = plate_mesh(mg, blocks)
     flows = [(ma, 0.0, re, -1.0) for ma, re in DROP_BATCH]
     b = igks.BatchSolver([m] * len(flows), precision=igks.IGKS_MIXED, cfl_init=10.0, chunk=100,
-                         sweep_blocks=None if blk is None else [blk] * len(flows))
+                         sweep_blocks=None if blk is None else [blk] * len(flows), **opt)
     for i, f in enumerate(flows):
         b.set_freestream(i, *f)
     torch.cuda.synchronize()
@@ -659,7 +661,7 @@ def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000, blocks=SMALL_BLOCKS
     t_batch = time.perf_counter() - t0
     t_seq, its_seq = 0.0, []
     for f in flows:
-        s = igks.Solver(m, precision=igks.IGKS_FP64, cfl_init=10.0, chunk=100, sweep_blocks=blk)
+        s = igks.Solver(m, precision=igks.IGKS_FP64, cfl_init=10.0, chunk=100, sweep_blocks=blk, **opt)
         s.set_freestream(*f)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -673,7 +675,7 @@ def time_to_drop_batch(igks, mg, target=1e-10, max_it=20000, blocks=SMALL_BLOCKS
         t_seq += time.perf_counter() - t0
         its_seq.append(k)
         say(f"plate {f[:3]} alone: {k} iterations")
-    return dict(instances=len(flows), flows_ma_re=DROP_BATCH, sweep_blocks=blocks, batch_mixed_seconds=round(t_batch, 4),
+    return dict(**opt, instances=len(flows), flows_ma_re=DROP_BATCH, sweep_blocks=blocks, batch_mixed_seconds=round(t_batch, 4),
                 batch_iterations_to_target=first, fp64_sequential_seconds=round(t_seq, 4),
                 fp64_iterations_to_target=its_seq, speedup=round(t_seq / t_batch, 3))
 
