@@ -219,7 +219,8 @@ int igks_bind_workspace(igks_ctx *ctx, void *dptr, size_t bytes);
  * data uploaded, wall distance computed, state to be set by
  * igks_set_freestream); no device memory is allocated or freed.
  * IGKS_ENOMEM (nothing bound) if igks_workspace_size exceeds 64 MiB (about
- * 70 000 cells).  The array is one per GPU and shared: binding it to a
+ * 70 000 cells; fewer with lusgs_op 1, whose blocks take 128 bytes per cell in
+ * FP64).  The array is one per GPU and shared: binding it to a
  * context overwrites what it held for an earlier context on that GPU, which
  * then gets IGKS_EINVAL from every call that needs its workspace until it
  * binds one again; calls of different contexts on the same GPU that
