@@ -472,6 +472,9 @@ def roe_time_to_solution(igks, mg):
                                                                     blocks=None, lusgs_op=1),
             "turbulent_plate_to_eq40": time_to_converge_turbulent_plate(igks, mg, label="turbulent plate roe",
                                                                         lusgs_op=1),
+            "kinetic_plate_fp64": time_to_drop(igks, mg, igks.IGKS_FP64, lusgs_op=2),
+            "kinetic_turbulent_plate_to_eq40": time_to_converge_turbulent_plate(
+                igks, mg, label="turbulent plate roe kinetic", lusgs_op=2),
             "jouk40k_blocks_fp64": guarded(run_to_drop, igks, mb, flow, igks.IGKS_FP64, blk, max_it=60000,
                                            label="jouk40k blocks fp64 roe", lusgs_op=1)}
 

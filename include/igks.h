@@ -117,6 +117,11 @@ typedef struct igks_options {
                            The steady answer is the same; the implicit iteration converges in fewer
                            steps.  The SA equation keeps its scalar form, and faces between sweep
                            blocks keep lambda_ij I (with |A| there the block iteration stalls).
+                           2: the same matrix with each eigenvalue magnitude |s| replaced by the
+                           mean of |u| for normal velocities u spread as a Maxwellian of temperature
+                           c^2 / gamma about s, s erf(s / sqrt(2RT)) + sqrt(2RT / pi) exp(-s^2 / 2RT)
+                           (at least 0.67 c): slower than 1 where 1 converges, but it also converges
+                           the SA plate and the flows where 1 stalls.
                            Ignored by the explicit scheme.  Other values: IGKS_EINVAL. */
 } igks_options;
 

@@ -65,7 +65,8 @@ typedef struct {
     int tau_jump;       /* 1: add dt |p_l - p_r| / (p_l + p_r) to the collision time of Eq.34 */
     int lusgs_op;       /* dissipation of the LU-SGS operator: 0 the scalar spectral radius of Eq.20
                            (lambda_ij I); 1 the first-order Roe matrix |A_ij| (Eq.18), except on
-                           faces between sweep blocks, which keep lambda_ij I */
+                           faces between sweep blocks, which keep lambda_ij I; 2 the same with the
+                           kinetic wave magnitudes (roe_abs) */
 } oigks_options;
 
 typedef struct {
@@ -521,7 +522,7 @@ EXPORT int oigks_create(oigks_ctx **out, const oigks_options *opt)
     *out = c;
     if (!(c->opt.wall_temp >= 0.0) || !isfinite(c->opt.wall_temp)) { seterr(c, "wall_temp must be >= 0"); return -1; }
     if (c->opt.tau_jump < 0 || c->opt.tau_jump > 1) { seterr(c, "tau_jump must be 0 or 1"); return -1; }
-    if (c->opt.lusgs_op < 0 || c->opt.lusgs_op > 1) { seterr(c, "lusgs_op must be 0 or 1"); return -1; }
+    if (c->opt.lusgs_op < 0 || c->opt.lusgs_op > 2) { seterr(c, "lusgs_op must be 0, 1 or 2"); return -1; }
     if (!(c->opt.limiter_freeze >= 0.0) || !(c->opt.limiter_freeze < 1.0)) {
         seterr(c, "limiter_freeze must be in [0, 1)");
         return -1;
@@ -855,12 +856,18 @@ static const double ROE_DELTA = 0.1;
 
 /* |A| = R |Lambda| L of the Euler flux Jacobian in direction n at the Roe
  * average of the states Wl, Wr (the first-order Roe scheme's dissipation
- * matrix, Eq.18), with the eigenvalues q - c, q, q, q + c limited below by
- * ROE_DELTA c, plus vis times the identity (the viscous part of the
+ * matrix, Eq.18), plus vis times the identity (the viscous part of the
  * spectral radius).  Written out as the product of the right eigenvectors,
  * the eigenvalue magnitudes and the left eigenvectors of the conservative
- * variables (rho, rho u, rho v, rho E). */
-static void roe_abs(const double *Wl, const double *Wr, double nx, double ny, double vis, double *A)
+ * variables (rho, rho u, rho v, rho E).  The magnitudes of the eigenvalues
+ * s = q - c, q, q, q + c: kin 0, |s| limited below by ROE_DELTA c; kin 1
+ * (reading: the dissipation a wave of speed s gets when its particles'
+ * normal velocities spread as a Maxwellian of temperature RT = c^2 / gamma
+ * about s and are split by sign at the interface, as in the collisionless
+ * part of the kinetic flux, Eq.13 with tau >> dt), the mean of |u| for
+ * u ~ N(s, RT): s erf(s / sqrt(2RT)) + sqrt(2RT / pi) exp(-s^2 / (2RT)),
+ * which is at least |s| and sqrt(2RT / pi) at s = 0. */
+static void roe_abs(const double *Wl, const double *Wr, double nx, double ny, double vis, int kin, double *A)
 {
     const double b = GAMMA - 1.0;
     double rl = Wl[0], rr = Wr[0];
@@ -871,8 +878,13 @@ static void roe_abs(const double *Wl, const double *Wr, double nx, double ny, do
     double u = (sl * ul + sr * ur) / (sl + sr), v = (sl * vl + sr * vr) / (sl + sr), H = (sl * Hl + sr * Hr) / (sl + sr);
     double k = 0.5 * (u * u + v * v), c2 = b * (H - k), c = sqrt(c2);
     double q = u * nx + v * ny, qt = -u * ny + v * nx;
-    double lm[4] = {fabs(q - c), fabs(q), fabs(q), fabs(q + c)};
-    for (int m = 0; m < 4; m++) if (lm[m] < ROE_DELTA * c) lm[m] = ROE_DELTA * c;
+    double lm[4] = {q - c, q, q, q + c};
+    const double rt2 = 2.0 * c2 / GAMMA;   /* 2RT */
+    for (int m = 0; m < 4; m++) {
+        const double sv = lm[m];
+        if (kin) lm[m] = sv * erf(sv / sqrt(rt2)) + sqrt(rt2 / M_PI) * exp(-sv * sv / rt2);
+        else lm[m] = fabs(sv) < ROE_DELTA * c ? ROE_DELTA * c : fabs(sv);
+    }
     double R[4][4] = {{1.0, 1.0, 0.0, 1.0},
                       {u - c * nx, u, -ny, u + c * nx},
                       {v - c * ny, v, nx, v + c * ny},
@@ -1133,7 +1145,8 @@ static int residual(oigks_ctx *c)
                 lam += 2.0 * 0.5 * (mi / Wi[0] + mj / WjC[0]) / rn;
             }
             c->flam[f] = lam;
-            if (c->opt.lusgs_op) roe_abs(Wi, WjC, nx, ny, lam - (li > lj ? li : lj), &c->fabsA[16 * f]);
+            if (c->opt.lusgs_op)
+                roe_abs(Wi, WjC, nx, ny, lam - (li > lj ? li : lj), c->opt.lusgs_op == 2, &c->fabsA[16 * f]);
         }
         /* SA face terms (Eq.28-30) from cell-centre values */
         if (c->sa) {
@@ -1657,9 +1670,9 @@ EXPORT int oigks_get_roe(const oigks_ctx *c, double *absA)
 }
 
 /* ---------------- kernel-level entry points used by the pins ---------------- */
-EXPORT void oigks_roe_abs(const double *Wl, const double *Wr, double nx, double ny, double vis, double *A)
+EXPORT void oigks_roe_abs(const double *Wl, const double *Wr, double nx, double ny, double vis, int kin, double *A)
 {
-    roe_abs(Wl, Wr, nx, ny, vis, A);
+    roe_abs(Wl, Wr, nx, ny, vis, kin, A);
 }
 EXPORT void oigks_moments(double U, double lam, int kind, int n, double *out)
 {

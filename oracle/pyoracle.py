@@ -76,7 +76,7 @@ def lib():
         L.oigks_set_sweep_blocks.argtypes = [p, C.POINTER(C.c_int)]
         L.oigks_set_block_passes.argtypes = [p, i]
         L.oigks_get_roe.argtypes = [p, dp]
-        L.oigks_roe_abs.argtypes = [dp, dp, d, d, d, dp]
+        L.oigks_roe_abs.argtypes = [dp, dp, d, d, d, i, dp]
         _lib = L
     return _lib
 
@@ -303,10 +303,10 @@ def sa_source(nut, nu, d, omega):
     return out
 
 
-def roe_abs(Wl, Wr, nx, ny, vis=0.0):
+def roe_abs(Wl, Wr, nx, ny, vis=0.0, kinetic=False):
     Wl, pl = _d(Wl); Wr, pr = _d(Wr)
     out = np.zeros(16)
-    lib().oigks_roe_abs(pl, pr, nx, ny, vis, out.ctypes.data_as(C.POINTER(C.c_double)))
+    lib().oigks_roe_abs(pl, pr, nx, ny, vis, int(kinetic), out.ctypes.data_as(C.POINTER(C.c_double)))
     return out.reshape(4, 4)
 
 

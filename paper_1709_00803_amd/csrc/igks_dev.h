@@ -93,6 +93,7 @@ struct Params {
     T *dinv;                   // Roe-matrix operator: the inverse of each cell's 4x4 LU-SGS
                                // diagonal block, entry (r, k) at (4 r + k) nc + c; null with
                                // the scalar operator
+    int roe_kin;               // Roe-matrix operator with the kinetic wave magnitudes
     const double *xc, *yc, *area, *lsinv, *dwall;
     const double *vtx;         // vertex offsets from the centroid: (x, y) of slot v of block b at (2v) nb + b
     int nb;                    // entry / vertex blocks: nc + overflow blocks

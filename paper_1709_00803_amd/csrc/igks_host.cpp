@@ -663,7 +663,7 @@ WsMap layout(const Global &G, int ninst, const igks_options &o, int hist_cap)
     // the first pass's increments (two block passes)
     w.dW1 = L.add(o.block_passes == 2 ? 5 * N * (o.precision == IGKS_MIXED ? sizeof(float) : D) : 0);
     // the inverted 4x4 LU-SGS diagonal blocks (Roe-matrix operator)
-    w.dinv = L.add(o.lusgs_op == 1 && o.scheme == 0 ? 16 * N * (o.precision == IGKS_MIXED ? sizeof(float) : D) : 0);
+    w.dinv = L.add(o.lusgs_op >= 1 && o.scheme == 0 ? 16 * N * (o.precision == IGKS_MIXED ? sizeof(float) : D) : 0);
     w.xc = L.add(N * D); w.yc = L.add(N * D); w.area = L.add(N * D); w.lsinv = L.add(3 * N * D);
     w.dwall = L.add(N * D); w.vtx = L.add(2 * MAXV * (size_t)G.NB * D);
     w.cinst = L.add(N * I); w.finst = L.add(F * I); w.icell = L.add(N * I); w.ioff = L.add((NI + 1) * I);
@@ -715,7 +715,8 @@ void fill_params(igks_ctx *c, Params<T> &P)
     P.Wa = D(w.Wa); P.Wb = D(w.Wb); P.grad = D(w.grad); P.lamc = D(w.lamc); P.vort = D(w.vort); P.nu = D(w.nu);
     P.M = D(w.M); P.lsum = D(w.lsum); P.sadiag = D(w.sadiag); P.r2 = D(w.r2); P.dW = (T *)(b + w.dW.off);
     P.dWx = nullptr;
-    P.dinv = c->opt.lusgs_op == 1 && c->opt.scheme == 0 ? (T *)(b + w.dinv.off) : nullptr;
+    P.dinv = c->opt.lusgs_op >= 1 && c->opt.scheme == 0 ? (T *)(b + w.dinv.off) : nullptr;
+    P.roe_kin = c->opt.lusgs_op == 2;
     P.xc = D(w.xc); P.yc = D(w.yc); P.area = D(w.area); P.lsinv = D(w.lsinv); P.dwall = D(w.dwall); P.vtx = D(w.vtx);
     P.nb = c->g.NB;
     P.cf_face = In(w.cf_face); P.cf_nbr = In(w.cf_nbr); P.cf_flag = In(w.cf_flag);
@@ -1099,7 +1100,7 @@ int igks_batch_create(igks_ctx **out, const igks_options *opt, void *hip_stream,
     if (c->opt.block_passes == 0) c->opt.block_passes = 1;
     if (c->opt.block_passes < 1 || c->opt.block_passes > 2) { delete c; return IGKS_EINVAL; }
     if (c->opt.block_passes == 2 && c->opt.sweep != 0 && c->opt.sweep != 3) { delete c; return IGKS_EINVAL; }
-    if (c->opt.lusgs_op < 0 || c->opt.lusgs_op > 1) { delete c; return IGKS_EINVAL; }
+    if (c->opt.lusgs_op < 0 || c->opt.lusgs_op > 2) { delete c; return IGKS_EINVAL; }
     for (int k = 0; k < NCLASS; k++) c->block[k] = c->opt.block;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;

@@ -1382,22 +1382,31 @@ __device__ __forceinline__ V quad_fold(V a, V t)
     return acc_add(acc_add(acc_add(acc_add(a, t0), t1), t2), t3);
 }
 
-// ---- Roe-matrix LU-SGS operator (option lusgs_op = 1) ----
+// ---- Roe-matrix LU-SGS operator (option lusgs_op = 1 or 2) ----
 // The dissipation of the first-order Roe flux (Eq.18) in place of the
 // scalar spectral radius of Eq.20: |A| = R |Lambda| L of the Euler flux
-// Jacobian at the Roe average of the two cell-centre states, the eigenvalue
-// magnitudes |q - c|, |q|, |q|, |q + c| held at least at ROE_DELTA c.
+// Jacobian at the Roe average of the two cell-centre states.  The magnitudes
+// of the eigenvalues s = q - c, q, q, q + c: option 1, |s| held at least at
+// ROE_DELTA c; option 2, the mean of |u| for u ~ N(s, RT), RT = c^2 / gamma,
+// s erf(s / sqrt(2RT)) + sqrt(2RT / pi) exp(-s^2 / (2RT)) (the spread a
+// Maxwellian gives each wave at the interface).
 
 constexpr double ROE_DELTA = 0.1;
 
 // Roe average of states a (the cell) and b (the neighbour or ghost) for the
 // normal n out of the cell; smax = max(|q_a| + c_a, |q_b| + c_b), the
-// inviscid part of the face's spectral radius
+// inviscid part of the face's spectral radius; m0, m1, m3 the magnitudes of
+// the eigenvalues q - c, q, q + c
 struct RoeAvg {
-    double u, v, H, k, c, q, qt, smax;
+    double u, v, H, k, c, q, qt, smax, m0, m1, m3;
 };
 
-__device__ __forceinline__ RoeAvg roe_avg(const double *a, const double *b, double nx, double ny)
+__device__ __forceinline__ double kin_mag(double s, double rt2)
+{
+    return s * erf(s / sqrt(rt2)) + sqrt(rt2 * (1.0 / M_PI)) * exp(-s * s / rt2);
+}
+
+__device__ __forceinline__ RoeAvg roe_avg(const double *a, const double *b, double nx, double ny, bool kin)
 {
     const double g1 = GAMMA - 1.0;
     const double ra = a[0], rb = b[0];
@@ -1413,6 +1422,17 @@ __device__ __forceinline__ RoeAvg roe_avg(const double *a, const double *b, doub
     R.q = R.u * nx + R.v * ny;
     R.qt = -R.u * ny + R.v * nx;
     R.smax = fmax(fabs(ua * nx + va * ny) + sqrt(GAMMA * pa / ra), fabs(ub * nx + vb * ny) + sqrt(GAMMA * pb / rb));
+    if (kin) {
+        const double rt2 = 2.0 * R.c * R.c / GAMMA;   // 2RT
+        R.m0 = kin_mag(R.q - R.c, rt2);
+        R.m1 = kin_mag(R.q, rt2);
+        R.m3 = kin_mag(R.q + R.c, rt2);
+    } else {
+        const double fl = ROE_DELTA * R.c;
+        R.m0 = fmax(fabs(R.q - R.c), fl);
+        R.m1 = fmax(fabs(R.q), fl);
+        R.m3 = fmax(fabs(R.q + R.c), fl);
+    }
     return R;
 }
 
@@ -1424,12 +1444,10 @@ __device__ __forceinline__ void roe_apply(const RoeAvg &R, double nx, double ny,
     const double ic = 1.0 / R.c, g1c2 = (GAMMA - 1.0) * ic * ic;
     const double dpc = g1c2 * (R.k * d[0] - R.u * d[1] - R.v * d[2] + d[3]);
     const double dun = (-R.q * d[0] + nx * d[1] + ny * d[2]) * ic;
-    const double fl = ROE_DELTA * R.c;
-    const double a0 = 0.5 * (dpc - dun) * fmax(fabs(R.q - R.c), fl);
-    const double a3 = 0.5 * (dpc + dun) * fmax(fabs(R.q + R.c), fl);
-    const double m1 = fmax(fabs(R.q), fl);
-    const double a1 = (d[0] - dpc) * m1;
-    const double a2 = (-R.qt * d[0] - ny * d[1] + nx * d[2]) * m1;
+    const double a0 = 0.5 * (dpc - dun) * R.m0;
+    const double a3 = 0.5 * (dpc + dun) * R.m3;
+    const double a1 = (d[0] - dpc) * R.m1;
+    const double a2 = (-R.qt * d[0] - ny * d[1] + nx * d[2]) * R.m1;
     out[0] = a0 + a1 + a3;
     out[1] = a0 * (R.u - R.c * nx) + a1 * R.u - a2 * ny + a3 * (R.u + R.c * nx);
     out[2] = a0 * (R.v - R.c * ny) + a1 * R.v + a2 * nx + a3 * (R.v + R.c * ny);
@@ -1501,7 +1519,7 @@ __global__ __launch_bounds__(256) void k_roe_diag(Params<T> P)
             } else {
                 ghost(ip, P.fbc[f], w, nx, ny, wj);
             }
-            const RoeAvg R = roe_avg(w, wj, nx, ny);
+            const RoeAvg R = roe_avg(w, wj, nx, ny, P.roe_kin);
 #pragma unroll
             for (int col = 0; col < 4; col++) {
                 double d[4] = {0.0, 0.0, 0.0, 0.0}, o[4];
@@ -1600,7 +1618,7 @@ __device__ __forceinline__ void sweep_term(const Params<T> &P, const InstParam &
     if (ROE && !cross) {
         // (|A| + (lambda - smax) I) dW_j: the Roe matrix plus the viscous
         // part of the spectral radius
-        const RoeAvg R = roe_avg(w, wj, nx, ny);
+        const RoeAvg R = roe_avg(w, wj, nx, ny, P.roe_kin);
         const double dd[4] = {double(dj[0]), double(dj[1]), double(dj[2]), double(dj[3])};
         double ad[4];
         roe_apply(R, nx, ny, dd, ad);

@@ -23,8 +23,8 @@ def igks():
     return m
 
 
-def oracle(m, flow, blk=None, passes=1, **opt):
-    o = po.Oracle(m, threads=sens.host_threads(), lusgs_op=1, **opt)
+def oracle(m, flow, blk=None, passes=1, op=1, **opt):
+    o = po.Oracle(m, threads=sens.host_threads(), lusgs_op=op, **opt)
     if blk is not None:
         o.set_sweep_blocks(blk)
         o.set_block_passes(passes)
@@ -37,19 +37,20 @@ def state_err(Wg, Wo):
     return (np.abs(Wg - Wo) / np.maximum(scale, 1e-300)).max()
 
 
-@pytest.mark.parametrize("sa", [False, True])
-def test_roe_trajectory_parity(igks, sa):
+@pytest.mark.parametrize("sa,op", [(False, 1), (True, 1), (True, 2)])
+def test_roe_trajectory_parity(igks, sa, op):
     """Natural (wavefront) order, the launch-per-wavefront and the
-    one-workgroup sweeps: both follow the oracle's Roe-operator iterates,
-    CFL law included, and agree with each other to rounding."""
+    one-workgroup sweeps: both follow the oracle's Roe-operator iterates
+    (op 2: the kinetic wave magnitudes), CFL law included, and agree with
+    each other to rounding."""
     m = mg.colour_order(mg.random_hybrid(14, 10, seed=5, tags=TAGS_SYM, jitter=0.25))[0]
     flow = (0.3, 2.0, 3e4 if sa else 3e3, 3.0 if sa else -1.0)
-    tag = f"roe trajectory sa={sa}"
+    tag = f"roe trajectory sa={sa} op={op}"
     say("case", tag)
-    o = oracle(m, flow, cfl_init=5.0)
+    o = oracle(m, flow, op=op, cfl_init=5.0)
     runs = []
     for sweep in (1, 2):
-        g = igks.Solver(m, cfl_init=5.0, chunk=5, sweep=sweep, lusgs_op=1)
+        g = igks.Solver(m, cfl_init=5.0, chunk=5, sweep=sweep, lusgs_op=op)
         assert g.schedule()[4] == sweep
         g.set_freestream(*flow)
         runs.append(g)
@@ -71,18 +72,18 @@ def test_roe_trajectory_parity(igks, sa):
         assert abs(rg["res_l2"] - ro["res_l2"]) <= 1e-8 * ro["res_l2"]
 
 
-@pytest.mark.parametrize("passes", [1, 2])
-def test_roe_sweep_blocks_parity(igks, passes):
+@pytest.mark.parametrize("passes,op", [(1, 1), (2, 1), (2, 2)])
+def test_roe_sweep_blocks_parity(igks, passes, op):
     """Sweep blocks on the wave-per-block schedule, one and two block passes
     (faces between blocks keep the scalar dissipation, in the diagonal
     blocks and in the second pass's cross-block terms)."""
     m0 = mg.random_hybrid(16, 12, seed=17, tags=TAGS_SYM, jitter=0.25)
     m, blk = mg.block_order(m0, 24)
     flow = (0.3, 2.0, 3e4, 3.0)
-    tag = f"roe sweep blocks passes={passes}"
+    tag = f"roe sweep blocks passes={passes} op={op}"
     say("case", tag, m.n_cells, "cells,", int(blk.max()) + 1, "blocks")
-    o = oracle(m, flow, blk, passes, cfl_init=5.0)
-    g = igks.Solver(m, cfl_init=5.0, chunk=5, sweep=3, sweep_blocks=blk, block_passes=passes, lusgs_op=1)
+    o = oracle(m, flow, blk, passes, op, cfl_init=5.0)
+    g = igks.Solver(m, cfl_init=5.0, chunk=5, sweep=3, sweep_blocks=blk, block_passes=passes, lusgs_op=op)
     g.set_freestream(*flow)
     for step in range(4):
         o.iterate(5)
@@ -175,3 +176,28 @@ def test_roe_plate_converges_faster_to_the_same_answer(igks, blocks):
     assert state_err(W1[:4], W0[:4]) <= 1e-8
     assert d1 == pytest.approx(d0, rel=1e-7)
     assert 3 * n1 <= n0
+
+
+def test_roe_kinetic_converges_where_the_floor_stalls(igks):
+    """The 64x32 plate at Ma 0.2, Re 1.2e4 on coupled blocks of 128: with the
+    Roe matrix and |s| held at 0.1 c (op 1) the iteration stalls near a drop
+    of 1e-2; with the kinetic wave magnitudes (op 2) it reaches 1e-10, to
+    the scalar operator's drag."""
+    m, blk = mg.block_order(mg.flat_plate(), 128, "coupled")
+    cd, its = {}, {}
+    for op in (0, 1, 2):
+        g = igks.Solver(m, cfl_init=10.0, chunk=100, sweep_blocks=blk, lusgs_op=op)
+        g.set_freestream(0.2, 0.0, 1.2e4)
+        it = 0
+        while it < (3000 if op == 1 else 12000):
+            g.iterate(100)
+            it += 100
+            if g.residual()["res_drop"] <= 1e-10:
+                break
+        its[op], cd[op] = it, g.wall_loads()["cd"]
+        say(f"[roe kinetic plate] lusgs_op={op}: {it} iterations, drop {g.residual()['res_drop']:.2e}, cd {cd[op]:.12f}")
+        if op == 1:
+            assert g.residual()["res_drop"] > 1e-6
+        else:
+            assert g.residual()["res_drop"] <= 1e-10
+    assert cd[2] == pytest.approx(cd[0], rel=1e-7)

@@ -248,6 +248,7 @@ def test_roe_operator_workspace():
     m = mg.random_hybrid(9, 7, seed=3, tags=dict(bottom=mg.WALL))
     sizes = {}
     for key, opt in (("scalar", {}), ("roe", dict(lusgs_op=1)), ("roe_mixed", dict(lusgs_op=1, precision=1)),
+                     ("kinetic", dict(lusgs_op=2)),
                      ("mixed", dict(precision=1)), ("explicit", dict(scheme=1)),
                      ("explicit_roe", dict(scheme=1, lusgs_op=1))):
         rc, ctx = ctx_for(**opt)
@@ -262,6 +263,7 @@ def test_roe_operator_workspace():
             igks.igks_destroy(ctx)
     pad = lambda b: (b + 255) // 256 * 256
     assert sizes["roe"] - sizes["scalar"] == pad(16 * nc * 8)
+    assert sizes["kinetic"] == sizes["roe"]
     assert sizes["roe_mixed"] - sizes["mixed"] == pad(16 * nc * 4)
     assert sizes["explicit_roe"] == sizes["explicit"]
 
@@ -270,7 +272,7 @@ def test_call_order_and_option_errors():
     for bad in (dict(block=96), dict(block=512), dict(sweep=4), dict(precision=5), dict(chunk=-1),
                 dict(flux_lanes=3), dict(wall_temp=-1.0), dict(wall_temp=float("nan")), dict(limiter_freeze=-0.1),
                 dict(limiter_freeze=1.0), dict(tau_jump=2), dict(block_passes=3), dict(block_passes=-1),
-                dict(block_passes=2, sweep=1), dict(block_passes=2, sweep=2), dict(lusgs_op=2), dict(lusgs_op=-1)):
+                dict(block_passes=2, sweep=1), dict(block_passes=2, sweep=2), dict(lusgs_op=3), dict(lusgs_op=-1)):
         rc, ctx = ctx_for(**bad)
         assert rc == igks.IGKS_EINVAL, bad
         assert not ctx.value

@@ -41,7 +41,19 @@ def _jac_cs(W, nx, ny):
     return J
 
 
-def _abs_by_eig(Wl, Wr, nx, ny):
+def _kin_mag(s, c):
+    """The mean of |u| for u normal with mean s and variance RT = c^2/gamma,
+    by adaptive quadrature of each side of the kink at u = 0 (independent of
+    the closed form the oracle uses)."""
+    from scipy.integrate import quad
+    sig = c / math.sqrt(GAM)
+    pdf = lambda u: math.exp(-0.5 * ((u - s) / sig) ** 2) / (sig * math.sqrt(2 * math.pi))
+    lo = quad(lambda u: -u * pdf(u), -np.inf, 0.0, epsabs=1e-14, epsrel=1e-13)[0]
+    hi = quad(lambda u: u * pdf(u), 0.0, np.inf, epsabs=1e-14, epsrel=1e-13)[0]
+    return lo + hi
+
+
+def _abs_by_eig(Wl, Wr, nx, ny, kin=False):
     """|A| as a function of the Jacobian J at the Roe state: J is
     diagonalisable with the three distinct eigenvalues q - c, q, q + c, so
     f(J) = sum_m f(l_m) prod_{k != m} (J - l_k I) / (l_m - l_k) (Sylvester's
@@ -57,7 +69,7 @@ def _abs_by_eig(Wl, Wr, nx, ny):
         for k, lk in enumerate(ls):
             if k != m:
                 P = P @ (J - lk * np.eye(4)) / (lm - lk)
-        A += max(abs(lm), DELTA * c) * P
+        A += (_kin_mag(lm, c) if kin else max(abs(lm), DELTA * c)) * P
     return A, Wa
 
 
@@ -66,6 +78,24 @@ CASES = [  # (Wl, Wr, n): subsonic, supersonic, a stagnation-like low normal spe
     ([1.0, 2.4, 0.3, 5.5], [1.1, 2.5, 0.1, 5.9], (1.0, 0.0)),
     ([1.0, 0.01, 0.4, 1.9], [1.05, -0.01, 0.45, 2.0], (math.cos(0.03), math.sin(0.03))),
 ]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_roe_abs_kinetic_magnitudes(case):
+    """lusgs_op 2: the same matrix function with each eigenvalue s replaced
+    by the mean of |u| over a Maxwellian spread of normal velocities about s
+    (quadrature here): at least |s|, about 0.674 c at s = 0 (sqrt(2/(pi
+    gamma)) c), and |s| far from 0."""
+    Wl, Wr, (nx, ny) = CASES[case]
+    Wl = np.array(Wl + [0.0]); Wr = np.array(Wr + [0.0])
+    want, _ = _abs_by_eig(Wl, Wr, nx, ny, kin=True)
+    got = po.roe_abs(Wl, Wr, nx, ny, kinetic=True)
+    assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
+    _, c = _roe_state(Wl, Wr)
+    assert _kin_mag(0.0, c) == pytest.approx(math.sqrt(2.0 / (math.pi * GAM)) * c, rel=1e-12)
+    assert _kin_mag(5.0 * c, c) == pytest.approx(5.0 * c, rel=1e-6)
+    ev = np.sort(np.real(np.linalg.eigvals(got)))
+    assert ev[0] >= 0.67 * c
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
@@ -113,9 +143,10 @@ def test_roe_abs_of_equal_states_is_abs_jacobian():
     assert np.allclose(ev, np.sort([abs(q - c), abs(q), abs(q), abs(q + c)]), rtol=1e-10)
 
 
-@pytest.mark.parametrize("top,blocks", [(mg.OUTFLOW, 0), (mg.MOVING_WALL, 0), (mg.OUTFLOW, 1), (mg.OUTFLOW, 2)],
-                         ids=["outflow", "moving_wall", "blocks", "blocks2"])
-def test_roe_lusgs_solves_factored_system(top, blocks):
+@pytest.mark.parametrize("top,blocks,op", [(mg.OUTFLOW, 0, 1), (mg.MOVING_WALL, 0, 1), (mg.OUTFLOW, 1, 1),
+                                           (mg.OUTFLOW, 2, 1), (mg.MOVING_WALL, 1, 2)],
+                         ids=["outflow", "moving_wall", "blocks", "blocks2", "kinetic"])
+def test_roe_lusgs_solves_factored_system(top, blocks, op):
     """With the Roe operator the sweeps solve (L + D) D^-1 (D + U) dW = M with
     4x4 blocks D_i = Omega/dt I + 1/2 sum |A_ij| S_ij (dt of Eq.24) and
     off-diagonal blocks 1/2 (J_j - |A_ij|) S_ij, the lagged ghost increments
@@ -125,10 +156,10 @@ def test_roe_lusgs_solves_factored_system(top, blocks):
     times the identity.  With sweep blocks a face between two blocks keeps
     lambda_ij I in D, its pair is left out of L and U, and with two passes
     the second solves again with M - X dW1 on the right (X: those pairs'
-    1/2 (J_j - lambda_ij I) S_ij)."""
+    1/2 (J_j - lambda_ij I) S_ij).  op 2: the kinetic wave magnitudes."""
     tags = dict(bottom=mg.WALL, top=top, left=mg.FREESTREAM, right=mg.SYMMETRY)
     m = mg.colour_order(mg.random_hybrid(5, 4, seed=7, tags=tags))[0]
-    o = po.Oracle(m, lusgs_op=1)
+    o = po.Oracle(m, lusgs_op=op)
     blk = mg.sweep_blocks(m, 7) if blocks else np.zeros(m.n_cells, dtype=np.int32)
     if blocks:
         assert blk.max() >= 3
@@ -153,8 +184,8 @@ def test_roe_lusgs_solves_factored_system(top, blocks):
             sr.append(abs(u * nx + v * ny) + math.sqrt(GAM * p / r))
         vis = lam[k] - max(sr)
         assert vis > 0.0
-        want, _ = _abs_by_eig(W[:, i], Wj, nx, ny)
-        assert np.abs(A[k] - vis * np.eye(4) - want).max() <= 1e-12 * np.abs(want).max()
+        want, _ = _abs_by_eig(W[:, i], Wj, nx, ny, kin=op == 2)
+        assert np.abs(A[k] - vis * np.eye(4) - want).max() <= (1e-9 if op == 2 else 1e-12) * np.abs(want).max()
     Dm = np.zeros((4 * n, 4 * n)); L = np.zeros_like(Dm); U = np.zeros_like(Dm); G = np.zeros_like(Dm)
     X = np.zeros_like(Dm)
     for i in range(n):
@@ -234,7 +265,7 @@ def test_roe_operator_keeps_the_fixed_point():
 def test_lusgs_op_is_validated():
     m = mg.random_hybrid(3, 3, seed=1)
     with pytest.raises(po.OracleError):
-        po.Oracle(m, lusgs_op=2)
+        po.Oracle(m, lusgs_op=3)
     o = po.Oracle(m)
     o.set_freestream(0.3, 0.0, 1e3)
     with pytest.raises(po.OracleError):
